@@ -1,0 +1,303 @@
+"""Seeded synthetic inputs shared by the oracle, the tests and the benchmark.
+
+This module builds *inputs only*: wall-normal face coordinates, triangulated
+surfaces, the host-side kinematic coefficients of each body (every
+transcendental is evaluated here, on the host) and the initial velocity
+fields.  It holds none of the method's arithmetic: no tagging, no forcing, no
+differential operator, no solver.  Both the CPU oracle and the HIP path consume
+the arrays produced here, so the two sides see bit-identical inputs without
+sharing any code.
+
+Shapes follow the paper's workloads (a periodic channel, x1/x2 periodic and
+uniform, x3 stretched, Sec. 2; plates of the heaving/pitching test, Sec. 4.4;
+spheres of the settling tests, Sec. 4.5; closed deforming membranes of the
+bubble test, Sec. 4.7).  The paper evaluates on no public dataset; these
+seeded generators stand in for its setups, whose data is not available.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+
+__all__ = [
+    "uniform_faces", "tanh_faces", "icosphere", "plate_mesh",
+    "rigid_coef", "sphere_translation", "plate_heave_pitch",
+    "deform_vertex_data", "deform_coef", "splitmix64_uniform",
+    "initial_velocity", "Workload", "config", "CONFIG_NAMES",
+]
+
+# --------------------------------------------------------------------------
+# wall-normal grids (the caller-supplied face coordinates y_f[0..ny])
+# --------------------------------------------------------------------------
+
+def uniform_faces(ny: int, y0: float = -1.0, y1: float = 1.0) -> np.ndarray:
+    """ny+1 uniformly spaced faces on [y0, y1] (end points exact)."""
+    j = np.arange(ny + 1, dtype=np.float64)
+    yf = y0 + (y1 - y0) * j / ny
+    yf[0], yf[-1] = y0, y1
+    return yf
+
+
+def tanh_faces(ny: int, beta: float = 2.0) -> np.ndarray:
+    """ny+1 faces on [-1, 1] clustered at both walls:
+    y_f[j] = tanh(beta*(2j/ny - 1)) / tanh(beta).  For even ny the middle face
+    is exactly 0."""
+    j = np.arange(ny + 1, dtype=np.float64)
+    yf = np.tanh(beta * (2.0 * j / ny - 1.0)) / math.tanh(beta)
+    yf[0], yf[-1] = -1.0, 1.0
+    if ny % 2 == 0:
+        yf[ny // 2] = 0.0
+    return yf
+
+# --------------------------------------------------------------------------
+# triangulated surfaces
+# --------------------------------------------------------------------------
+
+def icosphere(level: int):
+    """Unit icosphere: 20*4**level triangles, outward counter-clockwise.
+    Returns (verts f64[nv,3], tris i32[nt,3])."""
+    t = (1.0 + math.sqrt(5.0)) / 2.0
+    v = [(-1, t, 0), (1, t, 0), (-1, -t, 0), (1, -t, 0),
+         (0, -1, t), (0, 1, t), (0, -1, -t), (0, 1, -t),
+         (t, 0, -1), (t, 0, 1), (-t, 0, -1), (-t, 0, 1)]
+    verts = [np.array(p, dtype=np.float64) / math.sqrt(1.0 + t * t) for p in v]
+    faces = [(0, 11, 5), (0, 5, 1), (0, 1, 7), (0, 7, 10), (0, 10, 11),
+             (1, 5, 9), (5, 11, 4), (11, 10, 2), (10, 7, 6), (7, 1, 8),
+             (3, 9, 4), (3, 4, 2), (3, 2, 6), (3, 6, 8), (3, 8, 9),
+             (4, 9, 5), (2, 4, 11), (6, 2, 10), (8, 6, 7), (9, 8, 1)]
+    for _ in range(level):
+        cache = {}
+
+        def mid(a, b):
+            key = (a, b) if a < b else (b, a)
+            if key not in cache:
+                m = verts[a] + verts[b]
+                verts.append(m / np.linalg.norm(m))
+                cache[key] = len(verts) - 1
+            return cache[key]
+
+        nf = []
+        for a, b, c in faces:
+            ab, bc, ca = mid(a, b), mid(b, c), mid(c, a)
+            nf += [(a, ab, ca), (b, bc, ab), (c, ca, bc), (ab, bc, ca)]
+        faces = nf
+    V = np.array(verts, dtype=np.float64)
+    F = np.array(faces, dtype=np.int32)
+    # orient outward: (B-A)x(C-A) points away from the centre
+    n = np.cross(V[F[:, 1]] - V[F[:, 0]], V[F[:, 2]] - V[F[:, 0]])
+    flip = np.einsum("ij,ij->i", n, V[F].mean(axis=1)) < 0
+    F[flip] = F[flip][:, [0, 2, 1]]
+    return V, F
+
+
+def plate_mesh(chord: float, span: float, nq_x: int, nq_z: int):
+    """Zero-thickness flat plate in the x-z plane (y = 0), centred at the
+    origin: chord along x, span along z, nq_x*nq_z quads split by a fixed
+    diagonal into 2*nq_x*nq_z triangles.  Returns (verts, tris)."""
+    xs = -0.5 * chord + chord * np.arange(nq_x + 1, dtype=np.float64) / nq_x
+    zs = -0.5 * span + span * np.arange(nq_z + 1, dtype=np.float64) / nq_z
+    X, Z = np.meshgrid(xs, zs, indexing="ij")
+    V = np.stack([X.ravel(), np.zeros(X.size), Z.ravel()], axis=1)
+    tris = []
+    for a in range(nq_x):
+        for b in range(nq_z):
+            v00 = a * (nq_z + 1) + b
+            v10 = (a + 1) * (nq_z + 1) + b
+            v01 = v00 + 1
+            v11 = v10 + 1
+            tris.append((v00, v10, v11))
+            tris.append((v00, v11, v01))
+    return V, np.array(tris, dtype=np.int32)
+
+# --------------------------------------------------------------------------
+# host-side kinematics: coefficients only (every sin/cos is taken here)
+# --------------------------------------------------------------------------
+
+def rigid_coef(c, R, cdot, omega) -> np.ndarray:
+    """Pack a rigid motion X = c + R X0, U = cdot + omega x (X - c) into the
+    18-double coefficient vector [c(3), R(9, row-major), cdot(3), omega(3)]."""
+    out = np.empty(18, dtype=np.float64)
+    out[0:3] = c
+    out[3:12] = np.asarray(R, dtype=np.float64).reshape(9)
+    out[12:15] = cdot
+    out[15:18] = omega
+    return out
+
+
+def sphere_translation(t: float, c0, U) -> np.ndarray:
+    """Rigid translation at constant velocity U from centre c0."""
+    c0 = np.asarray(c0, np.float64)
+    U = np.asarray(U, np.float64)
+    return rigid_coef(c0 + U * t, np.eye(3), U, np.zeros(3))
+
+
+def plate_heave_pitch(t: float, centre=(math.pi, 0.0, 0.5 * math.pi),
+                      heave=0.2, freq=1.0, pitch=math.pi / 12.0) -> np.ndarray:
+    """Heaving (along y) and pitching (about z through the centre) plate:
+    y_c = heave*sin(2 pi f t), theta = pitch*sin(4 pi f t) (pitch at twice the
+    heave frequency, as in the heaving/pitching plate test)."""
+    w = 2.0 * math.pi * freq
+    th = pitch * math.sin(2.0 * w * t)
+    thd = pitch * 2.0 * w * math.cos(2.0 * w * t)
+    ct, st = math.cos(th), math.sin(th)
+    R = [[ct, -st, 0.0], [st, ct, 0.0], [0.0, 0.0, 1.0]]
+    c = (centre[0], centre[1] + heave * math.sin(w * t), centre[2])
+    cd = (0.0, heave * w * math.cos(w * t), 0.0)
+    return rigid_coef(c, R, cd, (0.0, 0.0, thd))
+
+
+def deform_vertex_data(unit_verts: np.ndarray, r0: float, amp: float = 0.1):
+    """Per-vertex data of the deforming closed body
+    r(theta, t) = r0 (1 + amp Y20(theta) sin(4 pi t)), theta from +y:
+    returns f64[nv,4] = [direction(3), r0*amp*Y20(theta)]."""
+    d = unit_verts / np.linalg.norm(unit_verts, axis=1, keepdims=True)
+    ct = d[:, 1]
+    y20 = 0.25 * math.sqrt(5.0 / math.pi) * (3.0 * ct * ct - 1.0)
+    out = np.empty((len(d), 4), dtype=np.float64)
+    out[:, :3] = d
+    out[:, 3] = r0 * amp * y20
+    return out
+
+
+def deform_coef(t: float, centre, r0: float, freq: float = 2.0) -> np.ndarray:
+    """Scalars of the deforming body at time t: [c(3), r0, s, sdot] with
+    s = sin(2 pi freq t)."""
+    w = 2.0 * math.pi * freq
+    return np.array([centre[0], centre[1], centre[2], r0,
+                     math.sin(w * t), w * math.cos(w * t)], dtype=np.float64)
+
+# --------------------------------------------------------------------------
+# initial fields
+# --------------------------------------------------------------------------
+
+_M64 = np.uint64(0xFFFFFFFFFFFFFFFF)
+
+
+def splitmix64_uniform(seed: int, comp: int, n: int, start: int = 0) -> np.ndarray:
+    """xi in [0,1) with 53 random bits: SplitMix64 (Steele, Lea, Flood 2014)
+    applied to the counter (seed << 34) | (comp << 32) | index."""
+    with np.errstate(over="ignore"):
+        idx = np.arange(start, start + n, dtype=np.uint64)
+        x = (np.uint64(seed) << np.uint64(34)) | (np.uint64(comp) << np.uint64(32)) | idx
+        z = x + np.uint64(0x9E3779B97F4A7C15)
+        z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+        z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+        z = z ^ (z >> np.uint64(31))
+    return (z >> np.uint64(11)).astype(np.float64) * (1.0 / 9007199254740992.0)
+
+
+def initial_velocity(nx, ny, nz, y_faces, uc=1.0, amp=0.01, seed=1):
+    """Laminar profile u = uc (1 - y^2) at the u-node heights plus a seeded
+    uniform perturbation amp*(2 xi - 1) on every interior u, v, w unknown.
+    Layout [y][z][x]; v has ny+1 planes, the wall planes are 0.
+    Returns (u, v, w) f64 arrays."""
+    yf = np.asarray(y_faces, np.float64)
+    yn = (yf[:-1] + yf[1:]) * 0.5                     # u-node heights
+    n = nx * ny * nz
+    u = (uc * (1.0 - yn * yn))[:, None, None] * np.ones((ny, nz, nx))
+    u += amp * (2.0 * splitmix64_uniform(seed, 0, n).reshape(ny, nz, nx) - 1.0)
+    v = np.zeros((ny + 1, nz, nx))
+    nv = (ny - 1) * nz * nx
+    v[1:ny] = amp * (2.0 * splitmix64_uniform(seed, 1, nv).reshape(ny - 1, nz, nx) - 1.0)
+    w = amp * (2.0 * splitmix64_uniform(seed, 2, n).reshape(ny, nz, nx) - 1.0)
+    return u, v, w
+
+# --------------------------------------------------------------------------
+# workloads
+# --------------------------------------------------------------------------
+
+@dataclass
+class Body:
+    kind: str                  # "rigid" or "deform"
+    ref: np.ndarray            # rigid: X0 (relative to centre) f64[nv,3];
+                               # deform: f64[nv,4] [dir, amplitude]
+    tris: np.ndarray           # i32[nt,3]
+    coef: object               # callable t -> coefficient vector
+
+
+@dataclass
+class Workload:
+    name: str
+    nx: int
+    ny: int
+    nz: int
+    lx: float
+    lz: float
+    y_faces: np.ndarray
+    re: float
+    dt: float
+    steps: int
+    uc: float
+    amp: float
+    seed: int
+    dpdx: float                # mean pressure gradient dP/dx (driving force -dP/dx)
+    bodies: list = field(default_factory=list)
+    scheme: str = "rk2"
+
+    @property
+    def cells(self) -> int:
+        return self.nx * self.ny * self.nz
+
+    def fields(self):
+        return initial_velocity(self.nx, self.ny, self.nz, self.y_faces,
+                                self.uc, self.amp, self.seed)
+
+
+def _sphere_body(level, radius, c0, U):
+    V, F = icosphere(level)
+    c0 = np.asarray(c0, np.float64)
+    U = np.asarray(U, np.float64)
+    return Body("rigid", V * radius, F, lambda t: sphere_translation(t, c0, U))
+
+
+def config(name: str) -> Workload:
+    """Named synthetic workloads.
+
+    c1   64x48x64 uniform channel, Re 100, dt 1e-3, 10 steps; one sphere of
+         diameter 0.5 (1280 triangles) translating at (0.5, 0, 0).
+    c2   256x192x256 tanh-stretched channel, Re 1000, dt 1e-3, 100 steps; a
+         zero-thickness 1.0 x 0.6 plate (1920 triangles) heaving
+         0.2 sin(2 pi t) and pitching +-15 deg at twice the frequency.
+    c3   512x384x512 stretched channel, Re 2000, dt 1e-3, 200 steps; a
+         deforming closed body r = 0.4 (1 + 0.1 Y20 sin 4 pi t), 20480 tris.
+    tiny  small ragged grids for parity tests (several tiles plus a tail).
+    """
+    two_pi, pi = 2.0 * math.pi, math.pi
+    if name == "c1":
+        ny = 48
+        return Workload("c1", 64, ny, 64, two_pi, pi, uniform_faces(ny), 100.0,
+                        1e-3, 10, 1.0, 0.01, 1, -2.0 / 100.0,
+                        [_sphere_body(3, 0.25, (pi, 0.0, 0.5 * pi), (0.5, 0.0, 0.0))])
+    if name == "c2":
+        ny = 192
+        V, F = plate_mesh(1.0, 0.6, 40, 24)
+        return Workload("c2", 256, ny, 256, two_pi, pi, tanh_faces(ny, 2.0), 1000.0,
+                        1e-3, 100, 1.0, 0.01, 2, -2.0 / 1000.0,
+                        [Body("rigid", V, F, plate_heave_pitch)])
+    if name == "c3":
+        ny = 384
+        V, F = icosphere(5)
+        c = (pi, 0.0, 0.5 * pi)
+        return Workload("c3", 512, ny, 512, two_pi, pi, tanh_faces(ny, 2.0), 2000.0,
+                        1e-3, 200, 1.0, 0.01, 3, -2.0 / 2000.0,
+                        [Body("deform", deform_vertex_data(V, 0.4), F,
+                              lambda t: deform_coef(t, c, 0.4))])
+    if name == "tiny":
+        # ragged, non-power-of-two sizes: 40 = 8*5 and 36 = 4*9 exercise the
+        # mixed-radix transforms; the sphere spans several tiles.
+        ny = 30
+        return Workload("tiny", 40, ny, 36, two_pi, pi, tanh_faces(ny, 1.5), 100.0,
+                        2e-3, 3, 1.0, 0.05, 7, -2.0 / 100.0,
+                        [_sphere_body(2, 0.5, (3.0, 0.0, 1.6), (0.3, 0.1, -0.2))])
+    if name == "tiny_plate":
+        ny = 32
+        V, F = plate_mesh(1.2, 0.8, 10, 6)
+        return Workload("tiny_plate", 48, ny, 40, two_pi, pi, tanh_faces(ny, 2.0), 200.0,
+                        2e-3, 3, 1.0, 0.02, 11, -2.0 / 200.0,
+                        [Body("rigid", V, F, plate_heave_pitch)])
+    raise KeyError(name)
+
+
+CONFIG_NAMES = ("c1", "c2", "c3", "tiny", "tiny_plate")
