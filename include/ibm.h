@@ -1,0 +1,223 @@
+/*
+ * ibm.h -- C-ABI of the MI355X (gfx950) implementation of the per-time-step
+ * hot path of the sharp-interface immersed boundary fractional-step scheme of
+ * Vagnoli, Scarpolini, Verzicco and Viola ("A fast and consistent
+ * sharp-interface immersed boundary method for moving bodies of arbitrary
+ * thickness").
+ *
+ * Problem statement followed by the calls (paper Sec. 2): a box periodic and
+ * uniform in x and z, stretched in y between two no-slip walls; a staggered
+ * grid with the pressure at cell centres and each velocity component on the
+ * faces normal to it; moving surfaces made of triangles with a prescribed wall
+ * velocity; Reynolds number Re, time step dt and a fractional-step scheme
+ * (RK2+CN or AB+CN).
+ *
+ * Conventions shared by every call
+ *   - Arrays are row-major [y][z][x] (x fastest), FP64.  u, w and p hold
+ *     ny*nz*nx values; v holds (ny+1)*nz*nx values including the two wall
+ *     planes j = 0 and j = ny, which the library keeps at 0.
+ *     u(i,j,k) sits at (i dx, yc[j], (k+1/2) dz), v(i,j,k) at
+ *     ((i+1/2) dx, yf[j], (k+1/2) dz), w(i,j,k) at ((i+1/2) dx, yc[j], k dz),
+ *     p(i,j,k) at ((i+1/2) dx, yc[j], (k+1/2) dz).
+ *   - "dev" pointers are device memory on the context's device; "host"
+ *     pointers are host memory.  The caller owns every array it passes; the
+ *     library owns its workspace and the tag buffers.
+ *   - Every call is enqueued on the context's HIP stream and returns without
+ *     synchronising, except ibm_check and the *_host calls.  A context is
+ *     bound to one stream and one device and is not thread-safe.
+ *   - Return value: IBM_OK (0) or a negative IBM_E* code.  Conditions found
+ *     on the device (capacity overflow, non-finite values, geometry limits)
+ *     are recorded in a sticky device word that ibm_check returns.  No call
+ *     aborts or throws across the ABI.
+ */
+#ifndef IBM_H
+#define IBM_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* return codes */
+#define IBM_OK 0
+#define IBM_EINVAL (-1)    /* bad size, layout, pointer or grid */
+#define IBM_ENOMEM (-2)    /* device allocation failed at create */
+#define IBM_EHIP (-3)      /* HIP runtime error; text in ibm_strerror */
+#define IBM_ECAPACITY (-4) /* forcing list or C_B list overflowed */
+#define IBM_ENONFINITE (-5)
+#define IBM_EGEOM (-7)     /* body too large for the periodic box, probe
+                              leaving the channel, or a probe stencil that
+                              contains its own forcing node */
+
+/* sticky device flags returned by ibm_check */
+#define IBM_FLAG_CAPACITY 1u
+#define IBM_FLAG_NONFINITE 2u
+#define IBM_FLAG_GEOM 4u
+
+#define IBM_FP64 0
+#define IBM_RK2CN 0
+#define IBM_AB2CN 1
+
+typedef struct ibm_ctx ibm_ctx;
+
+/* Grid (paper Sec. 2, Fig. 1).  y_faces: host array of ny+1 strictly
+ * increasing face heights; the walls are y_faces[0] and y_faces[ny].
+ * Periodic spacings are lx/nx and lz/nz. */
+typedef struct {
+  int32_t nx, ny, nz;
+  int32_t reserved;
+  double lx, lz;
+  const double* y_faces; /* host, ny+1 */
+} ibm_grid;
+
+/* Options.  dpdx is the mean pressure gradient dP/dx; the driving volume
+ * force is -dpdx along x.  force_cap bounds each forcing list and the C_B
+ * list (0 = automatic: max(65536, cells/16)).  use_q = 1 applies the
+ * consistent mass correction of Sec. 3.2, 0 the standard projection. */
+typedef struct {
+  int32_t precision; /* IBM_FP64 */
+  int32_t scheme;    /* IBM_RK2CN or IBM_AB2CN */
+  double re;
+  double dpdx;
+  int64_t force_cap;
+  int32_t use_q;
+  int32_t reserved;
+} ibm_opts;
+
+/* One triangulated surface at time t^n (paper Sec. 2: the wall position
+ * X(t) and velocity U(X(t))).  xyz, vel: dev f64[nv*3]; tri: dev i32[nt*3]
+ * vertex indices.  Several bodies are numbered globally: the triangle id of
+ * triangle t of body b is (sum of nt of bodies before b) + t. */
+typedef struct {
+  int32_t nv, nt;
+  const double* xyz;
+  const double* vel;
+  const int32_t* tri;
+} ibm_body;
+
+/* Views of the context-owned tag buffers, filled by ibm_tag and valid until
+ * the next ibm_tag.  idx[c]: dev i64, ascending linear node indices of the
+ * forcing nodes of component c (v indices count the wall plane j = 0);
+ * tri[c]: dev i32 forcing triangle of each; cb: dev i64 ascending linear
+ * indices of the boundary cells C_B; count: dev i64[4] = forcing counts of
+ * u, v, w and |C_B|; mask[c], cb_mask: dev bitmaps, bit n of word n/32. */
+typedef struct {
+  int64_t* idx[3];
+  int32_t* tri[3];
+  int64_t* cb;
+  int64_t* count;
+  uint32_t* mask[3];
+  uint32_t* cb_mask;
+  int64_t capacity;
+} ibm_tags;
+
+/* Flow state owned by the caller.  h[3] (AB+CN only): dev H^{n-1} read and
+ * H^n written; may be NULL for RK2+CN. */
+typedef struct {
+  double *u, *v, *w, *p;
+  double* h[3];
+} ibm_state;
+
+/* Create a context on the current HIP device for one grid; all workspace is
+ * allocated here and nothing later.  stream: hipStream_t (NULL = default). */
+int ibm_create(const ibm_grid* g, const ibm_opts* o, void* stream, ibm_ctx** out);
+void ibm_destroy(ibm_ctx* ctx);
+int ibm_set_stream(ibm_ctx* ctx, void* stream);
+
+/* Body transforms (the wall position and velocity at t^n from host-evaluated
+ * coefficients; only +, - and * on the device, in a fixed order, so the
+ * vertices are bit-identical to any implementation of the same order).
+ * rigid:  X = c + R X0, U = cdot + omega x (X - c);
+ *         coef (host) = [c(3), R(9 row-major), cdot(3), omega(3)];
+ *         x0: dev f64[nv*3] reference positions.
+ * deform: X = c + (r0 + f s) d, U = (f sdot) d;
+ *         coef (host) = [c(3), r0, s, sdot]; data: dev f64[nv*4] = [d(3), f].
+ * Output xyz, vel: dev f64[nv*3]. */
+int ibm_body_rigid(ibm_ctx* ctx, const double* x0, int32_t nv, const double* coef,
+                   double* xyz, double* vel);
+int ibm_body_deform(ibm_ctx* ctx, const double* data, int32_t nv, const double* coef,
+                    double* xyz, double* vel);
+
+/* Tagging (paper Alg. 1, Sec. 3.1) of the three staggered lattices and the
+ * boundary cells C_B (Sec. 3.2: cells all of whose faces carry forcing
+ * nodes).  A node x is a forcing node if for some triangle T, with X the
+ * closest point of T to x and N = x - X, either |N| = 0 or N.(x_n - X) < 0
+ * for one of its six same-lattice neighbours x_n; its forcing triangle is
+ * the classifying triangle of least |N|^2, ties to the lowest id.  The
+ * decision uses IEEE binary64 +,-,*,/ in a fixed order (no FMA), so results
+ * are exact integers independent of scheduling.  Also stores the bodies for
+ * the following ibm_force / ibm_step calls.  out may be NULL. */
+int ibm_tag(ibm_ctx* ctx, const ibm_body* bodies, int32_t nbody, ibm_tags* out);
+/* Synchronises and copies the four counts (u, v, w, C_B) to the host. */
+int ibm_tags_count_host(ibm_ctx* ctx, int64_t* counts);
+/* Stream-ordered device-to-device copy of the first n entries of a list of
+ * the last ibm_tag: list 0, 1, 2 = forcing nodes of u, v, w (idx_dst: dev
+ * i64[n]; tri_dst: dev i32[n] or NULL), list 3 = C_B (idx_dst only).
+ * n must not exceed the list's count (IBM_EINVAL if it exceeds the
+ * capacity). */
+int ibm_tags_copy(ibm_ctx* ctx, int32_t list, int64_t* idx_dst, int32_t* tri_dst, int64_t n);
+
+/* Two-sided IB forcing (paper Eqs. IB_step, probe and new_IB): every forcing
+ * node of the last ibm_tag receives u^f = (1 - a) U + a u^e, a = |N|/h,
+ * x^e = X + h N/|N|, h = 2 x (local cell diagonal), u^e the trilinear
+ * interpolation of its component at x^e, U the barycentric wall velocity;
+ * all values are computed from the input fields before any is written.
+ * u, v, w: dev, updated in place. */
+int ibm_force(ibm_ctx* ctx, double* u, double* v, double* w);
+
+/* Predictor on the fluid nodes (paper Eq. NS_prov): explicit right-hand side
+ * R = dt [gamma H(u) + rho H_prev - alpha (G p + dpdx e_x) + (alpha/Re) L u]
+ * and the approximate factorisation (I - bL_x)(I - bL_z)(I - bL_y) du = R,
+ * b = alpha dt/(2 Re), with identity rows on the forcing nodes; then
+ * u <- u + du.  gamma, rho: the sub-stage coefficients; h_prev (read when
+ * rho != 0) and h_out (written when not NULL): dev arrays of H per
+ * component (NULL entries allowed).  p: dev.  u, v, w: dev, in place. */
+int ibm_viscous(ibm_ctx* ctx, const double* p, const double* const* h_prev,
+                double* const* h_out, double gamma, double rho, double dt,
+                double* u, double* v, double* w);
+
+/* Consistent mass correction (paper Eqs. mod_div, q_boundary, q_F,
+ * elliptic_mod): q_F = -(sum_{C_B} D u dV)/|C_F| from the last ibm_tag, and
+ * rhs = (D u - q_F)/alpha_dt on C_F, 0 on C_B (use_q = 0: rhs = D u/alpha_dt).
+ * rhs: dev ny*nz*nx; qf: dev f64[1] (may be NULL). */
+int ibm_mass_rhs(ibm_ctx* ctx, const double* u, const double* v, const double* w,
+                 double alpha_dt, double* rhs, double* qf);
+
+/* Direct solve of L_c phi = rhs (paper Eq. elliptic / elliptic_mod; L_c = D G
+ * with homogeneous Neumann walls): real FFT in x, complex FFT in z,
+ * tridiagonal solve in y per Fourier mode.  The singular (0,0) mode is fixed
+ * by phi_0 = 0 and the result is shifted to zero volume-weighted mean.
+ * rhs, phi: dev ny*nz*nx (may alias). */
+int poisson_solve(ibm_ctx* ctx, const double* rhs, double* phi);
+
+/* Projection and pressure update (paper Eqs. projection, update_pressure):
+ * u <- u - alpha_dt G phi on every interior velocity node;
+ * p <- p + phi - alpha_dt/(2 Re) L_c phi.  All dev, in place. */
+int ibm_project(ibm_ctx* ctx, const double* phi, double alpha_dt, double* u,
+                double* v, double* w, double* p);
+
+/* One whole time step of the scheme (paper Sec. 2 and Sec. 3): tags the
+ * bodies at t^n once, then for every sub-stage: IB forcing, predictor,
+ * consistent mass correction, Poisson solve, projection and pressure update.
+ * The bodies stay at t^n for all sub-stages. */
+int ibm_step(ibm_ctx* ctx, ibm_state* s, const ibm_body* bodies, int32_t nbody,
+             double dt);
+
+/* Synchronise the stream and return (and clear) the sticky device flags. */
+int ibm_check(ibm_ctx* ctx, uint32_t* flags);
+const char* ibm_strerror(int code);
+
+/* Per-kernel timing with HIP events on the context's stream.  enable = 1
+ * records an event pair around every launch of a kernel whose name contains
+ * `filter` (NULL or "" = all kernels); ibm_profile_read synchronises and
+ * writes up to `cap` (name, launches, total ms) records, returns the number
+ * written, and resets the accumulators. */
+int ibm_profile(ibm_ctx* ctx, int32_t enable, const char* filter);
+int ibm_profile_read(ibm_ctx* ctx, char* names, int32_t name_len, int64_t* launches,
+                     double* total_ms, int32_t cap);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* IBM_H */

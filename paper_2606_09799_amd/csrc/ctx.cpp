@@ -1,0 +1,792 @@
+// Host side of libibm: the context (grid metrics, workspace, line-solve and
+// FFT tables), the orchestration of one time step on one HIP stream, the
+// sticky error word, per-kernel event timing, and the exported C-ABI of
+// include/ibm.h.  Every call only enqueues work; nothing synchronises except
+// ibm_check, ibm_tags_count_host and ibm_profile_read.
+#include "ibm.h"
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+using namespace ibm;
+
+static thread_local std::string g_last_error;
+
+#define HIPCHK(expr)                                                       \
+  do {                                                                     \
+    hipError_t e_ = (expr);                                                \
+    if (e_ != hipSuccess) {                                                \
+      g_last_error = std::string(#expr) + ": " + hipGetErrorString(e_);   \
+      return IBM_EHIP;                                                     \
+    }                                                                      \
+  } while (0)
+
+// ------------------------------------------------------------ profiling
+namespace ibm {
+struct Prof {
+  bool enabled = false;
+  std::string filter;
+  struct Rec {
+    std::string name;
+    hipEvent_t a, b;
+  };
+  std::vector<Rec> recs;
+  std::vector<hipEvent_t> pool;
+  bool open = false;
+
+  hipEvent_t take() {
+    if (!pool.empty()) {
+      hipEvent_t e = pool.back();
+      pool.pop_back();
+      return e;
+    }
+    hipEvent_t e = nullptr;
+    (void)hipEventCreate(&e);
+    return e;
+  }
+};
+
+void prof_begin(Prof* p, const char* name, hipStream_t s) {
+  if (!p || !p->enabled) return;
+  if (!p->filter.empty() && std::strstr(name, p->filter.c_str()) == nullptr) return;
+  Prof::Rec r{name, p->take(), p->take()};
+  (void)hipEventRecord(r.a, s);
+  p->recs.push_back(r);
+  p->open = true;
+}
+
+void prof_end(Prof* p, hipStream_t s) {
+  if (!p || !p->open) return;
+  (void)hipEventRecord(p->recs.back().b, s);
+  p->open = false;
+}
+}  // namespace ibm
+
+// ------------------------------------------------------------ context
+struct ibm_ctx {
+  int dev = 0;
+  hipStream_t stream = nullptr;
+  int nx = 0, ny = 0, nz = 0;
+  double lx = 0, lz = 0;
+  ibm_opts opts{};
+  int64_t ncell = 0, nvface = 0;
+  std::vector<double> yf, yc, dy, dyc, extuw;
+  GridView g{};
+  std::vector<void*> allocs;
+
+  TagBuffers tb{};
+  double* force_vals = nullptr;
+  std::vector<BodyDev> bodies;  // bodies of the last ibm_tag
+  std::vector<BodyDev> last_bodies;
+  int ntri = 0;
+  static constexpr int NSLOT = 8;
+  BodyDev* dslots = nullptr;  // NSLOT x 64 descriptors (device)
+  BodyDev* hslots = nullptr;  // NSLOT x 64 descriptors (pinned host)
+  hipEvent_t slot_ev[NSLOT] = {};
+  bool slot_used[NSLOT] = {};
+  int cur_slot = -1;
+  const BodyDev* d_bodies = nullptr;
+
+  double* R[3] = {};
+  double* H[3] = {};
+  double* scratch[3] = {};
+  double* rhs_tmp = nullptr;
+  double* phi = nullptr;
+  double2* spec = nullptr;
+  double* cscr = nullptr;
+  double* partial = nullptr;
+  double* qf = nullptr;
+  uint32_t* flags = nullptr;
+
+  // line-solve tables for one beta
+  double tab_beta = -1.0;
+  double* tabmem = nullptr;
+  CyclicTab ctx_x{}, ctx_z{};
+  YTab yt[2]{};  // 0: u and w, 1: v
+
+  // Poisson
+  FFTPlan px{}, pz{};
+  double* lamx = nullptr;
+  double* lamz = nullptr;
+  double* ylo = nullptr;
+  double* yhi = nullptr;
+  double sum_dy = 0, vtot = 0;
+
+  Prof prof;
+};
+
+template <typename T>
+static int dalloc(ibm_ctx* c, T** p, int64_t n) {
+  void* q = nullptr;
+  size_t bytes = (size_t)std::max<int64_t>(n, 1) * sizeof(T);
+  if (hipMalloc(&q, bytes) != hipSuccess) {
+    (void)hipGetLastError();
+    g_last_error = "hipMalloc of " + std::to_string(bytes) + " bytes failed";
+    return IBM_ENOMEM;
+  }
+  c->allocs.push_back(q);
+  *p = (T*)q;
+  return IBM_OK;
+}
+
+template <typename T>
+static int upload(ibm_ctx* c, T* dst, const std::vector<T>& src) {
+  HIPCHK(hipMemcpy(dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice));
+  (void)c;
+  return IBM_OK;
+}
+
+static bool plan_fft(int n, FFTPlan* P) {
+  P->n = n;
+  P->nst = 0;
+  int m = n;
+  const int radices[5] = {4, 2, 3, 5, 7};
+  for (int r : radices) {
+    while (m % r == 0) {
+      if (r == 2 && m % 4 == 0) break;
+      if (P->nst >= 16) return false;
+      P->radix[P->nst++] = r;
+      m /= r;
+    }
+  }
+  return m == 1;
+}
+
+static int make_twiddles(ibm_ctx* c, FFTPlan* P) {
+  std::vector<double2> tw(P->n);
+  for (int k = 0; k < P->n; ++k) {
+    const long double a = 2.0L * 3.14159265358979323846264338327950288L * k / P->n;
+    tw[k] = make_double2((double)cosl(a), (double)(-sinl(a)));
+  }
+  double2* d = nullptr;
+  int rc = dalloc(c, &d, P->n);
+  if (rc) return rc;
+  rc = upload(c, d, tw);
+  if (rc) return rc;
+  P->tw = d;
+  return IBM_OK;
+}
+
+// Thomas factorisation tables of the line solves for one beta (host FP64).
+static int build_tables(ibm_ctx* c, double beta) {
+  if (beta == c->tab_beta) return IBM_OK;
+  const int nx = c->nx, nz = c->nz, ny = c->ny;
+  std::vector<double> h;
+  auto cyclic = [&](int n, double hsp, CyclicTab* t, std::vector<double>& out) {
+    const double r = beta / (hsp * hsp);
+    const double a = -r, cc = -r, b = 1.0 + 2.0 * r;
+    const double gam = -b;
+    std::vector<double> cp(n), inv(n), W(n), Z(n), zp(n);
+    const double t00 = b - gam;
+    const double tnn = b - cc * a / gam;  // corner product A[n-1][0] A[0][n-1]
+    inv[0] = 1.0 / t00;
+    cp[0] = cc * inv[0];
+    for (int i = 1; i < n; ++i) {
+      const double bi = (i == n - 1) ? tnn : b;
+      inv[i] = 1.0 / (bi - a * cp[i - 1]);
+      cp[i] = (i == n - 1) ? 0.0 : cc * inv[i];
+    }
+    W[0] = 1.0;
+    for (int i = 1; i < n; ++i) W[i] = -W[i - 1] * cp[i - 1];
+    for (int i = 0; i < n; ++i) {
+      const double ui = (i == 0) ? gam : (i == n - 1 ? cc : 0.0);
+      zp[i] = (ui - (i ? a * zp[i - 1] : 0.0)) * inv[i];
+    }
+    Z[n - 1] = zp[n - 1];
+    for (int i = n - 2; i >= 0; --i) Z[i] = zp[i] - cp[i] * Z[i + 1];
+    t->a = a;
+    t->b = b;
+    t->c = cc;
+    t->ratio = a / gam;
+    t->fden_inv = 1.0 / (1.0 + Z[0] + t->ratio * Z[n - 1]);
+    for (auto* v : {&cp, &inv, &W, &Z}) out.insert(out.end(), v->begin(), v->end());
+  };
+  auto ysys = [&](bool isv, std::vector<double>& out, YTab* t) {
+    const int n = isv ? ny - 1 : ny;
+    std::vector<double> A(n), B(n), C(n), cp(n), inv(n);
+    for (int r = 0; r < n; ++r) {
+      double lo, hi;
+      if (isv) {
+        const int j = r + 1;
+        lo = beta / (c->dy[j - 1] * c->dyc[j]);
+        hi = beta / (c->dy[j] * c->dyc[j]);
+      } else {
+        lo = beta / (c->dyc[r] * c->dy[r]);
+        hi = beta / (c->dyc[r + 1] * c->dy[r]);
+      }
+      A[r] = (r > 0) ? -lo : 0.0;
+      C[r] = (r < n - 1) ? -hi : 0.0;
+      B[r] = 1.0 + (lo + hi);
+    }
+    for (int r = 0; r < n; ++r) {
+      inv[r] = 1.0 / (B[r] - (r ? A[r] * cp[r - 1] : 0.0));
+      cp[r] = C[r] * inv[r];
+    }
+    t->n = n;
+    t->j0 = isv ? 1 : 0;
+    for (auto* v : {&A, &B, &C, &cp, &inv}) out.insert(out.end(), v->begin(), v->end());
+  };
+  std::vector<double> hx, hz, hy0, hy1;
+  cyclic(nx, c->g.dx, &c->ctx_x, hx);
+  cyclic(nz, c->g.dz, &c->ctx_z, hz);
+  ysys(false, hy0, &c->yt[0]);
+  ysys(true, hy1, &c->yt[1]);
+  h.insert(h.end(), hx.begin(), hx.end());
+  h.insert(h.end(), hz.begin(), hz.end());
+  h.insert(h.end(), hy0.begin(), hy0.end());
+  h.insert(h.end(), hy1.begin(), hy1.end());
+  // the tables are read by kernels already enqueued: order the update on the
+  // stream, and keep the host copy alive until it has been consumed
+  HIPCHK(hipStreamSynchronize(c->stream));
+  HIPCHK(hipMemcpy(c->tabmem, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice));
+  double* p = c->tabmem;
+  auto take = [&](int n) {
+    const double* q = p;
+    p += n;
+    return q;
+  };
+  c->ctx_x.cp = take(nx); c->ctx_x.inv = take(nx); c->ctx_x.W = take(nx); c->ctx_x.Z = take(nx);
+  c->ctx_z.cp = take(nz); c->ctx_z.inv = take(nz); c->ctx_z.W = take(nz); c->ctx_z.Z = take(nz);
+  for (int q = 0; q < 2; ++q) {
+    const int n = c->yt[q].n;
+    c->yt[q].a = take(n); c->yt[q].b = take(n); c->yt[q].c = take(n);
+    c->yt[q].cp = take(n); c->yt[q].inv = take(n);
+  }
+  c->tab_beta = beta;
+  return IBM_OK;
+}
+
+static void free_all(ibm_ctx* c) {
+  for (void* p : c->allocs) (void)hipFree(p);
+  c->allocs.clear();
+  if (c->hslots) (void)hipHostFree(c->hslots);
+  c->hslots = nullptr;
+  for (auto& e : c->slot_ev)
+    if (e) (void)hipEventDestroy(e);
+  for (auto& r : c->prof.recs) {
+    (void)hipEventDestroy(r.a);
+    (void)hipEventDestroy(r.b);
+  }
+  for (auto e : c->prof.pool) (void)hipEventDestroy(e);
+}
+
+extern "C" {
+
+const char* ibm_strerror(int code) {
+  switch (code) {
+    case IBM_OK: return "ok";
+    case IBM_EINVAL: return g_last_error.empty() ? "invalid argument" : g_last_error.c_str();
+    case IBM_ENOMEM: return g_last_error.empty() ? "out of device memory" : g_last_error.c_str();
+    case IBM_EHIP: return g_last_error.empty() ? "HIP runtime error" : g_last_error.c_str();
+    case IBM_ECAPACITY: return "forcing-node or boundary-cell list overflowed its capacity";
+    case IBM_ENONFINITE: return "non-finite value in a reduction";
+    case IBM_EGEOM: return "geometry limit: body too large for the periodic box, probe leaving "
+                           "the channel, or probe stencil containing its own node";
+    default: return "unknown error";
+  }
+}
+
+#define FAIL(code, msg)     \
+  do {                      \
+    g_last_error = (msg);   \
+    return (code);          \
+  } while (0)
+
+int ibm_create(const ibm_grid* gr, const ibm_opts* o, void* stream, ibm_ctx** out) {
+  if (!gr || !o || !out) FAIL(IBM_EINVAL, "null argument");
+  *out = nullptr;
+  if (gr->nx < 4 || gr->nz < 4 || gr->ny < 3) FAIL(IBM_EINVAL, "grid too small (nx, nz >= 4, ny >= 3)");
+  if (!gr->y_faces) FAIL(IBM_EINVAL, "y_faces is NULL");
+  if (!(gr->lx > 0) || !(gr->lz > 0) || !(o->re > 0)) FAIL(IBM_EINVAL, "lx, lz and re must be > 0");
+  if (o->precision != IBM_FP64) FAIL(IBM_EINVAL, "only IBM_FP64 is available");
+  if (o->scheme != IBM_RK2CN && o->scheme != IBM_AB2CN) FAIL(IBM_EINVAL, "unknown scheme");
+  for (int j = 0; j < gr->ny; ++j)
+    if (!(gr->y_faces[j + 1] > gr->y_faces[j])) FAIL(IBM_EINVAL, "y_faces not strictly increasing");
+  ibm_ctx* c = new ibm_ctx();
+  int rc = IBM_OK;
+#define TRY(x)                 \
+  do {                         \
+    rc = (x);                  \
+    if (rc) {                  \
+      free_all(c);             \
+      delete c;                \
+      return rc;               \
+    }                          \
+  } while (0)
+  if (hipGetDevice(&c->dev) != hipSuccess) {
+    delete c;
+    FAIL(IBM_EHIP, "no HIP device");
+  }
+  c->stream = (hipStream_t)stream;
+  c->nx = gr->nx;
+  c->ny = gr->ny;
+  c->nz = gr->nz;
+  c->lx = gr->lx;
+  c->lz = gr->lz;
+  c->opts = *o;
+  const int nx = c->nx, ny = c->ny, nz = c->nz;
+  if (!plan_fft(nx, &c->px) || !plan_fft(nz, &c->pz)) {
+    delete c;
+    FAIL(IBM_EINVAL, "nx and nz must factor into 2, 3, 5 and 7");
+  }
+  c->ncell = (int64_t)nx * ny * nz;
+  c->nvface = (int64_t)nx * (ny + 1) * nz;
+  // grid metrics (same operations as any other implementation of the grid)
+  c->yf.assign(gr->y_faces, gr->y_faces + ny + 1);
+  c->yc.resize(ny);
+  c->dy.resize(ny);
+  c->dyc.resize(ny + 1);
+  for (int j = 0; j < ny; ++j) {
+    c->yc[j] = (c->yf[j] + c->yf[j + 1]) * 0.5;
+    c->dy[j] = c->yf[j + 1] - c->yf[j];
+  }
+  c->dyc[0] = c->yc[0] - c->yf[0];
+  for (int j = 1; j < ny; ++j) c->dyc[j] = c->yc[j] - c->yc[j - 1];
+  c->dyc[ny] = c->yf[ny] - c->yc[ny - 1];
+  c->extuw.push_back(c->yf[0]);
+  c->extuw.insert(c->extuw.end(), c->yc.begin(), c->yc.end());
+  c->extuw.push_back(c->yf[ny]);
+  GridView& g = c->g;
+  g.nx = nx;
+  g.ny = ny;
+  g.nz = nz;
+  g.nxh = nx / 2 + 1;
+  g.lx = c->lx;
+  g.lz = c->lz;
+  g.dx = c->lx / nx;
+  g.dz = c->lz / nz;
+  double dm = std::max(g.dx, g.dz);
+  for (double v : c->dyc) dm = std::max(dm, v);
+  for (double v : c->dy) dm = std::max(dm, v);
+  g.dmax = dm;
+  double *dyf, *dyc_, *ddy, *ddyc, *dext;
+  TRY(dalloc(c, &dyf, ny + 1));
+  TRY(dalloc(c, &dyc_, ny));
+  TRY(dalloc(c, &ddy, ny));
+  TRY(dalloc(c, &ddyc, ny + 1));
+  TRY(dalloc(c, &dext, ny + 2));
+  TRY(upload(c, dyf, c->yf));
+  TRY(upload(c, dyc_, c->yc));
+  TRY(upload(c, ddy, c->dy));
+  TRY(upload(c, ddyc, c->dyc));
+  TRY(upload(c, dext, c->extuw));
+  g.yf = dyf;
+  g.yc = dyc_;
+  g.dy = ddy;
+  g.dyc = ddyc;
+  g.extuw = dext;
+
+  // tag buffers
+  TagBuffers& tb = c->tb;
+  tb.cap = o->force_cap > 0 ? o->force_cap : std::max<int64_t>(65536, c->ncell / 16);
+  int64_t maxw = 0;
+  for (int q = 0; q < 3; ++q) {
+    const int64_t nn = (q == 1) ? c->nvface : c->ncell;
+    tb.nwords[q] = (nn + 31) / 32;
+    maxw = std::max(maxw, tb.nwords[q]);
+    TRY(dalloc(c, &tb.mask[q], tb.nwords[q]));
+    TRY(dalloc(c, &tb.best_d[q], nn));
+    TRY(dalloc(c, &tb.best_t[q], nn));
+    TRY(dalloc(c, &tb.idx[q], tb.cap));
+    TRY(dalloc(c, &tb.tri[q], tb.cap));
+    TRY(dalloc(c, &tb.xflag[q], (int64_t)(ny + 1) * nz));
+    TRY(dalloc(c, &tb.zflag[q], (int64_t)(ny + 1) * nx));
+    TRY(dalloc(c, &tb.yflag[q], (int64_t)nz * nx));
+  }
+  tb.nwords_cb = (c->ncell + 31) / 32;
+  TRY(dalloc(c, &tb.cb_mask, tb.nwords_cb));
+  TRY(dalloc(c, &tb.cb, tb.cap));
+  TRY(dalloc(c, &tb.count, 4));
+  TRY(dalloc(c, &tb.block_sums, maxw / 1024 + 2));
+  TRY(dalloc(c, &c->force_vals, 3 * tb.cap));
+  TRY(dalloc(c, &c->dslots, (int64_t)ibm_ctx::NSLOT * 64));
+  if (hipHostMalloc((void**)&c->hslots, sizeof(BodyDev) * ibm_ctx::NSLOT * 64) != hipSuccess) {
+    c->hslots = nullptr;
+    TRY(IBM_ENOMEM);
+  }
+  for (int q = 0; q < ibm_ctx::NSLOT; ++q)
+    if (hipEventCreateWithFlags(&c->slot_ev[q], hipEventDisableTiming) != hipSuccess) TRY(IBM_EHIP);
+
+  for (int q = 0; q < 3; ++q) {
+    const int64_t nn = (q == 1) ? c->nvface : c->ncell;
+    TRY(dalloc(c, &c->R[q], nn));
+    TRY(dalloc(c, &c->H[q], nn));
+    TRY(dalloc(c, &c->scratch[q], nn));
+  }
+  TRY(dalloc(c, &c->rhs_tmp, c->ncell));
+  TRY(dalloc(c, &c->phi, c->ncell));
+  const int64_t nspec = (int64_t)ny * nz * g.nxh;
+  TRY(dalloc(c, &c->spec, nspec));
+  TRY(dalloc(c, &c->cscr, nspec));
+  TRY(dalloc(c, &c->partial, 512));
+  TRY(dalloc(c, &c->qf, 1));
+  TRY(dalloc(c, &c->flags, 1));
+  TRY(dalloc(c, &c->tabmem, 4 * (int64_t)(nx + nz) + 10 * (int64_t)ny));
+
+  // Poisson tables
+  TRY(make_twiddles(c, &c->px));
+  TRY(make_twiddles(c, &c->pz));
+  {
+    std::vector<double> lx(g.nxh), lz(nz), lo(ny, 0.0), hi(ny, 0.0);
+    const double pi = 3.14159265358979323846;
+    for (int p = 0; p < g.nxh; ++p) {
+      const double s = std::sin(pi * p / nx);
+      lx[p] = -(4.0 / (g.dx * g.dx)) * s * s;
+    }
+    for (int m = 0; m < nz; ++m) {
+      const double s = std::sin(pi * m / nz);
+      lz[m] = -(4.0 / (g.dz * g.dz)) * s * s;
+    }
+    for (int j = 1; j < ny; ++j) lo[j] = 1.0 / (c->dyc[j] * c->dy[j]);
+    for (int j = 0; j + 1 < ny; ++j) hi[j] = 1.0 / (c->dyc[j + 1] * c->dy[j]);
+    TRY(dalloc(c, &c->lamx, g.nxh));
+    TRY(dalloc(c, &c->lamz, nz));
+    TRY(dalloc(c, &c->ylo, ny));
+    TRY(dalloc(c, &c->yhi, ny));
+    TRY(upload(c, c->lamx, lx));
+    TRY(upload(c, c->lamz, lz));
+    TRY(upload(c, c->ylo, lo));
+    TRY(upload(c, c->yhi, hi));
+    c->sum_dy = 0;
+    for (double v : c->dy) c->sum_dy += v;
+    c->vtot = g.dx * g.dz * (double)nx * (double)nz * c->sum_dy;
+  }
+  // initial state of the tag scratch: best keys at +inf, flags clear
+  for (int q = 0; q < 3; ++q) {
+    const int64_t nn = (q == 1) ? c->nvface : c->ncell;
+    launch_fill_u64(nullptr, c->stream, tb.best_d[q], nn, ~0ull);
+    launch_fill_i32(nullptr, c->stream, tb.best_t[q], nn, 0x7fffffff);
+    launch_fill_u32(nullptr, c->stream, tb.mask[q], tb.nwords[q], 0u);
+    launch_fill_u8(nullptr, c->stream, tb.xflag[q], (int64_t)(ny + 1) * nz, 0);
+    launch_fill_u8(nullptr, c->stream, tb.zflag[q], (int64_t)(ny + 1) * nx, 0);
+    launch_fill_u8(nullptr, c->stream, tb.yflag[q], (int64_t)nz * nx, 0);
+  }
+  launch_fill_u32(nullptr, c->stream, tb.cb_mask, tb.nwords_cb, 0u);
+  launch_fill_u32(nullptr, c->stream, c->flags, 1, 0u);
+  launch_fill_u64(nullptr, c->stream, reinterpret_cast<u64*>(tb.count), 4, 0ull);
+  launch_fill_f64(nullptr, c->stream, c->qf, 1, 0.0);
+  if (hipStreamSynchronize(c->stream) != hipSuccess || hipGetLastError() != hipSuccess) {
+    free_all(c);
+    delete c;
+    FAIL(IBM_EHIP, "initialisation kernels failed");
+  }
+#undef TRY
+  *out = c;
+  return IBM_OK;
+}
+
+void ibm_destroy(ibm_ctx* c) {
+  if (!c) return;
+  (void)hipStreamSynchronize(c->stream);
+  free_all(c);
+  delete c;
+}
+
+int ibm_set_stream(ibm_ctx* c, void* stream) {
+  if (!c) FAIL(IBM_EINVAL, "null context");
+  c->stream = (hipStream_t)stream;
+  return IBM_OK;
+}
+
+static int launch_status() {
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) FAIL(IBM_EHIP, std::string("kernel launch: ") + hipGetErrorString(e));
+  return IBM_OK;
+}
+
+int ibm_body_rigid(ibm_ctx* c, const double* x0, int32_t nv, const double* coef, double* xyz,
+                   double* vel) {
+  if (!c || !coef || nv < 0 || (nv > 0 && (!x0 || !xyz || !vel))) FAIL(IBM_EINVAL, "ibm_body_rigid: bad argument");
+  launch_body_rigid(&c->prof, c->stream, x0, nv, coef, xyz, vel);
+  return launch_status();
+}
+
+int ibm_body_deform(ibm_ctx* c, const double* data, int32_t nv, const double* coef, double* xyz,
+                    double* vel) {
+  if (!c || !coef || nv < 0 || (nv > 0 && (!data || !xyz || !vel))) FAIL(IBM_EINVAL, "ibm_body_deform: bad argument");
+  launch_body_deform(&c->prof, c->stream, data, nv, coef, xyz, vel);
+  return launch_status();
+}
+
+static int set_bodies(ibm_ctx* c, const ibm_body* b, int32_t nb) {
+  if (nb < 0 || (nb > 0 && !b)) FAIL(IBM_EINVAL, "bad body list");
+  if (nb > 64) FAIL(IBM_EINVAL, "at most 64 bodies per context");
+  c->bodies.clear();
+  int64_t off = 0;
+  for (int i = 0; i < nb; ++i) {
+    if (b[i].nt < 0 || b[i].nv < 0 || (b[i].nt > 0 && (!b[i].xyz || !b[i].vel || !b[i].tri)))
+      FAIL(IBM_EINVAL, "bad body");
+    BodyDev d;
+    d.xyz = b[i].xyz;
+    d.vel = b[i].vel;
+    d.tri = b[i].tri;
+    d.nt = b[i].nt;
+    d.toff = (int32_t)off;
+    off += b[i].nt;
+    if (off > INT32_MAX) FAIL(IBM_EINVAL, "too many triangles");
+    c->bodies.push_back(d);
+  }
+  c->ntri = (int)off;
+  return IBM_OK;
+}
+
+}  // extern "C"
+
+// Body descriptors live in device memory: a small ring of device slots
+// filled by stream-ordered copies from pinned host slots.  An unchanged list
+// (the usual case from one step to the next) reuses the current slot and
+// costs no copy; a pinned slot is rewritten only after its previous copy has
+// completed (its event), so no copy ever reads a slot being rewritten.
+static int upload_bodies(ibm_ctx* c) {
+  const size_t n = c->bodies.size();
+  if (n == 0) {
+    c->d_bodies = nullptr;
+    return IBM_OK;
+  }
+  if (c->cur_slot >= 0 && c->last_bodies == c->bodies) {
+    c->d_bodies = c->dslots + (size_t)c->cur_slot * 64;
+    return IBM_OK;
+  }
+  const int k = (c->cur_slot + 1) % ibm_ctx::NSLOT;
+  if (c->slot_used[k]) HIPCHK(hipEventSynchronize(c->slot_ev[k]));
+  std::memcpy(c->hslots + (size_t)k * 64, c->bodies.data(), n * sizeof(BodyDev));
+  HIPCHK(hipMemcpyAsync(c->dslots + (size_t)k * 64, c->hslots + (size_t)k * 64,
+                        n * sizeof(BodyDev), hipMemcpyHostToDevice, c->stream));
+  HIPCHK(hipEventRecord(c->slot_ev[k], c->stream));
+  c->slot_used[k] = true;
+  c->cur_slot = k;
+  c->last_bodies = c->bodies;
+  c->d_bodies = c->dslots + (size_t)k * 64;
+  return IBM_OK;
+}
+
+extern "C" {
+
+int ibm_tag(ibm_ctx* c, const ibm_body* b, int32_t nb, ibm_tags* out) {
+  if (!c) FAIL(IBM_EINVAL, "null context");
+  int rc = set_bodies(c, b, nb);
+  if (rc) return rc;
+  rc = upload_bodies(c);
+  if (rc) return rc;
+  launch_tag(&c->prof, c->stream, c->g, c->d_bodies, (int)c->bodies.size(), c->ntri, c->tb,
+             c->flags);
+  rc = launch_status();
+  if (rc) return rc;
+  if (out) {
+    for (int q = 0; q < 3; ++q) {
+      out->idx[q] = c->tb.idx[q];
+      out->tri[q] = c->tb.tri[q];
+      out->mask[q] = c->tb.mask[q];
+    }
+    out->cb = c->tb.cb;
+    out->count = c->tb.count;
+    out->cb_mask = c->tb.cb_mask;
+    out->capacity = c->tb.cap;
+  }
+  return IBM_OK;
+}
+
+int ibm_tags_count_host(ibm_ctx* c, int64_t* counts) {
+  if (!c || !counts) FAIL(IBM_EINVAL, "null argument");
+  HIPCHK(hipStreamSynchronize(c->stream));
+  HIPCHK(hipMemcpy(counts, c->tb.count, 4 * sizeof(int64_t), hipMemcpyDeviceToHost));
+  return IBM_OK;
+}
+
+int ibm_tags_copy(ibm_ctx* c, int32_t list, int64_t* idx_dst, int32_t* tri_dst, int64_t n) {
+  if (!c || list < 0 || list > 3 || n < 0 || n > c->tb.cap || (n > 0 && !idx_dst))
+    FAIL(IBM_EINVAL, "ibm_tags_copy: bad argument");
+  if (n == 0) return IBM_OK;
+  const int64_t* src = (list == 3) ? c->tb.cb : c->tb.idx[list];
+  HIPCHK(hipMemcpyAsync(idx_dst, src, n * sizeof(int64_t), hipMemcpyDeviceToDevice, c->stream));
+  if (tri_dst && list < 3)
+    HIPCHK(hipMemcpyAsync(tri_dst, c->tb.tri[list], n * sizeof(int32_t), hipMemcpyDeviceToDevice,
+                          c->stream));
+  return IBM_OK;
+}
+
+int ibm_force(ibm_ctx* c, double* u, double* v, double* w) {
+  if (!c || !u || !v || !w) FAIL(IBM_EINVAL, "null argument");
+  double* f[3] = {u, v, w};
+  launch_force(&c->prof, c->stream, c->g, c->d_bodies, (int)c->bodies.size(), c->tb, f,
+               c->force_vals, c->flags);
+  return launch_status();
+}
+
+static int viscous(ibm_ctx* c, const double* p, const double* const* hprev, double* const* hout,
+                   double gamma, double rho, double dt, double* u, double* v, double* w) {
+  const double alpha = gamma + rho;
+  int rc = build_tables(c, alpha * dt / (2.0 * c->opts.re));
+  if (rc) return rc;
+  RhsArgs a{};
+  a.u = u;
+  a.v = v;
+  a.w = w;
+  a.p = p;
+  for (int q = 0; q < 3; ++q) {
+    a.hprev[q] = hprev ? hprev[q] : nullptr;
+    a.hout[q] = hout ? hout[q] : nullptr;
+    a.R[q] = c->R[q];
+    a.mask[q] = c->tb.mask[q];
+  }
+  if (rho != 0.0 && (!a.hprev[0] || !a.hprev[1] || !a.hprev[2]))
+    FAIL(IBM_EINVAL, "rho != 0 needs the previous H");
+  a.gamma = gamma;
+  a.rho = rho;
+  a.alpha = alpha;
+  a.dt = dt;
+  a.re = c->opts.re;
+  a.fx = -c->opts.dpdx;
+  launch_rhs(&c->prof, c->stream, c->g, a);
+  double* f[3] = {u, v, w};
+  for (int q = 0; q < 3; ++q) {
+    launch_adi_x(&c->prof, c->stream, c->g, q, c->R[q], c->tb.xflag[q], c->tb.mask[q], c->ctx_x,
+                 c->scratch[q]);
+    launch_adi_z(&c->prof, c->stream, c->g, q, c->R[q], c->tb.zflag[q], c->tb.mask[q], c->ctx_z,
+                 c->scratch[q]);
+    launch_adi_y(&c->prof, c->stream, c->g, q, c->R[q], f[q], c->tb.yflag[q], c->tb.mask[q],
+                 c->yt[q == 1 ? 1 : 0], c->scratch[q]);
+  }
+  return launch_status();
+}
+
+int ibm_viscous(ibm_ctx* c, const double* p, const double* const* h_prev, double* const* h_out,
+                double gamma, double rho, double dt, double* u, double* v, double* w) {
+  if (!c || !p || !u || !v || !w || !(dt > 0)) FAIL(IBM_EINVAL, "ibm_viscous: bad argument");
+  return viscous(c, p, h_prev, h_out, gamma, rho, dt, u, v, w);
+}
+
+int ibm_mass_rhs(ibm_ctx* c, const double* u, const double* v, const double* w, double alpha_dt,
+                 double* rhs, double* qf) {
+  if (!c || !u || !v || !w || !rhs || !(alpha_dt > 0)) FAIL(IBM_EINVAL, "ibm_mass_rhs: bad argument");
+  launch_mass(&c->prof, c->stream, c->g, u, v, w, c->tb.cb, c->tb.count, c->tb.cap, c->vtot,
+              c->opts.use_q, c->partial, c->qf, c->flags);
+  launch_mass_rhs(&c->prof, c->stream, c->g, u, v, w, c->opts.use_q ? c->tb.cb_mask : nullptr,
+                  c->qf, 1.0 / alpha_dt, rhs);
+  if (qf) HIPCHK(hipMemcpyAsync(qf, c->qf, sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  return launch_status();
+}
+
+static PoissonArgs pargs(ibm_ctx* c) {
+  PoissonArgs a{};
+  a.px = &c->px;
+  a.pz = &c->pz;
+  a.lamx = c->lamx;
+  a.lamz = c->lamz;
+  a.ylo = c->ylo;
+  a.yhi = c->yhi;
+  a.spec = c->spec;
+  a.cscr = c->cscr;
+  a.sum_dy = c->sum_dy;
+  return a;
+}
+
+int poisson_solve(ibm_ctx* c, const double* rhs, double* phi) {
+  if (!c || !rhs || !phi) FAIL(IBM_EINVAL, "poisson_solve: bad argument");
+  launch_poisson(&c->prof, c->stream, c->g, pargs(c), rhs, nullptr, nullptr, nullptr, nullptr,
+                 nullptr, 1.0, phi);
+  return launch_status();
+}
+
+int ibm_project(ibm_ctx* c, const double* phi, double alpha_dt, double* u, double* v, double* w,
+                double* p) {
+  if (!c || !phi || !u || !v || !w || !p) FAIL(IBM_EINVAL, "ibm_project: bad argument");
+  launch_project(&c->prof, c->stream, c->g, phi, alpha_dt, c->opts.re, u, v, w, p);
+  return launch_status();
+}
+
+int ibm_step(ibm_ctx* c, ibm_state* s, const ibm_body* b, int32_t nb, double dt) {
+  if (!c || !s || !s->u || !s->v || !s->w || !s->p || !(dt > 0)) FAIL(IBM_EINVAL, "ibm_step: bad argument");
+  int rc = ibm_tag(c, b, nb, nullptr);
+  if (rc) return rc;
+  struct Sub {
+    double gamma, rho;
+    const double* const* hprev;
+    double* const* hout;
+  };
+  double* H1[3] = {c->H[0], c->H[1], c->H[2]};
+  std::vector<Sub> subs;
+  if (c->opts.scheme == IBM_RK2CN) {
+    subs.push_back({0.5, 0.0, nullptr, H1});
+    subs.push_back({1.0, -0.5, H1, nullptr});
+  } else {
+    if (!s->h[0] || !s->h[1] || !s->h[2]) FAIL(IBM_EINVAL, "AB+CN needs state->h");
+    subs.push_back({1.5, -0.5, s->h, s->h});
+  }
+  double* f[3] = {s->u, s->v, s->w};
+  for (const Sub& sb : subs) {
+    const double alpha = sb.gamma + sb.rho;
+    launch_force(&c->prof, c->stream, c->g, c->d_bodies, (int)c->bodies.size(), c->tb, f,
+                 c->force_vals, c->flags);
+    rc = viscous(c, s->p, sb.hprev, sb.hout, sb.gamma, sb.rho, dt, s->u, s->v, s->w);
+    if (rc) return rc;
+    launch_mass(&c->prof, c->stream, c->g, s->u, s->v, s->w, c->tb.cb, c->tb.count, c->tb.cap,
+                c->vtot, c->opts.use_q, c->partial, c->qf, c->flags);
+    launch_poisson(&c->prof, c->stream, c->g, pargs(c), nullptr, s->u, s->v, s->w,
+                   c->opts.use_q ? c->tb.cb_mask : nullptr, c->qf, 1.0 / (alpha * dt), c->phi);
+    launch_project(&c->prof, c->stream, c->g, c->phi, alpha * dt, c->opts.re, s->u, s->v, s->w,
+                   s->p);
+    rc = launch_status();
+    if (rc) return rc;
+  }
+  return IBM_OK;
+}
+
+int ibm_check(ibm_ctx* c, uint32_t* flags) {
+  if (!c || !flags) FAIL(IBM_EINVAL, "null argument");
+  HIPCHK(hipStreamSynchronize(c->stream));
+  HIPCHK(hipMemcpy(flags, c->flags, sizeof(uint32_t), hipMemcpyDeviceToHost));
+  launch_fill_u32(nullptr, c->stream, c->flags, 1, 0u);
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return IBM_OK;
+}
+
+int ibm_profile(ibm_ctx* c, int32_t enable, const char* filter) {
+  if (!c) FAIL(IBM_EINVAL, "null context");
+  c->prof.enabled = enable != 0;
+  c->prof.filter = filter ? filter : "";
+  return IBM_OK;
+}
+
+int ibm_profile_read(ibm_ctx* c, char* names, int32_t name_len, int64_t* launches,
+                     double* total_ms, int32_t cap) {
+  if (!c) FAIL(IBM_EINVAL, "null context");
+  HIPCHK(hipStreamSynchronize(c->stream));
+  std::vector<std::string> nm;
+  std::vector<int64_t> cnt;
+  std::vector<double> tot;
+  for (auto& r : c->prof.recs) {
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, r.a, r.b);
+    size_t k = 0;
+    while (k < nm.size() && nm[k] != r.name) ++k;
+    if (k == nm.size()) {
+      nm.push_back(r.name);
+      cnt.push_back(0);
+      tot.push_back(0.0);
+    }
+    cnt[k] += 1;
+    tot[k] += ms;
+    c->prof.pool.push_back(r.a);
+    c->prof.pool.push_back(r.b);
+  }
+  c->prof.recs.clear();
+  int n = 0;
+  for (size_t k = 0; k < nm.size() && n < cap; ++k, ++n) {
+    if (names && name_len > 0) {
+      std::strncpy(names + (size_t)n * name_len, nm[k].c_str(), name_len - 1);
+      names[(size_t)n * name_len + name_len - 1] = 0;
+    }
+    if (launches) launches[n] = cnt[k];
+    if (total_ms) total_ms[n] = tot[k];
+  }
+  return n;
+}
+
+}  // extern "C"

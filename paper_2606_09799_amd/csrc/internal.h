@@ -1,0 +1,179 @@
+// Internal declarations shared by the HIP translation units of libibm.
+// Not part of the public ABI (include/ibm.h is).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+
+namespace ibm {
+
+typedef unsigned long long u64;
+
+// Grid metrics as seen by the kernels (all device pointers).  The y lattice of
+// a component including its two wall points ("ext"): u and w use extuw
+// (ny+2 heights: yf[0], yc[0..ny-1], yf[ny]; node j <-> ext index j+1); v uses
+// yf (ny+1 heights; node j <-> ext index j).
+struct GridView {
+  int nx, ny, nz, nxh;  // nxh = nx/2 + 1 (half spectrum)
+  double dx, dz, lx, lz;
+  double dmax;          // largest same-lattice neighbour distance
+  const double* yf;     // ny+1
+  const double* yc;     // ny
+  const double* dy;     // ny
+  const double* dyc;    // ny+1
+  const double* extuw;  // ny+2
+};
+
+struct BodyDev {
+  const double* xyz;
+  const double* vel;
+  const int32_t* tri;
+  int32_t nt;
+  int32_t toff;  // global id of the body's first triangle
+};
+inline bool operator==(const BodyDev& a, const BodyDev& b) {
+  return a.xyz == b.xyz && a.vel == b.vel && a.tri == b.tri && a.nt == b.nt && a.toff == b.toff;
+}
+
+// Coefficient tables of the three line-solve directions for one beta
+// (device arrays).  Cyclic x/z: the Thomas factorisation of the matrix with
+// its corners removed (Sherman-Morrison form), the weights W that give
+// y_0 = sum_i W_i d'_i during the forward sweep, and z = T^{-1} u.
+struct CyclicTab {
+  const double* cp;
+  const double* inv;
+  const double* W;
+  const double* Z;
+  double a, b, c;        // constant sub/main/super diagonal
+  double ratio;          // beta_corner / gamma
+  double fden_inv;       // 1 / (1 + z_0 + ratio z_{n-1})
+};
+
+struct YTab {
+  // rows r = 0..n-1 of the wall-normal system of one lattice (u/w: n = ny,
+  // row r <-> node j = r; v: n = ny-1, row r <-> node j = r+1)
+  const double* a;   // sub-diagonal
+  const double* b;   // diagonal
+  const double* c;   // super-diagonal
+  const double* cp;  // Thomas c' of the mask-free system
+  const double* inv; // 1/pivot of the mask-free system
+  int n, j0;
+};
+
+struct FFTPlan {
+  int n;
+  int nst;
+  int radix[16];
+  const double2* tw;  // exp(-2 pi i k/n), k = 0..n-1
+};
+
+// profiling hook (ctx.cpp): an event pair around each kernel launch when
+// profiling is enabled and the kernel name matches the filter
+struct Prof;
+void prof_begin(Prof* p, const char* name, hipStream_t s);
+void prof_end(Prof* p, hipStream_t s);
+#define IBM_LAUNCH(pf, name, s, ...)  \
+  do {                                \
+    ::ibm::prof_begin(pf, name, s);   \
+    __VA_ARGS__;                      \
+    ::ibm::prof_end(pf, s);           \
+  } while (0)
+
+// sticky flags (same bits as IBM_FLAG_*)
+constexpr uint32_t FLAG_CAPACITY = 1u, FLAG_NONFINITE = 2u, FLAG_GEOM = 4u;
+
+// ------------------------------------------------------------ launchers
+// body.hip
+void launch_body_rigid(Prof* pf, hipStream_t s, const double* x0, int nv, const double* coef,
+                       double* xyz, double* vel);
+void launch_body_deform(Prof* pf, hipStream_t s, const double* data, int nv, const double* coef,
+                        double* xyz, double* vel);
+
+// tag.hip
+struct TagBuffers {
+  uint32_t* mask[3];
+  u64* best_d[3];
+  int32_t* best_t[3];
+  int64_t* idx[3];
+  int32_t* tri[3];
+  int64_t* cb;
+  uint32_t* cb_mask;
+  int64_t* count;        // [4]
+  uint8_t* xflag[3];     // (ny+1)*nz
+  uint8_t* zflag[3];     // (ny+1)*nx
+  uint8_t* yflag[3];     // nz*nx
+  int64_t* block_sums;   // scan scratch
+  int64_t cap;
+  int64_t nwords[3];     // mask words per component
+  int64_t nwords_cb;
+};
+void launch_tag(Prof* pf, hipStream_t s, const GridView& g, const BodyDev* bodies, int nbody,
+                int ntri, TagBuffers& tb, uint32_t* flags);
+
+// force.hip
+void launch_force(Prof* pf, hipStream_t s, const GridView& g, const BodyDev* bodies, int nbody,
+                  const TagBuffers& tb, double* const* fields, double* vals,
+                  uint32_t* flags);
+
+// rhs.hip
+struct RhsArgs {
+  const double *u, *v, *w, *p;
+  const double* hprev[3];
+  double* hout[3];
+  double* R[3];
+  const uint32_t* mask[3];
+  double gamma, rho, alpha, dt, re, fx;
+};
+void launch_rhs(Prof* pf, hipStream_t s, const GridView& g, const RhsArgs& a);
+
+// adi.hip
+void launch_adi_x(Prof* pf, hipStream_t s, const GridView& g, int comp, double* d,
+                  const uint8_t* xflag, const uint32_t* mask, const CyclicTab& t,
+                  double* scratch);
+void launch_adi_z(Prof* pf, hipStream_t s, const GridView& g, int comp, double* d,
+                  const uint8_t* zflag, const uint32_t* mask, const CyclicTab& t,
+                  double* scratch);
+void launch_adi_y(Prof* pf, hipStream_t s, const GridView& g, int comp, const double* d,
+                  double* u, const uint8_t* yflag, const uint32_t* mask, const YTab& t,
+                  double* scratch);
+
+// mass.hip
+void launch_mass(Prof* pf, hipStream_t s, const GridView& g, const double* u, const double* v,
+                 const double* w, const int64_t* cb, const int64_t* count, int64_t cap,
+                 double vtot, int use_q, double* partial, double* qf, uint32_t* flags);
+void launch_mass_rhs(Prof* pf, hipStream_t s, const GridView& g, const double* u, const double* v,
+                     const double* w, const uint32_t* cb_mask, const double* qf,
+                     double inv_adt, double* rhs);
+
+// poisson.hip
+struct PoissonArgs {
+  const FFTPlan* px;   // length nx (host copy of the plan, tables on device)
+  const FFTPlan* pz;   // length nz
+  const double* lamx;  // nxh
+  const double* lamz;  // nz
+  const double* ylo;   // ny: coefficient of phi[j-1]
+  const double* yhi;   // ny: coefficient of phi[j+1]
+  double2* spec;       // ny*nz*nxh
+  double* cscr;        // ny*nz*nxh real scratch
+  double sum_dy;
+};
+// rhs from an array (rhs != NULL) or formed on the fly from the velocity
+// (rhs == NULL): (D u - q_F)/alpha_dt on C_F, 0 on C_B
+void launch_poisson(Prof* pf, hipStream_t s, const GridView& g, const PoissonArgs& a,
+                    const double* rhs, const double* u, const double* v, const double* w,
+                    const uint32_t* cb_mask, const double* qf, double inv_adt, double* phi);
+
+// project.hip
+void launch_project(Prof* pf, hipStream_t s, const GridView& g, const double* phi, double adt,
+                    double re, double* u, double* v, double* w, double* p);
+
+// utilities (util.hip)
+void launch_fill_u32(Prof* pf, hipStream_t s, uint32_t* p, int64_t n, uint32_t val);
+void launch_fill_u8(Prof* pf, hipStream_t s, uint8_t* p, int64_t n, uint8_t val);
+void launch_fill_u64(Prof* pf, hipStream_t s, u64* p, int64_t n, u64 val);
+void launch_fill_i32(Prof* pf, hipStream_t s, int32_t* p, int64_t n, int32_t val);
+void launch_fill_f64(Prof* pf, hipStream_t s, double* p, int64_t n, double val);
+
+
+}  // namespace ibm

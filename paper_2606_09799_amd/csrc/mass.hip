@@ -1,0 +1,126 @@
+// Consistent mass correction (paper Sec. 3.2, Eqs. mod_div, q_boundary, q_F,
+// elliptic_mod):
+//   A   = sum over C_B of (D u_hat) dV,   V_B = sum over C_B of dV,
+//   q_F = -A / |C_F|,  |C_F| = V_total - V_B,
+//   rhs = (D u_hat - q_F)/(alpha dt) on C_F and 0 on C_B.
+// The sums run over the sorted C_B list only (O(surface) work), in a fixed
+// two-level order (a fixed partition into blocks, a fixed tree inside each
+// block, then a fixed tree over the block partials), so the result is
+// reproducible bit for bit from run to run.  No floating-point atomics.
+#include "geom.h"
+
+namespace ibm {
+
+constexpr int MB = 256;   // blocks of the first level
+constexpr int MT = 256;   // threads per block
+
+__device__ __forceinline__ double div_at(const GridView& g, const double* u, const double* v,
+                                         const double* w, int64_t cell) {
+  const int64_t plane = (int64_t)g.nz * g.nx;
+  const int i = (int)(cell % g.nx);
+  const int k = (int)((cell / g.nx) % g.nz);
+  const int j = (int)(cell / plane);
+  const int ip = (i + 1 == g.nx) ? 0 : i + 1;
+  const int kp = (k + 1 == g.nz) ? 0 : k + 1;
+  const int64_t row = (int64_t)j * plane + (int64_t)k * g.nx;
+  return (u[row + ip] - u[cell]) / g.dx + (v[cell + plane] - v[cell]) / g.dy[j] +
+         (w[(int64_t)j * plane + (int64_t)kp * g.nx + i] - w[cell]) / g.dz;
+}
+
+__global__ __launch_bounds__(MT) void k_mass_partial(GridView g, const double* __restrict__ u,
+                                                     const double* __restrict__ v,
+                                                     const double* __restrict__ w,
+                                                     const int64_t* __restrict__ cb,
+                                                     const int64_t* __restrict__ count, int64_t cap,
+                                                     double* __restrict__ partial) {
+  __shared__ double sa[MT], sv[MT];
+  int64_t n = count[3];
+  if (n > cap) n = cap;
+  const int64_t chunk = (n + MB - 1) / MB;
+  const int64_t lo = blockIdx.x * chunk;
+  const int64_t hi = (lo + chunk < n) ? lo + chunk : n;
+  double A = 0.0, V = 0.0;
+  const double dxdz = g.dx * g.dz;
+  for (int64_t f = lo + threadIdx.x; f < hi; f += MT) {
+    const int64_t cell = cb[f];
+    const int j = (int)(cell / ((int64_t)g.nz * g.nx));
+    const double dV = dxdz * g.dy[j];
+    A += div_at(g, u, v, w, cell) * dV;
+    V += dV;
+  }
+  sa[threadIdx.x] = A;
+  sv[threadIdx.x] = V;
+  __syncthreads();
+  for (int off = MT / 2; off > 0; off >>= 1) {
+    if (threadIdx.x < off) {
+      sa[threadIdx.x] += sa[threadIdx.x + off];
+      sv[threadIdx.x] += sv[threadIdx.x + off];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    partial[2 * blockIdx.x] = sa[0];
+    partial[2 * blockIdx.x + 1] = sv[0];
+  }
+}
+
+__global__ __launch_bounds__(MB) void k_mass_final(const double* __restrict__ partial,
+                                                   const int64_t* __restrict__ count, double vtot,
+                                                   int use_q, double* __restrict__ qf,
+                                                   uint32_t* flags) {
+  __shared__ double sa[MB], sv[MB];
+  sa[threadIdx.x] = partial[2 * threadIdx.x];
+  sv[threadIdx.x] = partial[2 * threadIdx.x + 1];
+  __syncthreads();
+  for (int off = MB / 2; off > 0; off >>= 1) {
+    if (threadIdx.x < off) {
+      sa[threadIdx.x] += sa[threadIdx.x + off];
+      sv[threadIdx.x] += sv[threadIdx.x + off];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    double q = 0.0;
+    if (use_q && count[3] > 0) q = -sa[0] / (vtot - sv[0]);
+    if (!isfinite(q)) {
+      atomicOr(flags, FLAG_NONFINITE);
+      q = 0.0;
+    }
+    *qf = q;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_mass_rhs(GridView g, const double* __restrict__ u,
+                                                  const double* __restrict__ v,
+                                                  const double* __restrict__ w,
+                                                  const uint32_t* __restrict__ cb_mask,
+                                                  const double* __restrict__ qf, double inv_adt,
+                                                  double* __restrict__ rhs) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int k = blockIdx.y;
+  const int j = blockIdx.z;
+  if (i >= g.nx) return;
+  const int64_t cell = ((int64_t)j * g.nz + k) * g.nx + i;
+  const double q = *qf;
+  rhs[cell] = (cb_mask && test_bit(cb_mask, cell)) ? 0.0
+                                                   : (div_at(g, u, v, w, cell) - q) * inv_adt;
+}
+
+void launch_mass(Prof* pf, hipStream_t s, const GridView& g, const double* u, const double* v,
+                 const double* w, const int64_t* cb, const int64_t* count, int64_t cap,
+                 double vtot, int use_q, double* partial, double* qf, uint32_t* flags) {
+  IBM_LAUNCH(pf, "mass_partial", s,
+             k_mass_partial<<<MB, MT, 0, s>>>(g, u, v, w, cb, count, cap, partial));
+  IBM_LAUNCH(pf, "mass_final", s,
+             k_mass_final<<<1, MB, 0, s>>>(partial, count, vtot, use_q, qf, flags));
+}
+
+void launch_mass_rhs(Prof* pf, hipStream_t s, const GridView& g, const double* u, const double* v,
+                     const double* w, const uint32_t* cb_mask, const double* qf, double inv_adt,
+                     double* rhs) {
+  dim3 grid((g.nx + 255) / 256, g.nz, g.ny);
+  IBM_LAUNCH(pf, "mass_rhs", s,
+             k_mass_rhs<<<grid, 256, 0, s>>>(g, u, v, w, cb_mask, qf, inv_adt, rhs));
+}
+
+}  // namespace ibm

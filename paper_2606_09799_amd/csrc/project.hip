@@ -1,0 +1,51 @@
+// Projection and pressure update (paper Eqs. projection and update_pressure):
+//   u <- u_hat - alpha dt G phi   on every interior velocity node
+//   p <- p + phi - alpha dt/(2 Re) L_c phi,  L_c = D G (Neumann at the walls)
+// One thread per (i, j, k), x fastest.
+#include "geom.h"
+
+namespace ibm {
+
+__global__ __launch_bounds__(256) void k_project(GridView g, const double* __restrict__ phi,
+                                                 double adt, double pc, double* __restrict__ u,
+                                                 double* __restrict__ v, double* __restrict__ w,
+                                                 double* __restrict__ p) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int k = blockIdx.y;
+  const int j = blockIdx.z;
+  if (i >= g.nx) return;
+  const int64_t plane = (int64_t)g.nz * g.nx;
+  const int64_t c = (int64_t)j * plane + (int64_t)k * g.nx + i;
+  const int im = (i == 0) ? g.nx - 1 : i - 1;
+  const int ip = (i + 1 == g.nx) ? 0 : i + 1;
+  const int km = (k == 0) ? g.nz - 1 : k - 1;
+  const int kp = (k + 1 == g.nz) ? 0 : k + 1;
+  const int64_t row = (int64_t)j * plane + (int64_t)k * g.nx;
+  const double fc = phi[c];
+  const double fw = phi[row + im], fe = phi[row + ip];
+  const double fb = phi[(int64_t)j * plane + (int64_t)km * g.nx + i];
+  const double ft = phi[(int64_t)j * plane + (int64_t)kp * g.nx + i];
+  const double gx = (fc - fw) / g.dx;
+  const double gz = (fc - fb) / g.dz;
+  u[c] -= adt * gx;
+  w[c] -= adt * gz;
+  double fluxs = 0.0, fluxn = 0.0;
+  if (j > 0) {
+    const double gy = (fc - phi[c - plane]) / g.dyc[j];
+    v[c] -= adt * gy;
+    fluxs = gy;
+  }
+  if (j + 1 < g.ny) fluxn = (phi[c + plane] - fc) / g.dyc[j + 1];
+  const double lc = ((fe - fc) / g.dx - gx) / g.dx + ((ft - fc) / g.dz - gz) / g.dz +
+                    (fluxn - fluxs) / g.dy[j];
+  p[c] += fc - pc * lc;
+}
+
+void launch_project(Prof* pf, hipStream_t s, const GridView& g, const double* phi, double adt,
+                    double re, double* u, double* v, double* w, double* p) {
+  dim3 grid((g.nx + 255) / 256, g.nz, g.ny);
+  const double pc = adt / (2.0 * re);
+  IBM_LAUNCH(pf, "project", s, k_project<<<grid, 256, 0, s>>>(g, phi, adt, pc, u, v, w, p));
+}
+
+}  // namespace ibm

@@ -1,0 +1,140 @@
+// Explicit right-hand side of the predictor (paper Eq. NS_prov in delta form):
+//   R = dt [gamma H(u) + rho H_prev - alpha (G p - f) + (alpha/Re) L u]
+// on the fluid nodes, R = 0 on the forcing nodes (Eq. IB_step: those nodes
+// are not predicted) and on the v wall planes.  H = -div(u u) in flux
+// (conservative) form; L the viscous Laplacian with the wall value 0 at half
+// a cell from the first centre; G p the staggered pressure gradient; f the
+// constant driving force along x.
+//
+// One thread per (i, j, k) computes the three components; x is the fastest
+// thread index so every neighbour access of a wavefront is a contiguous row
+// segment.  The neighbourhood reuse across rows is served by the caches.
+#include "geom.h"
+
+namespace ibm {
+
+struct RhsK {
+  GridView g;
+  RhsArgs a;
+};
+
+#define IDX(i, j, k) (((int64_t)(j) * g.nz + (k)) * g.nx + (i))
+
+__global__ __launch_bounds__(256) void k_rhs(RhsK K) {
+  const GridView& g = K.g;
+  const RhsArgs& a = K.a;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int k = blockIdx.y * blockDim.y + threadIdx.y;
+  const int j = blockIdx.z;
+  if (i >= g.nx || k >= g.nz) return;
+  const int im = (i == 0) ? g.nx - 1 : i - 1;
+  const int ip = (i + 1 == g.nx) ? 0 : i + 1;
+  const int km = (k == 0) ? g.nz - 1 : k - 1;
+  const int kp = (k + 1 == g.nz) ? 0 : k + 1;
+  const double dx = g.dx, dz = g.dz;
+  const double idx2 = 1.0 / (dx * dx), idz2 = 1.0 / (dz * dz);
+  const double* __restrict__ u = a.u;
+  const double* __restrict__ v = a.v;
+  const double* __restrict__ w = a.w;
+  const double* __restrict__ p = a.p;
+  const int64_t c = IDX(i, j, k);
+  const double dyj = g.dy[j];
+  const bool has_s = j > 0, has_n = j + 1 < g.ny;
+  const double dys = has_s ? g.dy[j - 1] : 0.0;
+  const double dyn = has_n ? g.dy[j + 1] : 0.0;
+  const double am = a.alpha / a.re;
+
+  // ------------------------------------------------------------ u node
+  {
+    const double uc = u[c], ue = u[IDX(ip, j, k)], uw = u[IDX(im, j, k)];
+    const double ut = u[IDX(i, j, kp)], ub = u[IDX(i, j, km)];
+    const double un = has_n ? u[IDX(i, j + 1, k)] : 0.0;
+    const double us = has_s ? u[IDX(i, j - 1, k)] : 0.0;
+    const double bp = 0.5 * (uc + ue), bm = 0.5 * (uw + uc);
+    const double tx = (bp * bp - bm * bm) / dx;
+    const double iyn = has_n ? (uc * dyn + un * dyj) / (dyj + dyn) : 0.0;
+    const double iys = has_s ? (us * dyj + uc * dys) / (dys + dyj) : 0.0;
+    const double vn = 0.5 * (v[IDX(im, j + 1, k)] + v[IDX(i, j + 1, k)]);
+    const double vs = 0.5 * (v[IDX(im, j, k)] + v[IDX(i, j, k)]);
+    const double ty = (iyn * vn - iys * vs) / dyj;
+    const double fzp = (0.5 * (uc + ut)) * (0.5 * (w[IDX(im, j, kp)] + w[IDX(i, j, kp)]));
+    const double fzm = (0.5 * (ub + uc)) * (0.5 * (w[IDX(im, j, k)] + w[IDX(i, j, k)]));
+    const double tz = (fzp - fzm) / dz;
+    const double H = -(tx + ty + tz);
+    const double L = ((ue - uc) - (uc - uw)) * idx2 + ((ut - uc) - (uc - ub)) * idz2 +
+                     ((un - uc) / g.dyc[j + 1] - (uc - us) / g.dyc[j]) / dyj;
+    const double gp = (p[c] - p[IDX(im, j, k)]) / dx;
+    double r = a.gamma * H - a.alpha * (gp - a.fx) + am * L;
+    if (a.rho != 0.0) r += a.rho * a.hprev[0][c];
+    if (a.hout[0]) a.hout[0][c] = H;
+    a.R[0][c] = test_bit(a.mask[0], c) ? 0.0 : a.dt * r;
+  }
+  // ------------------------------------------------------------ w node
+  {
+    const double wc = w[c], we = w[IDX(ip, j, k)], ww = w[IDX(im, j, k)];
+    const double wt = w[IDX(i, j, kp)], wb = w[IDX(i, j, km)];
+    const double wn = has_n ? w[IDX(i, j + 1, k)] : 0.0;
+    const double ws = has_s ? w[IDX(i, j - 1, k)] : 0.0;
+    const double bp = 0.5 * (wc + wt), bm = 0.5 * (wb + wc);
+    const double tz = (bp * bp - bm * bm) / dz;
+    const double iyn = has_n ? (wc * dyn + wn * dyj) / (dyj + dyn) : 0.0;
+    const double iys = has_s ? (ws * dyj + wc * dys) / (dys + dyj) : 0.0;
+    const double vn = 0.5 * (v[IDX(i, j + 1, km)] + v[IDX(i, j + 1, k)]);
+    const double vs = 0.5 * (v[IDX(i, j, km)] + v[IDX(i, j, k)]);
+    const double ty = (iyn * vn - iys * vs) / dyj;
+    const double fxp = (0.5 * (wc + we)) * (0.5 * (u[IDX(ip, j, km)] + u[IDX(ip, j, k)]));
+    const double fxm = (0.5 * (ww + wc)) * (0.5 * (u[IDX(i, j, km)] + u[IDX(i, j, k)]));
+    const double tx = (fxp - fxm) / dx;
+    const double H = -(tx + ty + tz);
+    const double L = ((we - wc) - (wc - ww)) * idx2 + ((wt - wc) - (wc - wb)) * idz2 +
+                     ((wn - wc) / g.dyc[j + 1] - (wc - ws) / g.dyc[j]) / dyj;
+    const double gp = (p[c] - p[IDX(i, j, km)]) / dz;
+    double r = a.gamma * H - a.alpha * gp + am * L;
+    if (a.rho != 0.0) r += a.rho * a.hprev[2][c];
+    if (a.hout[2]) a.hout[2][c] = H;
+    a.R[2][c] = test_bit(a.mask[2], c) ? 0.0 : a.dt * r;
+  }
+  // ------------------------------------------------------ v node (face j)
+  if (j == 0) {
+    a.R[1][c] = 0.0;  // wall planes
+    a.R[1][IDX(i, g.ny, k)] = 0.0;
+    if (a.hout[1]) {
+      a.hout[1][c] = 0.0;
+      a.hout[1][IDX(i, g.ny, k)] = 0.0;
+    }
+    return;
+  }
+  {
+    const double vc = v[c], ve = v[IDX(ip, j, k)], vw = v[IDX(im, j, k)];
+    const double vt = v[IDX(i, j, kp)], vb = v[IDX(i, j, km)];
+    const double vn = v[IDX(i, j + 1, k)], vs = v[IDX(i, j - 1, k)];
+    const double den = 1.0 / (dys + dyj);
+    const double uy_i = (u[IDX(i, j - 1, k)] * dyj + u[c] * dys) * den;
+    const double uy_ip = (u[IDX(ip, j - 1, k)] * dyj + u[IDX(ip, j, k)] * dys) * den;
+    const double tx = (uy_ip * (0.5 * (vc + ve)) - uy_i * (0.5 * (vw + vc))) / dx;
+    const double ct = 0.5 * (vc + vn), cs = 0.5 * (vs + vc);
+    const double ty = (ct * ct - cs * cs) / g.dyc[j];
+    const double wy_k = (w[IDX(i, j - 1, k)] * dyj + w[c] * dys) * den;
+    const double wy_kp = (w[IDX(i, j - 1, kp)] * dyj + w[IDX(i, j, kp)] * dys) * den;
+    const double tz = (wy_kp * (0.5 * (vc + vt)) - wy_k * (0.5 * (vb + vc))) / dz;
+    const double H = -(tx + ty + tz);
+    const double L = ((ve - vc) - (vc - vw)) * idx2 + ((vt - vc) - (vc - vb)) * idz2 +
+                     ((vn - vc) / dyj - (vc - vs) / dys) / g.dyc[j];
+    const double gp = (p[c] - p[IDX(i, j - 1, k)]) / g.dyc[j];
+    double r = a.gamma * H - a.alpha * gp + am * L;
+    if (a.rho != 0.0) r += a.rho * a.hprev[1][c];
+    if (a.hout[1]) a.hout[1][c] = H;
+    a.R[1][c] = test_bit(a.mask[1], c) ? 0.0 : a.dt * r;
+  }
+}
+
+void launch_rhs(Prof* pf, hipStream_t s, const GridView& g, const RhsArgs& a) {
+  RhsK K;
+  K.g = g;
+  K.a = a;
+  dim3 block(64, 4);
+  dim3 grid((g.nx + 63) / 64, (g.nz + 3) / 4, g.ny);
+  IBM_LAUNCH(pf, "rhs", s, k_rhs<<<grid, block, 0, s>>>(K));
+}
+
+}  // namespace ibm

@@ -1,0 +1,314 @@
+"""Thin ctypes binding of libibm (include/ibm.h): argument marshalling only.
+
+Every computation happens in the HIP kernels of libibm.so; this module checks
+shapes, dtypes and devices of torch tensors (PyTorch supplies only device
+memory and the stream) and forwards raw pointers.  If the library has not
+been built, importing this module raises: there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from ctypes import POINTER, c_char_p, c_double, c_int32, c_int64, c_uint32, c_void_p
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libibm.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with "
+                      "`python -m paper_2606_09799_amd.build` (no CPU fallback exists)")
+_lib = ctypes.CDLL(LIB_PATH)
+
+IBM_OK, IBM_EINVAL, IBM_ENOMEM, IBM_EHIP, IBM_ECAPACITY = 0, -1, -2, -3, -4
+IBM_ENONFINITE, IBM_EGEOM = -5, -7
+FLAG_CAPACITY, FLAG_NONFINITE, FLAG_GEOM = 1, 2, 4
+IBM_FP64 = 0
+IBM_RK2CN, IBM_AB2CN = 0, 1
+
+
+class IbmGrid(ctypes.Structure):
+    _fields_ = [("nx", c_int32), ("ny", c_int32), ("nz", c_int32), ("reserved", c_int32),
+                ("lx", c_double), ("lz", c_double), ("y_faces", POINTER(c_double))]
+
+
+class IbmOpts(ctypes.Structure):
+    _fields_ = [("precision", c_int32), ("scheme", c_int32), ("re", c_double),
+                ("dpdx", c_double), ("force_cap", c_int64), ("use_q", c_int32),
+                ("reserved", c_int32)]
+
+
+class IbmBody(ctypes.Structure):
+    _fields_ = [("nv", c_int32), ("nt", c_int32), ("xyz", c_void_p), ("vel", c_void_p),
+                ("tri", c_void_p)]
+
+
+class IbmTags(ctypes.Structure):
+    _fields_ = [("idx", c_void_p * 3), ("tri", c_void_p * 3), ("cb", c_void_p),
+                ("count", c_void_p), ("mask", c_void_p * 3), ("cb_mask", c_void_p),
+                ("capacity", c_int64)]
+
+
+class IbmState(ctypes.Structure):
+    _fields_ = [("u", c_void_p), ("v", c_void_p), ("w", c_void_p), ("p", c_void_p),
+                ("h", c_void_p * 3)]
+
+
+def _sig(name, res, *args):
+    f = getattr(_lib, name)
+    f.restype = res
+    f.argtypes = list(args)
+    return f
+
+
+_create = _sig("ibm_create", c_int32, POINTER(IbmGrid), POINTER(IbmOpts), c_void_p,
+               POINTER(c_void_p))
+_destroy = _sig("ibm_destroy", None, c_void_p)
+_set_stream = _sig("ibm_set_stream", c_int32, c_void_p, c_void_p)
+_body_rigid = _sig("ibm_body_rigid", c_int32, c_void_p, c_void_p, c_int32, POINTER(c_double),
+                   c_void_p, c_void_p)
+_body_deform = _sig("ibm_body_deform", c_int32, c_void_p, c_void_p, c_int32, POINTER(c_double),
+                    c_void_p, c_void_p)
+_tag = _sig("ibm_tag", c_int32, c_void_p, POINTER(IbmBody), c_int32, POINTER(IbmTags))
+_count_host = _sig("ibm_tags_count_host", c_int32, c_void_p, POINTER(c_int64))
+_tags_copy = _sig("ibm_tags_copy", c_int32, c_void_p, c_int32, c_void_p, c_void_p, c_int64)
+_force = _sig("ibm_force", c_int32, c_void_p, c_void_p, c_void_p, c_void_p)
+_viscous = _sig("ibm_viscous", c_int32, c_void_p, c_void_p, POINTER(c_void_p),
+                POINTER(c_void_p), c_double, c_double, c_double, c_void_p, c_void_p, c_void_p)
+_mass_rhs = _sig("ibm_mass_rhs", c_int32, c_void_p, c_void_p, c_void_p, c_void_p, c_double,
+                 c_void_p, c_void_p)
+_poisson = _sig("poisson_solve", c_int32, c_void_p, c_void_p, c_void_p)
+_project = _sig("ibm_project", c_int32, c_void_p, c_void_p, c_double, c_void_p, c_void_p,
+                c_void_p, c_void_p)
+_step = _sig("ibm_step", c_int32, c_void_p, POINTER(IbmState), POINTER(IbmBody), c_int32,
+             c_double)
+_check = _sig("ibm_check", c_int32, c_void_p, POINTER(c_uint32))
+_strerror = _sig("ibm_strerror", c_char_p, c_int32)
+_profile = _sig("ibm_profile", c_int32, c_void_p, c_int32, c_char_p)
+_profile_read = _sig("ibm_profile_read", c_int32, c_void_p, c_char_p, c_int32,
+                     POINTER(c_int64), POINTER(c_double), c_int32)
+
+EXPORTS = ("ibm_create", "ibm_destroy", "ibm_set_stream", "ibm_body_rigid", "ibm_body_deform",
+           "ibm_tag", "ibm_tags_count_host", "ibm_tags_copy", "ibm_force", "ibm_viscous",
+           "ibm_mass_rhs", "poisson_solve", "ibm_project", "ibm_step", "ibm_check",
+           "ibm_strerror", "ibm_profile", "ibm_profile_read")
+
+
+class IbmError(RuntimeError):
+    def __init__(self, code, where):
+        super().__init__(f"{where}: {code} ({_strerror(code).decode()})")
+        self.code = code
+
+
+def _ok(code, where):
+    if code != IBM_OK:
+        raise IbmError(code, where)
+
+
+def _stream():
+    return c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dev(t, dtype, numel, name):
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError(f"{name}: expected a CUDA (HIP) tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{name}: expected {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name}: expected a contiguous tensor")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{name}: expected {numel} elements, got {t.numel()}")
+    return c_void_p(t.data_ptr())
+
+
+class Context:
+    """One grid on the current device, bound to torch's current stream."""
+
+    def __init__(self, nx, ny, nz, lx, lz, y_faces, re, dpdx=0.0, scheme="rk2", use_q=True,
+                 force_cap=0):
+        self.nx, self.ny, self.nz = int(nx), int(ny), int(nz)
+        self.cells = self.nx * self.ny * self.nz
+        self.vfaces = self.nx * (self.ny + 1) * self.nz
+        yf = np.ascontiguousarray(np.asarray(y_faces, dtype=np.float64))
+        if yf.shape != (self.ny + 1,):
+            raise ValueError("y_faces must hold ny+1 values")
+        self._yf = yf
+        g = IbmGrid(self.nx, self.ny, self.nz, 0, float(lx), float(lz),
+                    yf.ctypes.data_as(POINTER(c_double)))
+        o = IbmOpts(IBM_FP64, IBM_RK2CN if scheme == "rk2" else IBM_AB2CN, float(re),
+                    float(dpdx), int(force_cap), 1 if use_q else 0, 0)
+        h = c_void_p()
+        _ok(_create(ctypes.byref(g), ctypes.byref(o), _stream(), ctypes.byref(h)), "ibm_create")
+        self.handle = h
+        self.re = float(re)
+
+    def close(self):
+        if self.handle:
+            _destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def comp_numel(self, c):
+        return self.vfaces if c == 1 else self.cells
+
+    def bind_current_stream(self):
+        _ok(_set_stream(self.handle, _stream()), "ibm_set_stream")
+
+
+class Body:
+    """Device arrays of one triangulated surface (f64 vertices/velocities,
+    i32 triangles)."""
+
+    def __init__(self, xyz, vel, tri):
+        self.xyz, self.vel, self.tri = xyz, vel, tri
+        self.nv = xyz.shape[0]
+        self.nt = tri.shape[0]
+
+    def desc(self):
+        return IbmBody(self.nv, self.nt, _dev(self.xyz, torch.float64, 3 * self.nv, "xyz"),
+                       _dev(self.vel, torch.float64, 3 * self.nv, "vel"),
+                       _dev(self.tri, torch.int32, 3 * self.nt, "tri"))
+
+
+def _bodies(bodies):
+    arr = (IbmBody * max(1, len(bodies)))()
+    for i, b in enumerate(bodies):
+        arr[i] = b.desc()
+    return arr, len(bodies)
+
+
+def ibm_body_rigid(ctx, x0, coef, xyz, vel):
+    nv = x0.shape[0]
+    cf = np.ascontiguousarray(np.asarray(coef, np.float64))
+    if cf.shape != (18,):
+        raise ValueError("rigid coefficients: 18 values")
+    _ok(_body_rigid(ctx.handle, _dev(x0, torch.float64, 3 * nv, "x0"), nv,
+                    cf.ctypes.data_as(POINTER(c_double)), _dev(xyz, torch.float64, 3 * nv, "xyz"),
+                    _dev(vel, torch.float64, 3 * nv, "vel")), "ibm_body_rigid")
+
+
+def ibm_body_deform(ctx, data, coef, xyz, vel):
+    nv = data.shape[0]
+    cf = np.ascontiguousarray(np.asarray(coef, np.float64))
+    if cf.shape != (6,):
+        raise ValueError("deform coefficients: 6 values")
+    _ok(_body_deform(ctx.handle, _dev(data, torch.float64, 4 * nv, "data"), nv,
+                     cf.ctypes.data_as(POINTER(c_double)),
+                     _dev(xyz, torch.float64, 3 * nv, "xyz"),
+                     _dev(vel, torch.float64, 3 * nv, "vel")), "ibm_body_deform")
+
+
+def ibm_tag(ctx, bodies):
+    arr, n = _bodies(bodies)
+    t = IbmTags()
+    _ok(_tag(ctx.handle, arr, n, ctypes.byref(t)), "ibm_tag")
+    return t
+
+
+def ibm_tags_count_host(ctx):
+    out = (c_int64 * 4)()
+    _ok(_count_host(ctx.handle, out), "ibm_tags_count_host")
+    return [int(x) for x in out]
+
+
+def tag_lists(ctx):
+    """Copies of the last tagging: ([(idx i64, tri i32)] per component, cb i64)
+    as CUDA tensors (synchronises once for the counts)."""
+    counts = ibm_tags_count_host(ctx)
+    out = []
+    for c in range(3):
+        n = counts[c]
+        idx = torch.empty(n, dtype=torch.int64, device="cuda")
+        tri = torch.empty(n, dtype=torch.int32, device="cuda")
+        _ok(_tags_copy(ctx.handle, c, c_void_p(idx.data_ptr()) if n else None,
+                       c_void_p(tri.data_ptr()) if n else None, n), "ibm_tags_copy")
+        out.append((idx, tri))
+    n = counts[3]
+    cb = torch.empty(n, dtype=torch.int64, device="cuda")
+    _ok(_tags_copy(ctx.handle, 3, c_void_p(cb.data_ptr()) if n else None, None, n),
+        "ibm_tags_copy")
+    return out, cb
+
+
+def ibm_force(ctx, u, v, w):
+    _ok(_force(ctx.handle, _dev(u, torch.float64, ctx.cells, "u"),
+               _dev(v, torch.float64, ctx.vfaces, "v"),
+               _dev(w, torch.float64, ctx.cells, "w")), "ibm_force")
+
+
+def _ptr3(ts, ctx, name):
+    if ts is None:
+        return None
+    arr = (c_void_p * 3)()
+    for c in range(3):
+        arr[c] = _dev(ts[c], torch.float64, ctx.comp_numel(c), f"{name}[{c}]")
+    return arr
+
+
+def ibm_viscous(ctx, p, h_prev, h_out, gamma, rho, dt, u, v, w):
+    _ok(_viscous(ctx.handle, _dev(p, torch.float64, ctx.cells, "p"), _ptr3(h_prev, ctx, "h_prev"),
+                 _ptr3(h_out, ctx, "h_out"), float(gamma), float(rho), float(dt),
+                 _dev(u, torch.float64, ctx.cells, "u"), _dev(v, torch.float64, ctx.vfaces, "v"),
+                 _dev(w, torch.float64, ctx.cells, "w")), "ibm_viscous")
+
+
+def ibm_mass_rhs(ctx, u, v, w, alpha_dt, rhs, qf=None):
+    _ok(_mass_rhs(ctx.handle, _dev(u, torch.float64, ctx.cells, "u"),
+                  _dev(v, torch.float64, ctx.vfaces, "v"),
+                  _dev(w, torch.float64, ctx.cells, "w"), float(alpha_dt),
+                  _dev(rhs, torch.float64, ctx.cells, "rhs"),
+                  _dev(qf, torch.float64, 1, "qf")), "ibm_mass_rhs")
+
+
+def poisson_solve(ctx, rhs, phi):
+    _ok(_poisson(ctx.handle, _dev(rhs, torch.float64, ctx.cells, "rhs"),
+                 _dev(phi, torch.float64, ctx.cells, "phi")), "poisson_solve")
+
+
+def ibm_project(ctx, phi, alpha_dt, u, v, w, p):
+    _ok(_project(ctx.handle, _dev(phi, torch.float64, ctx.cells, "phi"), float(alpha_dt),
+                 _dev(u, torch.float64, ctx.cells, "u"), _dev(v, torch.float64, ctx.vfaces, "v"),
+                 _dev(w, torch.float64, ctx.cells, "w"),
+                 _dev(p, torch.float64, ctx.cells, "p")), "ibm_project")
+
+
+def ibm_step(ctx, u, v, w, p, bodies, dt, h=None):
+    st = IbmState(_dev(u, torch.float64, ctx.cells, "u"), _dev(v, torch.float64, ctx.vfaces, "v"),
+                  _dev(w, torch.float64, ctx.cells, "w"), _dev(p, torch.float64, ctx.cells, "p"))
+    if h is not None:
+        for c in range(3):
+            st.h[c] = _dev(h[c], torch.float64, ctx.comp_numel(c), f"h[{c}]")
+    arr, n = _bodies(bodies)
+    _ok(_step(ctx.handle, ctypes.byref(st), arr, n, float(dt)), "ibm_step")
+
+
+def ibm_check(ctx):
+    f = c_uint32()
+    _ok(_check(ctx.handle, ctypes.byref(f)), "ibm_check")
+    return int(f.value)
+
+
+def ibm_profile(ctx, enable=True, filter_=None):
+    _ok(_profile(ctx.handle, 1 if enable else 0, filter_.encode() if filter_ else None),
+        "ibm_profile")
+
+
+def ibm_profile_read(ctx, cap=64):
+    L = 48
+    names = ctypes.create_string_buffer(L * cap)
+    cnt = (c_int64 * cap)()
+    tot = (c_double * cap)()
+    n = _profile_read(ctx.handle, names, L, cnt, tot, cap)
+    if n < 0:
+        raise IbmError(n, "ibm_profile_read")
+    return {names.raw[i * L:(i + 1) * L].split(b"\0")[0].decode(): (int(cnt[i]), float(tot[i]))
+            for i in range(n)}
