@@ -95,7 +95,8 @@ struct ibm_ctx {
 
   double* R[3] = {};
   double* H[3] = {};
-  double* scratch[3] = {};
+  double* sa = nullptr;  // line-solve scratch (segments with forcing nodes)
+  double* sc = nullptr;
   double* rhs_tmp = nullptr;
   double* phi = nullptr;
   double2* spec = nullptr;
@@ -107,6 +108,7 @@ struct ibm_ctx {
   // line-solve tables for one beta
   double tab_beta = -1.0;
   double* tabmem = nullptr;
+  int64_t tabcap = 0;
   CyclicTab ctx_x{}, ctx_z{};
   YTab yt[2]{};  // 0: u and w, 1: v
 
@@ -232,15 +234,65 @@ static int build_tables(ibm_ctx* c, double beta) {
     t->j0 = isv ? 1 : 0;
     for (auto* v : {&A, &B, &C, &cp, &inv}) out.insert(out.end(), v->begin(), v->end());
   };
-  std::vector<double> hx, hz, hy0, hy1;
+  // elimination tables of the partitioned solve for mask-free segments:
+  // [0] 1/pivot, [1] c~ (forward), [2] a^ and [3] c^ (responses of every
+  // interior row to the left and right separators)
+  auto segtab = [&](int n, bool cyc, const double* A, const double* B, const double* C,
+                    std::vector<double>& out) {
+    int P, L, r;
+    line_plan(n, cyc, &P, &L, &r);
+    std::vector<double> t(4 * (size_t)P * LINE_LMAX, 0.0);
+    for (int s = 0; s < P; ++s) {
+      const int lo = s * L + std::min(s, r);
+      const int m = L + (s < r ? 1 : 0) - 1;
+      double at = 0, ct = 0;
+      std::vector<double> va(m), vc(m);
+      for (int e = 0; e < m; ++e) {
+        const int i = lo + e;
+        const double inv = 1.0 / (B[i] - A[i] * ct);
+        at = (e == 0) ? A[i] * inv : -A[i] * at * inv;
+        ct = C[i] * inv;
+        t[(0 * P + s) * LINE_LMAX + e] = inv;
+        t[(1 * P + s) * LINE_LMAX + e] = ct;
+        va[e] = at;
+        vc[e] = ct;
+      }
+      double ah = 0, ch = 0;
+      for (int e = m - 1; e >= 0; --e) {
+        if (e == m - 1) {
+          ah = va[e];
+          ch = vc[e];
+        } else {
+          ah = va[e] - vc[e] * ah;
+          ch = -vc[e] * ch;
+        }
+        t[(2 * P + s) * LINE_LMAX + e] = ah;
+        t[(3 * P + s) * LINE_LMAX + e] = ch;
+      }
+    }
+    out.insert(out.end(), t.begin(), t.end());
+  };
+  auto constseg = [&](int n, const CyclicTab& t, std::vector<double>& out) {
+    std::vector<double> A(n, t.a), B(n, t.b), C(n, t.c);
+    segtab(n, true, A.data(), B.data(), C.data(), out);
+  };
+  std::vector<double> hx, hz, hy0, hy1, sx, sz, sy0, sy1;
   cyclic(nx, c->g.dx, &c->ctx_x, hx);
   cyclic(nz, c->g.dz, &c->ctx_z, hz);
   ysys(false, hy0, &c->yt[0]);
   ysys(true, hy1, &c->yt[1]);
-  h.insert(h.end(), hx.begin(), hx.end());
-  h.insert(h.end(), hz.begin(), hz.end());
-  h.insert(h.end(), hy0.begin(), hy0.end());
-  h.insert(h.end(), hy1.begin(), hy1.end());
+  constseg(nx, c->ctx_x, sx);
+  constseg(nz, c->ctx_z, sz);
+  for (int q = 0; q < 2; ++q) {
+    const int n = c->yt[q].n;
+    const std::vector<double>& hy = q ? hy1 : hy0;
+    segtab(n, false, hy.data(), hy.data() + n, hy.data() + 2 * n, q ? sy1 : sy0);
+  }
+  for (auto* v : {&hx, &hz, &hy0, &hy1, &sx, &sz, &sy0, &sy1}) h.insert(h.end(), v->begin(), v->end());
+  if ((int64_t)h.size() > c->tabcap) {
+    g_last_error = "line-solve tables exceed their buffer";
+    return IBM_EINVAL;
+  }
   // the tables are read by kernels already enqueued: order the update on the
   // stream, and keep the host copy alive until it has been consumed
   HIPCHK(hipStreamSynchronize(c->stream));
@@ -258,6 +310,10 @@ static int build_tables(ibm_ctx* c, double beta) {
     c->yt[q].a = take(n); c->yt[q].b = take(n); c->yt[q].c = take(n);
     c->yt[q].cp = take(n); c->yt[q].inv = take(n);
   }
+  c->ctx_x.seg = take((int)sx.size());
+  c->ctx_z.seg = take((int)sz.size());
+  c->yt[0].seg = take((int)sy0.size());
+  c->yt[1].seg = take((int)sy1.size());
   c->tab_beta = beta;
   return IBM_OK;
 }
@@ -301,7 +357,7 @@ const char* ibm_strerror(int code) {
 int ibm_create(const ibm_grid* gr, const ibm_opts* o, void* stream, ibm_ctx** out) {
   if (!gr || !o || !out) FAIL(IBM_EINVAL, "null argument");
   *out = nullptr;
-  if (gr->nx < 4 || gr->nz < 4 || gr->ny < 3) FAIL(IBM_EINVAL, "grid too small (nx, nz >= 4, ny >= 3)");
+  if (gr->nx < 8 || gr->nz < 8 || gr->ny < 3) FAIL(IBM_EINVAL, "grid too small (nx, nz >= 8, ny >= 3)");
   if (!gr->y_faces) FAIL(IBM_EINVAL, "y_faces is NULL");
   if (!(gr->lx > 0) || !(gr->lz > 0) || !(o->re > 0)) FAIL(IBM_EINVAL, "lx, lz and re must be > 0");
   if (o->precision != IBM_FP64) FAIL(IBM_EINVAL, "only IBM_FP64 is available");
@@ -395,9 +451,6 @@ int ibm_create(const ibm_grid* gr, const ibm_opts* o, void* stream, ibm_ctx** ou
     TRY(dalloc(c, &tb.best_t[q], nn));
     TRY(dalloc(c, &tb.idx[q], tb.cap));
     TRY(dalloc(c, &tb.tri[q], tb.cap));
-    TRY(dalloc(c, &tb.xflag[q], (int64_t)(ny + 1) * nz));
-    TRY(dalloc(c, &tb.zflag[q], (int64_t)(ny + 1) * nx));
-    TRY(dalloc(c, &tb.yflag[q], (int64_t)nz * nx));
   }
   tb.nwords_cb = (c->ncell + 31) / 32;
   TRY(dalloc(c, &tb.cb_mask, tb.nwords_cb));
@@ -417,8 +470,9 @@ int ibm_create(const ibm_grid* gr, const ibm_opts* o, void* stream, ibm_ctx** ou
     const int64_t nn = (q == 1) ? c->nvface : c->ncell;
     TRY(dalloc(c, &c->R[q], nn));
     TRY(dalloc(c, &c->H[q], nn));
-    TRY(dalloc(c, &c->scratch[q], nn));
   }
+  TRY(dalloc(c, &c->sa, c->nvface));
+  TRY(dalloc(c, &c->sc, c->nvface));
   TRY(dalloc(c, &c->rhs_tmp, c->ncell));
   TRY(dalloc(c, &c->phi, c->ncell));
   const int64_t nspec = (int64_t)ny * nz * g.nxh;
@@ -427,7 +481,17 @@ int ibm_create(const ibm_grid* gr, const ibm_opts* o, void* stream, ibm_ctx** ou
   TRY(dalloc(c, &c->partial, 512));
   TRY(dalloc(c, &c->qf, 1));
   TRY(dalloc(c, &c->flags, 1));
-  TRY(dalloc(c, &c->tabmem, 4 * (int64_t)(nx + nz) + 10 * (int64_t)ny));
+  {
+    int P, L, r, segs = 0;
+    line_plan(nx, true, &P, &L, &r);
+    segs += P;
+    line_plan(nz, true, &P, &L, &r);
+    segs += P;
+    line_plan(ny, false, &P, &L, &r);
+    segs += 2 * P;
+    c->tabcap = 4 * (int64_t)(nx + nz) + 10 * (int64_t)ny + 4 * (int64_t)segs * LINE_LMAX;
+    TRY(dalloc(c, &c->tabmem, c->tabcap));
+  }
 
   // Poisson tables
   TRY(make_twiddles(c, &c->px));
@@ -463,9 +527,6 @@ int ibm_create(const ibm_grid* gr, const ibm_opts* o, void* stream, ibm_ctx** ou
     launch_fill_u64(nullptr, c->stream, tb.best_d[q], nn, ~0ull);
     launch_fill_i32(nullptr, c->stream, tb.best_t[q], nn, 0x7fffffff);
     launch_fill_u32(nullptr, c->stream, tb.mask[q], tb.nwords[q], 0u);
-    launch_fill_u8(nullptr, c->stream, tb.xflag[q], (int64_t)(ny + 1) * nz, 0);
-    launch_fill_u8(nullptr, c->stream, tb.zflag[q], (int64_t)(ny + 1) * nx, 0);
-    launch_fill_u8(nullptr, c->stream, tb.yflag[q], (int64_t)nz * nx, 0);
   }
   launch_fill_u32(nullptr, c->stream, tb.cb_mask, tb.nwords_cb, 0u);
   launch_fill_u32(nullptr, c->stream, c->flags, 1, 0u);
@@ -646,12 +707,10 @@ static int viscous(ibm_ctx* c, const double* p, const double* const* hprev, doub
   launch_rhs(&c->prof, c->stream, c->g, a);
   double* f[3] = {u, v, w};
   for (int q = 0; q < 3; ++q) {
-    launch_adi_x(&c->prof, c->stream, c->g, q, c->R[q], c->tb.xflag[q], c->tb.mask[q], c->ctx_x,
-                 c->scratch[q]);
-    launch_adi_z(&c->prof, c->stream, c->g, q, c->R[q], c->tb.zflag[q], c->tb.mask[q], c->ctx_z,
-                 c->scratch[q]);
-    launch_adi_y(&c->prof, c->stream, c->g, q, c->R[q], f[q], c->tb.yflag[q], c->tb.mask[q],
-                 c->yt[q == 1 ? 1 : 0], c->scratch[q]);
+    launch_adi_x(&c->prof, c->stream, c->g, q, c->R[q], c->tb.mask[q], c->ctx_x, c->sa, c->sc);
+    launch_adi_z(&c->prof, c->stream, c->g, q, c->R[q], c->tb.mask[q], c->ctx_z, c->sa, c->sc);
+    launch_adi_y(&c->prof, c->stream, c->g, q, c->R[q], f[q], c->tb.mask[q],
+                 c->yt[q == 1 ? 1 : 0], c->sa, c->sc);
   }
   return launch_status();
 }

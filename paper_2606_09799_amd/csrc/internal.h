@@ -48,6 +48,7 @@ struct CyclicTab {
   double a, b, c;        // constant sub/main/super diagonal
   double ratio;          // beta_corner / gamma
   double fden_inv;       // 1 / (1 + z_0 + ratio z_{n-1})
+  const double* seg;     // partitioned-solve tables [4][P][LINE_LMAX]
 };
 
 struct YTab {
@@ -58,8 +59,22 @@ struct YTab {
   const double* c;   // super-diagonal
   const double* cp;  // Thomas c' of the mask-free system
   const double* inv; // 1/pivot of the mask-free system
+  const double* seg; // partitioned-solve tables [4][P][LINE_LMAX]
   int n, j0;
 };
+
+// Segmentation of a line of n rows for the partitioned solves: P balanced
+// segments of at most LINE_LMAX rows (the first r segments hold L+1 rows,
+// the others L); cyclic lines use at least 3 segments.  Shared by the
+// kernels and the host code that builds their tables.
+constexpr int LINE_LMAX = 16;
+inline void line_plan(int n, bool cyc, int* P, int* L, int* r) {
+  int p = (n + LINE_LMAX - 1) / LINE_LMAX;
+  if (cyc && p < 3) p = 3;
+  *P = p;
+  *L = n / p;
+  *r = n % p;
+}
 
 struct FFTPlan {
   int n;
@@ -100,9 +115,6 @@ struct TagBuffers {
   int64_t* cb;
   uint32_t* cb_mask;
   int64_t* count;        // [4]
-  uint8_t* xflag[3];     // (ny+1)*nz
-  uint8_t* zflag[3];     // (ny+1)*nx
-  uint8_t* yflag[3];     // nz*nx
   int64_t* block_sums;   // scan scratch
   int64_t cap;
   int64_t nwords[3];     // mask words per component
@@ -128,15 +140,14 @@ struct RhsArgs {
 void launch_rhs(Prof* pf, hipStream_t s, const GridView& g, const RhsArgs& a);
 
 // adi.hip
+// sa, sc: scratch of the size of the field (used only by segments that
+// hold forcing nodes)
 void launch_adi_x(Prof* pf, hipStream_t s, const GridView& g, int comp, double* d,
-                  const uint8_t* xflag, const uint32_t* mask, const CyclicTab& t,
-                  double* scratch);
+                  const uint32_t* mask, const CyclicTab& t, double* sa, double* sc);
 void launch_adi_z(Prof* pf, hipStream_t s, const GridView& g, int comp, double* d,
-                  const uint8_t* zflag, const uint32_t* mask, const CyclicTab& t,
-                  double* scratch);
-void launch_adi_y(Prof* pf, hipStream_t s, const GridView& g, int comp, const double* d,
-                  double* u, const uint8_t* yflag, const uint32_t* mask, const YTab& t,
-                  double* scratch);
+                  const uint32_t* mask, const CyclicTab& t, double* sa, double* sc);
+void launch_adi_y(Prof* pf, hipStream_t s, const GridView& g, int comp, double* d, double* u,
+                  const uint32_t* mask, const YTab& t, double* sa, double* sc);
 
 // mass.hip
 void launch_mass(Prof* pf, hipStream_t s, const GridView& g, const double* u, const double* v,

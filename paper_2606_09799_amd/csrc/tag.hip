@@ -14,8 +14,7 @@
 //   3. Compaction of each bitmap (block popcounts, one scan, emission in
 //      increasing node order): the sorted forcing list, its triangles, and a
 //      sparse reset of best_d / best_t for the next call.
-//   4. C_B from the u list (all six faces forcing), compacted the same way;
-//      per-line flags marking the x-, z- and y-lines that hold forcing nodes.
+//   4. C_B from the u list (all six faces forcing), compacted the same way.
 #pragma clang fp contract(off)
 
 #include "geom.h"
@@ -215,26 +214,6 @@ __global__ void k_cells(GridView g, const int64_t* __restrict__ idx_u,
   }
 }
 
-// flags of the lines that hold a forcing node: x-line (j,k), z-line (j,i),
-// y-line (k,i)
-__global__ void k_lineflags(GridView g, const int64_t* __restrict__ idx,
-                            const int64_t* __restrict__ count, int comp, int64_t cap,
-                            uint8_t* __restrict__ xf, uint8_t* __restrict__ zf,
-                            uint8_t* __restrict__ yf) {
-  int64_t n = count[comp];
-  if (n > cap) n = cap;
-  for (int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; f < n;
-       f += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t node = idx[f];
-    const int i = (int)(node % g.nx);
-    const int k = (int)((node / g.nx) % g.nz);
-    const int j = (int)(node / ((int64_t)g.nz * g.nx));
-    xf[(int64_t)j * g.nz + k] = 1;
-    zf[(int64_t)j * g.nx + i] = 1;
-    yf[(int64_t)k * g.nx + i] = 1;
-  }
-}
-
 static void compact(Prof* pf, hipStream_t s, const uint32_t* mask, int64_t nwords,
                     int64_t* bsum, int64_t* count_slot, int64_t* idx, int32_t* tri, u64* best_d,
                     int32_t* best_t, int64_t cap, uint32_t* flags) {
@@ -250,9 +229,6 @@ void launch_tag(Prof* pf, hipStream_t s, const GridView& g, const BodyDev* bodie
                 int ntri, TagBuffers& tb, uint32_t* flags) {
   for (int c = 0; c < 3; ++c) {
     launch_fill_u32(pf, s, tb.mask[c], tb.nwords[c], 0u);
-    launch_fill_u8(pf, s, tb.xflag[c], (int64_t)(g.ny + 1) * g.nz, 0);
-    launch_fill_u8(pf, s, tb.zflag[c], (int64_t)(g.ny + 1) * g.nx, 0);
-    launch_fill_u8(pf, s, tb.yflag[c], (int64_t)g.nz * g.nx, 0);
   }
   launch_fill_u32(pf, s, tb.cb_mask, tb.nwords_cb, 0u);
   if (ntri > 0) {
@@ -282,10 +258,6 @@ void launch_tag(Prof* pf, hipStream_t s, const GridView& g, const BodyDev* bodie
                                           tb.mask[2], tb.cb_mask));
   compact(pf, s, tb.cb_mask, tb.nwords_cb, tb.block_sums, tb.count + 3, tb.cb, nullptr, nullptr,
           nullptr, tb.cap, flags);
-  for (int c = 0; c < 3; ++c)
-    IBM_LAUNCH(pf, "tag_lineflags", s,
-               k_lineflags<<<256, 256, 0, s>>>(g, tb.idx[c], tb.count, c, tb.cap, tb.xflag[c],
-                                               tb.zflag[c], tb.yflag[c]));
 }
 
 }  // namespace ibm
