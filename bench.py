@@ -47,6 +47,39 @@ def algorithmic_bytes(name, nx, ny, nz):
     return table.get(name)
 
 
+# kernel name in the library's event profile -> kernel symbol in rocprofv3
+COUNTER_NAME = {"rhs": "k_rhs", "pois_fftx_fwd": "k_fftx_fwd", "pois_fftz_fwd": "k_fftz<false>",
+                "pois_fftz_inv": "k_fftz<true>", "pois_tri_y": "k_tri_y",
+                "pois_fftx_inv": "k_fftx_inv", "project": "k_project"}
+
+
+def csrc_sha():
+    import hashlib
+    h = hashlib.sha256()
+    d = os.path.join(ROOT, "paper_2606_09799_amd", "csrc")
+    for f in sorted(os.listdir(d)):
+        h.update(f.encode())
+        with open(os.path.join(d, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(kernel, workload):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 PMC
+    summary (FETCH_SIZE and WRITE_SIZE, scaled by a plain copy), or None when
+    no summary exists for this workload or the kernel sources changed since."""
+    path = os.path.join(ROOT, "profiles", f"{workload}_fp64_traffic.json")
+    name = COUNTER_NAME.get(kernel)
+    if not name or not os.path.exists(path):
+        return None
+    with open(path) as f:
+        t = json.load(f)
+    if t.get("csrc_sha") != csrc_sha() or name not in t["kernels"]:
+        return None
+    k = t["kernels"][name]
+    return int(k["read_bytes"] + k["write_bytes"])
+
+
 def cpu_baseline(wl):
     """The oracle as it stands, on one full time step (tagging and both RK2
     sub-stages: IB forcing, predictor, mass correction, Poisson, projection)
@@ -149,7 +182,8 @@ def main():
         ach = ab / avg_s / 1e9
         roof = {"bound": "hbm", "kernel": dominant, "achieved": round(ach, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
-                "traffic": None, "avg_launch_us": round(avg_s * 1e6, 2),
+                "traffic": measured_traffic(dominant, wl.name),
+                "avg_launch_us": round(avg_s * 1e6, 2),
                 "algorithmic_bytes": ab}
     warm = {k: round(vv[1] / max(1, args.warmup), 4) for k, vv in prof.items()}
     copy_ref = None

@@ -437,6 +437,31 @@ int ibm_create(const ibm_grid* gr, const ibm_opts* o, void* stream, ibm_ctx** ou
   g.dy = ddy;
   g.dyc = ddyc;
   g.extuw = dext;
+  {
+    std::vector<double> idy(ny), idyc(ny + 1), fw0(ny + 1, 0.0), fw1(ny + 1, 0.0);
+    for (int j = 0; j < ny; ++j) idy[j] = 1.0 / c->dy[j];
+    for (int j = 0; j <= ny; ++j) idyc[j] = 1.0 / c->dyc[j];
+    for (int f = 1; f < ny; ++f) {
+      const double s = c->dy[f - 1] + c->dy[f];
+      fw0[f] = c->dy[f] / s;
+      fw1[f] = c->dy[f - 1] / s;
+    }
+    double *a, *b, *d0, *d1;
+    TRY(dalloc(c, &a, ny));
+    TRY(dalloc(c, &b, ny + 1));
+    TRY(dalloc(c, &d0, ny + 1));
+    TRY(dalloc(c, &d1, ny + 1));
+    TRY(upload(c, a, idy));
+    TRY(upload(c, b, idyc));
+    TRY(upload(c, d0, fw0));
+    TRY(upload(c, d1, fw1));
+    g.idy = a;
+    g.idyc = b;
+    g.fw0 = d0;
+    g.fw1 = d1;
+    g.idx = 1.0 / g.dx;
+    g.idz = 1.0 / g.dz;
+  }
 
   // tag buffers
   TagBuffers& tb = c->tb;

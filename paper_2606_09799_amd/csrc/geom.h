@@ -141,6 +141,20 @@ __device__ __forceinline__ int upper_bound(const double* ext, int n, double v) {
   return lo;
 }
 
+// XCD-aware tile order: workgroups are dispatched round-robin over the 8
+// XCDs of the chip, each with its own L2.  Block b runs on XCD b % 8; give
+// XCD x the contiguous range of tiles [x T/8, (x+1) T/8) so that tiles that
+// share halo rows (neighbours in x, z and the wall-normal direction) are
+// processed by the same L2, close together in time.
+constexpr int NUM_XCD = 8;
+__device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t T) {
+  const int64_t per = T / NUM_XCD, rem = T % NUM_XCD;
+  const int64_t x = b % NUM_XCD, r = b / NUM_XCD;
+  // XCDs 0..rem-1 own per+1 tiles, the others per tiles
+  if (r < per || (r == per && x < rem)) return x * per + (x < rem ? x : rem) + r;
+  return b;  // unreachable for b < T
+}
+
 __device__ __forceinline__ int find_body(const BodyDev* b, int nbody, int t) {
   int k = 0;
   while (k + 1 < nbody && t >= b[k + 1].toff) ++k;

@@ -23,6 +23,13 @@ struct GridView {
   const double* dy;     // ny
   const double* dyc;    // ny+1
   const double* extuw;  // ny+2
+  // reciprocals and interpolation weights (host-computed; no division in the
+  // stencil kernels)
+  double idx, idz;      // 1/dx, 1/dz
+  const double* idy;    // ny: 1/dy[j]
+  const double* idyc;   // ny+1: 1/dyc[j]
+  const double* fw0;    // ny+1: face f value = a[f-1] fw0[f] + a[f] fw1[f]
+  const double* fw1;    //       (f = 1..ny-1; 0 at the walls)
 };
 
 struct BodyDev {

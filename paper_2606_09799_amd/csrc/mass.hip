@@ -23,8 +23,8 @@ __device__ __forceinline__ double div_at(const GridView& g, const double* u, con
   const int ip = (i + 1 == g.nx) ? 0 : i + 1;
   const int kp = (k + 1 == g.nz) ? 0 : k + 1;
   const int64_t row = (int64_t)j * plane + (int64_t)k * g.nx;
-  return (u[row + ip] - u[cell]) / g.dx + (v[cell + plane] - v[cell]) / g.dy[j] +
-         (w[(int64_t)j * plane + (int64_t)kp * g.nx + i] - w[cell]) / g.dz;
+  return (u[row + ip] - u[cell]) * g.idx + (v[cell + plane] - v[cell]) * g.idy[j] +
+         (w[(int64_t)j * plane + (int64_t)kp * g.nx + i] - w[cell]) * g.idz;
 }
 
 __global__ __launch_bounds__(MT) void k_mass_partial(GridView g, const double* __restrict__ u,

@@ -172,9 +172,9 @@ __global__ __launch_bounds__(256) void k_fftx_fwd(PoisK K) {
       const int j = (int)(rr / g.nz), k = (int)(rr % g.nz);
       const int ip = (i + 1 == nx) ? 0 : i + 1;
       const int kp = (k + 1 == g.nz) ? 0 : k + 1;
-      const double D = (K.u[cell - i + ip] - K.u[cell]) / g.dx +
-                       (K.v[cell + plane] - K.v[cell]) / g.dy[j] +
-                       (K.w[(int64_t)j * plane + (int64_t)kp * nx + i] - K.w[cell]) / g.dz;
+      const double D = (K.u[cell - i + ip] - K.u[cell]) * g.idx +
+                       (K.v[cell + plane] - K.v[cell]) * g.idy[j] +
+                       (K.w[(int64_t)j * plane + (int64_t)kp * nx + i] - K.w[cell]) * g.idz;
       val = (D - q) * K.inv_adt;
     }
     a[r * nx + i] = make_double2(val, 0.0);

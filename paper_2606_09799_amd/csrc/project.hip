@@ -1,7 +1,8 @@
 // Projection and pressure update (paper Eqs. projection and update_pressure):
 //   u <- u_hat - alpha dt G phi   on every interior velocity node
 //   p <- p + phi - alpha dt/(2 Re) L_c phi,  L_c = D G (Neumann at the walls)
-// One thread per (i, j, k), x fastest.
+// One thread per (i, j, k), x fastest; rows are ordered per XCD so that the
+// neighbouring rows of phi are reused from the same L2 (xcd_tile).
 #include "geom.h"
 
 namespace ibm {
@@ -10,9 +11,11 @@ __global__ __launch_bounds__(256) void k_project(GridView g, const double* __res
                                                  double adt, double pc, double* __restrict__ u,
                                                  double* __restrict__ v, double* __restrict__ w,
                                                  double* __restrict__ p) {
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  const int k = blockIdx.y;
-  const int j = blockIdx.z;
+  const int nbx = (g.nx + 255) / 256;
+  const int64_t t = xcd_tile(blockIdx.x, (int64_t)nbx * g.nz * g.ny);
+  const int i = (int)(t % nbx) * 256 + threadIdx.x;
+  const int k = (int)((t / nbx) % g.nz);
+  const int j = (int)(t / ((int64_t)nbx * g.nz));
   if (i >= g.nx) return;
   const int64_t plane = (int64_t)g.nz * g.nx;
   const int64_t c = (int64_t)j * plane + (int64_t)k * g.nx + i;
@@ -25,25 +28,25 @@ __global__ __launch_bounds__(256) void k_project(GridView g, const double* __res
   const double fw = phi[row + im], fe = phi[row + ip];
   const double fb = phi[(int64_t)j * plane + (int64_t)km * g.nx + i];
   const double ft = phi[(int64_t)j * plane + (int64_t)kp * g.nx + i];
-  const double gx = (fc - fw) / g.dx;
-  const double gz = (fc - fb) / g.dz;
+  const double gx = (fc - fw) * g.idx;
+  const double gz = (fc - fb) * g.idz;
   u[c] -= adt * gx;
   w[c] -= adt * gz;
   double fluxs = 0.0, fluxn = 0.0;
   if (j > 0) {
-    const double gy = (fc - phi[c - plane]) / g.dyc[j];
+    const double gy = (fc - phi[c - plane]) * g.idyc[j];
     v[c] -= adt * gy;
     fluxs = gy;
   }
-  if (j + 1 < g.ny) fluxn = (phi[c + plane] - fc) / g.dyc[j + 1];
-  const double lc = ((fe - fc) / g.dx - gx) / g.dx + ((ft - fc) / g.dz - gz) / g.dz +
-                    (fluxn - fluxs) / g.dy[j];
+  if (j + 1 < g.ny) fluxn = (phi[c + plane] - fc) * g.idyc[j + 1];
+  const double lc = ((fe - fc) * g.idx - gx) * g.idx + ((ft - fc) * g.idz - gz) * g.idz +
+                    (fluxn - fluxs) * g.idy[j];
   p[c] += fc - pc * lc;
 }
 
 void launch_project(Prof* pf, hipStream_t s, const GridView& g, const double* phi, double adt,
                     double re, double* u, double* v, double* w, double* p) {
-  dim3 grid((g.nx + 255) / 256, g.nz, g.ny);
+  dim3 grid((unsigned)((int64_t)((g.nx + 255) / 256) * g.nz * g.ny));
   const double pc = adt / (2.0 * re);
   IBM_LAUNCH(pf, "project", s, k_project<<<grid, 256, 0, s>>>(g, phi, adt, pc, u, v, w, p));
 }

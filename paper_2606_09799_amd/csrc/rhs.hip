@@ -8,7 +8,8 @@
 //
 // One thread per (i, j, k) computes the three components; x is the fastest
 // thread index so every neighbour access of a wavefront is a contiguous row
-// segment.  The neighbourhood reuse across rows is served by the caches.
+// segment.  The neighbourhood reuse across rows is served by the L2: tiles
+// are ordered so that each XCD sweeps a contiguous slab (xcd_tile).
 #include "geom.h"
 
 namespace ibm {
@@ -23,25 +24,28 @@ struct RhsK {
 __global__ __launch_bounds__(256) void k_rhs(RhsK K) {
   const GridView& g = K.g;
   const RhsArgs& a = K.a;
-  const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  const int k = blockIdx.y * blockDim.y + threadIdx.y;
-  const int j = blockIdx.z;
+  const int nbx = (g.nx + 63) / 64, nbz = (g.nz + 3) / 4;
+  const int64_t t = xcd_tile(blockIdx.x, (int64_t)nbx * nbz * g.ny);
+  const int i = (int)(t % nbx) * 64 + threadIdx.x;
+  const int k = (int)((t / nbx) % nbz) * 4 + threadIdx.y;
+  const int j = (int)(t / ((int64_t)nbx * nbz));
   if (i >= g.nx || k >= g.nz) return;
   const int im = (i == 0) ? g.nx - 1 : i - 1;
   const int ip = (i + 1 == g.nx) ? 0 : i + 1;
   const int km = (k == 0) ? g.nz - 1 : k - 1;
   const int kp = (k + 1 == g.nz) ? 0 : k + 1;
-  const double dx = g.dx, dz = g.dz;
-  const double idx2 = 1.0 / (dx * dx), idz2 = 1.0 / (dz * dz);
+  const double idx = g.idx, idz = g.idz;
+  const double idx2 = idx * idx, idz2 = idz * idz;
   const double* __restrict__ u = a.u;
   const double* __restrict__ v = a.v;
   const double* __restrict__ w = a.w;
   const double* __restrict__ p = a.p;
   const int64_t c = IDX(i, j, k);
-  const double dyj = g.dy[j];
+  const double idyj = g.idy[j];
   const bool has_s = j > 0, has_n = j + 1 < g.ny;
-  const double dys = has_s ? g.dy[j - 1] : 0.0;
-  const double dyn = has_n ? g.dy[j + 1] : 0.0;
+  const double ic_n = g.idyc[j + 1], ic_s = g.idyc[j];
+  // weights of the face interpolations at faces j+1 (north) and j (south)
+  const double n0 = g.fw0[j + 1], n1 = g.fw1[j + 1], s0 = g.fw0[j], s1 = g.fw1[j];
   const double am = a.alpha / a.re;
 
   // ------------------------------------------------------------ u node
@@ -51,19 +55,19 @@ __global__ __launch_bounds__(256) void k_rhs(RhsK K) {
     const double un = has_n ? u[IDX(i, j + 1, k)] : 0.0;
     const double us = has_s ? u[IDX(i, j - 1, k)] : 0.0;
     const double bp = 0.5 * (uc + ue), bm = 0.5 * (uw + uc);
-    const double tx = (bp * bp - bm * bm) / dx;
-    const double iyn = has_n ? (uc * dyn + un * dyj) / (dyj + dyn) : 0.0;
-    const double iys = has_s ? (us * dyj + uc * dys) / (dys + dyj) : 0.0;
+    const double tx = (bp * bp - bm * bm) * idx;
+    const double iyn = has_n ? uc * n0 + un * n1 : 0.0;
+    const double iys = has_s ? us * s0 + uc * s1 : 0.0;
     const double vn = 0.5 * (v[IDX(im, j + 1, k)] + v[IDX(i, j + 1, k)]);
     const double vs = 0.5 * (v[IDX(im, j, k)] + v[IDX(i, j, k)]);
-    const double ty = (iyn * vn - iys * vs) / dyj;
+    const double ty = (iyn * vn - iys * vs) * idyj;
     const double fzp = (0.5 * (uc + ut)) * (0.5 * (w[IDX(im, j, kp)] + w[IDX(i, j, kp)]));
     const double fzm = (0.5 * (ub + uc)) * (0.5 * (w[IDX(im, j, k)] + w[IDX(i, j, k)]));
-    const double tz = (fzp - fzm) / dz;
+    const double tz = (fzp - fzm) * idz;
     const double H = -(tx + ty + tz);
     const double L = ((ue - uc) - (uc - uw)) * idx2 + ((ut - uc) - (uc - ub)) * idz2 +
-                     ((un - uc) / g.dyc[j + 1] - (uc - us) / g.dyc[j]) / dyj;
-    const double gp = (p[c] - p[IDX(im, j, k)]) / dx;
+                     ((un - uc) * ic_n - (uc - us) * ic_s) * idyj;
+    const double gp = (p[c] - p[IDX(im, j, k)]) * idx;
     double r = a.gamma * H - a.alpha * (gp - a.fx) + am * L;
     if (a.rho != 0.0) r += a.rho * a.hprev[0][c];
     if (a.hout[0]) a.hout[0][c] = H;
@@ -76,19 +80,19 @@ __global__ __launch_bounds__(256) void k_rhs(RhsK K) {
     const double wn = has_n ? w[IDX(i, j + 1, k)] : 0.0;
     const double ws = has_s ? w[IDX(i, j - 1, k)] : 0.0;
     const double bp = 0.5 * (wc + wt), bm = 0.5 * (wb + wc);
-    const double tz = (bp * bp - bm * bm) / dz;
-    const double iyn = has_n ? (wc * dyn + wn * dyj) / (dyj + dyn) : 0.0;
-    const double iys = has_s ? (ws * dyj + wc * dys) / (dys + dyj) : 0.0;
+    const double tz = (bp * bp - bm * bm) * idz;
+    const double iyn = has_n ? wc * n0 + wn * n1 : 0.0;
+    const double iys = has_s ? ws * s0 + wc * s1 : 0.0;
     const double vn = 0.5 * (v[IDX(i, j + 1, km)] + v[IDX(i, j + 1, k)]);
     const double vs = 0.5 * (v[IDX(i, j, km)] + v[IDX(i, j, k)]);
-    const double ty = (iyn * vn - iys * vs) / dyj;
+    const double ty = (iyn * vn - iys * vs) * idyj;
     const double fxp = (0.5 * (wc + we)) * (0.5 * (u[IDX(ip, j, km)] + u[IDX(ip, j, k)]));
     const double fxm = (0.5 * (ww + wc)) * (0.5 * (u[IDX(i, j, km)] + u[IDX(i, j, k)]));
-    const double tx = (fxp - fxm) / dx;
+    const double tx = (fxp - fxm) * idx;
     const double H = -(tx + ty + tz);
     const double L = ((we - wc) - (wc - ww)) * idx2 + ((wt - wc) - (wc - wb)) * idz2 +
-                     ((wn - wc) / g.dyc[j + 1] - (wc - ws) / g.dyc[j]) / dyj;
-    const double gp = (p[c] - p[IDX(i, j, km)]) / dz;
+                     ((wn - wc) * ic_n - (wc - ws) * ic_s) * idyj;
+    const double gp = (p[c] - p[IDX(i, j, km)]) * idz;
     double r = a.gamma * H - a.alpha * gp + am * L;
     if (a.rho != 0.0) r += a.rho * a.hprev[2][c];
     if (a.hout[2]) a.hout[2][c] = H;
@@ -108,19 +112,18 @@ __global__ __launch_bounds__(256) void k_rhs(RhsK K) {
     const double vc = v[c], ve = v[IDX(ip, j, k)], vw = v[IDX(im, j, k)];
     const double vt = v[IDX(i, j, kp)], vb = v[IDX(i, j, km)];
     const double vn = v[IDX(i, j + 1, k)], vs = v[IDX(i, j - 1, k)];
-    const double den = 1.0 / (dys + dyj);
-    const double uy_i = (u[IDX(i, j - 1, k)] * dyj + u[c] * dys) * den;
-    const double uy_ip = (u[IDX(ip, j - 1, k)] * dyj + u[IDX(ip, j, k)] * dys) * den;
-    const double tx = (uy_ip * (0.5 * (vc + ve)) - uy_i * (0.5 * (vw + vc))) / dx;
+    const double uy_i = u[IDX(i, j - 1, k)] * s0 + u[c] * s1;
+    const double uy_ip = u[IDX(ip, j - 1, k)] * s0 + u[IDX(ip, j, k)] * s1;
+    const double tx = (uy_ip * (0.5 * (vc + ve)) - uy_i * (0.5 * (vw + vc))) * idx;
     const double ct = 0.5 * (vc + vn), cs = 0.5 * (vs + vc);
-    const double ty = (ct * ct - cs * cs) / g.dyc[j];
-    const double wy_k = (w[IDX(i, j - 1, k)] * dyj + w[c] * dys) * den;
-    const double wy_kp = (w[IDX(i, j - 1, kp)] * dyj + w[IDX(i, j, kp)] * dys) * den;
-    const double tz = (wy_kp * (0.5 * (vc + vt)) - wy_k * (0.5 * (vb + vc))) / dz;
+    const double ty = (ct * ct - cs * cs) * ic_s;
+    const double wy_k = w[IDX(i, j - 1, k)] * s0 + w[c] * s1;
+    const double wy_kp = w[IDX(i, j - 1, kp)] * s0 + w[IDX(i, j, kp)] * s1;
+    const double tz = (wy_kp * (0.5 * (vc + vt)) - wy_k * (0.5 * (vb + vc))) * idz;
     const double H = -(tx + ty + tz);
     const double L = ((ve - vc) - (vc - vw)) * idx2 + ((vt - vc) - (vc - vb)) * idz2 +
-                     ((vn - vc) / dyj - (vc - vs) / dys) / g.dyc[j];
-    const double gp = (p[c] - p[IDX(i, j - 1, k)]) / g.dyc[j];
+                     ((vn - vc) * idyj - (vc - vs) * g.idy[j - 1]) * ic_s;
+    const double gp = (p[c] - p[IDX(i, j - 1, k)]) * ic_s;
     double r = a.gamma * H - a.alpha * gp + am * L;
     if (a.rho != 0.0) r += a.rho * a.hprev[1][c];
     if (a.hout[1]) a.hout[1][c] = H;
@@ -133,7 +136,8 @@ void launch_rhs(Prof* pf, hipStream_t s, const GridView& g, const RhsArgs& a) {
   K.g = g;
   K.a = a;
   dim3 block(64, 4);
-  dim3 grid((g.nx + 63) / 64, (g.nz + 3) / 4, g.ny);
+  const int64_t tiles = (int64_t)((g.nx + 63) / 64) * ((g.nz + 3) / 4) * g.ny;
+  dim3 grid((unsigned)tiles);
   IBM_LAUNCH(pf, "rhs", s, k_rhs<<<grid, block, 0, s>>>(K));
 }
 
