@@ -3,14 +3,17 @@
 One "step" is one full time step of the scheme (tagging of the moving body
 at t^n, then two RK2 sub-stages of IB forcing, predictor, consistent mass
 correction, Poisson solve and projection) on the 256x192x256 stretched
-channel with the heaving/pitching zero-thickness plate, FP64, inputs resident
-in HBM.  The body vertices are recomputed on the device every step from
+channel with the heaving/pitching zero-thickness plate, inputs resident in
+HBM.  The body vertices are recomputed on the device every step from
 host-evaluated coefficients (included in the timing).
 
 Prints one JSON line: cell-steps/s per fractional step (cells x sub-stages /
-s), the roofline of the dominant kernel (algorithmic bytes per launch over
-its average duration, from HIP events recorded around that kernel inside the
-timed region), and the CPU oracle timed on a bounded sample.
+s) of the first precision form (FP64 by default), the roofline of its
+dominant kernel (algorithmic bytes per launch over its average duration,
+from HIP events recorded around that kernel inside the timed region), the
+CPU oracle timed on a bounded sample, and under "forms" the same
+measurement for every form timed (the mixed form with its FP64-residual
+refinement counts).
 """
 from __future__ import annotations
 
@@ -28,22 +31,40 @@ METRIC = "cell-steps/s per fractional step, 1 MI355X: FP64 vs mixed vs batched; 
 HBM_PEAK_GBS = 8000.0
 
 
-def algorithmic_bytes(name, nx, ny, nz):
-    """Bytes a launch of kernel `name` must move at minimum (FP64): the
-    fields it reads and writes once, per the pass model of the step."""
+def algorithmic_bytes(name, nx, ny, nz, form="fp64"):
+    """Bytes a launch of kernel `name` must move at minimum: the fields it
+    reads and writes once, per the pass model of the step.  FP64 form: 8-byte
+    values; mixed form: the velocity and phi FP64, p, H, R and the spectrum
+    FP32 (the refinement passes are not counted here)."""
     N = nx * ny * nz
     Nv = nx * (ny + 1) * nz
-    spec = ny * nz * (nx // 2 + 1) * 16
-    table = {
-        "rhs": 8 * (N + Nv + N + N) + 8 * (N + Nv + N) * 2,   # u,v,w,p + H + R
-        "adi_x": 16 * N, "adi_z": 16 * N,                      # per component
-        "adi_y": 24 * N,                                       # w2, u -> u_hat
-        "pois_fftx_fwd": 8 * (N + Nv + N) + spec,              # u_hat -> spectrum
-        "pois_fftz_fwd": 2 * spec, "pois_fftz_inv": 2 * spec,
-        "pois_tri_y": 2 * spec,
-        "pois_fftx_inv": spec + 8 * N,
-        "project": 8 * (N + Nv + N) * 2 + 8 * N + 8 * N * 2,   # u_hat,phi,p -> u,p
-    }
+    U = N + Nv + N                       # u, v, w values
+    if form == "fp64":
+        r = 8
+        spec = ny * nz * (nx // 2 + 1) * 16
+        table = {
+            "rhs": 8 * (U + N) + 8 * U * 2,          # u,v,w,p + H + R
+            "adi_x": 16 * N, "adi_z": 16 * N,        # per component
+            "adi_y": 24 * N,                         # w2, u -> u_hat
+            "pois_fftx_fwd": 8 * U + spec,           # u_hat -> spectrum
+            "pois_fftz_fwd": 2 * spec, "pois_fftz_inv": 2 * spec,
+            "pois_tri_y": 2 * spec,
+            "pois_fftx_inv": spec + 8 * N,
+            "project": 8 * U * 2 + 8 * N + 8 * N * 2,  # u_hat,phi,p -> u,p
+        }
+    else:
+        r = 4
+        spec = ny * nz * (nx // 2 + 1) * 8
+        table = {
+            "rhs": 8 * U + r * N + r * U * 2,        # u,v,w (f64), p + H + R (f32)
+            "adi_x": 2 * r * N, "adi_z": 2 * r * N,
+            "adi_y": r * N + 16 * N,                 # w2 (f32), u (f64) -> u_hat
+            "pois_fftx_fwd": 8 * U + 8 * N + spec,   # u_hat -> kept f64 rhs + spectrum
+            "pois_fftz_fwd": 2 * spec, "pois_fftz_inv": 2 * spec,
+            "pois_tri_y": 2 * spec,
+            "pois_fftx_inv": spec + 8 * N,
+            "project": 8 * U * 2 + 8 * N + r * N * 2,
+        }
     return table.get(name)
 
 
@@ -64,11 +85,12 @@ def csrc_sha():
     return h.hexdigest()[:16]
 
 
-def measured_traffic(kernel, workload):
+def measured_traffic(kernel, workload, form="fp64"):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 PMC
     summary (FETCH_SIZE and WRITE_SIZE, scaled by a plain copy), or None when
-    no summary exists for this workload or the kernel sources changed since."""
-    path = os.path.join(ROOT, "profiles", f"{workload}_fp64_traffic.json")
+    no summary exists for this workload and form or the kernel sources
+    changed since."""
+    path = os.path.join(ROOT, "profiles", f"{workload}_{form}_traffic.json")
     name = COUNTER_NAME.get(kernel)
     if not name or not os.path.exists(path):
         return None
@@ -100,35 +122,21 @@ def cpu_baseline(wl):
                       f"one thread)"}
 
 
-def main():
-    ap = argparse.ArgumentParser()
-    ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="c2")
-    ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--copy-ref-mib", type=int, default=0,
-                    help="also run a plain device copy of this size (PMC scale reference)")
-    args = ap.parse_args()
-    if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for {args.gpus}); the "
-              "multi-GPU design is documented, not built", file=sys.stderr)
-        sys.exit(2)
-
+def run_form(args, wl, form, dev):
+    """Times args.steps full steps of workload wl in one precision form.
+    Returns (elapsed s, warm-up per-kernel profile, dominant kernel, its
+    timed-region event profile, refinement statistics or None)."""
     import numpy as np
     import torch
-    import workloads
     from paper_2606_09799_amd import ibm
 
-    torch.cuda.set_device(0)
-    dev = "cuda:0"
-    wl = workloads.config(args.workload)
-    ctx = ibm.Context(wl.nx, wl.ny, wl.nz, wl.lx, wl.lz, wl.y_faces, wl.re, wl.dpdx)
+    ctx = ibm.Context(wl.nx, wl.ny, wl.nz, wl.lx, wl.lz, wl.y_faces, wl.re, wl.dpdx,
+                      precision=form)
     u0, v0, w0 = wl.fields()
     T = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
     u, v, w = T(u0), T(v0), T(w0)
     del u0, v0, w0
-    p = torch.zeros(ctx.cells, dtype=torch.float64, device=dev)
+    p = torch.zeros(ctx.cells, dtype=ctx.pdtype, device=dev)
     dbodies = []
     for b in wl.bodies:
         ref = T(b.ref)
@@ -151,8 +159,9 @@ def main():
     for s in range(args.warmup):
         one_step(s)
     prof = ibm.ibm_profile_read(ctx)
-    dominant = max((k for k in prof if algorithmic_bytes(k, wl.nx, wl.ny, wl.nz)),
+    dominant = max((k for k in prof if algorithmic_bytes(k, wl.nx, wl.ny, wl.nz, form)),
                    key=lambda k: prof[k][1], default=None)
+    stats = ibm.ibm_refine_stats(ctx, reset=True) if form == "mixed" else None
     # timed region: events only around the dominant kernel
     ibm.ibm_profile(ctx, True, dominant)
     torch.cuda.synchronize()
@@ -163,29 +172,67 @@ def main():
     el = time.perf_counter() - t0
     dom = ibm.ibm_profile_read(ctx)
     ibm.ibm_profile(ctx, False, None)
+    if form == "mixed":
+        stats = ibm.ibm_refine_stats(ctx)
     flags = ibm.ibm_check(ctx)
     if flags:
-        print(f"bench.py: device flags {flags} after the run", file=sys.stderr)
+        print(f"bench.py: device flags {flags} after the {form} run", file=sys.stderr)
         sys.exit(1)
     if not all(torch.isfinite(x).all().item() for x in (u, v, w, p)):
-        print("bench.py: non-finite state", file=sys.stderr)
+        print(f"bench.py: non-finite state after the {form} run", file=sys.stderr)
         sys.exit(1)
+    ctx.close()
+    return el, prof, dominant, dom, stats
 
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="c2")
+    ap.add_argument("--forms", default="fp64,mixed",
+                    help="precision forms to time; the first one is the headline value")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-ref-mib", type=int, default=0,
+                    help="also run a plain device copy of this size (PMC scale reference)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (asked for {args.gpus}); the "
+              "multi-GPU design is documented, not built", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import workloads
+
+    torch.cuda.set_device(0)
+    dev = "cuda:0"
+    wl = workloads.config(args.workload)
+    forms = [f for f in args.forms.split(",") if f]
     substeps = 2
-    value = wl.cells * substeps * args.steps / el
-    roof = None
-    if dominant and dominant in dom:
-        # exact kernel names in the filter match a prefix family (e.g. adi_y)
-        launches, total_ms = dom[dominant]
-        avg_s = total_ms / launches / 1e3
-        ab = algorithmic_bytes(dominant, wl.nx, wl.ny, wl.nz)
-        ach = ab / avg_s / 1e9
-        roof = {"bound": "hbm", "kernel": dominant, "achieved": round(ach, 1),
-                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(ach / HBM_PEAK_GBS, 4),
-                "traffic": measured_traffic(dominant, wl.name),
-                "avg_launch_us": round(avg_s * 1e6, 2),
-                "algorithmic_bytes": ab}
-    warm = {k: round(vv[1] / max(1, args.warmup), 4) for k, vv in prof.items()}
+    results = {}
+    for form in forms:
+        el, prof, dominant, dom, stats = run_form(args, wl, form, dev)
+        r = {"value": wl.cells * substeps * args.steps / el, "ms_per_step": el / args.steps * 1e3,
+             "kernel_ms_per_step": {k: round(vv[1] / max(1, args.warmup), 4)
+                                    for k, vv in prof.items()}}
+        if dominant and dominant in dom:
+            launches, total_ms = dom[dominant]
+            avg_s = total_ms / launches / 1e3
+            ab = algorithmic_bytes(dominant, wl.nx, wl.ny, wl.nz, form)
+            ach = ab / avg_s / 1e9
+            r["roofline"] = {"bound": "hbm", "kernel": dominant, "achieved": round(ach, 1),
+                             "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                             "frac": round(ach / HBM_PEAK_GBS, 4),
+                             "traffic": measured_traffic(dominant, wl.name, form),
+                             "avg_launch_us": round(avg_s * 1e6, 2), "algorithmic_bytes": ab}
+        if stats is not None:
+            solves, corr, worst = stats
+            r["refinement"] = {"poisson_solves": solves, "corrections": corr,
+                               "corrections_per_solve": round(corr / max(1, solves), 3),
+                               "max_final_divergence": worst}
+        results[form] = r
+    head = results[forms[0]]
     copy_ref = None
     if args.copy_ref_mib:
         nb = args.copy_ref_mib * 1024 * 1024 // 8
@@ -197,19 +244,24 @@ def main():
         copy_ref = {"bytes_read": nb * 8, "bytes_written": nb * 8, "launches": 3}
     cpu = None if args.no_cpu_baseline else cpu_baseline(wl)
     out = {
-        "metric": METRIC, "value": value, "unit": "cell-steps/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": el / args.steps * 1e3,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "metric": METRIC, "value": head["value"], "unit": "cell-steps/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": head["ms_per_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if forms[0] == "fp64" else "f32+f64",
         "data": "synthetic",
         "config": {"workload": f"{wl.name}: {wl.nx}x{wl.ny}x{wl.nz} channel, tanh-stretched y, "
-                               f"Re {wl.re:g}, dt {wl.dt:g}, RK2+CN, FP64, "
+                               f"Re {wl.re:g}, dt {wl.dt:g}, RK2+CN, "
                                f"{sum(b.tris.shape[0] for b in wl.bodies)} triangles",
                    "cells": wl.cells, "substeps_per_step": substeps,
-                   "form": "fp64", "parallelism": "single GPU"},
-        "roofline": roof,
+                   "form": forms[0], "parallelism": "single GPU"},
+        "roofline": head.get("roofline"),
         "cpu_baseline": cpu,
-        "kernel_ms_per_step": warm,
+        "kernel_ms_per_step": head["kernel_ms_per_step"],
+        "forms": {f: {k: v for k, v in r.items() if k != "kernel_ms_per_step"}
+                  for f, r in results.items()},
     }
+    if len(forms) > 1:
+        out["forms"]["kernel_ms_per_step"] = {f: r["kernel_ms_per_step"] for f, r in results.items()}
     if copy_ref:
         out["copy_ref"] = copy_ref
     print(json.dumps(out), flush=True)

@@ -13,12 +13,18 @@
  * (RK2+CN or AB+CN).
  *
  * Conventions shared by every call
- *   - Arrays are row-major [y][z][x] (x fastest), FP64.  u, w and p hold
+ *   - Arrays are row-major [y][z][x] (x fastest).  u, w and p hold
  *     ny*nz*nx values; v holds (ny+1)*nz*nx values including the two wall
  *     planes j = 0 and j = ny, which the library keeps at 0.
  *     u(i,j,k) sits at (i dx, yc[j], (k+1/2) dz), v(i,j,k) at
  *     ((i+1/2) dx, yf[j], (k+1/2) dz), w(i,j,k) at ((i+1/2) dx, yc[j], k dz),
  *     p(i,j,k) at ((i+1/2) dx, yc[j], (k+1/2) dz).
+ *   - Precision (ibm_opts.precision).  IBM_FP64: every array is FP64.
+ *     IBM_MIXED: u, v, w, phi and every right-hand side passed in stay FP64;
+ *     p and the H arrays are FP32 ("f32/f64" below: FP32 in the mixed form,
+ *     FP64 otherwise).  The mixed form runs the predictor's line solves and
+ *     the Poisson transforms in FP32 and refines each Poisson solve with
+ *     FP64 residuals (see poisson_solve).
  *   - "dev" pointers are device memory on the context's device; "host"
  *     pointers are host memory.  The caller owns every array it passes; the
  *     library owns its workspace and the tag buffers.
@@ -54,8 +60,11 @@ extern "C" {
 #define IBM_FLAG_CAPACITY 1u
 #define IBM_FLAG_NONFINITE 2u
 #define IBM_FLAG_GEOM 4u
+#define IBM_FLAG_REFINE 8u /* mixed form: a Poisson solve ended above the
+                              refinement tolerance after refine_max steps */
 
 #define IBM_FP64 0
+#define IBM_MIXED 1
 #define IBM_RK2CN 0
 #define IBM_AB2CN 1
 
@@ -74,15 +83,20 @@ typedef struct {
 /* Options.  dpdx is the mean pressure gradient dP/dx; the driving volume
  * force is -dpdx along x.  force_cap bounds each forcing list and the C_B
  * list (0 = automatic: max(65536, cells/16)).  use_q = 1 applies the
- * consistent mass correction of Sec. 3.2, 0 the standard projection. */
+ * consistent mass correction of Sec. 3.2, 0 the standard projection.
+ * Mixed form only: refine_max (0..16, 0 = 3) bounds the FP64-residual
+ * refinements of one Poisson solve, which stop once max|rhs - L_c phi| *
+ * alpha_dt <= refine_tol (0 = 1e-11; alpha_dt = 1 for poisson_solve); after
+ * the projection that product is max|D u - q| (paper Eq. mod_div). */
 typedef struct {
-  int32_t precision; /* IBM_FP64 */
+  int32_t precision; /* IBM_FP64 or IBM_MIXED */
   int32_t scheme;    /* IBM_RK2CN or IBM_AB2CN */
   double re;
   double dpdx;
   int64_t force_cap;
   int32_t use_q;
-  int32_t reserved;
+  int32_t refine_max;
+  double refine_tol;
 } ibm_opts;
 
 /* One triangulated surface at time t^n (paper Sec. 2: the wall position
@@ -112,11 +126,13 @@ typedef struct {
   int64_t capacity;
 } ibm_tags;
 
-/* Flow state owned by the caller.  h[3] (AB+CN only): dev H^{n-1} read and
- * H^n written; may be NULL for RK2+CN. */
+/* Flow state owned by the caller.  u, v, w: dev f64; p: dev f32/f64.
+ * h[3] (AB+CN only): dev f32/f64 H^{n-1} read and H^n written; may be NULL
+ * for RK2+CN. */
 typedef struct {
-  double *u, *v, *w, *p;
-  double* h[3];
+  double *u, *v, *w;
+  void* p;
+  void* h[3];
 } ibm_state;
 
 /* Create a context on the current HIP device for one grid; all workspace is
@@ -171,10 +187,12 @@ int ibm_force(ibm_ctx* ctx, double* u, double* v, double* w);
  * and the approximate factorisation (I - bL_x)(I - bL_z)(I - bL_y) du = R,
  * b = alpha dt/(2 Re), with identity rows on the forcing nodes; then
  * u <- u + du.  gamma, rho: the sub-stage coefficients; h_prev (read when
- * rho != 0) and h_out (written when not NULL): dev arrays of H per
- * component (NULL entries allowed).  p: dev.  u, v, w: dev, in place. */
-int ibm_viscous(ibm_ctx* ctx, const double* p, const double* const* h_prev,
-                double* const* h_out, double gamma, double rho, double dt,
+ * rho != 0) and h_out (written when not NULL): dev f32/f64 arrays of H per
+ * component (NULL entries allowed).  p: dev f32/f64.  u, v, w: dev f64, in
+ * place (the mixed form computes R and H in FP64 arithmetic, stores them in
+ * FP32, solves the three factors in FP32 and adds du to the FP64 u). */
+int ibm_viscous(ibm_ctx* ctx, const void* p, const void* const* h_prev,
+                void* const* h_out, double gamma, double rho, double dt,
                 double* u, double* v, double* w);
 
 /* Consistent mass correction (paper Eqs. mod_div, q_boundary, q_F,
@@ -188,14 +206,19 @@ int ibm_mass_rhs(ibm_ctx* ctx, const double* u, const double* v, const double* w
  * with homogeneous Neumann walls): real FFT in x, complex FFT in z,
  * tridiagonal solve in y per Fourier mode.  The singular (0,0) mode is fixed
  * by phi_0 = 0 and the result is shifted to zero volume-weighted mean.
- * rhs, phi: dev ny*nz*nx (may alias). */
+ * rhs, phi: dev f64 ny*nz*nx (may alias).  Mixed form: the transforms run
+ * in FP32 and the result is refined, phi += S(rhs - L_c phi) with the
+ * residual in FP64, until max|rhs - L_c phi| <= refine_tol or refine_max
+ * refinements; the stopping test runs on the device (no synchronisation),
+ * IBM_FLAG_REFINE is raised if the tolerance was not reached. */
 int poisson_solve(ibm_ctx* ctx, const double* rhs, double* phi);
 
 /* Projection and pressure update (paper Eqs. projection, update_pressure):
  * u <- u - alpha_dt G phi on every interior velocity node;
- * p <- p + phi - alpha_dt/(2 Re) L_c phi.  All dev, in place. */
+ * p <- p + phi - alpha_dt/(2 Re) L_c phi.  phi, u, v, w: dev f64; p: dev
+ * f32/f64; in place. */
 int ibm_project(ibm_ctx* ctx, const double* phi, double alpha_dt, double* u,
-                double* v, double* w, double* p);
+                double* v, double* w, void* p);
 
 /* One whole time step of the scheme (paper Sec. 2 and Sec. 3): tags the
  * bodies at t^n once, then for every sub-stage: IB forcing, predictor,
@@ -203,6 +226,12 @@ int ibm_project(ibm_ctx* ctx, const double* phi, double alpha_dt, double* u,
  * The bodies stay at t^n for all sub-stages. */
 int ibm_step(ibm_ctx* ctx, ibm_state* s, const ibm_body* bodies, int32_t nbody,
              double dt);
+
+/* Mixed form: synchronise and copy the refinement statistics since the
+ * last reset to stats (host double[3]): Poisson solves, FP64-residual
+ * corrections applied, and the largest final max|rhs - L_c phi| * alpha_dt.
+ * reset = 1 clears them. */
+int ibm_refine_stats(ibm_ctx* ctx, double* stats, int32_t reset);
 
 /* Synchronise the stream and return (and clear) the sticky device flags. */
 int ibm_check(ibm_ctx* ctx, uint32_t* flags);

@@ -17,32 +17,38 @@
 // line; each thread finally reconstructs its rows.  Every element is read
 // once and written once.  Identity rows (a = c = 0, b = 1, d = 0) need no
 // special path.
+//
+// Precision T: double, or float in the mixed form (right-hand sides,
+// tables, scratch and arithmetic in FP32; the y sweep adds its FP32 solution
+// to the FP64 velocity).
 #include "geom.h"
 
 namespace ibm {
 
 constexpr int LMAX = LINE_LMAX;
 
+template <typename T>
 struct LineK {
-  double* d;          // right-hand side in; solution out (x, z)
+  T* d;               // right-hand side in; solution out (x, z)
   double* u;          // y only: u += solution
   const uint32_t* mask;
-  double* sa;         // scratch for segments holding identity rows
-  double* sc;
-  const double* tab;  // mask-free elimination tables [4][P][LMAX]
+  T* sa;              // scratch for segments holding identity rows
+  T* sc;
+  const T* tab;       // mask-free elimination tables [4][P][LMAX]
   int n, P, L, r;     // rows, segments, base length, segments with L+1 rows
   int cyc;
-  double a, b, c;     // constant coefficients (x, z)
-  const double* A;    // per-row coefficients (y)
-  const double* B;
-  const double* C;
+  T a, b, c;          // constant coefficients (x, z)
+  const T* A;         // per-row coefficients (y)
+  const T* B;
+  const T* C;
   int mode;           // 0 x-rows, 1 z-lines, 2 y-lines
   int nx, nz, j0, nj;
   int64_t plane;
   int tl;             // lines per block
 };
 
-__device__ __forceinline__ void row_coef(const LineK& K, int i, double& a, double& b, double& c) {
+template <typename T>
+__device__ __forceinline__ void row_coef(const LineK<T>& K, int i, T& a, T& b, T& c) {
   if (K.A) {
     a = K.A[i];
     b = K.B[i];
@@ -54,26 +60,27 @@ __device__ __forceinline__ void row_coef(const LineK& K, int i, double& a, doubl
   }
 }
 
-__device__ __forceinline__ double row_a(const LineK& K, int i) { return K.A ? K.A[i] : K.a; }
+template <typename T>
+__device__ __forceinline__ T row_a(const LineK<T>& K, int i) { return K.A ? K.A[i] : K.a; }
 
 // serial solve of one line's P x P cyclic separator system (Sherman-
 // Morrison on top of Thomas), for cyclic lines whose segment count is not a
 // power of two.  A(f, s) addresses the LDS arrays: f = 3..6 the sub-, main,
 // super-diagonal and right-hand side, 7 the solution, 0 and 1 scratch.
-template <typename Acc>
+template <typename T, typename Acc>
 __device__ void reduced_solve_cyclic(Acc A, int P) {
-  const double g0 = -A(4, 0);
-  const double bc = A(3, 0);      // couples z[P-1] in row 0
-  const double ac = A(5, P - 1);  // couples z[0] in row P-1
-  double cpp = 0.0, yp = 0.0, zp = 0.0;
+  const T g0 = -A(4, 0);
+  const T bc = A(3, 0);      // couples z[P-1] in row 0
+  const T ac = A(5, P - 1);  // couples z[0] in row P-1
+  T cpp = 0, yp = 0, zp = 0;
   for (int s = 0; s < P; ++s) {
-    double bs = A(4, s);
+    T bs = A(4, s);
     if (s == 0) bs -= g0;
     if (s == P - 1) bs -= ac * bc / g0;
-    const double as = s ? A(3, s) : 0.0;
-    const double inv = 1.0 / (bs - as * cpp);
-    const double us = (s == 0) ? g0 : (s == P - 1 ? ac : 0.0);
-    cpp = (s < P - 1) ? A(5, s) * inv : 0.0;
+    const T as = s ? A(3, s) : T(0);
+    const T inv = T(1) / (bs - as * cpp);
+    const T us = (s == 0) ? g0 : (s == P - 1 ? ac : T(0));
+    cpp = (s < P - 1) ? A(5, s) * inv : T(0);
     yp = (A(6, s) - as * yp) * inv;
     zp = (us - as * zp) * inv;
     A(0, s) = cpp;
@@ -84,16 +91,18 @@ __device__ void reduced_solve_cyclic(Acc A, int P) {
     A(7, s) -= A(0, s) * A(7, s + 1);
     A(1, s) -= A(0, s) * A(1, s + 1);
   }
-  const double fact = (A(7, 0) + bc * A(7, P - 1) / g0) / (1.0 + A(1, 0) + bc * A(1, P - 1) / g0);
+  const T fact = (A(7, 0) + bc * A(7, P - 1) / g0) / (T(1) + A(1, 0) + bc * A(1, P - 1) / g0);
   for (int s = 0; s < P; ++s) A(7, s) -= fact * A(1, s);
 }
 
-__global__ __launch_bounds__(256) void k_line(LineK K) {
-  extern __shared__ double lds[];
+template <typename T>
+__global__ __launch_bounds__(256) void k_line(LineK<T> K) {
+  extern __shared__ __align__(16) unsigned char ldsraw[];
+  T* lds = reinterpret_cast<T*>(ldsraw);
   const int tid = threadIdx.x;
   const int P = K.P;
-  double* tabs = lds;                    // 4 * P * LMAX
-  double* sm = lds + 4 * P * LMAX;       // 8 * P * lines per block
+  T* tabs = lds;                         // 4 * P * LMAX
+  T* sm = lds + 4 * P * LMAX;            // 8 * P * lines per block
   for (int q = tid; q < 4 * P * LMAX; q += blockDim.x) {
     const int qq = q / (P * LMAX), rem = q % (P * LMAX), ss = rem / LMAX, ee = rem % LMAX;
     tabs[(qq * LMAX + ee) * P + ss] = K.tab[q];
@@ -134,13 +143,13 @@ __global__ __launch_bounds__(256) void k_line(LineK K) {
   // table entry (q, e) of this segment; layout [q][e][s] keeps the lanes of
   // consecutive segments on consecutive LDS words
 #define TAB(q, e) tabs[((q) * LMAX + (e)) * P + s]
-  double dd[LMAX];
-  double dz = 0.0, az = 0.0, bz = 1.0, cz = 0.0;
-  double a0 = 0.0, c0 = 0.0, ahl = 0.0, chl = 0.0, dhl = 0.0;
+  T dd[LMAX];
+  T dz = 0, az = 0, bz = 1, cz = 0;
+  T a0 = 0, c0 = 0, ahl = 0, chl = 0, dhl = 0;
   uint32_t mbits = 0;
   if (valid) {
     // issue every load of the segment before using any of them
-    double raw[LMAX];
+    T raw[LMAX];
 #pragma unroll
     for (int e = 0; e < LMAX; ++e)
       if (e < len) raw[e] = K.d[base + (int64_t)(lo + e) * es];
@@ -159,19 +168,19 @@ __global__ __launch_bounds__(256) void k_line(LineK K) {
 #pragma unroll
     for (int e = 0; e < LMAX; ++e)
       if (e < len) {
-        const double v = ((mbits >> e) & 1u) ? 0.0 : raw[e];
+        const T v = ((mbits >> e) & 1u) ? T(0) : raw[e];
         if (e < m) dd[e] = v; else dz = v;
       }
     if ((mbits & ((1u << m) - 1u)) == 0u) {
       // mask-free interior: the elimination coefficients come from the tables
-      double dt = 0.0;
+      T dt = 0;
 #pragma unroll
       for (int e = 0; e < LMAX - 1; ++e)
         if (e < m) {
           dt = (dd[e] - row_a(K, lo + e) * dt) * TAB(0, e);
           dd[e] = dt;
         }
-      double dh = 0.0;
+      T dh = 0;
 #pragma unroll
       for (int e = LMAX - 2; e >= 0; --e)
         if (e < m) {
@@ -185,20 +194,20 @@ __global__ __launch_bounds__(256) void k_line(LineK K) {
       chl = TAB(3, m - 1);
     } else {
       // general interior with identity rows: coefficients through the scratch
-      double at = 0.0, ct = 0.0, dt = 0.0;
+      T at = 0, ct = 0, dt = 0;
 #pragma unroll
       for (int e = 0; e < LMAX - 1; ++e)
         if (e < m) {
           const int i = lo + e;
           const int64_t o = base + (int64_t)i * es;
-          double a, b, c;
+          T a, b, c;
           row_coef(K, i, a, b, c);
           if ((mbits >> e) & 1u) {
-            a = 0.0;
-            b = 1.0;
-            c = 0.0;
+            a = 0;
+            b = 1;
+            c = 0;
           }
-          const double inv = 1.0 / (b - a * ct);
+          const T inv = T(1) / (b - a * ct);
           at = (e == 0) ? a * inv : -a * at * inv;
           ct = c * inv;
           dt = (dd[e] - a * dt) * inv;
@@ -206,12 +215,12 @@ __global__ __launch_bounds__(256) void k_line(LineK K) {
           K.sa[o] = at;
           K.sc[o] = ct;
         }
-      double ah = 0.0, ch = 0.0, dh = 0.0;
+      T ah = 0, ch = 0, dh = 0;
 #pragma unroll
       for (int e = LMAX - 2; e >= 0; --e)
         if (e < m) {
           const int64_t o = base + (int64_t)(lo + e) * es;
-          const double at_e = K.sa[o], ct_e = K.sc[o];
+          const T at_e = K.sa[o], ct_e = K.sc[o];
           if (e == m - 1) {
             ah = at_e;
             ch = ct_e;
@@ -233,9 +242,9 @@ __global__ __launch_bounds__(256) void k_line(LineK K) {
     }
     row_coef(K, lo + m, az, bz, cz);
     if ((mbits >> m) & 1u) {
-      az = 0.0;
-      bz = 1.0;
-      cz = 0.0;
+      az = 0;
+      bz = 1;
+      cz = 0;
     }
   }
   // LDS: 8 arrays of P doubles per line; neighbouring lanes (consecutive
@@ -243,22 +252,22 @@ __global__ __launch_bounds__(256) void k_line(LineK K) {
   // consecutive words
   const int TL = K.tl;
   const bool rowmajor = (K.mode == 0);
-  auto at = [&](int f, int seg) -> double& {
+  auto at = [&](int f, int seg) -> T& {
     return rowmajor ? sm[((size_t)f * TL + lb) * P + seg] : sm[((size_t)f * P + seg) * TL + lb];
   };
   if (active) {
     at(0, s) = a0;
     at(1, s) = c0;
-    at(2, s) = valid ? dd[0] : 0.0;
+    at(2, s) = valid ? dd[0] : T(0);
   }
   __syncthreads();
-  double ra = 0.0, rb = 1.0, rg = 0.0, rd = 0.0;  // this segment's separator row
+  T ra = 0, rb = 1, rg = 0, rd = 0;  // this segment's separator row
   if (active) {
     int sn = s + 1;
-    double czz = cz;
+    T czz = cz;
     if (sn == P) {
       sn = 0;
-      if (!K.cyc) czz = 0.0;
+      if (!K.cyc) czz = 0;
     }
     ra = -az * ahl;
     rb = bz - az * chl - czz * at(0, sn);
@@ -278,10 +287,10 @@ __global__ __launch_bounds__(256) void k_line(LineK K) {
     // out-of-range rows of a walled line act as identity rows; a cyclic
     // system of 2^k rows closes with couplings onto the row itself
     for (int st = 1; st < P; st <<= 1) {
-      double na = 0.0, nb = 1.0, ng = 0.0, nd = 0.0;
+      T na = 0, nb = 1, ng = 0, nd = 0;
       if (active) {
         int im = s - st, ip = s + st;
-        double am = 0.0, bm = 1.0, gm = 0.0, dm = 0.0, ap = 0.0, bp = 1.0, gp = 0.0, dp = 0.0;
+        T am = 0, bm = 1, gm = 0, dm = 0, ap = 0, bp = 1, gp = 0, dp = 0;
         if (K.cyc) {
           im &= P - 1;
           ip &= P - 1;
@@ -298,7 +307,7 @@ __global__ __launch_bounds__(256) void k_line(LineK K) {
           gp = at(5, ip);
           dp = at(6, ip);
         }
-        const double k1 = ra / bm, k2 = rg / bp;
+        const T k1 = ra / bm, k2 = rg / bp;
         na = -am * k1;
         ng = -gp * k2;
         nb = rb - gm * k1 - ap * k2;
@@ -319,29 +328,30 @@ __global__ __launch_bounds__(256) void k_line(LineK K) {
     }
     if (active) at(7, s) = K.cyc ? rd / (ra + rb + rg) : rd / rb;
   } else {
-    if (active && s == 0) reduced_solve_cyclic(at, P);
+    if (active && s == 0) reduced_solve_cyclic<T>(at, P);
   }
   __syncthreads();
   if (valid) {
-    const double zr = at(7, s);
-    const double zl = (s > 0) ? at(7, s - 1) : (K.cyc ? at(7, P - 1) : 0.0);
+    const T zr = at(7, s);
+    const T zl = (s > 0) ? at(7, s - 1) : (K.cyc ? at(7, P - 1) : T(0));
     const bool fast = (mbits & ((1u << m) - 1u)) == 0u;
 #pragma unroll
     for (int e = 0; e < LMAX; ++e)
       if (e < len) {
         const int64_t o = base + (int64_t)(lo + e) * es;
-        double x = zr;
+        T x = zr;
         if (e < m) x = fast ? dd[e] - TAB(2, e) * zl - TAB(3, e) * zr
                             : dd[e] - K.sa[o] * zl - K.sc[o] * zr;
         if (K.mode == 2)
-          K.u[o] += x;
+          K.u[o] += (double)x;
         else
           K.d[o] = x;
       }
   }
 }
 
-static void launch_line(Prof* pf, hipStream_t s, LineK K, const char* name) {
+template <typename T>
+static void launch_line(Prof* pf, hipStream_t s, LineK<T> K, const char* name) {
   dim3 grid;
   int threads;
   if (K.mode == 0) {
@@ -355,74 +365,82 @@ static void launch_line(Prof* pf, hipStream_t s, LineK K, const char* name) {
     threads = K.tl * K.P;
     grid = dim3((K.nx + K.tl - 1) / K.tl, K.mode == 1 ? K.nj : K.nz);
   }
-  const size_t shm = sizeof(double) * (4 * (size_t)K.P * LMAX + 8 * (size_t)K.P * K.tl);
-  IBM_LAUNCH(pf, name, s, k_line<<<grid, threads, shm, s>>>(K));
+  const size_t shm = sizeof(T) * (4 * (size_t)K.P * LMAX + 8 * (size_t)K.P * K.tl);
+  IBM_LAUNCH(pf, name, s, k_line<T><<<grid, threads, shm, s>>>(K));
 }
 
-static LineK base_k(const GridView& g, double* d, const uint32_t* mask) {
-  LineK K{};
-  K.d = d;
+template <typename T>
+static LineK<T> base_k(const GridView& g, void* d, const uint32_t* mask, void* sa, void* sc) {
+  LineK<T> K{};
+  K.d = static_cast<T*>(d);
   K.mask = mask;
+  K.sa = static_cast<T*>(sa);
+  K.sc = static_cast<T*>(sc);
   K.nx = g.nx;
   K.nz = g.nz;
   K.plane = (int64_t)g.nz * g.nx;
   return K;
 }
 
-void launch_adi_x(Prof* pf, hipStream_t s, const GridView& g, int comp, double* d,
-                  const uint32_t* mask, const CyclicTab& t, double* sa, double* sc) {
-  LineK K = base_k(g, d, mask);
-  K.sa = sa;
-  K.sc = sc;
-  K.tab = t.seg;
-  K.mode = 0;
-  K.n = g.nx;
+template <typename T>
+static void adi_periodic(Prof* pf, hipStream_t s, const GridView& g, int comp, int mode, void* d,
+                         const uint32_t* mask, const CyclicTab& t, void* sa, void* sc) {
+  LineK<T> K = base_k<T>(g, d, mask, sa, sc);
+  K.tab = static_cast<const T*>(sizeof(T) == sizeof(float) ? (const void*)t.seg32 : (const void*)t.seg);
+  K.mode = mode;
+  K.n = (mode == 0) ? g.nx : g.nz;
   K.cyc = 1;
   line_plan(K.n, true, &K.P, &K.L, &K.r);
-  K.a = t.a;
-  K.b = t.b;
-  K.c = t.c;
+  K.a = (T)t.a;
+  K.b = (T)t.b;
+  K.c = (T)t.c;
   K.j0 = (comp == 1) ? 1 : 0;
   K.nj = (comp == 1) ? g.ny - 1 : g.ny;
-  launch_line(pf, s, K, "adi_x");
+  launch_line(pf, s, K, mode == 0 ? "adi_x" : "adi_z");
 }
 
-void launch_adi_z(Prof* pf, hipStream_t s, const GridView& g, int comp, double* d,
-                  const uint32_t* mask, const CyclicTab& t, double* sa, double* sc) {
-  LineK K = base_k(g, d, mask);
-  K.sa = sa;
-  K.sc = sc;
-  K.tab = t.seg;
-  K.mode = 1;
-  K.n = g.nz;
-  K.cyc = 1;
-  line_plan(K.n, true, &K.P, &K.L, &K.r);
-  K.a = t.a;
-  K.b = t.b;
-  K.c = t.c;
-  K.j0 = (comp == 1) ? 1 : 0;
-  K.nj = (comp == 1) ? g.ny - 1 : g.ny;
-  launch_line(pf, s, K, "adi_z");
+void launch_adi_x(Prof* pf, hipStream_t s, const GridView& g, int comp, void* d,
+                  const uint32_t* mask, const CyclicTab& t, void* sa, void* sc, int fp32) {
+  if (fp32)
+    adi_periodic<float>(pf, s, g, comp, 0, d, mask, t, sa, sc);
+  else
+    adi_periodic<double>(pf, s, g, comp, 0, d, mask, t, sa, sc);
 }
 
-void launch_adi_y(Prof* pf, hipStream_t s, const GridView& g, int comp, double* d, double* u,
-                  const uint32_t* mask, const YTab& t, double* sa, double* sc) {
-  LineK K = base_k(g, d, mask);
-  K.sa = sa;
-  K.sc = sc;
-  K.tab = t.seg;
+void launch_adi_z(Prof* pf, hipStream_t s, const GridView& g, int comp, void* d,
+                  const uint32_t* mask, const CyclicTab& t, void* sa, void* sc, int fp32) {
+  if (fp32)
+    adi_periodic<float>(pf, s, g, comp, 1, d, mask, t, sa, sc);
+  else
+    adi_periodic<double>(pf, s, g, comp, 1, d, mask, t, sa, sc);
+}
+
+template <typename T>
+static void adi_wall(Prof* pf, hipStream_t s, const GridView& g, void* d, double* u,
+                     const uint32_t* mask, const YTab& t, void* sa, void* sc) {
+  LineK<T> K = base_k<T>(g, d, mask, sa, sc);
+  const bool f = sizeof(T) == sizeof(float);
+  K.tab = static_cast<const T*>(f ? (const void*)t.seg32 : (const void*)t.seg);
   K.mode = 2;
   K.u = u;
   K.n = t.n;
   K.cyc = 0;
   line_plan(K.n, false, &K.P, &K.L, &K.r);
-  K.A = t.a;
-  K.B = t.b;
-  K.C = t.c;
+  K.A = static_cast<const T*>(f ? (const void*)t.a32 : (const void*)t.a);
+  K.B = static_cast<const T*>(f ? (const void*)t.b32 : (const void*)t.b);
+  K.C = static_cast<const T*>(f ? (const void*)t.c32 : (const void*)t.c);
   K.j0 = t.j0;
   K.nj = t.n;
-  (void)comp;
   launch_line(pf, s, K, "adi_y");
+}
+
+void launch_adi_y(Prof* pf, hipStream_t s, const GridView& g, int comp, void* d, double* u,
+                  const uint32_t* mask, const YTab& t, void* sa, void* sc, int fp32) {
+  (void)comp;
+  if (fp32)
+    adi_wall<float>(pf, s, g, d, u, mask, t, sa, sc);
+  else
+    adi_wall<double>(pf, s, g, d, u, mask, t, sa, sc);
 }
 
 }  // namespace ibm

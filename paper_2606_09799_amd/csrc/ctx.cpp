@@ -93,14 +93,26 @@ struct ibm_ctx {
   int cur_slot = -1;
   const BodyDev* d_bodies = nullptr;
 
-  double* R[3] = {};
-  double* H[3] = {};
-  double* sa = nullptr;  // line-solve scratch (segments with forcing nodes)
-  double* sc = nullptr;
+  // precision of the predictor and spectral work: FP64, or FP32 in the mixed
+  // form (element size es); the velocity and phi are FP64 in both
+  int fp32 = 0;
+  size_t es = sizeof(double);
+  void* R[3] = {};
+  void* H[3] = {};
+  void* sa = nullptr;  // line-solve scratch (segments with forcing nodes)
+  void* sc = nullptr;
   double* rhs_tmp = nullptr;
   double* phi = nullptr;
-  double2* spec = nullptr;
-  double* cscr = nullptr;
+  void* spec = nullptr;
+  // mixed form: FP64-residual refinement of the Poisson solve
+  double* rhs_keep = nullptr;
+  u64* rmax = nullptr;
+  double* rstats = nullptr;
+  double* zm = nullptr;
+  double* psum = nullptr;
+  double* msum = nullptr;
+  int nref = 0;
+  double rtol = 0.0;
   double* partial = nullptr;
   double* qf = nullptr;
   uint32_t* flags = nullptr;
@@ -108,6 +120,7 @@ struct ibm_ctx {
   // line-solve tables for one beta
   double tab_beta = -1.0;
   double* tabmem = nullptr;
+  float* tabmem32 = nullptr;
   int64_t tabcap = 0;
   CyclicTab ctx_x{}, ctx_z{};
   YTab yt[2]{};  // 0: u and w, 1: v
@@ -137,6 +150,13 @@ static int dalloc(ibm_ctx* c, T** p, int64_t n) {
   return IBM_OK;
 }
 
+static int dalloc_bytes(ibm_ctx* c, void** p, int64_t n, size_t es) {
+  char* q = nullptr;
+  int rc = dalloc(c, &q, n * (int64_t)es);
+  *p = q;
+  return rc;
+}
+
 template <typename T>
 static int upload(ibm_ctx* c, T* dst, const std::vector<T>& src) {
   HIPCHK(hipMemcpy(dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice));
@@ -162,16 +182,24 @@ static bool plan_fft(int n, FFTPlan* P) {
 
 static int make_twiddles(ibm_ctx* c, FFTPlan* P) {
   std::vector<double2> tw(P->n);
+  std::vector<float2> tw32(P->n);
   for (int k = 0; k < P->n; ++k) {
     const long double a = 2.0L * 3.14159265358979323846264338327950288L * k / P->n;
     tw[k] = make_double2((double)cosl(a), (double)(-sinl(a)));
+    tw32[k] = make_float2((float)cosl(a), (float)(-sinl(a)));
   }
   double2* d = nullptr;
+  float2* d32 = nullptr;
   int rc = dalloc(c, &d, P->n);
+  if (rc) return rc;
+  rc = dalloc(c, &d32, P->n);
   if (rc) return rc;
   rc = upload(c, d, tw);
   if (rc) return rc;
+  rc = upload(c, d32, tw32);
+  if (rc) return rc;
   P->tw = d;
+  P->tw32 = d32;
   return IBM_OK;
 }
 
@@ -297,23 +325,35 @@ static int build_tables(ibm_ctx* c, double beta) {
   // stream, and keep the host copy alive until it has been consumed
   HIPCHK(hipStreamSynchronize(c->stream));
   HIPCHK(hipMemcpy(c->tabmem, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice));
-  double* p = c->tabmem;
+  if (c->fp32) {  // the same tables rounded to FP32, at the same offsets
+    std::vector<float> h32(h.begin(), h.end());
+    HIPCHK(hipMemcpy(c->tabmem32, h32.data(), h32.size() * sizeof(float), hipMemcpyHostToDevice));
+  }
+  int64_t off = 0;
   auto take = [&](int n) {
-    const double* q = p;
-    p += n;
-    return q;
+    const int64_t o = off;
+    off += n;
+    return o;
   };
-  c->ctx_x.cp = take(nx); c->ctx_x.inv = take(nx); c->ctx_x.W = take(nx); c->ctx_x.Z = take(nx);
-  c->ctx_z.cp = take(nz); c->ctx_z.inv = take(nz); c->ctx_z.W = take(nz); c->ctx_z.Z = take(nz);
+  auto d64 = [&](int64_t o) { return (const double*)(c->tabmem + o); };
+  auto d32 = [&](int64_t o) { return c->tabmem32 ? (const float*)(c->tabmem32 + o) : nullptr; };
+  c->ctx_x.cp = d64(take(nx)); c->ctx_x.inv = d64(take(nx));
+  c->ctx_x.W = d64(take(nx)); c->ctx_x.Z = d64(take(nx));
+  c->ctx_z.cp = d64(take(nz)); c->ctx_z.inv = d64(take(nz));
+  c->ctx_z.W = d64(take(nz)); c->ctx_z.Z = d64(take(nz));
   for (int q = 0; q < 2; ++q) {
     const int n = c->yt[q].n;
-    c->yt[q].a = take(n); c->yt[q].b = take(n); c->yt[q].c = take(n);
-    c->yt[q].cp = take(n); c->yt[q].inv = take(n);
+    const int64_t oa = take(n), ob = take(n), oc = take(n);
+    c->yt[q].a = d64(oa); c->yt[q].b = d64(ob); c->yt[q].c = d64(oc);
+    c->yt[q].a32 = d32(oa); c->yt[q].b32 = d32(ob); c->yt[q].c32 = d32(oc);
+    c->yt[q].cp = d64(take(n)); c->yt[q].inv = d64(take(n));
   }
-  c->ctx_x.seg = take((int)sx.size());
-  c->ctx_z.seg = take((int)sz.size());
-  c->yt[0].seg = take((int)sy0.size());
-  c->yt[1].seg = take((int)sy1.size());
+  const int64_t ox = take((int)sx.size()), oz = take((int)sz.size());
+  const int64_t oy0 = take((int)sy0.size()), oy1 = take((int)sy1.size());
+  c->ctx_x.seg = d64(ox); c->ctx_x.seg32 = d32(ox);
+  c->ctx_z.seg = d64(oz); c->ctx_z.seg32 = d32(oz);
+  c->yt[0].seg = d64(oy0); c->yt[0].seg32 = d32(oy0);
+  c->yt[1].seg = d64(oy1); c->yt[1].seg32 = d32(oy1);
   c->tab_beta = beta;
   return IBM_OK;
 }
@@ -360,7 +400,10 @@ int ibm_create(const ibm_grid* gr, const ibm_opts* o, void* stream, ibm_ctx** ou
   if (gr->nx < 8 || gr->nz < 8 || gr->ny < 3) FAIL(IBM_EINVAL, "grid too small (nx, nz >= 8, ny >= 3)");
   if (!gr->y_faces) FAIL(IBM_EINVAL, "y_faces is NULL");
   if (!(gr->lx > 0) || !(gr->lz > 0) || !(o->re > 0)) FAIL(IBM_EINVAL, "lx, lz and re must be > 0");
-  if (o->precision != IBM_FP64) FAIL(IBM_EINVAL, "only IBM_FP64 is available");
+  if (o->precision != IBM_FP64 && o->precision != IBM_MIXED) FAIL(IBM_EINVAL, "unknown precision");
+  if (o->refine_max < 0 || o->refine_max > 16 || o->refine_tol < 0 || !(o->refine_tol == o->refine_tol))
+    FAIL(IBM_EINVAL, "refine_max must be 0..16 and refine_tol >= 0");
+  if (gr->ny > 8192) FAIL(IBM_EINVAL, "ny above 8192");
   if (o->scheme != IBM_RK2CN && o->scheme != IBM_AB2CN) FAIL(IBM_EINVAL, "unknown scheme");
   for (int j = 0; j < gr->ny; ++j)
     if (!(gr->y_faces[j + 1] > gr->y_faces[j])) FAIL(IBM_EINVAL, "y_faces not strictly increasing");
@@ -386,6 +429,10 @@ int ibm_create(const ibm_grid* gr, const ibm_opts* o, void* stream, ibm_ctx** ou
   c->lx = gr->lx;
   c->lz = gr->lz;
   c->opts = *o;
+  c->fp32 = (o->precision == IBM_MIXED) ? 1 : 0;
+  c->es = c->fp32 ? sizeof(float) : sizeof(double);
+  c->nref = o->refine_max > 0 ? o->refine_max : 3;
+  c->rtol = o->refine_tol > 0 ? o->refine_tol : 1e-11;
   const int nx = c->nx, ny = c->ny, nz = c->nz;
   if (!plan_fft(nx, &c->px) || !plan_fft(nz, &c->pz)) {
     delete c;
@@ -493,16 +540,24 @@ int ibm_create(const ibm_grid* gr, const ibm_opts* o, void* stream, ibm_ctx** ou
 
   for (int q = 0; q < 3; ++q) {
     const int64_t nn = (q == 1) ? c->nvface : c->ncell;
-    TRY(dalloc(c, &c->R[q], nn));
-    TRY(dalloc(c, &c->H[q], nn));
+    TRY(dalloc_bytes(c, &c->R[q], nn, c->es));
+    TRY(dalloc_bytes(c, &c->H[q], nn, c->es));
   }
-  TRY(dalloc(c, &c->sa, c->nvface));
-  TRY(dalloc(c, &c->sc, c->nvface));
+  TRY(dalloc_bytes(c, &c->sa, c->nvface, c->es));
+  TRY(dalloc_bytes(c, &c->sc, c->nvface, c->es));
   TRY(dalloc(c, &c->rhs_tmp, c->ncell));
   TRY(dalloc(c, &c->phi, c->ncell));
   const int64_t nspec = (int64_t)ny * nz * g.nxh;
-  TRY(dalloc(c, &c->spec, nspec));
-  TRY(dalloc(c, &c->cscr, nspec));
+  TRY(dalloc_bytes(c, &c->spec, nspec, 2 * c->es));
+  if (c->fp32) {
+    TRY(dalloc(c, &c->rhs_keep, c->ncell));
+    TRY(dalloc(c, &c->rmax, c->nref + 2));
+    TRY(dalloc(c, &c->zm, ny));
+    TRY(dalloc(c, &c->msum, c->nref + 2));
+    // per-block partials of the x passes (at least one x-row per block)
+    TRY(dalloc(c, &c->psum, (int64_t)ny * nz));
+  }
+  TRY(dalloc(c, &c->rstats, 3));
   TRY(dalloc(c, &c->partial, 512));
   TRY(dalloc(c, &c->qf, 1));
   TRY(dalloc(c, &c->flags, 1));
@@ -516,6 +571,7 @@ int ibm_create(const ibm_grid* gr, const ibm_opts* o, void* stream, ibm_ctx** ou
     segs += 2 * P;
     c->tabcap = 4 * (int64_t)(nx + nz) + 10 * (int64_t)ny + 4 * (int64_t)segs * LINE_LMAX;
     TRY(dalloc(c, &c->tabmem, c->tabcap));
+    if (c->fp32) TRY(dalloc(c, &c->tabmem32, c->tabcap));
   }
 
   // Poisson tables
@@ -557,6 +613,7 @@ int ibm_create(const ibm_grid* gr, const ibm_opts* o, void* stream, ibm_ctx** ou
   launch_fill_u32(nullptr, c->stream, c->flags, 1, 0u);
   launch_fill_u64(nullptr, c->stream, reinterpret_cast<u64*>(tb.count), 4, 0ull);
   launch_fill_f64(nullptr, c->stream, c->qf, 1, 0.0);
+  launch_fill_f64(nullptr, c->stream, c->rstats, 3, 0.0);
   if (hipStreamSynchronize(c->stream) != hipSuccess || hipGetLastError() != hipSuccess) {
     free_all(c);
     delete c;
@@ -705,7 +762,7 @@ int ibm_force(ibm_ctx* c, double* u, double* v, double* w) {
   return launch_status();
 }
 
-static int viscous(ibm_ctx* c, const double* p, const double* const* hprev, double* const* hout,
+static int viscous(ibm_ctx* c, const void* p, const void* const* hprev, void* const* hout,
                    double gamma, double rho, double dt, double* u, double* v, double* w) {
   const double alpha = gamma + rho;
   int rc = build_tables(c, alpha * dt / (2.0 * c->opts.re));
@@ -729,18 +786,21 @@ static int viscous(ibm_ctx* c, const double* p, const double* const* hprev, doub
   a.dt = dt;
   a.re = c->opts.re;
   a.fx = -c->opts.dpdx;
+  a.fp32 = c->fp32;
   launch_rhs(&c->prof, c->stream, c->g, a);
   double* f[3] = {u, v, w};
   for (int q = 0; q < 3; ++q) {
-    launch_adi_x(&c->prof, c->stream, c->g, q, c->R[q], c->tb.mask[q], c->ctx_x, c->sa, c->sc);
-    launch_adi_z(&c->prof, c->stream, c->g, q, c->R[q], c->tb.mask[q], c->ctx_z, c->sa, c->sc);
+    launch_adi_x(&c->prof, c->stream, c->g, q, c->R[q], c->tb.mask[q], c->ctx_x, c->sa, c->sc,
+                 c->fp32);
+    launch_adi_z(&c->prof, c->stream, c->g, q, c->R[q], c->tb.mask[q], c->ctx_z, c->sa, c->sc,
+                 c->fp32);
     launch_adi_y(&c->prof, c->stream, c->g, q, c->R[q], f[q], c->tb.mask[q],
-                 c->yt[q == 1 ? 1 : 0], c->sa, c->sc);
+                 c->yt[q == 1 ? 1 : 0], c->sa, c->sc, c->fp32);
   }
   return launch_status();
 }
 
-int ibm_viscous(ibm_ctx* c, const double* p, const double* const* h_prev, double* const* h_out,
+int ibm_viscous(ibm_ctx* c, const void* p, const void* const* h_prev, void* const* h_out,
                 double gamma, double rho, double dt, double* u, double* v, double* w) {
   if (!c || !p || !u || !v || !w || !(dt > 0)) FAIL(IBM_EINVAL, "ibm_viscous: bad argument");
   return viscous(c, p, h_prev, h_out, gamma, rho, dt, u, v, w);
@@ -766,8 +826,19 @@ static PoissonArgs pargs(ibm_ctx* c) {
   a.ylo = c->ylo;
   a.yhi = c->yhi;
   a.spec = c->spec;
-  a.cscr = c->cscr;
   a.sum_dy = c->sum_dy;
+  a.fp32 = c->fp32;
+  a.refine = c->fp32;
+  a.nref = c->nref;
+  a.tol = c->rtol;
+  a.rhs_keep = c->rhs_keep;
+  a.rmax = c->rmax;
+  a.stats = c->rstats;
+  a.zm = c->zm;
+  a.psum = c->psum;
+  a.msum = c->msum;
+  a.vtot = c->vtot;
+  a.flags = c->flags;
   return a;
 }
 
@@ -779,9 +850,9 @@ int poisson_solve(ibm_ctx* c, const double* rhs, double* phi) {
 }
 
 int ibm_project(ibm_ctx* c, const double* phi, double alpha_dt, double* u, double* v, double* w,
-                double* p) {
+                void* p) {
   if (!c || !phi || !u || !v || !w || !p) FAIL(IBM_EINVAL, "ibm_project: bad argument");
-  launch_project(&c->prof, c->stream, c->g, phi, alpha_dt, c->opts.re, u, v, w, p);
+  launch_project(&c->prof, c->stream, c->g, phi, alpha_dt, c->opts.re, u, v, w, p, c->fp32);
   return launch_status();
 }
 
@@ -791,10 +862,10 @@ int ibm_step(ibm_ctx* c, ibm_state* s, const ibm_body* b, int32_t nb, double dt)
   if (rc) return rc;
   struct Sub {
     double gamma, rho;
-    const double* const* hprev;
-    double* const* hout;
+    const void* const* hprev;
+    void* const* hout;
   };
-  double* H1[3] = {c->H[0], c->H[1], c->H[2]};
+  void* H1[3] = {c->H[0], c->H[1], c->H[2]};
   std::vector<Sub> subs;
   if (c->opts.scheme == IBM_RK2CN) {
     subs.push_back({0.5, 0.0, nullptr, H1});
@@ -815,9 +886,20 @@ int ibm_step(ibm_ctx* c, ibm_state* s, const ibm_body* b, int32_t nb, double dt)
     launch_poisson(&c->prof, c->stream, c->g, pargs(c), nullptr, s->u, s->v, s->w,
                    c->opts.use_q ? c->tb.cb_mask : nullptr, c->qf, 1.0 / (alpha * dt), c->phi);
     launch_project(&c->prof, c->stream, c->g, c->phi, alpha * dt, c->opts.re, s->u, s->v, s->w,
-                   s->p);
+                   s->p, c->fp32);
     rc = launch_status();
     if (rc) return rc;
+  }
+  return IBM_OK;
+}
+
+int ibm_refine_stats(ibm_ctx* c, double* stats, int32_t reset) {
+  if (!c || !stats) FAIL(IBM_EINVAL, "null argument");
+  HIPCHK(hipStreamSynchronize(c->stream));
+  HIPCHK(hipMemcpy(stats, c->rstats, 3 * sizeof(double), hipMemcpyDeviceToHost));
+  if (reset) {
+    launch_fill_f64(nullptr, c->stream, c->rstats, 3, 0.0);
+    HIPCHK(hipStreamSynchronize(c->stream));
   }
   return IBM_OK;
 }

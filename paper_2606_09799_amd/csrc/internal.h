@@ -56,6 +56,7 @@ struct CyclicTab {
   double ratio;          // beta_corner / gamma
   double fden_inv;       // 1 / (1 + z_0 + ratio z_{n-1})
   const double* seg;     // partitioned-solve tables [4][P][LINE_LMAX]
+  const float* seg32;    // the same tables in FP32 (mixed form)
 };
 
 struct YTab {
@@ -67,6 +68,8 @@ struct YTab {
   const double* cp;  // Thomas c' of the mask-free system
   const double* inv; // 1/pivot of the mask-free system
   const double* seg; // partitioned-solve tables [4][P][LINE_LMAX]
+  // FP32 copies of a, b, c and seg (mixed form)
+  const float *a32, *b32, *c32, *seg32;
   int n, j0;
 };
 
@@ -75,12 +78,15 @@ struct YTab {
 // the others L); cyclic lines use at least 3 segments.  Shared by the
 // kernels and the host code that builds their tables.
 constexpr int LINE_LMAX = 16;
-inline void line_plan(int n, bool cyc, int* P, int* L, int* r) {
-  int p = (n + LINE_LMAX - 1) / LINE_LMAX;
+inline void line_plan(int n, bool cyc, int lmax, int* P, int* L, int* r) {
+  int p = (n + lmax - 1) / lmax;
   if (cyc && p < 3) p = 3;
   *P = p;
   *L = n / p;
   *r = n % p;
+}
+inline void line_plan(int n, bool cyc, int* P, int* L, int* r) {
+  line_plan(n, cyc, LINE_LMAX, P, L, r);
 }
 
 struct FFTPlan {
@@ -88,6 +94,7 @@ struct FFTPlan {
   int nst;
   int radix[16];
   const double2* tw;  // exp(-2 pi i k/n), k = 0..n-1
+  const float2* tw32; // the same, rounded to FP32
 };
 
 // profiling hook (ctx.cpp): an event pair around each kernel launch when
@@ -103,7 +110,7 @@ void prof_end(Prof* p, hipStream_t s);
   } while (0)
 
 // sticky flags (same bits as IBM_FLAG_*)
-constexpr uint32_t FLAG_CAPACITY = 1u, FLAG_NONFINITE = 2u, FLAG_GEOM = 4u;
+constexpr uint32_t FLAG_CAPACITY = 1u, FLAG_NONFINITE = 2u, FLAG_GEOM = 4u, FLAG_REFINE = 8u;
 
 // ------------------------------------------------------------ launchers
 // body.hip
@@ -136,25 +143,28 @@ void launch_force(Prof* pf, hipStream_t s, const GridView& g, const BodyDev* bod
                   uint32_t* flags);
 
 // rhs.hip
+// p, hprev, hout and R are FP64, or FP32 when fp32 is set (mixed form)
 struct RhsArgs {
-  const double *u, *v, *w, *p;
-  const double* hprev[3];
-  double* hout[3];
-  double* R[3];
+  const double *u, *v, *w;
+  const void* p;
+  const void* hprev[3];
+  void* hout[3];
+  void* R[3];
   const uint32_t* mask[3];
   double gamma, rho, alpha, dt, re, fx;
+  int fp32;
 };
 void launch_rhs(Prof* pf, hipStream_t s, const GridView& g, const RhsArgs& a);
 
 // adi.hip
-// sa, sc: scratch of the size of the field (used only by segments that
-// hold forcing nodes)
-void launch_adi_x(Prof* pf, hipStream_t s, const GridView& g, int comp, double* d,
-                  const uint32_t* mask, const CyclicTab& t, double* sa, double* sc);
-void launch_adi_z(Prof* pf, hipStream_t s, const GridView& g, int comp, double* d,
-                  const uint32_t* mask, const CyclicTab& t, double* sa, double* sc);
-void launch_adi_y(Prof* pf, hipStream_t s, const GridView& g, int comp, double* d, double* u,
-                  const uint32_t* mask, const YTab& t, double* sa, double* sc);
+// d, sa, sc: FP64, or FP32 when fp32 is set.  sa, sc: scratch of the size of
+// the field (used only by segments that hold forcing nodes)
+void launch_adi_x(Prof* pf, hipStream_t s, const GridView& g, int comp, void* d,
+                  const uint32_t* mask, const CyclicTab& t, void* sa, void* sc, int fp32);
+void launch_adi_z(Prof* pf, hipStream_t s, const GridView& g, int comp, void* d,
+                  const uint32_t* mask, const CyclicTab& t, void* sa, void* sc, int fp32);
+void launch_adi_y(Prof* pf, hipStream_t s, const GridView& g, int comp, void* d, double* u,
+                  const uint32_t* mask, const YTab& t, void* sa, void* sc, int fp32);
 
 // mass.hip
 void launch_mass(Prof* pf, hipStream_t s, const GridView& g, const double* u, const double* v,
@@ -172,9 +182,21 @@ struct PoissonArgs {
   const double* lamz;  // nz
   const double* ylo;   // ny: coefficient of phi[j-1]
   const double* yhi;   // ny: coefficient of phi[j+1]
-  double2* spec;       // ny*nz*nxh
-  double* cscr;        // ny*nz*nxh real scratch
+  void* spec;          // ny*nz*nxh complex: double2, or float2 when fp32
   double sum_dy;
+  int fp32;            // FP32 spectrum and transforms
+  // FP64-residual refinement (mixed form)
+  int refine;          // on/off
+  int nref;            // refinements at most
+  double tol;          // bound on max|rhs - L_c phi| * alpha dt
+  double* rhs_keep;    // N: FP64 right-hand side kept for the residuals
+  u64* rmax;           // nref + 2 slots
+  double* stats;       // [solves, corrections, largest final residual]
+  double* zm;          // ny: the (0,0) mode column in FP64 (FP32 spectrum)
+  double* psum;        // per-block partial sums (x-pass blocks)
+  double* msum;        // nref + 2: sum of phi dV at each refinement
+  double vtot;         // volume of the box
+  uint32_t* flags;
 };
 // rhs from an array (rhs != NULL) or formed on the fly from the velocity
 // (rhs == NULL): (D u - q_F)/alpha_dt on C_F, 0 on C_B
@@ -183,8 +205,9 @@ void launch_poisson(Prof* pf, hipStream_t s, const GridView& g, const PoissonArg
                     const uint32_t* cb_mask, const double* qf, double inv_adt, double* phi);
 
 // project.hip
+// p: FP64, or FP32 when fp32 is set
 void launch_project(Prof* pf, hipStream_t s, const GridView& g, const double* phi, double adt,
-                    double re, double* u, double* v, double* w, double* p);
+                    double re, double* u, double* v, double* w, void* p, int fp32);
 
 // utilities (util.hip)
 void launch_fill_u32(Prof* pf, hipStream_t s, uint32_t* p, int64_t n, uint32_t val);

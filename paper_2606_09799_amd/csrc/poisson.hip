@@ -5,63 +5,88 @@
 //      the predicted velocity: (D u - q_F)/(alpha dt) on C_F, 0 on C_B) and
 //      transform it along x; keep the nx/2+1 non-redundant bins
 //   2. per (y-plane, tile of x-modes): complex FFT along z
-//   3. per mode (p, m): Thomas along y with the diagonal shifted by the
-//      eigenvalues lambda_x(p) + lambda_z(m) of the periodic second
+//   3. per mode (p, m): tridiagonal solve along y with the diagonal shifted by
+//      the eigenvalues lambda_x(p) + lambda_z(m) of the periodic second
 //      differences; the singular (0,0) mode has its first row replaced by
 //      phi_0 = 0 and is shifted to zero volume-weighted mean
 //   4. inverse z transform, 5. inverse x transform -> phi.
 // The transforms are mixed-radix (2, 3, 4, 5, 7) Stockham autosort FFTs
-// staged in LDS (ping-pong buffers), twiddles from a precomputed FP64 table.
+// staged in LDS (ping-pong buffers), twiddles from a precomputed table.
+//
+// Spectral precision.  The spectrum and the transforms are FP64 (double2) or
+// FP32 (float2, the mixed form).  The wall-normal solves always run in FP64
+// arithmetic.  In the mixed form the FP32 solve S is the inner solver of an
+// FP64-residual refinement: phi = S(rhs), then while max|rhs - L_c phi| is
+// above the tolerance, phi += S(rhs - L_c phi).  The residual is formed in
+// FP64 inside the first pass of the next solve; the decision to go on is
+// taken on the device (every pass of a refinement returns at once when the
+// residual that opened it is below the tolerance), so the whole sequence is
+// enqueued without any host synchronisation.
 #include "geom.h"
 
 namespace ibm {
 
-__device__ __forceinline__ double2 cmul(double2 a, double2 b) {
-  return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
+template <typename C> struct RealOf;
+template <> struct RealOf<double2> { using T = double; };
+template <> struct RealOf<float2> { using T = float; };
+
+template <typename C>
+__device__ __forceinline__ C mkc(typename RealOf<C>::T a, typename RealOf<C>::T b) {
+  C r;
+  r.x = a;
+  r.y = b;
+  return r;
 }
-__device__ __forceinline__ double2 cadd(double2 a, double2 b) {
-  return make_double2(a.x + b.x, a.y + b.y);
+template <typename C>
+__device__ __forceinline__ C cmul(C a, C b) {
+  return mkc<C>(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
-__device__ __forceinline__ double2 csub(double2 a, double2 b) {
-  return make_double2(a.x - b.x, a.y - b.y);
+template <typename C>
+__device__ __forceinline__ C cadd(C a, C b) {
+  return mkc<C>(a.x + b.x, a.y + b.y);
+}
+template <typename C>
+__device__ __forceinline__ C csub(C a, C b) {
+  return mkc<C>(a.x - b.x, a.y - b.y);
 }
 
+template <typename C>
 struct PlanDev {
   int n, nst;
   int radix[16];
-  const double2* tw;
+  const C* tw;
 };
 
 // small DFT of size R on u[0..R-1] (forward: exp(-2 pi i rq/R)); R is a
 // compile-time constant so the butterfly stays in registers
-template <int R, bool INV>
-__device__ __forceinline__ void small_dft(double2* u, const double2* tw, int n) {
+template <typename C, int R, bool INV>
+__device__ __forceinline__ void small_dft(C* u, const C* tw, int n) {
   if constexpr (R == 2) {
-    const double2 a = u[0], b = u[1];
+    const C a = u[0], b = u[1];
     u[0] = cadd(a, b);
     u[1] = csub(a, b);
   } else if constexpr (R == 4) {
-    const double2 a0 = u[0], a1 = u[1], a2 = u[2], a3 = u[3];
-    const double2 s02 = cadd(a0, a2), d02 = csub(a0, a2);
-    const double2 s13 = cadd(a1, a3), d13 = csub(a1, a3);
+    const C a0 = u[0], a1 = u[1], a2 = u[2], a3 = u[3];
+    const C s02 = cadd(a0, a2), d02 = csub(a0, a2);
+    const C s13 = cadd(a1, a3), d13 = csub(a1, a3);
     // forward: multiply d13 by -i; inverse: by +i
-    const double2 rot = INV ? make_double2(-d13.y, d13.x) : make_double2(d13.y, -d13.x);
+    const C rot = INV ? mkc<C>(-d13.y, d13.x) : mkc<C>(d13.y, -d13.x);
     u[0] = cadd(s02, s13);
     u[1] = cadd(d02, rot);
     u[2] = csub(s02, s13);
     u[3] = csub(d02, rot);
   } else {
-    double2 w[R];
+    C w[R];
     const int st = n / R;
 #pragma unroll
     for (int m = 0; m < R; ++m) {
       w[m] = tw[m * st];
       if (INV) w[m].y = -w[m].y;
     }
-    double2 y[R];
+    C y[R];
 #pragma unroll
     for (int q = 0; q < R; ++q) {
-      double2 acc = u[0];
+      C acc = u[0];
 #pragma unroll
       for (int r = 1; r < R; ++r) acc = cadd(acc, cmul(u[r], w[(r * q) % R]));
       y[q] = acc;
@@ -73,9 +98,9 @@ __device__ __forceinline__ void small_dft(double2* u, const double2* tw, int n) 
 
 // one Stockham stage of radix R (current sub-transform length p) for ncols
 // sequences at buf[idx*si + col*sc]
-template <int R, bool INV>
-__device__ __forceinline__ void fft_stage(const double2* src, double2* dst, const PlanDev& P,
-                                          int p, int ncols, int si, int sc) {
+template <typename C, int R, bool INV>
+__device__ __forceinline__ void fft_stage(const C* src, C* dst, const PlanDev<C>& P, int p,
+                                          int ncols, int si, int sc) {
   const int n = P.n;
   const int T = n / R;
   const int step = n / (p * R);
@@ -85,16 +110,16 @@ __device__ __forceinline__ void fft_stage(const double2* src, double2* dst, cons
     const int col = (si == 1) ? bb / T : bb % ncols;
     const int i = (si == 1) ? bb % T : bb / ncols;
     const int k = i % p;
-    double2 u[R];
+    C u[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) u[r] = src[(i + r * T) * si + col * sc];
 #pragma unroll
     for (int r = 1; r < R; ++r) {
-      double2 w = P.tw[r * k * step];
+      C w = P.tw[r * k * step];
       if (INV) w.y = -w.y;
       u[r] = cmul(u[r], w);
     }
-    small_dft<R, INV>(u, P.tw, n);
+    small_dft<C, R, INV>(u, P.tw, n);
     const int ob = (i - k) * R + k;
 #pragma unroll
     for (int r = 0; r < R; ++r) dst[(ob + r * p) * si + col * sc] = u[r];
@@ -104,22 +129,22 @@ __device__ __forceinline__ void fft_stage(const double2* src, double2* dst, cons
 // Stockham FFT of ncols independent length-n sequences held in LDS at
 // buf[idx*si + col*sc]; ping-pongs between a and b; returns the buffer that
 // holds the result.  All threads of the block must call it.
-template <bool INV>
-__device__ double2* lds_fft(double2* a, double2* b, const PlanDev& P, int ncols, int si, int sc) {
+template <typename C, bool INV>
+__device__ C* lds_fft(C* a, C* b, const PlanDev<C>& P, int ncols, int si, int sc) {
   int p = 1;
-  double2* src = a;
-  double2* dst = b;
+  C* src = a;
+  C* dst = b;
   for (int s = 0; s < P.nst; ++s) {
     const int R = P.radix[s];
     switch (R) {
-      case 2: fft_stage<2, INV>(src, dst, P, p, ncols, si, sc); break;
-      case 3: fft_stage<3, INV>(src, dst, P, p, ncols, si, sc); break;
-      case 4: fft_stage<4, INV>(src, dst, P, p, ncols, si, sc); break;
-      case 5: fft_stage<5, INV>(src, dst, P, p, ncols, si, sc); break;
-      default: fft_stage<7, INV>(src, dst, P, p, ncols, si, sc); break;
+      case 2: fft_stage<C, 2, INV>(src, dst, P, p, ncols, si, sc); break;
+      case 3: fft_stage<C, 3, INV>(src, dst, P, p, ncols, si, sc); break;
+      case 4: fft_stage<C, 4, INV>(src, dst, P, p, ncols, si, sc); break;
+      case 5: fft_stage<C, 5, INV>(src, dst, P, p, ncols, si, sc); break;
+      default: fft_stage<C, 7, INV>(src, dst, P, p, ncols, si, sc); break;
     }
     __syncthreads();
-    double2* t = src;
+    C* t = src;
     src = dst;
     dst = t;
     p *= R;
@@ -127,16 +152,25 @@ __device__ double2* lds_fft(double2* a, double2* b, const PlanDev& P, int ncols,
   return src;
 }
 
+// source of the first x pass
+enum : int { SRC_ARRAY = 0, SRC_VELOCITY = 1, SRC_RESIDUAL = 2, SRC_CHECK = 3 };
+
+template <typename C>
 struct PoisK {
   GridView g;
-  PlanDev px, pz;
-  const double* rhs;
-  const double *u, *v, *w;
+  PlanDev<C> px, pz;
+  int mode;
+  const double* rhs;           // SRC_ARRAY: the right-hand side; SRC_RESIDUAL/CHECK: kept copy
+  const double *u, *v, *w;     // SRC_VELOCITY
   const uint32_t* cb_mask;
   const double* qf;
   double inv_adt;
-  double2* spec;
-  double* cscr;
+  double* rhs_keep;            // FP64 copy of the right-hand side formed in pass 1 (or NULL)
+  const double* phi_in;        // SRC_RESIDUAL/CHECK: current phi
+  u64* rmax;                   // SRC_RESIDUAL/CHECK: max |r| (bits of a non-negative double)
+  const u64* gate;             // the launch does nothing when *gate <= gate_tol
+  double gate_tol;
+  C* spec;
   const double* lamx;
   const double* lamz;
   const double* ylo;
@@ -144,198 +178,509 @@ struct PoisK {
   double inv_sum_dy;
   double scale;
   double* phi;
-  int rows;  // x-rows per block
-  int tp;    // x-modes per block in the z passes
+  int accumulate;              // inverse x pass: phi += result instead of phi = result
+  double* zm;                  // FP32 spectrum: the (0,0) mode column kept in FP64 (ny)
+  double* psum;                // SRC_RESIDUAL: per-block sums of phi dV (fixed order)
+  const double* msum;          // inverse x pass of a refinement: sum of phi dV to remove
+  double inv_vtot;
+  int rows;                    // x-rows per block
+  int tp;                      // x-modes per block in the z passes
+  int yP, yL, yr, ytl;         // wall-normal solve: segments, base length, longer ones, lines per block
 };
 
-__global__ __launch_bounds__(256) void k_fftx_fwd(PoisK K) {
-  extern __shared__ double2 sm[];
+template <typename C>
+__device__ __forceinline__ bool gated(const PoisK<C>& K) {
+  return K.gate && __longlong_as_double((long long)*K.gate) <= K.gate_tol;
+}
+
+// L_c phi at one cell: the discrete operator the solve inverts (second
+// differences in x and z, face fluxes in y with zero flux at the walls)
+__device__ __forceinline__ double lap_c(const GridView& g, const double* __restrict__ f,
+                                        int64_t cell, int i, int j, int k) {
+  const int64_t plane = (int64_t)g.nz * g.nx;
+  const int64_t row = cell - i;
+  const int im = (i == 0) ? g.nx - 1 : i - 1;
+  const int ip = (i + 1 == g.nx) ? 0 : i + 1;
+  const int km = (k == 0) ? g.nz - 1 : k - 1;
+  const int kp = (k + 1 == g.nz) ? 0 : k + 1;
+  const double fc = f[cell];
+  const double gx0 = (fc - f[row + im]) * g.idx, gx1 = (f[row + ip] - fc) * g.idx;
+  const double gz0 = (fc - f[cell + (int64_t)(km - k) * g.nx]) * g.idz;
+  const double gz1 = (f[cell + (int64_t)(kp - k) * g.nx] - fc) * g.idz;
+  const double fs = (j > 0) ? (fc - f[cell - plane]) * g.idyc[j] : 0.0;
+  const double fn = (j + 1 < g.ny) ? (f[cell + plane] - fc) * g.idyc[j + 1] : 0.0;
+  return (gx1 - gx0) * g.idx + (gz1 - gz0) * g.idz + (fn - fs) * g.idy[j];
+}
+
+template <typename C>
+__global__ __launch_bounds__(256) void k_fftx_fwd(PoisK<C> K) {
+  using R = typename RealOf<C>::T;
+  if (gated(K)) return;
+  extern __shared__ __align__(16) unsigned char smraw[];
+  C* sm = reinterpret_cast<C*>(smraw);
+  __shared__ double red[8];
   const GridView& g = K.g;
   const int nx = g.nx, nxh = g.nxh;
   const int64_t nrows = (int64_t)g.ny * g.nz;
   const int64_t row0 = (int64_t)blockIdx.x * K.rows;
   const int nr = (int)((row0 + K.rows <= nrows) ? K.rows : nrows - row0);
-  double2* a = sm;
-  double2* b = sm + K.rows * nx;
+  C* a = sm;
+  C* b = sm + K.rows * nx;
   const int64_t plane = (int64_t)g.nz * nx;
-  const double q = K.rhs ? 0.0 : *K.qf;
+  const double q = (K.mode == SRC_VELOCITY) ? *K.qf : 0.0;
+  const bool resid = K.mode >= SRC_RESIDUAL;
+  double rmax = 0.0, vsum = 0.0;
   for (int e = threadIdx.x; e < nr * nx; e += blockDim.x) {
     const int r = e / nx, i = e % nx;
     const int64_t cell = (row0 + r) * nx + i;
     double val;
-    if (K.rhs) {
+    if (K.mode == SRC_ARRAY) {
       val = K.rhs[cell];
-    } else if (K.cb_mask && test_bit(K.cb_mask, cell)) {
-      val = 0.0;
+    } else if (K.mode == SRC_VELOCITY) {
+      if (K.cb_mask && test_bit(K.cb_mask, cell)) {
+        val = 0.0;
+      } else {
+        const int64_t rr = row0 + r;
+        const int j = (int)(rr / g.nz), k = (int)(rr % g.nz);
+        const int ip = (i + 1 == nx) ? 0 : i + 1;
+        const int kp = (k + 1 == g.nz) ? 0 : k + 1;
+        const double D = (K.u[cell - i + ip] - K.u[cell]) * g.idx +
+                         (K.v[cell + plane] - K.v[cell]) * g.idy[j] +
+                         (K.w[(int64_t)j * plane + (int64_t)kp * nx + i] - K.w[cell]) * g.idz;
+        val = (D - q) * K.inv_adt;
+      }
     } else {
       const int64_t rr = row0 + r;
       const int j = (int)(rr / g.nz), k = (int)(rr % g.nz);
-      const int ip = (i + 1 == nx) ? 0 : i + 1;
-      const int kp = (k + 1 == g.nz) ? 0 : k + 1;
-      const double D = (K.u[cell - i + ip] - K.u[cell]) * g.idx +
-                       (K.v[cell + plane] - K.v[cell]) * g.idy[j] +
-                       (K.w[(int64_t)j * plane + (int64_t)kp * nx + i] - K.w[cell]) * g.idz;
-      val = (D - q) * K.inv_adt;
+      val = K.rhs[cell] - lap_c(g, K.phi_in, cell, i, j, k);
+      rmax = fmax(rmax, fabs(val));
+      vsum += K.phi_in[cell] * g.dy[j];
     }
-    a[r * nx + i] = make_double2(val, 0.0);
+    if (K.rhs_keep) K.rhs_keep[cell] = val;
+    if (K.mode != SRC_CHECK) a[r * nx + i] = mkc<C>((R)val, (R)0);
   }
-  for (int e = nr * nx + threadIdx.x; e < K.rows * nx; e += blockDim.x)
-    a[e] = make_double2(0.0, 0.0);
+  if (resid) {
+    // block maximum of |r|, then one atomic per block on the bit pattern
+    // (non-negative doubles order like their bits); block sum of phi dV in a
+    // fixed order (the refinement removes the volume-weighted mean of phi,
+    // which the residual cannot see)
+    for (int off = 32; off > 0; off >>= 1) {
+      rmax = fmax(rmax, __shfl_xor(rmax, off));
+      vsum += __shfl_xor(vsum, off);
+    }
+    if ((threadIdx.x & 63) == 0) {
+      red[threadIdx.x >> 6] = rmax;
+      red[4 + (threadIdx.x >> 6)] = vsum;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      double m = red[0], sm4 = red[4];
+      for (int t = 1; t < (int)(blockDim.x >> 6); ++t) {
+        m = fmax(m, red[t]);
+        sm4 += red[4 + t];
+      }
+      atomicMax(reinterpret_cast<unsigned long long*>(K.rmax),
+                (unsigned long long)__double_as_longlong(m));
+      if (K.psum) K.psum[blockIdx.x] = sm4 * (g.dx * g.dz);
+    }
+    if (K.mode == SRC_CHECK) return;  // block-uniform
+  }
+  for (int e = nr * nx + threadIdx.x; e < K.rows * nx; e += blockDim.x) a[e] = mkc<C>((R)0, (R)0);
   __syncthreads();
-  double2* out = lds_fft<false>(a, b, K.px, K.rows, 1, nx);
+  C* out = lds_fft<C, false>(a, b, K.px, K.rows, 1, nx);
   for (int e = threadIdx.x; e < nr * nxh; e += blockDim.x) {
     const int r = e / nxh, p = e % nxh;
     K.spec[(row0 + r) * nxh + p] = out[r * nx + p];
   }
 }
 
-template <bool INV>
-__global__ __launch_bounds__(256) void k_fftz(PoisK K) {
-  extern __shared__ double2 sm[];
+template <typename C, bool INV>
+__global__ __launch_bounds__(256) void k_fftz(PoisK<C> K) {
+  using R = typename RealOf<C>::T;
+  if (gated(K)) return;
+  extern __shared__ __align__(16) unsigned char smraw[];
+  C* sm = reinterpret_cast<C*>(smraw);
   const GridView& g = K.g;
   const int nz = g.nz, nxh = g.nxh, tp = K.tp;
   const int j = blockIdx.y;
   const int p0 = blockIdx.x * tp;
   const int nc = (p0 + tp <= nxh) ? tp : nxh - p0;
-  double2* a = sm;
-  double2* b = sm + nz * tp;
-  double2* spec = K.spec + (int64_t)j * nz * nxh + p0;
+  C* a = sm;
+  C* b = sm + nz * tp;
+  C* spec = K.spec + (int64_t)j * nz * nxh + p0;
   for (int e = threadIdx.x; e < nz * tp; e += blockDim.x) {
     const int k = e / tp, c = e % tp;
-    a[e] = (c < nc) ? spec[(int64_t)k * nxh + c] : make_double2(0.0, 0.0);
+    a[e] = (c < nc) ? spec[(int64_t)k * nxh + c] : mkc<C>((R)0, (R)0);
   }
   __syncthreads();
-  double2* out = lds_fft<INV>(a, b, K.pz, tp, tp, 1);
+  C* out = lds_fft<C, INV>(a, b, K.pz, tp, tp, 1);
   for (int e = threadIdx.x; e < nz * tp; e += blockDim.x) {
     const int k = e / tp, c = e % tp;
     if (c < nc) spec[(int64_t)k * nxh + c] = out[e];
   }
 }
 
-constexpr int YCH = 4;
+// Wall-normal solves, one per Fourier mode, partitioned like the line solves
+// of the predictor: each mode's ny rows are cut into P balanced segments of
+// at most YL rows, one thread per segment, the values in registers.  Each
+// thread eliminates its interior rows so that they become affine functions
+// of the two separators around the segment (its own last row and the
+// previous segment's), the P separator rows form a tridiagonal system solved
+// by parallel cyclic reduction in LDS, and each thread reconstructs its rows.
+// Every spectral value is read once and written once; the arithmetic is FP64
+// whatever the storage precision.  The systems are diagonally dominant
+// (|b| >= |a| + |c|), so the elimination needs no pivoting.
+constexpr int YL = 8;
 
-__global__ __launch_bounds__(256) void k_tri_y(PoisK K) {
+template <typename C>
+__global__ __launch_bounds__(1024) void k_tri_y(PoisK<C> K) {
+  using R = typename RealOf<C>::T;
+  if (gated(K)) return;
+  extern __shared__ __align__(16) unsigned char smraw[];
+  double* sm = reinterpret_cast<double*>(smraw);  // 7 arrays of P doubles per line
   const GridView& g = K.g;
-  const int nxh = g.nxh;
-  const int64_t nm = (int64_t)g.nz * nxh;
-  const int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (q >= nm) return;
-  const int m = (int)(q / nxh), p = (int)(q % nxh);
-  const double lam = K.lamx[p] + K.lamz[m];
-  const int ny = g.ny;
-  double2* __restrict__ X = K.spec + q;
-  double* __restrict__ C = K.cscr + q;
+  const int TL = K.ytl, P = K.yP;
+  const int lb = threadIdx.x % TL, s = threadIdx.x / TL;
+  const int64_t nm = (int64_t)g.nz * g.nxh;
+  const int64_t q = (int64_t)blockIdx.x * TL + lb;
+  const bool valid = q < nm;
+  auto at = [&](int f, int seg) -> double& { return sm[((size_t)f * P + seg) * TL + lb]; };
+  const int lo = s * K.yL + (s < K.yr ? s : K.yr);
+  const int len = K.yL + (s < K.yr ? 1 : 0);
+  const int m = len - 1;  // interior rows (at least 2); row lo+m is the separator
   const bool zero = (q == 0);
-  double cpp = 0.0;
-  double2 dpp = make_double2(0.0, 0.0);
-  for (int j0 = 0; j0 < ny; j0 += YCH) {
-    double2 buf[YCH];
+  // lanes past the last mode solve a harmless non-singular system
+  const double lam = valid ? K.lamx[q % g.nxh] + K.lamz[q / g.nxh] : -1.0;
+  C* __restrict__ X = K.spec + q;
+  double xr[YL], xi[YL], ah[YL], ch[YL];
+  double zr = 0.0, zi = 0.0;
 #pragma unroll
-    for (int t = 0; t < YCH; ++t)
-      if (j0 + t < ny) buf[t] = X[(int64_t)(j0 + t) * nm];
-#pragma unroll
-    for (int t = 0; t < YCH; ++t) {
-      const int j = j0 + t;
-      if (j < ny) {
-        double a = K.ylo[j], c = K.yhi[j], b = lam - (a + c);
-        double2 d = buf[t];
-        if (zero && j == 0) {
-          a = 0.0;
-          b = 1.0;
-          c = 0.0;
-          d = make_double2(0.0, 0.0);
-        }
-        const double mm = 1.0 / (b - a * cpp);
-        const double cp = c * mm;
-        const double2 dp = make_double2((d.x - a * dpp.x) * mm, (d.y - a * dpp.y) * mm);
-        C[(int64_t)j * nm] = cp;
-        buf[t] = dp;
-        cpp = cp;
-        dpp = dp;
-      }
-    }
-#pragma unroll
-    for (int t = 0; t < YCH; ++t)
-      if (j0 + t < ny) X[(int64_t)(j0 + t) * nm] = buf[t];
+  for (int e = 0; e < YL; ++e) {
+    xr[e] = 0.0;
+    xi[e] = 0.0;
+    ah[e] = 0.0;
+    ch[e] = 0.0;
   }
-  double2 xn = make_double2(0.0, 0.0);
-  double2 msum = make_double2(0.0, 0.0);
-  for (int j1 = ny; j1 > 0; j1 -= YCH) {
-    double2 buf[YCH];
-    double cb[YCH];
+  if (valid) {
 #pragma unroll
-    for (int t = 0; t < YCH; ++t)
-      if (j1 - 1 - t >= 0) {
-        buf[t] = X[(int64_t)(j1 - 1 - t) * nm];
-        cb[t] = C[(int64_t)(j1 - 1 - t) * nm];
-      }
-#pragma unroll
-    for (int t = 0; t < YCH; ++t) {
-      const int j = j1 - 1 - t;
-      if (j >= 0) {
-        const double2 x = make_double2(buf[t].x - cb[t] * xn.x, buf[t].y - cb[t] * xn.y);
-        buf[t] = x;
-        xn = x;
-        if (zero) {
-          msum.x += g.dy[j] * x.x;
-          msum.y += g.dy[j] * x.y;
+    for (int e = 0; e < YL; ++e)
+      if (e < len) {
+        const C v = X[(int64_t)(lo + e) * nm];
+        if (e < m) {
+          xr[e] = (double)v.x;
+          xi[e] = (double)v.y;
+        } else {
+          zr = (double)v.x;
+          zi = (double)v.y;
         }
       }
-    }
-#pragma unroll
-    for (int t = 0; t < YCH; ++t)
-      if (j1 - 1 - t >= 0) X[(int64_t)(j1 - 1 - t) * nm] = buf[t];
   }
-  if (zero) {  // zero volume-weighted mean of phi
-    const double2 M = make_double2(msum.x * K.inv_sum_dy, msum.y * K.inv_sum_dy);
-    for (int j = 0; j < ny; ++j) X[(int64_t)j * nm] = csub(X[(int64_t)j * nm], M);
+  // forward elimination of the interior rows: row e becomes
+  //   x_e + ct_e x_{e+1} = dt_e - at_e z_left
+  double atp = 0.0, ctp = 0.0, dr = 0.0, di = 0.0;
+#pragma unroll
+  for (int e = 0; e < YL - 1; ++e)
+    if (e < m) {
+      const int j = lo + e;
+      double a = K.ylo[j], c = K.yhi[j], b = lam - (a + c);
+      double er = xr[e], ei = xi[e];
+      if (zero && j == 0) {
+        a = 0.0;
+        b = 1.0;
+        c = 0.0;
+        er = 0.0;
+        ei = 0.0;
+      }
+      const double inv = 1.0 / (b - a * ctp);
+      atp = (e == 0) ? a * inv : -a * atp * inv;
+      ctp = c * inv;
+      dr = (er - a * dr) * inv;
+      di = (ei - a * di) * inv;
+      ah[e] = atp;
+      ch[e] = ctp;
+      xr[e] = dr;
+      xi[e] = di;
+    }
+  // backward: x_e = d_e - ah_e z_left - ch_e z_right
+  double ahl = 0.0, chl = 0.0, dlr = 0.0, dli = 0.0;  // row m-1
+#pragma unroll
+  for (int e = YL - 2; e >= 0; --e)
+    if (e < m) {
+      if (e == m - 1) {
+        ahl = ah[e];
+        chl = ch[e];
+        dlr = xr[e];
+        dli = xi[e];
+      } else {
+        const double ct = ch[e];
+        xr[e] -= ct * xr[e + 1];
+        xi[e] -= ct * xi[e + 1];
+        ah[e] -= ct * ah[e + 1];
+        ch[e] = -ct * ch[e + 1];
+      }
+    }
+  // the first interior row of each segment, for the separator row before it
+  at(0, s) = ah[0];
+  at(1, s) = ch[0];
+  at(2, s) = xr[0];
+  at(3, s) = xi[0];
+  __syncthreads();
+  const int jz = lo + m;
+  const double az = K.ylo[jz], cz = K.yhi[jz], bz = lam - (az + cz);
+  double ra = -az * ahl, rb = bz - az * chl, rg = 0.0;
+  double rdr = zr - az * dlr, rdi = zi - az * dli;
+  if (s + 1 < P) {
+    rb -= cz * at(0, s + 1);
+    rg = -cz * at(1, s + 1);
+    rdr -= cz * at(2, s + 1);
+    rdi -= cz * at(3, s + 1);
+  }
+  __syncthreads();
+  at(0, s) = ra;
+  at(1, s) = rb;
+  at(2, s) = rg;
+  at(3, s) = rdr;
+  at(4, s) = rdi;
+  __syncthreads();
+  // parallel cyclic reduction; rows outside 0..P-1 act as identity rows
+  for (int st = 1; st < P; st <<= 1) {
+    const int im = s - st, ip = s + st;
+    double am = 0.0, bm = 1.0, gm = 0.0, dmr = 0.0, dmi = 0.0;
+    double ap = 0.0, bp = 1.0, gp = 0.0, dpr = 0.0, dpi = 0.0;
+    if (im >= 0) {
+      am = at(0, im);
+      bm = at(1, im);
+      gm = at(2, im);
+      dmr = at(3, im);
+      dmi = at(4, im);
+    }
+    if (ip < P) {
+      ap = at(0, ip);
+      bp = at(1, ip);
+      gp = at(2, ip);
+      dpr = at(3, ip);
+      dpi = at(4, ip);
+    }
+    const double k1 = ra / bm, k2 = rg / bp;
+    const double na = -am * k1, ng = -gp * k2;
+    const double nb = rb - gm * k1 - ap * k2;
+    const double ndr = rdr - dmr * k1 - dpr * k2;
+    const double ndi = rdi - dmi * k1 - dpi * k2;
+    __syncthreads();
+    ra = na;
+    rb = nb;
+    rg = ng;
+    rdr = ndr;
+    rdi = ndi;
+    at(0, s) = ra;
+    at(1, s) = rb;
+    at(2, s) = rg;
+    at(3, s) = rdr;
+    at(4, s) = rdi;
+    __syncthreads();
+  }
+  at(5, s) = rdr / rb;
+  at(6, s) = rdi / rb;
+  __syncthreads();
+  const double zRr = at(5, s), zRi = at(6, s);
+  const double zLr = (s > 0) ? at(5, s - 1) : 0.0;
+  const double zLi = (s > 0) ? at(6, s - 1) : 0.0;
+#pragma unroll
+  for (int e = 0; e < YL - 1; ++e)
+    if (e < m) {
+      xr[e] = xr[e] - ah[e] * zLr - ch[e] * zRr;
+      xi[e] = xi[e] - ah[e] * zLi - ch[e] * zRi;
+    }
+  zr = zRr;
+  zi = zRi;
+  if (blockIdx.x == 0) {
+    // zero volume-weighted mean of the (0,0) mode (lane 0 of block 0):
+    // per-segment partial sums, then their sum in segment order
+    double pr = 0.0, pi = 0.0;
+    if (lb == 0) {
+#pragma unroll
+      for (int e = 0; e < YL; ++e)
+        if (e < len) {
+          const double dyj = g.dy[lo + e];
+          pr += dyj * (e < m ? xr[e] : zr);
+          pi += dyj * (e < m ? xi[e] : zi);
+        }
+    }
+    __syncthreads();
+    if (lb == 0) {
+      at(0, s) = pr;
+      at(1, s) = pi;
+    }
+    __syncthreads();
+    if (lb == 0) {
+      double Mr = 0.0, Mi = 0.0;
+      for (int t = 0; t < P; ++t) {
+        Mr += at(0, t);
+        Mi += at(1, t);
+      }
+      Mr *= K.inv_sum_dy;
+      Mi *= K.inv_sum_dy;
+#pragma unroll
+      for (int e = 0; e < YL - 1; ++e)
+        if (e < m) {
+          xr[e] -= Mr;
+          xi[e] -= Mi;
+        }
+      zr -= Mr;
+      zi -= Mi;
+    }
+  }
+  if (valid) {
+    // an FP32 spectrum hands the (0,0) mode (a real column) to the inverse x
+    // pass in FP64, so that the zero-mean gauge survives the FP32 rounding
+    const bool keep = zero && K.zm;
+#pragma unroll
+    for (int e = 0; e < YL; ++e)
+      if (e < len) {
+        const double vr = (e < m) ? xr[e] : zr;
+        const double vi = (e < m) ? xi[e] : zi;
+        if (keep) K.zm[lo + e] = vr;
+        X[(int64_t)(lo + e) * nm] = keep ? mkc<C>((R)0, (R)0) : mkc<C>((R)vr, (R)vi);
+      }
   }
 }
 
-__global__ __launch_bounds__(256) void k_fftx_inv(PoisK K) {
-  extern __shared__ double2 sm[];
+template <typename C>
+__global__ __launch_bounds__(256) void k_fftx_inv(PoisK<C> K) {
+  using R = typename RealOf<C>::T;
+  if (gated(K)) return;
+  extern __shared__ __align__(16) unsigned char smraw[];
+  C* sm = reinterpret_cast<C*>(smraw);
   const GridView& g = K.g;
   const int nx = g.nx, nxh = g.nxh;
   const int64_t nrows = (int64_t)g.ny * g.nz;
   const int64_t row0 = (int64_t)blockIdx.x * K.rows;
   const int nr = (int)((row0 + K.rows <= nrows) ? K.rows : nrows - row0);
-  double2* a = sm;
-  double2* b = sm + K.rows * nx;
+  C* a = sm;
+  C* b = sm + K.rows * nx;
   for (int e = threadIdx.x; e < K.rows * nx; e += blockDim.x) {
     const int r = e / nx, i = e % nx;
-    double2 val = make_double2(0.0, 0.0);
+    C val = mkc<C>((R)0, (R)0);
     if (r < nr) {
       if (i < nxh) {
         val = K.spec[(row0 + r) * nxh + i];
       } else {  // Hermitian extension of a real sequence
-        const double2 c = K.spec[(row0 + r) * nxh + (nx - i)];
-        val = make_double2(c.x, -c.y);
+        const C c = K.spec[(row0 + r) * nxh + (nx - i)];
+        val = mkc<C>(c.x, -c.y);
       }
     }
     a[e] = val;
   }
   __syncthreads();
-  double2* out = lds_fft<true>(a, b, K.px, K.rows, 1, nx);
-  for (int e = threadIdx.x; e < nr * nx; e += blockDim.x)
-    K.phi[row0 * nx + e] = out[e].x * K.scale;
+  C* out = lds_fft<C, true>(a, b, K.px, K.rows, 1, nx);
+  for (int e = threadIdx.x; e < nr * nx; e += blockDim.x) {
+    double v = (double)out[e].x * K.scale;
+    if (K.zm) v += K.zm[(int)((row0 + e / nx) / g.nz)] * K.scale;
+    if (K.msum) v -= *K.msum * K.inv_vtot;
+    if (K.accumulate)
+      K.phi[row0 * nx + e] += v;
+    else
+      K.phi[row0 * nx + e] = v;
+  }
 }
 
-static PlanDev to_dev(const FFTPlan* p) {
-  PlanDev d;
+// Sum of the per-block partials of phi dV in a fixed order (one block).
+__global__ __launch_bounds__(256) void k_sum_partials(const double* __restrict__ part, int n,
+                                                      double* __restrict__ out, const u64* gate,
+                                                      double gate_tol) {
+  if (gate && __longlong_as_double((long long)*gate) <= gate_tol) return;
+  __shared__ double s[256];
+  double a = 0.0;
+  for (int i = threadIdx.x; i < n; i += 256) a += part[i];
+  s[threadIdx.x] = a;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) s[threadIdx.x] += s[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = s[0];
+}
+
+// Refinement bookkeeping after one mixed solve: rmax[k] (k = 1..nref) is the
+// residual that opened refinement k (0 if it never ran), rmax[nref+1] the
+// final check.  stats: [solves, corrections, largest final max|r| * adt].
+__global__ void k_refine_stats(const u64* rmax, int nref, double tol, double adt, double* stats,
+                               uint32_t* flags) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  int k = 1, corr = 0;
+  double last = __longlong_as_double((long long)rmax[1]);
+  while (k <= nref && !(last <= tol)) {
+    ++corr;
+    ++k;
+    last = __longlong_as_double((long long)rmax[k]);
+  }
+  if (!(last <= tol)) atomicOr(flags, last == last ? FLAG_REFINE : FLAG_NONFINITE);
+  stats[0] += 1.0;
+  stats[1] += (double)corr;
+  const double fin = last * adt;
+  if (!(fin <= stats[2])) stats[2] = fin;
+}
+
+template <typename C>
+static PlanDev<C> to_dev(const FFTPlan* p, const C* tw) {
+  PlanDev<C> d;
   d.n = p->n;
   d.nst = p->nst;
   for (int i = 0; i < 16; ++i) d.radix[i] = p->radix[i];
-  d.tw = p->tw;
+  d.tw = tw;
   return d;
 }
 
-void launch_poisson(Prof* pf, hipStream_t s, const GridView& g, const PoissonArgs& a,
-                    const double* rhs, const double* u, const double* v, const double* w,
-                    const uint32_t* cb_mask, const double* qf, double inv_adt, double* phi) {
-  PoisK K{};
+template <typename C>
+static void run_passes(Prof* pf, hipStream_t s, const GridView& g, PoisK<C> K) {
+  constexpr int CB = (int)sizeof(C);
+  // LDS budget per block: 64 KB for the two ping-pong buffers
+  int rows = (2048 * 16 / CB) / g.nx;
+  if (rows < 1) rows = 1;
+  if (rows > 128 / CB) rows = 128 / CB;
+  K.rows = rows;
+  int tp = (2048 * 16 / CB) / g.nz;
+  if (tp < 1) tp = 1;
+  if (tp > 128 / CB) tp = 128 / CB;
+  K.tp = tp;
+  line_plan(g.ny, false, YL, &K.yP, &K.yL, &K.yr);
+  K.ytl = 1024 / K.yP;
+  if (K.ytl > 16) K.ytl = 16;
+  if (K.ytl < 1) K.ytl = 1;
+  const int64_t nrows = (int64_t)g.ny * g.nz;
+  const int xblocks = (int)((nrows + rows - 1) / rows);
+  const size_t xsh = 2 * (size_t)rows * g.nx * CB;
+  const size_t zsh = 2 * (size_t)tp * g.nz * CB;
+  dim3 zgrid((g.nxh + tp - 1) / tp, g.ny);
+  const int64_t nm = (int64_t)g.nz * g.nxh;
+  const int yblocks = (int)((nm + K.ytl - 1) / K.ytl);
+  const size_t ysh = 7 * sizeof(double) * (size_t)K.yP * K.ytl;
+  const bool resid = K.mode >= SRC_RESIDUAL;
+  IBM_LAUNCH(pf, resid ? "pois_resid_fftx" : "pois_fftx_fwd", s,
+             (k_fftx_fwd<C><<<xblocks, 256, xsh, s>>>(K)));
+  if (K.mode == SRC_CHECK) return;
+  if (resid) {
+    K.gate = K.rmax;  // the rest of a refinement runs only if its residual is too large
+    IBM_LAUNCH(pf, "pois_mean", s,
+               (k_sum_partials<<<1, 256, 0, s>>>(K.psum, xblocks, const_cast<double*>(K.msum),
+                                                  K.gate, K.gate_tol)));
+  }
+  IBM_LAUNCH(pf, "pois_fftz_fwd", s, (k_fftz<C, false><<<zgrid, 256, zsh, s>>>(K)));
+  IBM_LAUNCH(pf, "pois_tri_y", s, (k_tri_y<C><<<yblocks, K.ytl * K.yP, ysh, s>>>(K)));
+  IBM_LAUNCH(pf, "pois_fftz_inv", s, (k_fftz<C, true><<<zgrid, 256, zsh, s>>>(K)));
+  IBM_LAUNCH(pf, "pois_fftx_inv", s, (k_fftx_inv<C><<<xblocks, 256, xsh, s>>>(K)));
+}
+
+template <typename C>
+static void solve(Prof* pf, hipStream_t s, const GridView& g, const PoissonArgs& a,
+                  const C* twx, const C* twz, const double* rhs, const double* u,
+                  const double* v, const double* w, const uint32_t* cb_mask, const double* qf,
+                  double inv_adt, double* phi) {
+  PoisK<C> K{};
   K.g = g;
-  K.px = to_dev(a.px);
-  K.pz = to_dev(a.pz);
+  K.px = to_dev<C>(a.px, twx);
+  K.pz = to_dev<C>(a.pz, twz);
+  K.mode = rhs ? SRC_ARRAY : SRC_VELOCITY;
   K.rhs = rhs;
   K.u = u;
   K.v = v;
@@ -343,8 +688,7 @@ void launch_poisson(Prof* pf, hipStream_t s, const GridView& g, const PoissonArg
   K.cb_mask = cb_mask;
   K.qf = qf;
   K.inv_adt = inv_adt;
-  K.spec = a.spec;
-  K.cscr = a.cscr;
+  K.spec = reinterpret_cast<C*>(a.spec);
   K.lamx = a.lamx;
   K.lamz = a.lamz;
   K.ylo = a.ylo;
@@ -352,26 +696,39 @@ void launch_poisson(Prof* pf, hipStream_t s, const GridView& g, const PoissonArg
   K.inv_sum_dy = 1.0 / a.sum_dy;
   K.scale = 1.0 / ((double)g.nx * g.nz);
   K.phi = phi;
-  int rows = 2048 / g.nx;
-  if (rows < 1) rows = 1;
-  if (rows > 8) rows = 8;
-  K.rows = rows;
-  int tp = 2048 / g.nz;
-  if (tp < 1) tp = 1;
-  if (tp > 8) tp = 8;
-  K.tp = tp;
-  const int64_t nrows = (int64_t)g.ny * g.nz;
-  const int xblocks = (int)((nrows + rows - 1) / rows);
-  const size_t xsh = 2 * (size_t)rows * g.nx * sizeof(double2);
-  const size_t zsh = 2 * (size_t)tp * g.nz * sizeof(double2);
-  const int xthreads = 256;
-  dim3 zgrid((g.nxh + tp - 1) / tp, g.ny);
-  const int64_t nm = (int64_t)g.nz * g.nxh;
-  IBM_LAUNCH(pf, "pois_fftx_fwd", s, k_fftx_fwd<<<xblocks, xthreads, xsh, s>>>(K));
-  IBM_LAUNCH(pf, "pois_fftz_fwd", s, k_fftz<false><<<zgrid, 256, zsh, s>>>(K));
-  IBM_LAUNCH(pf, "pois_tri_y", s, k_tri_y<<<(int)((nm + 255) / 256), 256, 0, s>>>(K));
-  IBM_LAUNCH(pf, "pois_fftz_inv", s, k_fftz<true><<<zgrid, 256, zsh, s>>>(K));
-  IBM_LAUNCH(pf, "pois_fftx_inv", s, k_fftx_inv<<<xblocks, xthreads, xsh, s>>>(K));
+  const int nref = a.refine ? a.nref : 0;
+  K.rhs_keep = a.refine ? a.rhs_keep : nullptr;
+  K.zm = a.fp32 ? a.zm : nullptr;
+  // the tolerance bounds max|r| * alpha dt
+  K.gate_tol = a.tol * inv_adt;
+  if (a.refine) launch_fill_u64(pf, s, a.rmax, nref + 2, 0ull);
+  run_passes<C>(pf, s, g, K);
+  if (!a.refine) return;
+  K.rhs = a.rhs_keep;
+  K.rhs_keep = nullptr;
+  K.phi_in = phi;
+  K.accumulate = 1;
+  K.inv_vtot = 1.0 / a.vtot;
+  for (int k = 1; k <= nref + 1; ++k) {
+    K.mode = (k <= nref) ? SRC_RESIDUAL : SRC_CHECK;
+    K.rmax = a.rmax + k;
+    K.gate = (k > 1) ? a.rmax + (k - 1) : nullptr;
+    K.psum = (k <= nref) ? a.psum : nullptr;
+    K.msum = (k <= nref) ? a.msum + k : nullptr;
+    run_passes<C>(pf, s, g, K);
+  }
+  IBM_LAUNCH(pf, "pois_refine_stats", s,
+             (k_refine_stats<<<1, 64, 0, s>>>(a.rmax, nref, K.gate_tol, 1.0 / inv_adt, a.stats,
+                                              a.flags)));
+}
+
+void launch_poisson(Prof* pf, hipStream_t s, const GridView& g, const PoissonArgs& a,
+                    const double* rhs, const double* u, const double* v, const double* w,
+                    const uint32_t* cb_mask, const double* qf, double inv_adt, double* phi) {
+  if (a.fp32)
+    solve<float2>(pf, s, g, a, a.px->tw32, a.pz->tw32, rhs, u, v, w, cb_mask, qf, inv_adt, phi);
+  else
+    solve<double2>(pf, s, g, a, a.px->tw, a.pz->tw, rhs, u, v, w, cb_mask, qf, inv_adt, phi);
 }
 
 }  // namespace ibm

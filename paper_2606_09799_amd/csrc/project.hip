@@ -2,15 +2,18 @@
 //   u <- u_hat - alpha dt G phi   on every interior velocity node
 //   p <- p + phi - alpha dt/(2 Re) L_c phi,  L_c = D G (Neumann at the walls)
 // One thread per (i, j, k), x fastest; rows are ordered per XCD so that the
-// neighbouring rows of phi are reused from the same L2 (xcd_tile).
+// neighbouring rows of phi are reused from the same L2 (xcd_tile).  The
+// velocity update is FP64 in both forms; p is stored in T (float in the
+// mixed form) and updated in FP64 arithmetic.
 #include "geom.h"
 
 namespace ibm {
 
+template <typename T>
 __global__ __launch_bounds__(256) void k_project(GridView g, const double* __restrict__ phi,
                                                  double adt, double pc, double* __restrict__ u,
                                                  double* __restrict__ v, double* __restrict__ w,
-                                                 double* __restrict__ p) {
+                                                 T* __restrict__ p) {
   const int nbx = (g.nx + 255) / 256;
   const int64_t t = xcd_tile(blockIdx.x, (int64_t)nbx * g.nz * g.ny);
   const int i = (int)(t % nbx) * 256 + threadIdx.x;
@@ -41,14 +44,19 @@ __global__ __launch_bounds__(256) void k_project(GridView g, const double* __res
   if (j + 1 < g.ny) fluxn = (phi[c + plane] - fc) * g.idyc[j + 1];
   const double lc = ((fe - fc) * g.idx - gx) * g.idx + ((ft - fc) * g.idz - gz) * g.idz +
                     (fluxn - fluxs) * g.idy[j];
-  p[c] += fc - pc * lc;
+  p[c] = (T)((double)p[c] + (fc - pc * lc));
 }
 
 void launch_project(Prof* pf, hipStream_t s, const GridView& g, const double* phi, double adt,
-                    double re, double* u, double* v, double* w, double* p) {
+                    double re, double* u, double* v, double* w, void* p, int fp32) {
   dim3 grid((unsigned)((int64_t)((g.nx + 255) / 256) * g.nz * g.ny));
   const double pc = adt / (2.0 * re);
-  IBM_LAUNCH(pf, "project", s, k_project<<<grid, 256, 0, s>>>(g, phi, adt, pc, u, v, w, p));
+  if (fp32)
+    IBM_LAUNCH(pf, "project", s,
+               k_project<float><<<grid, 256, 0, s>>>(g, phi, adt, pc, u, v, w, (float*)p));
+  else
+    IBM_LAUNCH(pf, "project", s,
+               k_project<double><<<grid, 256, 0, s>>>(g, phi, adt, pc, u, v, w, (double*)p));
 }
 
 }  // namespace ibm

@@ -10,20 +10,33 @@
 // thread index so every neighbour access of a wavefront is a contiguous row
 // segment.  The neighbourhood reuse across rows is served by the L2: tiles
 // are ordered so that each XCD sweeps a contiguous slab (xcd_tile).
+//
+// Storage type T of p, H and R: double, or float in the mixed form.  The
+// stencil arithmetic is FP64 in both forms: the velocity is FP64, and
+// rounding it to FP32 before differencing would amplify its rounding error by
+// 1/spacing; only the results are stored in T.
 #include "geom.h"
 
 namespace ibm {
 
+template <typename T>
 struct RhsK {
   GridView g;
-  RhsArgs a;
+  const double *u, *v, *w;
+  const T* p;
+  const T* hprev[3];
+  T* hout[3];
+  T* R[3];
+  const uint32_t* mask[3];
+  double gamma, rho, alpha, dt, re, fx;
 };
 
 #define IDX(i, j, k) (((int64_t)(j) * g.nz + (k)) * g.nx + (i))
 
-__global__ __launch_bounds__(256) void k_rhs(RhsK K) {
+template <typename T>
+__global__ __launch_bounds__(256) void k_rhs(RhsK<T> K) {
   const GridView& g = K.g;
-  const RhsArgs& a = K.a;
+  const RhsK<T>& a = K;
   const int nbx = (g.nx + 63) / 64, nbz = (g.nz + 3) / 4;
   const int64_t t = xcd_tile(blockIdx.x, (int64_t)nbx * nbz * g.ny);
   const int i = (int)(t % nbx) * 64 + threadIdx.x;
@@ -39,7 +52,7 @@ __global__ __launch_bounds__(256) void k_rhs(RhsK K) {
   const double* __restrict__ u = a.u;
   const double* __restrict__ v = a.v;
   const double* __restrict__ w = a.w;
-  const double* __restrict__ p = a.p;
+  const T* __restrict__ p = a.p;
   const int64_t c = IDX(i, j, k);
   const double idyj = g.idy[j];
   const bool has_s = j > 0, has_n = j + 1 < g.ny;
@@ -67,11 +80,11 @@ __global__ __launch_bounds__(256) void k_rhs(RhsK K) {
     const double H = -(tx + ty + tz);
     const double L = ((ue - uc) - (uc - uw)) * idx2 + ((ut - uc) - (uc - ub)) * idz2 +
                      ((un - uc) * ic_n - (uc - us) * ic_s) * idyj;
-    const double gp = (p[c] - p[IDX(im, j, k)]) * idx;
+    const double gp = ((double)p[c] - (double)p[IDX(im, j, k)]) * idx;
     double r = a.gamma * H - a.alpha * (gp - a.fx) + am * L;
-    if (a.rho != 0.0) r += a.rho * a.hprev[0][c];
-    if (a.hout[0]) a.hout[0][c] = H;
-    a.R[0][c] = test_bit(a.mask[0], c) ? 0.0 : a.dt * r;
+    if (a.rho != 0.0) r += a.rho * (double)a.hprev[0][c];
+    if (a.hout[0]) a.hout[0][c] = (T)H;
+    a.R[0][c] = (T)(test_bit(a.mask[0], c) ? 0.0 : a.dt * r);
   }
   // ------------------------------------------------------------ w node
   {
@@ -92,19 +105,19 @@ __global__ __launch_bounds__(256) void k_rhs(RhsK K) {
     const double H = -(tx + ty + tz);
     const double L = ((we - wc) - (wc - ww)) * idx2 + ((wt - wc) - (wc - wb)) * idz2 +
                      ((wn - wc) * ic_n - (wc - ws) * ic_s) * idyj;
-    const double gp = (p[c] - p[IDX(i, j, km)]) * idz;
+    const double gp = ((double)p[c] - (double)p[IDX(i, j, km)]) * idz;
     double r = a.gamma * H - a.alpha * gp + am * L;
-    if (a.rho != 0.0) r += a.rho * a.hprev[2][c];
-    if (a.hout[2]) a.hout[2][c] = H;
-    a.R[2][c] = test_bit(a.mask[2], c) ? 0.0 : a.dt * r;
+    if (a.rho != 0.0) r += a.rho * (double)a.hprev[2][c];
+    if (a.hout[2]) a.hout[2][c] = (T)H;
+    a.R[2][c] = (T)(test_bit(a.mask[2], c) ? 0.0 : a.dt * r);
   }
   // ------------------------------------------------------ v node (face j)
   if (j == 0) {
-    a.R[1][c] = 0.0;  // wall planes
-    a.R[1][IDX(i, g.ny, k)] = 0.0;
+    a.R[1][c] = (T)0;  // wall planes
+    a.R[1][IDX(i, g.ny, k)] = (T)0;
     if (a.hout[1]) {
-      a.hout[1][c] = 0.0;
-      a.hout[1][IDX(i, g.ny, k)] = 0.0;
+      a.hout[1][c] = (T)0;
+      a.hout[1][IDX(i, g.ny, k)] = (T)0;
     }
     return;
   }
@@ -123,22 +136,45 @@ __global__ __launch_bounds__(256) void k_rhs(RhsK K) {
     const double H = -(tx + ty + tz);
     const double L = ((ve - vc) - (vc - vw)) * idx2 + ((vt - vc) - (vc - vb)) * idz2 +
                      ((vn - vc) * idyj - (vc - vs) * g.idy[j - 1]) * ic_s;
-    const double gp = (p[c] - p[IDX(i, j - 1, k)]) * ic_s;
+    const double gp = ((double)p[c] - (double)p[IDX(i, j - 1, k)]) * ic_s;
     double r = a.gamma * H - a.alpha * gp + am * L;
-    if (a.rho != 0.0) r += a.rho * a.hprev[1][c];
-    if (a.hout[1]) a.hout[1][c] = H;
-    a.R[1][c] = test_bit(a.mask[1], c) ? 0.0 : a.dt * r;
+    if (a.rho != 0.0) r += a.rho * (double)a.hprev[1][c];
+    if (a.hout[1]) a.hout[1][c] = (T)H;
+    a.R[1][c] = (T)(test_bit(a.mask[1], c) ? 0.0 : a.dt * r);
   }
 }
 
-void launch_rhs(Prof* pf, hipStream_t s, const GridView& g, const RhsArgs& a) {
-  RhsK K;
+template <typename T>
+static void run_rhs(Prof* pf, hipStream_t s, const GridView& g, const RhsArgs& a) {
+  RhsK<T> K;
   K.g = g;
-  K.a = a;
+  K.u = a.u;
+  K.v = a.v;
+  K.w = a.w;
+  K.p = static_cast<const T*>(a.p);
+  for (int q = 0; q < 3; ++q) {
+    K.hprev[q] = static_cast<const T*>(a.hprev[q]);
+    K.hout[q] = static_cast<T*>(a.hout[q]);
+    K.R[q] = static_cast<T*>(a.R[q]);
+    K.mask[q] = a.mask[q];
+  }
+  K.gamma = a.gamma;
+  K.rho = a.rho;
+  K.alpha = a.alpha;
+  K.dt = a.dt;
+  K.re = a.re;
+  K.fx = a.fx;
   dim3 block(64, 4);
   const int64_t tiles = (int64_t)((g.nx + 63) / 64) * ((g.nz + 3) / 4) * g.ny;
   dim3 grid((unsigned)tiles);
-  IBM_LAUNCH(pf, "rhs", s, k_rhs<<<grid, block, 0, s>>>(K));
+  IBM_LAUNCH(pf, "rhs", s, k_rhs<T><<<grid, block, 0, s>>>(K));
+}
+
+void launch_rhs(Prof* pf, hipStream_t s, const GridView& g, const RhsArgs& a) {
+  if (a.fp32)
+    run_rhs<float>(pf, s, g, a);
+  else
+    run_rhs<double>(pf, s, g, a);
 }
 
 }  // namespace ibm

@@ -24,8 +24,8 @@ _lib = ctypes.CDLL(LIB_PATH)
 
 IBM_OK, IBM_EINVAL, IBM_ENOMEM, IBM_EHIP, IBM_ECAPACITY = 0, -1, -2, -3, -4
 IBM_ENONFINITE, IBM_EGEOM = -5, -7
-FLAG_CAPACITY, FLAG_NONFINITE, FLAG_GEOM = 1, 2, 4
-IBM_FP64 = 0
+FLAG_CAPACITY, FLAG_NONFINITE, FLAG_GEOM, FLAG_REFINE = 1, 2, 4, 8
+IBM_FP64, IBM_MIXED = 0, 1
 IBM_RK2CN, IBM_AB2CN = 0, 1
 
 
@@ -37,7 +37,7 @@ class IbmGrid(ctypes.Structure):
 class IbmOpts(ctypes.Structure):
     _fields_ = [("precision", c_int32), ("scheme", c_int32), ("re", c_double),
                 ("dpdx", c_double), ("force_cap", c_int64), ("use_q", c_int32),
-                ("reserved", c_int32)]
+                ("refine_max", c_int32), ("refine_tol", c_double)]
 
 
 class IbmBody(ctypes.Structure):
@@ -84,6 +84,7 @@ _project = _sig("ibm_project", c_int32, c_void_p, c_void_p, c_double, c_void_p, 
                 c_void_p, c_void_p)
 _step = _sig("ibm_step", c_int32, c_void_p, POINTER(IbmState), POINTER(IbmBody), c_int32,
              c_double)
+_refine_stats = _sig("ibm_refine_stats", c_int32, c_void_p, POINTER(c_double), c_int32)
 _check = _sig("ibm_check", c_int32, c_void_p, POINTER(c_uint32))
 _strerror = _sig("ibm_strerror", c_char_p, c_int32)
 _profile = _sig("ibm_profile", c_int32, c_void_p, c_int32, c_char_p)
@@ -92,8 +93,8 @@ _profile_read = _sig("ibm_profile_read", c_int32, c_void_p, c_char_p, c_int32,
 
 EXPORTS = ("ibm_create", "ibm_destroy", "ibm_set_stream", "ibm_body_rigid", "ibm_body_deform",
            "ibm_tag", "ibm_tags_count_host", "ibm_tags_copy", "ibm_force", "ibm_viscous",
-           "ibm_mass_rhs", "poisson_solve", "ibm_project", "ibm_step", "ibm_check",
-           "ibm_strerror", "ibm_profile", "ibm_profile_read")
+           "ibm_mass_rhs", "poisson_solve", "ibm_project", "ibm_step", "ibm_refine_stats",
+           "ibm_check", "ibm_strerror", "ibm_profile", "ibm_profile_read")
 
 
 class IbmError(RuntimeError):
@@ -126,10 +127,16 @@ def _dev(t, dtype, numel, name):
 
 
 class Context:
-    """One grid on the current device, bound to torch's current stream."""
+    """One grid on the current device, bound to torch's current stream.
+    precision: "fp64", or "mixed" (p and H in float32; u, v, w in float64)."""
 
     def __init__(self, nx, ny, nz, lx, lz, y_faces, re, dpdx=0.0, scheme="rk2", use_q=True,
-                 force_cap=0):
+                 force_cap=0, precision="fp64", refine_max=0, refine_tol=0.0):
+        if precision not in ("fp64", "mixed"):
+            raise ValueError("precision: 'fp64' or 'mixed'")
+        self.precision = precision
+        # dtype of p and of the H arrays
+        self.pdtype = torch.float32 if precision == "mixed" else torch.float64
         self.nx, self.ny, self.nz = int(nx), int(ny), int(nz)
         self.cells = self.nx * self.ny * self.nz
         self.vfaces = self.nx * (self.ny + 1) * self.nz
@@ -139,8 +146,10 @@ class Context:
         self._yf = yf
         g = IbmGrid(self.nx, self.ny, self.nz, 0, float(lx), float(lz),
                     yf.ctypes.data_as(POINTER(c_double)))
-        o = IbmOpts(IBM_FP64, IBM_RK2CN if scheme == "rk2" else IBM_AB2CN, float(re),
-                    float(dpdx), int(force_cap), 1 if use_q else 0, 0)
+        o = IbmOpts(IBM_MIXED if precision == "mixed" else IBM_FP64,
+                    IBM_RK2CN if scheme == "rk2" else IBM_AB2CN, float(re),
+                    float(dpdx), int(force_cap), 1 if use_q else 0, int(refine_max),
+                    float(refine_tol))
         h = c_void_p()
         _ok(_create(ctypes.byref(g), ctypes.byref(o), _stream(), ctypes.byref(h)), "ibm_create")
         self.handle = h
@@ -250,12 +259,12 @@ def _ptr3(ts, ctx, name):
         return None
     arr = (c_void_p * 3)()
     for c in range(3):
-        arr[c] = _dev(ts[c], torch.float64, ctx.comp_numel(c), f"{name}[{c}]")
+        arr[c] = _dev(ts[c], ctx.pdtype, ctx.comp_numel(c), f"{name}[{c}]")
     return arr
 
 
 def ibm_viscous(ctx, p, h_prev, h_out, gamma, rho, dt, u, v, w):
-    _ok(_viscous(ctx.handle, _dev(p, torch.float64, ctx.cells, "p"), _ptr3(h_prev, ctx, "h_prev"),
+    _ok(_viscous(ctx.handle, _dev(p, ctx.pdtype, ctx.cells, "p"), _ptr3(h_prev, ctx, "h_prev"),
                  _ptr3(h_out, ctx, "h_out"), float(gamma), float(rho), float(dt),
                  _dev(u, torch.float64, ctx.cells, "u"), _dev(v, torch.float64, ctx.vfaces, "v"),
                  _dev(w, torch.float64, ctx.cells, "w")), "ibm_viscous")
@@ -278,17 +287,25 @@ def ibm_project(ctx, phi, alpha_dt, u, v, w, p):
     _ok(_project(ctx.handle, _dev(phi, torch.float64, ctx.cells, "phi"), float(alpha_dt),
                  _dev(u, torch.float64, ctx.cells, "u"), _dev(v, torch.float64, ctx.vfaces, "v"),
                  _dev(w, torch.float64, ctx.cells, "w"),
-                 _dev(p, torch.float64, ctx.cells, "p")), "ibm_project")
+                 _dev(p, ctx.pdtype, ctx.cells, "p")), "ibm_project")
 
 
 def ibm_step(ctx, u, v, w, p, bodies, dt, h=None):
     st = IbmState(_dev(u, torch.float64, ctx.cells, "u"), _dev(v, torch.float64, ctx.vfaces, "v"),
-                  _dev(w, torch.float64, ctx.cells, "w"), _dev(p, torch.float64, ctx.cells, "p"))
+                  _dev(w, torch.float64, ctx.cells, "w"), _dev(p, ctx.pdtype, ctx.cells, "p"))
     if h is not None:
         for c in range(3):
-            st.h[c] = _dev(h[c], torch.float64, ctx.comp_numel(c), f"h[{c}]")
+            st.h[c] = _dev(h[c], ctx.pdtype, ctx.comp_numel(c), f"h[{c}]")
     arr, n = _bodies(bodies)
     _ok(_step(ctx.handle, ctypes.byref(st), arr, n, float(dt)), "ibm_step")
+
+
+def ibm_refine_stats(ctx, reset=False):
+    """Mixed form: (Poisson solves, FP64-residual corrections, largest final
+    max|rhs - L_c phi| * alpha_dt) since the last reset (synchronises)."""
+    out = (c_double * 3)()
+    _ok(_refine_stats(ctx.handle, out, 1 if reset else 0), "ibm_refine_stats")
+    return int(out[0]), int(out[1]), float(out[2])
 
 
 def ibm_check(ctx):

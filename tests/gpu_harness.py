@@ -31,13 +31,13 @@ def rel(a, ref):
 class Case:
     """A workload on both sides: oracle grid + HIP context + bodies."""
 
-    def __init__(self, name, use_q=True, force_cap=0):
+    def __init__(self, name, use_q=True, force_cap=0, **ctx_opts):
         from paper_2606_09799_amd import ibm
         self.ibm = ibm
         self.wl = wl = workloads.config(name) if isinstance(name, str) else name
         self.g = Grid(wl.nx, wl.ny, wl.nz, wl.lx, wl.lz, wl.y_faces)
         self.ctx = ibm.Context(wl.nx, wl.ny, wl.nz, wl.lx, wl.lz, wl.y_faces, wl.re, wl.dpdx,
-                               use_q=use_q, force_cap=force_cap)
+                               use_q=use_q, force_cap=force_cap, **ctx_opts)
         self.fext = (-wl.dpdx, 0.0, 0.0)
         self.dev_bodies = []
         for b in wl.bodies:
