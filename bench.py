@@ -185,6 +185,59 @@ def run_form(args, wl, form, dev):
     return el, prof, dominant, dom, stats
 
 
+def run_batched(args, dev, nsim):
+    """Times the batched workload (nsim simulations of different sizes, one
+    body each) in each execution mode; returns {mode: (cell-steps/s,
+    ms per step)} and the total cell count."""
+    import numpy as np
+    import torch
+    import workloads
+    from paper_2606_09799_amd import ibm
+
+    wls = workloads.batch(nsim)
+    T = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
+    sims = []
+    for wl in wls:
+        u, v, w = (T(a) for a in wl.fields())
+        b = wl.bodies[0]
+        nv = b.ref.shape[0]
+        sims.append({"nx": wl.nx, "ny": wl.ny, "nz": wl.nz, "lx": wl.lx, "lz": wl.lz,
+                     "y_faces": wl.y_faces, "re": wl.re, "dpdx": wl.dpdx, "u": u, "v": v, "w": w,
+                     "p": torch.zeros(wl.cells, dtype=torch.float64, device=dev),
+                     "motion": b.kind, "ref": T(b.ref),
+                     "xyz": torch.empty(nv, 3, dtype=torch.float64, device=dev),
+                     "vel": torch.empty(nv, 3, dtype=torch.float64, device=dev),
+                     "tri": T(b.tris.astype(np.int32))})
+    batch = ibm.Batch(sims)
+    dt = wls[0].dt
+    cells = sum(wl.cells for wl in wls)
+    out = {}
+    k = 0
+    for name, mode in (("serial", ibm.BATCH_SERIAL), ("streams", ibm.BATCH_STREAMS),
+                       ("graph", ibm.BATCH_GRAPH)):
+        for _ in range(args.warmup):
+            batch.step([wl.bodies[0].coef(k * dt) for wl in wls], dt, mode)
+            k += 1
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            batch.step([wl.bodies[0].coef(k * dt) for wl in wls], dt, mode)
+            k += 1
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        out[name] = (cells * 2 * args.steps / el, el / args.steps * 1e3)
+    flags = batch.check()
+    if flags:
+        print(f"bench.py: device flags {flags} after the batched run", file=sys.stderr)
+        sys.exit(1)
+    for d in sims:
+        if not all(torch.isfinite(d[q]).all().item() for q in ("u", "v", "w", "p")):
+            print("bench.py: non-finite state after the batched run", file=sys.stderr)
+            sys.exit(1)
+    batch.close()
+    return out, cells
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -193,6 +246,8 @@ def main():
     ap.add_argument("--workload", default="c2")
     ap.add_argument("--forms", default="fp64,mixed",
                     help="precision forms to time; the first one is the headline value")
+    ap.add_argument("--batch-sims", type=int, default=64,
+                    help="simulations of the batched workload (0 = skip it)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-ref-mib", type=int, default=0,
                     help="also run a plain device copy of this size (PMC scale reference)")
@@ -232,6 +287,16 @@ def main():
                                "corrections_per_solve": round(corr / max(1, solves), 3),
                                "max_final_divergence": worst}
         results[form] = r
+    batched = None
+    if args.batch_sims > 0:
+        modes, bcells = run_batched(args, dev, args.batch_sims)
+        best = max(modes, key=lambda m: modes[m][0])
+        batched = {"workload": f"c4: {args.batch_sims} simulations, {bcells} cells in total "
+                               "(uniform spacing 1/32, 32..128 x 32..96 x 32..128, one sphere, "
+                               "plate or deforming body each), Re 100, dt 1e-3, FP64",
+                   "value": modes[best][0], "ms_per_step": modes[best][1], "mode": best,
+                   "modes": {m: {"value": v, "ms_per_step": ms} for m, (v, ms) in modes.items()},
+                   "speedup_vs_serial": modes[best][0] / modes["serial"][0]}
     head = results[forms[0]]
     copy_ref = None
     if args.copy_ref_mib:
@@ -260,6 +325,8 @@ def main():
         "forms": {f: {k: v for k, v in r.items() if k != "kernel_ms_per_step"}
                   for f, r in results.items()},
     }
+    if batched:
+        out["forms"]["batched"] = batched
     if len(forms) > 1:
         out["forms"]["kernel_ms_per_step"] = {f: r["kernel_ms_per_step"] for f, r in results.items()}
     if copy_ref:

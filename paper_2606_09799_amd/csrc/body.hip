@@ -17,10 +17,8 @@ struct Deform {
 };
 
 // X = c + R X0, U = cdot + omega x (X - c)
-__global__ void k_body_rigid(const double* __restrict__ x0, int nv, Rigid k,
-                             double* __restrict__ xyz, double* __restrict__ vel) {
-  int v = blockIdx.x * blockDim.x + threadIdx.x;
-  if (v >= nv) return;
+__device__ __forceinline__ void rigid_vertex(const Rigid& k, const double* __restrict__ x0, int v,
+                                             double* __restrict__ xyz, double* __restrict__ vel) {
   double a0 = x0[3 * v], a1 = x0[3 * v + 1], a2 = x0[3 * v + 2];
   double X[3];
   for (int d = 0; d < 3; ++d)
@@ -35,10 +33,9 @@ __global__ void k_body_rigid(const double* __restrict__ x0, int nv, Rigid k,
 }
 
 // X = c + (r0 + f s) d, U = (f sdot) d
-__global__ void k_body_deform(const double* __restrict__ data, int nv, Deform k,
-                              double* __restrict__ xyz, double* __restrict__ vel) {
-  int v = blockIdx.x * blockDim.x + threadIdx.x;
-  if (v >= nv) return;
+__device__ __forceinline__ void deform_vertex(const Deform& k, const double* __restrict__ data,
+                                              int v, double* __restrict__ xyz,
+                                              double* __restrict__ vel) {
   double f = data[4 * v + 3];
   double rad = k.r0 + f * k.s;
   double rd = f * k.sd;
@@ -47,6 +44,49 @@ __global__ void k_body_deform(const double* __restrict__ data, int nv, Deform k,
     xyz[3 * v + d] = k.c[d] + rad * dir;
     vel[3 * v + d] = rd * dir;
   }
+}
+
+__global__ void k_body_rigid(const double* __restrict__ x0, int nv, Rigid k,
+                             double* __restrict__ xyz, double* __restrict__ vel) {
+  int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= nv) return;
+  rigid_vertex(k, x0, v, xyz, vel);
+}
+
+__global__ void k_body_deform(const double* __restrict__ data, int nv, Deform k,
+                              double* __restrict__ xyz, double* __restrict__ vel) {
+  int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= nv) return;
+  deform_vertex(k, data, v, xyz, vel);
+}
+
+// the same transforms with the coefficients read from device memory (the
+// layout of the host coefficient vectors), so that a captured launch can be
+// replayed with new coefficients
+__global__ void k_body_rigid_dev(const double* __restrict__ x0, int nv,
+                                 const double* __restrict__ coef, double* __restrict__ xyz,
+                                 double* __restrict__ vel) {
+  int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= nv) return;
+  Rigid k;
+  for (int d = 0; d < 3; ++d) k.c[d] = coef[d];
+  for (int d = 0; d < 9; ++d) k.R[d] = coef[3 + d];
+  for (int d = 0; d < 3; ++d) k.cd[d] = coef[12 + d];
+  for (int d = 0; d < 3; ++d) k.om[d] = coef[15 + d];
+  rigid_vertex(k, x0, v, xyz, vel);
+}
+
+__global__ void k_body_deform_dev(const double* __restrict__ data, int nv,
+                                  const double* __restrict__ coef, double* __restrict__ xyz,
+                                  double* __restrict__ vel) {
+  int v = blockIdx.x * blockDim.x + threadIdx.x;
+  if (v >= nv) return;
+  Deform k;
+  for (int d = 0; d < 3; ++d) k.c[d] = coef[d];
+  k.r0 = coef[3];
+  k.s = coef[4];
+  k.sd = coef[5];
+  deform_vertex(k, data, v, xyz, vel);
 }
 
 void launch_body_rigid(Prof* pf, hipStream_t s, const double* x0, int nv, const double* coef,
@@ -71,6 +111,17 @@ void launch_body_deform(Prof* pf, hipStream_t s, const double* data, int nv, con
   if (nv <= 0) return;
   IBM_LAUNCH(pf, "body_deform", s,
              k_body_deform<<<(nv + 255) / 256, 256, 0, s>>>(data, nv, k, xyz, vel));
+}
+
+void launch_body_dev(Prof* pf, hipStream_t s, int deform, const double* ref, int nv,
+                     const double* coef_dev, double* xyz, double* vel) {
+  if (nv <= 0) return;
+  if (deform)
+    IBM_LAUNCH(pf, "body_deform", s,
+               k_body_deform_dev<<<(nv + 255) / 256, 256, 0, s>>>(ref, nv, coef_dev, xyz, vel));
+  else
+    IBM_LAUNCH(pf, "body_rigid", s,
+               k_body_rigid_dev<<<(nv + 255) / 256, 256, 0, s>>>(ref, nv, coef_dev, xyz, vel));
 }
 
 }  // namespace ibm

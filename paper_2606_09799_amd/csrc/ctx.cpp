@@ -956,3 +956,32 @@ int ibm_profile_read(ibm_ctx* c, char* names, int32_t name_len, int64_t* launche
 }
 
 }  // extern "C"
+
+// ------------------------------------------------------------ batch support
+namespace ibm {
+
+hipStream_t ctx_stream(ibm_ctx* c) { return c->stream; }
+Prof* ctx_prof(ibm_ctx* c) { return &c->prof; }
+
+// Everything a time step may need to do outside stream order, done ahead of
+// a graph capture: the body descriptors in device memory and the line-solve
+// tables of the scheme's beta for this dt (the sub-stages of both schemes
+// share one alpha).
+int ctx_prepare(ibm_ctx* c, const ibm_body* b, int32_t nb, double dt) {
+  int rc = set_bodies(c, b, nb);
+  if (rc) return rc;
+  rc = upload_bodies(c);
+  if (rc) return rc;
+  const double alpha = (c->opts.scheme == IBM_RK2CN) ? 1.0 + -0.5 : 1.5 + -0.5;
+  rc = build_tables(c, alpha * dt / (2.0 * c->opts.re));
+  if (rc) return rc;
+  HIPCHK(hipStreamSynchronize(c->stream));
+  return IBM_OK;
+}
+
+int ctx_fail(int code, const char* msg) {
+  g_last_error = msg;
+  return code;
+}
+
+}  // namespace ibm

@@ -118,6 +118,10 @@ void launch_body_rigid(Prof* pf, hipStream_t s, const double* x0, int nv, const 
                        double* xyz, double* vel);
 void launch_body_deform(Prof* pf, hipStream_t s, const double* data, int nv, const double* coef,
                         double* xyz, double* vel);
+// the same transforms with the coefficients in device memory (rigid: 18
+// values, deform: 6, the layouts of the host calls)
+void launch_body_dev(Prof* pf, hipStream_t s, int deform, const double* ref, int nv,
+                     const double* coef_dev, double* xyz, double* vel);
 
 // tag.hip
 struct TagBuffers {

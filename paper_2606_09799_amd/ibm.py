@@ -56,6 +56,11 @@ class IbmState(ctypes.Structure):
                 ("h", c_void_p * 3)]
 
 
+class IbmSim(ctypes.Structure):
+    _fields_ = [("state", IbmState), ("motion", c_int32), ("nv", c_int32), ("nt", c_int32),
+                ("ref", c_void_p), ("xyz", c_void_p), ("vel", c_void_p), ("tri", c_void_p)]
+
+
 def _sig(name, res, *args):
     f = getattr(_lib, name)
     f.restype = res
@@ -85,6 +90,12 @@ _project = _sig("ibm_project", c_int32, c_void_p, c_void_p, c_double, c_void_p, 
 _step = _sig("ibm_step", c_int32, c_void_p, POINTER(IbmState), POINTER(IbmBody), c_int32,
              c_double)
 _refine_stats = _sig("ibm_refine_stats", c_int32, c_void_p, POINTER(c_double), c_int32)
+_batch_create = _sig("ibm_batch_create", c_int32, POINTER(IbmGrid), POINTER(IbmOpts),
+                     POINTER(IbmSim), c_int32, c_void_p, POINTER(c_void_p))
+_batch_destroy = _sig("ibm_batch_destroy", None, c_void_p)
+_batch_context = _sig("ibm_batch_context", c_void_p, c_void_p, c_int32)
+_batch_step = _sig("ibm_batch_step", c_int32, c_void_p, POINTER(c_double), c_double, c_int32)
+_batch_check = _sig("ibm_batch_check", c_int32, c_void_p, POINTER(c_uint32))
 _check = _sig("ibm_check", c_int32, c_void_p, POINTER(c_uint32))
 _strerror = _sig("ibm_strerror", c_char_p, c_int32)
 _profile = _sig("ibm_profile", c_int32, c_void_p, c_int32, c_char_p)
@@ -94,7 +105,12 @@ _profile_read = _sig("ibm_profile_read", c_int32, c_void_p, c_char_p, c_int32,
 EXPORTS = ("ibm_create", "ibm_destroy", "ibm_set_stream", "ibm_body_rigid", "ibm_body_deform",
            "ibm_tag", "ibm_tags_count_host", "ibm_tags_copy", "ibm_force", "ibm_viscous",
            "ibm_mass_rhs", "poisson_solve", "ibm_project", "ibm_step", "ibm_refine_stats",
-           "ibm_check", "ibm_strerror", "ibm_profile", "ibm_profile_read")
+           "ibm_check", "ibm_strerror", "ibm_profile", "ibm_profile_read",
+           "ibm_batch_create", "ibm_batch_destroy", "ibm_batch_context", "ibm_batch_step",
+           "ibm_batch_check")
+COEF_STRIDE = 18
+BATCH_SERIAL, BATCH_STREAMS, BATCH_GRAPH = 0, 1, 2
+MOTION_RIGID, MOTION_DEFORM = 0, 1
 
 
 class IbmError(RuntimeError):
@@ -329,3 +345,85 @@ def ibm_profile_read(ctx, cap=64):
         raise IbmError(n, "ibm_profile_read")
     return {names.raw[i * L:(i + 1) * L].split(b"\0")[0].decode(): (int(cnt[i]), float(tot[i]))
             for i in range(n)}
+
+
+class _Sim:
+    """View of one simulation of a batch for the per-context calls
+    (ibm_check, tag_lists, ibm_refine_stats)."""
+
+    def __init__(self, handle, nx, ny, nz, pdtype):
+        self.handle = handle
+        self.cells = nx * ny * nz
+        self.vfaces = nx * (ny + 1) * nz
+        self.pdtype = pdtype
+
+
+class Batch:
+    """Simulations advanced together on one GPU (include/ibm.h, batch).
+
+    sims: list of dicts with keys nx, ny, nz, lx, lz, y_faces, re, dpdx,
+    u, v, w, p (device tensors, kept by pointer), motion ("rigid" or
+    "deform"), ref, xyz, vel, tri (device tensors of the body)."""
+
+    def __init__(self, sims, precision="fp64", scheme="rk2", use_q=True):
+        n = len(sims)
+        self.n = n
+        pdtype = torch.float32 if precision == "mixed" else torch.float64
+        grids = (IbmGrid * n)()
+        opts = (IbmOpts * n)()
+        descs = (IbmSim * n)()
+        self._keep = []
+        self.shapes = []
+        for s, d in enumerate(sims):
+            yf = np.ascontiguousarray(np.asarray(d["y_faces"], np.float64))
+            self._keep.append(yf)
+            nx, ny, nz = int(d["nx"]), int(d["ny"]), int(d["nz"])
+            grids[s] = IbmGrid(nx, ny, nz, 0, float(d["lx"]), float(d["lz"]),
+                               yf.ctypes.data_as(POINTER(c_double)))
+            opts[s] = IbmOpts(IBM_MIXED if precision == "mixed" else IBM_FP64,
+                              IBM_RK2CN if scheme == "rk2" else IBM_AB2CN, float(d["re"]),
+                              float(d["dpdx"]), 0, 1 if use_q else 0, 0, 0.0)
+            cells, vf = nx * ny * nz, nx * (ny + 1) * nz
+            st = IbmState(_dev(d["u"], torch.float64, cells, "u"),
+                          _dev(d["v"], torch.float64, vf, "v"),
+                          _dev(d["w"], torch.float64, cells, "w"),
+                          _dev(d["p"], pdtype, cells, "p"))
+            deform = d["motion"] == "deform"
+            nv = d["xyz"].shape[0]
+            nt = d["tri"].shape[0]
+            descs[s] = IbmSim(st, MOTION_DEFORM if deform else MOTION_RIGID, nv, nt,
+                              _dev(d["ref"], torch.float64, (4 if deform else 3) * nv, "ref"),
+                              _dev(d["xyz"], torch.float64, 3 * nv, "xyz"),
+                              _dev(d["vel"], torch.float64, 3 * nv, "vel"),
+                              _dev(d["tri"], torch.int32, 3 * nt, "tri"))
+            self.shapes.append((nx, ny, nz))
+        h = c_void_p()
+        _ok(_batch_create(grids, opts, descs, n, _stream(), ctypes.byref(h)), "ibm_batch_create")
+        self.handle = h
+        self.sims = [_Sim(c_void_p(_batch_context(h, s)), *self.shapes[s], pdtype)
+                     for s in range(n)]
+
+    def step(self, coef, dt, mode=BATCH_GRAPH):
+        cf = np.zeros((self.n, COEF_STRIDE), np.float64)
+        for s, c in enumerate(coef):
+            c = np.asarray(c, np.float64)
+            cf[s, :c.size] = c
+        cf = np.ascontiguousarray(cf)
+        _ok(_batch_step(self.handle, cf.ctypes.data_as(POINTER(c_double)), float(dt), int(mode)),
+            "ibm_batch_step")
+
+    def check(self):
+        f = c_uint32()
+        _ok(_batch_check(self.handle, ctypes.byref(f)), "ibm_batch_check")
+        return int(f.value)
+
+    def close(self):
+        if self.handle:
+            _batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

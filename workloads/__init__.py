@@ -25,7 +25,7 @@ __all__ = [
     "uniform_faces", "tanh_faces", "icosphere", "plate_mesh",
     "rigid_coef", "sphere_translation", "plate_heave_pitch",
     "deform_vertex_data", "deform_coef", "splitmix64_uniform",
-    "initial_velocity", "Workload", "config", "CONFIG_NAMES",
+    "initial_velocity", "Workload", "config", "CONFIG_NAMES", "batch_sim", "batch",
 ]
 
 # --------------------------------------------------------------------------
@@ -188,15 +188,16 @@ def splitmix64_uniform(seed: int, comp: int, n: int, start: int = 0) -> np.ndarr
     return (z >> np.uint64(11)).astype(np.float64) * (1.0 / 9007199254740992.0)
 
 
-def initial_velocity(nx, ny, nz, y_faces, uc=1.0, amp=0.01, seed=1):
-    """Laminar profile u = uc (1 - y^2) at the u-node heights plus a seeded
-    uniform perturbation amp*(2 xi - 1) on every interior u, v, w unknown.
-    Layout [y][z][x]; v has ny+1 planes, the wall planes are 0.
-    Returns (u, v, w) f64 arrays."""
+def initial_velocity(nx, ny, nz, y_faces, uc=1.0, amp=0.01, seed=1, half=1.0):
+    """Laminar profile u = uc (1 - (y/half)^2) at the u-node heights (walls at
+    y = -half and +half) plus a seeded uniform perturbation amp*(2 xi - 1) on
+    every interior u, v, w unknown.  Layout [y][z][x]; v has ny+1 planes, the
+    wall planes are 0.  Returns (u, v, w) f64 arrays."""
     yf = np.asarray(y_faces, np.float64)
     yn = (yf[:-1] + yf[1:]) * 0.5                     # u-node heights
     n = nx * ny * nz
-    u = (uc * (1.0 - yn * yn))[:, None, None] * np.ones((ny, nz, nx))
+    yh = yn / half
+    u = (uc * (1.0 - yh * yh))[:, None, None] * np.ones((ny, nz, nx))
     u += amp * (2.0 * splitmix64_uniform(seed, 0, n).reshape(ny, nz, nx) - 1.0)
     v = np.zeros((ny + 1, nz, nx))
     nv = (ny - 1) * nz * nx
@@ -235,6 +236,7 @@ class Workload:
     dpdx: float                # mean pressure gradient dP/dx (driving force -dP/dx)
     bodies: list = field(default_factory=list)
     scheme: str = "rk2"
+    half: float = 1.0          # channel half-height (walls at +-half)
 
     @property
     def cells(self) -> int:
@@ -242,7 +244,7 @@ class Workload:
 
     def fields(self):
         return initial_velocity(self.nx, self.ny, self.nz, self.y_faces,
-                                self.uc, self.amp, self.seed)
+                                self.uc, self.amp, self.seed, self.half)
 
 
 def _sphere_body(level, radius, c0, U):
@@ -301,3 +303,85 @@ def config(name: str) -> Workload:
 
 
 CONFIG_NAMES = ("c1", "c2", "c3", "tiny", "tiny_plate")
+
+
+def _plate_fixed(chord, span, nq_x, nq_z, c0, U, theta):
+    """Zero-thickness plate pitched by a fixed angle theta about z,
+    translating at constant velocity U from c0."""
+    V, F = plate_mesh(chord, span, nq_x, nq_z)
+    ct, st = math.cos(theta), math.sin(theta)
+    R = np.array([[ct, -st, 0.0], [st, ct, 0.0], [0.0, 0.0, 1.0]])
+    c0 = np.asarray(c0, np.float64)
+    U = np.asarray(U, np.float64)
+    return Body("rigid", V, F, lambda t: rigid_coef(c0 + U * t, R, U, np.zeros(3)))
+
+
+# quads (m, n) of the batch plates for 2*m*n triangles
+_PLATE_QUADS = {320: (16, 10), 640: (20, 16), 1280: (32, 20), 2560: (40, 32), 5120: (64, 40)}
+
+
+def batch_sim(s: int, steps: int = 20) -> Workload:
+    """Simulation s of the batched workload (seed 4000 + s).
+
+    Fixed-spacing box: uniform spacing 1/32 in every direction, nx, nz drawn
+    from {32, 48, ..., 128} and ny from {32, 48, ..., 96} (multiples of 16, so
+    the transform radices are 2, 3, 5, 7); Lx = nx/32, Lz = nz/32, walls at
+    y = -Ly/2 and +Ly/2 with Ly = ny/32.  Re 100, dt 1e-3, Poiseuille flow of
+    centre velocity 1 plus a 0.01 perturbation.  One body, its type drawn
+    uniformly: a sphere (level 2..4, diameter 0.3..0.5), a plate (chord and
+    span 0.3..0.6, 320..5120 triangles, pitched by a fixed angle within +-15
+    deg) - both translating at a speed drawn from U[0, 1] in a random
+    direction - or a deforming closed body (the law of the large deforming
+    case, r0 0.15..0.25, level 2..4) at rest.  The centre is uniform in the
+    box with a wall clearance of at least r + h + 2 d0 + 20 dt |U|
+    (h = 2 sqrt(3) d0 the probe length)."""
+    rng = np.random.default_rng(4000 + s)
+    d0 = 1.0 / 32.0
+    nx = int(rng.choice(np.arange(32, 129, 16)))
+    nz = int(rng.choice(np.arange(32, 129, 16)))
+    ny = int(rng.choice(np.arange(32, 97, 16)))
+    lx, lz, ly = nx * d0, nz * d0, ny * d0
+    half = 0.5 * ly
+    yf = uniform_faces(ny, -half, half)
+    re, dt = 100.0, 1e-3
+    h = 2.0 * math.sqrt(3.0) * d0
+    kind = int(rng.integers(3))
+    speed = float(rng.uniform(0.0, 1.0))
+    dirn = rng.standard_normal(3)
+    dirn /= np.linalg.norm(dirn)
+    U = speed * dirn
+    if kind == 0:
+        level = int(rng.integers(2, 5))
+        r = 0.5 * float(rng.uniform(0.3, 0.5))
+    elif kind == 1:
+        chord = float(rng.uniform(0.3, 0.6))
+        span = float(rng.uniform(0.3, 0.6))
+        ntri = int(rng.choice(sorted(_PLATE_QUADS)))
+        theta = float(rng.uniform(-1.0, 1.0)) * math.pi / 12.0
+        r = 0.5 * max(chord, span)
+    else:
+        level = int(rng.integers(2, 5))
+        r0 = float(rng.uniform(0.15, 0.25))
+        r = r0 * 1.07
+        U = np.zeros(3)
+    clear = r + h + 2.0 * d0 + 20.0 * dt * float(np.linalg.norm(U))
+    c = np.array([rng.uniform(0.0, lx), rng.uniform(-half + clear, half - clear),
+                  rng.uniform(0.0, lz)])
+    if kind == 0:
+        body = _sphere_body(level, r, c, U)
+    elif kind == 1:
+        m, n = _PLATE_QUADS[ntri]
+        body = _plate_fixed(chord, span, m, n, c, U, theta)
+    else:
+        V, F = icosphere(level)
+        cc = tuple(c)
+        body = Body("deform", deform_vertex_data(V, r0), F,
+                    lambda t, cc=cc, r0=r0: deform_coef(t, cc, r0))
+    dpdx = -2.0 * 1.0 / (re * half * half)
+    return Workload(f"c4.{s}", nx, ny, nz, lx, lz, yf, re, dt, steps, 1.0, 0.01, 4000 + s,
+                    dpdx, [body], half=half)
+
+
+def batch(nsim: int = 64, steps: int = 20):
+    """The batched workload: simulations 0..nsim-1 of batch_sim."""
+    return [batch_sim(s, steps) for s in range(nsim)]
