@@ -155,6 +155,28 @@ __device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t T) {
   return b;  // unreachable for b < T
 }
 
+// XCD slab order for stencil sweeps over tiles (it, kt, j) of a
+// [j][k][i] field: XCD x (the blocks b with b % 8 == x) owns the band of
+// k-tiles [x nbz/8, (x+1) nbz/8) and walks it plane by plane, j slowest, so
+// the planes j-1, j, j+1 that a stencil touches are all recent in its own
+// L2 (a band of whole planes per XCD would need three planes of every field
+// at once, more than one L2 holds).  The grid has xcd_slab_blocks() blocks;
+// the padding blocks of XCDs with a narrower band get false.
+__device__ __forceinline__ bool xcd_slab_tile(int64_t b, int nbx, int nbz, int ny, int& it,
+                                              int& kt, int& j) {
+  const int x = (int)(b % NUM_XCD);
+  const int64_t r = b / NUM_XCD;
+  const int kt0 = (int)((int64_t)x * nbz / NUM_XCD);
+  const int kt1 = (int)((int64_t)(x + 1) * nbz / NUM_XCD);
+  const int64_t per_plane = (int64_t)nbx * (kt1 - kt0);
+  if (per_plane == 0 || r >= per_plane * ny) return false;
+  j = (int)(r / per_plane);
+  const int rem = (int)(r % per_plane);
+  kt = kt0 + rem / nbx;
+  it = rem % nbx;
+  return true;
+}
+
 __device__ __forceinline__ int find_body(const BodyDev* b, int nbody, int t) {
   int k = 0;
   while (k + 1 < nbody && t >= b[k + 1].toff) ++k;

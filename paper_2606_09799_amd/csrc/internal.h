@@ -97,6 +97,12 @@ struct FFTPlan {
   const float2* tw32; // the same, rounded to FP32
 };
 
+// blocks of a launch in the XCD slab order (geom.h, xcd_slab_tile): eight
+// bands of ceil(nbz/8) k-tiles, each walked over all ny planes
+inline int64_t xcd_slab_blocks(int nbx, int nbz, int ny) {
+  return 8 * (int64_t)nbx * ((nbz + 7) / 8) * ny;
+}
+
 // profiling hook (ctx.cpp): an event pair around each kernel launch when
 // profiling is enabled and the kernel name matches the filter
 struct Prof;
