@@ -10,7 +10,7 @@ the two share no code: the only common inputs are the seeded arrays built by
 the separate ``workloads`` module.
 
 Every function cites the passage of the paper it follows.  Points the paper
-leaves open are fixed by the readings documented in DESIGN.md ("Readings");
+leaves open are fixed by explicit readings;
 the code states each reading where it is applied.
 
 Modules

@@ -8,7 +8,7 @@ is the wall velocity at X^f and u^e the trilinear interpolation of the same
 velocity component at x^e.  h is twice the diagonal of the local cell
 (Sec. 3.1; 2 sqrt(3) Delta on a uniform grid).
 
-Readings (DESIGN.md): the local cell of a u/w node has height dy[j], that of
+Readings: the local cell of a u/w node has height dy[j], that of
 a v node dyc[j]; U inside a triangle is the barycentric interpolation of the
 vertex velocities; a node on the surface (|N| = 0) takes u^f = U; all u^f are
 computed from the unmodified field and written afterwards (Jacobi), and the

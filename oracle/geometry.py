@@ -8,7 +8,7 @@ Collision Detection, 2004, Sec. 5.1.5, restated below), N = x - X, and x is a
 forcing node if the scalar product of N with x_n - X is negative for at least
 one of the six same-lattice neighbours x_n.
 
-Readings of points the paper leaves open ("Readings"):
+Readings of points the paper leaves open:
   * a node lying on the surface (|N| = 0) is a forcing node (weight 0);
   * the bounding box is inflated by the largest neighbour spacing of the
     grid (plus one node), so culling never changes the set: the

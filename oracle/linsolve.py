@@ -2,7 +2,7 @@
 solver (paper Sec. 2: "tridiagonal systems ... solved using the Thomas
 algorithm").  The periodic directions give cyclic systems, solved here with
 the Sherman-Morrison correction of a Thomas solve (the paper names only
-Thomas; DESIGN.md, reading "cyclic solves").
+Thomas; the periodic lines are read as cyclic systems).
 
 Lines run along axis 0; any trailing axes are a batch.  a[i], b[i], c[i] are
 the sub-, main and super-diagonal of row i; for the cyclic solver a[0]

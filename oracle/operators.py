@@ -4,8 +4,9 @@ Eq. discrete_div for D; L_c = DG in Eq. elliptic; H in conservative form in
 Eq. NS_prov; App. A for the discrete divergence theorem).
 
 The paper names these operators but does not print their stencils on a
-stretched staggered grid; the stencils below are the reading documented in
-DESIGN.md ("Operators").  Periodic shifts use np.roll; walls are at the two
+stretched staggered grid; the stencils below are this implementation's
+reading of them (flux-form H with linear face interpolation in y, finite-
+volume Laplacian with the wall value at half a cell, D as Eq. discrete_div).  Periodic shifts use np.roll; walls are at the two
 y boundaries, where v = 0 and u = w = 0 (no-slip, stationary walls).
 """
 from __future__ import annotations
@@ -137,3 +138,13 @@ def conv_v(g, u, v, w):
 
 def conv(g, u, v, w):
     return conv_u(g, u, v, w), conv_v(g, u, v, w), conv_w(g, u, v, w)
+
+
+def kinetic_energy(g, u, v, w):
+    """Cell-centred kinetic energy e = u.u/2 of a staggered field (the e of
+    App. B): each component's square averaged over the two faces of the cell
+    normal to it (x and z periodic; the v wall faces hold 0)."""
+    eu = 0.5 * (u * u + xp(u) * xp(u))
+    ev = 0.5 * (v[:-1] * v[:-1] + v[1:] * v[1:])
+    ew = 0.5 * (w * w + zp(w) * zp(w))
+    return 0.5 * (eu + ev + ew)

@@ -59,7 +59,7 @@ def substage(g, fields, p, hprev, tags, verts, vel, tris, gamma, rho, dt, re, fe
     masks = masks_of(g, tags)
     fib = forcing.apply_ib(g, fields, list(zip(tags.idx, tags.tri)), verts, vel, tris)
     uhat, H = predictor.predictor(g, fib, p, hprev, masks, gamma, rho, alpha, dt, re, fext)
-    rhs, qF, _ = projection.mass_correction(g, uhat, tags.cb, alpha, dt, use_q)
+    rhs, qF, _ = projection.mass_correction(g, uhat, tags.cb, alpha, dt, use_q, p)
     phi = poisson.solve(g, rhs)
     new, pn = projection.project(g, uhat, p, phi, alpha, dt, re)
     if diag is not None:
