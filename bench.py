@@ -68,10 +68,15 @@ def algorithmic_bytes(name, nx, ny, nz, form="fp64"):
     return table.get(name)
 
 
-# kernel name in the library's event profile -> kernel symbol in rocprofv3
-COUNTER_NAME = {"rhs": "k_rhs", "pois_fftx_fwd": "k_fftx_fwd", "pois_fftz_fwd": "k_fftz<false>",
-                "pois_fftz_inv": "k_fftz<true>", "pois_tri_y": "k_tri_y",
-                "pois_fftx_inv": "k_fftx_inv", "project": "k_project"}
+# kernel name in the library's event profile -> kernel name in the rocprofv3
+# summaries (template arguments of the storage type per form)
+def counter_name(kernel, form):
+    T, C = ("double", "double2") if form == "fp64" else ("float", "float2")
+    return {"rhs": f"k_rhs<{T}>", "adi_x": f"k_line<{T}>", "adi_z": f"k_line<{T}>",
+            "adi_y": f"k_line<{T}>", "pois_fftx_fwd": f"k_fftx_fwd<{C}>",
+            "pois_fftz_fwd": f"k_fftz<{C}, false>", "pois_fftz_inv": f"k_fftz<{C}, true>",
+            "pois_tri_y": f"k_tri_y<{C}>", "pois_fftx_inv": f"k_fftx_inv<{C}>",
+            "project": f"k_project<{T}>"}.get(kernel)
 
 
 def csrc_sha():
@@ -91,8 +96,9 @@ def measured_traffic(kernel, workload, form="fp64"):
     no summary exists for this workload and form or the kernel sources
     changed since."""
     path = os.path.join(ROOT, "profiles", f"{workload}_{form}_traffic.json")
-    name = COUNTER_NAME.get(kernel)
-    if not name or not os.path.exists(path):
+    name = counter_name(kernel, form)
+    if kernel.startswith("adi_") or not name or not os.path.exists(path):
+        # the three line-solve directions share one kernel symbol
         return None
     with open(path) as f:
         t = json.load(f)
@@ -122,6 +128,10 @@ def cpu_baseline(wl):
                       f"one thread)"}
 
 
+def progress(msg):
+    print(f"bench.py: {msg}", file=sys.stderr, flush=True)
+
+
 def run_form(args, wl, form, dev):
     """Times args.steps full steps of workload wl in one precision form.
     Returns (elapsed s, warm-up per-kernel profile, dominant kernel, its
@@ -132,6 +142,7 @@ def run_form(args, wl, form, dev):
 
     ctx = ibm.Context(wl.nx, wl.ny, wl.nz, wl.lx, wl.lz, wl.y_faces, wl.re, wl.dpdx,
                       precision=form)
+    progress(f"{form}: context created, generating the initial field")
     u0, v0, w0 = wl.fields()
     T = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
     u, v, w = T(u0), T(v0), T(w0)
@@ -144,6 +155,7 @@ def run_form(args, wl, form, dev):
         vel = torch.empty_like(xyz)
         dbodies.append((b, ref, xyz, vel, T(b.tris.astype(np.int32))))
     bodies = [ibm.Body(x, vv, tr) for (_, _, x, vv, tr) in dbodies]
+    progress(f"{form}: state on the device, warming up")
 
     def one_step(s):
         tt = s * wl.dt
@@ -162,6 +174,7 @@ def run_form(args, wl, form, dev):
     dominant = max((k for k in prof if algorithmic_bytes(k, wl.nx, wl.ny, wl.nz, form)),
                    key=lambda k: prof[k][1], default=None)
     stats = ibm.ibm_refine_stats(ctx, reset=True) if form == "mixed" else None
+    progress(f"{form}: warm-up done, timing {args.steps} steps")
     # timed region: events only around the dominant kernel
     ibm.ibm_profile(ctx, True, dominant)
     torch.cuda.synchronize()
@@ -170,6 +183,7 @@ def run_form(args, wl, form, dev):
         one_step(s)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
+    progress(f"{form}: {el / args.steps * 1e3:.3f} ms per step")
     dom = ibm.ibm_profile_read(ctx)
     ibm.ibm_profile(ctx, False, None)
     if form == "mixed":
@@ -226,6 +240,7 @@ def run_batched(args, dev, nsim):
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
         out[name] = (cells * 2 * args.steps / el, el / args.steps * 1e3)
+        progress(f"batched {name}: {el / args.steps * 1e3:.3f} ms per step")
     flags = batch.check()
     if flags:
         print(f"bench.py: device flags {flags} after the batched run", file=sys.stderr)
@@ -307,6 +322,8 @@ def main():
             bb.copy_(a)
         torch.cuda.synchronize()
         copy_ref = {"bytes_read": nb * 8, "bytes_written": nb * 8, "launches": 3}
+    if not args.no_cpu_baseline:
+        progress("timing the CPU oracle on one step")
     cpu = None if args.no_cpu_baseline else cpu_baseline(wl)
     out = {
         "metric": METRIC, "value": head["value"], "unit": "cell-steps/s", "n_gpus": 1,

@@ -68,6 +68,12 @@ extern "C" {
 #define IBM_RK2CN 0
 #define IBM_AB2CN 1
 
+/* shape of the sinks/sources q on the fluid cells (ibm_opts.use_q) */
+#define IBM_Q_NONE 0    /* standard projection, D u = 0 everywhere */
+#define IBM_Q_UNIFORM 1 /* uniform q_F (Sec. 3.2, Eq. q_F): mass */
+#define IBM_Q_ENERGY 2  /* q_F = c0 + c1 (p - e) (App. B, Eq. unif_shape):
+                           mass and kinetic energy in the inviscid limit */
+
 typedef struct ibm_ctx ibm_ctx;
 
 /* Grid (paper Sec. 2, Fig. 1).  y_faces: host array of ny+1 strictly
@@ -82,8 +88,12 @@ typedef struct {
 
 /* Options.  dpdx is the mean pressure gradient dP/dx; the driving volume
  * force is -dpdx along x.  force_cap bounds each forcing list and the C_B
- * list (0 = automatic: max(65536, cells/16)).  use_q = 1 applies the
- * consistent mass correction of Sec. 3.2, 0 the standard projection.
+ * list (0 = automatic: max(65536, cells/16)).  use_q: IBM_Q_UNIFORM applies
+ * the consistent mass correction of Sec. 3.2, IBM_Q_ENERGY its mass- and
+ * energy-conserving shape of App. B (p = the sub-stage's pressure, e = the
+ * cell-centred kinetic energy of u_hat, each component's square averaged
+ * over the two faces; a constant p - e on C_F falls back to the uniform
+ * shape), IBM_Q_NONE the standard projection.
  * Mixed form only: refine_max (0..16, 0 = 3) bounds the FP64-residual
  * refinements of one Poisson solve, which stop once max|rhs - L_c phi| *
  * alpha_dt <= refine_tol (0 = 1e-11; alpha_dt = 1 for poisson_solve); after
@@ -197,10 +207,13 @@ int ibm_viscous(ibm_ctx* ctx, const void* p, const void* const* h_prev,
 
 /* Consistent mass correction (paper Eqs. mod_div, q_boundary, q_F,
  * elliptic_mod): q_F = -(sum_{C_B} D u dV)/|C_F| from the last ibm_tag, and
- * rhs = (D u - q_F)/alpha_dt on C_F, 0 on C_B (use_q = 0: rhs = D u/alpha_dt).
- * rhs: dev ny*nz*nx; qf: dev f64[1] (may be NULL). */
+ * rhs = (D u - q_F)/alpha_dt on C_F, 0 on C_B (IBM_Q_NONE: rhs =
+ * D u/alpha_dt).  IBM_Q_ENERGY: q_F = c0 + c1 (p - e) (App. B), p required
+ * (dev f32/f64), the two coefficients from five fixed-order sums over all
+ * cells.  rhs: dev f64 ny*nz*nx; qf: dev f64[1] (q_F) or f64[2] (c0, c1)
+ * (may be NULL); p: NULL unless IBM_Q_ENERGY. */
 int ibm_mass_rhs(ibm_ctx* ctx, const double* u, const double* v, const double* w,
-                 double alpha_dt, double* rhs, double* qf);
+                 const void* p, double alpha_dt, double* rhs, double* qf);
 
 /* Direct solve of L_c phi = rhs (paper Eq. elliptic / elliptic_mod; L_c = D G
  * with homogeneous Neumann walls): real FFT in x, complex FFT in z,

@@ -34,7 +34,7 @@ struct LineK {
   const uint32_t* mask;
   T* sa;              // scratch for segments holding identity rows
   T* sc;
-  const T* tab;       // mask-free elimination tables [4][P][LMAX]
+  const T* tab;       // mask-free elimination tables [LINE_NTAB][P][LMAX]
   int n, P, L, r;     // rows, segments, base length, segments with L+1 rows
   int cyc;
   T a, b, c;          // constant coefficients (x, z)
@@ -60,8 +60,6 @@ __device__ __forceinline__ void row_coef(const LineK<T>& K, int i, T& a, T& b, T
   }
 }
 
-template <typename T>
-__device__ __forceinline__ T row_a(const LineK<T>& K, int i) { return K.A ? K.A[i] : K.a; }
 
 // serial solve of one line's P x P cyclic separator system (Sherman-
 // Morrison on top of Thomas), for cyclic lines whose segment count is not a
@@ -101,9 +99,15 @@ __global__ __launch_bounds__(256) void k_line(LineK<T> K) {
   T* lds = reinterpret_cast<T*>(ldsraw);
   const int tid = threadIdx.x;
   const int P = K.P;
-  T* tabs = lds;                         // 4 * P * LMAX
-  T* sm = lds + 4 * P * LMAX;            // 8 * P * lines per block
-  for (int q = tid; q < 4 * P * LMAX; q += blockDim.x) {
+  T* tabs = lds;                         // LINE_NTAB * P * LMAX
+  T* sm = lds + LINE_NTAB * P * LMAX;    // 8 * P * lines per block
+  // x sweep: the block's rows are staged through LDS (coalesced loads and
+  // stores; each thread then reads its segment from LDS), one pad slot every
+  // 16 values so that consecutive segments fall on different banks; the row
+  // buffer is reused for the separator arrays once the rows are in registers
+  T* rowbuf = sm;
+  const int RS = K.n + (K.n >> 4) + 1;
+  for (int q = tid; q < LINE_NTAB * P * LMAX; q += blockDim.x) {
     const int qq = q / (P * LMAX), rem = q % (P * LMAX), ss = rem / LMAX, ee = rem % LMAX;
     tabs[(qq * LMAX + ee) * P + ss] = K.tab[q];
   }
@@ -140,6 +144,20 @@ __global__ __launch_bounds__(256) void k_line(LineK<T> K) {
   const int lo = s * K.L + (s < K.r ? s : K.r);
   const int len = K.L + (s < K.r ? 1 : 0);
   const int m = len - 1;  // interior rows; row lo+m is the separator
+  // x sweep: rows of this block and their staging
+  int xrows = 0;
+  const T* xsrc = nullptr;
+  if (K.mode == 0) {
+    const int64_t l0 = (int64_t)blockIdx.x * K.tl;
+    const int64_t nl = (int64_t)K.nj * K.nz;
+    xrows = (int)((l0 + K.tl <= nl) ? K.tl : nl - l0);
+    xsrc = K.d + ((int64_t)K.j0 * K.nz + l0) * K.n;
+    for (int r = 0; r < xrows; ++r)
+      for (int c = tid; c < K.n; c += blockDim.x)
+        rowbuf[r * RS + c + (c >> 4)] = xsrc[(int64_t)r * K.n + c];
+    __syncthreads();
+  }
+  auto xpos = [&](int e) { return lb * RS + (lo + e) + ((lo + e) >> 4); };
   // table entry (q, e) of this segment; layout [q][e][s] keeps the lanes of
   // consecutive segments on consecutive LDS words
 #define TAB(q, e) tabs[((q) * LMAX + (e)) * P + s]
@@ -152,7 +170,7 @@ __global__ __launch_bounds__(256) void k_line(LineK<T> K) {
     T raw[LMAX];
 #pragma unroll
     for (int e = 0; e < LMAX; ++e)
-      if (e < len) raw[e] = K.d[base + (int64_t)(lo + e) * es];
+      if (e < len) raw[e] = (K.mode == 0) ? rowbuf[xpos(e)] : K.d[base + (int64_t)(lo + e) * es];
     if (es == 1) {  // contiguous row: the segment's bits span at most two words
       const int64_t b0 = base + lo;
       const uint32_t w0 = K.mask[b0 >> 5];
@@ -177,7 +195,7 @@ __global__ __launch_bounds__(256) void k_line(LineK<T> K) {
 #pragma unroll
       for (int e = 0; e < LMAX - 1; ++e)
         if (e < m) {
-          dt = (dd[e] - row_a(K, lo + e) * dt) * TAB(0, e);
+          dt = (dd[e] - TAB(4, e) * dt) * TAB(0, e);
           dd[e] = dt;
         }
       T dh = 0;
@@ -250,6 +268,7 @@ __global__ __launch_bounds__(256) void k_line(LineK<T> K) {
   // LDS: 8 arrays of P doubles per line; neighbouring lanes (consecutive
   // lines in the z/y sweeps, consecutive segments in the x sweep) take
   // consecutive words
+  if (K.mode == 0) __syncthreads();  // the row buffer becomes the separator arrays
   const int TL = K.tl;
   const bool rowmajor = (K.mode == 0);
   auto at = [&](int f, int seg) -> T& {
@@ -342,11 +361,27 @@ __global__ __launch_bounds__(256) void k_line(LineK<T> K) {
         T x = zr;
         if (e < m) x = fast ? dd[e] - TAB(2, e) * zl - TAB(3, e) * zr
                             : dd[e] - K.sa[o] * zl - K.sc[o] * zr;
-        if (K.mode == 2)
+        if (K.mode == 0) {
+          if (e < m) dd[e] = x; else dz = x;
+        } else if (K.mode == 2) {
           K.u[o] += (double)x;
-        else
+        } else {
           K.d[o] = x;
+        }
       }
+  }
+  if (K.mode == 0) {
+    __syncthreads();  // every thread has read the separator values
+    if (valid) {
+#pragma unroll
+      for (int e = 0; e < LMAX; ++e)
+        if (e < len) rowbuf[xpos(e)] = (e < m) ? dd[e] : dz;
+    }
+    __syncthreads();
+    T* xdst = K.d + (xsrc - K.d);
+    for (int r = 0; r < xrows; ++r)
+      for (int c = tid; c < K.n; c += blockDim.x)
+        xdst[(int64_t)r * K.n + c] = rowbuf[r * RS + c + (c >> 4)];
   }
 }
 
@@ -365,7 +400,12 @@ static void launch_line(Prof* pf, hipStream_t s, LineK<T> K, const char* name) {
     threads = K.tl * K.P;
     grid = dim3((K.nx + K.tl - 1) / K.tl, K.mode == 1 ? K.nj : K.nz);
   }
-  const size_t shm = sizeof(T) * (4 * (size_t)K.P * LMAX + 8 * (size_t)K.P * K.tl);
+  size_t work = 8 * (size_t)K.P * K.tl;  // separator arrays
+  if (K.mode == 0) {                      // x sweep: also the staged rows
+    const size_t rows = (size_t)K.tl * (K.n + (K.n >> 4) + 1);
+    if (rows > work) work = rows;
+  }
+  const size_t shm = sizeof(T) * (LINE_NTAB * (size_t)K.P * LMAX + work);
   IBM_LAUNCH(pf, name, s, k_line<T><<<grid, threads, shm, s>>>(K));
 }
 

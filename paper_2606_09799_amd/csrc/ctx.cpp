@@ -86,8 +86,9 @@ struct ibm_ctx {
   std::vector<BodyDev> last_bodies;
   int ntri = 0;
   static constexpr int NSLOT = 8;
-  BodyDev* dslots = nullptr;  // NSLOT x 64 descriptors (device)
-  BodyDev* hslots = nullptr;  // NSLOT x 64 descriptors (pinned host)
+  static constexpr int MAXB = 128;  // bodies per context
+  BodyDev* dslots = nullptr;  // NSLOT x MAXB descriptors (device)
+  BodyDev* hslots = nullptr;  // NSLOT x MAXB descriptors (pinned host)
   hipEvent_t slot_ev[NSLOT] = {};
   bool slot_used[NSLOT] = {};
   int cur_slot = -1;
@@ -264,12 +265,13 @@ static int build_tables(ibm_ctx* c, double beta) {
   };
   // elimination tables of the partitioned solve for mask-free segments:
   // [0] 1/pivot, [1] c~ (forward), [2] a^ and [3] c^ (responses of every
-  // interior row to the left and right separators)
+  // interior row to the left and right separators), [4] the row's
+  // sub-diagonal
   auto segtab = [&](int n, bool cyc, const double* A, const double* B, const double* C,
                     std::vector<double>& out) {
     int P, L, r;
     line_plan(n, cyc, &P, &L, &r);
-    std::vector<double> t(4 * (size_t)P * LINE_LMAX, 0.0);
+    std::vector<double> t(LINE_NTAB * (size_t)P * LINE_LMAX, 0.0);
     for (int s = 0; s < P; ++s) {
       const int lo = s * L + std::min(s, r);
       const int m = L + (s < r ? 1 : 0) - 1;
@@ -282,6 +284,7 @@ static int build_tables(ibm_ctx* c, double beta) {
         ct = C[i] * inv;
         t[(0 * P + s) * LINE_LMAX + e] = inv;
         t[(1 * P + s) * LINE_LMAX + e] = ct;
+        t[(4 * P + s) * LINE_LMAX + e] = A[i];
         va[e] = at;
         vc[e] = ct;
       }
@@ -404,7 +407,9 @@ int ibm_create(const ibm_grid* gr, const ibm_opts* o, void* stream, ibm_ctx** ou
   if (o->refine_max < 0 || o->refine_max > 16 || o->refine_tol < 0 || !(o->refine_tol == o->refine_tol))
     FAIL(IBM_EINVAL, "refine_max must be 0..16 and refine_tol >= 0");
   if (gr->ny > 8192) FAIL(IBM_EINVAL, "ny above 8192");
+  if (gr->nx > 1024 || gr->nz > 1024) FAIL(IBM_EINVAL, "nx and nz at most 1024");
   if (o->scheme != IBM_RK2CN && o->scheme != IBM_AB2CN) FAIL(IBM_EINVAL, "unknown scheme");
+  if (o->use_q < IBM_Q_NONE || o->use_q > IBM_Q_ENERGY) FAIL(IBM_EINVAL, "unknown use_q");
   for (int j = 0; j < gr->ny; ++j)
     if (!(gr->y_faces[j + 1] > gr->y_faces[j])) FAIL(IBM_EINVAL, "y_faces not strictly increasing");
   ibm_ctx* c = new ibm_ctx();
@@ -530,8 +535,8 @@ int ibm_create(const ibm_grid* gr, const ibm_opts* o, void* stream, ibm_ctx** ou
   TRY(dalloc(c, &tb.count, 4));
   TRY(dalloc(c, &tb.block_sums, maxw / 1024 + 2));
   TRY(dalloc(c, &c->force_vals, 3 * tb.cap));
-  TRY(dalloc(c, &c->dslots, (int64_t)ibm_ctx::NSLOT * 64));
-  if (hipHostMalloc((void**)&c->hslots, sizeof(BodyDev) * ibm_ctx::NSLOT * 64) != hipSuccess) {
+  TRY(dalloc(c, &c->dslots, (int64_t)ibm_ctx::NSLOT * ibm_ctx::MAXB));
+  if (hipHostMalloc((void**)&c->hslots, sizeof(BodyDev) * ibm_ctx::NSLOT * ibm_ctx::MAXB) != hipSuccess) {
     c->hslots = nullptr;
     TRY(IBM_ENOMEM);
   }
@@ -558,8 +563,8 @@ int ibm_create(const ibm_grid* gr, const ibm_opts* o, void* stream, ibm_ctx** ou
     TRY(dalloc(c, &c->psum, (int64_t)ny * nz));
   }
   TRY(dalloc(c, &c->rstats, 3));
-  TRY(dalloc(c, &c->partial, 512));
-  TRY(dalloc(c, &c->qf, 1));
+  TRY(dalloc(c, &c->partial, 5 * 512));  // block partials of the mass sums
+  TRY(dalloc(c, &c->qf, 2));              // q_F, or (c0, c1) of the energy shape
   TRY(dalloc(c, &c->flags, 1));
   {
     int P, L, r, segs = 0;
@@ -569,7 +574,7 @@ int ibm_create(const ibm_grid* gr, const ibm_opts* o, void* stream, ibm_ctx** ou
     segs += P;
     line_plan(ny, false, &P, &L, &r);
     segs += 2 * P;
-    c->tabcap = 4 * (int64_t)(nx + nz) + 10 * (int64_t)ny + 4 * (int64_t)segs * LINE_LMAX;
+    c->tabcap = 4 * (int64_t)(nx + nz) + 10 * (int64_t)ny + LINE_NTAB * (int64_t)segs * LINE_LMAX;
     TRY(dalloc(c, &c->tabmem, c->tabcap));
     if (c->fp32) TRY(dalloc(c, &c->tabmem32, c->tabcap));
   }
@@ -612,7 +617,7 @@ int ibm_create(const ibm_grid* gr, const ibm_opts* o, void* stream, ibm_ctx** ou
   launch_fill_u32(nullptr, c->stream, tb.cb_mask, tb.nwords_cb, 0u);
   launch_fill_u32(nullptr, c->stream, c->flags, 1, 0u);
   launch_fill_u64(nullptr, c->stream, reinterpret_cast<u64*>(tb.count), 4, 0ull);
-  launch_fill_f64(nullptr, c->stream, c->qf, 1, 0.0);
+  launch_fill_f64(nullptr, c->stream, c->qf, 2, 0.0);
   launch_fill_f64(nullptr, c->stream, c->rstats, 3, 0.0);
   if (hipStreamSynchronize(c->stream) != hipSuccess || hipGetLastError() != hipSuccess) {
     free_all(c);
@@ -659,7 +664,7 @@ int ibm_body_deform(ibm_ctx* c, const double* data, int32_t nv, const double* co
 
 static int set_bodies(ibm_ctx* c, const ibm_body* b, int32_t nb) {
   if (nb < 0 || (nb > 0 && !b)) FAIL(IBM_EINVAL, "bad body list");
-  if (nb > 64) FAIL(IBM_EINVAL, "at most 64 bodies per context");
+  if (nb > ibm_ctx::MAXB) FAIL(IBM_EINVAL, "at most 128 bodies per context");
   c->bodies.clear();
   int64_t off = 0;
   for (int i = 0; i < nb; ++i) {
@@ -693,19 +698,19 @@ static int upload_bodies(ibm_ctx* c) {
     return IBM_OK;
   }
   if (c->cur_slot >= 0 && c->last_bodies == c->bodies) {
-    c->d_bodies = c->dslots + (size_t)c->cur_slot * 64;
+    c->d_bodies = c->dslots + (size_t)c->cur_slot * ibm_ctx::MAXB;
     return IBM_OK;
   }
   const int k = (c->cur_slot + 1) % ibm_ctx::NSLOT;
   if (c->slot_used[k]) HIPCHK(hipEventSynchronize(c->slot_ev[k]));
-  std::memcpy(c->hslots + (size_t)k * 64, c->bodies.data(), n * sizeof(BodyDev));
-  HIPCHK(hipMemcpyAsync(c->dslots + (size_t)k * 64, c->hslots + (size_t)k * 64,
+  std::memcpy(c->hslots + (size_t)k * ibm_ctx::MAXB, c->bodies.data(), n * sizeof(BodyDev));
+  HIPCHK(hipMemcpyAsync(c->dslots + (size_t)k * ibm_ctx::MAXB, c->hslots + (size_t)k * ibm_ctx::MAXB,
                         n * sizeof(BodyDev), hipMemcpyHostToDevice, c->stream));
   HIPCHK(hipEventRecord(c->slot_ev[k], c->stream));
   c->slot_used[k] = true;
   c->cur_slot = k;
   c->last_bodies = c->bodies;
-  c->d_bodies = c->dslots + (size_t)k * 64;
+  c->d_bodies = c->dslots + (size_t)k * ibm_ctx::MAXB;
   return IBM_OK;
 }
 
@@ -806,14 +811,23 @@ int ibm_viscous(ibm_ctx* c, const void* p, const void* const* h_prev, void* cons
   return viscous(c, p, h_prev, h_out, gamma, rho, dt, u, v, w);
 }
 
-int ibm_mass_rhs(ibm_ctx* c, const double* u, const double* v, const double* w, double alpha_dt,
-                 double* rhs, double* qf) {
+int ibm_mass_rhs(ibm_ctx* c, const double* u, const double* v, const double* w, const void* p,
+                 double alpha_dt, double* rhs, double* qf) {
   if (!c || !u || !v || !w || !rhs || !(alpha_dt > 0)) FAIL(IBM_EINVAL, "ibm_mass_rhs: bad argument");
-  launch_mass(&c->prof, c->stream, c->g, u, v, w, c->tb.cb, c->tb.count, c->tb.cap, c->vtot,
-              c->opts.use_q, c->partial, c->qf, c->flags);
-  launch_mass_rhs(&c->prof, c->stream, c->g, u, v, w, c->opts.use_q ? c->tb.cb_mask : nullptr,
-                  c->qf, 1.0 / alpha_dt, rhs);
-  if (qf) HIPCHK(hipMemcpyAsync(qf, c->qf, sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+  if (c->opts.use_q == IBM_Q_ENERGY) {
+    if (!p) FAIL(IBM_EINVAL, "ibm_mass_rhs: the energy-conserving shape needs p");
+    launch_mass_energy(&c->prof, c->stream, c->g, u, v, w, p, c->fp32, c->tb.cb_mask, c->partial,
+                       c->qf, c->flags);
+    launch_mass_rhs_energy(&c->prof, c->stream, c->g, u, v, w, p, c->fp32, c->tb.cb_mask, c->qf,
+                           1.0 / alpha_dt, rhs);
+  } else {
+    launch_mass(&c->prof, c->stream, c->g, u, v, w, c->tb.cb, c->tb.count, c->tb.cap, c->vtot,
+                c->opts.use_q, c->partial, c->qf, c->flags);
+    launch_mass_rhs(&c->prof, c->stream, c->g, u, v, w, c->opts.use_q ? c->tb.cb_mask : nullptr,
+                    c->qf, 1.0 / alpha_dt, rhs);
+  }
+  const size_t nq = (c->opts.use_q == IBM_Q_ENERGY) ? 2 : 1;
+  if (qf) HIPCHK(hipMemcpyAsync(qf, c->qf, nq * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
   return launch_status();
 }
 
@@ -845,7 +859,7 @@ static PoissonArgs pargs(ibm_ctx* c) {
 int poisson_solve(ibm_ctx* c, const double* rhs, double* phi) {
   if (!c || !rhs || !phi) FAIL(IBM_EINVAL, "poisson_solve: bad argument");
   launch_poisson(&c->prof, c->stream, c->g, pargs(c), rhs, nullptr, nullptr, nullptr, nullptr,
-                 nullptr, 1.0, phi);
+                 nullptr, nullptr, 1.0, phi);
   return launch_status();
 }
 
@@ -881,10 +895,16 @@ int ibm_step(ibm_ctx* c, ibm_state* s, const ibm_body* b, int32_t nb, double dt)
                  c->force_vals, c->flags);
     rc = viscous(c, s->p, sb.hprev, sb.hout, sb.gamma, sb.rho, dt, s->u, s->v, s->w);
     if (rc) return rc;
-    launch_mass(&c->prof, c->stream, c->g, s->u, s->v, s->w, c->tb.cb, c->tb.count, c->tb.cap,
-                c->vtot, c->opts.use_q, c->partial, c->qf, c->flags);
+    const bool energy = c->opts.use_q == IBM_Q_ENERGY;
+    if (energy)
+      launch_mass_energy(&c->prof, c->stream, c->g, s->u, s->v, s->w, s->p, c->fp32,
+                         c->tb.cb_mask, c->partial, c->qf, c->flags);
+    else
+      launch_mass(&c->prof, c->stream, c->g, s->u, s->v, s->w, c->tb.cb, c->tb.count, c->tb.cap,
+                  c->vtot, c->opts.use_q, c->partial, c->qf, c->flags);
     launch_poisson(&c->prof, c->stream, c->g, pargs(c), nullptr, s->u, s->v, s->w,
-                   c->opts.use_q ? c->tb.cb_mask : nullptr, c->qf, 1.0 / (alpha * dt), c->phi);
+                   c->opts.use_q ? c->tb.cb_mask : nullptr, c->qf, energy ? s->p : nullptr,
+                   1.0 / (alpha * dt), c->phi);
     launch_project(&c->prof, c->stream, c->g, c->phi, alpha * dt, c->opts.re, s->u, s->v, s->w,
                    s->p, c->fp32);
     rc = launch_status();

@@ -55,7 +55,7 @@ struct CyclicTab {
   double a, b, c;        // constant sub/main/super diagonal
   double ratio;          // beta_corner / gamma
   double fden_inv;       // 1 / (1 + z_0 + ratio z_{n-1})
-  const double* seg;     // partitioned-solve tables [4][P][LINE_LMAX]
+  const double* seg;     // partitioned-solve tables [LINE_NTAB][P][LINE_LMAX]
   const float* seg32;    // the same tables in FP32 (mixed form)
 };
 
@@ -67,7 +67,7 @@ struct YTab {
   const double* c;   // super-diagonal
   const double* cp;  // Thomas c' of the mask-free system
   const double* inv; // 1/pivot of the mask-free system
-  const double* seg; // partitioned-solve tables [4][P][LINE_LMAX]
+  const double* seg; // partitioned-solve tables [LINE_NTAB][P][LINE_LMAX]
   // FP32 copies of a, b, c and seg (mixed form)
   const float *a32, *b32, *c32, *seg32;
   int n, j0;
@@ -78,6 +78,7 @@ struct YTab {
 // the others L); cyclic lines use at least 3 segments.  Shared by the
 // kernels and the host code that builds their tables.
 constexpr int LINE_LMAX = 16;
+constexpr int LINE_NTAB = 5;  // tables per segment row (see the partitioned solve)
 inline void line_plan(int n, bool cyc, int lmax, int* P, int* L, int* r) {
   int p = (n + lmax - 1) / lmax;
   if (cyc && p < 3) p = 3;
@@ -184,6 +185,17 @@ void launch_mass_rhs(Prof* pf, hipStream_t s, const GridView& g, const double* u
                      const double* w, const uint32_t* cb_mask, const double* qf,
                      double inv_adt, double* rhs);
 
+// mass- and energy-conserving q_F (App. B): qcoef[0..1] = (c0, c1) with
+// q_F = c0 + c1 (p - e); partial: 5 * 512 doubles; p: FP64, or FP32 when fp32
+void launch_mass_energy(Prof* pf, hipStream_t s, const GridView& g, const double* u,
+                        const double* v, const double* w, const void* p, int fp32,
+                        const uint32_t* cb_mask, double* partial, double* qcoef,
+                        uint32_t* flags);
+void launch_mass_rhs_energy(Prof* pf, hipStream_t s, const GridView& g, const double* u,
+                            const double* v, const double* w, const void* p, int fp32,
+                            const uint32_t* cb_mask, const double* qcoef, double inv_adt,
+                            double* rhs);
+
 // poisson.hip
 struct PoissonArgs {
   const FFTPlan* px;   // length nx (host copy of the plan, tables on device)
@@ -209,10 +221,13 @@ struct PoissonArgs {
   uint32_t* flags;
 };
 // rhs from an array (rhs != NULL) or formed on the fly from the velocity
-// (rhs == NULL): (D u - q_F)/alpha_dt on C_F, 0 on C_B
+// (rhs == NULL): (D u - q)/alpha_dt on C_F, 0 on C_B, with q = qf[0], or
+// q = qf[0] + qf[1] (p - e) when p != NULL (the energy-conserving shape; p
+// in the precision of the spectrum)
 void launch_poisson(Prof* pf, hipStream_t s, const GridView& g, const PoissonArgs& a,
                     const double* rhs, const double* u, const double* v, const double* w,
-                    const uint32_t* cb_mask, const double* qf, double inv_adt, double* phi);
+                    const uint32_t* cb_mask, const double* qf, const void* p, double inv_adt,
+                    double* phi);
 
 // project.hip
 // p: FP64, or FP32 when fp32 is set

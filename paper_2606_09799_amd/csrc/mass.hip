@@ -106,6 +106,160 @@ __global__ __launch_bounds__(256) void k_mass_rhs(GridView g, const double* __re
                                                    : (div_at(g, u, v, w, cell) - q) * inv_adt;
 }
 
+// Mass- and energy-conserving shape of q_F (paper App. B, Eq. unif_shape):
+// q_F = c0 + c1 (p - e) on C_F with r = p - e (e the cell-centred kinetic
+// energy of u_hat: each component's square averaged over the two faces),
+//   S_i = sum_{C_F} r^i dV, A = sum_{C_B} D u dV, B = sum_{C_B} r D u dV,
+//   c0 = (-A S2 + B S1)/C, c1 = (A S1 - B S0)/C, C = S0 S2 - S1^2;
+// C vanishes only when r is constant on C_F (the two constraints coincide):
+// then the uniform shape c0 = -A/S0, c1 = 0.  The five sums are dense
+// (every cell), taken in a fixed two-level order (fixed chunks per block, a
+// fixed tree inside each block, then the block partials in order).
+constexpr int EB = 512;   // blocks of the first level
+
+__device__ __forceinline__ double kin_at(const GridView& g, const double* u, const double* v,
+                                         const double* w, int64_t cell) {
+  const int64_t plane = (int64_t)g.nz * g.nx;
+  const int i = (int)(cell % g.nx);
+  const int k = (int)((cell / g.nx) % g.nz);
+  const int j = (int)(cell / plane);
+  const int ip = (i + 1 == g.nx) ? 0 : i + 1;
+  const int kp = (k + 1 == g.nz) ? 0 : k + 1;
+  const int64_t row = (int64_t)j * plane + (int64_t)k * g.nx;
+  const double u0 = u[cell], u1 = u[row + ip];
+  const double v0 = v[cell], v1 = v[cell + plane];
+  const double w0 = w[cell], w1 = w[(int64_t)j * plane + (int64_t)kp * g.nx + i];
+  const double eu = 0.5 * (u0 * u0 + u1 * u1);
+  const double ev = 0.5 * (v0 * v0 + v1 * v1);
+  const double ew = 0.5 * (w0 * w0 + w1 * w1);
+  return 0.5 * ((eu + ev) + ew);
+}
+
+template <typename T>
+__global__ __launch_bounds__(MT) void k_energy_partial(GridView g, const double* __restrict__ u,
+                                                       const double* __restrict__ v,
+                                                       const double* __restrict__ w,
+                                                       const T* __restrict__ p,
+                                                       const uint32_t* __restrict__ cb_mask,
+                                                       double* __restrict__ partial) {
+  __shared__ double s[5][MT];
+  const int64_t ncell = (int64_t)g.nx * g.ny * g.nz;
+  const int64_t chunk = (ncell + EB - 1) / EB;
+  const int64_t lo = blockIdx.x * chunk;
+  const int64_t hi = (lo + chunk < ncell) ? lo + chunk : ncell;
+  const int64_t plane = (int64_t)g.nz * g.nx;
+  const double dxdz = g.dx * g.dz;
+  double S0 = 0.0, S1 = 0.0, S2 = 0.0, A = 0.0, B = 0.0;
+  for (int64_t cell = lo + threadIdx.x; cell < hi; cell += MT) {
+    const double dV = dxdz * g.dy[(int)(cell / plane)];
+    const double r = (double)p[cell] - kin_at(g, u, v, w, cell);
+    if (test_bit(cb_mask, cell)) {
+      const double D = div_at(g, u, v, w, cell);
+      A += D * dV;
+      B += (r * D) * dV;
+    } else {
+      S0 += dV;
+      S1 += r * dV;
+      S2 += (r * r) * dV;
+    }
+  }
+  s[0][threadIdx.x] = S0;
+  s[1][threadIdx.x] = S1;
+  s[2][threadIdx.x] = S2;
+  s[3][threadIdx.x] = A;
+  s[4][threadIdx.x] = B;
+  __syncthreads();
+  for (int off = MT / 2; off > 0; off >>= 1) {
+    if (threadIdx.x < off)
+      for (int q = 0; q < 5; ++q) s[q][threadIdx.x] += s[q][threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x < 5) partial[5 * blockIdx.x + threadIdx.x] = s[threadIdx.x][0];
+}
+
+__global__ __launch_bounds__(EB) void k_energy_final(const double* __restrict__ partial,
+                                                     double* __restrict__ qcoef,
+                                                     uint32_t* flags) {
+  __shared__ double s[5][EB];
+  for (int q = 0; q < 5; ++q) s[q][threadIdx.x] = partial[5 * threadIdx.x + q];
+  __syncthreads();
+  for (int off = EB / 2; off > 0; off >>= 1) {
+    if (threadIdx.x < off)
+      for (int q = 0; q < 5; ++q) s[q][threadIdx.x] += s[q][threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    const double S0 = s[0][0], S1 = s[1][0], S2 = s[2][0], A = s[3][0], B = s[4][0];
+    const double C = S0 * S2 - S1 * S1;
+    double c0, c1;
+    if (C <= 1e-14 * S0 * S2) {
+      c0 = -A / S0;
+      c1 = 0.0;
+    } else {
+      c0 = (-A * S2 + B * S1) / C;
+      c1 = (A * S1 - B * S0) / C;
+    }
+    if (!isfinite(c0) || !isfinite(c1)) {
+      atomicOr(flags, FLAG_NONFINITE);
+      c0 = 0.0;
+      c1 = 0.0;
+    }
+    qcoef[0] = c0;
+    qcoef[1] = c1;
+  }
+}
+
+template <typename T>
+__global__ __launch_bounds__(256) void k_mass_rhs_energy(GridView g, const double* __restrict__ u,
+                                                         const double* __restrict__ v,
+                                                         const double* __restrict__ w,
+                                                         const T* __restrict__ p,
+                                                         const uint32_t* __restrict__ cb_mask,
+                                                         const double* __restrict__ qcoef,
+                                                         double inv_adt, double* __restrict__ rhs) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int k = blockIdx.y;
+  const int j = blockIdx.z;
+  if (i >= g.nx) return;
+  const int64_t cell = ((int64_t)j * g.nz + k) * g.nx + i;
+  if (test_bit(cb_mask, cell)) {
+    rhs[cell] = 0.0;
+    return;
+  }
+  const double q = qcoef[0] + qcoef[1] * ((double)p[cell] - kin_at(g, u, v, w, cell));
+  rhs[cell] = (div_at(g, u, v, w, cell) - q) * inv_adt;
+}
+
+void launch_mass_energy(Prof* pf, hipStream_t s, const GridView& g, const double* u,
+                        const double* v, const double* w, const void* p, int fp32,
+                        const uint32_t* cb_mask, double* partial, double* qcoef,
+                        uint32_t* flags) {
+  if (fp32)
+    IBM_LAUNCH(pf, "mass_energy", s,
+               (k_energy_partial<float><<<EB, MT, 0, s>>>(g, u, v, w, (const float*)p, cb_mask,
+                                                          partial)));
+  else
+    IBM_LAUNCH(pf, "mass_energy", s,
+               (k_energy_partial<double><<<EB, MT, 0, s>>>(g, u, v, w, (const double*)p,
+                                                           cb_mask, partial)));
+  IBM_LAUNCH(pf, "mass_final", s, k_energy_final<<<1, EB, 0, s>>>(partial, qcoef, flags));
+}
+
+void launch_mass_rhs_energy(Prof* pf, hipStream_t s, const GridView& g, const double* u,
+                            const double* v, const double* w, const void* p, int fp32,
+                            const uint32_t* cb_mask, const double* qcoef, double inv_adt,
+                            double* rhs) {
+  dim3 grid((g.nx + 255) / 256, g.nz, g.ny);
+  if (fp32)
+    IBM_LAUNCH(pf, "mass_rhs", s,
+               (k_mass_rhs_energy<float><<<grid, 256, 0, s>>>(g, u, v, w, (const float*)p,
+                                                              cb_mask, qcoef, inv_adt, rhs)));
+  else
+    IBM_LAUNCH(pf, "mass_rhs", s,
+               (k_mass_rhs_energy<double><<<grid, 256, 0, s>>>(g, u, v, w, (const double*)p,
+                                                               cb_mask, qcoef, inv_adt, rhs)));
+}
+
 void launch_mass(Prof* pf, hipStream_t s, const GridView& g, const double* u, const double* v,
                  const double* w, const int64_t* cb, const int64_t* count, int64_t cap,
                  double vtot, int use_q, double* partial, double* qf, uint32_t* flags) {

@@ -11,7 +11,8 @@
 //      phi_0 = 0 and is shifted to zero volume-weighted mean
 //   4. inverse z transform, 5. inverse x transform -> phi.
 // The transforms are mixed-radix (2, 3, 4, 5, 7) Stockham autosort FFTs
-// staged in LDS (ping-pong buffers), twiddles from a precomputed table.
+// staged in LDS (ping-pong buffers), twiddles from a precomputed table; the
+// real x transforms carry two rows per complex sequence.
 //
 // Spectral precision.  The spectrum and the transforms are FP64 (double2) or
 // FP32 (float2, the mixed form).  The wall-normal solves always run in FP64
@@ -96,6 +97,11 @@ __device__ __forceinline__ void small_dft(C* u, const C* tw, int n) {
   }
 }
 
+// Transforms hold at most 32 KB of LDS per block (two ping-pong buffers of
+// fft_buf complex values each), so that four blocks share a CU.
+template <typename C>
+constexpr int fft_buf() { return 16384 / (int)sizeof(C); }
+
 // one Stockham stage of radix R (current sub-transform length p) for ncols
 // sequences at buf[idx*si + col*sc]
 template <typename C, int R, bool INV>
@@ -163,7 +169,8 @@ struct PoisK {
   const double* rhs;           // SRC_ARRAY: the right-hand side; SRC_RESIDUAL/CHECK: kept copy
   const double *u, *v, *w;     // SRC_VELOCITY
   const uint32_t* cb_mask;
-  const double* qf;
+  const double* qf;            // q_F, or (c0, c1) of the energy-conserving shape
+  const typename RealOf<C>::T* pq;  // energy-conserving shape: p (else NULL)
   double inv_adt;
   double* rhs_keep;            // FP64 copy of the right-hand side formed in pass 1 (or NULL)
   const double* phi_in;        // SRC_RESIDUAL/CHECK: current phi
@@ -224,10 +231,12 @@ __global__ __launch_bounds__(256) void k_fftx_fwd(PoisK<C> K) {
   const int64_t nrows = (int64_t)g.ny * g.nz;
   const int64_t row0 = (int64_t)blockIdx.x * K.rows;
   const int nr = (int)((row0 + K.rows <= nrows) ? K.rows : nrows - row0);
-  C* a = sm;
-  C* b = sm + K.rows * nx;
+  // two real rows per complex sequence: row r is the real (r even) or the
+  // imaginary (r odd) part of sequence r/2
+  R* sr = reinterpret_cast<R*>(sm);
   const int64_t plane = (int64_t)g.nz * nx;
-  const double q = (K.mode == SRC_VELOCITY) ? *K.qf : 0.0;
+  const double q = (K.mode == SRC_VELOCITY) ? K.qf[0] : 0.0;
+  const double q1 = (K.mode == SRC_VELOCITY && K.pq) ? K.qf[1] : 0.0;
   const bool resid = K.mode >= SRC_RESIDUAL;
   double rmax = 0.0, vsum = 0.0;
   for (int e = threadIdx.x; e < nr * nx; e += blockDim.x) {
@@ -244,10 +253,18 @@ __global__ __launch_bounds__(256) void k_fftx_fwd(PoisK<C> K) {
         const int j = (int)(rr / g.nz), k = (int)(rr % g.nz);
         const int ip = (i + 1 == nx) ? 0 : i + 1;
         const int kp = (k + 1 == g.nz) ? 0 : k + 1;
-        const double D = (K.u[cell - i + ip] - K.u[cell]) * g.idx +
-                         (K.v[cell + plane] - K.v[cell]) * g.idy[j] +
-                         (K.w[(int64_t)j * plane + (int64_t)kp * nx + i] - K.w[cell]) * g.idz;
-        val = (D - q) * K.inv_adt;
+        const double u0 = K.u[cell], u1 = K.u[cell - i + ip];
+        const double v0 = K.v[cell], v1 = K.v[cell + plane];
+        const double w0 = K.w[cell], w1 = K.w[(int64_t)j * plane + (int64_t)kp * nx + i];
+        const double D = (u1 - u0) * g.idx + (v1 - v0) * g.idy[j] + (w1 - w0) * g.idz;
+        double qq = q;
+        if (K.pq) {  // q_F = c0 + c1 (p - e), e the cell's kinetic energy
+          const double eu = 0.5 * (u0 * u0 + u1 * u1);
+          const double ev = 0.5 * (v0 * v0 + v1 * v1);
+          const double ew = 0.5 * (w0 * w0 + w1 * w1);
+          qq = q + q1 * ((double)K.pq[cell] - 0.5 * ((eu + ev) + ew));
+        }
+        val = (D - qq) * K.inv_adt;
       }
     } else {
       const int64_t rr = row0 + r;
@@ -257,7 +274,7 @@ __global__ __launch_bounds__(256) void k_fftx_fwd(PoisK<C> K) {
       vsum += K.phi_in[cell] * g.dy[j];
     }
     if (K.rhs_keep) K.rhs_keep[cell] = val;
-    if (K.mode != SRC_CHECK) a[r * nx + i] = mkc<C>((R)val, (R)0);
+    if (K.mode != SRC_CHECK) sr[2 * ((r >> 1) * nx + i) + (r & 1)] = (R)val;
   }
   if (resid) {
     // block maximum of |r|, then one atomic per block on the bit pattern
@@ -285,12 +302,20 @@ __global__ __launch_bounds__(256) void k_fftx_fwd(PoisK<C> K) {
     }
     if (K.mode == SRC_CHECK) return;  // block-uniform
   }
-  for (int e = nr * nx + threadIdx.x; e < K.rows * nx; e += blockDim.x) a[e] = mkc<C>((R)0, (R)0);
+  for (int e = nr * nx + threadIdx.x; e < K.rows * nx; e += blockDim.x) {
+    const int r = e / nx, i = e % nx;
+    sr[2 * ((r >> 1) * nx + i) + (r & 1)] = (R)0;
+  }
   __syncthreads();
-  C* out = lds_fft<C, false>(a, b, K.px, K.rows, 1, nx);
+  const C* out = lds_fft<C, false>(sm, sm + (K.rows / 2) * nx, K.px, K.rows / 2, 1, nx);
+  // split: with Z = A + iB, A[k] = (Z[k] + conj Z[n-k])/2, B[k] = (Z[k] - conj Z[n-k])/2i
   for (int e = threadIdx.x; e < nr * nxh; e += blockDim.x) {
     const int r = e / nxh, p = e % nxh;
-    K.spec[(row0 + r) * nxh + p] = out[r * nx + p];
+    const C zk = out[(r >> 1) * nx + p];
+    const C zm = out[(r >> 1) * nx + (p == 0 ? 0 : nx - p)];
+    const R h = (R)0.5;
+    K.spec[(row0 + r) * nxh + p] = (r & 1) ? mkc<C>(h * (zk.y + zm.y), h * (zm.x - zk.x))
+                                           : mkc<C>(h * (zk.x + zm.x), h * (zk.y - zm.y));
   }
 }
 
@@ -305,15 +330,13 @@ __global__ __launch_bounds__(256) void k_fftz(PoisK<C> K) {
   const int j = blockIdx.y;
   const int p0 = blockIdx.x * tp;
   const int nc = (p0 + tp <= nxh) ? tp : nxh - p0;
-  C* a = sm;
-  C* b = sm + nz * tp;
   C* spec = K.spec + (int64_t)j * nz * nxh + p0;
   for (int e = threadIdx.x; e < nz * tp; e += blockDim.x) {
     const int k = e / tp, c = e % tp;
-    a[e] = (c < nc) ? spec[(int64_t)k * nxh + c] : mkc<C>((R)0, (R)0);
+    sm[e] = (c < nc) ? spec[(int64_t)k * nxh + c] : mkc<C>((R)0, (R)0);
   }
   __syncthreads();
-  C* out = lds_fft<C, INV>(a, b, K.pz, tp, tp, 1);
+  const C* out = lds_fft<C, INV>(sm, sm + nz * tp, K.pz, tp, tp, 1);
   for (int e = threadIdx.x; e < nz * tp; e += blockDim.x) {
     const int k = e / tp, c = e % tp;
     if (c < nc) spec[(int64_t)k * nxh + c] = out[e];
@@ -556,25 +579,27 @@ __global__ __launch_bounds__(256) void k_fftx_inv(PoisK<C> K) {
   const int64_t nrows = (int64_t)g.ny * g.nz;
   const int64_t row0 = (int64_t)blockIdx.x * K.rows;
   const int nr = (int)((row0 + K.rows <= nrows) ? K.rows : nrows - row0);
-  C* a = sm;
-  C* b = sm + K.rows * nx;
-  for (int e = threadIdx.x; e < K.rows * nx; e += blockDim.x) {
-    const int r = e / nx, i = e % nx;
-    C val = mkc<C>((R)0, (R)0);
-    if (r < nr) {
-      if (i < nxh) {
-        val = K.spec[(row0 + r) * nxh + i];
-      } else {  // Hermitian extension of a real sequence
-        const C c = K.spec[(row0 + r) * nxh + (nx - i)];
-        val = mkc<C>(c.x, -c.y);
-      }
-    }
-    a[e] = val;
+  // two half spectra per complex sequence: Z = A + iB over the Hermitian
+  // extension (the bins 0 and nx/2 of a real sequence are real), so that the
+  // real and imaginary parts of the inverse are rows 2c and 2c+1
+  auto bin = [&](int r, int k) -> C {
+    if (r >= nr) return mkc<C>((R)0, (R)0);
+    C c = (k < nxh) ? K.spec[(row0 + r) * nxh + k] : K.spec[(row0 + r) * nxh + (nx - k)];
+    if (k >= nxh) c.y = -c.y;
+    if (k == 0 || 2 * k == nx) c.y = (R)0;
+    return c;
+  };
+  for (int e = threadIdx.x; e < (K.rows / 2) * nx; e += blockDim.x) {
+    const int col = e / nx, k = e % nx;
+    const C A = bin(2 * col, k), B = bin(2 * col + 1, k);
+    sm[e] = mkc<C>(A.x - B.y, A.y + B.x);
   }
   __syncthreads();
-  C* out = lds_fft<C, true>(a, b, K.px, K.rows, 1, nx);
+  const C* out = lds_fft<C, true>(sm, sm + (K.rows / 2) * nx, K.px, K.rows / 2, 1, nx);
+  const R* sr = reinterpret_cast<const R*>(out);
   for (int e = threadIdx.x; e < nr * nx; e += blockDim.x) {
-    double v = (double)out[e].x * K.scale;
+    const int r = e / nx, i = e % nx;
+    double v = (double)sr[2 * ((r >> 1) * nx + i) + (r & 1)] * K.scale;
     if (K.zm) v += K.zm[(int)((row0 + e / nx) / g.nz)] * K.scale;
     if (K.msum) v -= *K.msum * K.inv_vtot;
     if (K.accumulate)
@@ -634,14 +659,14 @@ static PlanDev<C> to_dev(const FFTPlan* p, const C* tw) {
 template <typename C>
 static void run_passes(Prof* pf, hipStream_t s, const GridView& g, PoisK<C> K) {
   constexpr int CB = (int)sizeof(C);
-  // LDS budget per block: 64 KB for the two ping-pong buffers
-  int rows = (2048 * 16 / CB) / g.nx;
-  if (rows < 1) rows = 1;
-  if (rows > 128 / CB) rows = 128 / CB;
+  // per block two LDS buffers of at most fft_buf complex values: x passes
+  // take an even number of real rows, two per complex sequence (nx and nz
+  // <= fft_buf, checked when the context is created)
+  int rows = 2 * (fft_buf<C>() / g.nx);
+  if (rows > 32) rows = 32;
   K.rows = rows;
-  int tp = (2048 * 16 / CB) / g.nz;
-  if (tp < 1) tp = 1;
-  if (tp > 128 / CB) tp = 128 / CB;
+  int tp = fft_buf<C>() / g.nz;
+  if (tp > 16) tp = 16;
   K.tp = tp;
   line_plan(g.ny, false, YL, &K.yP, &K.yL, &K.yr);
   K.ytl = 1024 / K.yP;
@@ -649,7 +674,7 @@ static void run_passes(Prof* pf, hipStream_t s, const GridView& g, PoisK<C> K) {
   if (K.ytl < 1) K.ytl = 1;
   const int64_t nrows = (int64_t)g.ny * g.nz;
   const int xblocks = (int)((nrows + rows - 1) / rows);
-  const size_t xsh = 2 * (size_t)rows * g.nx * CB;
+  const size_t xsh = 2 * (size_t)(rows / 2) * g.nx * CB;
   const size_t zsh = 2 * (size_t)tp * g.nz * CB;
   dim3 zgrid((g.nxh + tp - 1) / tp, g.ny);
   const int64_t nm = (int64_t)g.nz * g.nxh;
@@ -675,7 +700,7 @@ template <typename C>
 static void solve(Prof* pf, hipStream_t s, const GridView& g, const PoissonArgs& a,
                   const C* twx, const C* twz, const double* rhs, const double* u,
                   const double* v, const double* w, const uint32_t* cb_mask, const double* qf,
-                  double inv_adt, double* phi) {
+                  const void* p, double inv_adt, double* phi) {
   PoisK<C> K{};
   K.g = g;
   K.px = to_dev<C>(a.px, twx);
@@ -687,6 +712,7 @@ static void solve(Prof* pf, hipStream_t s, const GridView& g, const PoissonArgs&
   K.w = w;
   K.cb_mask = cb_mask;
   K.qf = qf;
+  K.pq = static_cast<const typename RealOf<C>::T*>(p);
   K.inv_adt = inv_adt;
   K.spec = reinterpret_cast<C*>(a.spec);
   K.lamx = a.lamx;
@@ -724,11 +750,13 @@ static void solve(Prof* pf, hipStream_t s, const GridView& g, const PoissonArgs&
 
 void launch_poisson(Prof* pf, hipStream_t s, const GridView& g, const PoissonArgs& a,
                     const double* rhs, const double* u, const double* v, const double* w,
-                    const uint32_t* cb_mask, const double* qf, double inv_adt, double* phi) {
+                    const uint32_t* cb_mask, const double* qf, const void* p, double inv_adt,
+                    double* phi) {
   if (a.fp32)
-    solve<float2>(pf, s, g, a, a.px->tw32, a.pz->tw32, rhs, u, v, w, cb_mask, qf, inv_adt, phi);
+    solve<float2>(pf, s, g, a, a.px->tw32, a.pz->tw32, rhs, u, v, w, cb_mask, qf, p, inv_adt,
+                  phi);
   else
-    solve<double2>(pf, s, g, a, a.px->tw, a.pz->tw, rhs, u, v, w, cb_mask, qf, inv_adt, phi);
+    solve<double2>(pf, s, g, a, a.px->tw, a.pz->tw, rhs, u, v, w, cb_mask, qf, p, inv_adt, phi);
 }
 
 }  // namespace ibm

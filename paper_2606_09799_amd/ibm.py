@@ -27,6 +27,7 @@ IBM_ENONFINITE, IBM_EGEOM = -5, -7
 FLAG_CAPACITY, FLAG_NONFINITE, FLAG_GEOM, FLAG_REFINE = 1, 2, 4, 8
 IBM_FP64, IBM_MIXED = 0, 1
 IBM_RK2CN, IBM_AB2CN = 0, 1
+IBM_Q_NONE, IBM_Q_UNIFORM, IBM_Q_ENERGY = 0, 1, 2
 
 
 class IbmGrid(ctypes.Structure):
@@ -82,8 +83,8 @@ _tags_copy = _sig("ibm_tags_copy", c_int32, c_void_p, c_int32, c_void_p, c_void_
 _force = _sig("ibm_force", c_int32, c_void_p, c_void_p, c_void_p, c_void_p)
 _viscous = _sig("ibm_viscous", c_int32, c_void_p, c_void_p, POINTER(c_void_p),
                 POINTER(c_void_p), c_double, c_double, c_double, c_void_p, c_void_p, c_void_p)
-_mass_rhs = _sig("ibm_mass_rhs", c_int32, c_void_p, c_void_p, c_void_p, c_void_p, c_double,
-                 c_void_p, c_void_p)
+_mass_rhs = _sig("ibm_mass_rhs", c_int32, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+                 c_double, c_void_p, c_void_p)
 _poisson = _sig("poisson_solve", c_int32, c_void_p, c_void_p, c_void_p)
 _project = _sig("ibm_project", c_int32, c_void_p, c_void_p, c_double, c_void_p, c_void_p,
                 c_void_p, c_void_p)
@@ -144,7 +145,9 @@ def _dev(t, dtype, numel, name):
 
 class Context:
     """One grid on the current device, bound to torch's current stream.
-    precision: "fp64", or "mixed" (p and H in float32; u, v, w in float64)."""
+    precision: "fp64", or "mixed" (p and H in float32; u, v, w in float64).
+    use_q: True (uniform q_F), "energy" (mass- and energy-conserving shape)
+    or False (standard projection)."""
 
     def __init__(self, nx, ny, nz, lx, lz, y_faces, re, dpdx=0.0, scheme="rk2", use_q=True,
                  force_cap=0, precision="fp64", refine_max=0, refine_tol=0.0):
@@ -162,9 +165,10 @@ class Context:
         self._yf = yf
         g = IbmGrid(self.nx, self.ny, self.nz, 0, float(lx), float(lz),
                     yf.ctypes.data_as(POINTER(c_double)))
+        qmode = IBM_Q_ENERGY if use_q == "energy" else (IBM_Q_UNIFORM if use_q else IBM_Q_NONE)
         o = IbmOpts(IBM_MIXED if precision == "mixed" else IBM_FP64,
                     IBM_RK2CN if scheme == "rk2" else IBM_AB2CN, float(re),
-                    float(dpdx), int(force_cap), 1 if use_q else 0, int(refine_max),
+                    float(dpdx), int(force_cap), qmode, int(refine_max),
                     float(refine_tol))
         h = c_void_p()
         _ok(_create(ctypes.byref(g), ctypes.byref(o), _stream(), ctypes.byref(h)), "ibm_create")
@@ -286,12 +290,14 @@ def ibm_viscous(ctx, p, h_prev, h_out, gamma, rho, dt, u, v, w):
                  _dev(w, torch.float64, ctx.cells, "w")), "ibm_viscous")
 
 
-def ibm_mass_rhs(ctx, u, v, w, alpha_dt, rhs, qf=None):
+def ibm_mass_rhs(ctx, u, v, w, alpha_dt, rhs, qf=None, p=None):
+    """qf: 1 value (q_F), or 2 (c0, c1) for the energy-conserving shape,
+    which also needs p."""
     _ok(_mass_rhs(ctx.handle, _dev(u, torch.float64, ctx.cells, "u"),
                   _dev(v, torch.float64, ctx.vfaces, "v"),
-                  _dev(w, torch.float64, ctx.cells, "w"), float(alpha_dt),
-                  _dev(rhs, torch.float64, ctx.cells, "rhs"),
-                  _dev(qf, torch.float64, 1, "qf")), "ibm_mass_rhs")
+                  _dev(w, torch.float64, ctx.cells, "w"), _dev(p, ctx.pdtype, ctx.cells, "p"),
+                  float(alpha_dt), _dev(rhs, torch.float64, ctx.cells, "rhs"),
+                  _dev(qf, torch.float64, None, "qf")), "ibm_mass_rhs")
 
 
 def poisson_solve(ctx, rhs, phi):
@@ -382,7 +388,8 @@ class Batch:
                                yf.ctypes.data_as(POINTER(c_double)))
             opts[s] = IbmOpts(IBM_MIXED if precision == "mixed" else IBM_FP64,
                               IBM_RK2CN if scheme == "rk2" else IBM_AB2CN, float(d["re"]),
-                              float(d["dpdx"]), 0, 1 if use_q else 0, 0, 0.0)
+                              float(d["dpdx"]), 0,
+                              IBM_Q_ENERGY if use_q == "energy" else (1 if use_q else 0), 0, 0.0)
             cells, vf = nx * ny * nz, nx * (ny + 1) * nz
             st = IbmState(_dev(d["u"], torch.float64, cells, "u"),
                           _dev(d["v"], torch.float64, vf, "v"),

@@ -264,6 +264,9 @@ def config(name: str) -> Workload:
          0.2 sin(2 pi t) and pitching +-15 deg at twice the frequency.
     c3   512x384x512 stretched channel, Re 2000, dt 1e-3, 200 steps; a
          deforming closed body r = 0.4 (1 + 0.1 Y20 sin 4 pi t), 20480 tris.
+    c5   1024x768x1024 stretched channel, Re 2800, dt 1e-3, 50 steps; 64
+         translating spheres (1280 tris each) and 3 hinged rotating
+         leaflets (10000 tris each), 111920 triangles.
     tiny  small ragged grids for parity tests (several tiles plus a tail).
     """
     two_pi, pi = 2.0 * math.pi, math.pi
@@ -286,6 +289,14 @@ def config(name: str) -> Workload:
                         1e-3, 200, 1.0, 0.01, 3, -2.0 / 2000.0,
                         [Body("deform", deform_vertex_data(V, 0.4), F,
                               lambda t: deform_coef(t, c, 0.4))])
+    if name == "c5":
+        # 1024x768x1024 stretched channel, Re 2800 (bulk Reynolds number 5600
+        # on the channel height), centre velocity 1.5 (bulk 1) plus a 0.1
+        # perturbation, 50 steps of 1e-3; a constant driving gradient of the
+        # laminar profile stands in for constant-flow-rate control
+        ny = 768
+        return Workload("c5", 1024, ny, 1024, two_pi, pi, tanh_faces(ny, 2.0), 2800.0,
+                        1e-3, 50, 1.5, 0.1, 5, -2.0 * 1.5 / 2800.0, c5_bodies())
     if name == "tiny":
         # ragged, non-power-of-two sizes: 40 = 8*5 and 36 = 4*9 exercise the
         # mixed-radix transforms; the sphere spans several tiles.
@@ -302,7 +313,75 @@ def config(name: str) -> Workload:
     raise KeyError(name)
 
 
-CONFIG_NAMES = ("c1", "c2", "c3", "tiny", "tiny_plate")
+def leaflet_mesh(radius: float, chord: float, span: float, n_arc: int, n_span: int):
+    """Zero-thickness leaflet: a cylindrical arc in the x-y plane (radius
+    `radius`, chord `chord`) extruded along z over `span`, with one edge on
+    the z axis (its hinge).  The arc rises from the hinge along +y, bulging
+    towards -x.  n_arc x n_span quads, 2 triangles each.  Returns (verts
+    relative to the hinge centre, tris)."""
+    ang = 2.0 * math.asin(0.5 * chord / radius)
+    ph = ang * np.arange(n_arc + 1, dtype=np.float64) / n_arc
+    zs = -0.5 * span + span * np.arange(n_span + 1, dtype=np.float64) / n_span
+    x = -radius + radius * np.cos(ph)
+    y = radius * np.sin(ph)
+    X = np.repeat(x, n_span + 1)
+    Y = np.repeat(y, n_span + 1)
+    Z = np.tile(zs, n_arc + 1)
+    V = np.stack([X, Y, Z], axis=1)
+    tris = []
+    for a in range(n_arc):
+        for b in range(n_span):
+            v00 = a * (n_span + 1) + b
+            v10 = (a + 1) * (n_span + 1) + b
+            tris.append((v00, v10, v10 + 1))
+            tris.append((v00, v10 + 1, v00 + 1))
+    return V, np.array(tris, dtype=np.int32)
+
+
+def leaflet_rotation(t: float, hinge) -> np.ndarray:
+    """Rigid rotation of a leaflet about the z axis through its hinge:
+    theta(t) = (pi/3) (1 - cos(2 pi (t + 1/4)))/2."""
+    w = 2.0 * math.pi
+    th = (math.pi / 3.0) * 0.5 * (1.0 - math.cos(w * (t + 0.25)))
+    thd = (math.pi / 3.0) * 0.5 * w * math.sin(w * (t + 0.25))
+    ct, st = math.cos(th), math.sin(th)
+    R = [[ct, -st, 0.0], [st, ct, 0.0], [0.0, 0.0, 1.0]]
+    return rigid_coef(hinge, R, (0.0, 0.0, 0.0), (0.0, 0.0, thd))
+
+
+def c5_bodies(seed: int = 5, nspheres: int = 64, h: float = 0.016):
+    """Bodies of the large multi-body workload: three leaflets (10000
+    triangles each) hinged along z at (x_h, -0.3) for x_h = pi/2, pi, 3 pi/2
+    and spanning z in [0.57, 2.57], and `nspheres` spheres of diameter 0.1
+    (1280 triangles) with centres at |y| <= 0.8, at least 2h apart from each
+    other and clear of the leaflets' swept region, each translating at a
+    speed drawn from U[0, 1] in a random direction."""
+    rng = np.random.default_rng(seed)
+    bodies = []
+    hinges = [(0.5 * math.pi, -0.3, 1.57), (math.pi, -0.3, 1.57), (1.5 * math.pi, -0.3, 1.57)]
+    V, F = leaflet_mesh(0.3, 0.3, 2.0, 50, 100)
+    for hg in hinges:
+        bodies.append(Body("rigid", V, F, lambda t, hg=hg: leaflet_rotation(t, hg)))
+    r = 0.05
+    centres = []
+    while len(centres) < nspheres:
+        c = np.array([rng.uniform(0.0, 2.0 * math.pi), rng.uniform(-0.8, 0.8),
+                      rng.uniform(0.0, math.pi)])
+        # clear of the leaflets (|x - x_h| < 0.45 within their y and z range)
+        near_leaflet = any(abs(c[0] - hg[0]) < 0.45 and -0.75 < c[1] < 0.15 and
+                           0.4 < c[2] < 2.75 for hg in hinges)
+        if near_leaflet:
+            continue
+        if all(np.linalg.norm(c - o) >= 2 * r + 2 * h for o in centres):
+            centres.append(c)
+    for c in centres:
+        d = rng.standard_normal(3)
+        d /= np.linalg.norm(d)
+        bodies.append(_sphere_body(3, r, c, float(rng.uniform(0.0, 1.0)) * d))
+    return bodies
+
+
+CONFIG_NAMES = ("c1", "c2", "c3", "c5", "tiny", "tiny_plate")
 
 
 def _plate_fixed(chord, span, nq_x, nq_z, c0, U, theta):
