@@ -33,45 +33,33 @@ HBM_PEAK_GBS = 8000.0
 
 def algorithmic_bytes(name, nx, ny, nz, form="fp64"):
     """Bytes a launch of kernel `name` must move at minimum: the fields it
-    reads and writes once, per the pass model of the step.  FP64 form: 8-byte
-    values; mixed form: the velocity and phi FP64, p, H, R and the spectrum
-    FP32 (the refinement passes are not counted here)."""
+    reads and writes once, per the pass model of the step.  The velocity and
+    phi are FP64 in every form; p, H, R and the line-solve data are FP32 in
+    the mixed forms; the spectrum is FP32 in mixed_refined (whose refinement
+    passes are not counted here)."""
     N = nx * ny * nz
     Nv = nx * (ny + 1) * nz
     U = N + Nv + N                       # u, v, w values
-    if form == "fp64":
-        r = 8
-        spec = ny * nz * (nx // 2 + 1) * 16
-        table = {
-            "rhs": 8 * (U + N) + 8 * U * 2,          # u,v,w,p + H + R
-            "adi_x": 16 * N, "adi_z": 16 * N,        # per component
-            "adi_y": 24 * N,                         # w2, u -> u_hat
-            "pois_fftx_fwd": 8 * U + spec,           # u_hat -> spectrum
-            "pois_fftz_fwd": 2 * spec, "pois_fftz_inv": 2 * spec,
-            "pois_tri_y": 2 * spec,
-            "pois_fftx_inv": spec + 8 * N,
-            "project": 8 * U * 2 + 8 * N + 8 * N * 2,  # u_hat,phi,p -> u,p
-        }
-    else:
-        r = 4
-        spec = ny * nz * (nx // 2 + 1) * 8
-        table = {
-            "rhs": 8 * U + r * N + r * U * 2,        # u,v,w (f64), p + H + R (f32)
-            "adi_x": 2 * r * N, "adi_z": 2 * r * N,
-            "adi_y": r * N + 16 * N,                 # w2 (f32), u (f64) -> u_hat
-            "pois_fftx_fwd": 8 * U + 8 * N + spec,   # u_hat -> kept f64 rhs + spectrum
-            "pois_fftz_fwd": 2 * spec, "pois_fftz_inv": 2 * spec,
-            "pois_tri_y": 2 * spec,
-            "pois_fftx_inv": spec + 8 * N,
-            "project": 8 * U * 2 + 8 * N + r * N * 2,
-        }
+    r = 8 if form == "fp64" else 4       # p, H, R, line-solve data
+    spec = ny * nz * (nx // 2 + 1) * (8 if form == "mixed_refined" else 16)
+    table = {
+        "rhs": 8 * U + r * N + r * U * 2,          # u,v,w (f64), p + H + R
+        "adi_x": 2 * r * N, "adi_z": 2 * r * N,    # per component
+        "adi_y": r * N + 16 * N,                   # w2, u (f64) -> u_hat
+        "pois_fftx_fwd": 8 * U + spec + (8 * N if form == "mixed_refined" else 0),
+        "pois_fftz_fwd": 2 * spec, "pois_fftz_inv": 2 * spec,
+        "pois_tri_y": 2 * spec,
+        "pois_fftx_inv": spec + 8 * N,
+        "project": 8 * U * 2 + 8 * N + r * N * 2,  # u_hat, phi, p -> u, p
+    }
     return table.get(name)
 
 
 # kernel name in the library's event profile -> kernel name in the rocprofv3
 # summaries (template arguments of the storage type per form)
 def counter_name(kernel, form):
-    T, C = ("double", "double2") if form == "fp64" else ("float", "float2")
+    T = "double" if form == "fp64" else "float"
+    C = "float2" if form == "mixed_refined" else "double2"
     return {"rhs": f"k_rhs<{T}>", "adi_x": f"k_line<{T}>", "adi_z": f"k_line<{T}>",
             "adi_y": f"k_line<{T}>", "pois_fftx_fwd": f"k_fftx_fwd<{C}>",
             "pois_fftz_fwd": f"k_fftz<{C}, false>", "pois_fftz_inv": f"k_fftz<{C}, true>",
@@ -141,7 +129,8 @@ def run_form(args, wl, form, dev):
     from paper_2606_09799_amd import ibm
 
     ctx = ibm.Context(wl.nx, wl.ny, wl.nz, wl.lx, wl.lz, wl.y_faces, wl.re, wl.dpdx,
-                      precision=form)
+                      precision="fp64" if form == "fp64" else "mixed",
+                      mixed_poisson="refined" if form == "mixed_refined" else "fp64")
     progress(f"{form}: context created, generating the initial field")
     u0, v0, w0 = wl.fields()
     T = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
@@ -173,7 +162,7 @@ def run_form(args, wl, form, dev):
     prof = ibm.ibm_profile_read(ctx)
     dominant = max((k for k in prof if algorithmic_bytes(k, wl.nx, wl.ny, wl.nz, form)),
                    key=lambda k: prof[k][1], default=None)
-    stats = ibm.ibm_refine_stats(ctx, reset=True) if form == "mixed" else None
+    stats = ibm.ibm_refine_stats(ctx, reset=True) if form == "mixed_refined" else None
     progress(f"{form}: warm-up done, timing {args.steps} steps")
     # timed region: events only around the dominant kernel
     ibm.ibm_profile(ctx, True, dominant)
@@ -186,8 +175,8 @@ def run_form(args, wl, form, dev):
     progress(f"{form}: {el / args.steps * 1e3:.3f} ms per step")
     dom = ibm.ibm_profile_read(ctx)
     ibm.ibm_profile(ctx, False, None)
-    if form == "mixed":
-        stats = ibm.ibm_refine_stats(ctx)
+    if form == "mixed_refined":
+        stats = ibm.ibm_refine_stats(ctx, after_first=True)
     flags = ibm.ibm_check(ctx)
     if flags:
         print(f"bench.py: device flags {flags} after the {form} run", file=sys.stderr)
@@ -259,8 +248,10 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="c2")
-    ap.add_argument("--forms", default="fp64,mixed",
-                    help="precision forms to time; the first one is the headline value")
+    ap.add_argument("--forms", default="fp64,mixed,mixed_refined",
+                    help="precision forms to time (fp64; mixed: FP32 predictor and FP64 "
+                         "Poisson; mixed_refined: also FP32 Poisson transforms refined with "
+                         "FP64 residuals); the first one is the headline value")
     ap.add_argument("--batch-sims", type=int, default=64,
                     help="simulations of the batched workload (0 = skip it)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -297,10 +288,11 @@ def main():
                              "traffic": measured_traffic(dominant, wl.name, form),
                              "avg_launch_us": round(avg_s * 1e6, 2), "algorithmic_bytes": ab}
         if stats is not None:
-            solves, corr, worst = stats
+            solves, corr, worst, first = stats
             r["refinement"] = {"poisson_solves": solves, "corrections": corr,
                                "corrections_per_solve": round(corr / max(1, solves), 3),
-                               "max_final_divergence": worst}
+                               "max_final_divergence": worst,
+                               "max_divergence_after_first_correction": first}
         results[form] = r
     batched = None
     if args.batch_sims > 0:

@@ -22,9 +22,9 @@
  *   - Precision (ibm_opts.precision).  IBM_FP64: every array is FP64.
  *     IBM_MIXED: u, v, w, phi and every right-hand side passed in stay FP64;
  *     p and the H arrays are FP32 ("f32/f64" below: FP32 in the mixed form,
- *     FP64 otherwise).  The mixed form runs the predictor's line solves and
- *     the Poisson transforms in FP32 and refines each Poisson solve with
- *     FP64 residuals (see poisson_solve).
+ *     FP64 otherwise).  The mixed form runs the predictor (right-hand side
+ *     storage and line solves) in FP32; its Poisson solve is FP64, or FP32
+ *     transforms refined with FP64 residuals (ibm_opts.mixed_poisson).
  *   - "dev" pointers are device memory on the context's device; "host"
  *     pointers are host memory.  The caller owns every array it passes; the
  *     library owns its workspace and the tag buffers.
@@ -65,6 +65,11 @@ extern "C" {
 
 #define IBM_FP64 0
 #define IBM_MIXED 1
+
+/* Poisson solve of the mixed form (ibm_opts.mixed_poisson) */
+#define IBM_POISSON_FP64 0    /* FP64 transforms and solves (default) */
+#define IBM_POISSON_REFINED 1 /* FP32 transforms, FP64 wall-normal solves,
+                                 FP64-residual refinement */
 #define IBM_RK2CN 0
 #define IBM_AB2CN 1
 
@@ -94,10 +99,15 @@ typedef struct {
  * cell-centred kinetic energy of u_hat, each component's square averaged
  * over the two faces; a constant p - e on C_F falls back to the uniform
  * shape), IBM_Q_NONE the standard projection.
- * Mixed form only: refine_max (0..16, 0 = 3) bounds the FP64-residual
- * refinements of one Poisson solve, which stop once max|rhs - L_c phi| *
- * alpha_dt <= refine_tol (0 = 1e-11; alpha_dt = 1 for poisson_solve); after
- * the projection that product is max|D u - q| (paper Eq. mod_div). */
+ * Mixed form only: mixed_poisson selects the Poisson solve, FP64
+ * (IBM_POISSON_FP64, the default: on stretched grids the FP32 solve's
+ * rounding, amplified by the largest wall-normal eigenvalue, needs two
+ * refinements to reach the divergence bound, which costs more than an FP64
+ * solve) or FP32 transforms refined with FP64 residuals
+ * (IBM_POISSON_REFINED); refine_max (0..16, 0 = 3) bounds the refinements of
+ * one solve, which stop once max|rhs - L_c phi| * alpha_dt <= refine_tol
+ * (0 = 1e-11; alpha_dt = 1 for poisson_solve); after the projection that
+ * product is max|D u - q| (paper Eq. mod_div). */
 typedef struct {
   int32_t precision; /* IBM_FP64 or IBM_MIXED */
   int32_t scheme;    /* IBM_RK2CN or IBM_AB2CN */
@@ -107,6 +117,8 @@ typedef struct {
   int32_t use_q;
   int32_t refine_max;
   double refine_tol;
+  int32_t mixed_poisson;
+  int32_t reserved;
 } ibm_opts;
 
 /* One triangulated surface at time t^n (paper Sec. 2: the wall position
@@ -293,9 +305,10 @@ int ibm_batch_step(ibm_batch* b, const double* coef, double dt, int32_t mode);
 int ibm_batch_check(ibm_batch* b, uint32_t* flags);
 
 /* Mixed form: synchronise and copy the refinement statistics since the
- * last reset to stats (host double[3]): Poisson solves, FP64-residual
- * corrections applied, and the largest final max|rhs - L_c phi| * alpha_dt.
- * reset = 1 clears them. */
+ * last reset to stats (host double[4]): Poisson solves, FP64-residual
+ * corrections applied, the largest final max|rhs - L_c phi| * alpha_dt, and
+ * the largest such residual left by the first correction.  reset = 1 clears
+ * them. */
 int ibm_refine_stats(ibm_ctx* ctx, double* stats, int32_t reset);
 
 /* Synchronise the stream and return (and clear) the sticky device flags. */

@@ -93,7 +93,10 @@ __device__ void reduced_solve_cyclic(Acc A, int P) {
   for (int s = 0; s < P; ++s) A(7, s) -= fact * A(1, s);
 }
 
-template <typename T>
+// MODE: 0 x rows, 1 z lines, 2 y lines (compile time, so each instance
+// carries only its own addressing).  FIXED: every segment holds exactly LMAX
+// rows (n = P * LMAX), so the segment loops have no runtime bounds.
+template <typename T, int MODE, bool FIXED>
 __global__ __launch_bounds__(256) void k_line(LineK<T> K) {
   extern __shared__ __align__(16) unsigned char ldsraw[];
   T* lds = reinterpret_cast<T*>(ldsraw);
@@ -113,7 +116,7 @@ __global__ __launch_bounds__(256) void k_line(LineK<T> K) {
   }
   __syncthreads();
   int lb, s;
-  if (K.mode == 0) {
+  if (MODE == 0) {
     s = tid % P;
     lb = tid / P;
   } else {
@@ -124,7 +127,7 @@ __global__ __launch_bounds__(256) void k_line(LineK<T> K) {
   // line base offset and element stride
   int64_t base = 0, es = 1;
   bool valid = active;
-  if (K.mode == 0) {
+  if (MODE == 0) {
     const int64_t line = (int64_t)blockIdx.x * K.tl + lb;
     valid = valid && line < (int64_t)K.nj * K.nz;
     const int j = K.j0 + (int)(line / K.nz), k = (int)(line % K.nz);
@@ -133,7 +136,7 @@ __global__ __launch_bounds__(256) void k_line(LineK<T> K) {
   } else {
     const int i = blockIdx.x * K.tl + lb;
     valid = valid && i < K.nx;
-    if (K.mode == 1) {
+    if (MODE == 1) {
       base = (int64_t)(K.j0 + blockIdx.y) * K.plane + i;
       es = K.nx;
     } else {
@@ -141,13 +144,13 @@ __global__ __launch_bounds__(256) void k_line(LineK<T> K) {
       es = K.plane;
     }
   }
-  const int lo = s * K.L + (s < K.r ? s : K.r);
-  const int len = K.L + (s < K.r ? 1 : 0);
+  const int lo = FIXED ? s * LMAX : s * K.L + (s < K.r ? s : K.r);
+  const int len = FIXED ? LMAX : K.L + (s < K.r ? 1 : 0);
   const int m = len - 1;  // interior rows; row lo+m is the separator
   // x sweep: rows of this block and their staging
   int xrows = 0;
   const T* xsrc = nullptr;
-  if (K.mode == 0) {
+  if (MODE == 0) {
     const int64_t l0 = (int64_t)blockIdx.x * K.tl;
     const int64_t nl = (int64_t)K.nj * K.nz;
     xrows = (int)((l0 + K.tl <= nl) ? K.tl : nl - l0);
@@ -170,7 +173,7 @@ __global__ __launch_bounds__(256) void k_line(LineK<T> K) {
     T raw[LMAX];
 #pragma unroll
     for (int e = 0; e < LMAX; ++e)
-      if (e < len) raw[e] = (K.mode == 0) ? rowbuf[xpos(e)] : K.d[base + (int64_t)(lo + e) * es];
+      if (e < len) raw[e] = (MODE == 0) ? rowbuf[xpos(e)] : K.d[base + (int64_t)(lo + e) * es];
     if (es == 1) {  // contiguous row: the segment's bits span at most two words
       const int64_t b0 = base + lo;
       const uint32_t w0 = K.mask[b0 >> 5];
@@ -268,9 +271,9 @@ __global__ __launch_bounds__(256) void k_line(LineK<T> K) {
   // LDS: 8 arrays of P doubles per line; neighbouring lanes (consecutive
   // lines in the z/y sweeps, consecutive segments in the x sweep) take
   // consecutive words
-  if (K.mode == 0) __syncthreads();  // the row buffer becomes the separator arrays
+  if (MODE == 0) __syncthreads();  // the row buffer becomes the separator arrays
   const int TL = K.tl;
-  const bool rowmajor = (K.mode == 0);
+  const bool rowmajor = (MODE == 0);
   auto at = [&](int f, int seg) -> T& {
     return rowmajor ? sm[((size_t)f * TL + lb) * P + seg] : sm[((size_t)f * P + seg) * TL + lb];
   };
@@ -361,16 +364,16 @@ __global__ __launch_bounds__(256) void k_line(LineK<T> K) {
         T x = zr;
         if (e < m) x = fast ? dd[e] - TAB(2, e) * zl - TAB(3, e) * zr
                             : dd[e] - K.sa[o] * zl - K.sc[o] * zr;
-        if (K.mode == 0) {
+        if (MODE == 0) {
           if (e < m) dd[e] = x; else dz = x;
-        } else if (K.mode == 2) {
+        } else if (MODE == 2) {
           K.u[o] += (double)x;
         } else {
           K.d[o] = x;
         }
       }
   }
-  if (K.mode == 0) {
+  if (MODE == 0) {
     __syncthreads();  // every thread has read the separator values
     if (valid) {
 #pragma unroll
@@ -406,7 +409,23 @@ static void launch_line(Prof* pf, hipStream_t s, LineK<T> K, const char* name) {
     if (rows > work) work = rows;
   }
   const size_t shm = sizeof(T) * (LINE_NTAB * (size_t)K.P * LMAX + work);
-  IBM_LAUNCH(pf, name, s, k_line<T><<<grid, threads, shm, s>>>(K));
+  // fixed-length segments only for the x sweep: unrolled strided z/y
+  // segments need ~190 VGPRs (2 waves per SIMD), slower than the ragged form
+  const bool fixed = (K.mode == 0 && K.r == 0 && K.L == LMAX);
+#define IBM_LINE(M)                                                                   \
+  do {                                                                                \
+    if (fixed)                                                                        \
+      IBM_LAUNCH(pf, name, s, (k_line<T, M, true><<<grid, threads, shm, s>>>(K)));   \
+    else                                                                              \
+      IBM_LAUNCH(pf, name, s, (k_line<T, M, false><<<grid, threads, shm, s>>>(K)));  \
+  } while (0)
+  if (K.mode == 0)
+    IBM_LINE(0);
+  else if (K.mode == 1)
+    IBM_LAUNCH(pf, name, s, (k_line<T, 1, false><<<grid, threads, shm, s>>>(K)));
+  else
+    IBM_LAUNCH(pf, name, s, (k_line<T, 2, false><<<grid, threads, shm, s>>>(K)));
+#undef IBM_LINE
 }
 
 template <typename T>

@@ -97,6 +97,7 @@ struct ibm_ctx {
   // precision of the predictor and spectral work: FP64, or FP32 in the mixed
   // form (element size es); the velocity and phi are FP64 in both
   int fp32 = 0;
+  int pfp32 = 0;  // mixed form: FP32 Poisson transforms with FP64-residual refinement
   size_t es = sizeof(double);
   void* R[3] = {};
   void* H[3] = {};
@@ -406,6 +407,8 @@ int ibm_create(const ibm_grid* gr, const ibm_opts* o, void* stream, ibm_ctx** ou
   if (o->precision != IBM_FP64 && o->precision != IBM_MIXED) FAIL(IBM_EINVAL, "unknown precision");
   if (o->refine_max < 0 || o->refine_max > 16 || o->refine_tol < 0 || !(o->refine_tol == o->refine_tol))
     FAIL(IBM_EINVAL, "refine_max must be 0..16 and refine_tol >= 0");
+  if (o->mixed_poisson != IBM_POISSON_FP64 && o->mixed_poisson != IBM_POISSON_REFINED)
+    FAIL(IBM_EINVAL, "unknown mixed_poisson");
   if (gr->ny > 8192) FAIL(IBM_EINVAL, "ny above 8192");
   if (gr->nx > 1024 || gr->nz > 1024) FAIL(IBM_EINVAL, "nx and nz at most 1024");
   if (o->scheme != IBM_RK2CN && o->scheme != IBM_AB2CN) FAIL(IBM_EINVAL, "unknown scheme");
@@ -435,6 +438,7 @@ int ibm_create(const ibm_grid* gr, const ibm_opts* o, void* stream, ibm_ctx** ou
   c->lz = gr->lz;
   c->opts = *o;
   c->fp32 = (o->precision == IBM_MIXED) ? 1 : 0;
+  c->pfp32 = (c->fp32 && o->mixed_poisson == IBM_POISSON_REFINED) ? 1 : 0;
   c->es = c->fp32 ? sizeof(float) : sizeof(double);
   c->nref = o->refine_max > 0 ? o->refine_max : 3;
   c->rtol = o->refine_tol > 0 ? o->refine_tol : 1e-11;
@@ -553,8 +557,8 @@ int ibm_create(const ibm_grid* gr, const ibm_opts* o, void* stream, ibm_ctx** ou
   TRY(dalloc(c, &c->rhs_tmp, c->ncell));
   TRY(dalloc(c, &c->phi, c->ncell));
   const int64_t nspec = (int64_t)ny * nz * g.nxh;
-  TRY(dalloc_bytes(c, &c->spec, nspec, 2 * c->es));
-  if (c->fp32) {
+  TRY(dalloc_bytes(c, &c->spec, nspec, c->pfp32 ? 2 * sizeof(float) : 2 * sizeof(double)));
+  if (c->pfp32) {
     TRY(dalloc(c, &c->rhs_keep, c->ncell));
     TRY(dalloc(c, &c->rmax, c->nref + 2));
     TRY(dalloc(c, &c->zm, ny));
@@ -562,7 +566,7 @@ int ibm_create(const ibm_grid* gr, const ibm_opts* o, void* stream, ibm_ctx** ou
     // per-block partials of the x passes (at least one x-row per block)
     TRY(dalloc(c, &c->psum, (int64_t)ny * nz));
   }
-  TRY(dalloc(c, &c->rstats, 3));
+  TRY(dalloc(c, &c->rstats, 4));
   TRY(dalloc(c, &c->partial, 5 * 512));  // block partials of the mass sums
   TRY(dalloc(c, &c->qf, 2));              // q_F, or (c0, c1) of the energy shape
   TRY(dalloc(c, &c->flags, 1));
@@ -618,7 +622,7 @@ int ibm_create(const ibm_grid* gr, const ibm_opts* o, void* stream, ibm_ctx** ou
   launch_fill_u32(nullptr, c->stream, c->flags, 1, 0u);
   launch_fill_u64(nullptr, c->stream, reinterpret_cast<u64*>(tb.count), 4, 0ull);
   launch_fill_f64(nullptr, c->stream, c->qf, 2, 0.0);
-  launch_fill_f64(nullptr, c->stream, c->rstats, 3, 0.0);
+  launch_fill_f64(nullptr, c->stream, c->rstats, 4, 0.0);
   if (hipStreamSynchronize(c->stream) != hipSuccess || hipGetLastError() != hipSuccess) {
     free_all(c);
     delete c;
@@ -841,8 +845,9 @@ static PoissonArgs pargs(ibm_ctx* c) {
   a.yhi = c->yhi;
   a.spec = c->spec;
   a.sum_dy = c->sum_dy;
-  a.fp32 = c->fp32;
-  a.refine = c->fp32;
+  a.fp32 = c->pfp32;
+  a.refine = c->pfp32;
+  a.p_fp32 = c->fp32;
   a.nref = c->nref;
   a.tol = c->rtol;
   a.rhs_keep = c->rhs_keep;
@@ -916,9 +921,9 @@ int ibm_step(ibm_ctx* c, ibm_state* s, const ibm_body* b, int32_t nb, double dt)
 int ibm_refine_stats(ibm_ctx* c, double* stats, int32_t reset) {
   if (!c || !stats) FAIL(IBM_EINVAL, "null argument");
   HIPCHK(hipStreamSynchronize(c->stream));
-  HIPCHK(hipMemcpy(stats, c->rstats, 3 * sizeof(double), hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpy(stats, c->rstats, 4 * sizeof(double), hipMemcpyDeviceToHost));
   if (reset) {
-    launch_fill_f64(nullptr, c->stream, c->rstats, 3, 0.0);
+    launch_fill_f64(nullptr, c->stream, c->rstats, 4, 0.0);
     HIPCHK(hipStreamSynchronize(c->stream));
   }
   return IBM_OK;

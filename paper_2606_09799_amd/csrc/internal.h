@@ -207,6 +207,7 @@ struct PoissonArgs {
   void* spec;          // ny*nz*nxh complex: double2, or float2 when fp32
   double sum_dy;
   int fp32;            // FP32 spectrum and transforms
+  int p_fp32;          // the pressure (read by the energy-conserving q) is FP32
   // FP64-residual refinement (mixed form)
   int refine;          // on/off
   int nref;            // refinements at most
@@ -223,7 +224,7 @@ struct PoissonArgs {
 // rhs from an array (rhs != NULL) or formed on the fly from the velocity
 // (rhs == NULL): (D u - q)/alpha_dt on C_F, 0 on C_B, with q = qf[0], or
 // q = qf[0] + qf[1] (p - e) when p != NULL (the energy-conserving shape; p
-// in the precision of the spectrum)
+// FP32 when a.p_fp32)
 void launch_poisson(Prof* pf, hipStream_t s, const GridView& g, const PoissonArgs& a,
                     const double* rhs, const double* u, const double* v, const double* w,
                     const uint32_t* cb_mask, const double* qf, const void* p, double inv_adt,

@@ -170,7 +170,8 @@ struct PoisK {
   const double *u, *v, *w;     // SRC_VELOCITY
   const uint32_t* cb_mask;
   const double* qf;            // q_F, or (c0, c1) of the energy-conserving shape
-  const typename RealOf<C>::T* pq;  // energy-conserving shape: p (else NULL)
+  const void* pq;              // energy-conserving shape: p (else NULL)
+  int pq32;                    // p stored in FP32
   double inv_adt;
   double* rhs_keep;            // FP64 copy of the right-hand side formed in pass 1 (or NULL)
   const double* phi_in;        // SRC_RESIDUAL/CHECK: current phi
@@ -262,7 +263,9 @@ __global__ __launch_bounds__(256) void k_fftx_fwd(PoisK<C> K) {
           const double eu = 0.5 * (u0 * u0 + u1 * u1);
           const double ev = 0.5 * (v0 * v0 + v1 * v1);
           const double ew = 0.5 * (w0 * w0 + w1 * w1);
-          qq = q + q1 * ((double)K.pq[cell] - 0.5 * ((eu + ev) + ew));
+          const double pc = K.pq32 ? (double)static_cast<const float*>(K.pq)[cell]
+                                   : static_cast<const double*>(K.pq)[cell];
+          qq = q + q1 * (pc - 0.5 * ((eu + ev) + ew));
         }
         val = (D - qq) * K.inv_adt;
       }
@@ -628,7 +631,8 @@ __global__ __launch_bounds__(256) void k_sum_partials(const double* __restrict__
 
 // Refinement bookkeeping after one mixed solve: rmax[k] (k = 1..nref) is the
 // residual that opened refinement k (0 if it never ran), rmax[nref+1] the
-// final check.  stats: [solves, corrections, largest final max|r| * adt].
+// final check.  stats: [solves, corrections, largest final max|r| * adt,
+// largest max|r| * adt after the first correction].
 __global__ void k_refine_stats(const u64* rmax, int nref, double tol, double adt, double* stats,
                                uint32_t* flags) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
@@ -644,6 +648,9 @@ __global__ void k_refine_stats(const u64* rmax, int nref, double tol, double adt
   stats[1] += (double)corr;
   const double fin = last * adt;
   if (!(fin <= stats[2])) stats[2] = fin;
+  // the residual left by the first correction (0 when none was needed)
+  const double r2 = (nref >= 2) ? __longlong_as_double((long long)rmax[2]) * adt : 0.0;
+  if (!(r2 <= stats[3])) stats[3] = r2;
 }
 
 template <typename C>
@@ -712,7 +719,8 @@ static void solve(Prof* pf, hipStream_t s, const GridView& g, const PoissonArgs&
   K.w = w;
   K.cb_mask = cb_mask;
   K.qf = qf;
-  K.pq = static_cast<const typename RealOf<C>::T*>(p);
+  K.pq = p;
+  K.pq32 = a.p_fp32;
   K.inv_adt = inv_adt;
   K.spec = reinterpret_cast<C*>(a.spec);
   K.lamx = a.lamx;

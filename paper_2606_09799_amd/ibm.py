@@ -38,7 +38,8 @@ class IbmGrid(ctypes.Structure):
 class IbmOpts(ctypes.Structure):
     _fields_ = [("precision", c_int32), ("scheme", c_int32), ("re", c_double),
                 ("dpdx", c_double), ("force_cap", c_int64), ("use_q", c_int32),
-                ("refine_max", c_int32), ("refine_tol", c_double)]
+                ("refine_max", c_int32), ("refine_tol", c_double),
+                ("mixed_poisson", c_int32), ("reserved", c_int32)]
 
 
 class IbmBody(ctypes.Structure):
@@ -145,12 +146,15 @@ def _dev(t, dtype, numel, name):
 
 class Context:
     """One grid on the current device, bound to torch's current stream.
-    precision: "fp64", or "mixed" (p and H in float32; u, v, w in float64).
+    precision: "fp64", or "mixed" (p and H in float32; u, v, w in float64);
+    mixed_poisson: "fp64" or "refined" (FP32 transforms refined with FP64
+    residuals) for the mixed form.
     use_q: True (uniform q_F), "energy" (mass- and energy-conserving shape)
     or False (standard projection)."""
 
     def __init__(self, nx, ny, nz, lx, lz, y_faces, re, dpdx=0.0, scheme="rk2", use_q=True,
-                 force_cap=0, precision="fp64", refine_max=0, refine_tol=0.0):
+                 force_cap=0, precision="fp64", refine_max=0, refine_tol=0.0,
+                 mixed_poisson="fp64"):
         if precision not in ("fp64", "mixed"):
             raise ValueError("precision: 'fp64' or 'mixed'")
         self.precision = precision
@@ -169,7 +173,7 @@ class Context:
         o = IbmOpts(IBM_MIXED if precision == "mixed" else IBM_FP64,
                     IBM_RK2CN if scheme == "rk2" else IBM_AB2CN, float(re),
                     float(dpdx), int(force_cap), qmode, int(refine_max),
-                    float(refine_tol))
+                    float(refine_tol), 1 if mixed_poisson == "refined" else 0, 0)
         h = c_void_p()
         _ok(_create(ctypes.byref(g), ctypes.byref(o), _stream(), ctypes.byref(h)), "ibm_create")
         self.handle = h
@@ -322,12 +326,14 @@ def ibm_step(ctx, u, v, w, p, bodies, dt, h=None):
     _ok(_step(ctx.handle, ctypes.byref(st), arr, n, float(dt)), "ibm_step")
 
 
-def ibm_refine_stats(ctx, reset=False):
+def ibm_refine_stats(ctx, reset=False, after_first=False):
     """Mixed form: (Poisson solves, FP64-residual corrections, largest final
-    max|rhs - L_c phi| * alpha_dt) since the last reset (synchronises)."""
-    out = (c_double * 3)()
+    max|rhs - L_c phi| * alpha_dt) since the last reset (synchronises); with
+    after_first also the largest residual left by the first correction."""
+    out = (c_double * 4)()
     _ok(_refine_stats(ctx.handle, out, 1 if reset else 0), "ibm_refine_stats")
-    return int(out[0]), int(out[1]), float(out[2])
+    r = (int(out[0]), int(out[1]), float(out[2]))
+    return r + (float(out[3]),) if after_first else r
 
 
 def ibm_check(ctx):
@@ -389,7 +395,8 @@ class Batch:
             opts[s] = IbmOpts(IBM_MIXED if precision == "mixed" else IBM_FP64,
                               IBM_RK2CN if scheme == "rk2" else IBM_AB2CN, float(d["re"]),
                               float(d["dpdx"]), 0,
-                              IBM_Q_ENERGY if use_q == "energy" else (1 if use_q else 0), 0, 0.0)
+                              IBM_Q_ENERGY if use_q == "energy" else (1 if use_q else 0), 0, 0.0,
+                              0, 0)
             cells, vf = nx * ny * nz, nx * (ny + 1) * nz
             st = IbmState(_dev(d["u"], torch.float64, cells, "u"),
                           _dev(d["v"], torch.float64, vf, "v"),

@@ -1,8 +1,8 @@
 """The mixed-precision form against the FP64 oracle (through the C-ABI).
 
 The mixed form keeps u, v, w in FP64 and stores p, H, the predictor
-right-hand side, the line-solve intermediates and the Poisson spectrum in
-FP32; each Poisson solve is refined with FP64 residuals until
+right-hand side and the line-solve intermediates in FP32.  Its Poisson solve
+is FP64 (the default), or FP32 transforms refined with FP64 residuals until
 max|rhs - L_c phi| * alpha_dt <= 1e-11, which after the projection is
 max|D u - q| (paper Eq. mod_div).  Bars: tags bit-exact (the geometry is FP64
 in both forms); velocity after whole steps within 1e-6 relative of the FP64
@@ -67,7 +67,7 @@ def test_mixed_viscous(name, stage):
 def test_mixed_poisson_refined(name):
     """FP32 transforms + FP64-residual refinement reach the requested
     residual; the result agrees with the FP64 oracle solve."""
-    case = Case(name, precision="mixed", refine_tol=1e-9)
+    case = Case(name, precision="mixed", mixed_poisson="refined", refine_tol=1e-9)
     g = case.g
     rng = np.random.default_rng(5)
     rhs = rng.standard_normal(g.shape)
@@ -88,7 +88,7 @@ def test_mixed_poisson_refined(name):
 
 
 def test_mixed_poisson_aliased_rhs():
-    case = Case("tiny", precision="mixed", refine_tol=1e-9)
+    case = Case("tiny", precision="mixed", mixed_poisson="refined", refine_tol=1e-9)
     g = case.g
     rng = np.random.default_rng(8)
     rhs = rng.standard_normal(g.shape)
@@ -103,7 +103,8 @@ def test_mixed_poisson_aliased_rhs():
 def test_mixed_refinement_flag():
     """An unreachable tolerance with one refinement allowed: exactly one
     correction runs and the sticky flag reports it (forced from the host)."""
-    case = Case("tiny", precision="mixed", refine_max=1, refine_tol=1e-300)
+    case = Case("tiny", precision="mixed", mixed_poisson="refined", refine_max=1,
+                refine_tol=1e-300)
     g = case.g
     rng = np.random.default_rng(9)
     rhs = rng.standard_normal(g.shape)
@@ -135,8 +136,8 @@ def test_mixed_project(name):
     assert rel(n(pd, g.shape).astype(np.float64), pref) < 1e-7
 
 
-def _run_mixed(name, steps):
-    case = Case(name, precision="mixed")
+def _run_mixed(name, steps, mixed_poisson):
+    case = Case(name, precision="mixed", mixed_poisson=mixed_poisson)
     g, wl = case.g, case.wl
     f = wl.fields()
     d = [t(a) for a in f]
@@ -158,17 +159,19 @@ def _run_mixed(name, steps):
     return case, g, d, pd, f, p, tags, worst_div
 
 
+@pytest.mark.parametrize("mixed_poisson", ["fp64", "refined"])
 @pytest.mark.parametrize("name,steps", [("tiny", 3), ("tiny_plate", 3), ("c1", 10)])
-def test_mixed_step_against_fp64_oracle(name, steps):
-    case, g, d, pd, f, p, tags, worst_div = _run_mixed(name, steps)
+def test_mixed_step_against_fp64_oracle(name, steps, mixed_poisson):
+    case, g, d, pd, f, p, tags, worst_div = _run_mixed(name, steps, mixed_poisson)
     _tags_equal(case, tags)
     for c in range(3):
         assert rel(n(d[c], f[c].shape), f[c]) < 1e-6, c
     assert worst_div < 1e-10
-    solves, corr, final = case.ibm.ibm_refine_stats(case.ctx)
-    assert solves == 2 * steps
-    assert final <= 1e-11
-    assert corr <= 3 * solves
+    if mixed_poisson == "refined":
+        solves, corr, final = case.ibm.ibm_refine_stats(case.ctx)
+        assert solves == 2 * steps
+        assert final <= 1e-11
+        assert corr <= 3 * solves
     mB = projection.cell_mask(g, tags.cb)
     dV = g.cell_volume()
     got = n(pd, g.shape).astype(np.float64)
