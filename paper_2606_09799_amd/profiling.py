@@ -14,7 +14,8 @@ what each counter reports for it scales the counter for every kernel.
 
     python -m paper_2606_09799_amd.profiling --tag c2_fp64 \\
         --trace gpurun_out/trace_c2 --fetch gpurun_out/pmc_fetch \\
-        --write gpurun_out/pmc_write --copy-mib 1024 --cmd "<bench args>"
+        --write gpurun_out/pmc_write --copy-mib 1024 \\
+        --trace-cmd "<bench.py args>" --pmc-cmd "<bench.py args>"
 """
 from __future__ import annotations
 
@@ -74,14 +75,14 @@ def pmc_per_kernel(path_dir: str):
     return out
 
 
-def summarise(tag, trace, fetch, write, copy_mib, cmd, workload):
+def summarise(tag, trace, fetch, write, copy_mib, trace_cmd, pmc_cmd, workload):
     sha = csrc_sha()
     with open(_one(trace, "kernel_stats.csv")) as f:
         stats = list(csv.DictReader(f))
     lines = [f"# Kernel trace, {workload}, rocprofv3 --stats", "",
              "Command (from the repository root on one MI355X):", "",
              "    cd /tmp && export TMPDIR=/tmp && rocprofv3 --kernel-trace --stats "
-             f"--output-format csv -d $REPO/{trace} -o run -- python3 $REPO/bench.py {cmd}",
+             f"--output-format csv -d $REPO/{trace} -o run -- python3 $REPO/bench.py {trace_cmd}",
              "", f"Kernel sources hash (paper_2606_09799_amd/csrc): `{sha}`", "",
              "| kernel | calls | total ms | average us | share % |", "|---|---|---|---|---|"]
     for r in stats[:32]:
@@ -101,9 +102,9 @@ def summarise(tag, trace, fetch, write, copy_mib, cmd, workload):
     lines = [f"# HBM traffic per dispatch, {workload}, rocprofv3 --pmc", "",
              "Two passes, one counter each (from the repository root on one MI355X):", "",
              "    cd /tmp && export TMPDIR=/tmp && rocprofv3 --pmc FETCH_SIZE --output-format csv "
-             f"-d $REPO/{fetch} -o run -- python3 $REPO/bench.py {cmd} --copy-ref-mib {copy_mib}",
+             f"-d $REPO/{fetch} -o run -- python3 $REPO/bench.py {pmc_cmd} --copy-ref-mib {copy_mib}",
              "    cd /tmp && export TMPDIR=/tmp && rocprofv3 --pmc WRITE_SIZE --output-format csv "
-             f"-d $REPO/{write} -o run -- python3 $REPO/bench.py {cmd} --copy-ref-mib {copy_mib}",
+             f"-d $REPO/{write} -o run -- python3 $REPO/bench.py {pmc_cmd} --copy-ref-mib {copy_mib}",
              "", "Summary: `python -m paper_2606_09799_amd.profiling` (this module).", "",
              f"Scale factors from the plain {copy_mib} MiB device copy of the same runs "
              f"({ref_kib:.0f} KiB read and written): FETCH_SIZE reads {cf:.0f} KiB -> x{fs:.3f}; "
@@ -136,10 +137,12 @@ def main():
     ap.add_argument("--fetch", required=True)
     ap.add_argument("--write", required=True)
     ap.add_argument("--copy-mib", type=int, default=1024)
-    ap.add_argument("--cmd", default="", help="the bench.py arguments of the profiled runs")
+    ap.add_argument("--trace-cmd", default="", help="bench.py arguments of the traced run")
+    ap.add_argument("--pmc-cmd", default="", help="bench.py arguments of the counter runs")
     ap.add_argument("--workload", default="256x192x256 plate workload")
     a = ap.parse_args()
-    print(summarise(a.tag, a.trace, a.fetch, a.write, a.copy_mib, a.cmd, a.workload))
+    print(summarise(a.tag, a.trace, a.fetch, a.write, a.copy_mib, a.trace_cmd, a.pmc_cmd,
+                    a.workload))
 
 
 if __name__ == "__main__":
