@@ -97,7 +97,7 @@ __device__ void reduced_solve_cyclic(Acc A, int P) {
 // carries only its own addressing).  FIXED: every segment holds exactly LMAX
 // rows (n = P * LMAX), so the segment loops have no runtime bounds.
 template <typename T, int MODE, bool FIXED>
-__global__ __launch_bounds__(256) void k_line(LineK<T> K) {
+__global__ __launch_bounds__(MODE == 0 ? 256 : 1024) void k_line(LineK<T> K) {
   extern __shared__ __align__(16) unsigned char ldsraw[];
   T* lds = reinterpret_cast<T*>(ldsraw);
   const int tid = threadIdx.x;
@@ -398,8 +398,11 @@ static void launch_line(Prof* pf, hipStream_t s, LineK<T> K, const char* name) {
     const int64_t rows = (int64_t)K.nj * K.nz;
     grid = dim3((unsigned)((rows + K.tl - 1) / K.tl));
   } else {
-    K.tl = 256 / K.P;
+    // 16 consecutive lines per block whenever the segments allow (a
+    // wavefront's loads then cover 128-byte row pieces), up to 1024 threads
+    K.tl = 1024 / K.P;
     if (K.tl > 16) K.tl = 16;
+    if (K.tl < 1) K.tl = 1;
     threads = K.tl * K.P;
     grid = dim3((K.nx + K.tl - 1) / K.tl, K.mode == 1 ? K.nj : K.nz);
   }
