@@ -210,7 +210,8 @@ int ibm_force(ibm_ctx* ctx, double* u, double* v, double* w);
  * b = alpha dt/(2 Re), with identity rows on the forcing nodes; then
  * u <- u + du.  gamma, rho: the sub-stage coefficients; h_prev (read when
  * rho != 0) and h_out (written when not NULL): dev f32/f64 arrays of H per
- * component (NULL entries allowed).  p: dev f32/f64.  u, v, w: dev f64, in
+ * component, all three given (IBM_EINVAL if h_out names only some).  p: dev
+ * f32/f64.  u, v, w: dev f64, in
  * place (the mixed form computes R and H in FP64 arithmetic, stores them in
  * FP32, solves the three factors in FP32 and adds du to the FP64 u). */
 int ibm_viscous(ibm_ctx* ctx, const void* p, const void* const* h_prev,

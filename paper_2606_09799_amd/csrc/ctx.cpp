@@ -789,6 +789,8 @@ static int viscous(ibm_ctx* c, const void* p, const void* const* hprev, void* co
   }
   if (rho != 0.0 && (!a.hprev[0] || !a.hprev[1] || !a.hprev[2]))
     FAIL(IBM_EINVAL, "rho != 0 needs the previous H");
+  if ((a.hout[0] || a.hout[1] || a.hout[2]) && !(a.hout[0] && a.hout[1] && a.hout[2]))
+    FAIL(IBM_EINVAL, "h_out: all three components or none");
   a.gamma = gamma;
   a.rho = rho;
   a.alpha = alpha;

@@ -15,6 +15,12 @@
 // ~50 neighbour reads thus cost LDS reads instead of vector-memory
 // instructions, which otherwise saturate the address units.
 //
+// Every global load of a step is issued one step ahead: the planes of the
+// next step, this thread's H_prev values and forcing-mask words.  Vector
+// loads complete in issue order, so a load issued late in a step and waited
+// for at once would also wait for the whole prefetch; the wall-normal metric
+// coefficients of the chunk are therefore staged in LDS at the start.
+//
 // Storage type T of p, H and R: double, or float in the mixed form.  The
 // stencil arithmetic is FP64 in both forms: the velocity is FP64, and
 // rounding it to FP32 before differencing would amplify its rounding error by
@@ -29,6 +35,10 @@ constexpr int RPL = RHX * RHZ;              // values per plane in LDS
 constexpr int RJC = 16;                     // planes per block
 // ring slots: u 0..2, v 3..5, w 6..8, p 9..10
 constexpr int RSLOTS = 11;
+// metric coefficients of a chunk after the ring: idy[j0-1 .. j0+JC-1],
+// idyc[j0 .. j0+JC], fw0[j0 .. j0+JC], fw1[j0 .. j0+JC]
+constexpr int RCN = RJC + 1;
+constexpr int RCOEF = 4 * RCN;
 
 template <typename T>
 struct RhsK {
@@ -47,8 +57,9 @@ constexpr int RPT = (RPL + RTX * RTZ - 1) / (RTX * RTZ);
 
 // Offsets within a plane of this thread's halo elements e = tid + q*threads
 // of the tile (i0, k0), with the periodic wrap (i >= -1 and k >= -1; grids
-// narrower than the tile wrap more than once); -1 past the tile.  The same
-// for every plane, so computed once per block.
+// narrower than the tile wrap more than once); 0 past the tile (read, never
+// stored: the loads stay unconditional).  The same for every plane, so
+// computed once per block.
 __device__ __forceinline__ void halo_offsets(int (&off)[RPT], const GridView& g, int i0, int k0) {
 #pragma unroll
   for (int q = 0; q < RPT; ++q) {
@@ -57,7 +68,7 @@ __device__ __forceinline__ void halo_offsets(int (&off)[RPT], const GridView& g,
     int i = i0 - 1 + lx, k = k0 - 1 + lz;
     i = (i < 0) ? i + g.nx : (i >= g.nx ? (i - g.nx) % g.nx : i);
     k = (k < 0) ? k + g.nz : (k >= g.nz ? (k - g.nz) % g.nz : k);
-    off[q] = (e < RPL) ? k * g.nx + i : -1;
+    off[q] = (e < RPL) ? k * g.nx + i : 0;
   }
 }
 
@@ -67,29 +78,39 @@ __device__ __forceinline__ void fetch_plane(double (&r)[RPT], const S* __restric
                                             const GridView& g, const int (&off)[RPT]) {
   const S* fp = f + (int64_t)j * g.nz * g.nx;
 #pragma unroll
-  for (int q = 0; q < RPT; ++q) r[q] = (off[q] >= 0) ? (double)fp[off[q]] : 0.0;
+  for (int q = 0; q < RPT; ++q) r[q] = (double)fp[off[q]];
 }
 
-// load plane j of a field into LDS slot `slot`
+// load plane j of a field into the LDS slot at offset sb
 template <typename S>
-__device__ __forceinline__ void load_plane(double* lds, int slot, const S* __restrict__ f, int j,
+__device__ __forceinline__ void load_plane(double* lds, int sb, const S* __restrict__ f, int j,
                                            const GridView& g, const int (&off)[RPT]) {
   const S* fp = f + (int64_t)j * g.nz * g.nx;
 #pragma unroll
   for (int q = 0; q < RPT; ++q)
-    if (off[q] >= 0) lds[slot * RPL + threadIdx.x + q * RTX * RTZ] = (double)fp[off[q]];
+    if (threadIdx.x + q * RTX * RTZ < RPL) lds[sb + threadIdx.x + q * RTX * RTZ] = (double)fp[off[q]];
 }
 
-__device__ __forceinline__ void put_plane(double* lds, int slot, const double (&r)[RPT]) {
+__device__ __forceinline__ void put_plane(double* lds, int sb, const double (&r)[RPT]) {
 #pragma unroll
   for (int q = 0; q < RPT; ++q) {
     const int e = threadIdx.x + q * RTX * RTZ;
-    if (e < RPL) lds[slot * RPL + e] = r[q];
+    if (e < RPL) lds[sb + e] = r[q];
   }
 }
 
-template <typename T>
-__global__ __launch_bounds__(RTX * RTZ) void k_rhs(RhsK<T> K) {
+// Flags of a launch, fixed at compile time so that the march is straight-line
+// code: the waits the compiler inserts for the prefetched loads then count
+// exactly the loads and stores issued after them.
+enum : int {
+  RHS_FULL = 1,  // nx and nz are multiples of the tile: every thread owns a cell
+  RHS_HPREV = 2, // rho != 0: H_prev is read
+  RHS_HOUT = 4,  // H is written (all three components)
+};
+
+template <typename T, int F>
+__global__ __launch_bounds__(RTX * RTZ) __attribute__((amdgpu_waves_per_eu(4))) void k_rhs(RhsK<T> K) {
+  constexpr bool FULL = F & RHS_FULL, HPREV = F & RHS_HPREV, HOUT = F & RHS_HOUT;
   extern __shared__ double lds[];
   const GridView& g = K.g;
   const RhsK<T>& a = K;
@@ -102,153 +123,211 @@ __global__ __launch_bounds__(RTX * RTZ) void k_rhs(RhsK<T> K) {
   const int j1 = (j0 + RJC < g.ny) ? j0 + RJC : g.ny;
   const int tx = threadIdx.x % RTX, tz = threadIdx.x / RTX;
   const int i = i0 + tx, k = k0 + tz;
-  const bool valid = i < g.nx && k < g.nz;
+  const bool valid = FULL || (i < g.nx && k < g.nz);
   const int lx = tx + 1, lz = tz + 1;
   const double idx = g.idx, idz = g.idz;
   const double idx2 = idx * idx, idz2 = idz * idz;
   const double am = a.alpha / a.re;
   const int64_t plane = (int64_t)g.nz * g.nx;
-  // value of a ring slot at an offset from this thread's cell
-  auto S = [&](int slot, int dx, int dz) -> double {
-    return lds[slot * RPL + (lz + dz) * RHX + (lx + dx)];
-  };
-  auto su = [](int jj) { return (jj + 3) % 3; };
-  auto sv = [](int jj) { return 3 + (jj + 3) % 3; };
-  auto sw = [](int jj) { return 6 + (jj + 3) % 3; };
-  auto sp = [](int jj) { return 9 + (jj + 2) % 2; };
+  // value of a ring slot (base offset sb = slot * RPL) at an offset from this
+  // thread's cell
+  const int me = lz * RHX + lx;
+  auto S = [&](int sb, int dx, int dz) -> double { return lds[sb + me + dz * RHX + dx]; };
   int off[RPT];
   halo_offsets(off, g, i0, k0);
+  // the chunk's metric coefficients (only entries the chunk reads)
+  double* cf = lds + RSLOTS * RPL;
+  for (int q = threadIdx.x; q < RCOEF; q += RTX * RTZ) {
+    const int arr = q / RCN, e = q % RCN;
+    double val = 0.0;
+    if (arr == 0) {
+      const int jj = j0 - 1 + e;
+      if (jj >= 0 && jj < j1) val = g.idy[jj];
+    } else {
+      const int jj = j0 + e;  // <= j1 <= ny
+      if (jj <= j1) val = (arr == 1 ? g.idyc : (arr == 2 ? g.fw0 : g.fw1))[jj];
+    }
+    cf[q] = val;
+  }
+  // ring slot bases: [0] plane j-1, [1] plane j, [2] plane j+1 (rotated each
+  // step); p keeps j-1 and j
+  int bu[3], bv[3], bw[3], bp[2];
+  for (int q = 0; q < 3; ++q) {
+    const int r = (j0 - 1 + q + 3) % 3;
+    bu[q] = r * RPL;
+    bv[q] = (3 + r) * RPL;
+    bw[q] = (6 + r) * RPL;
+  }
+  for (int q = 0; q < 2; ++q) bp[q] = (9 + (j0 - 1 + q + 2) % 2) * RPL;
   // ring before the first step: u, v, w at j0-1, j0, j0+1 and p at j0-1, j0
   if (j0 > 0) {
-    load_plane(lds, su(j0 - 1), a.u, j0 - 1, g, off);
-    load_plane(lds, sv(j0 - 1), a.v, j0 - 1, g, off);
-    load_plane(lds, sw(j0 - 1), a.w, j0 - 1, g, off);
-    load_plane(lds, sp(j0 - 1), a.p, j0 - 1, g, off);
+    load_plane(lds, bu[0], a.u, j0 - 1, g, off);
+    load_plane(lds, bv[0], a.v, j0 - 1, g, off);
+    load_plane(lds, bw[0], a.w, j0 - 1, g, off);
+    load_plane(lds, bp[0], a.p, j0 - 1, g, off);
   }
-  load_plane(lds, su(j0), a.u, j0, g, off);
-  load_plane(lds, sv(j0), a.v, j0, g, off);
-  load_plane(lds, sw(j0), a.w, j0, g, off);
-  load_plane(lds, sp(j0), a.p, j0, g, off);
+  load_plane(lds, bu[1], a.u, j0, g, off);
+  load_plane(lds, bv[1], a.v, j0, g, off);
+  load_plane(lds, bw[1], a.w, j0, g, off);
+  load_plane(lds, bp[1], a.p, j0, g, off);
   if (j0 + 1 < g.ny) {
-    load_plane(lds, su(j0 + 1), a.u, j0 + 1, g, off);
-    load_plane(lds, sw(j0 + 1), a.w, j0 + 1, g, off);
+    load_plane(lds, bu[2], a.u, j0 + 1, g, off);
+    load_plane(lds, bw[2], a.w, j0 + 1, g, off);
   }
-  load_plane(lds, sv(j0 + 1), a.v, j0 + 1, g, off);  // v has ny+1 planes
+  load_plane(lds, bv[2], a.v, j0 + 1, g, off);  // v has ny+1 planes
+  // this thread's column (threads past a ragged edge read the last cell and
+  // store nothing)
+  const int64_t col = (int64_t)(k < g.nz ? k : g.nz - 1) * g.nx + (i < g.nx ? i : g.nx - 1);
+  // the wall planes of v (j = 0 and ny): R = H = 0; plane 0 is also written
+  // by the march
+  if (j0 == 0 && valid) {
+    const int64_t top = (int64_t)g.ny * plane + col;
+    a.R[1][top] = (T)0;
+    if (HOUT) a.hout[1][top] = (T)0;
+  }
+  // this thread's H_prev values and mask words of a step, loaded a step ahead
+  double hp0 = 0.0, hp1 = 0.0, hp2 = 0.0;
+  uint32_t mw0, mw1, mw2;
+  auto fetch_cell = [&](int j) {
+    const int64_t c = (int64_t)j * plane + col;
+    mw0 = a.mask[0][c >> 5];
+    mw1 = a.mask[1][c >> 5];
+    mw2 = a.mask[2][c >> 5];
+    if (HPREV) {
+      hp0 = (double)a.hprev[0][c];
+      hp1 = (double)a.hprev[1][c];
+      hp2 = (double)a.hprev[2][c];
+    }
+  };
   // software pipeline: the planes of the next step (u, v, w at j+2 and p at
-  // j+1) are in flight in registers while plane j is computed
+  // j+1) are in flight in registers while plane j is computed.  The loads are
+  // unconditional (plane indices clamped; a clamped plane is never stored),
+  // so every step issues the same loads in the same order.
   double nu[RPT], nv[RPT], nw[RPT], np[RPT];
   auto fetch_next = [&](int j) {
-    if (j + 2 < g.ny) {
-      fetch_plane(nu, a.u, j + 2, g, off);
-      fetch_plane(nw, a.w, j + 2, g, off);
-    }
-    if (j + 2 <= g.ny) fetch_plane(nv, a.v, j + 2, g, off);
-    if (j + 1 < g.ny) fetch_plane(np, a.p, j + 1, g, off);
+    const int ju = (j + 2 < g.ny) ? j + 2 : g.ny - 1;
+    const int jv = (j + 2 <= g.ny) ? j + 2 : g.ny;
+    const int jp = (j + 1 < g.ny) ? j + 1 : g.ny - 1;
+    fetch_plane(nu, a.u, ju, g, off);
+    fetch_plane(nw, a.w, ju, g, off);
+    fetch_plane(nv, a.v, jv, g, off);
+    fetch_plane(np, a.p, jp, g, off);
   };
-  if (j0 + 1 < j1) fetch_next(j0);
+  fetch_cell(j0);
+  fetch_next(j0);
   __syncthreads();
   for (int j = j0; j < j1; ++j) {
+    const int64_t c = (int64_t)j * plane + col;
+    const int cj = j - j0;
+    const double idyj = cf[cj + 1];
+    const bool has_s = j > 0, has_n = j + 1 < g.ny;
+    const double ic_n = cf[RCN + cj + 1], ic_s = cf[RCN + cj];
+    // weights of the face interpolations at faces j+1 (north) and j (south)
+    const double n0 = cf[2 * RCN + cj + 1], n1 = cf[3 * RCN + cj + 1];
+    const double s0 = cf[2 * RCN + cj], s1 = cf[3 * RCN + cj];
+    const int U0 = bu[1], Um = bu[0], Up = bu[2];
+    const int V0 = bv[1], Vm = bv[0], Vp = bv[2];
+    const int W0 = bw[1], Wm = bw[0], Wp = bw[2];
+    const int P0 = bp[1], Pm = bp[0];
+    const uint32_t bit = (uint32_t)(c & 31);
+    double r_u, r_v = 0.0, r_w, h_u, h_v = 0.0, h_w;
+    // ---------------------------------------------------------- u node
+    {
+      const double uc = S(U0, 0, 0), ue = S(U0, 1, 0), uw = S(U0, -1, 0);
+      const double ut = S(U0, 0, 1), ub = S(U0, 0, -1);
+      const double un = has_n ? S(Up, 0, 0) : 0.0;
+      const double us = has_s ? S(Um, 0, 0) : 0.0;
+      const double bp_ = 0.5 * (uc + ue), bm = 0.5 * (uw + uc);
+      const double tx_ = (bp_ * bp_ - bm * bm) * idx;
+      const double iyn = has_n ? uc * n0 + un * n1 : 0.0;
+      const double iys = has_s ? us * s0 + uc * s1 : 0.0;
+      const double vn = 0.5 * (S(Vp, -1, 0) + S(Vp, 0, 0));
+      const double vs = 0.5 * (S(V0, -1, 0) + S(V0, 0, 0));
+      const double ty = (iyn * vn - iys * vs) * idyj;
+      const double fzp = (0.5 * (uc + ut)) * (0.5 * (S(W0, -1, 1) + S(W0, 0, 1)));
+      const double fzm = (0.5 * (ub + uc)) * (0.5 * (S(W0, -1, 0) + S(W0, 0, 0)));
+      const double tz = (fzp - fzm) * idz;
+      const double H = -(tx_ + ty + tz);
+      const double L = ((ue - uc) - (uc - uw)) * idx2 + ((ut - uc) - (uc - ub)) * idz2 +
+                       ((un - uc) * ic_n - (uc - us) * ic_s) * idyj;
+      const double gp = (S(P0, 0, 0) - S(P0, -1, 0)) * idx;
+      double r = a.gamma * H - a.alpha * (gp - a.fx) + am * L;
+      if (HPREV) r += a.rho * hp0;
+      h_u = H;
+      r_u = ((mw0 >> bit) & 1u) ? 0.0 : a.dt * r;
+    }
+    // ---------------------------------------------------------- w node
+    {
+      const double wc = S(W0, 0, 0), we = S(W0, 1, 0), ww = S(W0, -1, 0);
+      const double wt = S(W0, 0, 1), wb = S(W0, 0, -1);
+      const double wn = has_n ? S(Wp, 0, 0) : 0.0;
+      const double ws = has_s ? S(Wm, 0, 0) : 0.0;
+      const double bp_ = 0.5 * (wc + wt), bm = 0.5 * (wb + wc);
+      const double tz = (bp_ * bp_ - bm * bm) * idz;
+      const double iyn = has_n ? wc * n0 + wn * n1 : 0.0;
+      const double iys = has_s ? ws * s0 + wc * s1 : 0.0;
+      const double vn = 0.5 * (S(Vp, 0, -1) + S(Vp, 0, 0));
+      const double vs = 0.5 * (S(V0, 0, -1) + S(V0, 0, 0));
+      const double ty = (iyn * vn - iys * vs) * idyj;
+      const double fxp = (0.5 * (wc + we)) * (0.5 * (S(U0, 1, -1) + S(U0, 1, 0)));
+      const double fxm = (0.5 * (ww + wc)) * (0.5 * (S(U0, 0, -1) + S(U0, 0, 0)));
+      const double tx_ = (fxp - fxm) * idx;
+      const double H = -(tx_ + ty + tz);
+      const double L = ((we - wc) - (wc - ww)) * idx2 + ((wt - wc) - (wc - wb)) * idz2 +
+                       ((wn - wc) * ic_n - (wc - ws) * ic_s) * idyj;
+      const double gp = (S(P0, 0, 0) - S(P0, 0, -1)) * idz;
+      double r = a.gamma * H - a.alpha * gp + am * L;
+      if (HPREV) r += a.rho * hp2;
+      h_w = H;
+      r_w = ((mw2 >> bit) & 1u) ? 0.0 : a.dt * r;
+    }
+    // ---------------------------------------------------- v node (face j)
+    if (j > 0) {  // face 0 is the wall: R = H = 0
+      const double vc = S(V0, 0, 0), ve = S(V0, 1, 0), vw = S(V0, -1, 0);
+      const double vt = S(V0, 0, 1), vb = S(V0, 0, -1);
+      const double vn = S(Vp, 0, 0), vs = S(Vm, 0, 0);
+      const double uy_i = S(Um, 0, 0) * s0 + S(U0, 0, 0) * s1;
+      const double uy_ip = S(Um, 1, 0) * s0 + S(U0, 1, 0) * s1;
+      const double tx_ = (uy_ip * (0.5 * (vc + ve)) - uy_i * (0.5 * (vw + vc))) * idx;
+      const double ct = 0.5 * (vc + vn), cs = 0.5 * (vs + vc);
+      const double ty = (ct * ct - cs * cs) * ic_s;
+      const double wy_k = S(Wm, 0, 0) * s0 + S(W0, 0, 0) * s1;
+      const double wy_kp = S(Wm, 0, 1) * s0 + S(W0, 0, 1) * s1;
+      const double tz = (wy_kp * (0.5 * (vc + vt)) - wy_k * (0.5 * (vb + vc))) * idz;
+      const double H = -(tx_ + ty + tz);
+      const double L = ((ve - vc) - (vc - vw)) * idx2 + ((vt - vc) - (vc - vb)) * idz2 +
+                       ((vn - vc) * idyj - (vc - vs) * cf[cj]) * ic_s;
+      const double gp = (S(P0, 0, 0) - S(Pm, 0, 0)) * ic_s;
+      double r = a.gamma * H - a.alpha * gp + am * L;
+      if (HPREV) r += a.rho * hp1;
+      h_v = H;
+      r_v = ((mw1 >> bit) & 1u) ? 0.0 : a.dt * r;
+    }
     if (valid) {
-      const int64_t c = (int64_t)j * plane + (int64_t)k * g.nx + i;
-      const double idyj = g.idy[j];
-      const bool has_s = j > 0, has_n = j + 1 < g.ny;
-      const double ic_n = g.idyc[j + 1], ic_s = g.idyc[j];
-      // weights of the face interpolations at faces j+1 (north) and j (south)
-      const double n0 = g.fw0[j + 1], n1 = g.fw1[j + 1], s0 = g.fw0[j], s1 = g.fw1[j];
-      const int U0 = su(j), Um = su(j - 1), Up = su(j + 1);
-      const int V0 = sv(j), Vm = sv(j - 1), Vp = sv(j + 1);
-      const int W0 = sw(j), Wm = sw(j - 1), Wp = sw(j + 1);
-      const int P0 = sp(j), Pm = sp(j - 1);
-      // ---------------------------------------------------------- u node
-      {
-        const double uc = S(U0, 0, 0), ue = S(U0, 1, 0), uw = S(U0, -1, 0);
-        const double ut = S(U0, 0, 1), ub = S(U0, 0, -1);
-        const double un = has_n ? S(Up, 0, 0) : 0.0;
-        const double us = has_s ? S(Um, 0, 0) : 0.0;
-        const double bp = 0.5 * (uc + ue), bm = 0.5 * (uw + uc);
-        const double tx_ = (bp * bp - bm * bm) * idx;
-        const double iyn = has_n ? uc * n0 + un * n1 : 0.0;
-        const double iys = has_s ? us * s0 + uc * s1 : 0.0;
-        const double vn = 0.5 * (S(Vp, -1, 0) + S(Vp, 0, 0));
-        const double vs = 0.5 * (S(V0, -1, 0) + S(V0, 0, 0));
-        const double ty = (iyn * vn - iys * vs) * idyj;
-        const double fzp = (0.5 * (uc + ut)) * (0.5 * (S(W0, -1, 1) + S(W0, 0, 1)));
-        const double fzm = (0.5 * (ub + uc)) * (0.5 * (S(W0, -1, 0) + S(W0, 0, 0)));
-        const double tz = (fzp - fzm) * idz;
-        const double H = -(tx_ + ty + tz);
-        const double L = ((ue - uc) - (uc - uw)) * idx2 + ((ut - uc) - (uc - ub)) * idz2 +
-                         ((un - uc) * ic_n - (uc - us) * ic_s) * idyj;
-        const double gp = (S(P0, 0, 0) - S(P0, -1, 0)) * idx;
-        double r = a.gamma * H - a.alpha * (gp - a.fx) + am * L;
-        if (a.rho != 0.0) r += a.rho * (double)a.hprev[0][c];
-        if (a.hout[0]) a.hout[0][c] = (T)H;
-        a.R[0][c] = (T)(test_bit(a.mask[0], c) ? 0.0 : a.dt * r);
-      }
-      // ---------------------------------------------------------- w node
-      {
-        const double wc = S(W0, 0, 0), we = S(W0, 1, 0), ww = S(W0, -1, 0);
-        const double wt = S(W0, 0, 1), wb = S(W0, 0, -1);
-        const double wn = has_n ? S(Wp, 0, 0) : 0.0;
-        const double ws = has_s ? S(Wm, 0, 0) : 0.0;
-        const double bp = 0.5 * (wc + wt), bm = 0.5 * (wb + wc);
-        const double tz = (bp * bp - bm * bm) * idz;
-        const double iyn = has_n ? wc * n0 + wn * n1 : 0.0;
-        const double iys = has_s ? ws * s0 + wc * s1 : 0.0;
-        const double vn = 0.5 * (S(Vp, 0, -1) + S(Vp, 0, 0));
-        const double vs = 0.5 * (S(V0, 0, -1) + S(V0, 0, 0));
-        const double ty = (iyn * vn - iys * vs) * idyj;
-        const double fxp = (0.5 * (wc + we)) * (0.5 * (S(U0, 1, -1) + S(U0, 1, 0)));
-        const double fxm = (0.5 * (ww + wc)) * (0.5 * (S(U0, 0, -1) + S(U0, 0, 0)));
-        const double tx_ = (fxp - fxm) * idx;
-        const double H = -(tx_ + ty + tz);
-        const double L = ((we - wc) - (wc - ww)) * idx2 + ((wt - wc) - (wc - wb)) * idz2 +
-                         ((wn - wc) * ic_n - (wc - ws) * ic_s) * idyj;
-        const double gp = (S(P0, 0, 0) - S(P0, 0, -1)) * idz;
-        double r = a.gamma * H - a.alpha * gp + am * L;
-        if (a.rho != 0.0) r += a.rho * (double)a.hprev[2][c];
-        if (a.hout[2]) a.hout[2][c] = (T)H;
-        a.R[2][c] = (T)(test_bit(a.mask[2], c) ? 0.0 : a.dt * r);
-      }
-      // ---------------------------------------------------- v node (face j)
-      if (j == 0) {
-        const int64_t top = (int64_t)g.ny * plane + (int64_t)k * g.nx + i;
-        a.R[1][c] = (T)0;  // wall planes
-        a.R[1][top] = (T)0;
-        if (a.hout[1]) {
-          a.hout[1][c] = (T)0;
-          a.hout[1][top] = (T)0;
-        }
-      } else {
-        const double vc = S(V0, 0, 0), ve = S(V0, 1, 0), vw = S(V0, -1, 0);
-        const double vt = S(V0, 0, 1), vb = S(V0, 0, -1);
-        const double vn = S(Vp, 0, 0), vs = S(Vm, 0, 0);
-        const double uy_i = S(Um, 0, 0) * s0 + S(U0, 0, 0) * s1;
-        const double uy_ip = S(Um, 1, 0) * s0 + S(U0, 1, 0) * s1;
-        const double tx_ = (uy_ip * (0.5 * (vc + ve)) - uy_i * (0.5 * (vw + vc))) * idx;
-        const double ct = 0.5 * (vc + vn), cs = 0.5 * (vs + vc);
-        const double ty = (ct * ct - cs * cs) * ic_s;
-        const double wy_k = S(Wm, 0, 0) * s0 + S(W0, 0, 0) * s1;
-        const double wy_kp = S(Wm, 0, 1) * s0 + S(W0, 0, 1) * s1;
-        const double tz = (wy_kp * (0.5 * (vc + vt)) - wy_k * (0.5 * (vb + vc))) * idz;
-        const double H = -(tx_ + ty + tz);
-        const double L = ((ve - vc) - (vc - vw)) * idx2 + ((vt - vc) - (vc - vb)) * idz2 +
-                         ((vn - vc) * idyj - (vc - vs) * g.idy[j - 1]) * ic_s;
-        const double gp = (S(P0, 0, 0) - S(Pm, 0, 0)) * ic_s;
-        double r = a.gamma * H - a.alpha * gp + am * L;
-        if (a.rho != 0.0) r += a.rho * (double)a.hprev[1][c];
-        if (a.hout[1]) a.hout[1][c] = (T)H;
-        a.R[1][c] = (T)(test_bit(a.mask[1], c) ? 0.0 : a.dt * r);
+      a.R[0][c] = (T)r_u;
+      a.R[2][c] = (T)r_w;
+      a.R[1][c] = (T)r_v;
+      if (HOUT) {
+        a.hout[0][c] = (T)h_u;
+        a.hout[2][c] = (T)h_w;
+        a.hout[1][c] = (T)h_v;
       }
     }
     if (j + 1 < j1) {
       __syncthreads();  // every read of the slots of j-1 is done
+      // rotate: the slots of j-1 take the planes of j+2 (p: j-1 takes j+1)
+      int t_ = bu[0]; bu[0] = bu[1]; bu[1] = bu[2]; bu[2] = t_;
+      t_ = bv[0]; bv[0] = bv[1]; bv[1] = bv[2]; bv[2] = t_;
+      t_ = bw[0]; bw[0] = bw[1]; bw[1] = bw[2]; bw[2] = t_;
+      t_ = bp[0]; bp[0] = bp[1]; bp[1] = t_;
       if (j + 2 < g.ny) {
-        put_plane(lds, su(j + 2), nu);
-        put_plane(lds, sw(j + 2), nw);
+        put_plane(lds, bu[2], nu);
+        put_plane(lds, bw[2], nw);
       }
-      if (j + 2 <= g.ny) put_plane(lds, sv(j + 2), nv);
-      put_plane(lds, sp(j + 1), np);
-      if (j + 2 < j1) fetch_next(j + 1);
+      if (j + 2 <= g.ny) put_plane(lds, bv[2], nv);
+      put_plane(lds, bp[1], np);
+      fetch_cell(j + 1);
+      fetch_next(j + 1);
       __syncthreads();
     }
   }
@@ -276,8 +355,21 @@ static void run_rhs(Prof* pf, hipStream_t s, const GridView& g, const RhsArgs& a
   K.fx = a.fx;
   const int64_t blocks = (int64_t)((g.nx + RTX - 1) / RTX) * ((g.nz + RTZ - 1) / RTZ) *
                          ((g.ny + RJC - 1) / RJC);
-  const size_t shm = sizeof(double) * RSLOTS * RPL;
-  IBM_LAUNCH(pf, "rhs", s, k_rhs<T><<<(unsigned)blocks, RTX * RTZ, shm, s>>>(K));
+  const size_t shm = sizeof(double) * (RSLOTS * RPL + RCOEF);
+  const int f = ((g.nx % RTX == 0 && g.nz % RTZ == 0) ? RHS_FULL : 0) |
+                (a.rho != 0.0 ? RHS_HPREV : 0) |
+                ((a.hout[0] && a.hout[1] && a.hout[2]) ? RHS_HOUT : 0);
+  // H written per component when only some are requested: none here (the
+  // host passes all three or none), checked by the caller
+  switch (f) {
+#define RHS_CASE(F_)                                                              \
+  case F_:                                                                        \
+    IBM_LAUNCH(pf, "rhs", s, k_rhs<T, F_><<<(unsigned)blocks, RTX * RTZ, shm, s>>>(K)); \
+    break;
+    RHS_CASE(0) RHS_CASE(1) RHS_CASE(2) RHS_CASE(3)
+    RHS_CASE(4) RHS_CASE(5) RHS_CASE(6) RHS_CASE(7)
+#undef RHS_CASE
+  }
 }
 
 void launch_rhs(Prof* pf, hipStream_t s, const GridView& g, const RhsArgs& a) {
