@@ -331,13 +331,10 @@ def main():
         "roofline": head.get("roofline"),
         "cpu_baseline": cpu,
         "kernel_ms_per_step": head["kernel_ms_per_step"],
-        "forms": {f: {k: v for k, v in r.items() if k != "kernel_ms_per_step"}
-                  for f, r in results.items()},
+        "forms": {f: dict(r) for f, r in results.items()},
     }
     if batched:
         out["forms"]["batched"] = batched
-    if len(forms) > 1:
-        out["forms"]["kernel_ms_per_step"] = {f: r["kernel_ms_per_step"] for f, r in results.items()}
     if copy_ref:
         out["copy_ref"] = copy_ref
     print(json.dumps(out), flush=True)

@@ -388,6 +388,197 @@ __global__ __launch_bounds__(MODE == 0 ? 256 : 1024) void k_line(LineK<T> K) {
   }
 }
 
+// The value v of lane `src` of this wavefront (ds_bpermute: no LDS storage,
+// no barrier).
+__device__ __forceinline__ double lane_read(double v, int src) {
+  const int a = src << 2;
+  const int lo = __builtin_amdgcn_ds_bpermute(a, __double2loint(v));
+  const int hi = __builtin_amdgcn_ds_bpermute(a, __double2hiint(v));
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ float lane_read(float v, int src) {
+  return __int_as_float(__builtin_amdgcn_ds_bpermute(src << 2, __float_as_int(v)));
+}
+
+// orders this wavefront's LDS writes before its later LDS reads of other
+// lanes' values
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+template <typename T> struct Vec16;
+template <> struct Vec16<double> { using type = double2; };
+template <> struct Vec16<float> { using type = float4; };
+
+// x sweep with one wavefront per group of 64/P rows, for lines of n = P*LMAX
+// rows with P a power of two (4 <= P <= 64): lane rr*P + s holds segment s of
+// row rr.  The group's rows are staged through the wavefront's own LDS region
+// (16-byte loads and stores, a 16-byte pad after every segment so that the
+// lanes' segment reads fall on distinct banks), and the separator system is
+// solved by cyclic reduction over cross-lane reads, so the wavefronts of a
+// block never wait for each other.  Equal segments of a constant-coefficient
+// line share one set of elimination tables (segment 0's).
+template <typename T>
+__global__ __launch_bounds__(256) void k_line_xw(LineK<T> K) {
+  using V = typename Vec16<T>::type;
+  constexpr int VN = 16 / sizeof(T);  // values per 16 bytes
+  constexpr int SEGS = LMAX + VN;     // padded segment
+  extern __shared__ __align__(16) unsigned char ldsraw[];
+  T* lds = reinterpret_cast<T*>(ldsraw);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int P = K.P, n = K.n;
+  const int RW = 64 / P;          // rows per wavefront
+  const int RS = (n / LMAX) * SEGS;  // padded row
+  T* tab = lds;                   // [LINE_NTAB][LMAX]
+  T* rows = lds + LINE_NTAB * LMAX + (size_t)wv * RW * RS;
+  for (int q = threadIdx.x; q < LINE_NTAB * LMAX; q += blockDim.x)
+    tab[q] = K.tab[(size_t)(q / LMAX) * P * LMAX + q % LMAX];
+  __syncthreads();
+  const int64_t nl = (int64_t)K.nj * K.nz;  // rows of the sweep
+  const int64_t r0 = ((int64_t)blockIdx.x * (blockDim.x >> 6) + wv) * RW;
+  if (r0 >= nl) return;  // the whole wavefront is past the end
+  const int nrow = (int)((r0 + RW <= nl) ? RW : nl - r0);
+  const int64_t g0 = ((int64_t)K.j0 * K.nz + r0) * n;  // first element of the group
+  // stage the group's rows: value c of row r at rows[r*RS + (c/LMAX)*SEGS + c%LMAX]
+  const int nv = nrow * n / VN;
+  for (int q = lane; q < nv; q += 64) {
+    const int c0 = q * VN, r = c0 / n, c = c0 % n;
+    *reinterpret_cast<V*>(rows + r * RS + (c / LMAX) * SEGS + c % LMAX) =
+        *reinterpret_cast<const V*>(K.d + g0 + c0);
+  }
+  wave_sync();
+  const int rr = lane / P, s = lane % P;
+  const bool valid = rr < nrow;
+  const int grp = rr * P;  // first lane of this row
+  T* seg = rows + rr * RS + s * SEGS;
+  const int m = LMAX - 1;  // interior rows; row m is the separator
+  const int64_t base = g0 + (int64_t)rr * n + s * LMAX;  // first element of the segment
+  T dd[LMAX];
+  T dz = 0, az = 0, bz = 1, cz = 0;
+  T a0 = 0, c0 = 0, ahl = 0, chl = 0, dhl = 0;
+  uint32_t mbits = 0;
+  if (valid) {
+#pragma unroll
+    for (int e = 0; e < LMAX; ++e) dd[e] = seg[e];
+    // a segment starts at a multiple of 16: its bits lie in one mask word
+    mbits = (K.mask[base >> 5] >> (uint32_t)(base & 31)) & ((1u << LMAX) - 1u);
+#pragma unroll
+    for (int e = 0; e < LMAX; ++e)
+      if ((mbits >> e) & 1u) dd[e] = T(0);
+    dz = dd[m];
+    if ((mbits & ((1u << m) - 1u)) == 0u) {
+      T dt = 0;
+#pragma unroll
+      for (int e = 0; e < m; ++e) {
+        dt = (dd[e] - tab[4 * LMAX + e] * dt) * tab[e];
+        dd[e] = dt;
+      }
+      T dh = dd[m - 1];
+      dhl = dh;
+#pragma unroll
+      for (int e = m - 2; e >= 0; --e) {
+        dh = dd[e] - tab[LMAX + e] * dh;
+        dd[e] = dh;
+      }
+      a0 = tab[2 * LMAX];
+      c0 = tab[3 * LMAX];
+      ahl = tab[2 * LMAX + m - 1];
+      chl = tab[3 * LMAX + m - 1];
+    } else {
+      // identity rows inside the segment: coefficients through the scratch
+      T at = 0, ct = 0, dt = 0;
+#pragma unroll
+      for (int e = 0; e < m; ++e) {
+        T a = K.a, b = K.b, c = K.c;
+        if ((mbits >> e) & 1u) {
+          a = 0;
+          b = 1;
+          c = 0;
+        }
+        const T inv = T(1) / (b - a * ct);
+        at = (e == 0) ? a * inv : -a * at * inv;
+        ct = c * inv;
+        dt = (dd[e] - a * dt) * inv;
+        dd[e] = dt;
+        K.sa[base + e] = at;
+        K.sc[base + e] = ct;
+      }
+      T ah = 0, ch = 0, dh = 0;
+#pragma unroll
+      for (int e = m - 1; e >= 0; --e) {
+        const T at_e = K.sa[base + e], ct_e = K.sc[base + e];
+        if (e == m - 1) {
+          ah = at_e;
+          ch = ct_e;
+          dh = dd[e];
+          ahl = ah;
+          chl = ch;
+          dhl = dh;
+        } else {
+          dh = dd[e] - ct_e * dh;
+          ah = at_e - ct_e * ah;
+          ch = -ct_e * ch;
+        }
+        dd[e] = dh;
+        K.sa[base + e] = ah;
+        K.sc[base + e] = ch;
+      }
+      a0 = ah;
+      c0 = ch;
+    }
+    az = K.a;
+    bz = K.b;
+    cz = K.c;
+    if ((mbits >> m) & 1u) {
+      az = 0;
+      bz = 1;
+      cz = 0;
+    }
+  }
+  // separator row of this segment (every lane takes part in the cross-lane
+  // reads; lanes past the group's rows carry identity rows)
+  const int nxt = grp + ((s + 1) & (P - 1)), prv = grp + ((s - 1) & (P - 1));
+  const T a0n = lane_read(a0, nxt), c0n = lane_read(c0, nxt);
+  const T d0n = lane_read(valid ? dd[0] : T(0), nxt);
+  T ra = -az * ahl;
+  T rb = bz - az * chl - cz * a0n;
+  T rg = -cz * c0n;
+  T rd = dz - az * dhl - cz * d0n;
+  // cyclic reduction: a cyclic system of 2^k rows closes with couplings onto
+  // the row itself
+  for (int st = 1; st < P; st <<= 1) {
+    const int im = grp + ((s - st) & (P - 1)), ip = grp + ((s + st) & (P - 1));
+    const T am = lane_read(ra, im), bm = lane_read(rb, im), gm = lane_read(rg, im),
+            dm = lane_read(rd, im);
+    const T ap = lane_read(ra, ip), bp = lane_read(rb, ip), gp = lane_read(rg, ip),
+            dp = lane_read(rd, ip);
+    const T k1 = ra / bm, k2 = rg / bp;
+    const T na = -am * k1, ng = -gp * k2;
+    rb = rb - gm * k1 - ap * k2;
+    rd = rd - dm * k1 - dp * k2;
+    ra = na;
+    rg = ng;
+  }
+  const T zr = rd / (ra + rb + rg);
+  const T zl = lane_read(zr, prv);
+  if (valid) {
+    const bool fast = (mbits & ((1u << m) - 1u)) == 0u;
+#pragma unroll
+    for (int e = 0; e < m; ++e)
+      seg[e] = fast ? dd[e] - tab[2 * LMAX + e] * zl - tab[3 * LMAX + e] * zr
+                    : dd[e] - K.sa[base + e] * zl - K.sc[base + e] * zr;
+    seg[m] = zr;
+  }
+  wave_sync();
+  for (int q = lane; q < nv; q += 64) {
+    const int c0_ = q * VN, r = c0_ / n, c = c0_ % n;
+    *reinterpret_cast<V*>(K.d + g0 + c0_) =
+        *reinterpret_cast<const V*>(rows + r * RS + (c / LMAX) * SEGS + c % LMAX);
+  }
+}
+
 template <typename T>
 static void launch_line(Prof* pf, hipStream_t s, LineK<T> K, const char* name) {
   dim3 grid;
@@ -422,7 +613,14 @@ static void launch_line(Prof* pf, hipStream_t s, LineK<T> K, const char* name) {
     else                                                                              \
       IBM_LAUNCH(pf, name, s, (k_line<T, M, false><<<grid, threads, shm, s>>>(K)));  \
   } while (0)
-  if (K.mode == 0)
+  if (K.mode == 0 && fixed && (K.P & (K.P - 1)) == 0 && K.P >= 4 && K.P <= 64) {
+    // one wavefront per group of 64/P rows, four wavefronts per block
+    const int64_t rows = (int64_t)K.nj * K.nz;
+    const int64_t waves = (rows + 64 / K.P - 1) / (64 / K.P);
+    const size_t xshm = sizeof(T) * (LINE_NTAB * LMAX +
+                                     4 * (64 / K.P) * (size_t)(K.n / LMAX) * (LMAX + 16 / sizeof(T)));
+    IBM_LAUNCH(pf, name, s, (k_line_xw<T><<<(unsigned)((waves + 3) / 4), 256, xshm, s>>>(K)));
+  } else if (K.mode == 0)
     IBM_LINE(0);
   else if (K.mode == 1)
     IBM_LAUNCH(pf, name, s, (k_line<T, 1, false><<<grid, threads, shm, s>>>(K)));
