@@ -42,6 +42,8 @@ struct LineK {
   const T* B;
   const T* C;
   int mode;           // 0 x-rows, 1 z-lines, 2 y-lines
+  int tab1;           // every segment has the same table (constant
+                      // coefficients, equal segments): only segment 0's is staged
   int nx, nz, j0, nj;
   int64_t plane;
   int tl;             // lines per block
@@ -102,17 +104,20 @@ __global__ __launch_bounds__(MODE == 0 ? 256 : 1024) void k_line(LineK<T> K) {
   T* lds = reinterpret_cast<T*>(ldsraw);
   const int tid = threadIdx.x;
   const int P = K.P;
-  T* tabs = lds;                         // LINE_NTAB * P * LMAX
-  T* sm = lds + LINE_NTAB * P * LMAX;    // 8 * P * lines per block
+  const int tP = K.tab1 ? 1 : P;         // segments in the staged tables
+  T* tabs = lds;                         // LINE_NTAB * tP * LMAX
+  T* sm = lds + LINE_NTAB * tP * LMAX;   // 8 * P * lines per block
   // x sweep: the block's rows are staged through LDS (coalesced loads and
   // stores; each thread then reads its segment from LDS), one pad slot every
   // 16 values so that consecutive segments fall on different banks; the row
   // buffer is reused for the separator arrays once the rows are in registers
   T* rowbuf = sm;
   const int RS = K.n + (K.n >> 4) + 1;
-  for (int q = tid; q < LINE_NTAB * P * LMAX; q += blockDim.x) {
-    const int qq = q / (P * LMAX), rem = q % (P * LMAX), ss = rem / LMAX, ee = rem % LMAX;
-    tabs[(qq * LMAX + ee) * P + ss] = K.tab[q];
+  // tables [q][e][s] from the host layout [q][s][e], written in LDS order
+  // (consecutive lanes on consecutive words)
+  for (int q = tid; q < LINE_NTAB * tP * LMAX; q += blockDim.x) {
+    const int qe = q / tP, ss = q % tP, qq = qe / LMAX, ee = qe % LMAX;
+    tabs[q] = K.tab[((size_t)qq * P + ss) * LMAX + ee];
   }
   __syncthreads();
   int lb, s;
@@ -163,8 +168,10 @@ __global__ __launch_bounds__(MODE == 0 ? 256 : 1024) void k_line(LineK<T> K) {
   auto xpos = [&](int e) { return lb * RS + (lo + e) + ((lo + e) >> 4); };
   // table entry (q, e) of this segment; layout [q][e][s] keeps the lanes of
   // consecutive segments on consecutive LDS words
-#define TAB(q, e) tabs[((q) * LMAX + (e)) * P + s]
+  const int ts = K.tab1 ? 0 : s;
+#define TAB(q, e) tabs[((q) * LMAX + (e)) * tP + ts]
   T dd[LMAX];
+  double uu[MODE == 2 ? LMAX : 1];
   T dz = 0, az = 0, bz = 1, cz = 0;
   T a0 = 0, c0 = 0, ahl = 0, chl = 0, dhl = 0;
   uint32_t mbits = 0;
@@ -174,6 +181,13 @@ __global__ __launch_bounds__(MODE == 0 ? 256 : 1024) void k_line(LineK<T> K) {
 #pragma unroll
     for (int e = 0; e < LMAX; ++e)
       if (e < len) raw[e] = (MODE == 0) ? rowbuf[xpos(e)] : K.d[base + (int64_t)(lo + e) * es];
+    if (MODE == 2) {
+      // the velocity the solution is added to, loaded now so that its
+      // latency overlaps the solve
+#pragma unroll
+      for (int e = 0; e < LMAX; ++e)
+        if (e < len) uu[e] = K.u[base + (int64_t)(lo + e) * es];
+    }
     if (es == 1) {  // contiguous row: the segment's bits span at most two words
       const int64_t b0 = base + lo;
       const uint32_t w0 = K.mask[b0 >> 5];
@@ -367,7 +381,7 @@ __global__ __launch_bounds__(MODE == 0 ? 256 : 1024) void k_line(LineK<T> K) {
         if (MODE == 0) {
           if (e < m) dd[e] = x; else dz = x;
         } else if (MODE == 2) {
-          K.u[o] += (double)x;
+          K.u[o] = uu[MODE == 2 ? e : 0] + (double)x;
         } else {
           K.d[o] = x;
         }
@@ -602,7 +616,8 @@ static void launch_line(Prof* pf, hipStream_t s, LineK<T> K, const char* name) {
     const size_t rows = (size_t)K.tl * (K.n + (K.n >> 4) + 1);
     if (rows > work) work = rows;
   }
-  const size_t shm = sizeof(T) * (LINE_NTAB * (size_t)K.P * LMAX + work);
+  K.tab1 = (K.mode != 2 && K.r == 0) ? 1 : 0;
+  const size_t shm = sizeof(T) * (LINE_NTAB * (size_t)(K.tab1 ? 1 : K.P) * LMAX + work);
   // fixed-length segments only for the x sweep: unrolled strided z/y
   // segments need ~190 VGPRs (2 waves per SIMD), slower than the ragged form
   const bool fixed = (K.mode == 0 && K.r == 0 && K.L == LMAX);
