@@ -47,6 +47,7 @@ struct LineK {
   int nx, nz, j0, nj;
   int64_t plane;
   int tl;             // lines per block
+  int PP;             // column sweeps: P rounded up to a power of two
 };
 
 template <typename T>
@@ -593,6 +594,262 @@ __global__ __launch_bounds__(256) void k_line_xw(LineK<T> K) {
   }
 }
 
+// z and y sweeps for lines of n = P*LMAX rows (every segment LMAX rows) on
+// grids with nx a multiple of 16.  A block takes 16 lines of consecutive x
+// (a wavefront's loads then cover 128-byte row pieces).
+//  1. thread (line lb, segment s) loads its segment (and, for y, the velocity
+//     it adds to), takes the forcing-mask bits of its rows from one word per
+//     row that the 16 lanes of the segment load together, and eliminates the
+//     interior rows;
+//  2. the separator rows are formed in LDS and re-read transposed: a line's
+//     PP (P rounded up to a power of two) separators then sit in consecutive
+//     lanes of one wavefront, which solves them by cyclic reduction over
+//     cross-lane reads (rows past P act as identity rows);
+//  3. each thread reconstructs and stores its rows.
+// Four block barriers in all.
+// coefficients of row i: per-row arrays for the y sweep, the constants otherwise
+template <int MODE, typename T>
+__device__ __forceinline__ void col_coef(const LineK<T>& K, int i, T& a, T& b, T& c) {
+  if (MODE == 2) {
+    a = K.A[i];
+    b = K.B[i];
+    c = K.C[i];
+  } else {
+    a = K.a;
+    b = K.b;
+    c = K.c;
+  }
+}
+
+template <typename T, int MODE>
+__global__ __launch_bounds__(1024) void k_line_col(LineK<T> K) {
+  constexpr int TL = 16;       // lines per block
+  constexpr int SP = TL + 1;   // padded stride of the separator arrays
+  extern __shared__ __align__(16) unsigned char ldsraw[];
+  T* lds = reinterpret_cast<T*>(ldsraw);
+  const int tid = threadIdx.x;
+  const int P = K.P, PP = K.PP;
+  const int tP = K.tab1 ? 1 : P;
+  T* tabs = lds;                             // [LINE_NTAB][LMAX][tP]
+  T* Y = tabs + LINE_NTAB * LMAX * tP;       // a0, c0, d0 of each segment; then z
+  T* X = Y + 3 * PP * SP;                    // separator rows ra, rb, rg, rd
+  uint32_t* mws = reinterpret_cast<uint32_t*>(X + 4 * PP * SP);  // [P][16] mask words
+  for (int q = tid; q < LINE_NTAB * tP * LMAX; q += blockDim.x) {
+    const int qe = q / tP, ss = q % tP, qq = qe / LMAX, ee = qe % LMAX;
+    tabs[q] = K.tab[((size_t)qq * P + ss) * LMAX + ee];
+  }
+  const int lb = tid % TL, s = tid / TL;
+  const bool active = s < P;
+  const int i0 = blockIdx.x * TL;
+  const int ts = K.tab1 ? 0 : s;
+#define CTAB(q, e) tabs[((q) * LMAX + (e)) * tP + ts]
+  // element (row r of line lb): blk[lb + r * es]
+  const int64_t es = (MODE == 1) ? K.nx : K.plane;
+  const int64_t boff = (MODE == 1) ? (int64_t)(K.j0 + blockIdx.y) * K.plane + i0
+                                   : (int64_t)K.j0 * K.plane + (int64_t)blockIdx.y * K.nx + i0;
+  const int lo = s * LMAX;
+  constexpr int m = LMAX - 1;
+  T dd[LMAX];
+  double uu[MODE == 2 ? LMAX : 1];
+  T dz = 0, az = 0, bz = 1, cz = 0;
+  T a0 = 0, c0 = 0, ahl = 0, chl = 0, dhl = 0;
+  uint32_t mbits = 0;
+  // rows are addressed from the wavefront's first row (a uniform base) plus
+  // a 32-bit byte offset, one register per row instead of a 64-bit address
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int64_t wrow = (int64_t)wv * (64 / TL) * LMAX;  // first row of the wavefront
+  const T* dbase = K.d + boff + wrow * es;
+  const double* ubase = (MODE == 2) ? K.u + boff + wrow * es : nullptr;
+  const uint32_t lrow = (uint32_t)(lo - wrow);           // this segment's first row, from wrow
+  auto boffs = [&](int e, uint32_t sz) -> uint32_t {
+    return ((uint32_t)lb + (lrow + (uint32_t)e) * (uint32_t)es) * sz;
+  };
+  if (active) {
+#pragma unroll
+    for (int e = 0; e < LMAX; ++e)
+      dd[e] = *reinterpret_cast<const T*>(reinterpret_cast<const char*>(dbase) + boffs(e, sizeof(T)));
+    // lane lb fetches the mask word of row lo + lb (bits i0 .. i0+15 of the
+    // row: one word, nx and i0 being multiples of 16)
+    const int64_t rb = (MODE == 1) ? ((int64_t)(K.j0 + blockIdx.y) * K.nz + lo + lb) * K.nx
+                                   : ((int64_t)(K.j0 + lo + lb) * K.nz + blockIdx.y) * K.nx;
+    const int64_t bit = rb + i0;
+    mws[s * LMAX + lb] = (K.mask[bit >> 5] >> (uint32_t)(bit & 31)) & 0xffffu;
+  }
+  __syncthreads();  // tables and mask words
+  if (active) {
+#pragma unroll
+    for (int e = 0; e < LMAX; ++e) mbits |= ((mws[s * LMAX + e] >> lb) & 1u) << e;
+#pragma unroll
+    for (int e = 0; e < LMAX; ++e)
+      if ((mbits >> e) & 1u) dd[e] = T(0);
+    dz = dd[m];
+    if ((mbits & ((1u << m) - 1u)) == 0u) {
+      T dt = 0;
+#pragma unroll
+      for (int e = 0; e < m; ++e) {
+        dt = (dd[e] - CTAB(4, e) * dt) * CTAB(0, e);
+        dd[e] = dt;
+      }
+      T dh = dd[m - 1];
+      dhl = dh;
+#pragma unroll
+      for (int e = m - 2; e >= 0; --e) {
+        dh = dd[e] - CTAB(1, e) * dh;
+        dd[e] = dh;
+      }
+      a0 = CTAB(2, 0);
+      c0 = CTAB(3, 0);
+      ahl = CTAB(2, m - 1);
+      chl = CTAB(3, m - 1);
+    } else {
+      // identity rows inside the segment: coefficients through the scratch
+      T at = 0, ct = 0, dt = 0;
+      for (int e = 0; e < m; ++e) {
+        const int64_t o = boff + lb + (lo + e) * es;
+        T a, b, c;
+        col_coef<MODE>(K, lo + e, a, b, c);
+        if ((mbits >> e) & 1u) {
+          a = 0;
+          b = 1;
+          c = 0;
+        }
+        const T inv = T(1) / (b - a * ct);
+        at = (e == 0) ? a * inv : -a * at * inv;
+        ct = c * inv;
+        dt = (dd[e] - a * dt) * inv;
+        dd[e] = dt;
+        K.sa[o] = at;
+        K.sc[o] = ct;
+      }
+      T ah = 0, ch = 0, dh = 0;
+      for (int e = m - 1; e >= 0; --e) {
+        const int64_t o = boff + lb + (lo + e) * es;
+        const T at_e = K.sa[o], ct_e = K.sc[o];
+        if (e == m - 1) {
+          ah = at_e;
+          ch = ct_e;
+          dh = dd[e];
+          ahl = ah;
+          chl = ch;
+          dhl = dh;
+        } else {
+          dh = dd[e] - ct_e * dh;
+          ah = at_e - ct_e * ah;
+          ch = -ct_e * ch;
+        }
+        dd[e] = dh;
+        K.sa[o] = ah;
+        K.sc[o] = ch;
+      }
+      a0 = ah;
+      c0 = ch;
+    }
+    col_coef<MODE>(K, lo + m, az, bz, cz);
+    if ((mbits >> m) & 1u) {
+      az = 0;
+      bz = 1;
+      cz = 0;
+    }
+    Y[(0 * PP + s) * SP + lb] = a0;
+    Y[(1 * PP + s) * SP + lb] = c0;
+    Y[(2 * PP + s) * SP + lb] = dd[0];
+  }
+  __syncthreads();  // a0, c0, d0 of every segment
+  if (active) {
+    int sn = s + 1;
+    T czz = cz;
+    if (sn == P) {
+      sn = 0;
+      if (!K.cyc) czz = 0;
+    }
+    X[(0 * PP + s) * SP + lb] = -az * ahl;
+    X[(1 * PP + s) * SP + lb] = bz - az * chl - czz * Y[(0 * PP + sn) * SP + lb];
+    X[(2 * PP + s) * SP + lb] = -czz * Y[(1 * PP + sn) * SP + lb];
+    X[(3 * PP + s) * SP + lb] = dz - az * dhl - czz * Y[(2 * PP + sn) * SP + lb];
+  }
+  __syncthreads();  // separator rows
+  // transposed: thread (line lt, separator st) in PP consecutive lanes
+  {
+    const int lt = tid / PP, st = tid % PP;
+    const int lane = tid & 63, grp = lane - st;
+    T ra = 0, rb = 1, rg = 0, rd = 0;
+    if (lt < TL && st < P) {
+      ra = X[(0 * PP + st) * SP + lt];
+      rb = X[(1 * PP + st) * SP + lt];
+      rg = X[(2 * PP + st) * SP + lt];
+      rd = X[(3 * PP + st) * SP + lt];
+    }
+    for (int step = 1; step < PP; step <<= 1) {
+      int im = st - step, ip = st + step;
+      bool hm = true, hp = true;
+      if (K.cyc) {
+        im &= PP - 1;
+        ip &= PP - 1;
+      } else {
+        hm = im >= 0;
+        hp = ip < PP;
+      }
+      const int sm_ = grp + (hm ? im : st), sp_ = grp + (hp ? ip : st);
+      T am = lane_read(ra, sm_), bm = lane_read(rb, sm_), gm = lane_read(rg, sm_),
+        dm = lane_read(rd, sm_);
+      T ap = lane_read(ra, sp_), bp = lane_read(rb, sp_), gp = lane_read(rg, sp_),
+        dp = lane_read(rd, sp_);
+      if (!hm) {
+        am = 0;
+        bm = 1;
+        gm = 0;
+        dm = 0;
+      }
+      if (!hp) {
+        ap = 0;
+        bp = 1;
+        gp = 0;
+        dp = 0;
+      }
+      const T k1 = ra / bm, k2 = rg / bp;
+      const T na = -am * k1, ng = -gp * k2;
+      rb = rb - gm * k1 - ap * k2;
+      rd = rd - dm * k1 - dp * k2;
+      ra = na;
+      rg = ng;
+    }
+    if (lt < TL && st < P) Y[st * SP + lt] = K.cyc ? rd / (ra + rb + rg) : rd / rb;
+  }
+  if (MODE == 2 && active) {
+    // the velocity the solution is added to: loaded here, where the
+    // registers of the separator solve are free, in flight over the barrier
+#pragma unroll
+    for (int e = 0; e < LMAX; ++e)
+      uu[e] = *reinterpret_cast<const double*>(reinterpret_cast<const char*>(ubase) + boffs(e, 8));
+  }
+  __syncthreads();  // separator values
+  if (active) {
+    const T zr = Y[s * SP + lb];
+    const T zl = (s > 0) ? Y[(s - 1) * SP + lb] : (K.cyc ? Y[(P - 1) * SP + lb] : T(0));
+    if ((mbits & ((1u << m) - 1u)) == 0u) {
+#pragma unroll
+      for (int e = 0; e < m; ++e) dd[e] = dd[e] - CTAB(2, e) * zl - CTAB(3, e) * zr;
+    } else {
+#pragma unroll
+      for (int e = 0; e < m; ++e) {
+        const int64_t o = boff + lb + (lo + e) * es;
+        dd[e] = dd[e] - K.sa[o] * zl - K.sc[o] * zr;
+      }
+    }
+    dd[m] = zr;
+#pragma unroll
+    for (int e = 0; e < LMAX; ++e) {
+      if (MODE == 2)
+        *reinterpret_cast<double*>(reinterpret_cast<char*>(const_cast<double*>(ubase)) + boffs(e, 8)) =
+            uu[MODE == 2 ? e : 0] + (double)dd[e];
+      else
+        *reinterpret_cast<T*>(reinterpret_cast<char*>(const_cast<T*>(dbase)) + boffs(e, sizeof(T))) =
+            dd[e];
+    }
+#undef CTAB
+  }
+}
+
 template <typename T>
 static void launch_line(Prof* pf, hipStream_t s, LineK<T> K, const char* name) {
   dim3 grid;
@@ -635,8 +892,25 @@ static void launch_line(Prof* pf, hipStream_t s, LineK<T> K, const char* name) {
     const size_t xshm = sizeof(T) * (LINE_NTAB * LMAX +
                                      4 * (64 / K.P) * (size_t)(K.n / LMAX) * (LMAX + 16 / sizeof(T)));
     IBM_LAUNCH(pf, name, s, (k_line_xw<T><<<(unsigned)((waves + 3) / 4), 256, xshm, s>>>(K)));
-  } else if (K.mode == 0)
+  } else if (K.mode == 0) {
     IBM_LINE(0);
+  } else if (K.r == 0 && K.L == LMAX && K.nx % 16 == 0 && K.P <= 64 &&
+             (!K.cyc || (K.P & (K.P - 1)) == 0) &&
+             (K.mode == 1 ? (int64_t)K.nx : K.plane) * 64 * 8 < ((int64_t)1 << 31)) {
+    // column sweep: 16 lines per block, the separators solved per wavefront
+    int pp = 1;
+    while (pp < K.P) pp <<= 1;
+    K.PP = pp;
+    const int ct = 16 * pp;
+    const size_t cshm = sizeof(T) * (LINE_NTAB * (size_t)(K.tab1 ? 1 : K.P) * LMAX +
+                                     7 * (size_t)pp * 17) +
+                        sizeof(uint32_t) * (size_t)K.P * LMAX;
+    const dim3 cgrid(K.nx / 16, K.mode == 1 ? K.nj : K.nz);
+    if (K.mode == 1)
+      IBM_LAUNCH(pf, name, s, (k_line_col<T, 1><<<cgrid, ct, cshm, s>>>(K)));
+    else
+      IBM_LAUNCH(pf, name, s, (k_line_col<T, 2><<<cgrid, ct, cshm, s>>>(K)));
+  }
   else if (K.mode == 1)
     IBM_LAUNCH(pf, name, s, (k_line<T, 1, false><<<grid, threads, shm, s>>>(K)));
   else

@@ -239,10 +239,20 @@ static int build_tables(ibm_ctx* c, double beta) {
     t->fden_inv = 1.0 / (1.0 + Z[0] + t->ratio * Z[n - 1]);
     for (auto* v : {&cp, &inv, &W, &Z}) out.insert(out.end(), v->begin(), v->end());
   };
+  // v: the interior faces j = 1..ny-1 and, as an identity row, the top wall
+  // face j = ny (its right-hand side is 0), so that v lines have ny rows like
+  // u and w and take the same segmentation
   auto ysys = [&](bool isv, std::vector<double>& out, YTab* t) {
-    const int n = isv ? ny - 1 : ny;
+    const int n = ny;
+    const int nreal = isv ? ny - 1 : ny;
     std::vector<double> A(n), B(n), C(n), cp(n), inv(n);
     for (int r = 0; r < n; ++r) {
+      if (r >= nreal) {
+        A[r] = 0.0;
+        B[r] = 1.0;
+        C[r] = 0.0;
+        continue;
+      }
       double lo, hi;
       if (isv) {
         const int j = r + 1;
@@ -253,7 +263,7 @@ static int build_tables(ibm_ctx* c, double beta) {
         hi = beta / (c->dyc[r + 1] * c->dy[r]);
       }
       A[r] = (r > 0) ? -lo : 0.0;
-      C[r] = (r < n - 1) ? -hi : 0.0;
+      C[r] = (r < nreal - 1) ? -hi : 0.0;
       B[r] = 1.0 + (lo + hi);
     }
     for (int r = 0; r < n; ++r) {

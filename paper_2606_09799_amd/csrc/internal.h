@@ -60,8 +60,9 @@ struct CyclicTab {
 };
 
 struct YTab {
-  // rows r = 0..n-1 of the wall-normal system of one lattice (u/w: n = ny,
-  // row r <-> node j = r; v: n = ny-1, row r <-> node j = r+1)
+  // rows r = 0..n-1 of the wall-normal system of one lattice (n = ny; u/w:
+  // row r <-> node j = r; v: row r <-> face j = r+1, the last row being the
+  // top wall face as an identity row)
   const double* a;   // sub-diagonal
   const double* b;   // diagonal
   const double* c;   // super-diagonal
