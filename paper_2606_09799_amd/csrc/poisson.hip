@@ -346,6 +346,85 @@ __global__ __launch_bounds__(256) void k_fftz(PoisK<C> K) {
   }
 }
 
+// ---------------------------------------------------------------------------
+// Length-256 transforms as 16 x 16 (four-step): a thread loads 16 values of
+// its sequence (stride 16) from HBM, takes a 16-point DFT in registers
+// (radix 4 x 4), multiplies by the twiddles W_256^(n1 k2) and writes them
+// transposed to LDS; after one barrier each thread takes the second
+// 16-point DFT over the other index and stores its 16 outputs.  One LDS
+// round trip and one barrier instead of a Stockham stage per radix-4 factor.
+
+// forward: exp(-2 pi i m/16); inverse: the conjugate (m a compile-time value
+// in the unrolled loops below)
+template <typename C, bool INV>
+__device__ __forceinline__ C w16(int m) {
+  using R = typename RealOf<C>::T;
+  const double c1 = 0.92387953251128675613, s1 = 0.38268343236508977173;
+  const double r2 = 0.70710678118654752440;
+  const double cs[16] = {1, c1, r2, s1, 0, -s1, -r2, -c1, -1, -c1, -r2, -s1, 0, s1, r2, c1};
+  const double sn = cs[(m + 12) & 15];  // sin(2 pi m/16) = cos(2 pi (m - 4)/16)
+  return mkc<C>((R)cs[m & 15], (R)(INV ? sn : -sn));
+}
+
+template <typename C, bool INV>
+__device__ __forceinline__ void dft4(C& a0, C& a1, C& a2, C& a3) {
+  const C s02 = cadd(a0, a2), d02 = csub(a0, a2);
+  const C s13 = cadd(a1, a3), d13 = csub(a1, a3);
+  // forward: -i d13; inverse: +i d13
+  const C rot = INV ? mkc<C>(-d13.y, d13.x) : mkc<C>(d13.y, -d13.x);
+  a0 = cadd(s02, s13);
+  a1 = cadd(d02, rot);
+  a2 = csub(s02, s13);
+  a3 = csub(d02, rot);
+}
+
+// 16-point DFT in place; output k = k1 + 4 k2 is left at x[4 k1 + k2]
+template <typename C, bool INV>
+__device__ __forceinline__ void dft16(C (&x)[16]) {
+#pragma unroll
+  for (int n2 = 0; n2 < 4; ++n2) dft4<C, INV>(x[n2], x[n2 + 4], x[n2 + 8], x[n2 + 12]);
+#pragma unroll
+  for (int n2 = 1; n2 < 4; ++n2)
+#pragma unroll
+    for (int k1 = 1; k1 < 4; ++k1) x[n2 + 4 * k1] = cmul(x[n2 + 4 * k1], w16<C, INV>(n2 * k1));
+#pragma unroll
+  for (int k1 = 0; k1 < 4; ++k1) dft4<C, INV>(x[4 * k1], x[4 * k1 + 1], x[4 * k1 + 2], x[4 * k1 + 3]);
+}
+__device__ __forceinline__ constexpr int pos16(int k) { return 4 * (k & 3) + (k >> 2); }
+
+constexpr int Z16_TC = 8;                  // x-modes per block
+constexpr int Z16_LP = 16 * Z16_TC + 8;    // padded LDS stride of one k2 group
+
+template <typename C, bool INV>
+__global__ __launch_bounds__(16 * Z16_TC) void k_fftz256(PoisK<C> K) {
+  if (gated(K)) return;
+  __shared__ C T[16 * Z16_LP];
+  const GridView& g = K.g;
+  const int nxh = g.nxh;
+  const int c = threadIdx.x % Z16_TC, t = threadIdx.x / Z16_TC;
+  const int p = blockIdx.x * Z16_TC + c;
+  const bool valid = p < nxh;
+  C* col = K.spec + (int64_t)blockIdx.y * 256 * nxh + (valid ? p : 0);  // element k at col[k * nxh]
+  C x[16];
+#pragma unroll
+  for (int n2 = 0; n2 < 16; ++n2) x[n2] = col[(int64_t)(t + 16 * n2) * nxh];
+  dft16<C, INV>(x);
+#pragma unroll
+  for (int k2 = 0; k2 < 16; ++k2) {
+    C w = K.pz.tw[t * k2];
+    if (INV) w.y = -w.y;
+    T[k2 * Z16_LP + t * Z16_TC + c] = (k2 && t) ? cmul(x[pos16(k2)], w) : x[pos16(k2)];
+  }
+  __syncthreads();
+#pragma unroll
+  for (int n1 = 0; n1 < 16; ++n1) x[n1] = T[t * Z16_LP + n1 * Z16_TC + c];
+  dft16<C, INV>(x);
+  if (valid) {
+#pragma unroll
+    for (int k1 = 0; k1 < 16; ++k1) col[(int64_t)(t + 16 * k1) * nxh] = x[pos16(k1)];
+  }
+}
+
 // Wall-normal solves, one per Fourier mode, partitioned like the line solves
 // of the predictor: each mode's ny rows are cut into P balanced segments of
 // at most YL rows, one thread per segment, the values in registers.  Each
@@ -697,9 +776,17 @@ static void run_passes(Prof* pf, hipStream_t s, const GridView& g, PoisK<C> K) {
                (k_sum_partials<<<1, 256, 0, s>>>(K.psum, xblocks, const_cast<double*>(K.msum),
                                                   K.gate, K.gate_tol)));
   }
-  IBM_LAUNCH(pf, "pois_fftz_fwd", s, (k_fftz<C, false><<<zgrid, 256, zsh, s>>>(K)));
+  const bool z256 = (g.nz == 256);
+  const dim3 z16grid((g.nxh + Z16_TC - 1) / Z16_TC, g.ny);
+  if (z256)
+    IBM_LAUNCH(pf, "pois_fftz_fwd", s, (k_fftz256<C, false><<<z16grid, 16 * Z16_TC, 0, s>>>(K)));
+  else
+    IBM_LAUNCH(pf, "pois_fftz_fwd", s, (k_fftz<C, false><<<zgrid, 256, zsh, s>>>(K)));
   IBM_LAUNCH(pf, "pois_tri_y", s, (k_tri_y<C><<<yblocks, K.ytl * K.yP, ysh, s>>>(K)));
-  IBM_LAUNCH(pf, "pois_fftz_inv", s, (k_fftz<C, true><<<zgrid, 256, zsh, s>>>(K)));
+  if (z256)
+    IBM_LAUNCH(pf, "pois_fftz_inv", s, (k_fftz256<C, true><<<z16grid, 16 * Z16_TC, 0, s>>>(K)));
+  else
+    IBM_LAUNCH(pf, "pois_fftz_inv", s, (k_fftz<C, true><<<zgrid, 256, zsh, s>>>(K)));
   IBM_LAUNCH(pf, "pois_fftx_inv", s, (k_fftx_inv<C><<<xblocks, 256, xsh, s>>>(K)));
 }
 
