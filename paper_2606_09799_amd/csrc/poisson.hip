@@ -51,6 +51,14 @@ __device__ __forceinline__ C csub(C a, C b) {
   return mkc<C>(a.x - b.x, a.y - b.y);
 }
 
+// orders this wavefront's LDS writes before its later LDS reads of other
+// lanes' values (the lanes of one wavefront need no block barrier)
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 template <typename C>
 struct PlanDev {
   int n, nst;
@@ -220,6 +228,78 @@ __device__ __forceinline__ double lap_c(const GridView& g, const double* __restr
   return (gx1 - gx0) * g.idx + (gz1 - gz0) * g.idz + (fn - fs) * g.idy[j];
 }
 
+// Right-hand side of the solve at cell i of x-row rr (= j nz + k), by source
+// mode; the residual modes also accumulate max|r| and phi dV, and the FP64
+// copy is kept when asked.  q, q1: q_F, or (c0, c1) of the energy shape.
+template <typename C>
+__device__ __forceinline__ double fftx_source(const PoisK<C>& K, int64_t rr, int i, double q,
+                                              double q1, double& rmax, double& vsum) {
+  const GridView& g = K.g;
+  const int nx = g.nx;
+  const int64_t plane = (int64_t)g.nz * nx;
+  const int64_t cell = rr * nx + i;
+  double val;
+  if (K.mode == SRC_ARRAY) {
+    val = K.rhs[cell];
+  } else if (K.mode == SRC_VELOCITY) {
+    if (K.cb_mask && test_bit(K.cb_mask, cell)) {
+      val = 0.0;
+    } else {
+      const int j = (int)(rr / g.nz), k = (int)(rr % g.nz);
+      const int ip = (i + 1 == nx) ? 0 : i + 1;
+      const int kp = (k + 1 == g.nz) ? 0 : k + 1;
+      const double u0 = K.u[cell], u1 = K.u[cell - i + ip];
+      const double v0 = K.v[cell], v1 = K.v[cell + plane];
+      const double w0 = K.w[cell], w1 = K.w[(int64_t)j * plane + (int64_t)kp * nx + i];
+      const double D = (u1 - u0) * g.idx + (v1 - v0) * g.idy[j] + (w1 - w0) * g.idz;
+      double qq = q;
+      if (K.pq) {  // q_F = c0 + c1 (p - e), e the cell's kinetic energy
+        const double eu = 0.5 * (u0 * u0 + u1 * u1);
+        const double ev = 0.5 * (v0 * v0 + v1 * v1);
+        const double ew = 0.5 * (w0 * w0 + w1 * w1);
+        const double pc = K.pq32 ? (double)static_cast<const float*>(K.pq)[cell]
+                                 : static_cast<const double*>(K.pq)[cell];
+        qq = q + q1 * (pc - 0.5 * ((eu + ev) + ew));
+      }
+      val = (D - qq) * K.inv_adt;
+    }
+  } else {
+    const int j = (int)(rr / g.nz), k = (int)(rr % g.nz);
+    val = K.rhs[cell] - lap_c(g, K.phi_in, cell, i, j, k);
+    rmax = fmax(rmax, fabs(val));
+    vsum += K.phi_in[cell] * g.dy[j];
+  }
+  if (K.rhs_keep) K.rhs_keep[cell] = val;
+  return val;
+}
+
+// block maximum of |r| (one atomic on its bit pattern: non-negative doubles
+// order like their bits) and block sum of phi dV into psum[blockIdx.x], in a
+// fixed order; red: 2 * (waves per block) doubles of LDS
+__device__ __forceinline__ void resid_reduce(double rmax, double vsum, double* red, u64* rmax_out,
+                                             double* psum, double dxdz) {
+  for (int off = 32; off > 0; off >>= 1) {
+    rmax = fmax(rmax, __shfl_xor(rmax, off));
+    vsum += __shfl_xor(vsum, off);
+  }
+  const int nw = (int)(blockDim.x >> 6);
+  if ((threadIdx.x & 63) == 0) {
+    red[threadIdx.x >> 6] = rmax;
+    red[nw + (threadIdx.x >> 6)] = vsum;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double m = red[0], sm = red[nw];
+    for (int t = 1; t < nw; ++t) {
+      m = fmax(m, red[t]);
+      sm += red[nw + t];
+    }
+    atomicMax(reinterpret_cast<unsigned long long*>(rmax_out),
+              (unsigned long long)__double_as_longlong(m));
+    if (psum) psum[blockIdx.x] = sm * dxdz;
+  }
+}
+
 template <typename C>
 __global__ __launch_bounds__(256) void k_fftx_fwd(PoisK<C> K) {
   using R = typename RealOf<C>::T;
@@ -235,74 +315,17 @@ __global__ __launch_bounds__(256) void k_fftx_fwd(PoisK<C> K) {
   // two real rows per complex sequence: row r is the real (r even) or the
   // imaginary (r odd) part of sequence r/2
   R* sr = reinterpret_cast<R*>(sm);
-  const int64_t plane = (int64_t)g.nz * nx;
   const double q = (K.mode == SRC_VELOCITY) ? K.qf[0] : 0.0;
   const double q1 = (K.mode == SRC_VELOCITY && K.pq) ? K.qf[1] : 0.0;
   const bool resid = K.mode >= SRC_RESIDUAL;
   double rmax = 0.0, vsum = 0.0;
   for (int e = threadIdx.x; e < nr * nx; e += blockDim.x) {
     const int r = e / nx, i = e % nx;
-    const int64_t cell = (row0 + r) * nx + i;
-    double val;
-    if (K.mode == SRC_ARRAY) {
-      val = K.rhs[cell];
-    } else if (K.mode == SRC_VELOCITY) {
-      if (K.cb_mask && test_bit(K.cb_mask, cell)) {
-        val = 0.0;
-      } else {
-        const int64_t rr = row0 + r;
-        const int j = (int)(rr / g.nz), k = (int)(rr % g.nz);
-        const int ip = (i + 1 == nx) ? 0 : i + 1;
-        const int kp = (k + 1 == g.nz) ? 0 : k + 1;
-        const double u0 = K.u[cell], u1 = K.u[cell - i + ip];
-        const double v0 = K.v[cell], v1 = K.v[cell + plane];
-        const double w0 = K.w[cell], w1 = K.w[(int64_t)j * plane + (int64_t)kp * nx + i];
-        const double D = (u1 - u0) * g.idx + (v1 - v0) * g.idy[j] + (w1 - w0) * g.idz;
-        double qq = q;
-        if (K.pq) {  // q_F = c0 + c1 (p - e), e the cell's kinetic energy
-          const double eu = 0.5 * (u0 * u0 + u1 * u1);
-          const double ev = 0.5 * (v0 * v0 + v1 * v1);
-          const double ew = 0.5 * (w0 * w0 + w1 * w1);
-          const double pc = K.pq32 ? (double)static_cast<const float*>(K.pq)[cell]
-                                   : static_cast<const double*>(K.pq)[cell];
-          qq = q + q1 * (pc - 0.5 * ((eu + ev) + ew));
-        }
-        val = (D - qq) * K.inv_adt;
-      }
-    } else {
-      const int64_t rr = row0 + r;
-      const int j = (int)(rr / g.nz), k = (int)(rr % g.nz);
-      val = K.rhs[cell] - lap_c(g, K.phi_in, cell, i, j, k);
-      rmax = fmax(rmax, fabs(val));
-      vsum += K.phi_in[cell] * g.dy[j];
-    }
-    if (K.rhs_keep) K.rhs_keep[cell] = val;
+    const double val = fftx_source(K, row0 + r, i, q, q1, rmax, vsum);
     if (K.mode != SRC_CHECK) sr[2 * ((r >> 1) * nx + i) + (r & 1)] = (R)val;
   }
   if (resid) {
-    // block maximum of |r|, then one atomic per block on the bit pattern
-    // (non-negative doubles order like their bits); block sum of phi dV in a
-    // fixed order (the refinement removes the volume-weighted mean of phi,
-    // which the residual cannot see)
-    for (int off = 32; off > 0; off >>= 1) {
-      rmax = fmax(rmax, __shfl_xor(rmax, off));
-      vsum += __shfl_xor(vsum, off);
-    }
-    if ((threadIdx.x & 63) == 0) {
-      red[threadIdx.x >> 6] = rmax;
-      red[4 + (threadIdx.x >> 6)] = vsum;
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      double m = red[0], sm4 = red[4];
-      for (int t = 1; t < (int)(blockDim.x >> 6); ++t) {
-        m = fmax(m, red[t]);
-        sm4 += red[4 + t];
-      }
-      atomicMax(reinterpret_cast<unsigned long long*>(K.rmax),
-                (unsigned long long)__double_as_longlong(m));
-      if (K.psum) K.psum[blockIdx.x] = sm4 * (g.dx * g.dz);
-    }
+    resid_reduce(rmax, vsum, red, K.rmax, K.psum, g.dx * g.dz);
     if (K.mode == SRC_CHECK) return;  // block-uniform
   }
   for (int e = nr * nx + threadIdx.x; e < K.rows * nx; e += blockDim.x) {
@@ -422,6 +445,160 @@ __global__ __launch_bounds__(16 * Z16_TC) void k_fftz256(PoisK<C> K) {
   if (valid) {
 #pragma unroll
     for (int k1 = 0; k1 < 16; ++k1) col[(int64_t)(t + 16 * k1) * nxh] = x[pos16(k1)];
+  }
+}
+
+// Length-256 x transforms, two real rows per complex sequence, X16_SC
+// sequences (2 X16_SC consecutive rows) per block.  The 16 lanes of a
+// sequence (lane t = n1 in the first DFT, k2 in the second) lie in one
+// wavefront and own one LDS tile, so between the coalesced staging of the
+// block's rows and of its results only wavefront syncs are needed.
+constexpr int X16_SC = 8;
+constexpr int X16_SS = 16 * 17;  // complex values per sequence tile (>= 2 * 129)
+
+template <typename C>
+__global__ __launch_bounds__(32 * X16_SC) void k_fftx256_fwd(PoisK<C> K) {
+  using R = typename RealOf<C>::T;
+  if (gated(K)) return;
+  __shared__ C T[X16_SC * X16_SS];
+  __shared__ double red[2 * (32 * X16_SC / 64)];
+  const GridView& g = K.g;
+  const int nxh = g.nxh;
+  const int64_t nrows = (int64_t)g.ny * g.nz;
+  const int64_t row0 = (int64_t)blockIdx.x * (2 * X16_SC);
+  const int nr = (int)((row0 + 2 * X16_SC <= nrows) ? 2 * X16_SC : nrows - row0);
+  const double q = (K.mode == SRC_VELOCITY) ? K.qf[0] : 0.0;
+  const double q1 = (K.mode == SRC_VELOCITY && K.pq) ? K.qf[1] : 0.0;
+  double rmax = 0.0, vsum = 0.0;
+  // 1. the block's rows, coalesced: row r is the real (r even) or imaginary
+  //    (r odd) part of sequence r/2, value i at T[(r/2) X16_SS + i]
+  R* tr = reinterpret_cast<R*>(T);
+#pragma unroll 4
+  for (int e = threadIdx.x; e < 2 * X16_SC * 256; e += blockDim.x) {
+    const int r = e >> 8, i = e & 255;
+    const double val = (r < nr) ? fftx_source(K, row0 + r, i, q, q1, rmax, vsum) : 0.0;
+    tr[2 * ((r >> 1) * X16_SS + i) + (r & 1)] = (R)val;
+  }
+  if (K.mode >= SRC_RESIDUAL) {
+    resid_reduce(rmax, vsum, red, K.rmax, K.psum, g.dx * g.dz);
+    if (K.mode == SRC_CHECK) return;  // block-uniform
+  }
+  __syncthreads();
+  // 2. the transforms: the first 16 X16_SC threads, 16 lanes per sequence
+  // (the other wavefronts, which only help with the memory passes, wait at
+  // the next barrier)
+  if (threadIdx.x < 16 * X16_SC) {
+    const int t = threadIdx.x & 15, sc = threadIdx.x >> 4;
+    C* tile = T + sc * X16_SS;
+    C x[16];
+#pragma unroll
+    for (int n2 = 0; n2 < 16; ++n2) x[n2] = tile[t + 16 * n2];
+    dft16<C, false>(x);
+    wave_sync();
+#pragma unroll
+    for (int k2 = 0; k2 < 16; ++k2)
+      tile[k2 * 17 + t] = (k2 && t) ? cmul(x[pos16(k2)], K.px.tw[t * k2]) : x[pos16(k2)];
+    wave_sync();
+#pragma unroll
+    for (int n1 = 0; n1 < 16; ++n1) x[n1] = tile[t * 17 + n1];
+    dft16<C, false>(x);
+    wave_sync();
+#pragma unroll
+    for (int k1 = 0; k1 < 16; ++k1) tile[t + 16 * k1] = x[pos16(k1)];  // Z[k], k = t + 16 k1
+    wave_sync();
+    // split: with Z = A + iB, A[k] = (Z[k] + conj Z[n-k])/2,
+    // B[k] = (Z[k] - conj Z[n-k])/2i; bins p = t + 16 qq of both rows
+    const R h = (R)0.5;
+    C A[9], B[9];
+#pragma unroll
+    for (int qq = 0; qq < 9; ++qq) {
+      const int p = (t + 16 * qq) & 255;
+      const C zk = tile[p], zm = tile[(256 - p) & 255];
+      A[qq] = mkc<C>(h * (zk.x + zm.x), h * (zk.y - zm.y));
+      B[qq] = mkc<C>(h * (zk.y + zm.y), h * (zm.x - zk.x));
+    }
+    wave_sync();
+#pragma unroll
+    for (int qq = 0; qq < 9; ++qq) {
+      const int p = t + 16 * qq;
+      if (p < nxh) {
+        tile[p] = A[qq];
+        tile[nxh + p] = B[qq];
+      }
+    }
+  }
+  __syncthreads();
+  // 3. the block's spectrum rows are contiguous: rows row0.. at row0 * nxh
+  C* dst = K.spec + row0 * nxh;
+  for (int e = threadIdx.x; e < nr * nxh; e += blockDim.x) {
+    const int r = e / nxh, p = e - r * nxh;
+    dst[e] = T[(r >> 1) * X16_SS + (r & 1) * nxh + p];
+  }
+}
+
+template <typename C>
+__global__ __launch_bounds__(16 * X16_SC) void k_fftx256_inv(PoisK<C> K) {
+  using R = typename RealOf<C>::T;
+  if (gated(K)) return;
+  __shared__ C T[X16_SC * X16_SS];
+  const GridView& g = K.g;
+  const int nxh = g.nxh;
+  const int64_t nrows = (int64_t)g.ny * g.nz;
+  const int64_t row0 = (int64_t)blockIdx.x * (2 * X16_SC);
+  const int nr = (int)((row0 + 2 * X16_SC <= nrows) ? 2 * X16_SC : nrows - row0);
+  // 1. the block's half spectra, coalesced: row r at T[(r/2) X16_SS + (r%2) nxh]
+  const C* src = K.spec + row0 * nxh;
+  for (int e = threadIdx.x; e < 2 * X16_SC * nxh; e += blockDim.x) {
+    const int r = e / nxh, p = e - r * nxh;
+    T[(r >> 1) * X16_SS + (r & 1) * nxh + p] = (r < nr) ? src[e] : mkc<C>((R)0, (R)0);
+  }
+  __syncthreads();
+  const int t = threadIdx.x & 15, sc = threadIdx.x >> 4;
+  C* tile = T + sc * X16_SS;
+  // bin k of a half spectrum over the Hermitian extension (bins 0 and n/2 real)
+  auto bin = [&](int h, int k) -> C {
+    C c = (k < nxh) ? tile[h * nxh + k] : tile[h * nxh + (256 - k)];
+    if (k >= nxh) c.y = -c.y;
+    if (k == 0 || k == 128) c.y = (R)0;
+    return c;
+  };
+  C x[16];
+#pragma unroll
+  for (int n2 = 0; n2 < 16; ++n2) {
+    const int k = t + 16 * n2;
+    const C A = bin(0, k), B = bin(1, k);
+    x[n2] = mkc<C>(A.x - B.y, A.y + B.x);  // Z = A + iB
+  }
+  dft16<C, true>(x);
+  wave_sync();
+#pragma unroll
+  for (int k2 = 0; k2 < 16; ++k2) {
+    C w = K.px.tw[t * k2];
+    w.y = -w.y;
+    tile[k2 * 17 + t] = (k2 && t) ? cmul(x[pos16(k2)], w) : x[pos16(k2)];
+  }
+  wave_sync();
+#pragma unroll
+  for (int n1 = 0; n1 < 16; ++n1) x[n1] = tile[t * 17 + n1];
+  dft16<C, true>(x);
+  wave_sync();
+  // z[i], i = t + 16 k1: real part row 2 sc, imaginary part row 2 sc + 1
+#pragma unroll
+  for (int k1 = 0; k1 < 16; ++k1) tile[t + 16 * k1] = x[pos16(k1)];
+  __syncthreads();
+  // 2. the block's phi rows, coalesced
+  const R* tr = reinterpret_cast<const R*>(T);
+  const double msub = K.msum ? *K.msum * K.inv_vtot : 0.0;
+  double* dst = K.phi + row0 * 256;
+  for (int e = threadIdx.x; e < nr * 256; e += blockDim.x) {
+    const int r = e >> 8, i = e & 255;
+    double v = (double)tr[2 * ((r >> 1) * X16_SS + i) + (r & 1)] * K.scale;
+    if (K.zm) v += K.zm[(int)((row0 + r) / g.nz)] * K.scale;
+    v -= msub;
+    if (K.accumulate)
+      dst[e] += v;
+    else
+      dst[e] = v;
   }
 }
 
@@ -767,13 +944,20 @@ static void run_passes(Prof* pf, hipStream_t s, const GridView& g, PoisK<C> K) {
   const int yblocks = (int)((nm + K.ytl - 1) / K.ytl);
   const size_t ysh = 7 * sizeof(double) * (size_t)K.yP * K.ytl;
   const bool resid = K.mode >= SRC_RESIDUAL;
-  IBM_LAUNCH(pf, resid ? "pois_resid_fftx" : "pois_fftx_fwd", s,
-             (k_fftx_fwd<C><<<xblocks, 256, xsh, s>>>(K)));
+  // length-256 x transforms: 2 X16_SC rows per block
+  const bool x256 = (g.nx == 256);
+  const int xb = x256 ? (int)((nrows + 2 * X16_SC - 1) / (2 * X16_SC)) : xblocks;
+  if (x256)
+    IBM_LAUNCH(pf, resid ? "pois_resid_fftx" : "pois_fftx_fwd", s,
+               (k_fftx256_fwd<C><<<xb, 32 * X16_SC, 0, s>>>(K)));
+  else
+    IBM_LAUNCH(pf, resid ? "pois_resid_fftx" : "pois_fftx_fwd", s,
+               (k_fftx_fwd<C><<<xblocks, 256, xsh, s>>>(K)));
   if (K.mode == SRC_CHECK) return;
   if (resid) {
     K.gate = K.rmax;  // the rest of a refinement runs only if its residual is too large
     IBM_LAUNCH(pf, "pois_mean", s,
-               (k_sum_partials<<<1, 256, 0, s>>>(K.psum, xblocks, const_cast<double*>(K.msum),
+               (k_sum_partials<<<1, 256, 0, s>>>(K.psum, xb, const_cast<double*>(K.msum),
                                                   K.gate, K.gate_tol)));
   }
   const bool z256 = (g.nz == 256);
@@ -787,7 +971,10 @@ static void run_passes(Prof* pf, hipStream_t s, const GridView& g, PoisK<C> K) {
     IBM_LAUNCH(pf, "pois_fftz_inv", s, (k_fftz256<C, true><<<z16grid, 16 * Z16_TC, 0, s>>>(K)));
   else
     IBM_LAUNCH(pf, "pois_fftz_inv", s, (k_fftz<C, true><<<zgrid, 256, zsh, s>>>(K)));
-  IBM_LAUNCH(pf, "pois_fftx_inv", s, (k_fftx_inv<C><<<xblocks, 256, xsh, s>>>(K)));
+  if (x256)
+    IBM_LAUNCH(pf, "pois_fftx_inv", s, (k_fftx256_inv<C><<<xb, 16 * X16_SC, 0, s>>>(K)));
+  else
+    IBM_LAUNCH(pf, "pois_fftx_inv", s, (k_fftx_inv<C><<<xblocks, 256, xsh, s>>>(K)));
 }
 
 template <typename C>
