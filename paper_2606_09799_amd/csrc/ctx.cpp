@@ -566,7 +566,7 @@ int ibm_create(const ibm_grid* gr, const ibm_opts* o, void* stream, ibm_ctx** ou
   TRY(dalloc_bytes(c, &c->sc, c->nvface, c->es));
   TRY(dalloc(c, &c->rhs_tmp, c->ncell));
   TRY(dalloc(c, &c->phi, c->ncell));
-  const int64_t nspec = (int64_t)ny * nz * g.nxh;
+  const int64_t nspec = (int64_t)ny * nz * spec_ld(g.nxh, c->pfp32);
   TRY(dalloc_bytes(c, &c->spec, nspec, c->pfp32 ? 2 * sizeof(float) : 2 * sizeof(double)));
   if (c->pfp32) {
     TRY(dalloc(c, &c->rhs_keep, c->ncell));

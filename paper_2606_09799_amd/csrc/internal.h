@@ -91,6 +91,14 @@ inline void line_plan(int n, bool cyc, int* P, int* L, int* r) {
   line_plan(n, cyc, LINE_LMAX, P, L, r);
 }
 
+// Row stride (complex values) of the half spectrum [y][z][mode]: nx/2+1
+// modes padded to a multiple of 128 bytes, so that the z transforms' tiles of
+// consecutive modes start on cache-line boundaries
+inline int spec_ld(int nxh, bool fp32) {
+  const int a = fp32 ? 16 : 8;
+  return (nxh + a - 1) / a * a;
+}
+
 struct FFTPlan {
   int n;
   int nst;
@@ -205,7 +213,7 @@ struct PoissonArgs {
   const double* lamz;  // nz
   const double* ylo;   // ny: coefficient of phi[j-1]
   const double* yhi;   // ny: coefficient of phi[j+1]
-  void* spec;          // ny*nz*nxh complex: double2, or float2 when fp32
+  void* spec;          // ny*nz*spec_ld(nxh) complex: double2, or float2 when fp32
   double sum_dy;
   int fp32;            // FP32 spectrum and transforms
   int p_fp32;          // the pressure (read by the energy-conserving q) is FP32

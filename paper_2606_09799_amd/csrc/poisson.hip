@@ -199,6 +199,7 @@ struct PoisK {
   double* psum;                // SRC_RESIDUAL: per-block sums of phi dV (fixed order)
   const double* msum;          // inverse x pass of a refinement: sum of phi dV to remove
   double inv_vtot;
+  int ldx;                     // row stride of the spectrum (spec_ld)
   int rows;                    // x-rows per block
   int tp;                      // x-modes per block in the z passes
   int yP, yL, yr, ytl;         // wall-normal solve: segments, base length, longer ones, lines per block
@@ -340,7 +341,7 @@ __global__ __launch_bounds__(256) void k_fftx_fwd(PoisK<C> K) {
     const C zk = out[(r >> 1) * nx + p];
     const C zm = out[(r >> 1) * nx + (p == 0 ? 0 : nx - p)];
     const R h = (R)0.5;
-    K.spec[(row0 + r) * nxh + p] = (r & 1) ? mkc<C>(h * (zk.y + zm.y), h * (zm.x - zk.x))
+    K.spec[(row0 + r) * K.ldx + p] = (r & 1) ? mkc<C>(h * (zk.y + zm.y), h * (zm.x - zk.x))
                                            : mkc<C>(h * (zk.x + zm.x), h * (zk.y - zm.y));
   }
 }
@@ -356,16 +357,16 @@ __global__ __launch_bounds__(256) void k_fftz(PoisK<C> K) {
   const int j = blockIdx.y;
   const int p0 = blockIdx.x * tp;
   const int nc = (p0 + tp <= nxh) ? tp : nxh - p0;
-  C* spec = K.spec + (int64_t)j * nz * nxh + p0;
+  C* spec = K.spec + (int64_t)j * nz * K.ldx + p0;
   for (int e = threadIdx.x; e < nz * tp; e += blockDim.x) {
     const int k = e / tp, c = e % tp;
-    sm[e] = (c < nc) ? spec[(int64_t)k * nxh + c] : mkc<C>((R)0, (R)0);
+    sm[e] = (c < nc) ? spec[(int64_t)k * K.ldx + c] : mkc<C>((R)0, (R)0);
   }
   __syncthreads();
   const C* out = lds_fft<C, INV>(sm, sm + nz * tp, K.pz, tp, tp, 1);
   for (int e = threadIdx.x; e < nz * tp; e += blockDim.x) {
     const int k = e / tp, c = e % tp;
-    if (c < nc) spec[(int64_t)k * nxh + c] = out[e];
+    if (c < nc) spec[(int64_t)k * K.ldx + c] = out[e];
   }
 }
 
@@ -427,10 +428,11 @@ __global__ __launch_bounds__(16 * Z16_TC) void k_fftz256(PoisK<C> K) {
   const int c = threadIdx.x % Z16_TC, t = threadIdx.x / Z16_TC;
   const int p = blockIdx.x * Z16_TC + c;
   const bool valid = p < nxh;
-  C* col = K.spec + (int64_t)blockIdx.y * 256 * nxh + (valid ? p : 0);  // element k at col[k * nxh]
+  const int ldx = K.ldx;
+  C* col = K.spec + (int64_t)blockIdx.y * 256 * ldx + (valid ? p : 0);  // element k at col[k * ldx]
   C x[16];
 #pragma unroll
-  for (int n2 = 0; n2 < 16; ++n2) x[n2] = col[(int64_t)(t + 16 * n2) * nxh];
+  for (int n2 = 0; n2 < 16; ++n2) x[n2] = col[(int64_t)(t + 16 * n2) * ldx];
   dft16<C, INV>(x);
 #pragma unroll
   for (int k2 = 0; k2 < 16; ++k2) {
@@ -444,7 +446,7 @@ __global__ __launch_bounds__(16 * Z16_TC) void k_fftz256(PoisK<C> K) {
   dft16<C, INV>(x);
   if (valid) {
 #pragma unroll
-    for (int k1 = 0; k1 < 16; ++k1) col[(int64_t)(t + 16 * k1) * nxh] = x[pos16(k1)];
+    for (int k1 = 0; k1 < 16; ++k1) col[(int64_t)(t + 16 * k1) * ldx] = x[pos16(k1)];
   }
 }
 
@@ -528,11 +530,12 @@ __global__ __launch_bounds__(32 * X16_SC) void k_fftx256_fwd(PoisK<C> K) {
     }
   }
   __syncthreads();
-  // 3. the block's spectrum rows are contiguous: rows row0.. at row0 * nxh
-  C* dst = K.spec + row0 * nxh;
-  for (int e = threadIdx.x; e < nr * nxh; e += blockDim.x) {
-    const int r = e / nxh, p = e - r * nxh;
-    dst[e] = T[(r >> 1) * X16_SS + (r & 1) * nxh + p];
+  // 3. the block's spectrum rows (contiguous, padding included, written as 0)
+  const int ldx = K.ldx;
+  C* dst = K.spec + row0 * ldx;
+  for (int e = threadIdx.x; e < nr * ldx; e += blockDim.x) {
+    const int r = e / ldx, p = e - r * ldx;
+    dst[e] = (p < nxh) ? T[(r >> 1) * X16_SS + (r & 1) * nxh + p] : mkc<C>((R)0, (R)0);
   }
 }
 
@@ -547,10 +550,10 @@ __global__ __launch_bounds__(16 * X16_SC) void k_fftx256_inv(PoisK<C> K) {
   const int64_t row0 = (int64_t)blockIdx.x * (2 * X16_SC);
   const int nr = (int)((row0 + 2 * X16_SC <= nrows) ? 2 * X16_SC : nrows - row0);
   // 1. the block's half spectra, coalesced: row r at T[(r/2) X16_SS + (r%2) nxh]
-  const C* src = K.spec + row0 * nxh;
+  const C* src = K.spec + row0 * K.ldx;
   for (int e = threadIdx.x; e < 2 * X16_SC * nxh; e += blockDim.x) {
     const int r = e / nxh, p = e - r * nxh;
-    T[(r >> 1) * X16_SS + (r & 1) * nxh + p] = (r < nr) ? src[e] : mkc<C>((R)0, (R)0);
+    T[(r >> 1) * X16_SS + (r & 1) * nxh + p] = (r < nr) ? src[r * K.ldx + p] : mkc<C>((R)0, (R)0);
   }
   __syncthreads();
   const int t = threadIdx.x & 15, sc = threadIdx.x >> 4;
@@ -623,16 +626,17 @@ __global__ __launch_bounds__(1024) void k_tri_y(PoisK<C> K) {
   const GridView& g = K.g;
   const int TL = K.ytl, P = K.yP;
   const int lb = threadIdx.x % TL, s = threadIdx.x / TL;
-  const int64_t nm = (int64_t)g.nz * g.nxh;
+  // modes q = k ldx + p over the padded rows; padding columns are skipped
+  const int64_t nm = (int64_t)g.nz * K.ldx;
   const int64_t q = (int64_t)blockIdx.x * TL + lb;
-  const bool valid = q < nm;
+  const bool valid = q < nm && (int)(q % K.ldx) < g.nxh;
   auto at = [&](int f, int seg) -> double& { return sm[((size_t)f * P + seg) * TL + lb]; };
   const int lo = s * K.yL + (s < K.yr ? s : K.yr);
   const int len = K.yL + (s < K.yr ? 1 : 0);
   const int m = len - 1;  // interior rows (at least 2); row lo+m is the separator
   const bool zero = (q == 0);
   // lanes past the last mode solve a harmless non-singular system
-  const double lam = valid ? K.lamx[q % g.nxh] + K.lamz[q / g.nxh] : -1.0;
+  const double lam = valid ? K.lamx[q % K.ldx] + K.lamz[q / K.ldx] : -1.0;
   C* __restrict__ X = K.spec + q;
   double xr[YL], xi[YL], ah[YL], ch[YL];
   double zr = 0.0, zi = 0.0;
@@ -843,7 +847,7 @@ __global__ __launch_bounds__(256) void k_fftx_inv(PoisK<C> K) {
   // real and imaginary parts of the inverse are rows 2c and 2c+1
   auto bin = [&](int r, int k) -> C {
     if (r >= nr) return mkc<C>((R)0, (R)0);
-    C c = (k < nxh) ? K.spec[(row0 + r) * nxh + k] : K.spec[(row0 + r) * nxh + (nx - k)];
+    C c = (k < nxh) ? K.spec[(row0 + r) * K.ldx + k] : K.spec[(row0 + r) * K.ldx + (nx - k)];
     if (k >= nxh) c.y = -c.y;
     if (k == 0 || 2 * k == nx) c.y = (R)0;
     return c;
@@ -940,7 +944,8 @@ static void run_passes(Prof* pf, hipStream_t s, const GridView& g, PoisK<C> K) {
   const size_t xsh = 2 * (size_t)(rows / 2) * g.nx * CB;
   const size_t zsh = 2 * (size_t)tp * g.nz * CB;
   dim3 zgrid((g.nxh + tp - 1) / tp, g.ny);
-  const int64_t nm = (int64_t)g.nz * g.nxh;
+  K.ldx = spec_ld(g.nxh, sizeof(C) == sizeof(float2));
+  const int64_t nm = (int64_t)g.nz * K.ldx;
   const int yblocks = (int)((nm + K.ytl - 1) / K.ytl);
   const size_t ysh = 7 * sizeof(double) * (size_t)K.yP * K.ytl;
   const bool resid = K.mode >= SRC_RESIDUAL;
