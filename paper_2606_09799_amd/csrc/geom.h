@@ -221,4 +221,24 @@ __device__ __forceinline__ void load_triangle(const BodyDev* bodies, int nbody, 
   *vel = bd.vel;
 }
 
+// The value v of lane `src` of this wavefront (ds_bpermute: no LDS storage,
+// no barrier).
+__device__ __forceinline__ double lane_read(double v, int src) {
+  const int a = src << 2;
+  const int lo = __builtin_amdgcn_ds_bpermute(a, __double2loint(v));
+  const int hi = __builtin_amdgcn_ds_bpermute(a, __double2hiint(v));
+  return __hiloint2double(hi, lo);
+}
+__device__ __forceinline__ float lane_read(float v, int src) {
+  return __int_as_float(__builtin_amdgcn_ds_bpermute(src << 2, __float_as_int(v)));
+}
+
+// orders this wavefront's LDS writes before its later LDS reads of other
+// lanes' values
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 }  // namespace ibm

@@ -51,14 +51,6 @@ __device__ __forceinline__ C csub(C a, C b) {
   return mkc<C>(a.x - b.x, a.y - b.y);
 }
 
-// orders this wavefront's LDS writes before its later LDS reads of other
-// lanes' values (the lanes of one wavefront need no block barrier)
-__device__ __forceinline__ void wave_sync() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
 template <typename C>
 struct PlanDev {
   int n, nst;
@@ -203,6 +195,7 @@ struct PoisK {
   int rows;                    // x-rows per block
   int tp;                      // x-modes per block in the z passes
   int yP, yL, yr, ytl;         // wall-normal solve: segments, base length, longer ones, lines per block
+  int yPP;                     // yP rounded up to a power of two (lanes per mode in the reduction)
 };
 
 template <typename C>
@@ -611,7 +604,10 @@ __global__ __launch_bounds__(16 * X16_SC) void k_fftx256_inv(PoisK<C> K) {
 // thread eliminates its interior rows so that they become affine functions
 // of the two separators around the segment (its own last row and the
 // previous segment's), the P separator rows form a tridiagonal system solved
-// by parallel cyclic reduction in LDS, and each thread reconstructs its rows.
+// by cyclic reduction, and each thread reconstructs its rows.  The separator
+// rows are re-read transposed from LDS so that a mode's PP (P rounded up to a
+// power of two) separators sit in consecutive lanes of one wavefront, which
+// reduces them over cross-lane reads: three block barriers in all.
 // Every spectral value is read once and written once; the arithmetic is FP64
 // whatever the storage precision.  The systems are diagonally dominant
 // (|b| >= |a| + |c|), so the elimination needs no pivoting.
@@ -619,6 +615,240 @@ constexpr int YL = 8;
 
 template <typename C>
 __global__ __launch_bounds__(1024) void k_tri_y(PoisK<C> K) {
+  using R = typename RealOf<C>::T;
+  if (gated(K)) return;
+  extern __shared__ __align__(16) unsigned char smraw[];
+  double* sm = reinterpret_cast<double*>(smraw);  // 11 arrays [PP][TL + 1]
+  const GridView& g = K.g;
+  const int TL = K.ytl, P = K.yP, PP = K.yPP, SP = TL + 1;
+  const int lb = threadIdx.x % TL, s = threadIdx.x / TL;
+  const bool active = s < P;  // lanes of the padding segments only join the reduction
+  // modes q = k ldx + p over the padded rows; padding columns are skipped
+  const int64_t nm = (int64_t)g.nz * K.ldx;
+  const int64_t q = (int64_t)blockIdx.x * TL + lb;
+  const bool valid = active && q < nm && (int)(q % K.ldx) < g.nxh;
+  // LDS array f, separator seg, mode lane ln (padded stride: conflict-free in
+  // both the natural and the transposed order)
+  auto A = [&](int f, int seg, int ln) -> double& { return sm[((size_t)f * PP + seg) * SP + ln]; };
+  // padding lanes compute the last real segment's rows (never stored)
+  const int sx = active ? s : P - 1;
+  const int lo = sx * K.yL + (sx < K.yr ? sx : K.yr);
+  const int len = K.yL + (sx < K.yr ? 1 : 0);
+  const int m = len - 1;  // interior rows (at least 2); row lo+m is the separator
+  const bool zero = (q == 0);
+  // lanes past the last mode solve a harmless non-singular system
+  const double lam = valid ? K.lamx[q % K.ldx] + K.lamz[q / K.ldx] : -1.0;
+  C* __restrict__ X = K.spec + q;
+  double xr[YL], xi[YL], ah[YL], ch[YL];
+  double zr = 0.0, zi = 0.0;
+#pragma unroll
+  for (int e = 0; e < YL; ++e) {
+    xr[e] = 0.0;
+    xi[e] = 0.0;
+    ah[e] = 0.0;
+    ch[e] = 0.0;
+  }
+  if (valid) {
+#pragma unroll
+    for (int e = 0; e < YL; ++e)
+      if (e < len) {
+        const C v = X[(int64_t)(lo + e) * nm];
+        if (e < m) {
+          xr[e] = (double)v.x;
+          xi[e] = (double)v.y;
+        } else {
+          zr = (double)v.x;
+          zi = (double)v.y;
+        }
+      }
+  }
+  // forward elimination of the interior rows: row e becomes
+  //   x_e + ct_e x_{e+1} = dt_e - at_e z_left
+  double atp = 0.0, ctp = 0.0, dr = 0.0, di = 0.0;
+#pragma unroll
+  for (int e = 0; e < YL - 1; ++e)
+    if (e < m) {
+      const int j = lo + e;
+      double a = K.ylo[j], c = K.yhi[j], b = lam - (a + c);
+      double er = xr[e], ei = xi[e];
+      if (zero && j == 0) {
+        a = 0.0;
+        b = 1.0;
+        c = 0.0;
+        er = 0.0;
+        ei = 0.0;
+      }
+      const double inv = 1.0 / (b - a * ctp);
+      atp = (e == 0) ? a * inv : -a * atp * inv;
+      ctp = c * inv;
+      dr = (er - a * dr) * inv;
+      di = (ei - a * di) * inv;
+      ah[e] = atp;
+      ch[e] = ctp;
+      xr[e] = dr;
+      xi[e] = di;
+    }
+  // backward: x_e = d_e - ah_e z_left - ch_e z_right
+  double ahl = 0.0, chl = 0.0, dlr = 0.0, dli = 0.0;  // row m-1
+#pragma unroll
+  for (int e = YL - 2; e >= 0; --e)
+    if (e < m) {
+      if (e == m - 1) {
+        ahl = ah[e];
+        chl = ch[e];
+        dlr = xr[e];
+        dli = xi[e];
+      } else {
+        const double ct = ch[e];
+        xr[e] -= ct * xr[e + 1];
+        xi[e] -= ct * xi[e + 1];
+        ah[e] -= ct * ah[e + 1];
+        ch[e] = -ct * ch[e + 1];
+      }
+    }
+  // the first interior row of each segment, for the separator row before it
+  if (active) {
+    A(0, s, lb) = ah[0];
+    A(1, s, lb) = ch[0];
+    A(2, s, lb) = xr[0];
+    A(3, s, lb) = xi[0];
+  }
+  __syncthreads();
+  if (active) {
+    const int jz = lo + m;
+    const double az = K.ylo[jz], cz = K.yhi[jz], bz = lam - (az + cz);
+    double rb = bz - az * chl, rg = 0.0;
+    double rdr = zr - az * dlr, rdi = zi - az * dli;
+    if (s + 1 < P) {
+      rb -= cz * A(0, s + 1, lb);
+      rg = -cz * A(1, s + 1, lb);
+      rdr -= cz * A(2, s + 1, lb);
+      rdi -= cz * A(3, s + 1, lb);
+    }
+    A(4, s, lb) = -az * ahl;
+    A(5, s, lb) = rb;
+    A(6, s, lb) = rg;
+    A(7, s, lb) = rdr;
+    A(8, s, lb) = rdi;
+  }
+  __syncthreads();
+  {
+    // transposed: lane (mode lt, separator st), PP lanes per mode; rows past
+    // P and outside 0..PP-1 act as identity rows
+    const int lt = threadIdx.x / PP, st = threadIdx.x % PP;
+    const int grp = (threadIdx.x & 63) - st;
+    const bool own = lt < TL && st < P;
+    double ra = 0.0, rb = 1.0, rg = 0.0, rdr = 0.0, rdi = 0.0;
+    if (own) {
+      ra = A(4, st, lt);
+      rb = A(5, st, lt);
+      rg = A(6, st, lt);
+      rdr = A(7, st, lt);
+      rdi = A(8, st, lt);
+    }
+    for (int step = 1; step < PP; step <<= 1) {
+      const int im = st - step, ip = st + step;
+      const bool hm = im >= 0, hp = ip < PP;
+      const int sm_ = grp + (hm ? im : st), sp_ = grp + (hp ? ip : st);
+      double am = lane_read(ra, sm_), bm = lane_read(rb, sm_), gm = lane_read(rg, sm_);
+      double dmr = lane_read(rdr, sm_), dmi = lane_read(rdi, sm_);
+      double ap = lane_read(ra, sp_), bp = lane_read(rb, sp_), gp = lane_read(rg, sp_);
+      double dpr = lane_read(rdr, sp_), dpi = lane_read(rdi, sp_);
+      if (!hm) {
+        am = 0.0;
+        bm = 1.0;
+        gm = 0.0;
+        dmr = 0.0;
+        dmi = 0.0;
+      }
+      if (!hp) {
+        ap = 0.0;
+        bp = 1.0;
+        gp = 0.0;
+        dpr = 0.0;
+        dpi = 0.0;
+      }
+      const double k1 = ra / bm, k2 = rg / bp;
+      const double na = -am * k1, ng = -gp * k2;
+      rb = rb - gm * k1 - ap * k2;
+      rdr = rdr - dmr * k1 - dpr * k2;
+      rdi = rdi - dmi * k1 - dpi * k2;
+      ra = na;
+      rg = ng;
+    }
+    if (own) {
+      A(9, st, lt) = rdr / rb;
+      A(10, st, lt) = rdi / rb;
+    }
+  }
+  __syncthreads();
+  const double zRr = A(9, s, lb), zRi = A(10, s, lb);
+  const double zLr = (s > 0) ? A(9, s - 1, lb) : 0.0;
+  const double zLi = (s > 0) ? A(10, s - 1, lb) : 0.0;
+#pragma unroll
+  for (int e = 0; e < YL - 1; ++e)
+    if (e < m) {
+      xr[e] = xr[e] - ah[e] * zLr - ch[e] * zRr;
+      xi[e] = xi[e] - ah[e] * zLi - ch[e] * zRi;
+    }
+  zr = zRr;
+  zi = zRi;
+  if (blockIdx.x == 0) {
+    // zero volume-weighted mean of the (0,0) mode (lane 0 of block 0):
+    // per-segment partial sums, then their sum in segment order
+    double pr = 0.0, pi = 0.0;
+    if (lb == 0) {
+#pragma unroll
+      for (int e = 0; e < YL; ++e)
+        if (e < len) {
+          const double dyj = g.dy[lo + e];
+          pr += dyj * (e < m ? xr[e] : zr);
+          pi += dyj * (e < m ? xi[e] : zi);
+        }
+    }
+    __syncthreads();
+    if (lb == 0) {
+      A(0, s, 0) = pr;
+      A(1, s, 0) = pi;
+    }
+    __syncthreads();
+    if (lb == 0) {
+      double Mr = 0.0, Mi = 0.0;
+      for (int t = 0; t < P; ++t) {
+        Mr += A(0, t, 0);
+        Mi += A(1, t, 0);
+      }
+      Mr *= K.inv_sum_dy;
+      Mi *= K.inv_sum_dy;
+#pragma unroll
+      for (int e = 0; e < YL - 1; ++e)
+        if (e < m) {
+          xr[e] -= Mr;
+          xi[e] -= Mi;
+        }
+      zr -= Mr;
+      zi -= Mi;
+    }
+  }
+  if (valid) {
+    // an FP32 spectrum hands the (0,0) mode (a real column) to the inverse x
+    // pass in FP64, so that the zero-mean gauge survives the FP32 rounding
+    const bool keep = zero && K.zm;
+#pragma unroll
+    for (int e = 0; e < YL; ++e)
+      if (e < len) {
+        const double vr = (e < m) ? xr[e] : zr;
+        const double vi = (e < m) ? xi[e] : zi;
+        if (keep) K.zm[lo + e] = vr;
+        X[(int64_t)(lo + e) * nm] = keep ? mkc<C>((R)0, (R)0) : mkc<C>((R)vr, (R)vi);
+      }
+  }
+}
+
+// The same solve with the separator system reduced block-wide in LDS, for
+// modes of more than 64 separators (P rounded up past one wavefront).
+template <typename C>
+__global__ __launch_bounds__(1024) void k_tri_y_blk(PoisK<C> K) {
   using R = typename RealOf<C>::T;
   if (gated(K)) return;
   extern __shared__ __align__(16) unsigned char smraw[];
@@ -936,7 +1166,11 @@ static void run_passes(Prof* pf, hipStream_t s, const GridView& g, PoisK<C> K) {
   if (tp > 16) tp = 16;
   K.tp = tp;
   line_plan(g.ny, false, YL, &K.yP, &K.yL, &K.yr);
-  K.ytl = 1024 / K.yP;
+  K.yPP = 1;
+  while (K.yPP < K.yP) K.yPP <<= 1;
+  // separators of one mode in one wavefront when they fit; else block-wide
+  const bool ywave = K.yPP <= 64;
+  K.ytl = 1024 / (ywave ? K.yPP : K.yP);
   if (K.ytl > 16) K.ytl = 16;
   if (K.ytl < 1) K.ytl = 1;
   const int64_t nrows = (int64_t)g.ny * g.nz;
@@ -947,7 +1181,8 @@ static void run_passes(Prof* pf, hipStream_t s, const GridView& g, PoisK<C> K) {
   K.ldx = spec_ld(g.nxh, sizeof(C) == sizeof(float2));
   const int64_t nm = (int64_t)g.nz * K.ldx;
   const int yblocks = (int)((nm + K.ytl - 1) / K.ytl);
-  const size_t ysh = 7 * sizeof(double) * (size_t)K.yP * K.ytl;
+  const size_t ysh = ywave ? 11 * sizeof(double) * (size_t)K.yPP * (K.ytl + 1)
+                           : 7 * sizeof(double) * (size_t)K.yP * K.ytl;
   const bool resid = K.mode >= SRC_RESIDUAL;
   // length-256 x transforms: 2 X16_SC rows per block
   const bool x256 = (g.nx == 256);
@@ -971,7 +1206,10 @@ static void run_passes(Prof* pf, hipStream_t s, const GridView& g, PoisK<C> K) {
     IBM_LAUNCH(pf, "pois_fftz_fwd", s, (k_fftz256<C, false><<<z16grid, 16 * Z16_TC, 0, s>>>(K)));
   else
     IBM_LAUNCH(pf, "pois_fftz_fwd", s, (k_fftz<C, false><<<zgrid, 256, zsh, s>>>(K)));
-  IBM_LAUNCH(pf, "pois_tri_y", s, (k_tri_y<C><<<yblocks, K.ytl * K.yP, ysh, s>>>(K)));
+  if (ywave)
+    IBM_LAUNCH(pf, "pois_tri_y", s, (k_tri_y<C><<<yblocks, K.ytl * K.yPP, ysh, s>>>(K)));
+  else
+    IBM_LAUNCH(pf, "pois_tri_y", s, (k_tri_y_blk<C><<<yblocks, K.ytl * K.yP, ysh, s>>>(K)));
   if (z256)
     IBM_LAUNCH(pf, "pois_fftz_inv", s, (k_fftz256<C, true><<<z16grid, 16 * Z16_TC, 0, s>>>(K)));
   else
