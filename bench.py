@@ -192,8 +192,10 @@ def run_form(args, wl, form, dev):
 
 def run_batched(args, dev, nsim):
     """Times the batched workload (nsim simulations of different sizes, one
-    body each) in each execution mode; returns {mode: (cell-steps/s,
-    ms per step)} and the total cell count."""
+    body each) in each execution mode, then autotunes the plan (stream
+    groups, RHS tile, graph or streams) and times the tuned plan; returns
+    {mode: (cell-steps/s, ms per step)}, the total cell count and the tuner's
+    report."""
     import numpy as np
     import torch
     import workloads
@@ -232,6 +234,26 @@ def run_batched(args, dev, nsim):
         el = time.perf_counter() - t0
         out[name] = (cells * 2 * args.steps / el, el / args.steps * 1e3)
         progress(f"batched {name}: {el / args.steps * 1e3:.3f} ms per step")
+    progress("batched: autotuning the plan")
+    t0 = time.perf_counter()
+    best, tried = batch.tune([wl.bodies[0].coef(k * dt) for wl in wls], dt, steps=3)
+    tune_s = time.perf_counter() - t0
+    progress(f"batched: tuned plan {best} in {tune_s:.1f} s")
+    for _ in range(args.warmup):
+        batch.step([wl.bodies[0].coef(k * dt) for wl in wls], dt, ibm.BATCH_PLAN)
+        k += 1
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        batch.step([wl.bodies[0].coef(k * dt) for wl in wls], dt, ibm.BATCH_PLAN)
+        k += 1
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    out["tuned"] = (cells * 2 * args.steps / el, el / args.steps * 1e3)
+    progress(f"batched tuned: {el / args.steps * 1e3:.3f} ms per step")
+    tune = {"plan": best, "tune_seconds": round(tune_s, 2),
+            "tried": [{k2: (round(v, 3) if isinstance(v, float) else v) for k2, v in p.items()}
+                      for p in tried]}
     flags = batch.check()
     if flags:
         print(f"bench.py: device flags {flags} after the batched run", file=sys.stderr)
@@ -241,7 +263,7 @@ def run_batched(args, dev, nsim):
             print("bench.py: non-finite state after the batched run", file=sys.stderr)
             sys.exit(1)
     batch.close()
-    return out, cells
+    return out, cells, tune
 
 
 def main():
@@ -298,14 +320,15 @@ def main():
         results[form] = r
     batched = None
     if args.batch_sims > 0:
-        modes, bcells = run_batched(args, dev, args.batch_sims)
+        modes, bcells, tune = run_batched(args, dev, args.batch_sims)
         best = max(modes, key=lambda m: modes[m][0])
         batched = {"workload": f"c4: {args.batch_sims} simulations, {bcells} cells in total "
                                "(uniform spacing 1/32, 32..128 x 32..96 x 32..128, one sphere, "
                                "plate or deforming body each), Re 100, dt 1e-3, FP64",
                    "value": modes[best][0], "ms_per_step": modes[best][1], "mode": best,
                    "modes": {m: {"value": v, "ms_per_step": ms} for m, (v, ms) in modes.items()},
-                   "speedup_vs_serial": modes[best][0] / modes["serial"][0]}
+                   "speedup_vs_serial": modes[best][0] / modes["serial"][0],
+                   "autotune": tune}
     head = results[forms[0]]
     copy_ref = None
     if args.copy_ref_mib:

@@ -268,6 +268,7 @@ typedef struct ibm_batch ibm_batch;
 #define IBM_BATCH_SERIAL 0  /* one simulation after the other */
 #define IBM_BATCH_STREAMS 1 /* concurrent streams, launched every step */
 #define IBM_BATCH_GRAPH 2   /* one captured HIP graph replayed every step */
+#define IBM_BATCH_PLAN 3    /* the mode of the batch's current plan */
 
 /* One simulation of a batch.  state: dev arrays as for ibm_step (the
  * batch keeps the pointers); ref: dev f64[nv*3] reference vertices (rigid)
@@ -295,15 +296,51 @@ ibm_ctx* ibm_batch_context(ibm_batch* b, int32_t sim);
 /* One time step of every simulation: body transform at t^n from
  * coef (host f64[nsim*IBM_COEF_STRIDE]; simulation s at s*IBM_COEF_STRIDE,
  * rigid: the 18 values of ibm_body_rigid, deform: the first 6 values of
- * ibm_body_deform), then ibm_step.  mode: IBM_BATCH_SERIAL, _STREAMS or
- * _GRAPH; the first _GRAPH call for a dt captures the graph (a change of dt
- * drops it).  Results are identical in every mode and to ibm_step run on
+ * ibm_body_deform), then ibm_step.  mode: IBM_BATCH_SERIAL, _STREAMS,
+ * _GRAPH or _PLAN (the current plan's mode; streams and graph modes use the
+ * plan's stream groups and tile choice); the first graph call for a dt
+ * captures the graph (a change of dt or of plan drops it).  Results are identical in every mode and to ibm_step run on
  * each simulation alone.  The first call for a dt synchronises once (line
  * tables); later calls only enqueue, except that the host waits when the
  * coefficient staging ring (4 slots) is full. */
 int ibm_batch_step(ibm_batch* b, const double* coef, double dt, int32_t mode);
 /* Synchronise and return (and clear) the OR of every simulation's flags. */
 int ibm_batch_check(ibm_batch* b, uint32_t* flags);
+
+/* Execution plan of a batch (an arrangement of the same arithmetic: every
+ * plan gives results identical to IBM_BATCH_SERIAL).
+ *   mode:       IBM_BATCH_STREAMS or IBM_BATCH_GRAPH, used by IBM_BATCH_PLAN
+ *   streams:    stream groups, 1..nsim: the simulations, largest first, are
+ *               dealt round-robin to the groups; a group runs its
+ *               simulations one after the other, groups run concurrently
+ *   rhs_planes: wall-normal planes per block of the predictor right-hand
+ *               side, 1..16 (fewer planes, more blocks on small grids)
+ *   ms_per_step: filled by ibm_batch_tune (the measured time), else ignored
+ * A new batch starts with {IBM_BATCH_GRAPH, nsim, 16}. */
+typedef struct {
+  int32_t mode;
+  int32_t streams;
+  int32_t rhs_planes;
+  int32_t reserved;
+  double ms_per_step;
+} ibm_batch_plan;
+/* Apply a plan (drops a captured graph).  IBM_EINVAL for values out of
+ * range. */
+int ibm_batch_set_plan(ibm_batch* b, const ibm_batch_plan* plan);
+int ibm_batch_get_plan(ibm_batch* b, ibm_batch_plan* plan);
+/* Autotuner: times candidate plans on this batch's own simulations (a
+ * coordinate search over streams in {1, 2, 4, ..., nsim}, then rhs_planes in
+ * {16, 8, 4}, then graph vs eager streams), `steps` timed steps each after
+ * one untimed step, all with the body coefficients `coef` and step dt.  The
+ * simulations' states (u, v, w, p and, for AB2, h) are saved first and
+ * restored after every trial, so tuning leaves them as they were; the
+ * snapshot is device memory allocated and freed inside the call.  Applies
+ * the fastest plan and returns it in *best; if table is not NULL, up to
+ * max_entries tried plans (with their times) are written there and *n_tried
+ * gets their count.  Synchronises. */
+int ibm_batch_tune(ibm_batch* b, const double* coef, double dt, int32_t steps,
+                   ibm_batch_plan* best, ibm_batch_plan* table, int32_t max_entries,
+                   int32_t* n_tried);
 
 /* Mixed form: synchronise and copy the refinement statistics since the
  * last reset to stats (host double[4]): Poisson solves, FP64-residual

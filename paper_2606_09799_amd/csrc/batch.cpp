@@ -9,9 +9,18 @@
 // coefficients, which change every step, are read by the body kernels from a
 // device buffer that is refreshed (one stream-ordered copy) before each step,
 // so a replayed graph sees the new motion.
+//
+// Execution plans and the autotuner: the simulations, largest first, are
+// dealt round-robin to a chosen number of stream groups (each group runs its
+// simulations one after the other); together with the graph/eager choice and
+// the planes per block of the RHS march this is the plan.  ibm_batch_tune
+// times candidate plans on the batch's own simulations and keeps the
+// fastest, restoring the simulations' states after every trial.
 #include "ibm.h"
 
+#include <algorithm>
 #include <cstring>
+#include <numeric>
 #include <vector>
 
 #include "internal.h"
@@ -21,6 +30,8 @@ hipStream_t ctx_stream(ibm_ctx* c);
 Prof* ctx_prof(ibm_ctx* c);
 int ctx_prepare(ibm_ctx* c, const ibm_body* b, int32_t nb, double dt);
 int ctx_fail(int code, const char* msg);
+void ctx_set_rhs_planes(ibm_ctx* c, int planes);
+void ctx_state_layout(ibm_ctx* c, int64_t* ncell, int64_t* nvface, int* pbytes);
 }  // namespace ibm
 
 using namespace ibm;
@@ -48,6 +59,9 @@ struct ibm_batch {
   double prep_dt = -1.0;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
+  ibm_batch_plan plan{IBM_BATCH_GRAPH, 0, 16, 0, 0.0};
+  std::vector<int> order;  // simulations by decreasing cell count
+  std::vector<int> grp;    // stream group of each simulation
 };
 
 #define BCHK(expr)                                                          \
@@ -89,11 +103,22 @@ static void free_batch(ibm_batch* b) {
 
 // every simulation's body transform and step, forked from b->own and joined
 // back into it; serial: each simulation waits for the previous one
+// every simulation's body transform and step, forked from b->own and joined
+// back into it.  Serial: each simulation waits for the previous one.
+// Otherwise the plan's stream groups run concurrently, each group's
+// simulations (largest first) one after the other on the group's stream.
 static int enqueue(ibm_batch* b, double dt, bool serial) {
   BCHK(hipEventRecord(b->fork, b->own));
-  for (int s = 0; s < b->n; ++s) {
-    hipStream_t ss = b->sstream[s];
-    BCHK(hipStreamWaitEvent(ss, (serial && s > 0) ? b->done[s - 1] : b->fork, 0));
+  std::vector<int> last(b->n, -1);  // last simulation enqueued on each group
+  int prev = -1;
+  for (int r = 0; r < b->n; ++r) {
+    const int s = b->order[r];
+    const int gi = b->grp[s];
+    hipStream_t ss = b->sstream[gi];
+    if (serial)
+      BCHK(hipStreamWaitEvent(ss, prev >= 0 ? b->done[prev] : b->fork, 0));
+    else if (last[gi] < 0)
+      BCHK(hipStreamWaitEvent(ss, b->fork, 0));
     const ibm_sim& m = b->sim[s];
     launch_body_dev(ctx_prof(b->ctx[s]), ss, m.motion == IBM_MOTION_DEFORM, m.ref, m.nv,
                     b->coef_dev + (size_t)s * IBM_COEF_STRIDE, m.xyz, m.vel);
@@ -101,13 +126,28 @@ static int enqueue(ibm_batch* b, double dt, bool serial) {
     const int rc = ibm_step(b->ctx[s], &st, &b->body[s], 1, dt);
     if (rc) return rc;
     BCHK(hipEventRecord(b->done[s], ss));
+    last[gi] = s;
+    prev = s;
   }
   if (serial) {
-    BCHK(hipStreamWaitEvent(b->own, b->done[b->n - 1], 0));
+    BCHK(hipStreamWaitEvent(b->own, b->done[prev], 0));
   } else {
-    for (int s = 0; s < b->n; ++s) BCHK(hipStreamWaitEvent(b->own, b->done[s], 0));
+    for (int gi = 0; gi < b->n; ++gi)
+      if (last[gi] >= 0) BCHK(hipStreamWaitEvent(b->own, b->done[last[gi]], 0));
   }
   return IBM_OK;
+}
+
+// deal the simulations (largest first) to the plan's stream groups and point
+// each context at its group's stream; set the RHS tile of every context
+static void apply_plan(ibm_batch* b, const ibm_batch_plan& p) {
+  drop_graph(b);
+  b->plan = p;
+  for (int r = 0; r < b->n; ++r) b->grp[b->order[r]] = r % p.streams;
+  for (int s = 0; s < b->n; ++s) {
+    (void)ibm_set_stream(b->ctx[s], b->sstream[b->grp[s]]);
+    ctx_set_rhs_planes(b->ctx[s], p.rhs_planes);
+  }
 }
 
 extern "C" {
@@ -157,6 +197,18 @@ int ibm_batch_create(const ibm_grid* grids, const ibm_opts* opts, const ibm_sim*
     bd.tri = sims[s].tri;
     b->body.push_back(bd);
   }
+  {
+    // simulations by decreasing cell count (ties by index)
+    std::vector<int64_t> cells(nsim);
+    for (int s = 0; s < nsim; ++s) cells[s] = (int64_t)grids[s].nx * grids[s].ny * grids[s].nz;
+    b->order.resize(nsim);
+    std::iota(b->order.begin(), b->order.end(), 0);
+    std::stable_sort(b->order.begin(), b->order.end(),
+                     [&](int x, int y) { return cells[x] > cells[y]; });
+    b->grp.assign(nsim, 0);
+    ibm_batch_plan p0{IBM_BATCH_GRAPH, nsim, 16, 0, 0.0};
+    apply_plan(b, p0);
+  }
   BTRY(hipEventCreateWithFlags(&b->fork, hipEventDisableTiming));
   BTRY(hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming));
   BTRY(hipEventCreateWithFlags(&b->ev_out, hipEventDisableTiming));
@@ -181,8 +233,9 @@ ibm_ctx* ibm_batch_context(ibm_batch* b, int32_t sim) {
 }
 
 int ibm_batch_step(ibm_batch* b, const double* coef, double dt, int32_t mode) {
-  if (!b || !coef || !(dt > 0) || mode < IBM_BATCH_SERIAL || mode > IBM_BATCH_GRAPH)
+  if (!b || !coef || !(dt > 0) || mode < IBM_BATCH_SERIAL || mode > IBM_BATCH_PLAN)
     return ctx_fail(IBM_EINVAL, "ibm_batch_step: bad argument");
+  if (mode == IBM_BATCH_PLAN) mode = b->plan.mode;
   if (dt != b->prep_dt) {
     // tables and body descriptors for this dt, outside any capture
     drop_graph(b);
@@ -227,6 +280,155 @@ int ibm_batch_step(ibm_batch* b, const double* coef, double dt, int32_t mode) {
   }
   BCHK(hipEventRecord(b->ev_out, b->own));
   BCHK(hipStreamWaitEvent(b->stream, b->ev_out, 0));
+  return IBM_OK;
+}
+
+static bool plan_ok(const ibm_batch* b, const ibm_batch_plan& p) {
+  return (p.mode == IBM_BATCH_STREAMS || p.mode == IBM_BATCH_GRAPH) && p.streams >= 1 &&
+         p.streams <= b->n && p.rhs_planes >= 1 && p.rhs_planes <= 16;
+}
+
+int ibm_batch_set_plan(ibm_batch* b, const ibm_batch_plan* plan) {
+  if (!b || !plan || !plan_ok(b, *plan)) return ctx_fail(IBM_EINVAL, "ibm_batch_set_plan: bad plan");
+  BCHK(hipStreamSynchronize(b->own));
+  apply_plan(b, *plan);
+  return IBM_OK;
+}
+
+int ibm_batch_get_plan(ibm_batch* b, ibm_batch_plan* plan) {
+  if (!b || !plan) return ctx_fail(IBM_EINVAL, "ibm_batch_get_plan: bad argument");
+  *plan = b->plan;
+  return IBM_OK;
+}
+
+int ibm_batch_tune(ibm_batch* b, const double* coef, double dt, int32_t steps,
+                   ibm_batch_plan* best, ibm_batch_plan* table, int32_t max_entries,
+                   int32_t* n_tried) {
+  if (!b || !coef || !best || !(dt > 0) || steps < 1 || steps > 1000 ||
+      (table && max_entries < 0))
+    return ctx_fail(IBM_EINVAL, "ibm_batch_tune: bad argument");
+  // snapshot of every simulation's state: u, v, w, p and the AB2 H arrays
+  struct Arr {
+    void* p;
+    size_t bytes;
+    size_t off;
+  };
+  std::vector<Arr> arrs;
+  size_t total = 0;
+  for (int s = 0; s < b->n; ++s) {
+    int64_t nc = 0, nv = 0;
+    int pb = 8;
+    ctx_state_layout(b->ctx[s], &nc, &nv, &pb);
+    const ibm_state& st = b->sim[s].state;
+    auto add = [&](void* p, size_t bytes) {
+      if (!p) return;
+      total = (total + 255) / 256 * 256;
+      arrs.push_back({p, bytes, total});
+      total += bytes;
+    };
+    add(st.u, 8 * (size_t)nc);
+    add(st.v, 8 * (size_t)nv);
+    add(st.w, 8 * (size_t)nc);
+    add(st.p, (size_t)pb * nc);
+    for (int q = 0; q < 3; ++q) add(st.h[q], (size_t)pb * (q == 1 ? nv : nc));
+  }
+  BCHK(hipStreamSynchronize(b->stream));
+  BCHK(hipStreamSynchronize(b->own));
+  char* snap = nullptr;
+  BCHK(hipMalloc(&snap, total ? total : 1));
+  hipEvent_t t0 = nullptr, t1 = nullptr;
+  int rc = IBM_OK;
+  const ibm_batch_plan start = b->plan;
+  std::vector<ibm_batch_plan> tried;
+  auto copy_all = [&](bool save) -> int {
+    for (const Arr& a : arrs) {
+      hipError_t e = save ? hipMemcpyAsync(snap + a.off, a.p, a.bytes, hipMemcpyDeviceToDevice, b->own)
+                          : hipMemcpyAsync(a.p, snap + a.off, a.bytes, hipMemcpyDeviceToDevice, b->own);
+      if (e != hipSuccess) return ctx_fail(IBM_EHIP, "ibm_batch_tune: state copy failed");
+    }
+    return hipStreamSynchronize(b->own) == hipSuccess ? IBM_OK
+                                                      : ctx_fail(IBM_EHIP, "ibm_batch_tune: sync");
+  };
+  // one trial: an untimed step (it captures the graph), then `steps` timed
+  // steps, the state restored before each part
+  auto trial = [&](ibm_batch_plan p, double* ms) -> int {
+    apply_plan(b, p);
+    int r = copy_all(false);
+    if (r) return r;
+    r = ibm_batch_step(b, coef, dt, p.mode);
+    if (r) return r;
+    if (hipStreamSynchronize(b->stream) != hipSuccess) return ctx_fail(IBM_EHIP, "ibm_batch_tune: sync");
+    r = copy_all(false);
+    if (r) return r;
+    if (hipEventRecord(t0, b->stream) != hipSuccess) return ctx_fail(IBM_EHIP, "ibm_batch_tune: event");
+    for (int k = 0; k < steps; ++k) {
+      r = ibm_batch_step(b, coef, dt, p.mode);
+      if (r) return r;
+    }
+    if (hipEventRecord(t1, b->stream) != hipSuccess || hipEventSynchronize(t1) != hipSuccess)
+      return ctx_fail(IBM_EHIP, "ibm_batch_tune: event");
+    float el = 0.f;
+    if (hipEventElapsedTime(&el, t0, t1) != hipSuccess) return ctx_fail(IBM_EHIP, "ibm_batch_tune: event");
+    *ms = (double)el / steps;
+    p.ms_per_step = *ms;
+    tried.push_back(p);
+    return IBM_OK;
+  };
+  ibm_batch_plan bp{IBM_BATCH_GRAPH, b->n, 16, 0, 1e300};
+  do {
+    if (hipEventCreate(&t0) != hipSuccess || hipEventCreate(&t1) != hipSuccess) {
+      rc = ctx_fail(IBM_EHIP, "ibm_batch_tune: event create");
+      break;
+    }
+    rc = copy_all(true);
+    if (rc) break;
+    // 1. stream groups (graph mode, 16 planes)
+    std::vector<int> gs;
+    for (int g = 1; g < b->n; g *= 2) gs.push_back(g);
+    gs.push_back(b->n);
+    for (int g : gs) {
+      double ms = 0.0;
+      ibm_batch_plan p{IBM_BATCH_GRAPH, g, 16, 0, 0.0};
+      rc = trial(p, &ms);
+      if (rc) break;
+      if (ms < bp.ms_per_step) bp = tried.back();
+    }
+    if (rc) break;
+    // 2. planes per block of the RHS march
+    for (int pl : {8, 4}) {
+      double ms = 0.0;
+      ibm_batch_plan p = bp;
+      p.rhs_planes = pl;
+      rc = trial(p, &ms);
+      if (rc) break;
+      if (ms < bp.ms_per_step) bp = tried.back();
+    }
+    if (rc) break;
+    // 3. eager streams instead of the graph
+    {
+      double ms = 0.0;
+      ibm_batch_plan p = bp;
+      p.mode = IBM_BATCH_STREAMS;
+      rc = trial(p, &ms);
+      if (rc) break;
+      if (ms < bp.ms_per_step) bp = tried.back();
+    }
+  } while (false);
+  // restore the states and apply the winner (or the starting plan on failure)
+  const int rc2 = copy_all(false);
+  (void)hipFree(snap);
+  if (t0) (void)hipEventDestroy(t0);
+  if (t1) (void)hipEventDestroy(t1);
+  if (rc) {
+    apply_plan(b, start);
+    return rc;
+  }
+  if (rc2) return rc2;
+  apply_plan(b, bp);
+  *best = bp;
+  if (table)
+    for (int k = 0; k < (int)tried.size() && k < max_entries; ++k) table[k] = tried[k];
+  if (n_tried) *n_tried = (int32_t)tried.size();
   return IBM_OK;
 }
 

@@ -71,6 +71,7 @@ void prof_end(Prof* p, hipStream_t s) {
 // ------------------------------------------------------------ context
 struct ibm_ctx {
   int dev = 0;
+  int rhs_planes = 0;  // planes per block of the RHS march (0: the default)
   hipStream_t stream = nullptr;
   int nx = 0, ny = 0, nz = 0;
   double lx = 0, lz = 0;
@@ -808,6 +809,7 @@ static int viscous(ibm_ctx* c, const void* p, const void* const* hprev, void* co
   a.re = c->opts.re;
   a.fx = -c->opts.dpdx;
   a.fp32 = c->fp32;
+  a.planes = c->rhs_planes;
   launch_rhs(&c->prof, c->stream, c->g, a);
   double* f[3] = {u, v, w};
   for (int q = 0; q < 3; ++q) {
@@ -1019,6 +1021,17 @@ int ctx_prepare(ibm_ctx* c, const ibm_body* b, int32_t nb, double dt) {
 int ctx_fail(int code, const char* msg) {
   g_last_error = msg;
   return code;
+}
+
+void ctx_set_rhs_planes(ibm_ctx* c, int planes) { c->rhs_planes = planes; }
+
+// element counts of the state arrays and their element sizes: u, w and p
+// have ncell values, v nvface; u, v, w are FP64; p and the AB2 H arrays are
+// pbytes wide (8, or 4 in the mixed form)
+void ctx_state_layout(ibm_ctx* c, int64_t* ncell, int64_t* nvface, int* pbytes) {
+  *ncell = c->ncell;
+  *nvface = c->nvface;
+  *pbytes = (int)c->es;
 }
 
 }  // namespace ibm

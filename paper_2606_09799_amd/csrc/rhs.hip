@@ -32,7 +32,7 @@ namespace ibm {
 constexpr int RTX = 64, RTZ = 8;           // tile (threads per block: RTX x RTZ)
 constexpr int RHX = RTX + 2, RHZ = RTZ + 2; // tile with halo
 constexpr int RPL = RHX * RHZ;              // values per plane in LDS
-constexpr int RJC = 16;                     // planes per block
+constexpr int RJC = 16;                     // planes per block (at most; a launch may take fewer)
 // ring slots: u 0..2, v 3..5, w 6..8, p 9..10
 constexpr int RSLOTS = 11;
 // metric coefficients of a chunk after the ring: idy[j0-1 .. j0+JC-1],
@@ -50,6 +50,7 @@ struct RhsK {
   T* R[3];
   const uint32_t* mask[3];
   double gamma, rho, alpha, dt, re, fx;
+  int jc;  // planes per block, 1..RJC
 };
 
 // elements of one halo plane per thread (RPL values over RTX*RTZ threads)
@@ -115,12 +116,13 @@ __global__ __launch_bounds__(RTX * RTZ) __attribute__((amdgpu_waves_per_eu(4))) 
   const GridView& g = K.g;
   const RhsK<T>& a = K;
   const int nbx = (g.nx + RTX - 1) / RTX, nbz = (g.nz + RTZ - 1) / RTZ;
-  const int nchunk = (g.ny + RJC - 1) / RJC;
+  const int jc = K.jc;
+  const int nchunk = (g.ny + jc - 1) / jc;
   const int64_t t = xcd_tile(blockIdx.x, (int64_t)nbx * nbz * nchunk);
   const int i0 = (int)(t % nbx) * RTX;
   const int k0 = (int)((t / nbx) % nbz) * RTZ;
-  const int j0 = (int)(t / ((int64_t)nbx * nbz)) * RJC;
-  const int j1 = (j0 + RJC < g.ny) ? j0 + RJC : g.ny;
+  const int j0 = (int)(t / ((int64_t)nbx * nbz)) * jc;
+  const int j1 = (j0 + jc < g.ny) ? j0 + jc : g.ny;
   const int tx = threadIdx.x % RTX, tz = threadIdx.x / RTX;
   const int i = i0 + tx, k = k0 + tz;
   const bool valid = FULL || (i < g.nx && k < g.nz);
@@ -353,8 +355,9 @@ static void run_rhs(Prof* pf, hipStream_t s, const GridView& g, const RhsArgs& a
   K.dt = a.dt;
   K.re = a.re;
   K.fx = a.fx;
+  K.jc = (a.planes >= 1 && a.planes <= RJC) ? a.planes : RJC;
   const int64_t blocks = (int64_t)((g.nx + RTX - 1) / RTX) * ((g.nz + RTZ - 1) / RTZ) *
-                         ((g.ny + RJC - 1) / RJC);
+                         ((g.ny + K.jc - 1) / K.jc);
   const size_t shm = sizeof(double) * (RSLOTS * RPL + RCOEF);
   const int f = ((g.nx % RTX == 0 && g.nz % RTZ == 0) ? RHS_FULL : 0) |
                 (a.rho != 0.0 ? RHS_HPREV : 0) |

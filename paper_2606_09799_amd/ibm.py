@@ -98,6 +98,17 @@ _batch_destroy = _sig("ibm_batch_destroy", None, c_void_p)
 _batch_context = _sig("ibm_batch_context", c_void_p, c_void_p, c_int32)
 _batch_step = _sig("ibm_batch_step", c_int32, c_void_p, POINTER(c_double), c_double, c_int32)
 _batch_check = _sig("ibm_batch_check", c_int32, c_void_p, POINTER(c_uint32))
+
+
+class IbmBatchPlan(ctypes.Structure):
+    _fields_ = [("mode", c_int32), ("streams", c_int32), ("rhs_planes", c_int32),
+                ("reserved", c_int32), ("ms_per_step", c_double)]
+
+
+_batch_set_plan = _sig("ibm_batch_set_plan", c_int32, c_void_p, POINTER(IbmBatchPlan))
+_batch_get_plan = _sig("ibm_batch_get_plan", c_int32, c_void_p, POINTER(IbmBatchPlan))
+_batch_tune = _sig("ibm_batch_tune", c_int32, c_void_p, POINTER(c_double), c_double, c_int32,
+                   POINTER(IbmBatchPlan), POINTER(IbmBatchPlan), c_int32, POINTER(c_int32))
 _check = _sig("ibm_check", c_int32, c_void_p, POINTER(c_uint32))
 _strerror = _sig("ibm_strerror", c_char_p, c_int32)
 _profile = _sig("ibm_profile", c_int32, c_void_p, c_int32, c_char_p)
@@ -109,9 +120,10 @@ EXPORTS = ("ibm_create", "ibm_destroy", "ibm_set_stream", "ibm_body_rigid", "ibm
            "ibm_mass_rhs", "poisson_solve", "ibm_project", "ibm_step", "ibm_refine_stats",
            "ibm_check", "ibm_strerror", "ibm_profile", "ibm_profile_read",
            "ibm_batch_create", "ibm_batch_destroy", "ibm_batch_context", "ibm_batch_step",
-           "ibm_batch_check")
+           "ibm_batch_check", "ibm_batch_set_plan", "ibm_batch_get_plan", "ibm_batch_tune")
 COEF_STRIDE = 18
-BATCH_SERIAL, BATCH_STREAMS, BATCH_GRAPH = 0, 1, 2
+BATCH_SERIAL, BATCH_STREAMS, BATCH_GRAPH, BATCH_PLAN = 0, 1, 2, 3
+_MODE_NAMES = {BATCH_STREAMS: "streams", BATCH_GRAPH: "graph"}
 MOTION_RIGID, MOTION_DEFORM = 0, 1
 
 
@@ -417,14 +429,44 @@ class Batch:
         self.sims = [_Sim(c_void_p(_batch_context(h, s)), *self.shapes[s], pdtype)
                      for s in range(n)]
 
-    def step(self, coef, dt, mode=BATCH_GRAPH):
+    def _coef(self, coef):
         cf = np.zeros((self.n, COEF_STRIDE), np.float64)
         for s, c in enumerate(coef):
             c = np.asarray(c, np.float64)
             cf[s, :c.size] = c
-        cf = np.ascontiguousarray(cf)
+        return np.ascontiguousarray(cf)
+
+    def step(self, coef, dt, mode=BATCH_GRAPH):
+        cf = self._coef(coef)
         _ok(_batch_step(self.handle, cf.ctypes.data_as(POINTER(c_double)), float(dt), int(mode)),
             "ibm_batch_step")
+
+    @staticmethod
+    def _plan_dict(p):
+        return {"mode": _MODE_NAMES.get(p.mode, p.mode), "streams": p.streams,
+                "rhs_planes": p.rhs_planes, "ms_per_step": p.ms_per_step}
+
+    def tune(self, coef, dt, steps=3, max_entries=64):
+        """Autotune the execution plan (ibm_batch_tune); the states are left
+        as they were.  Returns (best plan, list of tried plans), as dicts."""
+        cf = self._coef(coef)
+        best = IbmBatchPlan()
+        table = (IbmBatchPlan * max_entries)()
+        ntried = c_int32()
+        _ok(_batch_tune(self.handle, cf.ctypes.data_as(POINTER(c_double)), float(dt), int(steps),
+                        ctypes.byref(best), table, max_entries, ctypes.byref(ntried)),
+            "ibm_batch_tune")
+        return self._plan_dict(best), [self._plan_dict(table[k]) for k in range(ntried.value)]
+
+    def set_plan(self, mode="graph", streams=None, rhs_planes=16):
+        m = {"graph": BATCH_GRAPH, "streams": BATCH_STREAMS}[mode]
+        p = IbmBatchPlan(m, int(streams or self.n), int(rhs_planes), 0, 0.0)
+        _ok(_batch_set_plan(self.handle, ctypes.byref(p)), "ibm_batch_set_plan")
+
+    def get_plan(self):
+        p = IbmBatchPlan()
+        _ok(_batch_get_plan(self.handle, ctypes.byref(p)), "ibm_batch_get_plan")
+        return self._plan_dict(p)
 
     def check(self):
         f = c_uint32()

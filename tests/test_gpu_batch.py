@@ -125,3 +125,42 @@ def test_batch_simulation_against_oracle():
         f, p, _, _ = ostep.step(g, f, p, (X, U, b.tris), wl.dt, wl.re, (-wl.dpdx, 0.0, 0.0))
     for c in range(3):
         assert rel(got[c].reshape(f[c].shape), f[c]) < 1e-10, c
+
+
+def test_autotuner_keeps_states_and_results():
+    """ibm_batch_tune leaves every simulation's state as it was, applies the
+    fastest plan it measured, and stepping with any plan (the tuned one, or
+    extreme ones set by hand) gives results bit-identical to serial mode."""
+    from paper_2606_09799_amd import ibm
+    wls = _small_sims()
+    ref = _run_batch(wls, 2, ibm.BATCH_SERIAL)
+    sims = [_device_sim(wl) for wl in wls]
+    before = [_state(d) for d in sims]
+    batch = ibm.Batch(sims)
+    dt = wls[0].dt
+    best, tried = batch.tune([wl.bodies[0].coef(0.0) for wl in wls], dt, steps=2)
+    after = [_state(d) for d in sims]
+    for a, b in zip(before, after):
+        for x, y in zip(a, b):
+            assert np.array_equal(x, y)
+    assert len(tried) >= 5 and best["ms_per_step"] == min(p["ms_per_step"] for p in tried)
+    assert batch.get_plan() == best
+    for k in range(2):
+        batch.step([wl.bodies[0].coef(k * dt) for wl in wls], dt, ibm.BATCH_PLAN)
+    assert batch.check() == 0
+    for a, b in zip(ref, [_state(d) for d in sims]):
+        for x, y in zip(a, b):
+            assert np.array_equal(x, y)
+    batch.close()
+    for plan in ({"mode": "streams", "streams": 1, "rhs_planes": 1},
+                 {"mode": "graph", "streams": 2, "rhs_planes": 5}):
+        sims = [_device_sim(wl) for wl in wls]
+        batch = ibm.Batch(sims)
+        batch.set_plan(**plan)
+        for k in range(2):
+            batch.step([wl.bodies[0].coef(k * dt) for wl in wls], dt, ibm.BATCH_PLAN)
+        assert batch.check() == 0
+        for a, b in zip(ref, [_state(d) for d in sims]):
+            for x, y in zip(a, b):
+                assert np.array_equal(x, y)
+        batch.close()

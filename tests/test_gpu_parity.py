@@ -132,6 +132,27 @@ def test_poisson_parity(name):
     assert abs(np.sum(got * dV)) < 1e-12 * np.sum(np.abs(got) * dV)
 
 
+@pytest.mark.parametrize("shape", [(256, 12, 16), (16, 12, 256), (16, 528, 16)])
+def test_poisson_parity_kernel_paths(shape):
+    """Shapes that select the other kernel paths, compared with the oracle
+    value by value: length-256 x transforms (four-step), length-256 z
+    transforms (four-step), and a wall-normal solve with more than 64
+    separators per mode (block-wide reduction); stretched y."""
+    import workloads
+    nx, ny, nz = shape
+    wl = workloads.Workload("paths", nx, ny, nz, 2 * np.pi, np.pi, workloads.tanh_faces(ny),
+                            1.0, 1.0, 1, 0.0, 0.0, 1, 0.0, [])
+    case = Case(wl)
+    g = case.g
+    rng = np.random.default_rng(11)
+    rhs = rng.standard_normal(g.shape)
+    dV = g.cell_volume()
+    rhs -= np.sum(rhs * dV) / np.sum(dV)
+    phi = torch.empty(g.cells, dtype=torch.float64, device=DEV)
+    case.ibm.poisson_solve(case.ctx, t(rhs), phi)
+    assert rel(n(phi, g.shape), poisson.solve(g, rhs)) < 1e-11
+
+
 def test_poisson_closed_form_eigenmode():
     import workloads
     wl = workloads.Workload("eig", 16, 12, 10, 2 * np.pi, np.pi, workloads.uniform_faces(12),
