@@ -183,11 +183,22 @@ def run_form(args, wl, form, dev):
     if flags:
         print(f"bench.py: device flags {flags} after the {form} run", file=sys.stderr)
         sys.exit(1)
+    # no-slip error (Sec. 4.4) of the final fields against the body at the
+    # final time (untimed: body transform and tagging at t, then the error)
+    tend = (args.warmup + args.steps) * wl.dt
+    for (b, ref, xyz, vel, _) in dbodies:
+        if b.kind == "rigid":
+            ibm.ibm_body_rigid(ctx, ref, b.coef(tend), xyz, vel)
+        else:
+            ibm.ibm_body_deform(ctx, ref, b.coef(tend), xyz, vel)
+    ibm.ibm_tag(ctx, bodies)
+    eps, eps_c = ibm.ibm_noslip_error(ctx, u, v, w)
+    noslip = {"mean": eps, "u": eps_c[0], "v": eps_c[1], "w": eps_c[2], "time": tend}
     if not all(torch.isfinite(x).all().item() for x in (u, v, w, p)):
         print(f"bench.py: non-finite state after the {form} run", file=sys.stderr)
         sys.exit(1)
     ctx.close()
-    return el, prof, dominant, dom, stats
+    return el, prof, dominant, dom, stats, noslip
 
 
 def run_batched(args, dev, nsim):
@@ -297,7 +308,7 @@ def main():
     substeps = 2
     results = {}
     for form in forms:
-        el, prof, dominant, dom, stats = run_form(args, wl, form, dev)
+        el, prof, dominant, dom, stats, noslip = run_form(args, wl, form, dev)
         r = {"value": wl.cells * substeps * args.steps / el, "ms_per_step": el / args.steps * 1e3,
              "kernel_ms_per_step": {k: round(vv[1] / max(1, args.warmup - 1), 4)
                                     for k, vv in prof.items()}}
@@ -317,6 +328,7 @@ def main():
                                "corrections_per_solve": round(corr / max(1, solves), 3),
                                "max_final_divergence": worst,
                                "max_divergence_after_first_correction": first}
+        r["noslip_error"] = noslip
         results[form] = r
     batched = None
     if args.batch_sims > 0:

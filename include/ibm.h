@@ -239,6 +239,34 @@ int ibm_mass_rhs(ibm_ctx* ctx, const double* u, const double* v, const double* w
  * IBM_FLAG_REFINE is raised if the tolerance was not reached. */
 int poisson_solve(ibm_ctx* ctx, const double* rhs, double* phi);
 
+/* No-slip (transpiration) error (paper Sec. 4.4): at every forcing node of
+ * the last ibm_tag (or ibm_step) on this context, the flow velocity
+ * extrapolated to the wall with the forcing interpolator of Eq. new_IB,
+ * (u(x^f) - a u(x^e)) / (1 - a) with the node's wall point, probe x^e and
+ * a = |N|/h as in the forcing (u(x^f) itself when |N| = 0), minus the wall
+ * velocity U(X^f).  eps: host double[4]: the mean of the three components'
+ * values, then for u, v, w the mean of |error| over that component's
+ * forcing nodes (0 without any).  u, v, w: dev f64.  Uses the forcing
+ * buffer of the context (not concurrent with a step on it).  Synchronises. */
+int ibm_noslip_error(ibm_ctx* ctx, const double* u, const double* v, const double* w,
+                     double* eps);
+
+/* Pressure on the boundary cells (paper Sec. 2, after Eq. q_F: the solve does
+ * not define p on C_B; it is rebuilt from the surrounding field with the
+ * strategy of the forcing, as post-processing that never enters the step).
+ * Reading: for each cell of the C_B list of the last ibm_tag (or ibm_step),
+ * the wall point X is the closest point of the cell centre on the forcing
+ * triangles of its six faces (least |N|^2, ties to the lowest triangle id),
+ * the probe x^e = X + h N/|N| with h twice the cell diagonal, and the cell
+ * takes p(x^e) (zero normal gradient at the wall), trilinear on the
+ * cell-centre lattice, constant beyond the first and last centres; a centre
+ * on the surface takes the mean of the probes on both sides.  p: dev f32
+ * (mixed form) or f64, ny*nz*nx.  out: dev f64[out_cap]; out[f] for the
+ * f-th boundary cell in ascending order (ibm_tags_count_host gives the
+ * count); a count above out_cap fills out_cap values and raises
+ * IBM_FLAG_CAPACITY.  Enqueued on the context's stream. */
+int ibm_pressure_cb(ibm_ctx* ctx, const void* p, double* out, int64_t out_cap);
+
 /* Projection and pressure update (paper Eqs. projection, update_pressure):
  * u <- u - alpha_dt G phi on every interior velocity node;
  * p <- p + phi - alpha_dt/(2 Re) L_c phi.  phi, u, v, w: dev f64; p: dev

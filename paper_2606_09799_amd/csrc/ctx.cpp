@@ -118,6 +118,7 @@ struct ibm_ctx {
   double rtol = 0.0;
   double* partial = nullptr;
   double* qf = nullptr;
+  double* diag = nullptr;  // per-component no-slip errors (3)
   uint32_t* flags = nullptr;
 
   // line-solve tables for one beta
@@ -580,6 +581,7 @@ int ibm_create(const ibm_grid* gr, const ibm_opts* o, void* stream, ibm_ctx** ou
   TRY(dalloc(c, &c->rstats, 4));
   TRY(dalloc(c, &c->partial, 5 * 512));  // block partials of the mass sums
   TRY(dalloc(c, &c->qf, 2));              // q_F, or (c0, c1) of the energy shape
+  TRY(dalloc(c, &c->diag, 4));
   TRY(dalloc(c, &c->flags, 1));
   {
     int P, L, r, segs = 0;
@@ -879,6 +881,32 @@ int poisson_solve(ibm_ctx* c, const double* rhs, double* phi) {
   if (!c || !rhs || !phi) FAIL(IBM_EINVAL, "poisson_solve: bad argument");
   launch_poisson(&c->prof, c->stream, c->g, pargs(c), rhs, nullptr, nullptr, nullptr, nullptr,
                  nullptr, nullptr, 1.0, phi);
+  return launch_status();
+}
+
+int ibm_noslip_error(ibm_ctx* c, const double* u, const double* v, const double* w,
+                     double* eps) {
+  if (!c || !u || !v || !w || !eps) FAIL(IBM_EINVAL, "ibm_noslip_error: bad argument");
+  const double* f[3] = {u, v, w};
+  launch_noslip(&c->prof, c->stream, c->g, c->d_bodies, (int)c->bodies.size(), c->tb, f,
+                c->force_vals, c->diag, c->flags);
+  int rc = launch_status();
+  if (rc) return rc;
+  double h[3];
+  HIPCHK(hipMemcpyAsync(h, c->diag, sizeof(h), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  eps[1] = h[0];
+  eps[2] = h[1];
+  eps[3] = h[2];
+  eps[0] = (h[0] + h[1] + h[2]) / 3.0;
+  return IBM_OK;
+}
+
+int ibm_pressure_cb(ibm_ctx* c, const void* p, double* out, int64_t out_cap) {
+  if (!c || !p || (!out && out_cap > 0) || out_cap < 0)
+    FAIL(IBM_EINVAL, "ibm_pressure_cb: bad argument");
+  launch_pressure_cb(&c->prof, c->stream, c->g, c->d_bodies, (int)c->bodies.size(), c->tb, p,
+                     c->fp32, out, out_cap, c->flags);
   return launch_status();
 }
 

@@ -158,6 +158,16 @@ void launch_tag(Prof* pf, hipStream_t s, const GridView& g, const BodyDev* bodie
                 int ntri, TagBuffers& tb, uint32_t* flags);
 
 // force.hip
+// pressure reconstructed on the boundary cells of tb (p: FP32 when fp32),
+// out[f] for the f-th cell of the C_B list (at most out_cap values)
+void launch_pressure_cb(Prof* pf, hipStream_t s, const GridView& g, const BodyDev* bodies,
+                        int nbody, const TagBuffers& tb, const void* p, int fp32, double* out,
+                        int64_t out_cap, uint32_t* flags);
+// no-slip error of the fields at the forcing nodes of tb: per-node errors in
+// vals (3 * cap), per-component means in out[3] (device)
+void launch_noslip(Prof* pf, hipStream_t s, const GridView& g, const BodyDev* bodies, int nbody,
+                   const TagBuffers& tb, const double* const* fields, double* vals, double* out,
+                   uint32_t* flags);
 void launch_force(Prof* pf, hipStream_t s, const GridView& g, const BodyDev* bodies, int nbody,
                   const TagBuffers& tb, double* const* fields, double* vals,
                   uint32_t* flags);

@@ -110,6 +110,9 @@ _batch_get_plan = _sig("ibm_batch_get_plan", c_int32, c_void_p, POINTER(IbmBatch
 _batch_tune = _sig("ibm_batch_tune", c_int32, c_void_p, POINTER(c_double), c_double, c_int32,
                    POINTER(IbmBatchPlan), POINTER(IbmBatchPlan), c_int32, POINTER(c_int32))
 _check = _sig("ibm_check", c_int32, c_void_p, POINTER(c_uint32))
+_noslip = _sig("ibm_noslip_error", c_int32, c_void_p, c_void_p, c_void_p, c_void_p,
+               POINTER(c_double))
+_pressure_cb = _sig("ibm_pressure_cb", c_int32, c_void_p, c_void_p, c_void_p, c_int64)
 _strerror = _sig("ibm_strerror", c_char_p, c_int32)
 _profile = _sig("ibm_profile", c_int32, c_void_p, c_int32, c_char_p)
 _profile_read = _sig("ibm_profile_read", c_int32, c_void_p, c_char_p, c_int32,
@@ -120,7 +123,8 @@ EXPORTS = ("ibm_create", "ibm_destroy", "ibm_set_stream", "ibm_body_rigid", "ibm
            "ibm_mass_rhs", "poisson_solve", "ibm_project", "ibm_step", "ibm_refine_stats",
            "ibm_check", "ibm_strerror", "ibm_profile", "ibm_profile_read",
            "ibm_batch_create", "ibm_batch_destroy", "ibm_batch_context", "ibm_batch_step",
-           "ibm_batch_check", "ibm_batch_set_plan", "ibm_batch_get_plan", "ibm_batch_tune")
+           "ibm_batch_check", "ibm_batch_set_plan", "ibm_batch_get_plan", "ibm_batch_tune",
+           "ibm_noslip_error", "ibm_pressure_cb")
 COEF_STRIDE = 18
 BATCH_SERIAL, BATCH_STREAMS, BATCH_GRAPH, BATCH_PLAN = 0, 1, 2, 3
 _MODE_NAMES = {BATCH_STREAMS: "streams", BATCH_GRAPH: "graph"}
@@ -304,6 +308,25 @@ def ibm_viscous(ctx, p, h_prev, h_out, gamma, rho, dt, u, v, w):
                  _ptr3(h_out, ctx, "h_out"), float(gamma), float(rho), float(dt),
                  _dev(u, torch.float64, ctx.cells, "u"), _dev(v, torch.float64, ctx.vfaces, "v"),
                  _dev(w, torch.float64, ctx.cells, "w")), "ibm_viscous")
+
+
+def ibm_noslip_error(ctx, u, v, w):
+    """No-slip error at the forcing nodes of the last tagging: (mean of the
+    three components, [u, v, w] means of |error|)."""
+    eps = (c_double * 4)()
+    _ok(_noslip(ctx.handle, _dev(u, torch.float64, ctx.cells, "u"),
+                _dev(v, torch.float64, ctx.vfaces, "v"), _dev(w, torch.float64, ctx.cells, "w"),
+                eps), "ibm_noslip_error")
+    return eps[0], [eps[1], eps[2], eps[3]]
+
+
+def ibm_pressure_cb(ctx, p, out):
+    """Pressure reconstructed on the boundary cells of the last tagging into
+    out (f64 device tensor, one value per boundary cell, ascending)."""
+    if out.dtype != torch.float64 or not out.is_cuda or not out.is_contiguous():
+        raise ValueError("out: contiguous float64 device tensor")
+    _ok(_pressure_cb(ctx.handle, _dev(p, ctx.pdtype, ctx.cells, "p"), c_void_p(out.data_ptr()),
+                     out.numel()), "ibm_pressure_cb")
 
 
 def ibm_mass_rhs(ctx, u, v, w, alpha_dt, rhs, qf=None, p=None):

@@ -11,7 +11,7 @@ import pytest
 import torch
 
 from gpu_harness import Case, DEV, n, rel, t
-from oracle import forcing, poisson, predictor, projection, step as ostep
+from oracle import diagnostics, forcing, poisson, predictor, projection, step as ostep
 from oracle import operators as op
 
 pytestmark = pytest.mark.gpu
@@ -93,6 +93,49 @@ def test_viscous_parity(name, stage):
     for c in range(3):
         assert rel(n(d[c], f[c].shape) - f[c], ref[c] - f[c]) < 1e-12, c
         assert rel(n(ho[c], f[c].shape), Href[c]) < 1e-12, c
+
+
+@pytest.mark.parametrize("name,time", [("tiny", 0.011), ("tiny_plate", 0.137), ("c1", 0.0)])
+def test_noslip_error_parity(name, time):
+    """No-slip error of Sec. 4.4 at the forcing nodes of the current tags,
+    per component and averaged, against the oracle's diagnostics on the same
+    fields (random, so that every node contributes)."""
+    case = Case(name)
+    bodies, (X, U, T) = case.bodies_at(time)
+    case.ibm.ibm_tag(case.ctx, bodies)
+    tags = ostep.compute_tags(case.g, X, T)
+    f = case.random_fields(7)
+    eps, per = case.ibm.ibm_noslip_error(case.ctx, *[t(a) for a in f])
+    eps_ref, per_ref = diagnostics.noslip_error(case.g, f, tags, X, U, T)
+    assert eps_ref > 0
+    assert abs(eps - eps_ref) <= 1e-12 * eps_ref
+    for a, b in zip(per, per_ref):
+        assert abs(a - b) <= 1e-12 * max(b, 1e-300)
+    assert case.ibm.ibm_check(case.ctx) == 0
+
+
+@pytest.mark.parametrize("name,time,precision", [("c1", 0.0, "fp64"), ("c1", 0.009, "fp64"),
+                                                  ("tiny", 0.011, "fp64"), ("c1", 0.0, "mixed")])
+def test_pressure_cb_parity(name, time, precision):
+    """Pressure rebuilt on the boundary cells (Sec. 2, after Eq. q_F; the
+    reading of the oracle) against the oracle on the same random p; the
+    mixed form reads an FP32 p.  An output shorter than the boundary-cell
+    count raises the capacity flag."""
+    case = Case(name, precision=precision)
+    bodies, (X, U, T) = case.bodies_at(time)
+    case.ibm.ibm_tag(case.ctx, bodies)
+    tags = ostep.compute_tags(case.g, X, T)
+    assert len(tags.cb) > 0
+    p = np.random.default_rng(9).standard_normal(case.g.shape)
+    pd = t(p).to(torch.float32 if precision == "mixed" else torch.float64)
+    ref = diagnostics.pressure_cb(case.g, n(pd.double(), case.g.shape), tags, X, T)
+    out = torch.full((len(tags.cb),), float("nan"), dtype=torch.float64, device=DEV)
+    case.ibm.ibm_pressure_cb(case.ctx, pd, out)
+    assert np.max(np.abs(n(out) - ref)) <= 1e-12 * np.max(np.abs(p))
+    assert case.ibm.ibm_check(case.ctx) == 0
+    short = torch.zeros(len(tags.cb) - 1, dtype=torch.float64, device=DEV)
+    case.ibm.ibm_pressure_cb(case.ctx, pd, short)
+    assert case.ibm.ibm_check(case.ctx) & case.ibm.FLAG_CAPACITY
 
 
 @pytest.mark.parametrize("name", SMALL)
