@@ -55,16 +55,22 @@ def algorithmic_bytes(name, nx, ny, nz, form="fp64"):
     return table.get(name)
 
 
-# kernel name in the library's event profile -> kernel name in the rocprofv3
-# summaries (template arguments of the storage type per form)
-def counter_name(kernel, form):
+# kernel name in the library's event profile -> prefixes of its kernel symbols
+# in the rocprofv3 summaries (every variant the launcher may pick: flags of
+# the RHS march, the line-solve and transform kernels by line length)
+def counter_names(kernel, form):
     T = "double" if form == "fp64" else "float"
     C = "float2" if form == "mixed_refined" else "double2"
-    return {"rhs": f"k_rhs<{T}>", "adi_x": f"k_line<{T}>", "adi_z": f"k_line<{T}>",
-            "adi_y": f"k_line<{T}>", "pois_fftx_fwd": f"k_fftx_fwd<{C}>",
-            "pois_fftz_fwd": f"k_fftz<{C}, false>", "pois_fftz_inv": f"k_fftz<{C}, true>",
-            "pois_tri_y": f"k_tri_y<{C}>", "pois_fftx_inv": f"k_fftx_inv<{C}>",
-            "project": f"k_project<{T}>"}.get(kernel)
+    return {"rhs": [f"k_rhs<{T},"],
+            "adi_x": [f"k_line_xw<{T}>", f"k_line<{T}, 0,"],
+            "adi_z": [f"k_line_col<{T}, 1>", f"k_line<{T}, 1,"],
+            "adi_y": [f"k_line_col<{T}, 2>", f"k_line<{T}, 2,"],
+            "pois_fftx_fwd": [f"k_fftx256_fwd<{C}", f"k_fftx_fwd<{C}"],
+            "pois_fftz_fwd": [f"k_fftz256<{C}, false>", f"k_fftz<{C}, false>"],
+            "pois_fftz_inv": [f"k_fftz256<{C}, true>", f"k_fftz<{C}, true>"],
+            "pois_tri_y": [f"k_tri_y<{C}", f"k_tri_y_blk<{C}"],
+            "pois_fftx_inv": [f"k_fftx256_inv<{C}", f"k_fftx_inv<{C}"],
+            "project": [f"k_project<{T}>"]}.get(kernel, [])
 
 
 def csrc_sha():
@@ -80,20 +86,23 @@ def csrc_sha():
 
 def measured_traffic(kernel, workload, form="fp64"):
     """HBM bytes per launch of `kernel` from the committed rocprofv3 PMC
-    summary (FETCH_SIZE and WRITE_SIZE, scaled by a plain copy), or None when
-    no summary exists for this workload and form or the kernel sources
-    changed since."""
+    summary (FETCH_SIZE and WRITE_SIZE, scaled by a plain copy; averaged over
+    the kernel's symbol variants by dispatch count), or None when no summary
+    exists for this workload and form or the kernel sources changed since."""
     path = os.path.join(ROOT, "profiles", f"{workload}_{form}_traffic.json")
-    name = counter_name(kernel, form)
-    if kernel.startswith("adi_") or not name or not os.path.exists(path):
-        # the three line-solve directions share one kernel symbol
+    names = counter_names(kernel, form)
+    if not names or not os.path.exists(path):
         return None
     with open(path) as f:
         t = json.load(f)
-    if t.get("csrc_sha") != csrc_sha() or name not in t["kernels"]:
+    if t.get("csrc_sha") != csrc_sha():
         return None
-    k = t["kernels"][name]
-    return int(k["read_bytes"] + k["write_bytes"])
+    tot, n = 0.0, 0
+    for sym, k in t["kernels"].items():
+        if any(sym.startswith(nm) for nm in names):
+            tot += (k["read_bytes"] + k["write_bytes"]) * k["dispatches"]
+            n += k["dispatches"]
+    return int(tot / n) if n else None
 
 
 def cpu_baseline(wl):
@@ -322,6 +331,16 @@ def main():
                              "frac": round(ach / HBM_PEAK_GBS, 4),
                              "traffic": measured_traffic(dominant, wl.name, form),
                              "avg_launch_us": round(avg_s * 1e6, 2), "algorithmic_bytes": ab}
+        # whole step: algorithmic bytes of every dense kernel per step over the
+        # step time
+        nprof = max(1, args.warmup - 1)
+        path_bytes = sum((algorithmic_bytes(k, wl.nx, wl.ny, wl.nz, form) or 0) * vv[0] / nprof
+                         for k, vv in prof.items())
+        path_gbs = path_bytes / (el / args.steps) / 1e9
+        r["path_roofline"] = {"bound": "hbm", "achieved": round(path_gbs, 1),
+                              "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                              "frac": round(path_gbs / HBM_PEAK_GBS, 4),
+                              "algorithmic_bytes_per_step": int(path_bytes)}
         if stats is not None:
             solves, corr, worst, first = stats
             r["refinement"] = {"poisson_solves": solves, "corrections": corr,

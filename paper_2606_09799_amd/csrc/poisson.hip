@@ -533,7 +533,7 @@ __global__ __launch_bounds__(32 * X16_SC) void k_fftx256_fwd(PoisK<C> K) {
 }
 
 template <typename C>
-__global__ __launch_bounds__(16 * X16_SC) void k_fftx256_inv(PoisK<C> K) {
+__global__ __launch_bounds__(32 * X16_SC) void k_fftx256_inv(PoisK<C> K) {
   using R = typename RealOf<C>::T;
   if (gated(K)) return;
   __shared__ C T[X16_SC * X16_SS];
@@ -549,38 +549,42 @@ __global__ __launch_bounds__(16 * X16_SC) void k_fftx256_inv(PoisK<C> K) {
     T[(r >> 1) * X16_SS + (r & 1) * nxh + p] = (r < nr) ? src[r * K.ldx + p] : mkc<C>((R)0, (R)0);
   }
   __syncthreads();
-  const int t = threadIdx.x & 15, sc = threadIdx.x >> 4;
-  C* tile = T + sc * X16_SS;
-  // bin k of a half spectrum over the Hermitian extension (bins 0 and n/2 real)
-  auto bin = [&](int h, int k) -> C {
-    C c = (k < nxh) ? tile[h * nxh + k] : tile[h * nxh + (256 - k)];
-    if (k >= nxh) c.y = -c.y;
-    if (k == 0 || k == 128) c.y = (R)0;
-    return c;
-  };
-  C x[16];
+  // the transforms: the first 16 X16_SC threads, 16 lanes per sequence (the
+  // other wavefronts only help with the memory passes)
+  if (threadIdx.x < 16 * X16_SC) {
+    const int t = threadIdx.x & 15, sc = threadIdx.x >> 4;
+    C* tile = T + sc * X16_SS;
+    // bin k of a half spectrum over the Hermitian extension (bins 0 and n/2 real)
+    auto bin = [&](int h, int k) -> C {
+      C c = (k < nxh) ? tile[h * nxh + k] : tile[h * nxh + (256 - k)];
+      if (k >= nxh) c.y = -c.y;
+      if (k == 0 || k == 128) c.y = (R)0;
+      return c;
+    };
+    C x[16];
 #pragma unroll
-  for (int n2 = 0; n2 < 16; ++n2) {
-    const int k = t + 16 * n2;
-    const C A = bin(0, k), B = bin(1, k);
-    x[n2] = mkc<C>(A.x - B.y, A.y + B.x);  // Z = A + iB
+    for (int n2 = 0; n2 < 16; ++n2) {
+      const int k = t + 16 * n2;
+      const C A = bin(0, k), B = bin(1, k);
+      x[n2] = mkc<C>(A.x - B.y, A.y + B.x);  // Z = A + iB
+    }
+    dft16<C, true>(x);
+    wave_sync();
+#pragma unroll
+    for (int k2 = 0; k2 < 16; ++k2) {
+      C w = K.px.tw[t * k2];
+      w.y = -w.y;
+      tile[k2 * 17 + t] = (k2 && t) ? cmul(x[pos16(k2)], w) : x[pos16(k2)];
+    }
+    wave_sync();
+#pragma unroll
+    for (int n1 = 0; n1 < 16; ++n1) x[n1] = tile[t * 17 + n1];
+    dft16<C, true>(x);
+    wave_sync();
+    // z[i], i = t + 16 k1: real part row 2 sc, imaginary part row 2 sc + 1
+#pragma unroll
+    for (int k1 = 0; k1 < 16; ++k1) tile[t + 16 * k1] = x[pos16(k1)];
   }
-  dft16<C, true>(x);
-  wave_sync();
-#pragma unroll
-  for (int k2 = 0; k2 < 16; ++k2) {
-    C w = K.px.tw[t * k2];
-    w.y = -w.y;
-    tile[k2 * 17 + t] = (k2 && t) ? cmul(x[pos16(k2)], w) : x[pos16(k2)];
-  }
-  wave_sync();
-#pragma unroll
-  for (int n1 = 0; n1 < 16; ++n1) x[n1] = tile[t * 17 + n1];
-  dft16<C, true>(x);
-  wave_sync();
-  // z[i], i = t + 16 k1: real part row 2 sc, imaginary part row 2 sc + 1
-#pragma unroll
-  for (int k1 = 0; k1 < 16; ++k1) tile[t + 16 * k1] = x[pos16(k1)];
   __syncthreads();
   // 2. the block's phi rows, coalesced
   const R* tr = reinterpret_cast<const R*>(T);
@@ -1215,7 +1219,7 @@ static void run_passes(Prof* pf, hipStream_t s, const GridView& g, PoisK<C> K) {
   else
     IBM_LAUNCH(pf, "pois_fftz_inv", s, (k_fftz<C, true><<<zgrid, 256, zsh, s>>>(K)));
   if (x256)
-    IBM_LAUNCH(pf, "pois_fftx_inv", s, (k_fftx256_inv<C><<<xb, 16 * X16_SC, 0, s>>>(K)));
+    IBM_LAUNCH(pf, "pois_fftx_inv", s, (k_fftx256_inv<C><<<xb, 32 * X16_SC, 0, s>>>(K)));
   else
     IBM_LAUNCH(pf, "pois_fftx_inv", s, (k_fftx_inv<C><<<xblocks, 256, xsh, s>>>(K)));
 }
