@@ -342,7 +342,7 @@ int ibm_batch_check(ibm_batch* b, uint32_t* flags);
  *               dealt round-robin to the groups; a group runs its
  *               simulations one after the other, groups run concurrently
  *   rhs_planes: wall-normal planes per block of the predictor right-hand
- *               side, 1..16 (fewer planes, more blocks on small grids)
+ *               side, 1..64 (fewer planes, more blocks on small grids)
  *   ms_per_step: filled by ibm_batch_tune (the measured time), else ignored
  * A new batch starts with {IBM_BATCH_GRAPH, nsim, 16}. */
 typedef struct {
@@ -358,7 +358,7 @@ int ibm_batch_set_plan(ibm_batch* b, const ibm_batch_plan* plan);
 int ibm_batch_get_plan(ibm_batch* b, ibm_batch_plan* plan);
 /* Autotuner: times candidate plans on this batch's own simulations (a
  * coordinate search over streams in {1, 2, 4, ..., nsim}, then rhs_planes in
- * {16, 8, 4}, then graph vs eager streams), `steps` timed steps each after
+ * {16, 48, 8, 4}, then graph vs eager streams), `steps` timed steps each after
  * one untimed step, all with the body coefficients `coef` and step dt.  The
  * simulations' states (u, v, w, p and, for AB2, h) are saved first and
  * restored after every trial, so tuning leaves them as they were; the

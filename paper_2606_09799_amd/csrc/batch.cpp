@@ -285,7 +285,7 @@ int ibm_batch_step(ibm_batch* b, const double* coef, double dt, int32_t mode) {
 
 static bool plan_ok(const ibm_batch* b, const ibm_batch_plan& p) {
   return (p.mode == IBM_BATCH_STREAMS || p.mode == IBM_BATCH_GRAPH) && p.streams >= 1 &&
-         p.streams <= b->n && p.rhs_planes >= 1 && p.rhs_planes <= 16;
+         p.streams <= b->n && p.rhs_planes >= 1 && p.rhs_planes <= 64;
 }
 
 int ibm_batch_set_plan(ibm_batch* b, const ibm_batch_plan* plan) {
@@ -395,7 +395,7 @@ int ibm_batch_tune(ibm_batch* b, const double* coef, double dt, int32_t steps,
     }
     if (rc) break;
     // 2. planes per block of the RHS march
-    for (int pl : {8, 4}) {
+    for (int pl : {48, 8, 4}) {
       double ms = 0.0;
       ibm_batch_plan p = bp;
       p.rhs_planes = pl;

@@ -183,7 +183,7 @@ struct RhsArgs {
   const uint32_t* mask[3];
   double gamma, rho, alpha, dt, re, fx;
   int fp32;
-  int planes;  // wall-normal planes per block of the march (1..16; 0: 16)
+  int planes;  // wall-normal planes per block of the march (1..64; 0: the default)
 };
 void launch_rhs(Prof* pf, hipStream_t s, const GridView& g, const RhsArgs& a);
 

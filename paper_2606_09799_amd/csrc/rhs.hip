@@ -32,7 +32,11 @@ namespace ibm {
 constexpr int RTX = 64, RTZ = 8;           // tile (threads per block: RTX x RTZ)
 constexpr int RHX = RTX + 2, RHZ = RTZ + 2; // tile with halo
 constexpr int RPL = RHX * RHZ;              // values per plane in LDS
-constexpr int RJC = 16;                     // planes per block (at most; a launch may take fewer)
+constexpr int RJC = 64;  // planes per block at most
+// planes per block unless the caller chooses: on 256x192x256 one round of
+// blocks on the chip, and 2 halo planes re-read per 48 (measured best of
+// 8 .. 48)
+constexpr int RJC_DEF = 48;
 // ring slots: u 0..2, v 3..5, w 6..8, p 9..10
 constexpr int RSLOTS = 11;
 // metric coefficients of a chunk after the ring: idy[j0-1 .. j0+JC-1],
@@ -355,7 +359,7 @@ static void run_rhs(Prof* pf, hipStream_t s, const GridView& g, const RhsArgs& a
   K.dt = a.dt;
   K.re = a.re;
   K.fx = a.fx;
-  K.jc = (a.planes >= 1 && a.planes <= RJC) ? a.planes : RJC;
+  K.jc = (a.planes >= 1 && a.planes <= RJC) ? a.planes : RJC_DEF;
   const int64_t blocks = (int64_t)((g.nx + RTX - 1) / RTX) * ((g.nz + RTZ - 1) / RTZ) *
                          ((g.ny + K.jc - 1) / K.jc);
   const size_t shm = sizeof(double) * (RSLOTS * RPL + RCOEF);
