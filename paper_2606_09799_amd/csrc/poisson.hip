@@ -604,7 +604,8 @@ __global__ __launch_bounds__(32 * X16_SC) void k_fftx256_inv(PoisK<C> K) {
 
 // Wall-normal solves, one per Fourier mode, partitioned like the line solves
 // of the predictor: each mode's ny rows are cut into P balanced segments of
-// at most YL rows, one thread per segment, the values in registers.  Each
+// at most YL rows (6: ny = 192 gives exactly 32 separators, a power of two),
+// one thread per segment, the values in registers.  Each
 // thread eliminates its interior rows so that they become affine functions
 // of the two separators around the segment (its own last row and the
 // previous segment's), the P separator rows form a tridiagonal system solved
@@ -615,7 +616,7 @@ __global__ __launch_bounds__(32 * X16_SC) void k_fftx256_inv(PoisK<C> K) {
 // Every spectral value is read once and written once; the arithmetic is FP64
 // whatever the storage precision.  The systems are diagonally dominant
 // (|b| >= |a| + |c|), so the elimination needs no pivoting.
-constexpr int YL = 8;
+constexpr int YL = 6;
 
 template <typename C>
 __global__ __launch_bounds__(1024) void k_tri_y(PoisK<C> K) {
@@ -1172,9 +1173,11 @@ static void run_passes(Prof* pf, hipStream_t s, const GridView& g, PoisK<C> K) {
   line_plan(g.ny, false, YL, &K.yP, &K.yL, &K.yr);
   K.yPP = 1;
   while (K.yPP < K.yP) K.yPP <<= 1;
-  // separators of one mode in one wavefront when they fit; else block-wide
+  // separators of one mode in one wavefront when they fit; else block-wide.
+  // Wavefront form: 8 modes per block once a mode has 32 or more separators
+  // (blocks of 256-512 threads: more blocks per CU; 128-byte row pieces)
   const bool ywave = K.yPP <= 64;
-  K.ytl = 1024 / (ywave ? K.yPP : K.yP);
+  K.ytl = ywave ? (K.yPP >= 32 ? 8 : 1024 / K.yPP) : 1024 / K.yP;
   if (K.ytl > 16) K.ytl = 16;
   if (K.ytl < 1) K.ytl = 1;
   const int64_t nrows = (int64_t)g.ny * g.nz;
