@@ -549,7 +549,8 @@ int ibm_create(const ibm_grid* gr, const ibm_opts* o, void* stream, ibm_ctx** ou
   TRY(dalloc(c, &tb.cb_mask, tb.nwords_cb));
   TRY(dalloc(c, &tb.cb, tb.cap));
   TRY(dalloc(c, &tb.count, 4));
-  TRY(dalloc(c, &tb.block_sums, maxw / 1024 + 2));
+  tb.bsum_stride = maxw / 1024 + 2;  // >= blocks of 1024 mask words of any list
+  TRY(dalloc(c, &tb.block_sums, 3 * tb.bsum_stride));
   TRY(dalloc(c, &c->force_vals, 3 * tb.cap));
   TRY(dalloc(c, &c->dslots, (int64_t)ibm_ctx::NSLOT * ibm_ctx::MAXB));
   if (hipHostMalloc((void**)&c->hslots, sizeof(BodyDev) * ibm_ctx::NSLOT * ibm_ctx::MAXB) != hipSuccess) {

@@ -149,7 +149,8 @@ struct TagBuffers {
   int64_t* cb;
   uint32_t* cb_mask;
   int64_t* count;        // [4]
-  int64_t* block_sums;   // scan scratch
+  int64_t* block_sums;   // scan scratch: 3 regions of bsum_stride values
+  int64_t bsum_stride;
   int64_t cap;
   int64_t nwords[3];     // mask words per component
   int64_t nwords_cb;

@@ -114,22 +114,44 @@ __device__ int64_t block_excl_scan(int64_t v, int64_t* sh, int64_t* total) {
   return incl - v;
 }
 
-__global__ __launch_bounds__(CT) void k_count(const uint32_t* __restrict__ mask, int64_t nwords,
-                                              int64_t* __restrict__ bsum) {
+// Up to three lists compacted by one launch of each kernel: list y of the
+// grid (blockIdx.y) with its own mask, block sums, outputs and count.
+struct CompactSet {
+  const uint32_t* mask[3];
+  int64_t nwords[3];
+  int64_t nb[3];        // blocks of CWB words
+  int64_t* bsum[3];
+  int64_t* idx[3];
+  int32_t* tri[3];      // forcing triangles (NULL for C_B)
+  u64* best_d[3];       // reset to the empty key after reading (NULL for C_B)
+  int32_t* best_t[3];
+  int64_t* count[3];
+  int64_t cap;
+  uint32_t* flags;
+};
+
+__global__ __launch_bounds__(CT) void k_count(CompactSet S) {
   __shared__ int64_t sh[CT];
+  const int l = blockIdx.y;
+  if ((int64_t)blockIdx.x >= S.nb[l]) return;  // block-uniform
+  const uint32_t* mask = S.mask[l];
+  const int64_t nwords = S.nwords[l];
   const int64_t base = (int64_t)blockIdx.x * CWB + (int64_t)threadIdx.x * CWT;
   int64_t c = 0;
   for (int q = 0; q < CWT; ++q)
     if (base + q < nwords) c += __popc(mask[base + q]);
   int64_t tot;
   block_excl_scan(c, sh, &tot);
-  if (threadIdx.x == 0) bsum[blockIdx.x] = tot;
+  if (threadIdx.x == 0) S.bsum[l][blockIdx.x] = tot;
 }
 
-// exclusive scan of nb block sums in place (one block); total -> *count
-__global__ __launch_bounds__(1024) void k_scan(int64_t* __restrict__ bsum, int64_t nb,
-                                               int64_t* __restrict__ count) {
+// exclusive scan of a list's nb block sums in place (one block per list);
+// total -> its count
+__global__ __launch_bounds__(1024) void k_scan(CompactSet S) {
   __shared__ int64_t sh[1024];
+  const int l = blockIdx.x;
+  int64_t* bsum = S.bsum[l];
+  const int64_t nb = S.nb[l];
   const int t = threadIdx.x;
   const int64_t chunk = (nb + 1023) / 1024;
   const int64_t lo = t * chunk, hi = (lo + chunk < nb) ? lo + chunk : nb;
@@ -149,15 +171,20 @@ __global__ __launch_bounds__(1024) void k_scan(int64_t* __restrict__ bsum, int64
     bsum[i] = run;
     run += v;
   }
-  if (t == 1023) *count = sh[1023];
+  if (t == 1023) *S.count[l] = sh[1023];
 }
 
-__global__ __launch_bounds__(CT) void k_emit(const uint32_t* __restrict__ mask, int64_t nwords,
-                                             const int64_t* __restrict__ boff,
-                                             int64_t* __restrict__ idx, int32_t* __restrict__ tri,
-                                             u64* __restrict__ best_d, int32_t* __restrict__ best_t,
-                                             int64_t cap, uint32_t* flags) {
+__global__ __launch_bounds__(CT) void k_emit(CompactSet S) {
   __shared__ int64_t sh[CT];
+  const int l = blockIdx.y;
+  if ((int64_t)blockIdx.x >= S.nb[l]) return;  // block-uniform
+  const uint32_t* mask = S.mask[l];
+  const int64_t nwords = S.nwords[l];
+  int64_t* idx = S.idx[l];
+  int32_t* tri = S.tri[l];
+  u64* best_d = S.best_d[l];
+  int32_t* best_t = S.best_t[l];
+  const int64_t cap = S.cap;
   const int64_t base = (int64_t)blockIdx.x * CWB + (int64_t)threadIdx.x * CWT;
   uint32_t w[CWT];
   int64_t c = 0;
@@ -166,7 +193,7 @@ __global__ __launch_bounds__(CT) void k_emit(const uint32_t* __restrict__ mask, 
     c += __popc(w[q]);
   }
   int64_t tot;
-  int64_t pos = boff[blockIdx.x] + block_excl_scan(c, sh, &tot);
+  int64_t pos = S.bsum[l][blockIdx.x] + block_excl_scan(c, sh, &tot);
   bool over = false;
   for (int q = 0; q < CWT; ++q) {
     uint32_t m = w[q];
@@ -187,7 +214,18 @@ __global__ __launch_bounds__(CT) void k_emit(const uint32_t* __restrict__ mask, 
       ++pos;
     }
   }
-  if (over) atomicOr(flags, FLAG_CAPACITY);
+  if (over) atomicOr(S.flags, FLAG_CAPACITY);
+}
+
+// zero up to four bitmaps in one launch (array blockIdx.y)
+__global__ __launch_bounds__(256) void k_zero_masks(uint32_t* m0, int64_t n0, uint32_t* m1,
+                                                    int64_t n1, uint32_t* m2, int64_t n2,
+                                                    uint32_t* m3, int64_t n3) {
+  uint32_t* m = blockIdx.y == 0 ? m0 : (blockIdx.y == 1 ? m1 : (blockIdx.y == 2 ? m2 : m3));
+  const int64_t n = blockIdx.y == 0 ? n0 : (blockIdx.y == 1 ? n1 : (blockIdx.y == 2 ? n2 : n3));
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    m[i] = 0u;
 }
 
 // C_B: cells all six of whose faces carry forcing nodes (checked from the
@@ -214,23 +252,32 @@ __global__ void k_cells(GridView g, const int64_t* __restrict__ idx_u,
   }
 }
 
-static void compact(Prof* pf, hipStream_t s, const uint32_t* mask, int64_t nwords,
-                    int64_t* bsum, int64_t* count_slot, int64_t* idx, int32_t* tri, u64* best_d,
-                    int32_t* best_t, int64_t cap, uint32_t* flags) {
-  const int64_t nb = (nwords + CWB - 1) / CWB;
-  IBM_LAUNCH(pf, "tag_count", s, k_count<<<(int)nb, CT, 0, s>>>(mask, nwords, bsum));
-  IBM_LAUNCH(pf, "tag_scan", s, k_scan<<<1, 1024, 0, s>>>(bsum, nb, count_slot));
-  IBM_LAUNCH(pf, "tag_emit", s,
-             k_emit<<<(int)nb, CT, 0, s>>>(mask, nwords, bsum, idx, tri, best_d, best_t, cap,
-                                           flags));
+// compact nl lists (the three forcing lists, or C_B alone): count, scan and
+// emit, one launch each
+static void compact(Prof* pf, hipStream_t s, CompactSet S, int nl) {
+  int64_t nbmax = 1;
+  for (int l = 0; l < nl; ++l) {
+    S.nb[l] = (S.nwords[l] + CWB - 1) / CWB;
+    if (S.nb[l] > nbmax) nbmax = S.nb[l];
+  }
+  const dim3 grid((unsigned)nbmax, (unsigned)nl);
+  IBM_LAUNCH(pf, "tag_count", s, k_count<<<grid, CT, 0, s>>>(S));
+  IBM_LAUNCH(pf, "tag_scan", s, k_scan<<<nl, 1024, 0, s>>>(S));
+  IBM_LAUNCH(pf, "tag_emit", s, k_emit<<<grid, CT, 0, s>>>(S));
 }
 
 void launch_tag(Prof* pf, hipStream_t s, const GridView& g, const BodyDev* bodies, int nbody,
                 int ntri, TagBuffers& tb, uint32_t* flags) {
-  for (int c = 0; c < 3; ++c) {
-    launch_fill_u32(pf, s, tb.mask[c], tb.nwords[c], 0u);
+  {
+    int64_t nmax = tb.nwords_cb;
+    for (int c = 0; c < 3; ++c) nmax = tb.nwords[c] > nmax ? tb.nwords[c] : nmax;
+    int64_t blocks = (nmax + 255) / 256;
+    if (blocks > 4096) blocks = 4096;
+    IBM_LAUNCH(pf, "fill_u32", s,
+               (k_zero_masks<<<dim3((unsigned)blocks, 4), 256, 0, s>>>(
+                   tb.mask[0], tb.nwords[0], tb.mask[1], tb.nwords[1], tb.mask[2], tb.nwords[2],
+                   tb.cb_mask, tb.nwords_cb)));
   }
-  launch_fill_u32(pf, s, tb.cb_mask, tb.nwords_cb, 0u);
   if (ntri > 0) {
     TagK a;
     a.g = g;
@@ -249,15 +296,34 @@ void launch_tag(Prof* pf, hipStream_t s, const GridView& g, const BodyDev* bodie
     a.pass = 1;
     IBM_LAUNCH(pf, "tag_pairs", s, k_tag_pairs<<<grid, 64, 0, s>>>(a));
   }
-  // the block-sum scratch is reused; kernels on one stream run in order
-  for (int c = 0; c < 3; ++c)
-    compact(pf, s, tb.mask[c], tb.nwords[c], tb.block_sums, tb.count + c, tb.idx[c], tb.tri[c],
-            tb.best_d[c], tb.best_t[c], tb.cap, flags);
+  // the three forcing lists in one pass; each list has its own block sums
+  // (tb.bsum_stride values apart)
+  CompactSet S{};
+  S.cap = tb.cap;
+  S.flags = flags;
+  for (int c = 0; c < 3; ++c) {
+    S.mask[c] = tb.mask[c];
+    S.nwords[c] = tb.nwords[c];
+    S.bsum[c] = tb.block_sums + c * tb.bsum_stride;
+    S.idx[c] = tb.idx[c];
+    S.tri[c] = tb.tri[c];
+    S.best_d[c] = tb.best_d[c];
+    S.best_t[c] = tb.best_t[c];
+    S.count[c] = tb.count + c;
+  }
+  compact(pf, s, S, 3);
   IBM_LAUNCH(pf, "tag_cells", s,
              k_cells<<<1024, 256, 0, s>>>(g, tb.idx[0], tb.count, tb.cap, tb.mask[0], tb.mask[1],
                                           tb.mask[2], tb.cb_mask));
-  compact(pf, s, tb.cb_mask, tb.nwords_cb, tb.block_sums, tb.count + 3, tb.cb, nullptr, nullptr,
-          nullptr, tb.cap, flags);
+  CompactSet B{};
+  B.cap = tb.cap;
+  B.flags = flags;
+  B.mask[0] = tb.cb_mask;
+  B.nwords[0] = tb.nwords_cb;
+  B.bsum[0] = tb.block_sums;
+  B.idx[0] = tb.cb;
+  B.count[0] = tb.count + 3;
+  compact(pf, s, B, 1);
 }
 
 }  // namespace ibm
