@@ -222,12 +222,13 @@ __device__ __forceinline__ double lap_c(const GridView& g, const double* __restr
   return (gx1 - gx0) * g.idx + (gz1 - gz0) * g.idz + (fn - fs) * g.idy[j];
 }
 
-// Right-hand side of the solve at cell i of x-row rr (= j nz + k), by source
-// mode; the residual modes also accumulate max|r| and phi dV, and the FP64
-// copy is kept when asked.  q, q1: q_F, or (c0, c1) of the energy shape.
+// Right-hand side of the solve at cell i of x-row rr = j nz + k (the caller
+// supplies j and k), by source mode; the residual modes also accumulate
+// max|r| and phi dV, and the FP64 copy is kept when asked.  q, q1: q_F, or
+// (c0, c1) of the energy shape.
 template <typename C>
-__device__ __forceinline__ double fftx_source(const PoisK<C>& K, int64_t rr, int i, double q,
-                                              double q1, double& rmax, double& vsum) {
+__device__ __forceinline__ double fftx_source(const PoisK<C>& K, int64_t rr, int j, int k, int i,
+                                              double q, double q1, double& rmax, double& vsum) {
   const GridView& g = K.g;
   const int nx = g.nx;
   const int64_t plane = (int64_t)g.nz * nx;
@@ -239,7 +240,6 @@ __device__ __forceinline__ double fftx_source(const PoisK<C>& K, int64_t rr, int
     if (K.cb_mask && test_bit(K.cb_mask, cell)) {
       val = 0.0;
     } else {
-      const int j = (int)(rr / g.nz), k = (int)(rr % g.nz);
       const int ip = (i + 1 == nx) ? 0 : i + 1;
       const int kp = (k + 1 == g.nz) ? 0 : k + 1;
       const double u0 = K.u[cell], u1 = K.u[cell - i + ip];
@@ -258,7 +258,6 @@ __device__ __forceinline__ double fftx_source(const PoisK<C>& K, int64_t rr, int
       val = (D - qq) * K.inv_adt;
     }
   } else {
-    const int j = (int)(rr / g.nz), k = (int)(rr % g.nz);
     val = K.rhs[cell] - lap_c(g, K.phi_in, cell, i, j, k);
     rmax = fmax(rmax, fabs(val));
     vsum += K.phi_in[cell] * g.dy[j];
@@ -315,7 +314,9 @@ __global__ __launch_bounds__(256) void k_fftx_fwd(PoisK<C> K) {
   double rmax = 0.0, vsum = 0.0;
   for (int e = threadIdx.x; e < nr * nx; e += blockDim.x) {
     const int r = e / nx, i = e % nx;
-    const double val = fftx_source(K, row0 + r, i, q, q1, rmax, vsum);
+    const int64_t rr = row0 + r;
+    const int jr = (int)(rr / g.nz), kr = (int)(rr - (int64_t)jr * g.nz);
+    const double val = fftx_source(K, rr, jr, kr, i, q, q1, rmax, vsum);
     if (K.mode != SRC_CHECK) sr[2 * ((r >> 1) * nx + i) + (r & 1)] = (R)val;
   }
   if (resid) {
@@ -468,10 +469,18 @@ __global__ __launch_bounds__(32 * X16_SC) void k_fftx256_fwd(PoisK<C> K) {
   // 1. the block's rows, coalesced: row r is the real (r even) or imaginary
   //    (r odd) part of sequence r/2, value i at T[(r/2) X16_SS + i]
   R* tr = reinterpret_cast<R*>(T);
+  // (j, k) of the block's first row; the rows of a block follow in k (32-bit
+  // arithmetic: ny nz < 2^31)
+  const int j00 = (int)(row0 / g.nz), k00 = (int)(row0 - (int64_t)j00 * g.nz);
 #pragma unroll 4
   for (int e = threadIdx.x; e < 2 * X16_SC * 256; e += blockDim.x) {
     const int r = e >> 8, i = e & 255;
-    const double val = (r < nr) ? fftx_source(K, row0 + r, i, q, q1, rmax, vsum) : 0.0;
+    int kr = k00 + r, jr = j00;
+    while (kr >= g.nz) {
+      kr -= g.nz;
+      ++jr;
+    }
+    const double val = (r < nr) ? fftx_source(K, row0 + r, jr, kr, i, q, q1, rmax, vsum) : 0.0;
     tr[2 * ((r >> 1) * X16_SS + i) + (r & 1)] = (R)val;
   }
   if (K.mode >= SRC_RESIDUAL) {
