@@ -438,8 +438,9 @@ __global__ __launch_bounds__(256) void k_line_xw(LineK<T> K) {
   const int64_t g0 = ((int64_t)K.j0 * K.nz + r0) * n;  // first element of the group
   // stage the group's rows: value c of row r at rows[r*RS + (c/LMAX)*SEGS + c%LMAX]
   const int nv = nrow * n / VN;
+  const int lgn = 31 - __clz(n);  // n = P LMAX is a power of two
   for (int q = lane; q < nv; q += 64) {
-    const int c0 = q * VN, r = c0 / n, c = c0 % n;
+    const int c0 = q * VN, r = c0 >> lgn, c = c0 & (n - 1);
     *reinterpret_cast<V*>(rows + r * RS + (c / LMAX) * SEGS + c % LMAX) =
         *reinterpret_cast<const V*>(K.d + g0 + c0);
   }
@@ -568,7 +569,7 @@ __global__ __launch_bounds__(256) void k_line_xw(LineK<T> K) {
   }
   wave_sync();
   for (int q = lane; q < nv; q += 64) {
-    const int c0_ = q * VN, r = c0_ / n, c = c0_ % n;
+    const int c0_ = q * VN, r = c0_ >> lgn, c = c0_ & (n - 1);
     *reinterpret_cast<V*>(K.d + g0 + c0_) =
         *reinterpret_cast<const V*>(rows + r * RS + (c / LMAX) * SEGS + c % LMAX);
   }
