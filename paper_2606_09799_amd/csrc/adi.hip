@@ -403,9 +403,32 @@ __global__ __launch_bounds__(MODE == 0 ? 256 : 1024) void k_line(LineK<T> K) {
   }
 }
 
+// 16 bytes of T as a native vector (kept in registers where an array of them
+// lives across a loop)
 template <typename T> struct Vec16;
-template <> struct Vec16<double> { using type = double2; };
-template <> struct Vec16<float> { using type = float4; };
+template <> struct Vec16<double> { using type = double __attribute__((ext_vector_type(2))); };
+template <> struct Vec16<float> { using type = float __attribute__((ext_vector_type(4))); };
+
+// a group's rows and this lane's mask word for the x sweep below (a segment
+// starts at a multiple of 16: its bits lie in one word)
+template <typename T, int VPL>
+__device__ __forceinline__ void xw_fetch(const LineK<T>& K, typename Vec16<T>::type (&pf)[VPL],
+                                         uint32_t& pmw, int64_t gg, int RW, int64_t nl,
+                                         int64_t e0, int lane, int rr, int s) {
+  using V = typename Vec16<T>::type;
+  constexpr int VN = 16 / sizeof(T);
+  const int n = K.n;
+  const int64_t g0 = e0 + gg * RW * n;
+  const int64_t nv = (nl - gg * RW) * n / VN;  // vectors left in the sweep
+#pragma unroll
+  for (int v = 0; v < VPL; ++v) {
+    // (past the end: a repeat of the last vector, so that the loop keeps a
+    // fixed trip count and the array stays in registers)
+    const int q = lane + 64 * v < nv ? lane + 64 * v : (int)nv - 1;
+    pf[v] = *reinterpret_cast<const V*>(K.d + g0 + (int64_t)q * VN);
+  }
+  if (gg * RW + rr < nl) pmw = K.mask[(g0 + (int64_t)rr * n + s * LMAX) >> 5];
+}
 
 // x sweep with one wavefront per group of 64/P rows, for lines of n = P*LMAX
 // rows with P a power of two (4 <= P <= 64): lane rr*P + s holds segment s of
@@ -415,163 +438,190 @@ template <> struct Vec16<float> { using type = float4; };
 // solved by cyclic reduction over cross-lane reads, so the wavefronts of a
 // block never wait for each other.  Equal segments of a constant-coefficient
 // line share one set of elimination tables (segment 0's).
+//
+// A group always holds 64 LMAX values (64/P rows of P LMAX).  The grid holds
+// only as many wavefronts as are resident at once; each takes the groups
+// g, g + W, g + 2W, ... (W wavefronts in all) and loads the next group's rows
+// and mask words into registers before it solves the current one, so that
+// the chip's loads stay in flight through the elimination and the stores
+// instead of arriving in one wave of requests per round of blocks.
 template <typename T>
-__global__ __launch_bounds__(256) void k_line_xw(LineK<T> K) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
+void k_line_xw(LineK<T> K) {
   using V = typename Vec16<T>::type;
   constexpr int VN = 16 / sizeof(T);  // values per 16 bytes
   constexpr int SEGS = LMAX + VN;     // padded segment
+  constexpr int GV = 64 * LMAX / VN;  // 16-byte vectors per group
+  constexpr int VPL = GV / 64;        // ... per lane
   extern __shared__ __align__(16) unsigned char ldsraw[];
   T* lds = reinterpret_cast<T*>(ldsraw);
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int P = K.P, n = K.n;
-  const int RW = 64 / P;          // rows per wavefront
+  const int RW = 64 / P;             // rows per group
   const int RS = (n / LMAX) * SEGS;  // padded row
-  T* tab = lds;                   // [LINE_NTAB][LMAX]
+  T* tab = lds;                      // [LINE_NTAB][LMAX]
   T* rows = lds + LINE_NTAB * LMAX + (size_t)wv * RW * RS;
   for (int q = threadIdx.x; q < LINE_NTAB * LMAX; q += blockDim.x)
     tab[q] = K.tab[(size_t)(q / LMAX) * P * LMAX + q % LMAX];
   __syncthreads();
   const int64_t nl = (int64_t)K.nj * K.nz;  // rows of the sweep
-  const int64_t r0 = ((int64_t)blockIdx.x * (blockDim.x >> 6) + wv) * RW;
-  if (r0 >= nl) return;  // the whole wavefront is past the end
-  const int nrow = (int)((r0 + RW <= nl) ? RW : nl - r0);
-  const int64_t g0 = ((int64_t)K.j0 * K.nz + r0) * n;  // first element of the group
-  // stage the group's rows: value c of row r at rows[r*RS + (c/LMAX)*SEGS + c%LMAX]
-  const int nv = nrow * n / VN;
+  const int64_t ng = (nl + RW - 1) / RW;    // groups
+  const int64_t gstep = (int64_t)gridDim.x * (blockDim.x >> 6);
+  int64_t g = (int64_t)blockIdx.x * (blockDim.x >> 6) + wv;
+  if (g >= ng) return;  // the whole wavefront is past the end
   const int lgn = 31 - __clz(n);  // n = P LMAX is a power of two
-  for (int q = lane; q < nv; q += 64) {
-    const int c0 = q * VN, r = c0 >> lgn, c = c0 & (n - 1);
-    *reinterpret_cast<V*>(rows + r * RS + (c / LMAX) * SEGS + c % LMAX) =
-        *reinterpret_cast<const V*>(K.d + g0 + c0);
-  }
-  wave_sync();
   const int rr = lane / P, s = lane % P;
-  const bool valid = rr < nrow;
   const int grp = rr * P;  // first lane of this row
   T* seg = rows + rr * RS + s * SEGS;
   const int m = LMAX - 1;  // interior rows; row m is the separator
-  const int64_t base = g0 + (int64_t)rr * n + s * LMAX;  // first element of the segment
-  T dd[LMAX];
-  T dz = 0, az = 0, bz = 1, cz = 0;
-  T a0 = 0, c0 = 0, ahl = 0, chl = 0, dhl = 0;
-  uint32_t mbits = 0;
-  if (valid) {
-#pragma unroll
-    for (int e = 0; e < LMAX; ++e) dd[e] = seg[e];
-    // a segment starts at a multiple of 16: its bits lie in one mask word
-    mbits = (K.mask[base >> 5] >> (uint32_t)(base & 31)) & ((1u << LMAX) - 1u);
-#pragma unroll
-    for (int e = 0; e < LMAX; ++e)
-      if ((mbits >> e) & 1u) dd[e] = T(0);
-    dz = dd[m];
-    if ((mbits & ((1u << m) - 1u)) == 0u) {
-      T dt = 0;
-#pragma unroll
-      for (int e = 0; e < m; ++e) {
-        dt = (dd[e] - tab[4 * LMAX + e] * dt) * tab[e];
-        dd[e] = dt;
-      }
-      T dh = dd[m - 1];
-      dhl = dh;
-#pragma unroll
-      for (int e = m - 2; e >= 0; --e) {
-        dh = dd[e] - tab[LMAX + e] * dh;
-        dd[e] = dh;
-      }
-      a0 = tab[2 * LMAX];
-      c0 = tab[3 * LMAX];
-      ahl = tab[2 * LMAX + m - 1];
-      chl = tab[3 * LMAX + m - 1];
-    } else {
-      // identity rows inside the segment: coefficients through the scratch
-      T at = 0, ct = 0, dt = 0;
-#pragma unroll
-      for (int e = 0; e < m; ++e) {
-        T a = K.a, b = K.b, c = K.c;
-        if ((mbits >> e) & 1u) {
-          a = 0;
-          b = 1;
-          c = 0;
-        }
-        const T inv = T(1) / (b - a * ct);
-        at = (e == 0) ? a * inv : -a * at * inv;
-        ct = c * inv;
-        dt = (dd[e] - a * dt) * inv;
-        dd[e] = dt;
-        K.sa[base + e] = at;
-        K.sc[base + e] = ct;
-      }
-      T ah = 0, ch = 0, dh = 0;
-#pragma unroll
-      for (int e = m - 1; e >= 0; --e) {
-        const T at_e = K.sa[base + e], ct_e = K.sc[base + e];
-        if (e == m - 1) {
-          ah = at_e;
-          ch = ct_e;
-          dh = dd[e];
-          ahl = ah;
-          chl = ch;
-          dhl = dh;
-        } else {
-          dh = dd[e] - ct_e * dh;
-          ah = at_e - ct_e * ah;
-          ch = -ct_e * ch;
-        }
-        dd[e] = dh;
-        K.sa[base + e] = ah;
-        K.sc[base + e] = ch;
-      }
-      a0 = ah;
-      c0 = ch;
-    }
-    az = K.a;
-    bz = K.b;
-    cz = K.c;
-    if ((mbits >> m) & 1u) {
-      az = 0;
-      bz = 1;
-      cz = 0;
-    }
-  }
-  // separator row of this segment (every lane takes part in the cross-lane
-  // reads; lanes past the group's rows carry identity rows)
   const int nxt = grp + ((s + 1) & (P - 1)), prv = grp + ((s - 1) & (P - 1));
-  const T a0n = lane_read(a0, nxt), c0n = lane_read(c0, nxt);
-  const T d0n = lane_read(valid ? dd[0] : T(0), nxt);
-  T ra = -az * ahl;
-  T rb = bz - az * chl - cz * a0n;
-  T rg = -cz * c0n;
-  T rd = dz - az * dhl - cz * d0n;
-  // cyclic reduction: a cyclic system of 2^k rows closes with couplings onto
-  // the row itself
-  for (int st = 1; st < P; st <<= 1) {
-    const int im = grp + ((s - st) & (P - 1)), ip = grp + ((s + st) & (P - 1));
-    const T am = lane_read(ra, im), bm = lane_read(rb, im), gm = lane_read(rg, im),
-            dm = lane_read(rd, im);
-    const T ap = lane_read(ra, ip), bp = lane_read(rb, ip), gp = lane_read(rg, ip),
-            dp = lane_read(rd, ip);
-    const T k1 = ra / bm, k2 = rg / bp;
-    const T na = -am * k1, ng = -gp * k2;
-    rb = rb - gm * k1 - ap * k2;
-    rd = rd - dm * k1 - dp * k2;
-    ra = na;
-    rg = ng;
-  }
-  const T zr = rd / (ra + rb + rg);
-  const T zl = lane_read(zr, prv);
-  if (valid) {
-    const bool fast = (mbits & ((1u << m) - 1u)) == 0u;
+  const int64_t e0 = (int64_t)K.j0 * K.nz * n;  // first element of the sweep
+  // a group's rows and this lane's mask word (a segment starts at a multiple
+  // of 16: its bits lie in one word); vectors past the sweep are not loaded
+  V pf[VPL];
+  uint32_t pmw = 0;
+  xw_fetch<T, VPL>(K, pf, pmw, g, RW, nl, e0, lane, rr, s);
+  for (; g < ng; g += gstep) {
+    const int64_t r0 = g * RW;
+    const int nrow = (int)((r0 + RW <= nl) ? RW : nl - r0);
+    const int64_t g0 = e0 + r0 * n;  // first element of the group
+    const int nv = nrow * n / VN;
+    const bool valid = rr < nrow;
+    const int64_t base = g0 + (int64_t)rr * n + s * LMAX;  // first element of the segment
+    // stage the group's rows: value c of row r at rows[r*RS + (c/LMAX)*SEGS + c%LMAX]
 #pragma unroll
-    for (int e = 0; e < m; ++e)
-      seg[e] = fast ? dd[e] - tab[2 * LMAX + e] * zl - tab[3 * LMAX + e] * zr
-                    : dd[e] - K.sa[base + e] * zl - K.sc[base + e] * zr;
-    seg[m] = zr;
-  }
-  wave_sync();
-  for (int q = lane; q < nv; q += 64) {
-    const int c0_ = q * VN, r = c0_ >> lgn, c = c0_ & (n - 1);
-    *reinterpret_cast<V*>(K.d + g0 + c0_) =
-        *reinterpret_cast<const V*>(rows + r * RS + (c / LMAX) * SEGS + c % LMAX);
+    for (int v = 0; v < VPL; ++v) {
+      // rows past the group's end (a ragged last group) take unused values:
+      // they stay inside this wavefront's region
+      const int q = lane + 64 * v;
+      const int c0 = q * VN, r = c0 >> lgn, c = c0 & (n - 1);
+      *reinterpret_cast<V*>(rows + r * RS + (c / LMAX) * SEGS + c % LMAX) = pf[v];
+    }
+    const uint32_t mbits = valid ? (pmw >> (uint32_t)(base & 31)) & ((1u << LMAX) - 1u) : 0u;
+    wave_sync();
+    if (g + gstep < ng) xw_fetch<T, VPL>(K, pf, pmw, g + gstep, RW, nl, e0, lane, rr, s);
+    T dd[LMAX];
+    T dz = 0, az = 0, bz = 1, cz = 0;
+    T a0 = 0, c0 = 0, ahl = 0, chl = 0, dhl = 0;
+    if (valid) {
+#pragma unroll
+      for (int e = 0; e < LMAX; ++e) dd[e] = seg[e];
+#pragma unroll
+      for (int e = 0; e < LMAX; ++e)
+        if ((mbits >> e) & 1u) dd[e] = T(0);
+      dz = dd[m];
+      if ((mbits & ((1u << m) - 1u)) == 0u) {
+        T dt = 0;
+#pragma unroll
+        for (int e = 0; e < m; ++e) {
+          dt = (dd[e] - tab[4 * LMAX + e] * dt) * tab[e];
+          dd[e] = dt;
+        }
+        T dh = dd[m - 1];
+        dhl = dh;
+#pragma unroll
+        for (int e = m - 2; e >= 0; --e) {
+          dh = dd[e] - tab[LMAX + e] * dh;
+          dd[e] = dh;
+        }
+        a0 = tab[2 * LMAX];
+        c0 = tab[3 * LMAX];
+        ahl = tab[2 * LMAX + m - 1];
+        chl = tab[3 * LMAX + m - 1];
+      } else {
+        // identity rows inside the segment: coefficients through the scratch
+        T at = 0, ct = 0, dt = 0;
+#pragma unroll
+        for (int e = 0; e < m; ++e) {
+          T a = K.a, b = K.b, c = K.c;
+          if ((mbits >> e) & 1u) {
+            a = 0;
+            b = 1;
+            c = 0;
+          }
+          const T inv = T(1) / (b - a * ct);
+          at = (e == 0) ? a * inv : -a * at * inv;
+          ct = c * inv;
+          dt = (dd[e] - a * dt) * inv;
+          dd[e] = dt;
+          K.sa[base + e] = at;
+          K.sc[base + e] = ct;
+        }
+        T ah = 0, ch = 0, dh = 0;
+#pragma unroll
+        for (int e = m - 1; e >= 0; --e) {
+          const T at_e = K.sa[base + e], ct_e = K.sc[base + e];
+          if (e == m - 1) {
+            ah = at_e;
+            ch = ct_e;
+            dh = dd[e];
+            ahl = ah;
+            chl = ch;
+            dhl = dh;
+          } else {
+            dh = dd[e] - ct_e * dh;
+            ah = at_e - ct_e * ah;
+            ch = -ct_e * ch;
+          }
+          dd[e] = dh;
+          K.sa[base + e] = ah;
+          K.sc[base + e] = ch;
+        }
+        a0 = ah;
+        c0 = ch;
+      }
+      az = K.a;
+      bz = K.b;
+      cz = K.c;
+      if ((mbits >> m) & 1u) {
+        az = 0;
+        bz = 1;
+        cz = 0;
+      }
+    }
+    // separator row of this segment (every lane takes part in the cross-lane
+    // reads; lanes past the group's rows carry identity rows)
+    const T a0n = lane_read(a0, nxt), c0n = lane_read(c0, nxt);
+    const T d0n = lane_read(valid ? dd[0] : T(0), nxt);
+    T ra = -az * ahl;
+    T rb = bz - az * chl - cz * a0n;
+    T rg = -cz * c0n;
+    T rd = dz - az * dhl - cz * d0n;
+    // cyclic reduction: a cyclic system of 2^k rows closes with couplings onto
+    // the row itself
+    for (int st = 1; st < P; st <<= 1) {
+      const int im = grp + ((s - st) & (P - 1)), ip = grp + ((s + st) & (P - 1));
+      const T am = lane_read(ra, im), bm = lane_read(rb, im), gm = lane_read(rg, im),
+              dm = lane_read(rd, im);
+      const T ap = lane_read(ra, ip), bp = lane_read(rb, ip), gp = lane_read(rg, ip),
+              dp = lane_read(rd, ip);
+      const T k1 = ra / bm, k2 = rg / bp;
+      const T na = -am * k1, ng_ = -gp * k2;
+      rb = rb - gm * k1 - ap * k2;
+      rd = rd - dm * k1 - dp * k2;
+      ra = na;
+      rg = ng_;
+    }
+    const T zr = rd / (ra + rb + rg);
+    const T zl = lane_read(zr, prv);
+    if (valid) {
+      const bool fast = (mbits & ((1u << m) - 1u)) == 0u;
+#pragma unroll
+      for (int e = 0; e < m; ++e)
+        seg[e] = fast ? dd[e] - tab[2 * LMAX + e] * zl - tab[3 * LMAX + e] * zr
+                      : dd[e] - K.sa[base + e] * zl - K.sc[base + e] * zr;
+      seg[m] = zr;
+    }
+    wave_sync();
+#pragma unroll
+    for (int v = 0; v < VPL; ++v) {
+      // past the group's end: the last vector again (the same value)
+      const int q = lane + 64 * v < nv ? lane + 64 * v : nv - 1;
+      const int c0_ = q * VN, r = c0_ >> lgn, c = c0_ & (n - 1);
+      *reinterpret_cast<V*>(K.d + g0 + c0_) =
+          *reinterpret_cast<const V*>(rows + r * RS + (c / LMAX) * SEGS + c % LMAX);
+    }
+    wave_sync();  // the rows are read out before the next group is staged
   }
 }
 
@@ -867,12 +917,24 @@ static void launch_line(Prof* pf, hipStream_t s, LineK<T> K, const char* name) {
       IBM_LAUNCH(pf, name, s, (k_line<T, M, false><<<grid, threads, shm, s>>>(K)));  \
   } while (0)
   if (K.mode == 0 && fixed && (K.P & (K.P - 1)) == 0 && K.P >= 4 && K.P <= 64) {
-    // one wavefront per group of 64/P rows, four wavefronts per block
+    // one wavefront per group of 64/P rows, four wavefronts per block, as
+    // many blocks as are resident at once (each wavefront loops over groups)
     const int64_t rows = (int64_t)K.nj * K.nz;
     const int64_t waves = (rows + 64 / K.P - 1) / (64 / K.P);
-    const size_t xshm = sizeof(T) * (LINE_NTAB * LMAX +
-                                     4 * (64 / K.P) * (size_t)(K.n / LMAX) * (LMAX + 16 / sizeof(T)));
-    IBM_LAUNCH(pf, name, s, (k_line_xw<T><<<(unsigned)((waves + 3) / 4), 256, xshm, s>>>(K)));
+    const size_t xshm = sizeof(T) * (LINE_NTAB * LMAX + 4 * 64 * (size_t)(LMAX + 16 / sizeof(T)));
+    static int resident = 0;  // per element type: the shared memory size is fixed
+    if (resident == 0) {
+      int dev = 0, cus = 0, per = 0;
+      if (hipGetDevice(&dev) != hipSuccess ||
+          hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+          hipOccupancyMaxActiveBlocksPerMultiprocessor(&per, k_line_xw<T>, 256, xshm) != hipSuccess ||
+          cus < 1 || per < 1)
+        cus = 256, per = 1;
+      resident = cus * per;
+    }
+    int64_t blocks = (waves + 3) / 4;
+    if (blocks > resident) blocks = resident;
+    IBM_LAUNCH(pf, name, s, (k_line_xw<T><<<(unsigned)blocks, 256, xshm, s>>>(K)));
   } else if (K.mode == 0) {
     IBM_LINE(0);
   } else if (K.r == 0 && K.L == LMAX && K.nx % 16 == 0 && K.P <= 64 &&
