@@ -451,6 +451,56 @@ __global__ __launch_bounds__(16 * Z16_TC) void k_fftz256(PoisK<C> K) {
 // block's rows and of its results only wavefront syncs are needed.
 constexpr int X16_SC = 8;
 constexpr int X16_SS = 16 * 17;  // complex values per sequence tile (>= 2 * 129)
+// loads per thread of the inverse pass's staging: 16 spectrum rows of at
+// most X16_LDX_MAX values (the padded stride of 129 modes)
+constexpr int X16_LDX_MAX = 144;
+constexpr int X16_INV_NE = (2 * X16_SC * X16_LDX_MAX + 32 * X16_SC - 1) / (32 * X16_SC);
+
+// Velocity source of the length-256 forward x transform for the block's
+// rows (the SRC_VELOCITY case of fftx_source, same arithmetic): thread i
+// forms value i of every row.  All loads are issued whatever the C_B mask
+// says (a C_B cell's value is then selected to zero) and the uniform options
+// are template arguments, so the loads of successive rows are in flight
+// together instead of each row waiting first for its mask word.  PQ: 0 no
+// energy shape, 1 p in FP64, 2 p in FP32.
+template <typename C, bool CB, int PQ>
+__device__ __forceinline__ void fftx256_stage_vel(const PoisK<C>& K, typename RealOf<C>::T* tr,
+                                                  int64_t row0, int nr, int j00, int k00,
+                                                  double q, double q1, int ss) {
+  using R = typename RealOf<C>::T;
+  const GridView& g = K.g;
+  constexpr int nx = 256;
+  const int i = threadIdx.x, nz = g.nz;
+  const int64_t plane = (int64_t)nz * nx;
+  const int ip = (i + 1) & (nx - 1);
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int rv = r < nr ? r : 0;  // rows past the end: row 0 again, value discarded
+    const unsigned kk = (unsigned)(k00 + rv);
+    const unsigned jq = kk / (unsigned)nz;
+    const int jr = j00 + (int)jq, kr = (int)(kk - jq * (unsigned)nz);
+    const int kp = (kr + 1 == nz) ? 0 : kr + 1;
+    const int64_t rowc = (row0 + rv) * nx;
+    const int64_t cell = rowc + i;
+    const double u0 = K.u[cell], u1 = K.u[rowc + ip];
+    const double v0 = K.v[cell], v1 = K.v[cell + plane];
+    const double w0 = K.w[cell], w1 = K.w[(int64_t)jr * plane + (int64_t)kp * nx + i];
+    const double D = (u1 - u0) * g.idx + (v1 - v0) * g.idy[jr] + (w1 - w0) * g.idz;
+    double qq = q;
+    if (PQ) {
+      const double eu = 0.5 * (u0 * u0 + u1 * u1);
+      const double ev = 0.5 * (v0 * v0 + v1 * v1);
+      const double ew = 0.5 * (w0 * w0 + w1 * w1);
+      const double pc = (PQ == 2) ? (double)static_cast<const float*>(K.pq)[cell]
+                                  : static_cast<const double*>(K.pq)[cell];
+      qq = q + q1 * (pc - 0.5 * ((eu + ev) + ew));
+    }
+    double val = (D - qq) * K.inv_adt;
+    if (CB && ((K.cb_mask[cell >> 5] >> (uint32_t)(cell & 31)) & 1u)) val = 0.0;
+    if (r >= nr) val = 0.0;
+    tr[2 * ((r >> 1) * ss + i) + (r & 1)] = (R)val;
+  }
+}
 
 template <typename C>
 __global__ __launch_bounds__(32 * X16_SC) void k_fftx256_fwd(PoisK<C> K) {
@@ -472,6 +522,19 @@ __global__ __launch_bounds__(32 * X16_SC) void k_fftx256_fwd(PoisK<C> K) {
   // (j, k) of the block's first row; the rows of a block follow in k (32-bit
   // arithmetic: ny nz < 2^31)
   const int j00 = (int)(row0 / g.nz), k00 = (int)(row0 - (int64_t)j00 * g.nz);
+  static_assert(32 * X16_SC == 256 && 2 * X16_SC == 16, "one thread per x index, 16 rows");
+  if (K.mode == SRC_VELOCITY && !K.rhs_keep) {
+    const int pqm = K.pq ? (K.pq32 ? 2 : 1) : 0;
+    if (K.cb_mask) {
+      if (pqm == 0) fftx256_stage_vel<C, true, 0>(K, tr, row0, nr, j00, k00, q, q1, X16_SS);
+      else if (pqm == 1) fftx256_stage_vel<C, true, 1>(K, tr, row0, nr, j00, k00, q, q1, X16_SS);
+      else fftx256_stage_vel<C, true, 2>(K, tr, row0, nr, j00, k00, q, q1, X16_SS);
+    } else {
+      if (pqm == 0) fftx256_stage_vel<C, false, 0>(K, tr, row0, nr, j00, k00, q, q1, X16_SS);
+      else if (pqm == 1) fftx256_stage_vel<C, false, 1>(K, tr, row0, nr, j00, k00, q, q1, X16_SS);
+      else fftx256_stage_vel<C, false, 2>(K, tr, row0, nr, j00, k00, q, q1, X16_SS);
+    }
+  } else
 #pragma unroll 4
   for (int e = threadIdx.x; e < 2 * X16_SC * 256; e += blockDim.x) {
     const int r = e >> 8, i = e & 255;
@@ -551,11 +614,30 @@ __global__ __launch_bounds__(32 * X16_SC) void k_fftx256_inv(PoisK<C> K) {
   const int64_t nrows = (int64_t)g.ny * g.nz;
   const int64_t row0 = (int64_t)blockIdx.x * (2 * X16_SC);
   const int nr = (int)((row0 + 2 * X16_SC <= nrows) ? 2 * X16_SC : nrows - row0);
-  // 1. the block's half spectra, coalesced: row r at T[(r/2) X16_SS + (r%2) nxh]
+  // 1. the block's half spectra, coalesced: row r at T[(r/2) X16_SS + (r%2) nxh].
+  //    The rows are contiguous in memory (padding included): every load is
+  //    issued before the first LDS store, indexes past the end repeat the
+  //    last value and store nothing
   const C* src = K.spec + row0 * K.ldx;
-  for (int e = threadIdx.x; e < 2 * X16_SC * nxh; e += blockDim.x) {
-    const int r = e / nxh, p = e - r * nxh;
-    T[(r >> 1) * X16_SS + (r & 1) * nxh + p] = (r < nr) ? src[r * K.ldx + p] : mkc<C>((R)0, (R)0);
+  {
+    const int ldx = K.ldx, nf = nr * ldx;
+    C vals[X16_INV_NE];
+#pragma unroll
+    for (int it = 0; it < X16_INV_NE; ++it) {
+      const int f0 = threadIdx.x + it * 32 * X16_SC;
+      vals[it] = src[f0 < nf ? f0 : nf - 1];
+    }
+#pragma unroll
+    for (int it = 0; it < X16_INV_NE; ++it) {
+      const int f = threadIdx.x + it * 32 * X16_SC;
+      const int r = f / ldx, p = f - r * ldx;
+      if (f < nf && p < nxh) T[(r >> 1) * X16_SS + (r & 1) * nxh + p] = vals[it];
+    }
+    if (nr < 2 * X16_SC)  // the last block: rows past the end transform zeros
+      for (int e = nr * nxh + threadIdx.x; e < 2 * X16_SC * nxh; e += blockDim.x) {
+        const int r = e / nxh, p = e - r * nxh;
+        T[(r >> 1) * X16_SS + (r & 1) * nxh + p] = mkc<C>((R)0, (R)0);
+      }
   }
   __syncthreads();
   // the transforms: the first 16 X16_SC threads, 16 lanes per sequence (the
@@ -1201,7 +1283,7 @@ static void run_passes(Prof* pf, hipStream_t s, const GridView& g, PoisK<C> K) {
                            : 7 * sizeof(double) * (size_t)K.yP * K.ytl;
   const bool resid = K.mode >= SRC_RESIDUAL;
   // length-256 x transforms: 2 X16_SC rows per block
-  const bool x256 = (g.nx == 256);
+  const bool x256 = (g.nx == 256 && K.ldx <= X16_LDX_MAX);
   const int xb = x256 ? (int)((nrows + 2 * X16_SC - 1) / (2 * X16_SC)) : xblocks;
   if (x256)
     IBM_LAUNCH(pf, resid ? "pois_resid_fftx" : "pois_fftx_fwd", s,
