@@ -652,8 +652,9 @@ __device__ __forceinline__ void col_coef(const LineK<T>& K, int i, T& a, T& b, T
   }
 }
 
-template <typename T, int MODE>
-__global__ __launch_bounds__(1024) void k_line_col(LineK<T> K) {
+template <typename T, int MODE, int SL>
+__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(SL == 12 ? 5 : 1)))
+void k_line_col(LineK<T> K) {
   constexpr int TL = 16;       // lines per block
   constexpr int SP = TL + 1;   // padded stride of the separator arrays
   extern __shared__ __align__(16) unsigned char ldsraw[];
@@ -661,34 +662,34 @@ __global__ __launch_bounds__(1024) void k_line_col(LineK<T> K) {
   const int tid = threadIdx.x;
   const int P = K.P, PP = K.PP;
   const int tP = K.tab1 ? 1 : P;
-  T* tabs = lds;                             // [LINE_NTAB][LMAX][tP]
-  T* Y = tabs + LINE_NTAB * LMAX * tP;       // a0, c0, d0 of each segment; then z
+  T* tabs = lds;                             // [LINE_NTAB][SL][tP]
+  T* Y = tabs + LINE_NTAB * SL * tP;         // a0, c0, d0 of each segment; then z
   T* X = Y + 3 * PP * SP;                    // separator rows ra, rb, rg, rd
-  uint32_t* mws = reinterpret_cast<uint32_t*>(X + 4 * PP * SP);  // [P][16] mask words
-  for (int q = tid; q < LINE_NTAB * tP * LMAX; q += blockDim.x) {
-    const int qe = q / tP, ss = q % tP, qq = qe / LMAX, ee = qe % LMAX;
-    tabs[q] = K.tab[((size_t)qq * P + ss) * LMAX + ee];
+  uint32_t* mws = reinterpret_cast<uint32_t*>(X + 4 * PP * SP);  // [P][SL] mask words
+  for (int q = tid; q < LINE_NTAB * tP * SL; q += blockDim.x) {
+    const int qe = q / tP, ss = q % tP, qq = qe / SL, ee = qe % SL;
+    tabs[q] = K.tab[((size_t)qq * P + ss) * LMAX + ee];  // global tables: LMAX per segment
   }
   const int lb = tid % TL, s = tid / TL;
   const bool active = s < P;
   const int i0 = blockIdx.x * TL;
   const int ts = K.tab1 ? 0 : s;
-#define CTAB(q, e) tabs[((q) * LMAX + (e)) * tP + ts]
+#define CTAB(q, e) tabs[((q) * SL + (e)) * tP + ts]
   // element (row r of line lb): blk[lb + r * es]
   const int64_t es = (MODE == 1) ? K.nx : K.plane;
   const int64_t boff = (MODE == 1) ? (int64_t)(K.j0 + blockIdx.y) * K.plane + i0
                                    : (int64_t)K.j0 * K.plane + (int64_t)blockIdx.y * K.nx + i0;
-  const int lo = s * LMAX;
-  constexpr int m = LMAX - 1;
-  T dd[LMAX];
-  double uu[MODE == 2 ? LMAX : 1];
+  const int lo = s * SL;
+  constexpr int m = SL - 1;
+  T dd[SL];
+  double uu[MODE == 2 ? SL : 1];
   T dz = 0, az = 0, bz = 1, cz = 0;
   T a0 = 0, c0 = 0, ahl = 0, chl = 0, dhl = 0;
   uint32_t mbits = 0;
   // rows are addressed from the wavefront's first row (a uniform base) plus
   // a 32-bit byte offset, one register per row instead of a 64-bit address
   const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int64_t wrow = (int64_t)wv * (64 / TL) * LMAX;  // first row of the wavefront
+  const int64_t wrow = (int64_t)wv * (64 / TL) * SL;  // first row of the wavefront
   const T* dbase = K.d + boff + wrow * es;
   const double* ubase = (MODE == 2) ? K.u + boff + wrow * es : nullptr;
   const uint32_t lrow = (uint32_t)(lo - wrow);           // this segment's first row, from wrow
@@ -697,21 +698,23 @@ __global__ __launch_bounds__(1024) void k_line_col(LineK<T> K) {
   };
   if (active) {
 #pragma unroll
-    for (int e = 0; e < LMAX; ++e)
+    for (int e = 0; e < SL; ++e)
       dd[e] = *reinterpret_cast<const T*>(reinterpret_cast<const char*>(dbase) + boffs(e, sizeof(T)));
-    // lane lb fetches the mask word of row lo + lb (bits i0 .. i0+15 of the
-    // row: one word, nx and i0 being multiples of 16)
-    const int64_t rb = (MODE == 1) ? ((int64_t)(K.j0 + blockIdx.y) * K.nz + lo + lb) * K.nx
-                                   : ((int64_t)(K.j0 + lo + lb) * K.nz + blockIdx.y) * K.nx;
-    const int64_t bit = rb + i0;
-    mws[s * LMAX + lb] = (K.mask[bit >> 5] >> (uint32_t)(bit & 31)) & 0xffffu;
+    // lane lb < SL fetches the mask word of row lo + lb (bits i0 .. i0+15 of
+    // the row: one word, nx and i0 being multiples of 16)
+    if (lb < SL) {
+      const int64_t rb = (MODE == 1) ? ((int64_t)(K.j0 + blockIdx.y) * K.nz + lo + lb) * K.nx
+                                     : ((int64_t)(K.j0 + lo + lb) * K.nz + blockIdx.y) * K.nx;
+      const int64_t bit = rb + i0;
+      mws[s * SL + lb] = (K.mask[bit >> 5] >> (uint32_t)(bit & 31)) & 0xffffu;
+    }
   }
   __syncthreads();  // tables and mask words
   if (active) {
 #pragma unroll
-    for (int e = 0; e < LMAX; ++e) mbits |= ((mws[s * LMAX + e] >> lb) & 1u) << e;
+    for (int e = 0; e < SL; ++e) mbits |= ((mws[s * SL + e] >> lb) & 1u) << e;
 #pragma unroll
-    for (int e = 0; e < LMAX; ++e)
+    for (int e = 0; e < SL; ++e)
       if ((mbits >> e) & 1u) dd[e] = T(0);
     dz = dd[m];
     if ((mbits & ((1u << m) - 1u)) == 0u) {
@@ -850,7 +853,7 @@ __global__ __launch_bounds__(1024) void k_line_col(LineK<T> K) {
     // the velocity the solution is added to: loaded here, where the
     // registers of the separator solve are free, in flight over the barrier
 #pragma unroll
-    for (int e = 0; e < LMAX; ++e)
+    for (int e = 0; e < SL; ++e)
       uu[e] = *reinterpret_cast<const double*>(reinterpret_cast<const char*>(ubase) + boffs(e, 8));
   }
   __syncthreads();  // separator values
@@ -869,7 +872,7 @@ __global__ __launch_bounds__(1024) void k_line_col(LineK<T> K) {
     }
     dd[m] = zr;
 #pragma unroll
-    for (int e = 0; e < LMAX; ++e) {
+    for (int e = 0; e < SL; ++e) {
       if (MODE == 2)
         *reinterpret_cast<double*>(reinterpret_cast<char*>(const_cast<double*>(ubase)) + boffs(e, 8)) =
             uu[MODE == 2 ? e : 0] + (double)dd[e];
@@ -937,22 +940,24 @@ static void launch_line(Prof* pf, hipStream_t s, LineK<T> K, const char* name) {
     IBM_LAUNCH(pf, name, s, (k_line_xw<T><<<(unsigned)blocks, 256, xshm, s>>>(K)));
   } else if (K.mode == 0) {
     IBM_LINE(0);
-  } else if (K.r == 0 && K.L == LMAX && K.nx % 16 == 0 && K.P <= 64 &&
-             (!K.cyc || (K.P & (K.P - 1)) == 0) &&
+  } else if (K.r == 0 && (K.L == LMAX || (K.mode == 2 && K.L == 12)) && K.nx % 16 == 0 &&
+             K.P <= 64 && (!K.cyc || (K.P & (K.P - 1)) == 0) &&
              (K.mode == 1 ? (int64_t)K.nx : K.plane) * 64 * 8 < ((int64_t)1 << 31)) {
     // column sweep: 16 lines per block, the separators solved per wavefront
     int pp = 1;
     while (pp < K.P) pp <<= 1;
     K.PP = pp;
     const int ct = 16 * pp;
-    const size_t cshm = sizeof(T) * (LINE_NTAB * (size_t)(K.tab1 ? 1 : K.P) * LMAX +
+    const size_t cshm = sizeof(T) * (LINE_NTAB * (size_t)(K.tab1 ? 1 : K.P) * K.L +
                                      7 * (size_t)pp * 17) +
-                        sizeof(uint32_t) * (size_t)K.P * LMAX;
+                        sizeof(uint32_t) * (size_t)K.P * K.L;
     const dim3 cgrid(K.nx / 16, K.mode == 1 ? K.nj : K.nz);
     if (K.mode == 1)
-      IBM_LAUNCH(pf, name, s, (k_line_col<T, 1><<<cgrid, ct, cshm, s>>>(K)));
+      IBM_LAUNCH(pf, name, s, (k_line_col<T, 1, LMAX><<<cgrid, ct, cshm, s>>>(K)));
+    else if (K.L == 12)
+      IBM_LAUNCH(pf, name, s, (k_line_col<T, 2, 12><<<cgrid, ct, cshm, s>>>(K)));
     else
-      IBM_LAUNCH(pf, name, s, (k_line_col<T, 2><<<cgrid, ct, cshm, s>>>(K)));
+      IBM_LAUNCH(pf, name, s, (k_line_col<T, 2, LMAX><<<cgrid, ct, cshm, s>>>(K)));
   }
   else if (K.mode == 1)
     IBM_LAUNCH(pf, name, s, (k_line<T, 1, false><<<grid, threads, shm, s>>>(K)));
@@ -1017,7 +1022,7 @@ static void adi_wall(Prof* pf, hipStream_t s, const GridView& g, void* d, double
   K.u = u;
   K.n = t.n;
   K.cyc = 0;
-  line_plan(K.n, false, &K.P, &K.L, &K.r);
+  line_plan(K.n, false, wall_seg_len(K.n), &K.P, &K.L, &K.r);
   K.A = static_cast<const T*>(f ? (const void*)t.a32 : (const void*)t.a);
   K.B = static_cast<const T*>(f ? (const void*)t.b32 : (const void*)t.b);
   K.C = static_cast<const T*>(f ? (const void*)t.c32 : (const void*)t.c);

@@ -280,10 +280,10 @@ static int build_tables(ibm_ctx* c, double beta) {
   // [0] 1/pivot, [1] c~ (forward), [2] a^ and [3] c^ (responses of every
   // interior row to the left and right separators), [4] the row's
   // sub-diagonal
-  auto segtab = [&](int n, bool cyc, const double* A, const double* B, const double* C,
+  auto segtab = [&](int n, bool cyc, int lmax, const double* A, const double* B, const double* C,
                     std::vector<double>& out) {
     int P, L, r;
-    line_plan(n, cyc, &P, &L, &r);
+    line_plan(n, cyc, lmax, &P, &L, &r);
     std::vector<double> t(LINE_NTAB * (size_t)P * LINE_LMAX, 0.0);
     for (int s = 0; s < P; ++s) {
       const int lo = s * L + std::min(s, r);
@@ -318,7 +318,7 @@ static int build_tables(ibm_ctx* c, double beta) {
   };
   auto constseg = [&](int n, const CyclicTab& t, std::vector<double>& out) {
     std::vector<double> A(n, t.a), B(n, t.b), C(n, t.c);
-    segtab(n, true, A.data(), B.data(), C.data(), out);
+    segtab(n, true, LINE_LMAX, A.data(), B.data(), C.data(), out);
   };
   std::vector<double> hx, hz, hy0, hy1, sx, sz, sy0, sy1;
   cyclic(nx, c->g.dx, &c->ctx_x, hx);
@@ -330,7 +330,7 @@ static int build_tables(ibm_ctx* c, double beta) {
   for (int q = 0; q < 2; ++q) {
     const int n = c->yt[q].n;
     const std::vector<double>& hy = q ? hy1 : hy0;
-    segtab(n, false, hy.data(), hy.data() + n, hy.data() + 2 * n, q ? sy1 : sy0);
+    segtab(n, false, wall_seg_len(n), hy.data(), hy.data() + n, hy.data() + 2 * n, q ? sy1 : sy0);
   }
   for (auto* v : {&hx, &hz, &hy0, &hy1, &sx, &sz, &sy0, &sy1}) h.insert(h.end(), v->begin(), v->end());
   if ((int64_t)h.size() > c->tabcap) {
@@ -590,7 +590,7 @@ int ibm_create(const ibm_grid* gr, const ibm_opts* o, void* stream, ibm_ctx** ou
     segs += P;
     line_plan(nz, true, &P, &L, &r);
     segs += P;
-    line_plan(ny, false, &P, &L, &r);
+    line_plan(ny, false, wall_seg_len(ny), &P, &L, &r);
     segs += 2 * P;
     c->tabcap = 4 * (int64_t)(nx + nz) + 10 * (int64_t)ny + LINE_NTAB * (int64_t)segs * LINE_LMAX;
     TRY(dalloc(c, &c->tabmem, c->tabcap));

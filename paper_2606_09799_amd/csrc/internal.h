@@ -90,6 +90,17 @@ inline void line_plan(int n, bool cyc, int lmax, int* P, int* L, int* r) {
 inline void line_plan(int n, bool cyc, int* P, int* L, int* r) {
   line_plan(n, cyc, LINE_LMAX, P, L, r);
 }
+// Segment length of the wall-normal lines: 12 rows where that cuts a line of
+// n rows into a power of two of segments (4 to 64: the separator reduction
+// then has no idle lanes, and the per-thread arrays are shorter), else
+// LINE_LMAX.  The tables and the launch both take their plan from here.
+inline int wall_seg_len(int n) {
+  if (n % 12 == 0) {
+    const int p = n / 12;
+    if (p >= 4 && p <= 64 && (p & (p - 1)) == 0) return 12;
+  }
+  return LINE_LMAX;
+}
 
 // Row stride (complex values) of the half spectrum [y][z][mode]: nx/2+1
 // modes padded to a multiple of 128 bytes, so that the z transforms' tiles of
