@@ -21,7 +21,7 @@
 // Precision T: double, or float in the mixed form (right-hand sides,
 // tables, scratch and arithmetic in FP32; the y sweep adds its FP32 solution
 // to the FP64 velocity).
-#include "geom.h"
+#include "lanes.h"
 
 namespace ibm {
 

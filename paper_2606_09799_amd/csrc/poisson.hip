@@ -23,7 +23,7 @@
 // taken on the device (every pass of a refinement returns at once when the
 // residual that opened it is below the tolerance), so the whole sequence is
 // enqueued without any host synchronisation.
-#include "geom.h"
+#include "lanes.h"
 
 namespace ibm {
 

@@ -5,7 +5,7 @@
 // neighbouring rows of phi are reused from the same L2 (xcd_tile).  The
 // velocity update is FP64 in both forms; p is stored in T (float in the
 // mixed form) and updated in FP64 arithmetic.
-#include "geom.h"
+#include "lanes.h"
 
 namespace ibm {
 

@@ -25,7 +25,7 @@
 // stencil arithmetic is FP64 in both forms: the velocity is FP64, and
 // rounding it to FP32 before differencing would amplify its rounding error by
 // 1/spacing; only the results are stored in T.
-#include "geom.h"
+#include "lanes.h"
 
 namespace ibm {
 
