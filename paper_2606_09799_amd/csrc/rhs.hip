@@ -30,8 +30,7 @@
 namespace ibm {
 
 constexpr int RTX = 64, RTZ = 8;           // tile (threads per block: RTX x RTZ)
-constexpr int RHX = RTX + 2, RHZ = RTZ + 2; // tile with halo
-constexpr int RPL = RHX * RHZ;              // values per plane in LDS
+constexpr int RHZ = RTZ + 2;                // tile rows with the z halo
 constexpr int RJC = 64;  // planes per block at most
 // planes per block unless the caller chooses: on 256x192x256 one round of
 // blocks on the chip, and 2 halo planes re-read per 48 (measured best of
@@ -57,51 +56,89 @@ struct RhsK {
   int jc;  // planes per block, 1..RJC
 };
 
-// elements of one halo plane per thread (RPL values over RTX*RTZ threads)
-constexpr int RPT = (RPL + RTX * RTZ - 1) / (RTX * RTZ);
+// Layout of one halo plane in LDS.  Ragged tiles: rows of RTX + 2 values
+// (x from i0-1), fetched one value per load.  Whole tiles (nx a multiple of
+// RTX): rows of RTX + 4 values (x from i0-2), fetched as aligned pairs, one
+// 16-byte load (or 8 for an FP32 pressure) and one 16-byte LDS store per
+// pair, which halves the address work of the halo traffic.
+template <bool FULL>
+struct Halo {
+  static constexpr int W = FULL ? 2 : 1;            // values per load
+  static constexpr int HX = RTX + (FULL ? 4 : 2);   // values per row
+  static constexpr int XO = FULL ? 2 : 1;           // the tile's first column in a row
+  static constexpr int PL = HX * RHZ;               // values per plane
+  static constexpr int NI = PL / W;                 // loads per plane
+  static constexpr int N = (NI + RTX * RTZ - 1) / (RTX * RTZ);  // loads per thread
+};
+constexpr int RPL_MAX = Halo<true>::PL;  // LDS slot size of either layout
 
-// Offsets within a plane of this thread's halo elements e = tid + q*threads
-// of the tile (i0, k0), with the periodic wrap (i >= -1 and k >= -1; grids
-// narrower than the tile wrap more than once); 0 past the tile (read, never
-// stored: the loads stay unconditional).  The same for every plane, so
-// computed once per block.
-__device__ __forceinline__ void halo_offsets(int (&off)[RPT], const GridView& g, int i0, int k0) {
+template <typename S, int W> struct PairOf { using type = S; };
+template <> struct PairOf<double, 2> { using type = double2; };
+template <> struct PairOf<float, 2> { using type = float2; };
+
+// Offsets within a plane of this thread's loads e = tid + q*threads of the
+// tile (i0, k0), with the periodic wrap (grids narrower than a ragged tile
+// wrap more than once; a whole tile's pairs start at even x and never
+// straddle the wrap); 0 past the tile (read, never stored: the loads stay
+// unconditional).  The same for every plane, so computed once per block.
+template <bool FULL>
+__device__ __forceinline__ void halo_offsets(int (&off)[Halo<FULL>::N], const GridView& g, int i0,
+                                             int k0) {
+  using H = Halo<FULL>;
 #pragma unroll
-  for (int q = 0; q < RPT; ++q) {
+  for (int q = 0; q < H::N; ++q) {
     const int e = threadIdx.x + q * RTX * RTZ;
-    const int lz = e / RHX, lx = e % RHX;
-    int i = i0 - 1 + lx, k = k0 - 1 + lz;
+    const int lz = e / (H::HX / H::W), lx = (e % (H::HX / H::W)) * H::W;
+    int i = i0 - H::XO + lx, k = k0 - 1 + lz;
     i = (i < 0) ? i + g.nx : (i >= g.nx ? (i - g.nx) % g.nx : i);
     k = (k < 0) ? k + g.nz : (k >= g.nz ? (k - g.nz) % g.nz : k);
-    off[q] = (e < RPL) ? k * g.nx + i : 0;
+    off[q] = (e < H::NI) ? k * g.nx + i : 0;
   }
 }
 
 // issue the loads of plane j of a field into registers (no wait)
-template <typename S>
-__device__ __forceinline__ void fetch_plane(double (&r)[RPT], const S* __restrict__ f, int j,
-                                            const GridView& g, const int (&off)[RPT]) {
+template <bool FULL, typename S>
+__device__ __forceinline__ void fetch_plane(double (&r)[Halo<FULL>::N * Halo<FULL>::W],
+                                            const S* __restrict__ f, int j, const GridView& g,
+                                            const int (&off)[Halo<FULL>::N]) {
+  using H = Halo<FULL>;
   const S* fp = f + (int64_t)j * g.nz * g.nx;
 #pragma unroll
-  for (int q = 0; q < RPT; ++q) r[q] = (double)fp[off[q]];
+  for (int q = 0; q < H::N; ++q) {
+    if constexpr (H::W == 2) {
+      const auto v = *reinterpret_cast<const typename PairOf<S, 2>::type*>(fp + off[q]);
+      r[2 * q] = (double)v.x;
+      r[2 * q + 1] = (double)v.y;
+    } else {
+      r[q] = (double)fp[off[q]];
+    }
+  }
+}
+
+// store fetched values into the LDS slot at offset sb
+template <bool FULL>
+__device__ __forceinline__ void put_plane(double* lds, int sb,
+                                          const double (&r)[Halo<FULL>::N * Halo<FULL>::W]) {
+  using H = Halo<FULL>;
+#pragma unroll
+  for (int q = 0; q < H::N; ++q) {
+    const int e = threadIdx.x + q * RTX * RTZ;
+    if (e < H::NI) {
+      if constexpr (H::W == 2)
+        *reinterpret_cast<double2*>(lds + sb + 2 * e) = make_double2(r[2 * q], r[2 * q + 1]);
+      else
+        lds[sb + e] = r[q];
+    }
+  }
 }
 
 // load plane j of a field into the LDS slot at offset sb
-template <typename S>
+template <bool FULL, typename S>
 __device__ __forceinline__ void load_plane(double* lds, int sb, const S* __restrict__ f, int j,
-                                           const GridView& g, const int (&off)[RPT]) {
-  const S* fp = f + (int64_t)j * g.nz * g.nx;
-#pragma unroll
-  for (int q = 0; q < RPT; ++q)
-    if (threadIdx.x + q * RTX * RTZ < RPL) lds[sb + threadIdx.x + q * RTX * RTZ] = (double)fp[off[q]];
-}
-
-__device__ __forceinline__ void put_plane(double* lds, int sb, const double (&r)[RPT]) {
-#pragma unroll
-  for (int q = 0; q < RPT; ++q) {
-    const int e = threadIdx.x + q * RTX * RTZ;
-    if (e < RPL) lds[sb + e] = r[q];
-  }
+                                           const GridView& g, const int (&off)[Halo<FULL>::N]) {
+  double r[Halo<FULL>::N * Halo<FULL>::W];
+  fetch_plane<FULL>(r, f, j, g, off);
+  put_plane<FULL>(lds, sb, r);
 }
 
 // Flags of a launch, fixed at compile time so that the march is straight-line
@@ -130,19 +167,20 @@ __global__ __launch_bounds__(RTX * RTZ) __attribute__((amdgpu_waves_per_eu(4))) 
   const int tx = threadIdx.x % RTX, tz = threadIdx.x / RTX;
   const int i = i0 + tx, k = k0 + tz;
   const bool valid = FULL || (i < g.nx && k < g.nz);
-  const int lx = tx + 1, lz = tz + 1;
+  using H = Halo<FULL>;
+  const int lx = tx + H::XO, lz = tz + 1;
   const double idx = g.idx, idz = g.idz;
   const double idx2 = idx * idx, idz2 = idz * idz;
   const double am = a.alpha / a.re;
   const int64_t plane = (int64_t)g.nz * g.nx;
   // value of a ring slot (base offset sb = slot * RPL) at an offset from this
   // thread's cell
-  const int me = lz * RHX + lx;
-  auto S = [&](int sb, int dx, int dz) -> double { return lds[sb + me + dz * RHX + dx]; };
-  int off[RPT];
-  halo_offsets(off, g, i0, k0);
+  const int me = lz * H::HX + lx;
+  auto S = [&](int sb, int dx, int dz) -> double { return lds[sb + me + dz * H::HX + dx]; };
+  int off[H::N];
+  halo_offsets<FULL>(off, g, i0, k0);
   // the chunk's metric coefficients (only entries the chunk reads)
-  double* cf = lds + RSLOTS * RPL;
+  double* cf = lds + RSLOTS * H::PL;
   for (int q = threadIdx.x; q < RCOEF; q += RTX * RTZ) {
     const int arr = q / RCN, e = q % RCN;
     double val = 0.0;
@@ -160,27 +198,27 @@ __global__ __launch_bounds__(RTX * RTZ) __attribute__((amdgpu_waves_per_eu(4))) 
   int bu[3], bv[3], bw[3], bp[2];
   for (int q = 0; q < 3; ++q) {
     const int r = (j0 - 1 + q + 3) % 3;
-    bu[q] = r * RPL;
-    bv[q] = (3 + r) * RPL;
-    bw[q] = (6 + r) * RPL;
+    bu[q] = r * H::PL;
+    bv[q] = (3 + r) * H::PL;
+    bw[q] = (6 + r) * H::PL;
   }
-  for (int q = 0; q < 2; ++q) bp[q] = (9 + (j0 - 1 + q + 2) % 2) * RPL;
+  for (int q = 0; q < 2; ++q) bp[q] = (9 + (j0 - 1 + q + 2) % 2) * H::PL;
   // ring before the first step: u, v, w at j0-1, j0, j0+1 and p at j0-1, j0
   if (j0 > 0) {
-    load_plane(lds, bu[0], a.u, j0 - 1, g, off);
-    load_plane(lds, bv[0], a.v, j0 - 1, g, off);
-    load_plane(lds, bw[0], a.w, j0 - 1, g, off);
-    load_plane(lds, bp[0], a.p, j0 - 1, g, off);
+    load_plane<FULL>(lds, bu[0], a.u, j0 - 1, g, off);
+    load_plane<FULL>(lds, bv[0], a.v, j0 - 1, g, off);
+    load_plane<FULL>(lds, bw[0], a.w, j0 - 1, g, off);
+    load_plane<FULL>(lds, bp[0], a.p, j0 - 1, g, off);
   }
-  load_plane(lds, bu[1], a.u, j0, g, off);
-  load_plane(lds, bv[1], a.v, j0, g, off);
-  load_plane(lds, bw[1], a.w, j0, g, off);
-  load_plane(lds, bp[1], a.p, j0, g, off);
+  load_plane<FULL>(lds, bu[1], a.u, j0, g, off);
+  load_plane<FULL>(lds, bv[1], a.v, j0, g, off);
+  load_plane<FULL>(lds, bw[1], a.w, j0, g, off);
+  load_plane<FULL>(lds, bp[1], a.p, j0, g, off);
   if (j0 + 1 < g.ny) {
-    load_plane(lds, bu[2], a.u, j0 + 1, g, off);
-    load_plane(lds, bw[2], a.w, j0 + 1, g, off);
+    load_plane<FULL>(lds, bu[2], a.u, j0 + 1, g, off);
+    load_plane<FULL>(lds, bw[2], a.w, j0 + 1, g, off);
   }
-  load_plane(lds, bv[2], a.v, j0 + 1, g, off);  // v has ny+1 planes
+  load_plane<FULL>(lds, bv[2], a.v, j0 + 1, g, off);  // v has ny+1 planes
   // this thread's column (threads past a ragged edge read the last cell and
   // store nothing)
   const int64_t col = (int64_t)(k < g.nz ? k : g.nz - 1) * g.nx + (i < g.nx ? i : g.nx - 1);
@@ -209,15 +247,15 @@ __global__ __launch_bounds__(RTX * RTZ) __attribute__((amdgpu_waves_per_eu(4))) 
   // j+1) are in flight in registers while plane j is computed.  The loads are
   // unconditional (plane indices clamped; a clamped plane is never stored),
   // so every step issues the same loads in the same order.
-  double nu[RPT], nv[RPT], nw[RPT], np[RPT];
+  double nu[H::N * H::W], nv[H::N * H::W], nw[H::N * H::W], np[H::N * H::W];
   auto fetch_next = [&](int j) {
     const int ju = (j + 2 < g.ny) ? j + 2 : g.ny - 1;
     const int jv = (j + 2 <= g.ny) ? j + 2 : g.ny;
     const int jp = (j + 1 < g.ny) ? j + 1 : g.ny - 1;
-    fetch_plane(nu, a.u, ju, g, off);
-    fetch_plane(nw, a.w, ju, g, off);
-    fetch_plane(nv, a.v, jv, g, off);
-    fetch_plane(np, a.p, jp, g, off);
+    fetch_plane<FULL>(nu, a.u, ju, g, off);
+    fetch_plane<FULL>(nw, a.w, ju, g, off);
+    fetch_plane<FULL>(nv, a.v, jv, g, off);
+    fetch_plane<FULL>(np, a.p, jp, g, off);
   };
   fetch_cell(j0);
   fetch_next(j0);
@@ -327,11 +365,11 @@ __global__ __launch_bounds__(RTX * RTZ) __attribute__((amdgpu_waves_per_eu(4))) 
       t_ = bw[0]; bw[0] = bw[1]; bw[1] = bw[2]; bw[2] = t_;
       t_ = bp[0]; bp[0] = bp[1]; bp[1] = t_;
       if (j + 2 < g.ny) {
-        put_plane(lds, bu[2], nu);
-        put_plane(lds, bw[2], nw);
+        put_plane<FULL>(lds, bu[2], nu);
+        put_plane<FULL>(lds, bw[2], nw);
       }
-      if (j + 2 <= g.ny) put_plane(lds, bv[2], nv);
-      put_plane(lds, bp[1], np);
+      if (j + 2 <= g.ny) put_plane<FULL>(lds, bv[2], nv);
+      put_plane<FULL>(lds, bp[1], np);
       fetch_cell(j + 1);
       fetch_next(j + 1);
       __syncthreads();
@@ -362,7 +400,7 @@ static void run_rhs(Prof* pf, hipStream_t s, const GridView& g, const RhsArgs& a
   K.jc = (a.planes >= 1 && a.planes <= RJC) ? a.planes : RJC_DEF;
   const int64_t blocks = (int64_t)((g.nx + RTX - 1) / RTX) * ((g.nz + RTZ - 1) / RTZ) *
                          ((g.ny + K.jc - 1) / K.jc);
-  const size_t shm = sizeof(double) * (RSLOTS * RPL + RCOEF);
+  const size_t shm = sizeof(double) * (RSLOTS * RPL_MAX + RCOEF);
   const int f = ((g.nx % RTX == 0 && g.nz % RTZ == 0) ? RHS_FULL : 0) |
                 (a.rho != 0.0 ? RHS_HPREV : 0) |
                 ((a.hout[0] && a.hout[1] && a.hout[2]) ? RHS_HOUT : 0);
