@@ -444,6 +444,84 @@ __global__ __launch_bounds__(16 * Z16_TC) void k_fftz256(PoisK<C> K) {
   }
 }
 
+// Length 256 R z transforms (R = 2, 4: lengths 512 and 1024) as 16 x 16 x R
+// (four-step twice).  With M = 16 R threads per mode (t = 0..M-1) and
+// n = t + M n2:
+//  1. thread t loads x[t + M n2], n2 = 0..15, from HBM, takes a 16-point DFT
+//     (output k2) and the twiddle W_n^(t k2), and writes it to LDS;
+//  2. thread (k2, t1) (t = t1 + R t2) reads the 16 values t2 of its k2,
+//     takes a 16-point DFT (output k3) and the twiddle W_M^(t1 k3), and
+//     writes them back to LDS;
+//  3. each thread takes 16/R of the length-R DFTs over t1 (output k4) and
+//     stores X[k2 + 16 k3 + 256 k4].
+// 16/R modes per block (the 256 threads of a block load 64- or 128-byte row
+// pieces).  The LDS layouts keep every 16 consecutive lanes on distinct
+// 16-byte bank groups: step 2 reads stride-R rows, step 3 reads an XOR
+// swizzle of the (t1, mode) index by t1 of the reading thread.
+template <typename C, bool INV, int R>
+__global__ __launch_bounds__(256) void k_fftz4s(PoisK<C> K) {
+  constexpr int M = 16 * R;    // threads per mode
+  constexpr int N = 16 * M;    // transform length
+  constexpr int TC = 256 / M;  // modes per block
+  static_assert(R * TC == 16 && N * TC == 4096, "16 x 16 x R layout");
+  if (gated(K)) return;
+  __shared__ C T[4096];
+  const GridView& g = K.g;
+  const int nxh = g.nxh;
+  const int c = threadIdx.x % TC, tt = threadIdx.x / TC;
+  const int p = blockIdx.x * TC + c;
+  const bool valid = p < nxh;
+  const int ldx = K.ldx;
+  C* col = K.spec + (int64_t)blockIdx.y * N * ldx + (valid ? p : 0);  // element k at col[k ldx]
+  C x[16];
+  // 1.
+#pragma unroll
+  for (int n2 = 0; n2 < 16; ++n2) x[n2] = col[(int64_t)(tt + M * n2) * ldx];
+  dft16<C, INV>(x);
+#pragma unroll
+  for (int k2 = 0; k2 < 16; ++k2) {
+    C w = K.pz.tw[tt * k2];
+    if (INV) w.y = -w.y;
+    T[(k2 * M + tt) * TC + c] = (k2 && tt) ? cmul(x[pos16(k2)], w) : x[pos16(k2)];
+  }
+  __syncthreads();
+  // 2.
+  const int k2 = tt / R, t1 = tt % R;
+#pragma unroll
+  for (int t2 = 0; t2 < 16; ++t2) x[t2] = T[(k2 * M + t1 + R * t2) * TC + c];
+  dft16<C, INV>(x);
+  __syncthreads();  // every step-2 read is done before the buffer is rewritten
+  const int sw = t1 * TC;  // swizzle of the writing and of the reading thread alike
+#pragma unroll
+  for (int k3 = 0; k3 < 16; ++k3) {
+    C w = K.pz.tw[16 * t1 * k3];  // W_M^(t1 k3)
+    if (INV) w.y = -w.y;
+    const C v = (k3 && t1) ? cmul(x[pos16(k3)], w) : x[pos16(k3)];
+    // value (k2, k3, t1, c) at row k2 16 + k3, position (t1 TC + c) ^ (owner(k3) TC)
+    T[(k2 * 16 + k3) * 16 + ((t1 * TC + c) ^ ((k3 / (16 / R)) * TC))] = v;
+  }
+  __syncthreads();
+  // 3. k3 = t1 (16/R) + q: the length-R DFT over the R values of (k2, k3)
+#pragma unroll
+  for (int q = 0; q < 16 / R; ++q) {
+    const int k3 = t1 * (16 / R) + q;
+    C u[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) u[r] = T[(k2 * 16 + k3) * 16 + ((r * TC + c) ^ sw)];
+    if constexpr (R == 2) {
+      const C a = u[0], b = u[1];
+      u[0] = cadd(a, b);
+      u[1] = csub(a, b);
+    } else {
+      dft4<C, INV>(u[0], u[1], u[2], u[3]);
+    }
+    if (valid) {
+#pragma unroll
+      for (int k4 = 0; k4 < R; ++k4) col[(int64_t)(k2 + 16 * k3 + 256 * k4) * ldx] = u[k4];
+    }
+  }
+}
+
 // Length-256 x transforms, two real rows per complex sequence, X16_SC
 // sequences (2 X16_SC consecutive rows) per block.  The 16 lanes of a
 // sequence (lane t = n1 in the first DFT, k2 in the second) lie in one
@@ -1300,8 +1378,13 @@ static void run_passes(Prof* pf, hipStream_t s, const GridView& g, PoisK<C> K) {
   }
   const bool z256 = (g.nz == 256);
   const dim3 z16grid((g.nxh + Z16_TC - 1) / Z16_TC, g.ny);
+  const dim3 z512grid((g.nxh + 7) / 8, g.ny), z1kgrid((g.nxh + 3) / 4, g.ny);
   if (z256)
     IBM_LAUNCH(pf, "pois_fftz_fwd", s, (k_fftz256<C, false><<<z16grid, 16 * Z16_TC, 0, s>>>(K)));
+  else if (g.nz == 512)
+    IBM_LAUNCH(pf, "pois_fftz_fwd", s, (k_fftz4s<C, false, 2><<<z512grid, 256, 0, s>>>(K)));
+  else if (g.nz == 1024)
+    IBM_LAUNCH(pf, "pois_fftz_fwd", s, (k_fftz4s<C, false, 4><<<z1kgrid, 256, 0, s>>>(K)));
   else
     IBM_LAUNCH(pf, "pois_fftz_fwd", s, (k_fftz<C, false><<<zgrid, 256, zsh, s>>>(K)));
   if (ywave)
@@ -1310,6 +1393,10 @@ static void run_passes(Prof* pf, hipStream_t s, const GridView& g, PoisK<C> K) {
     IBM_LAUNCH(pf, "pois_tri_y", s, (k_tri_y_blk<C><<<yblocks, K.ytl * K.yP, ysh, s>>>(K)));
   if (z256)
     IBM_LAUNCH(pf, "pois_fftz_inv", s, (k_fftz256<C, true><<<z16grid, 16 * Z16_TC, 0, s>>>(K)));
+  else if (g.nz == 512)
+    IBM_LAUNCH(pf, "pois_fftz_inv", s, (k_fftz4s<C, true, 2><<<z512grid, 256, 0, s>>>(K)));
+  else if (g.nz == 1024)
+    IBM_LAUNCH(pf, "pois_fftz_inv", s, (k_fftz4s<C, true, 4><<<z1kgrid, 256, 0, s>>>(K)));
   else
     IBM_LAUNCH(pf, "pois_fftz_inv", s, (k_fftz<C, true><<<zgrid, 256, zsh, s>>>(K)));
   if (x256)

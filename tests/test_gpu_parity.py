@@ -175,12 +175,15 @@ def test_poisson_parity(name):
     assert abs(np.sum(got * dV)) < 1e-12 * np.sum(np.abs(got) * dV)
 
 
-@pytest.mark.parametrize("shape", [(256, 12, 16), (16, 12, 256), (16, 528, 16)])
+@pytest.mark.parametrize("shape", [(256, 12, 16), (16, 12, 256), (16, 528, 16), (16, 8, 512),
+                                   (24, 6, 1024)])
 def test_poisson_parity_kernel_paths(shape):
     """Shapes that select the other kernel paths, compared with the oracle
     value by value: length-256 x transforms (four-step), length-256 z
-    transforms (four-step), and a wall-normal solve with more than 64
-    separators per mode (block-wide reduction); stretched y."""
+    transforms (four-step), a wall-normal solve with more than 64
+    separators per mode (block-wide reduction), and length-512 and -1024 z
+    transforms (16 x 16 x R; 24 x-points: a partial last tile of modes);
+    stretched y."""
     import workloads
     nx, ny, nz = shape
     wl = workloads.Workload("paths", nx, ny, nz, 2 * np.pi, np.pi, workloads.tanh_faces(ny),
@@ -194,6 +197,26 @@ def test_poisson_parity_kernel_paths(shape):
     phi = torch.empty(g.cells, dtype=torch.float64, device=DEV)
     case.ibm.poisson_solve(case.ctx, t(rhs), phi)
     assert rel(n(phi, g.shape), poisson.solve(g, rhs)) < 1e-11
+
+
+@pytest.mark.parametrize("shape", [(16, 8, 512), (24, 6, 1024)])
+def test_poisson_refined_long_z(shape):
+    """The FP32 length-512 and -1024 z transforms inside the refined mixed
+    solve: the refined result agrees with the FP64 oracle solve."""
+    import workloads
+    nx, ny, nz = shape
+    wl = workloads.Workload("paths", nx, ny, nz, 2 * np.pi, np.pi, workloads.tanh_faces(ny),
+                            1.0, 1.0, 1, 0.0, 0.0, 1, 0.0, [])
+    case = Case(wl, precision="mixed", mixed_poisson="refined", refine_tol=1e-9)
+    g = case.g
+    rng = np.random.default_rng(12)
+    rhs = rng.standard_normal(g.shape)
+    dV = g.cell_volume()
+    rhs -= np.sum(rhs * dV) / np.sum(dV)
+    phi = torch.empty(g.cells, dtype=torch.float64, device=DEV)
+    case.ibm.poisson_solve(case.ctx, t(rhs), phi)
+    assert case.ibm.ibm_check(case.ctx) == 0
+    assert rel(n(phi, g.shape), poisson.solve(g, rhs)) < 1e-8
 
 
 def test_poisson_closed_form_eigenmode():
