@@ -652,10 +652,11 @@ __device__ __forceinline__ void col_coef(const LineK<T>& K, int i, T& a, T& b, T
   }
 }
 
-template <typename T, int MODE, int SL>
+template <typename T, int MODE, int SL, int TL>
 __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(SL == 12 ? 5 : 1)))
 void k_line_col(LineK<T> K) {
-  constexpr int TL = 16;       // lines per block
+  // TL lines per block: 16, or 32 in FP32 (a wavefront's loads then cover
+  // 128-byte row pieces in both)
   constexpr int SP = TL + 1;   // padded stride of the separator arrays
   extern __shared__ __align__(16) unsigned char ldsraw[];
   T* lds = reinterpret_cast<T*>(ldsraw);
@@ -700,13 +701,15 @@ void k_line_col(LineK<T> K) {
 #pragma unroll
     for (int e = 0; e < SL; ++e)
       dd[e] = *reinterpret_cast<const T*>(reinterpret_cast<const char*>(dbase) + boffs(e, sizeof(T)));
-    // lane lb < SL fetches the mask word of row lo + lb (bits i0 .. i0+15 of
-    // the row: one word, nx and i0 being multiples of 16)
+    // lane lb < SL fetches the mask word of row lo + lb (bits i0 .. i0+TL-1
+    // of the row: within one word, nx and i0 being multiples of TL)
+    static_assert(SL <= TL, "one mask word per lane");
     if (lb < SL) {
       const int64_t rb = (MODE == 1) ? ((int64_t)(K.j0 + blockIdx.y) * K.nz + lo + lb) * K.nx
                                      : ((int64_t)(K.j0 + lo + lb) * K.nz + blockIdx.y) * K.nx;
       const int64_t bit = rb + i0;
-      mws[s * SL + lb] = (K.mask[bit >> 5] >> (uint32_t)(bit & 31)) & 0xffffu;
+      const uint32_t w = K.mask[bit >> 5] >> (uint32_t)(bit & 31);
+      mws[s * SL + lb] = (TL == 32) ? w : (w & ((1u << (TL & 31)) - 1u));
     }
   }
   __syncthreads();  // tables and mask words
@@ -943,21 +946,34 @@ static void launch_line(Prof* pf, hipStream_t s, LineK<T> K, const char* name) {
   } else if (K.r == 0 && (K.L == LMAX || (K.mode == 2 && K.L == 12)) && K.nx % 16 == 0 &&
              K.P <= 64 && (!K.cyc || (K.P & (K.P - 1)) == 0) &&
              (K.mode == 1 ? (int64_t)K.nx : K.plane) * 64 * 8 < ((int64_t)1 << 31)) {
-    // column sweep: 16 lines per block, the separators solved per wavefront
+    // column sweep: 16 lines per block (32 in FP32 where the block stays
+    // within 1024 threads), the separators solved per wavefront
     int pp = 1;
     while (pp < K.P) pp <<= 1;
     K.PP = pp;
-    const int ct = 16 * pp;
+    const int tl = (sizeof(T) == sizeof(float) && pp <= 32 && K.nx % 32 == 0) ? 32 : 16;
+    const int ct = tl * pp;
     const size_t cshm = sizeof(T) * (LINE_NTAB * (size_t)(K.tab1 ? 1 : K.P) * K.L +
-                                     7 * (size_t)pp * 17) +
+                                     7 * (size_t)pp * (tl + 1)) +
                         sizeof(uint32_t) * (size_t)K.P * K.L;
-    const dim3 cgrid(K.nx / 16, K.mode == 1 ? K.nj : K.nz);
+    const dim3 cgrid(K.nx / tl, K.mode == 1 ? K.nj : K.nz);
+#define IBM_COL(M, SL_)                                                                        \
+  do {                                                                                        \
+    if constexpr (sizeof(T) == sizeof(float)) {                                               \
+      if (tl == 32) {                                                                         \
+        IBM_LAUNCH(pf, name, s, (k_line_col<T, M, SL_, 32><<<cgrid, ct, cshm, s>>>(K)));      \
+        break;                                                                                \
+      }                                                                                       \
+    }                                                                                         \
+    IBM_LAUNCH(pf, name, s, (k_line_col<T, M, SL_, 16><<<cgrid, ct, cshm, s>>>(K)));          \
+  } while (0)
     if (K.mode == 1)
-      IBM_LAUNCH(pf, name, s, (k_line_col<T, 1, LMAX><<<cgrid, ct, cshm, s>>>(K)));
+      IBM_COL(1, LMAX);
     else if (K.L == 12)
-      IBM_LAUNCH(pf, name, s, (k_line_col<T, 2, 12><<<cgrid, ct, cshm, s>>>(K)));
+      IBM_COL(2, 12);
     else
-      IBM_LAUNCH(pf, name, s, (k_line_col<T, 2, LMAX><<<cgrid, ct, cshm, s>>>(K)));
+      IBM_COL(2, LMAX);
+#undef IBM_COL
   }
   else if (K.mode == 1)
     IBM_LAUNCH(pf, name, s, (k_line<T, 1, false><<<grid, threads, shm, s>>>(K)));
