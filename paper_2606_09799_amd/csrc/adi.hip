@@ -673,13 +673,17 @@ void k_line_col(LineK<T> K) {
   }
   const int lb = tid % TL, s = tid / TL;
   const bool active = s < P;
-  const int i0 = blockIdx.x * TL;
+  // y sweep: blocks in z-major order (consecutive blocks on different z
+  // rows, hence different memory channels); z sweep: x-tile fastest
+  const int bx = (MODE == 2) ? (int)blockIdx.y : (int)blockIdx.x;
+  const int by = (MODE == 2) ? (int)blockIdx.x : (int)blockIdx.y;
+  const int i0 = bx * TL;
   const int ts = K.tab1 ? 0 : s;
 #define CTAB(q, e) tabs[((q) * SL + (e)) * tP + ts]
   // element (row r of line lb): blk[lb + r * es]
   const int64_t es = (MODE == 1) ? K.nx : K.plane;
-  const int64_t boff = (MODE == 1) ? (int64_t)(K.j0 + blockIdx.y) * K.plane + i0
-                                   : (int64_t)K.j0 * K.plane + (int64_t)blockIdx.y * K.nx + i0;
+  const int64_t boff = (MODE == 1) ? (int64_t)(K.j0 + by) * K.plane + i0
+                                   : (int64_t)K.j0 * K.plane + (int64_t)by * K.nx + i0;
   const int lo = s * SL;
   constexpr int m = SL - 1;
   T dd[SL];
@@ -705,8 +709,8 @@ void k_line_col(LineK<T> K) {
     // of the row: within one word, nx and i0 being multiples of TL)
     static_assert(SL <= TL, "one mask word per lane");
     if (lb < SL) {
-      const int64_t rb = (MODE == 1) ? ((int64_t)(K.j0 + blockIdx.y) * K.nz + lo + lb) * K.nx
-                                     : ((int64_t)(K.j0 + lo + lb) * K.nz + blockIdx.y) * K.nx;
+      const int64_t rb = (MODE == 1) ? ((int64_t)(K.j0 + by) * K.nz + lo + lb) * K.nx
+                                     : ((int64_t)(K.j0 + lo + lb) * K.nz + by) * K.nx;
       const int64_t bit = rb + i0;
       const uint32_t w = K.mask[bit >> 5] >> (uint32_t)(bit & 31);
       mws[s * SL + lb] = (TL == 32) ? w : (w & ((1u << (TL & 31)) - 1u));
@@ -956,7 +960,7 @@ static void launch_line(Prof* pf, hipStream_t s, LineK<T> K, const char* name) {
     const size_t cshm = sizeof(T) * (LINE_NTAB * (size_t)(K.tab1 ? 1 : K.P) * K.L +
                                      7 * (size_t)pp * (tl + 1)) +
                         sizeof(uint32_t) * (size_t)K.P * K.L;
-    const dim3 cgrid(K.nx / tl, K.mode == 1 ? K.nj : K.nz);
+    const dim3 cgrid = (K.mode == 1) ? dim3(K.nx / tl, K.nj) : dim3(K.nz, K.nx / tl);
 #define IBM_COL(M, SL_)                                                                        \
   do {                                                                                        \
     if constexpr (sizeof(T) == sizeof(float)) {                                               \
