@@ -797,10 +797,14 @@ __global__ __launch_bounds__(1024) void k_tri_y(PoisK<C> K) {
   const int TL = K.ytl, P = K.yP, PP = K.yPP, SP = TL + 1;
   const int lb = threadIdx.x % TL, s = threadIdx.x / TL;
   const bool active = s < P;  // lanes of the padding segments only join the reduction
-  // modes q = k ldx + p over the padded rows; padding columns are skipped
-  const int64_t nm = (int64_t)g.nz * K.ldx;
-  const int64_t q = (int64_t)blockIdx.x * TL + lb;
-  const bool valid = active && q < nm && (int)(q % K.ldx) < g.nxh;
+  // modes q = k ldx + p; blocks in z-major order (block b: row k = b mod nz,
+  // modes p of tile b / nz), so that consecutive blocks read different z
+  // rows, hence different memory channels; padding columns are skipped
+  const int64_t nm = (int64_t)g.nz * K.ldx;  // stride of one y row of modes
+  const int kq = (int)(blockIdx.x % (unsigned)g.nz);
+  const int pq = (int)(blockIdx.x / (unsigned)g.nz) * TL + lb;
+  const int64_t q = (int64_t)kq * K.ldx + pq;
+  const bool valid = active && pq < g.nxh;
   // LDS array f, separator seg, mode lane ln (padded stride: conflict-free in
   // both the natural and the transposed order)
   auto A = [&](int f, int seg, int ln) -> double& { return sm[((size_t)f * PP + seg) * SP + ln]; };
@@ -811,7 +815,7 @@ __global__ __launch_bounds__(1024) void k_tri_y(PoisK<C> K) {
   const int m = len - 1;  // interior rows (at least 2); row lo+m is the separator
   const bool zero = (q == 0);
   // lanes past the last mode solve a harmless non-singular system
-  const double lam = valid ? K.lamx[q % K.ldx] + K.lamz[q / K.ldx] : -1.0;
+  const double lam = valid ? K.lamx[pq] + K.lamz[kq] : -1.0;
   C* __restrict__ X = K.spec + q;
   double xr[YL], xi[YL], ah[YL], ch[YL];
   double zr = 0.0, zi = 0.0;
@@ -1357,6 +1361,8 @@ static void run_passes(Prof* pf, hipStream_t s, const GridView& g, PoisK<C> K) {
   K.ldx = spec_ld(g.nxh, sizeof(C) == sizeof(float2));
   const int64_t nm = (int64_t)g.nz * K.ldx;
   const int yblocks = (int)((nm + K.ytl - 1) / K.ytl);
+  // wavefront form: z-major blocks of ytl modes of one z row
+  const int ywblocks = g.nz * ((g.nxh + K.ytl - 1) / K.ytl);
   const size_t ysh = ywave ? 11 * sizeof(double) * (size_t)K.yPP * (K.ytl + 1)
                            : 7 * sizeof(double) * (size_t)K.yP * K.ytl;
   const bool resid = K.mode >= SRC_RESIDUAL;
@@ -1388,7 +1394,7 @@ static void run_passes(Prof* pf, hipStream_t s, const GridView& g, PoisK<C> K) {
   else
     IBM_LAUNCH(pf, "pois_fftz_fwd", s, (k_fftz<C, false><<<zgrid, 256, zsh, s>>>(K)));
   if (ywave)
-    IBM_LAUNCH(pf, "pois_tri_y", s, (k_tri_y<C><<<yblocks, K.ytl * K.yPP, ysh, s>>>(K)));
+    IBM_LAUNCH(pf, "pois_tri_y", s, (k_tri_y<C><<<ywblocks, K.ytl * K.yPP, ysh, s>>>(K)));
   else
     IBM_LAUNCH(pf, "pois_tri_y", s, (k_tri_y_blk<C><<<yblocks, K.ytl * K.yP, ysh, s>>>(K)));
   if (z256)
