@@ -293,6 +293,42 @@ __device__ __forceinline__ void resid_reduce(double rmax, double vsum, double* r
   }
 }
 
+// Velocity source (SRC_VELOCITY without the energy shape) of the generic
+// forward x transform on rows of nx = 256 M values, 256 threads: thread t
+// forms x = t + 256 m (m < M) of each row, all loads issued whatever the C_B
+// mask says (same arithmetic as fftx_source), so that a row's loads are in
+// flight together.  Rows past nr take the block's first row, stored as 0.
+template <typename C, bool CB, int M>
+__device__ __forceinline__ void fftx_stage_vel_rows(const PoisK<C>& K, typename RealOf<C>::T* sr,
+                                                    int64_t row0, int nr, int rows, double q) {
+  using R = typename RealOf<C>::T;
+  const GridView& g = K.g;
+  constexpr int nx = 256 * M;
+  const int nz = g.nz;
+  const int64_t plane = (int64_t)nz * nx;
+#pragma unroll 2
+  for (int r = 0; r < rows; ++r) {
+    const int64_t rr = row0 + (r < nr ? r : 0);
+    const int jr = (int)(rr / nz), kr = (int)(rr - (int64_t)jr * nz);
+    const int kp = (kr + 1 == nz) ? 0 : kr + 1;
+    const double idyj = g.idy[jr];
+#pragma unroll
+    for (int m = 0; m < M; ++m) {
+      const int i = (int)threadIdx.x + 256 * m;
+      const int ip = (i + 1 == nx) ? 0 : i + 1;
+      const int64_t cell = rr * nx + i;
+      const double u0 = K.u[cell], u1 = K.u[cell - i + ip];
+      const double v0 = K.v[cell], v1 = K.v[cell + plane];
+      const double w0 = K.w[cell], w1 = K.w[(int64_t)jr * plane + (int64_t)kp * nx + i];
+      const double D = (u1 - u0) * g.idx + (v1 - v0) * idyj + (w1 - w0) * g.idz;
+      double val = (D - q) * K.inv_adt;
+      if (CB && ((K.cb_mask[cell >> 5] >> (uint32_t)(cell & 31)) & 1u)) val = 0.0;
+      if (r >= nr) val = 0.0;
+      sr[2 * ((r >> 1) * nx + i) + (r & 1)] = (R)val;
+    }
+  }
+}
+
 template <typename C>
 __global__ __launch_bounds__(256) void k_fftx_fwd(PoisK<C> K) {
   using R = typename RealOf<C>::T;
@@ -312,20 +348,32 @@ __global__ __launch_bounds__(256) void k_fftx_fwd(PoisK<C> K) {
   const double q1 = (K.mode == SRC_VELOCITY && K.pq) ? K.qf[1] : 0.0;
   const bool resid = K.mode >= SRC_RESIDUAL;
   double rmax = 0.0, vsum = 0.0;
-  for (int e = threadIdx.x; e < nr * nx; e += blockDim.x) {
-    const int r = e / nx, i = e % nx;
-    const int64_t rr = row0 + r;
-    const int jr = (int)(rr / g.nz), kr = (int)(rr - (int64_t)jr * g.nz);
-    const double val = fftx_source(K, rr, jr, kr, i, q, q1, rmax, vsum);
-    if (K.mode != SRC_CHECK) sr[2 * ((r >> 1) * nx + i) + (r & 1)] = (R)val;
-  }
-  if (resid) {
-    resid_reduce(rmax, vsum, red, K.rmax, K.psum, g.dx * g.dz);
-    if (K.mode == SRC_CHECK) return;  // block-uniform
-  }
-  for (int e = nr * nx + threadIdx.x; e < K.rows * nx; e += blockDim.x) {
-    const int r = e / nx, i = e % nx;
-    sr[2 * ((r >> 1) * nx + i) + (r & 1)] = (R)0;
+  const bool fast = K.mode == SRC_VELOCITY && !K.rhs_keep && !K.pq && blockDim.x == 256 &&
+                    (nx == 512 || nx == 1024);
+  if (fast) {  // every row of the block staged, rows past nr as 0
+    if (nx == 512) {
+      if (K.cb_mask) fftx_stage_vel_rows<C, true, 2>(K, sr, row0, nr, K.rows, q);
+      else fftx_stage_vel_rows<C, false, 2>(K, sr, row0, nr, K.rows, q);
+    } else {
+      if (K.cb_mask) fftx_stage_vel_rows<C, true, 4>(K, sr, row0, nr, K.rows, q);
+      else fftx_stage_vel_rows<C, false, 4>(K, sr, row0, nr, K.rows, q);
+    }
+  } else {
+    for (int e = threadIdx.x; e < nr * nx; e += blockDim.x) {
+      const int r = e / nx, i = e % nx;
+      const int64_t rr = row0 + r;
+      const int jr = (int)(rr / g.nz), kr = (int)(rr - (int64_t)jr * g.nz);
+      const double val = fftx_source(K, rr, jr, kr, i, q, q1, rmax, vsum);
+      if (K.mode != SRC_CHECK) sr[2 * ((r >> 1) * nx + i) + (r & 1)] = (R)val;
+    }
+    if (resid) {
+      resid_reduce(rmax, vsum, red, K.rmax, K.psum, g.dx * g.dz);
+      if (K.mode == SRC_CHECK) return;  // block-uniform
+    }
+    for (int e = nr * nx + threadIdx.x; e < K.rows * nx; e += blockDim.x) {
+      const int r = e / nx, i = e % nx;
+      sr[2 * ((r >> 1) * nx + i) + (r & 1)] = (R)0;
+    }
   }
   __syncthreads();
   const C* out = lds_fft<C, false>(sm, sm + (K.rows / 2) * nx, K.px, K.rows / 2, 1, nx);
