@@ -351,7 +351,14 @@ def main():
         results[form] = r
     batched = None
     if args.batch_sims > 0:
-        modes, bcells, tune = run_batched(args, dev, args.batch_sims)
+        try:
+            modes, bcells, tune = run_batched(args, dev, args.batch_sims)
+        except Exception as e:  # the single-grid results above stand on their own
+            print(f"bench.py: the batched workload failed: {type(e).__name__}: {e}",
+                  file=sys.stderr, flush=True)
+            modes = None
+            batched = {"error": f"{type(e).__name__}: {e}"}
+    if args.batch_sims > 0 and modes is not None:
         best = max(modes, key=lambda m: modes[m][0])
         batched = {"workload": f"c4: {args.batch_sims} simulations, {bcells} cells in total "
                                "(uniform spacing 1/32, 32..128 x 32..96 x 32..128, one sphere, "
