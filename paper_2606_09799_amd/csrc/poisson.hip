@@ -835,7 +835,21 @@ __global__ __launch_bounds__(32 * X16_SC) void k_fftx256_inv(PoisK<C> K) {
 // (|b| >= |a| + |c|), so the elimination needs no pivoting.
 constexpr int YL = 6;
 
-template <typename C>
+// 1/x within about an ulp: the hardware reciprocal refined by two Newton
+// steps (fewer instructions than the IEEE division sequence).  Used on the
+// pivots of the wall-normal systems, whose magnitudes are far from the
+// limits of the FP64 range.
+__device__ __forceinline__ double recip(double x) {
+  double r = __builtin_amdgcn_rcp(x);
+  double e = fma(-x, r, 1.0);
+  r = fma(r, e, r);
+  e = fma(-x, r, 1.0);
+  return fma(r, e, r);
+}
+
+// UNI: every segment holds exactly YL rows (ny = P YL), so the row loops
+// are straight-line code.
+template <typename C, bool UNI>
 __global__ __launch_bounds__(1024) void k_tri_y(PoisK<C> K) {
   using R = typename RealOf<C>::T;
   if (gated(K)) return;
@@ -856,36 +870,32 @@ __global__ __launch_bounds__(1024) void k_tri_y(PoisK<C> K) {
   // LDS array f, separator seg, mode lane ln (padded stride: conflict-free in
   // both the natural and the transposed order)
   auto A = [&](int f, int seg, int ln) -> double& { return sm[((size_t)f * PP + seg) * SP + ln]; };
-  // padding lanes compute the last real segment's rows (never stored)
+  // Lanes of padding segments compute the last real segment's rows and lanes
+  // past the last mode the last mode's system: every lane loads and solves
+  // unconditionally, only valid lanes store
   const int sx = active ? s : P - 1;
-  const int lo = sx * K.yL + (sx < K.yr ? sx : K.yr);
-  const int len = K.yL + (sx < K.yr ? 1 : 0);
+  const int lo = UNI ? sx * YL : sx * K.yL + (sx < K.yr ? sx : K.yr);
+  const int len = UNI ? YL : K.yL + (sx < K.yr ? 1 : 0);
   const int m = len - 1;  // interior rows (at least 2); row lo+m is the separator
-  const bool zero = (q == 0);
-  // lanes past the last mode solve a harmless non-singular system
-  const double lam = valid ? K.lamx[pq] + K.lamz[kq] : -1.0;
-  C* __restrict__ X = K.spec + q;
-  double xr[YL], xi[YL], ah[YL], ch[YL];
-  double zr = 0.0, zi = 0.0;
+  const bool z0 = (q == 0) && lo == 0;  // the (0,0) mode's first row: identity, right side 0
+  const int pl = pq < g.nxh ? pq : g.nxh - 1;
+  const double lam = K.lamx[pl] + K.lamz[kq];
+  const C* __restrict__ Xl = K.spec + (int64_t)kq * K.ldx + pl;
+  double xr[YL], xi[YL], ah[YL - 1], ch[YL - 1];
 #pragma unroll
   for (int e = 0; e < YL; ++e) {
-    xr[e] = 0.0;
-    xi[e] = 0.0;
-    ah[e] = 0.0;
-    ch[e] = 0.0;
+    const int row = (UNI || lo + e < g.ny) ? lo + e : g.ny - 1;
+    const C v = Xl[(int64_t)row * nm];
+    xr[e] = (double)v.x;
+    xi[e] = (double)v.y;
   }
-  if (valid) {
+  double zr = xr[YL - 1], zi = xi[YL - 1];
+  if (!UNI) {
 #pragma unroll
-    for (int e = 0; e < YL; ++e)
-      if (e < len) {
-        const C v = X[(int64_t)(lo + e) * nm];
-        if (e < m) {
-          xr[e] = (double)v.x;
-          xi[e] = (double)v.y;
-        } else {
-          zr = (double)v.x;
-          zi = (double)v.y;
-        }
+    for (int e = 0; e < YL - 1; ++e)
+      if (e == m) {
+        zr = xr[e];
+        zi = xi[e];
       }
   }
   // forward elimination of the interior rows: row e becomes
@@ -893,18 +903,18 @@ __global__ __launch_bounds__(1024) void k_tri_y(PoisK<C> K) {
   double atp = 0.0, ctp = 0.0, dr = 0.0, di = 0.0;
 #pragma unroll
   for (int e = 0; e < YL - 1; ++e)
-    if (e < m) {
+    if (UNI || e < m) {
       const int j = lo + e;
       double a = K.ylo[j], c = K.yhi[j], b = lam - (a + c);
       double er = xr[e], ei = xi[e];
-      if (zero && j == 0) {
+      if (e == 0 && z0) {
         a = 0.0;
         b = 1.0;
         c = 0.0;
         er = 0.0;
         ei = 0.0;
       }
-      const double inv = 1.0 / (b - a * ctp);
+      const double inv = recip(b - a * ctp);
       atp = (e == 0) ? a * inv : -a * atp * inv;
       ctp = c * inv;
       dr = (er - a * dr) * inv;
@@ -918,7 +928,7 @@ __global__ __launch_bounds__(1024) void k_tri_y(PoisK<C> K) {
   double ahl = 0.0, chl = 0.0, dlr = 0.0, dli = 0.0;  // row m-1
 #pragma unroll
   for (int e = YL - 2; e >= 0; --e)
-    if (e < m) {
+    if (UNI || e < m) {
       if (e == m - 1) {
         ahl = ah[e];
         chl = ch[e];
@@ -960,7 +970,10 @@ __global__ __launch_bounds__(1024) void k_tri_y(PoisK<C> K) {
   __syncthreads();
   {
     // transposed: lane (mode lt, separator st), PP lanes per mode; rows past
-    // P and outside 0..PP-1 act as identity rows
+    // P act as identity rows.  Each step eliminates the neighbours at
+    // distance `step`; a neighbour outside 0..PP-1 is an identity row, which
+    // contributes nothing (its multiplier is 0), so the lane reads itself
+    // there and drops the term.
     const int lt = threadIdx.x / PP, st = threadIdx.x % PP;
     const int grp = (threadIdx.x & 63) - st;
     const bool own = lt < TL && st < P;
@@ -976,25 +989,12 @@ __global__ __launch_bounds__(1024) void k_tri_y(PoisK<C> K) {
       const int im = st - step, ip = st + step;
       const bool hm = im >= 0, hp = ip < PP;
       const int sm_ = grp + (hm ? im : st), sp_ = grp + (hp ? ip : st);
-      double am = lane_read(ra, sm_), bm = lane_read(rb, sm_), gm = lane_read(rg, sm_);
-      double dmr = lane_read(rdr, sm_), dmi = lane_read(rdi, sm_);
-      double ap = lane_read(ra, sp_), bp = lane_read(rb, sp_), gp = lane_read(rg, sp_);
-      double dpr = lane_read(rdr, sp_), dpi = lane_read(rdi, sp_);
-      if (!hm) {
-        am = 0.0;
-        bm = 1.0;
-        gm = 0.0;
-        dmr = 0.0;
-        dmi = 0.0;
-      }
-      if (!hp) {
-        ap = 0.0;
-        bp = 1.0;
-        gp = 0.0;
-        dpr = 0.0;
-        dpi = 0.0;
-      }
-      const double k1 = ra / bm, k2 = rg / bp;
+      const double rib = recip(rb);  // neighbours divide by this row's pivot
+      const double am = lane_read(ra, sm_), rm = lane_read(rib, sm_), gm = lane_read(rg, sm_);
+      const double dmr = lane_read(rdr, sm_), dmi = lane_read(rdi, sm_);
+      const double ap = lane_read(ra, sp_), rp = lane_read(rib, sp_), gp = lane_read(rg, sp_);
+      const double dpr = lane_read(rdr, sp_), dpi = lane_read(rdi, sp_);
+      const double k1 = hm ? ra * rm : 0.0, k2 = hp ? rg * rp : 0.0;
       const double na = -am * k1, ng = -gp * k2;
       rb = rb - gm * k1 - ap * k2;
       rdr = rdr - dmr * k1 - dpr * k2;
@@ -1003,8 +1003,9 @@ __global__ __launch_bounds__(1024) void k_tri_y(PoisK<C> K) {
       rg = ng;
     }
     if (own) {
-      A(9, st, lt) = rdr / rb;
-      A(10, st, lt) = rdi / rb;
+      const double rib = recip(rb);
+      A(9, st, lt) = rdr * rib;
+      A(10, st, lt) = rdi * rib;
     }
   }
   __syncthreads();
@@ -1013,7 +1014,7 @@ __global__ __launch_bounds__(1024) void k_tri_y(PoisK<C> K) {
   const double zLi = (s > 0) ? A(10, s - 1, lb) : 0.0;
 #pragma unroll
   for (int e = 0; e < YL - 1; ++e)
-    if (e < m) {
+    if (UNI || e < m) {
       xr[e] = xr[e] - ah[e] * zLr - ch[e] * zRr;
       xi[e] = xi[e] - ah[e] * zLi - ch[e] * zRi;
     }
@@ -1026,7 +1027,7 @@ __global__ __launch_bounds__(1024) void k_tri_y(PoisK<C> K) {
     if (lb == 0) {
 #pragma unroll
       for (int e = 0; e < YL; ++e)
-        if (e < len) {
+        if (UNI || e < len) {
           const double dyj = g.dy[lo + e];
           pr += dyj * (e < m ? xr[e] : zr);
           pi += dyj * (e < m ? xi[e] : zi);
@@ -1048,7 +1049,7 @@ __global__ __launch_bounds__(1024) void k_tri_y(PoisK<C> K) {
       Mi *= K.inv_sum_dy;
 #pragma unroll
       for (int e = 0; e < YL - 1; ++e)
-        if (e < m) {
+        if (UNI || e < m) {
           xr[e] -= Mr;
           xi[e] -= Mi;
         }
@@ -1059,10 +1060,11 @@ __global__ __launch_bounds__(1024) void k_tri_y(PoisK<C> K) {
   if (valid) {
     // an FP32 spectrum hands the (0,0) mode (a real column) to the inverse x
     // pass in FP64, so that the zero-mean gauge survives the FP32 rounding
-    const bool keep = zero && K.zm;
+    const bool keep = (q == 0) && K.zm;
+    C* __restrict__ X = K.spec + q;
 #pragma unroll
     for (int e = 0; e < YL; ++e)
-      if (e < len) {
+      if (UNI || e < len) {
         const double vr = (e < m) ? xr[e] : zr;
         const double vi = (e < m) ? xi[e] : zi;
         if (keep) K.zm[lo + e] = vr;
@@ -1441,8 +1443,10 @@ static void run_passes(Prof* pf, hipStream_t s, const GridView& g, PoisK<C> K) {
     IBM_LAUNCH(pf, "pois_fftz_fwd", s, (k_fftz4s<C, false, 4><<<z1kgrid, 256, 0, s>>>(K)));
   else
     IBM_LAUNCH(pf, "pois_fftz_fwd", s, (k_fftz<C, false><<<zgrid, 256, zsh, s>>>(K)));
-  if (ywave)
-    IBM_LAUNCH(pf, "pois_tri_y", s, (k_tri_y<C><<<ywblocks, K.ytl * K.yPP, ysh, s>>>(K)));
+  if (ywave && K.yr == 0 && K.yL == YL)
+    IBM_LAUNCH(pf, "pois_tri_y", s, (k_tri_y<C, true><<<ywblocks, K.ytl * K.yPP, ysh, s>>>(K)));
+  else if (ywave)
+    IBM_LAUNCH(pf, "pois_tri_y", s, (k_tri_y<C, false><<<ywblocks, K.ytl * K.yPP, ysh, s>>>(K)));
   else
     IBM_LAUNCH(pf, "pois_tri_y", s, (k_tri_y_blk<C><<<yblocks, K.ytl * K.yP, ysh, s>>>(K)));
   if (z256)
