@@ -76,6 +76,20 @@ template <typename S, int W> struct PairOf { using type = S; };
 template <> struct PairOf<double, 2> { using type = double2; };
 template <> struct PairOf<float, 2> { using type = float2; };
 
+// The element at a block-uniform base plus a per-thread 32-bit byte offset,
+// the address form that global loads and stores take directly (64-bit base
+// in scalar registers, 32-bit vector offset): no 64-bit address per thread
+// and field is kept live across the march.  Offsets within one plane stay
+// below 2^32 bytes (nx, nz <= 1024).
+template <typename X>
+__device__ __forceinline__ const X& at_off(const X* base, uint32_t byte_off) {
+  return *reinterpret_cast<const X*>(reinterpret_cast<const char*>(base) + byte_off);
+}
+template <typename X>
+__device__ __forceinline__ X& at_off(X* base, uint32_t byte_off) {
+  return *reinterpret_cast<X*>(reinterpret_cast<char*>(base) + byte_off);
+}
+
 // Offsets within a plane of this thread's loads e = tid + q*threads of the
 // tile (i0, k0), with the periodic wrap (grids narrower than a ragged tile
 // wrap more than once; a whole tile's pairs start at even x and never
@@ -105,12 +119,14 @@ __device__ __forceinline__ void fetch_plane(double (&r)[Halo<FULL>::N * Halo<FUL
   const S* fp = f + (int64_t)j * g.nz * g.nx;
 #pragma unroll
   for (int q = 0; q < H::N; ++q) {
+    const uint32_t ob = (uint32_t)off[q] * (uint32_t)sizeof(S);
     if constexpr (H::W == 2) {
-      const auto v = *reinterpret_cast<const typename PairOf<S, 2>::type*>(fp + off[q]);
+      using P2 = typename PairOf<S, 2>::type;
+      const P2 v = at_off(reinterpret_cast<const P2*>(fp), ob);
       r[2 * q] = (double)v.x;
       r[2 * q + 1] = (double)v.y;
     } else {
-      r[q] = (double)fp[off[q]];
+      r[q] = (double)at_off(fp, ob);
     }
   }
 }
@@ -232,15 +248,27 @@ __global__ __launch_bounds__(RTX * RTZ) __attribute__((amdgpu_waves_per_eu(4))) 
   // this thread's H_prev values and mask words of a step, loaded a step ahead
   double hp0 = 0.0, hp1 = 0.0, hp2 = 0.0;
   uint32_t mw0, mw1, mw2;
+  // this thread's byte offsets within a plane (cell values and, with whole
+  // tiles, whose planes hold a multiple of 32 cells, mask words)
+  const uint32_t ocell = (uint32_t)col * (uint32_t)sizeof(T);
+  const uint32_t oword = (uint32_t)(col >> 5) * 4u;
   auto fetch_cell = [&](int j) {
-    const int64_t c = (int64_t)j * plane + col;
-    mw0 = a.mask[0][c >> 5];
-    mw1 = a.mask[1][c >> 5];
-    mw2 = a.mask[2][c >> 5];
+    const int64_t pj = (int64_t)j * plane;
+    if (FULL) {
+      const int64_t wj = pj >> 5;
+      mw0 = at_off(a.mask[0] + wj, oword);
+      mw1 = at_off(a.mask[1] + wj, oword);
+      mw2 = at_off(a.mask[2] + wj, oword);
+    } else {
+      const int64_t c = pj + col;
+      mw0 = a.mask[0][c >> 5];
+      mw1 = a.mask[1][c >> 5];
+      mw2 = a.mask[2][c >> 5];
+    }
     if (HPREV) {
-      hp0 = (double)a.hprev[0][c];
-      hp1 = (double)a.hprev[1][c];
-      hp2 = (double)a.hprev[2][c];
+      hp0 = (double)at_off(a.hprev[0] + pj, ocell);
+      hp1 = (double)at_off(a.hprev[1] + pj, ocell);
+      hp2 = (double)at_off(a.hprev[2] + pj, ocell);
     }
   };
   // software pipeline: the planes of the next step (u, v, w at j+2 and p at
@@ -261,7 +289,7 @@ __global__ __launch_bounds__(RTX * RTZ) __attribute__((amdgpu_waves_per_eu(4))) 
   fetch_next(j0);
   __syncthreads();
   for (int j = j0; j < j1; ++j) {
-    const int64_t c = (int64_t)j * plane + col;
+    const int64_t pj = (int64_t)j * plane;
     const int cj = j - j0;
     const double idyj = cf[cj + 1];
     const bool has_s = j > 0, has_n = j + 1 < g.ny;
@@ -273,7 +301,7 @@ __global__ __launch_bounds__(RTX * RTZ) __attribute__((amdgpu_waves_per_eu(4))) 
     const int V0 = bv[1], Vm = bv[0], Vp = bv[2];
     const int W0 = bw[1], Wm = bw[0], Wp = bw[2];
     const int P0 = bp[1], Pm = bp[0];
-    const uint32_t bit = (uint32_t)(c & 31);
+    const uint32_t bit = FULL ? (uint32_t)(col & 31) : (uint32_t)((pj + col) & 31);
     double r_u, r_v = 0.0, r_w, h_u, h_v = 0.0, h_w;
     // ---------------------------------------------------------- u node
     {
@@ -348,13 +376,13 @@ __global__ __launch_bounds__(RTX * RTZ) __attribute__((amdgpu_waves_per_eu(4))) 
       r_v = ((mw1 >> bit) & 1u) ? 0.0 : a.dt * r;
     }
     if (valid) {
-      a.R[0][c] = (T)r_u;
-      a.R[2][c] = (T)r_w;
-      a.R[1][c] = (T)r_v;
+      at_off(a.R[0] + pj, ocell) = (T)r_u;
+      at_off(a.R[2] + pj, ocell) = (T)r_w;
+      at_off(a.R[1] + pj, ocell) = (T)r_v;
       if (HOUT) {
-        a.hout[0][c] = (T)h_u;
-        a.hout[2][c] = (T)h_w;
-        a.hout[1][c] = (T)h_v;
+        at_off(a.hout[0] + pj, ocell) = (T)h_u;
+        at_off(a.hout[2] + pj, ocell) = (T)h_w;
+        at_off(a.hout[1] + pj, ocell) = (T)h_v;
       }
     }
     if (j + 1 < j1) {
