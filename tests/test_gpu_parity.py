@@ -219,14 +219,15 @@ def test_poisson_parity(name):
 
 
 @pytest.mark.parametrize("shape", [(256, 12, 16), (16, 12, 256), (16, 528, 16), (16, 8, 512),
-                                   (24, 6, 1024)])
+                                   (24, 6, 1024), (16, 192, 16), (24, 100, 16)])
 def test_poisson_parity_kernel_paths(shape):
     """Shapes that select the other kernel paths, compared with the oracle
     value by value: length-256 x transforms (four-step), length-256 z
     transforms (four-step), a wall-normal solve with more than 64
-    separators per mode (block-wide reduction), and length-512 and -1024 z
-    transforms (16 x 16 x R; 24 x-points: a partial last tile of modes);
-    stretched y."""
+    separators per mode (block-wide reduction), length-512 and -1024 z
+    transforms (16 x 16 x R; 24 x-points: a partial last tile of modes), the
+    wall-normal solve of 32 equal 6-row segments (ny = 192, straight-line
+    rows) and of 17 unequal ones (ny = 100); stretched y."""
     import workloads
     nx, ny, nz = shape
     wl = workloads.Workload("paths", nx, ny, nz, 2 * np.pi, np.pi, workloads.tanh_faces(ny),
@@ -242,10 +243,11 @@ def test_poisson_parity_kernel_paths(shape):
     assert rel(n(phi, g.shape), poisson.solve(g, rhs)) < 1e-11
 
 
-@pytest.mark.parametrize("shape", [(16, 8, 512), (24, 6, 1024)])
+@pytest.mark.parametrize("shape", [(16, 8, 512), (24, 6, 1024), (16, 192, 16)])
 def test_poisson_refined_long_z(shape):
-    """The FP32 length-512 and -1024 z transforms inside the refined mixed
-    solve: the refined result agrees with the FP64 oracle solve."""
+    """The FP32 length-512 and -1024 z transforms, and the wall-normal solve
+    of an FP32 spectrum in 32 equal segments, inside the refined mixed solve:
+    the refined result agrees with the FP64 oracle solve."""
     import workloads
     nx, ny, nz = shape
     wl = workloads.Workload("paths", nx, ny, nz, 2 * np.pi, np.pi, workloads.tanh_faces(ny),
