@@ -589,7 +589,7 @@ constexpr int X16_INV_NE = (2 * X16_SC * X16_LDX_MAX + 32 * X16_SC - 1) / (32 * 
 // are template arguments, so the loads of successive rows are in flight
 // together instead of each row waiting first for its mask word.  PQ: 0 no
 // energy shape, 1 p in FP64, 2 p in FP32.
-template <typename C, bool CB, int PQ>
+template <typename C, bool CB, int PQ, bool KEEP>
 __device__ __forceinline__ void fftx256_stage_vel(const PoisK<C>& K, typename RealOf<C>::T* tr,
                                                   int64_t row0, int nr, int j00, int k00,
                                                   double q, double q1, int ss) {
@@ -647,9 +647,78 @@ __device__ __forceinline__ void fftx256_stage_vel(const PoisK<C>& K, typename Re
     }
     double val = (D - qq) * K.inv_adt;
     if (CB && ((MW[t] >> (uint32_t)(cell & 31)) & 1u)) val = 0.0;
+    // the FP64 copy a refinement reads (a template option: a global store
+    // that may alias the velocity would hold back the next batch's loads)
+    if (KEEP && r < nr) K.rhs_keep[cell] = val;
     if (r >= nr) val = 0.0;
     tr[2 * ((r >> 1) * ss + i) + (r & 1)] = (R)val;
   }
+  }
+}
+
+// Residual source of the length-256 forward x transform (the SRC_RESIDUAL
+// and SRC_CHECK cases of fftx_source, same arithmetic): r = rhs - L_c phi
+// for the block's rows, thread i forming value i of every row, with max|r|
+// and the sum of phi dy accumulated.  Every load of a row (rhs, phi and its
+// six neighbours; at a wall the cell's own value stands in for the missing
+// plane and its term is dropped afterwards) is issued before the row is
+// formed.  Rows past nr take the block's first row, stored as 0.
+template <typename C>
+__device__ __forceinline__ void fftx256_stage_res(const PoisK<C>& K, typename RealOf<C>::T* tr,
+                                                  int64_t row0, int nr, int j00, int k00,
+                                                  double& rmax, double& vsum, int ss) {
+  using R = typename RealOf<C>::T;
+  const GridView& g = K.g;
+  constexpr int nx = 256;
+  const int i = threadIdx.x, nz = g.nz;
+  const int64_t plane = (int64_t)nz * nx;
+  const int im = (i - 1) & (nx - 1), ip = (i + 1) & (nx - 1);
+  const double* __restrict__ f = K.phi_in;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int rv = r < nr ? r : 0;
+    const unsigned kk = (unsigned)(k00 + rv);
+    const unsigned jq = kk / (unsigned)nz;
+    const int j = j00 + (int)jq, k = (int)(kk - jq * (unsigned)nz);
+    const int km = (k == 0) ? nz - 1 : k - 1;
+    const int kp = (k + 1 == nz) ? 0 : k + 1;
+    const int64_t row = (int64_t)(row0 + rv) * nx;
+    const int64_t cell = row + i;
+    const bool hs = j > 0, hn = j + 1 < g.ny;
+    const double b = K.rhs[cell];
+    const double fc = f[cell], fw = f[row + im], fe = f[row + ip];
+    const double fb = f[cell + (int64_t)(km - k) * nx], ft = f[cell + (int64_t)(kp - k) * nx];
+    const double fsv = f[hs ? cell - plane : cell], fnv = f[hn ? cell + plane : cell];
+    const double icj = g.idyc[j], icn = g.idyc[j + 1], iyj = g.idy[j], dyj = g.dy[j];
+    const double gx0 = (fc - fw) * g.idx, gx1 = (fe - fc) * g.idx;
+    const double gz0 = (fc - fb) * g.idz, gz1 = (ft - fc) * g.idz;
+    const double fs = hs ? (fc - fsv) * icj : 0.0;
+    const double fn = hn ? (fnv - fc) * icn : 0.0;
+    const double val = b - ((gx1 - gx0) * g.idx + (gz1 - gz0) * g.idz + (fn - fs) * iyj);
+    if (r < nr) {
+      rmax = fmax(rmax, fabs(val));
+      vsum += fc * dyj;
+      if (K.rhs_keep) K.rhs_keep[cell] = val;
+    }
+    tr[2 * ((r >> 1) * ss + i) + (r & 1)] = (R)(r < nr ? val : 0.0);
+  }
+}
+
+// the velocity staging for the uniform options of a launch
+template <typename C, bool KEEP>
+__device__ __forceinline__ void fftx256_stage_vel_any(const PoisK<C>& K,
+                                                      typename RealOf<C>::T* tr, int64_t row0,
+                                                      int nr, int j00, int k00, double q,
+                                                      double q1) {
+  const int pqm = K.pq ? (K.pq32 ? 2 : 1) : 0;
+  if (K.cb_mask) {
+    if (pqm == 0) fftx256_stage_vel<C, true, 0, KEEP>(K, tr, row0, nr, j00, k00, q, q1, X16_SS);
+    else if (pqm == 1) fftx256_stage_vel<C, true, 1, KEEP>(K, tr, row0, nr, j00, k00, q, q1, X16_SS);
+    else fftx256_stage_vel<C, true, 2, KEEP>(K, tr, row0, nr, j00, k00, q, q1, X16_SS);
+  } else {
+    if (pqm == 0) fftx256_stage_vel<C, false, 0, KEEP>(K, tr, row0, nr, j00, k00, q, q1, X16_SS);
+    else if (pqm == 1) fftx256_stage_vel<C, false, 1, KEEP>(K, tr, row0, nr, j00, k00, q, q1, X16_SS);
+    else fftx256_stage_vel<C, false, 2, KEEP>(K, tr, row0, nr, j00, k00, q, q1, X16_SS);
   }
 }
 
@@ -674,17 +743,17 @@ __global__ __launch_bounds__(32 * X16_SC) void k_fftx256_fwd(PoisK<C> K) {
   // arithmetic: ny nz < 2^31)
   const int j00 = (int)(row0 / g.nz), k00 = (int)(row0 - (int64_t)j00 * g.nz);
   static_assert(32 * X16_SC == 256 && 2 * X16_SC == 16, "one thread per x index, 16 rows");
-  if (K.mode == SRC_VELOCITY && !K.rhs_keep) {
-    const int pqm = K.pq ? (K.pq32 ? 2 : 1) : 0;
-    if (K.cb_mask) {
-      if (pqm == 0) fftx256_stage_vel<C, true, 0>(K, tr, row0, nr, j00, k00, q, q1, X16_SS);
-      else if (pqm == 1) fftx256_stage_vel<C, true, 1>(K, tr, row0, nr, j00, k00, q, q1, X16_SS);
-      else fftx256_stage_vel<C, true, 2>(K, tr, row0, nr, j00, k00, q, q1, X16_SS);
-    } else {
-      if (pqm == 0) fftx256_stage_vel<C, false, 0>(K, tr, row0, nr, j00, k00, q, q1, X16_SS);
-      else if (pqm == 1) fftx256_stage_vel<C, false, 1>(K, tr, row0, nr, j00, k00, q, q1, X16_SS);
-      else fftx256_stage_vel<C, false, 2>(K, tr, row0, nr, j00, k00, q, q1, X16_SS);
-    }
+  // (refinement passes run on FP32 spectra only; an FP64 kernel meeting one
+  // takes the generic loop below)
+  if (K.mode >= SRC_RESIDUAL && sizeof(C) == sizeof(float2)) {
+    if constexpr (sizeof(C) == sizeof(float2))
+      fftx256_stage_res<C>(K, tr, row0, nr, j00, k00, rmax, vsum, X16_SS);
+  } else if (K.mode == SRC_VELOCITY && !K.rhs_keep) {
+    fftx256_stage_vel_any<C, false>(K, tr, row0, nr, j00, k00, q, q1);
+  } else if (K.mode == SRC_VELOCITY && sizeof(C) == sizeof(float2)) {
+    // the first pass of a refined solve (FP32 spectrum) keeps its source
+    if constexpr (sizeof(C) == sizeof(float2))
+      fftx256_stage_vel_any<C, true>(K, tr, row0, nr, j00, k00, q, q1);
   } else
 #pragma unroll 4
   for (int e = threadIdx.x; e < 2 * X16_SC * 256; e += blockDim.x) {

@@ -179,3 +179,25 @@ def test_mixed_step_against_fp64_oracle(name, steps, mixed_poisson):
     def centred(a):
         return a[~mB] - np.sum(a[~mB] * dV[~mB]) / np.sum(dV[~mB])
     assert rel(centred(got), centred(p)) < 1e-5
+
+
+def test_mixed_refined_step_x256():
+    """The refined mixed step on x lines of 256 cells, where the length-256 x
+    transforms run on the FP32 spectrum: the velocity source, kept in FP64
+    for the refinement, and the residual passes are formed by their
+    branch-free row stagings.  A sphere in the channel, two steps: velocity
+    within 1e-6 of the FP64 oracle, post-projection divergence below 1e-10,
+    the refinement reaching its tolerance."""
+    import workloads
+    d = 2.0 / 12
+    wl = workloads.Workload("x256", 256, 12, 16, 256 * d, 16 * d, workloads.uniform_faces(12),
+                            100.0, 1e-3, 2, 1.0, 0.01, 17, -0.02,
+                            [workloads._sphere_body(2, 0.3, (128 * d, 0.0, 8 * d),
+                                                    (0.2, 0.05, -0.1))])
+    case, g, dv, pd, f, p, tags, worst_div = _run_mixed(wl, 2, "refined")
+    _tags_equal(case, tags)
+    for c in range(3):
+        assert rel(n(dv[c], f[c].shape), f[c]) < 1e-6, c
+    assert worst_div < 1e-10
+    solves, corr, final = case.ibm.ibm_refine_stats(case.ctx)
+    assert solves == 4 and final <= 1e-11
