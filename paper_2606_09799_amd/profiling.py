@@ -13,8 +13,8 @@ The copy reference is the plain device copy that bench.py runs with
 what each counter reports for it scales the counter for every kernel.
 
     python -m paper_2606_09799_amd.profiling --tag c2_fp64 \\
-        --trace gpurun_out/trace_c2 --fetch gpurun_out/pmc_fetch \\
-        --write gpurun_out/pmc_write --copy-mib 1024 \\
+        --trace out/trace_fp64 --fetch out/fetch_fp64 \\
+        --write out/write_fp64 --copy-mib 1024 \\
         --trace-cmd "<bench.py args>" --pmc-cmd "<bench.py args>"
 """
 from __future__ import annotations
