@@ -122,9 +122,8 @@ def conv_v(g, u, v, w):
     """H for the y-momentum at interior v nodes; wall planes are zero."""
     ny = g.ny
     out = np.zeros_like(v)
-    d0, d1 = _col(g.dy[:-1]), _col(g.dy[1:])
-    uy = (u[:-1] * d1 + u[1:] * d0) / (d0 + d1)        # u at faces 1..ny-1
-    wy = (w[:-1] * d1 + w[1:] * d0) / (d0 + d1)        # w at faces 1..ny-1
+    uy = _to_faces(g, u)[1:ny]                         # u at faces 1..ny-1
+    wy = _to_faces(g, w)[1:ny]                         # w at faces 1..ny-1
     vi = v[1:ny]
     fx = xp(uy) * (0.5 * (vi + xp(vi)))                # (u v) at x=(i+1)dx
     tx = (fx - xm(fx)) / g.dx
