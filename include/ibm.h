@@ -52,9 +52,15 @@ extern "C" {
 #define IBM_EHIP (-3)      /* HIP runtime error; text in ibm_strerror */
 #define IBM_ECAPACITY (-4) /* forcing list or C_B list overflowed */
 #define IBM_ENONFINITE (-5)
+#define IBM_ECFL (-6)      /* a body vertex moves more than half the local
+                              spacing in one step (device flag
+                              IBM_FLAG_CFL) */
 #define IBM_EGEOM (-7)     /* body too large for the periodic box, probe
                               leaving the channel, or a probe stencil that
                               contains its own forcing node */
+#define IBM_ECOMPAT (-8)   /* a Poisson right-hand side that fails the
+                              compatibility condition (device flag
+                              IBM_FLAG_COMPAT) */
 
 /* sticky device flags returned by ibm_check */
 #define IBM_FLAG_CAPACITY 1u
@@ -62,6 +68,15 @@ extern "C" {
 #define IBM_FLAG_GEOM 4u
 #define IBM_FLAG_REFINE 8u /* mixed form: a Poisson solve ended above the
                               refinement tolerance after refine_max steps */
+#define IBM_FLAG_CFL 16u   /* ibm_step: over dt a body vertex moves more
+                              than half the local spacing along an axis
+                              (|U_x| dt > dx/2, |U_z| dt > dz/2 or |U_y| dt >
+                              dy/2 of the cell the vertex lies in): the
+                              one-layer fresh-cell treatment of Sec. 3.1
+                              needs less */
+#define IBM_FLAG_COMPAT 32u /* poisson_solve: |sum rhs dV| > 1e-12 sum |rhs|
+                               dV, so Eq. elliptic_mod has no solution (the
+                               solve still returns the gauged field) */
 
 #define IBM_FP64 0
 #define IBM_MIXED 1
@@ -185,7 +200,9 @@ int ibm_body_deform(ibm_ctx* ctx, const double* data, int32_t nv, const double* 
  * the classifying triangle of least |N|^2, ties to the lowest id.  The
  * decision uses IEEE binary64 +,-,*,/ in a fixed order (no FMA), so results
  * are exact integers independent of scheduling.  Also stores the bodies for
- * the following ibm_force / ibm_step calls.  out may be NULL. */
+ * the following ibm_force / ibm_step calls.  out may be NULL.  (ibm_tag has
+ * no time step, so the displacement check of IBM_FLAG_CFL runs only inside
+ * ibm_step.) */
 int ibm_tag(ibm_ctx* ctx, const ibm_body* bodies, int32_t nbody, ibm_tags* out);
 /* Synchronises and copies the four counts (u, v, w, C_B) to the host. */
 int ibm_tags_count_host(ibm_ctx* ctx, int64_t* counts);
@@ -232,7 +249,11 @@ int ibm_mass_rhs(ibm_ctx* ctx, const double* u, const double* v, const double* w
  * with homogeneous Neumann walls): real FFT in x, complex FFT in z,
  * tridiagonal solve in y per Fourier mode.  The singular (0,0) mode is fixed
  * by phi_0 = 0 and the result is shifted to zero volume-weighted mean.
- * rhs, phi: dev f64 ny*nz*nx (may alias).  Mixed form: the transforms run
+ * rhs, phi: dev f64 ny*nz*nx (may alias).  The compatibility condition of
+ * the Neumann problem (App. A: sum rhs dV = 0) is checked first with two
+ * fixed-order device sums; |sum rhs dV| > 1e-12 sum |rhs| dV raises
+ * IBM_FLAG_COMPAT (read by ibm_check; no synchronisation here).  Mixed form:
+ * the transforms run
  * in FP32 and the result is refined, phi += S(rhs - L_c phi) with the
  * residual in FP64, until max|rhs - L_c phi| <= refine_tol or refine_max
  * refinements; the stopping test runs on the device (no synchronisation),
@@ -277,7 +298,12 @@ int ibm_project(ibm_ctx* ctx, const double* phi, double alpha_dt, double* u,
 /* One whole time step of the scheme (paper Sec. 2 and Sec. 3): tags the
  * bodies at t^n once, then for every sub-stage: IB forcing, predictor,
  * consistent mass correction, Poisson solve, projection and pressure update.
- * The bodies stay at t^n for all sub-stages. */
+ * The bodies stay at t^n for all sub-stages.  The tagging also raises
+ * IBM_FLAG_CFL when a vertex velocity carries the vertex more than half the
+ * local spacing in dt.  A dt not seen before has its line-solve tables
+ * computed on the host and copied in stream order from pinned staging (no
+ * synchronisation; the host waits only if the stream is four such changes
+ * behind). */
 int ibm_step(ibm_ctx* ctx, ibm_state* s, const ibm_body* bodies, int32_t nbody,
              double dt);
 
@@ -329,8 +355,9 @@ ibm_ctx* ibm_batch_context(ibm_batch* b, int32_t sim);
  * plan's stream groups and tile choice); the first graph call for a dt
  * captures the graph (a change of dt or of plan drops it).  Results are identical in every mode and to ibm_step run on
  * each simulation alone.  The first call for a dt synchronises once (line
- * tables); later calls only enqueue, except that the host waits when the
- * coefficient staging ring (4 slots) is full. */
+ * tables, waiting for any earlier step before a captured graph is dropped);
+ * later calls only enqueue, except that the host waits when the coefficient
+ * staging ring (4 slots) is full. */
 int ibm_batch_step(ibm_batch* b, const double* coef, double dt, int32_t mode);
 /* Synchronise and return (and clear) the OR of every simulation's flags. */
 int ibm_batch_check(ibm_batch* b, uint32_t* flags);
@@ -360,15 +387,18 @@ int ibm_batch_get_plan(ibm_batch* b, ibm_batch_plan* plan);
  * coordinate search over streams in {1, 2, 4, ..., nsim}, then rhs_planes in
  * {16, 48, 8, 4}, then graph vs eager streams), `steps` timed steps each after
  * one untimed step, all with the body coefficients `coef` and step dt.  The
- * simulations' states (u, v, w, p and, for AB2, h) are saved first and
- * restored after every trial, so tuning leaves them as they were; the
- * snapshot is device memory allocated and freed inside the call.  Applies
- * the fastest plan and returns it in *best; if table is not NULL, up to
+ * simulations' states (u, v, w, p and, for AB2, h) are saved first into
+ * `scratch` (dev, 256-byte aligned, at least ibm_batch_tune_scratch_bytes
+ * bytes, owned by the caller; IBM_EINVAL otherwise) and restored after every
+ * trial, so tuning leaves them as they were; the library allocates nothing.
+ * Every stream of the batch is idle whenever a plan is applied.  Applies the
+ * fastest plan and returns it in *best; if table is not NULL, up to
  * max_entries tried plans (with their times) are written there and *n_tried
  * gets their count.  Synchronises. */
-int ibm_batch_tune(ibm_batch* b, const double* coef, double dt, int32_t steps,
-                   ibm_batch_plan* best, ibm_batch_plan* table, int32_t max_entries,
-                   int32_t* n_tried);
+int64_t ibm_batch_tune_scratch_bytes(ibm_batch* b);
+int ibm_batch_tune(ibm_batch* b, const double* coef, double dt, int32_t steps, void* scratch,
+                   int64_t scratch_bytes, ibm_batch_plan* best, ibm_batch_plan* table,
+                   int32_t max_entries, int32_t* n_tried);
 
 /* Mixed form: synchronise and copy the refinement statistics since the
  * last reset to stats (host double[4]): Poisson solves, FP64-residual

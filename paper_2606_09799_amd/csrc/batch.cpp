@@ -141,6 +141,11 @@ static int enqueue(ibm_batch* b, double dt, bool serial) {
 // deal the simulations (largest first) to the plan's stream groups and point
 // each context at its group's stream; set the RHS tile of every context
 static void apply_plan(ibm_batch* b, const ibm_batch_plan& p) {
+  // no work of the batch may still run when the contexts change streams and
+  // the graph goes: wait for the batch's own stream and every group stream
+  if (b->own) (void)hipStreamSynchronize(b->own);
+  for (hipStream_t s : b->sstream)
+    if (s) (void)hipStreamSynchronize(s);
   drop_graph(b);
   b->plan = p;
   for (int r = 0; r < b->n; ++r) b->grp[b->order[r]] = r % p.streams;
@@ -237,10 +242,12 @@ int ibm_batch_step(ibm_batch* b, const double* coef, double dt, int32_t mode) {
     return ctx_fail(IBM_EINVAL, "ibm_batch_step: bad argument");
   if (mode == IBM_BATCH_PLAN) mode = b->plan.mode;
   if (dt != b->prep_dt) {
-    // tables and body descriptors for this dt, outside any capture
-    drop_graph(b);
+    // tables and body descriptors for this dt, outside any capture; a graph
+    // launched by an earlier step may still run on b->own: wait for it
+    // before its executable is destroyed
     BCHK(hipStreamSynchronize(b->stream));
     BCHK(hipStreamSynchronize(b->own));
+    drop_graph(b);
     for (int s = 0; s < b->n; ++s) {
       const int rc = ctx_prepare(b->ctx[s], &b->body[s], 1, dt);
       if (rc) return rc;
@@ -301,19 +308,14 @@ int ibm_batch_get_plan(ibm_batch* b, ibm_batch_plan* plan) {
   return IBM_OK;
 }
 
-int ibm_batch_tune(ibm_batch* b, const double* coef, double dt, int32_t steps,
-                   ibm_batch_plan* best, ibm_batch_plan* table, int32_t max_entries,
-                   int32_t* n_tried) {
-  if (!b || !coef || !best || !(dt > 0) || steps < 1 || steps > 1000 ||
-      (table && max_entries < 0))
-    return ctx_fail(IBM_EINVAL, "ibm_batch_tune: bad argument");
-  // snapshot of every simulation's state: u, v, w, p and the AB2 H arrays
-  struct Arr {
-    void* p;
-    size_t bytes;
-    size_t off;
-  };
-  std::vector<Arr> arrs;
+// the arrays of every simulation's state (u, v, w, p and the AB2 H arrays)
+// and their offsets in a snapshot buffer (256-byte aligned pieces)
+struct SnapArr {
+  void* p;
+  size_t bytes;
+  size_t off;
+};
+static size_t snapshot_layout(ibm_batch* b, std::vector<SnapArr>* arrs) {
   size_t total = 0;
   for (int s = 0; s < b->n; ++s) {
     int64_t nc = 0, nv = 0;
@@ -323,7 +325,7 @@ int ibm_batch_tune(ibm_batch* b, const double* coef, double dt, int32_t steps,
     auto add = [&](void* p, size_t bytes) {
       if (!p) return;
       total = (total + 255) / 256 * 256;
-      arrs.push_back({p, bytes, total});
+      if (arrs) arrs->push_back({p, bytes, total});
       total += bytes;
     };
     add(st.u, 8 * (size_t)nc);
@@ -332,16 +334,35 @@ int ibm_batch_tune(ibm_batch* b, const double* coef, double dt, int32_t steps,
     add(st.p, (size_t)pb * nc);
     for (int q = 0; q < 3; ++q) add(st.h[q], (size_t)pb * (q == 1 ? nv : nc));
   }
+  return total;
+}
+
+int64_t ibm_batch_tune_scratch_bytes(ibm_batch* b) {
+  if (!b) return ctx_fail(IBM_EINVAL, "ibm_batch_tune_scratch_bytes: null batch");
+  return (int64_t)snapshot_layout(b, nullptr);
+}
+
+int ibm_batch_tune(ibm_batch* b, const double* coef, double dt, int32_t steps, void* scratch,
+                   int64_t scratch_bytes, ibm_batch_plan* best, ibm_batch_plan* table,
+                   int32_t max_entries, int32_t* n_tried) {
+  if (!b || !coef || !best || !(dt > 0) || steps < 1 || steps > 1000 ||
+      (table && max_entries < 0))
+    return ctx_fail(IBM_EINVAL, "ibm_batch_tune: bad argument");
+  std::vector<SnapArr> arrs;
+  const size_t total = snapshot_layout(b, &arrs);
+  if (!scratch || scratch_bytes < 0 || (size_t)scratch_bytes < total ||
+      ((uintptr_t)scratch & 255u) != 0)
+    return ctx_fail(IBM_EINVAL, "ibm_batch_tune: scratch missing, unaligned or smaller than "
+                                "ibm_batch_tune_scratch_bytes");
   BCHK(hipStreamSynchronize(b->stream));
   BCHK(hipStreamSynchronize(b->own));
-  char* snap = nullptr;
-  BCHK(hipMalloc(&snap, total ? total : 1));
+  char* snap = static_cast<char*>(scratch);
   hipEvent_t t0 = nullptr, t1 = nullptr;
   int rc = IBM_OK;
   const ibm_batch_plan start = b->plan;
   std::vector<ibm_batch_plan> tried;
   auto copy_all = [&](bool save) -> int {
-    for (const Arr& a : arrs) {
+    for (const SnapArr& a : arrs) {
       hipError_t e = save ? hipMemcpyAsync(snap + a.off, a.p, a.bytes, hipMemcpyDeviceToDevice, b->own)
                           : hipMemcpyAsync(a.p, snap + a.off, a.bytes, hipMemcpyDeviceToDevice, b->own);
       if (e != hipSuccess) return ctx_fail(IBM_EHIP, "ibm_batch_tune: state copy failed");
@@ -416,7 +437,6 @@ int ibm_batch_tune(ibm_batch* b, const double* coef, double dt, int32_t steps,
   } while (false);
   // restore the states and apply the winner (or the starting plan on failure)
   const int rc2 = copy_all(false);
-  (void)hipFree(snap);
   if (t0) (void)hipEventDestroy(t0);
   if (t1) (void)hipEventDestroy(t1);
   if (rc) {

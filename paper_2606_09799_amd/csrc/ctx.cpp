@@ -121,11 +121,18 @@ struct ibm_ctx {
   double* diag = nullptr;  // per-component no-slip errors (3)
   uint32_t* flags = nullptr;
 
-  // line-solve tables for one beta
+  // line-solve tables for one beta; a new beta is staged through a ring of
+  // pinned host slots and copied in stream order (no synchronisation)
   double tab_beta = -1.0;
   double* tabmem = nullptr;
   float* tabmem32 = nullptr;
   int64_t tabcap = 0;
+  static constexpr int NTSTAGE = 4;
+  double* tab_host[NTSTAGE] = {};
+  float* tab_host32[NTSTAGE] = {};
+  hipEvent_t tab_ev[NTSTAGE] = {};
+  bool tab_used[NTSTAGE] = {};
+  int tab_stage = 0;
   CyclicTab ctx_x{}, ctx_z{};
   YTab yt[2]{};  // 0: u and w, 1: v
 
@@ -166,22 +173,6 @@ static int upload(ibm_ctx* c, T* dst, const std::vector<T>& src) {
   HIPCHK(hipMemcpy(dst, src.data(), src.size() * sizeof(T), hipMemcpyHostToDevice));
   (void)c;
   return IBM_OK;
-}
-
-static bool plan_fft(int n, FFTPlan* P) {
-  P->n = n;
-  P->nst = 0;
-  int m = n;
-  const int radices[5] = {4, 2, 3, 5, 7};
-  for (int r : radices) {
-    while (m % r == 0) {
-      if (r == 2 && m % 4 == 0) break;
-      if (P->nst >= 16) return false;
-      P->radix[P->nst++] = r;
-      m /= r;
-    }
-  }
-  return m == 1;
 }
 
 static int make_twiddles(ibm_ctx* c, FFTPlan* P) {
@@ -337,14 +328,23 @@ static int build_tables(ibm_ctx* c, double beta) {
     g_last_error = "line-solve tables exceed their buffer";
     return IBM_EINVAL;
   }
-  // the tables are read by kernels already enqueued: order the update on the
-  // stream, and keep the host copy alive until it has been consumed
-  HIPCHK(hipStreamSynchronize(c->stream));
-  HIPCHK(hipMemcpy(c->tabmem, h.data(), h.size() * sizeof(double), hipMemcpyHostToDevice));
+  // kernels already enqueued read the previous tables: the new ones are
+  // copied in stream order, after them, from a pinned staging slot that is
+  // rewritten only once its previous copy has completed (the host waits only
+  // if the stream is four table changes behind)
+  const int ks = c->tab_stage;
+  c->tab_stage = (ks + 1) % ibm_ctx::NTSTAGE;
+  if (c->tab_used[ks]) HIPCHK(hipEventSynchronize(c->tab_ev[ks]));
+  std::memcpy(c->tab_host[ks], h.data(), h.size() * sizeof(double));
+  HIPCHK(hipMemcpyAsync(c->tabmem, c->tab_host[ks], h.size() * sizeof(double),
+                        hipMemcpyHostToDevice, c->stream));
   if (c->fp32) {  // the same tables rounded to FP32, at the same offsets
-    std::vector<float> h32(h.begin(), h.end());
-    HIPCHK(hipMemcpy(c->tabmem32, h32.data(), h32.size() * sizeof(float), hipMemcpyHostToDevice));
+    for (size_t q = 0; q < h.size(); ++q) c->tab_host32[ks][q] = (float)h[q];
+    HIPCHK(hipMemcpyAsync(c->tabmem32, c->tab_host32[ks], h.size() * sizeof(float),
+                          hipMemcpyHostToDevice, c->stream));
   }
+  HIPCHK(hipEventRecord(c->tab_ev[ks], c->stream));
+  c->tab_used[ks] = true;
   int64_t off = 0;
   auto take = [&](int n) {
     const int64_t o = off;
@@ -379,6 +379,14 @@ static void free_all(ibm_ctx* c) {
   c->allocs.clear();
   if (c->hslots) (void)hipHostFree(c->hslots);
   c->hslots = nullptr;
+  for (int k = 0; k < ibm_ctx::NTSTAGE; ++k) {
+    if (c->tab_host[k]) (void)hipHostFree(c->tab_host[k]);
+    if (c->tab_host32[k]) (void)hipHostFree(c->tab_host32[k]);
+    if (c->tab_ev[k]) (void)hipEventDestroy(c->tab_ev[k]);
+    c->tab_host[k] = nullptr;
+    c->tab_host32[k] = nullptr;
+    c->tab_ev[k] = nullptr;
+  }
   for (auto& e : c->slot_ev)
     if (e) (void)hipEventDestroy(e);
   for (auto& r : c->prof.recs) {
@@ -398,6 +406,9 @@ const char* ibm_strerror(int code) {
     case IBM_EHIP: return g_last_error.empty() ? "HIP runtime error" : g_last_error.c_str();
     case IBM_ECAPACITY: return "forcing-node or boundary-cell list overflowed its capacity";
     case IBM_ENONFINITE: return "non-finite value in a reduction";
+    case IBM_ECFL: return "a body vertex moves more than half the local grid spacing in one step";
+    case IBM_ECOMPAT: return "Poisson right-hand side fails the compatibility condition "
+                             "(|sum rhs dV| > 1e-12 sum |rhs| dV)";
     case IBM_EGEOM: return "geometry limit: body too large for the periodic box, probe leaving "
                            "the channel, or probe stencil containing its own node";
     default: return "unknown error";
@@ -595,6 +606,18 @@ int ibm_create(const ibm_grid* gr, const ibm_opts* o, void* stream, ibm_ctx** ou
     c->tabcap = 4 * (int64_t)(nx + nz) + 10 * (int64_t)ny + LINE_NTAB * (int64_t)segs * LINE_LMAX;
     TRY(dalloc(c, &c->tabmem, c->tabcap));
     if (c->fp32) TRY(dalloc(c, &c->tabmem32, c->tabcap));
+    for (int k = 0; k < ibm_ctx::NTSTAGE; ++k) {
+      if (hipHostMalloc((void**)&c->tab_host[k], sizeof(double) * c->tabcap) != hipSuccess) {
+        c->tab_host[k] = nullptr;
+        TRY(IBM_ENOMEM);
+      }
+      if (c->fp32 &&
+          hipHostMalloc((void**)&c->tab_host32[k], sizeof(float) * c->tabcap) != hipSuccess) {
+        c->tab_host32[k] = nullptr;
+        TRY(IBM_ENOMEM);
+      }
+      if (hipEventCreateWithFlags(&c->tab_ev[k], hipEventDisableTiming) != hipSuccess) TRY(IBM_EHIP);
+    }
   }
 
   // Poisson tables
@@ -734,14 +757,16 @@ static int upload_bodies(ibm_ctx* c) {
 
 extern "C" {
 
-int ibm_tag(ibm_ctx* c, const ibm_body* b, int32_t nb, ibm_tags* out) {
-  if (!c) FAIL(IBM_EINVAL, "null context");
+}  // extern "C"
+
+// tagging; dt > 0 also checks the vertex displacement over dt (FLAG_CFL)
+static int tag_bodies(ibm_ctx* c, const ibm_body* b, int32_t nb, ibm_tags* out, double dt) {
   int rc = set_bodies(c, b, nb);
   if (rc) return rc;
   rc = upload_bodies(c);
   if (rc) return rc;
   launch_tag(&c->prof, c->stream, c->g, c->d_bodies, (int)c->bodies.size(), c->ntri, c->tb,
-             c->flags);
+             c->flags, dt);
   rc = launch_status();
   if (rc) return rc;
   if (out) {
@@ -756,6 +781,13 @@ int ibm_tag(ibm_ctx* c, const ibm_body* b, int32_t nb, ibm_tags* out) {
     out->capacity = c->tb.cap;
   }
   return IBM_OK;
+}
+
+extern "C" {
+
+int ibm_tag(ibm_ctx* c, const ibm_body* b, int32_t nb, ibm_tags* out) {
+  if (!c) FAIL(IBM_EINVAL, "null context");
+  return tag_bodies(c, b, nb, out, 0.0);
 }
 
 int ibm_tags_count_host(ibm_ctx* c, int64_t* counts) {
@@ -880,6 +912,7 @@ static PoissonArgs pargs(ibm_ctx* c) {
 
 int poisson_solve(ibm_ctx* c, const double* rhs, double* phi) {
   if (!c || !rhs || !phi) FAIL(IBM_EINVAL, "poisson_solve: bad argument");
+  launch_compat(&c->prof, c->stream, c->g, rhs, c->partial, c->flags);
   launch_poisson(&c->prof, c->stream, c->g, pargs(c), rhs, nullptr, nullptr, nullptr, nullptr,
                  nullptr, nullptr, 1.0, phi);
   return launch_status();
@@ -920,7 +953,7 @@ int ibm_project(ibm_ctx* c, const double* phi, double alpha_dt, double* u, doubl
 
 int ibm_step(ibm_ctx* c, ibm_state* s, const ibm_body* b, int32_t nb, double dt) {
   if (!c || !s || !s->u || !s->v || !s->w || !s->p || !(dt > 0)) FAIL(IBM_EINVAL, "ibm_step: bad argument");
-  int rc = ibm_tag(c, b, nb, nullptr);
+  int rc = tag_bodies(c, b, nb, nullptr, dt);
   if (rc) return rc;
   struct Sub {
     double gamma, rho;

@@ -118,6 +118,25 @@ struct FFTPlan {
   const float2* tw32; // the same, rounded to FP32
 };
 
+// Stages of the mixed-radix transforms of length n (radices 4, 2, 3, 5, 7,
+// a 2 only where no 4 remains); false if n has another prime factor.  The
+// twiddle pointers are left to the caller.
+inline bool plan_fft(int n, FFTPlan* P) {
+  P->n = n;
+  P->nst = 0;
+  int m = n;
+  const int radices[5] = {4, 2, 3, 5, 7};
+  for (int r : radices) {
+    while (m % r == 0) {
+      if (r == 2 && m % 4 == 0) break;
+      if (P->nst >= 16) return false;
+      P->radix[P->nst++] = r;
+      m /= r;
+    }
+  }
+  return m == 1;
+}
+
 // blocks of a launch in the XCD slab order (geom.h, xcd_slab_tile): eight
 // bands of ceil(nbz/8) k-tiles, each walked over all ny planes
 inline int64_t xcd_slab_blocks(int nbx, int nbz, int ny) {
@@ -137,7 +156,8 @@ void prof_end(Prof* p, hipStream_t s);
   } while (0)
 
 // sticky flags (same bits as IBM_FLAG_*)
-constexpr uint32_t FLAG_CAPACITY = 1u, FLAG_NONFINITE = 2u, FLAG_GEOM = 4u, FLAG_REFINE = 8u;
+constexpr uint32_t FLAG_CAPACITY = 1u, FLAG_NONFINITE = 2u, FLAG_GEOM = 4u, FLAG_REFINE = 8u,
+                   FLAG_CFL = 16u, FLAG_COMPAT = 32u;
 
 // ------------------------------------------------------------ launchers
 // body.hip
@@ -166,8 +186,10 @@ struct TagBuffers {
   int64_t nwords[3];     // mask words per component
   int64_t nwords_cb;
 };
+// dt > 0: also flags (FLAG_CFL) a vertex whose velocity carries it more than
+// half the local spacing along an axis in dt
 void launch_tag(Prof* pf, hipStream_t s, const GridView& g, const BodyDev* bodies, int nbody,
-                int ntri, TagBuffers& tb, uint32_t* flags);
+                int ntri, TagBuffers& tb, uint32_t* flags, double dt);
 
 // force.hip
 // pressure reconstructed on the boundary cells of tb (p: FP32 when fp32),
@@ -216,6 +238,11 @@ void launch_mass(Prof* pf, hipStream_t s, const GridView& g, const double* u, co
 void launch_mass_rhs(Prof* pf, hipStream_t s, const GridView& g, const double* u, const double* v,
                      const double* w, const uint32_t* cb_mask, const double* qf,
                      double inv_adt, double* rhs);
+
+// compatibility of a Neumann right-hand side: FLAG_COMPAT when
+// |sum rhs dV| > 1e-12 sum |rhs| dV (fixed-order sums; partial: 512 doubles)
+void launch_compat(Prof* pf, hipStream_t s, const GridView& g, const double* rhs,
+                   double* partial, uint32_t* flags);
 
 // mass- and energy-conserving q_F (App. B): qcoef[0..1] = (c0, c1) with
 // q_F = c0 + c1 (p - e); partial: 5 * 512 doubles; p: FP64, or FP32 when fp32

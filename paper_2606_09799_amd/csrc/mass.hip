@@ -260,6 +260,73 @@ void launch_mass_rhs_energy(Prof* pf, hipStream_t s, const GridView& g, const do
                                                                cb_mask, qcoef, inv_adt, rhs)));
 }
 
+// Compatibility of the Neumann problem L_c phi = rhs (paper App. A: with
+// impermeable walls and periodic x, z the discrete divergence theorem makes
+// sum rhs dV vanish for rhs = D u / (alpha dt), the condition for Eq.
+// elliptic_mod to have a solution).  Fixed-order sums S = sum rhs dy[j] and
+// S_abs = sum |rhs| dy[j] (the factor dx dz cancels): block b takes the rows
+// (j, k) of a fixed chunk, its threads stride over x, then fixed trees.
+constexpr int CPB = 256;  // blocks of the first level
+
+__global__ __launch_bounds__(MT) void k_compat_partial(GridView g, const double* __restrict__ rhs,
+                                                       double* __restrict__ partial) {
+  __shared__ double ss[MT], sa[MT];
+  const int64_t rows = (int64_t)g.ny * g.nz;
+  const int64_t chunk = (rows + CPB - 1) / CPB;
+  const int64_t r0 = (int64_t)blockIdx.x * chunk;
+  const int64_t r1 = (r0 + chunk < rows) ? r0 + chunk : rows;
+  double S = 0.0, A = 0.0;
+  for (int64_t r = r0; r < r1; ++r) {
+    const double dyj = g.dy[r / g.nz];
+    const double* row = rhs + r * g.nx;
+    double s = 0.0, a = 0.0;
+    for (int i = threadIdx.x; i < g.nx; i += MT) {
+      s += row[i];
+      a += fabs(row[i]);
+    }
+    S += s * dyj;
+    A += a * dyj;
+  }
+  ss[threadIdx.x] = S;
+  sa[threadIdx.x] = A;
+  __syncthreads();
+  for (int off = MT / 2; off > 0; off >>= 1) {
+    if (threadIdx.x < off) {
+      ss[threadIdx.x] += ss[threadIdx.x + off];
+      sa[threadIdx.x] += sa[threadIdx.x + off];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    partial[2 * blockIdx.x] = ss[0];
+    partial[2 * blockIdx.x + 1] = sa[0];
+  }
+}
+
+__global__ __launch_bounds__(CPB) void k_compat_final(const double* __restrict__ partial,
+                                                      uint32_t* flags) {
+  __shared__ double ss[CPB], sa[CPB];
+  ss[threadIdx.x] = partial[2 * threadIdx.x];
+  sa[threadIdx.x] = partial[2 * threadIdx.x + 1];
+  __syncthreads();
+  for (int off = CPB / 2; off > 0; off >>= 1) {
+    if (threadIdx.x < off) {
+      ss[threadIdx.x] += ss[threadIdx.x + off];
+      sa[threadIdx.x] += sa[threadIdx.x + off];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    if (!(fabs(ss[0]) <= 1e-12 * sa[0])) atomicOr(flags, ss[0] == ss[0] ? FLAG_COMPAT : FLAG_NONFINITE);
+  }
+}
+
+void launch_compat(Prof* pf, hipStream_t s, const GridView& g, const double* rhs,
+                   double* partial, uint32_t* flags) {
+  IBM_LAUNCH(pf, "compat", s, k_compat_partial<<<CPB, MT, 0, s>>>(g, rhs, partial));
+  IBM_LAUNCH(pf, "compat", s, k_compat_final<<<1, CPB, 0, s>>>(partial, flags));
+}
+
 void launch_mass(Prof* pf, hipStream_t s, const GridView& g, const double* u, const double* v,
                  const double* w, const int64_t* cb, const int64_t* count, int64_t cap,
                  double vtot, int use_q, double* partial, double* qf, uint32_t* flags) {

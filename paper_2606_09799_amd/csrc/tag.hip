@@ -25,6 +25,7 @@ struct TagK {
   GridView g;
   const BodyDev* bodies;
   int nbody, ntri, pass;
+  double dt;  // > 0: check the vertex displacement over dt (pass 0)
   uint32_t* mask[3];
   u64* best_d[3];
   int32_t* best_t[3];
@@ -44,6 +45,21 @@ __global__ __launch_bounds__(64) void k_tag_pairs(TagK a) {
   for (int d = 0; d < 3; ++d) {
     lo[d] = fmin(A[d], fmin(B[d], C[d]));
     hi[d] = fmax(A[d], fmax(B[d], C[d]));
+  }
+  // the one-layer fresh-cell assumption (Sec. 3.1): over dt no vertex may
+  // move more than half the local spacing along an axis (the y spacing of the
+  // cell the vertex lies in)
+  if (a.dt > 0.0 && a.pass == 0 && c == 0 && threadIdx.x == 0) {
+    bool over = false;
+    for (int q = 0; q < 3; ++q) {
+      const double* U = vel + 3 * vid[q];
+      const double y = (q == 0) ? A[1] : (q == 1 ? B[1] : C[1]);
+      int j = upper_bound(g.yf, g.ny + 1, y) - 1;
+      j = j < 0 ? 0 : (j > g.ny - 1 ? g.ny - 1 : j);
+      over = over || fabs(U[0]) * a.dt > 0.5 * g.dx || fabs(U[2]) * a.dt > 0.5 * g.dz ||
+             fabs(U[1]) * a.dt > 0.5 * g.dy[j];
+    }
+    if (over) atomicOr(a.flags, FLAG_CFL);
   }
   const Lattice L = lattice(g, c);
   const Box bx = candidate_box(g, L, lo, hi);
@@ -267,7 +283,7 @@ static void compact(Prof* pf, hipStream_t s, CompactSet S, int nl) {
 }
 
 void launch_tag(Prof* pf, hipStream_t s, const GridView& g, const BodyDev* bodies, int nbody,
-                int ntri, TagBuffers& tb, uint32_t* flags) {
+                int ntri, TagBuffers& tb, uint32_t* flags, double dt) {
   {
     int64_t nmax = tb.nwords_cb;
     for (int c = 0; c < 3; ++c) nmax = tb.nwords[c] > nmax ? tb.nwords[c] : nmax;
@@ -290,6 +306,7 @@ void launch_tag(Prof* pf, hipStream_t s, const GridView& g, const BodyDev* bodie
       a.best_t[c] = tb.best_t[c];
     }
     a.flags = flags;
+    a.dt = dt;
     dim3 grid(ntri, 3);
     a.pass = 0;
     IBM_LAUNCH(pf, "tag_pairs", s, k_tag_pairs<<<grid, 64, 0, s>>>(a));

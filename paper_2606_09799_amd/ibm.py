@@ -23,8 +23,9 @@ if not os.path.exists(LIB_PATH):
 _lib = ctypes.CDLL(LIB_PATH)
 
 IBM_OK, IBM_EINVAL, IBM_ENOMEM, IBM_EHIP, IBM_ECAPACITY = 0, -1, -2, -3, -4
-IBM_ENONFINITE, IBM_EGEOM = -5, -7
+IBM_ENONFINITE, IBM_ECFL, IBM_EGEOM, IBM_ECOMPAT = -5, -6, -7, -8
 FLAG_CAPACITY, FLAG_NONFINITE, FLAG_GEOM, FLAG_REFINE = 1, 2, 4, 8
+FLAG_CFL, FLAG_COMPAT = 16, 32
 IBM_FP64, IBM_MIXED = 0, 1
 IBM_RK2CN, IBM_AB2CN = 0, 1
 IBM_Q_NONE, IBM_Q_UNIFORM, IBM_Q_ENERGY = 0, 1, 2
@@ -108,7 +109,9 @@ class IbmBatchPlan(ctypes.Structure):
 _batch_set_plan = _sig("ibm_batch_set_plan", c_int32, c_void_p, POINTER(IbmBatchPlan))
 _batch_get_plan = _sig("ibm_batch_get_plan", c_int32, c_void_p, POINTER(IbmBatchPlan))
 _batch_tune = _sig("ibm_batch_tune", c_int32, c_void_p, POINTER(c_double), c_double, c_int32,
-                   POINTER(IbmBatchPlan), POINTER(IbmBatchPlan), c_int32, POINTER(c_int32))
+                   c_void_p, c_int64, POINTER(IbmBatchPlan), POINTER(IbmBatchPlan), c_int32,
+                   POINTER(c_int32))
+_batch_tune_bytes = _sig("ibm_batch_tune_scratch_bytes", c_int64, c_void_p)
 _check = _sig("ibm_check", c_int32, c_void_p, POINTER(c_uint32))
 _noslip = _sig("ibm_noslip_error", c_int32, c_void_p, c_void_p, c_void_p, c_void_p,
                POINTER(c_double))
@@ -124,6 +127,7 @@ EXPORTS = ("ibm_create", "ibm_destroy", "ibm_set_stream", "ibm_body_rigid", "ibm
            "ibm_check", "ibm_strerror", "ibm_profile", "ibm_profile_read",
            "ibm_batch_create", "ibm_batch_destroy", "ibm_batch_context", "ibm_batch_step",
            "ibm_batch_check", "ibm_batch_set_plan", "ibm_batch_get_plan", "ibm_batch_tune",
+           "ibm_batch_tune_scratch_bytes",
            "ibm_noslip_error", "ibm_pressure_cb")
 COEF_STRIDE = 18
 BATCH_SERIAL, BATCH_STREAMS, BATCH_GRAPH, BATCH_PLAN = 0, 1, 2, 3
@@ -469,15 +473,29 @@ class Batch:
         return {"mode": _MODE_NAMES.get(p.mode, p.mode), "streams": p.streams,
                 "rhs_planes": p.rhs_planes, "ms_per_step": p.ms_per_step}
 
-    def tune(self, coef, dt, steps=3, max_entries=64):
+    def tune_scratch_bytes(self):
+        nb = int(_batch_tune_bytes(self.handle))
+        if nb < 0:
+            _ok(nb, "ibm_batch_tune_scratch_bytes")
+        return nb
+
+    def tune(self, coef, dt, steps=3, max_entries=64, scratch=None):
         """Autotune the execution plan (ibm_batch_tune); the states are left
-        as they were.  Returns (best plan, list of tried plans), as dicts."""
+        as they were.  scratch: a uint8 device tensor of at least
+        tune_scratch_bytes() bytes for the state snapshot (allocated here by
+        torch when None; the library allocates nothing).  Returns (best plan,
+        list of tried plans), as dicts."""
         cf = self._coef(coef)
+        nb = self.tune_scratch_bytes()
+        if scratch is None:
+            scratch = torch.empty(max(nb, 1), dtype=torch.uint8, device=torch.cuda.current_device())
+        ptr = _dev(scratch, torch.uint8, None, "scratch")
         best = IbmBatchPlan()
         table = (IbmBatchPlan * max_entries)()
         ntried = c_int32()
         _ok(_batch_tune(self.handle, cf.ctypes.data_as(POINTER(c_double)), float(dt), int(steps),
-                        ctypes.byref(best), table, max_entries, ctypes.byref(ntried)),
+                        ptr, scratch.numel(), ctypes.byref(best), table, max_entries,
+                        ctypes.byref(ntried)),
             "ibm_batch_tune")
         return self._plan_dict(best), [self._plan_dict(table[k]) for k in range(ntried.value)]
 

@@ -147,3 +147,75 @@ def test_c3_full_size_mixed_against_fp64():
         torch.cuda.empty_cache()
     for c in range(3):
         assert rel(res["mixed"][c], res["fp64"][c]) < 1e-6, c
+
+
+def test_incompatible_poisson_rhs_is_flagged():
+    """poisson_solve checks the compatibility condition of the Neumann
+    problem (App. A: sum rhs dV = 0): a right-hand side with its volume mean
+    removed passes; adding a constant (the mean of |rhs| times 1e-6) makes
+    |sum rhs dV| exceed 1e-12 sum |rhs| dV and raises IBM_FLAG_COMPAT, also
+    on the mixed form's refined solve."""
+    for opts in ({}, {"precision": "mixed", "mixed_poisson": "refined"}):
+        case = Case("tiny", **opts)
+        g = case.g
+        rng = np.random.default_rng(5)
+        r = rng.standard_normal(g.shape)
+        dV = g.cell_volume()
+        r -= np.sum(r * dV) / np.sum(dV)
+        phi = torch.empty(g.cells, dtype=torch.float64, device=DEV)
+        case.ibm.poisson_solve(case.ctx, t(r), phi)
+        assert case.ibm.ibm_check(case.ctx) & case.ibm.FLAG_COMPAT == 0
+        bad = r + 1e-6 * np.mean(np.abs(r))
+        case.ibm.poisson_solve(case.ctx, t(bad), phi)
+        fl = case.ibm.ibm_check(case.ctx)
+        assert fl & case.ibm.FLAG_COMPAT, fl
+        assert torch.isfinite(phi).all().item()
+
+
+def test_body_displacement_over_half_a_cell_is_flagged():
+    """ibm_step flags (IBM_FLAG_CFL) a body whose vertices move more than
+    half the local spacing in one step (the one-layer fresh-cell treatment of
+    Sec. 3.1 needs less): the sphere of the ragged case moved at 0.4 of the
+    x spacing per step passes, at 0.6 of it the flag is raised; the step
+    itself still runs."""
+    for frac, expect in ((0.4, False), (0.6, True)):
+        wl = workloads.config("tiny")
+        b = wl.bodies[0]
+        dx = wl.lx / wl.nx
+        U = np.array([frac * dx / wl.dt, 0.0, 0.0])
+        c0 = np.array([3.0, 0.0, 1.6])
+        wl.bodies = [workloads.Body("rigid", b.ref, b.tris,
+                                    lambda tt, U=U: workloads.sphere_translation(tt, c0, U))]
+        case = Case(wl)
+        bodies, _ = case.bodies_at(0.0)
+        d = [t(a) for a in wl.fields()]
+        pd = torch.zeros(case.g.cells, dtype=torch.float64, device=DEV)
+        case.ibm.ibm_step(case.ctx, *d, pd, bodies, wl.dt)
+        fl = case.ibm.ibm_check(case.ctx)
+        assert bool(fl & case.ibm.FLAG_CFL) == expect, (frac, fl)
+        assert fl & ~case.ibm.FLAG_CFL == 0, fl
+
+
+def test_first_step_at_a_new_dt_needs_no_host_wait():
+    """A new dt rebuilds the line-solve tables on the host and copies them in
+    stream order: steps at dt, 2 dt and back at dt, enqueued with no
+    synchronisation in between, equal the same steps taken one at a time with
+    a synchronisation after each."""
+    case = Case("tiny")
+    wl = case.wl
+    bodies, _ = case.bodies_at(0.0)
+    dts = (wl.dt, 2 * wl.dt, wl.dt, 0.5 * wl.dt)
+    a = [t(x) for x in wl.fields()]
+    pa = torch.zeros(case.g.cells, dtype=torch.float64, device=DEV)
+    for dt in dts:
+        case.ibm.ibm_step(case.ctx, *a, pa, bodies, dt)
+    case2 = Case("tiny")
+    bodies2, _ = case2.bodies_at(0.0)
+    b = [t(x) for x in wl.fields()]
+    pb = torch.zeros(case2.g.cells, dtype=torch.float64, device=DEV)
+    for dt in dts:
+        case2.ibm.ibm_step(case2.ctx, *b, pb, bodies2, dt)
+        torch.cuda.synchronize()
+    assert case.ibm.ibm_check(case.ctx) == 0 and case2.ibm.ibm_check(case2.ctx) == 0
+    for x, y in zip(a + [pa], b + [pb]):
+        assert torch.equal(x, y)

@@ -164,3 +164,46 @@ def test_autotuner_keeps_states_and_results():
             for x, y in zip(a, b):
                 assert np.array_equal(x, y)
         batch.close()
+
+
+def test_autotuner_takes_caller_scratch_and_allocates_nothing():
+    """The tuner's state snapshot lives in a caller buffer: one smaller than
+    ibm_batch_tune_scratch_bytes (or unaligned) is refused with IBM_EINVAL
+    before any work; an exact-size buffer, reused for a second tuning, leaves
+    the states as they were, and a change of dt between the tunings (which
+    drops the captured graph only after the batch's streams are idle) steps
+    like serial mode."""
+    from paper_2606_09799_amd import ibm
+    wls = _small_sims()
+    sims = [_device_sim(wl) for wl in wls]
+    batch = ibm.Batch(sims)
+    dt = wls[0].dt
+    coef = [wl.bodies[0].coef(0.0) for wl in wls]
+    nb = batch.tune_scratch_bytes()
+    expect = 0
+    for d in sims:
+        for key in ("u", "v", "w", "p"):
+            expect = (expect + 255) // 256 * 256 + d[key].numel() * d[key].element_size()
+    assert nb == expect
+    small = torch.empty(nb - 256, dtype=torch.uint8, device=DEV)
+    with pytest.raises(ibm.IbmError) as e:
+        batch.tune(coef, dt, steps=1, scratch=small)
+    assert e.value.code == ibm.IBM_EINVAL
+    scratch = torch.empty(nb, dtype=torch.uint8, device=DEV)
+    before = [_state(d) for d in sims]
+    for step_dt in (dt, 0.5 * dt):
+        batch.tune(coef, step_dt, steps=1, scratch=scratch)
+        for a, b in zip(before, [_state(d) for d in sims]):
+            for x, y in zip(a, b):
+                assert np.array_equal(x, y)
+    batch.step(coef, dt, ibm.BATCH_PLAN)
+    assert batch.check() == 0
+    batch.close()
+    ref_sims = [_device_sim(wl) for wl in wls]
+    ref = ibm.Batch(ref_sims)
+    ref.step(coef, dt, ibm.BATCH_SERIAL)
+    assert ref.check() == 0
+    for a, b in zip([_state(d) for d in ref_sims], [_state(d) for d in sims]):
+        for x, y in zip(a, b):
+            assert np.array_equal(x, y)
+    ref.close()
