@@ -1,0 +1,211 @@
+"""Parity with the CPU oracle on the configurations the small cases do not
+reach: the deforming-body law (host and device-coefficient kernels), the
+tags of the 512x384x512 deforming body and of all 67 bodies of the
+1024x768x1024 workload, a whole step of the 256x192x256 plate workload in FP64
+and in the refined mixed form, and a body fast enough to create fresh cells
+every step (paper Sec. 3.1, Fig. 5).
+
+Bar: tags and body vertices bit-exact; FP64 fields within 1e-10 relative;
+the mixed form within 1e-6 of the FP64 oracle with the post-projection
+divergence D u - q uniform on C_F to 1e-10 (paper Eq. mod_div)."""
+import numpy as np
+import pytest
+import torch
+
+import workloads
+from gpu_harness import Case, DEV, n, rel, t
+from oracle import kinematics, operators as op, projection, step as ostep
+from oracle.grid import Grid
+
+pytestmark = pytest.mark.gpu
+
+
+def _tags_equal(case, tags):
+    lists, cb = case.ibm.tag_lists(case.ctx)
+    for c in range(3):
+        assert np.array_equal(n(lists[c][0]), tags.idx[c]), f"forcing nodes, component {c}"
+        assert np.array_equal(n(lists[c][1]), tags.tri[c]), f"forcing triangles, component {c}"
+    assert np.array_equal(n(cb), tags.cb), "boundary cells"
+
+
+def test_deforming_body_transform_bit_exact():
+    """The deforming law X = c + (r0 + f s) d, U = (f sdot) d of the
+    512x384x512 body (20480 triangles) at several times, host-coefficient
+    kernel against the oracle's transform, bit for bit."""
+    from paper_2606_09799_amd import ibm
+    wl = workloads.config("c3")
+    b = wl.bodies[0]
+    ctx = ibm.Context(32, 16, 32, wl.lx, wl.lz, workloads.uniform_faces(16), wl.re)
+    ref = t(b.ref)
+    nv = b.ref.shape[0]
+    xyz = torch.empty(nv, 3, dtype=torch.float64, device=DEV)
+    vel = torch.empty_like(xyz)
+    for time in (0.0, 0.0137, 0.125, 0.31, 0.6):
+        ibm.ibm_body_deform(ctx, ref, b.coef(time), xyz, vel)
+        X, U = kinematics.body_at(b, time)
+        assert np.array_equal(n(xyz), X), time
+        assert np.array_equal(n(vel), U), time
+    ctx.close()
+
+
+def test_batch_body_kernels_bit_exact():
+    """The batched form's body kernels read their coefficients from device
+    memory: after a batched step at time t every simulation's vertices and
+    velocities equal the oracle's transform at t, bit for bit (a sphere, a
+    plate and a deforming body among them)."""
+    from paper_2606_09799_amd import ibm
+    picks = {}
+    for s in range(64):
+        wl = workloads.batch_sim(s)
+        kind = wl.bodies[0].kind
+        if wl.cells <= 160_000 and kind not in picks:
+            picks[kind] = wl
+        if len(picks) == 2:
+            break
+    wls = list(picks.values())
+    assert {w.bodies[0].kind for w in wls} == {"rigid", "deform"}
+    sims = []
+    for wl in wls:
+        u, v, w = (t(a) for a in wl.fields())
+        b = wl.bodies[0]
+        nv = b.ref.shape[0]
+        sims.append({"nx": wl.nx, "ny": wl.ny, "nz": wl.nz, "lx": wl.lx, "lz": wl.lz,
+                     "y_faces": wl.y_faces, "re": wl.re, "dpdx": wl.dpdx, "u": u, "v": v, "w": w,
+                     "p": torch.zeros(wl.cells, dtype=torch.float64, device=DEV),
+                     "motion": b.kind, "ref": t(b.ref),
+                     "xyz": torch.empty(nv, 3, dtype=torch.float64, device=DEV),
+                     "vel": torch.empty(nv, 3, dtype=torch.float64, device=DEV),
+                     "tri": t(b.tris.astype(np.int32))})
+    batch = ibm.Batch(sims)
+    for time in (0.0, 0.0417):
+        batch.step([wl.bodies[0].coef(time) for wl in wls], wls[0].dt, ibm.BATCH_SERIAL)
+        torch.cuda.synchronize()
+        for wl, d in zip(wls, sims):
+            X, U = kinematics.body_at(wl.bodies[0], time)
+            assert np.array_equal(n(d["xyz"]), X), (wl.name, time)
+            assert np.array_equal(n(d["vel"]), U), (wl.name, time)
+    assert batch.check() == 0
+    batch.close()
+
+
+@pytest.mark.parametrize("time", [0.0, 0.0625])
+def test_c3_deforming_body_tags_bit_exact(time):
+    """512x384x512 stretched channel, the 20480-triangle deforming closed
+    body at two phases of its deformation: forcing lists, forcing triangles
+    and C_B bit-exact."""
+    case = Case("c3", precision="mixed")
+    bodies, (X, U, T) = case.bodies_at(time)
+    case.ibm.ibm_tag(case.ctx, bodies)
+    tags = ostep.compute_tags(case.g, X, T)
+    assert min(tags.counts) > 1000 and len(tags.cb) > 1000
+    _tags_equal(case, tags)
+    assert case.ibm.ibm_check(case.ctx) == 0
+    case.ctx.close()
+
+
+@pytest.mark.parametrize("time", [0.0, 0.05])
+def test_c5_multibody_tags_bit_exact(time):
+    """1024x768x1024 stretched channel with its 67 bodies (64 spheres and
+    three hinged leaflets, 111920 triangles numbered globally across the
+    bodies): forcing lists, forcing triangles and C_B bit-exact at two
+    times."""
+    case = Case("c5", precision="mixed")
+    bodies, (X, U, T) = case.bodies_at(time)
+    assert len(bodies) == 67
+    case.ibm.ibm_tag(case.ctx, bodies)
+    tags = ostep.compute_tags(case.g, X, T)
+    assert max(max(tr) for tr in tags.tri if len(tr)) > 100000   # leaflet triangles take part
+    _tags_equal(case, tags)
+    assert case.ibm.ibm_check(case.ctx) == 0
+    case.ctx.close()
+
+
+@pytest.fixture(scope="module")
+def c2_oracle_step():
+    """One oracle step of the 256x192x256 plate workload from t = 0."""
+    wl = workloads.config("c2")
+    g = Grid(wl.nx, wl.ny, wl.nz, wl.lx, wl.lz, wl.y_faces)
+    f0 = wl.fields()
+    X, U = kinematics.body_at(wl.bodies[0], 0.0)
+    f, p, _, tags = ostep.step(g, f0, np.zeros(g.shape), (X, U, wl.bodies[0].tris), wl.dt,
+                               wl.re, (-wl.dpdx, 0.0, 0.0))
+    return g, f0, f, p, tags
+
+
+def _gpu_c2_step(f0, **opts):
+    case = Case("c2", **opts)
+    bodies, _ = case.bodies_at(0.0)
+    d = [t(a) for a in f0]
+    pd = torch.zeros(case.g.cells, dtype=case.ctx.pdtype, device=DEV)
+    case.ibm.ibm_step(case.ctx, *d, pd, bodies, case.wl.dt)
+    flags = case.ibm.ibm_check(case.ctx)
+    out = [n(x, f0[c].shape) for c, x in enumerate(d)], n(pd).astype(np.float64)
+    case.ctx.close()
+    return out, flags
+
+
+def _centred(g, a, mB):
+    dV = g.cell_volume()
+    return a[~mB] - np.sum(a[~mB] * dV[~mB]) / np.sum(dV[~mB])
+
+
+def test_c2_full_step_fp64(c2_oracle_step):
+    """A whole FP64 step of the 256x192x256 plate workload (two-sided forcing
+    of the zero-thickness plate on the v-node plane, stretched grid): u, v, w
+    within 1e-10 of the oracle, the pressure on C_F (mean removed) too."""
+    g, f0, f, p, tags = c2_oracle_step
+    (u, pg), flags = _gpu_c2_step(f0)
+    assert flags == 0
+    for c in range(3):
+        assert rel(u[c], f[c]) < 1e-10, c
+    mB = projection.cell_mask(g, tags.cb)
+    assert rel(_centred(g, pg.reshape(g.shape), mB), _centred(g, p, mB)) < 1e-10
+
+
+def test_c2_full_step_refined_mixed_against_fp64_oracle(c2_oracle_step):
+    """The same step in the mixed form with FP32 Poisson transforms refined
+    by FP64 residuals: velocity within 1e-6 of the FP64 oracle, and the
+    post-projection divergence uniform on C_F (D u = q_F) to 1e-10."""
+    g, f0, f, p, tags = c2_oracle_step
+    (u, pg), flags = _gpu_c2_step(f0, precision="mixed", mixed_poisson="refined")
+    assert flags == 0
+    for c in range(3):
+        assert rel(u[c], f[c]) < 1e-6, c
+    mB = projection.cell_mask(g, tags.cb)
+    D = op.divergence(g, *u)[~mB]
+    assert np.max(D) - np.min(D) < 2e-10
+
+
+def test_fresh_cells_fast_body():
+    """A sphere crossing 0.4 of the x spacing per step (fresh cells, paper
+    Sec. 3.1 and Fig. 5: nodes uncovered by the moving body rejoin the fluid
+    with the values the forcing gave them), 10 steps on the ragged grid:
+    tags bit-exact at every step and the fields within 1e-10 of the oracle,
+    with no flag raised (the displacement is below half a cell)."""
+    wl = workloads.config("tiny")
+    b = wl.bodies[0]
+    dx = wl.lx / wl.nx
+    U = np.array([0.4 * dx / wl.dt, 0.0, 0.0])
+    c0 = np.array([3.0, 0.05, 1.6])
+    wl.bodies = [workloads.Body("rigid", b.ref, b.tris,
+                                lambda tt: workloads.sphere_translation(tt, c0, U))]
+    case = Case(wl)
+    g = case.g
+    f = wl.fields()
+    d = [t(a) for a in f]
+    pd = torch.zeros(g.cells, dtype=torch.float64, device=DEV)
+    p = np.zeros(g.shape)
+    moved = []
+    for s in range(10):
+        time = s * wl.dt
+        bodies, surf = case.bodies_at(time)
+        case.ibm.ibm_step(case.ctx, *d, pd, bodies, wl.dt)
+        f, p, _, tags = ostep.step(g, f, p, surf, wl.dt, wl.re, case.fext)
+        _tags_equal(case, tags)
+        moved.append(set(tags.idx[0].tolist()))
+    assert case.ibm.ibm_check(case.ctx) == 0
+    # the forcing set really moves: nodes leave it (fresh cells) every step
+    assert all(len(a - b) > 0 for a, b in zip(moved[:-1], moved[1:]))
+    for c in range(3):
+        assert rel(n(d[c], f[c].shape), f[c]) < 1e-10, c
+    assert all(np.isfinite(n(x)).all() for x in d)
