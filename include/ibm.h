@@ -260,6 +260,21 @@ int ibm_mass_rhs(ibm_ctx* ctx, const double* u, const double* v, const double* w
  * IBM_FLAG_REFINE is raised if the tolerance was not reached. */
 int poisson_solve(ibm_ctx* ctx, const double* rhs, double* phi);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the solve of
+ * poisson_solve for an FP64 context, with no context.  Every table and the
+ * spectrum live in one static device array of IBM_STATIC_SCRATCH_BYTES per
+ * device (held until the process ends); the call allocates nothing and only
+ * enqueues kernels on `stream` (hipStream_t, NULL = default).  g: the grid as
+ * for ibm_create (host y_faces, copied into kernel arguments); rhs, phi: dev
+ * f64 ny*nz*nx (may alias).  IBM_EINVAL if the grid needs more than the
+ * static array (spectrum ny*nz*(nx/2+1 rounded up to 8)*16 bytes plus small
+ * tables: e.g. up to 128x96x128 fits) or is not a valid grid.  Calls that
+ * overlap on one device share the array and race.  The compatibility check
+ * of poisson_solve is not made (there is no context to report its flag). */
+#define IBM_STATIC_SCRATCH_BYTES (64ll * 1024 * 1024)
+int poisson_solve_static(const ibm_grid* g, const double* rhs, double* phi, void* stream);
+
 /* No-slip (transpiration) error (paper Sec. 4.4): at every forcing node of
  * the last ibm_tag (or ibm_step) on this context, the flow velocity
  * extrapolated to the wall with the forcing interpolator of Eq. new_IB,

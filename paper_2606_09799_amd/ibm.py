@@ -112,6 +112,8 @@ _batch_tune = _sig("ibm_batch_tune", c_int32, c_void_p, POINTER(c_double), c_dou
                    c_void_p, c_int64, POINTER(IbmBatchPlan), POINTER(IbmBatchPlan), c_int32,
                    POINTER(c_int32))
 _batch_tune_bytes = _sig("ibm_batch_tune_scratch_bytes", c_int64, c_void_p)
+_poisson_static = _sig("poisson_solve_static", c_int32, POINTER(IbmGrid), c_void_p, c_void_p,
+                       c_void_p)
 _check = _sig("ibm_check", c_int32, c_void_p, POINTER(c_uint32))
 _noslip = _sig("ibm_noslip_error", c_int32, c_void_p, c_void_p, c_void_p, c_void_p,
                POINTER(c_double))
@@ -127,7 +129,7 @@ EXPORTS = ("ibm_create", "ibm_destroy", "ibm_set_stream", "ibm_body_rigid", "ibm
            "ibm_check", "ibm_strerror", "ibm_profile", "ibm_profile_read",
            "ibm_batch_create", "ibm_batch_destroy", "ibm_batch_context", "ibm_batch_step",
            "ibm_batch_check", "ibm_batch_set_plan", "ibm_batch_get_plan", "ibm_batch_tune",
-           "ibm_batch_tune_scratch_bytes",
+           "ibm_batch_tune_scratch_bytes", "poisson_solve_static",
            "ibm_noslip_error", "ibm_pressure_cb")
 COEF_STRIDE = 18
 BATCH_SERIAL, BATCH_STREAMS, BATCH_GRAPH, BATCH_PLAN = 0, 1, 2, 3
@@ -341,6 +343,21 @@ def ibm_mass_rhs(ctx, u, v, w, alpha_dt, rhs, qf=None, p=None):
                   _dev(w, torch.float64, ctx.cells, "w"), _dev(p, ctx.pdtype, ctx.cells, "p"),
                   float(alpha_dt), _dev(rhs, torch.float64, ctx.cells, "rhs"),
                   _dev(qf, torch.float64, None, "qf")), "ibm_mass_rhs")
+
+
+def poisson_solve_static(nx, ny, nz, lx, lz, y_faces, rhs, phi):
+    """poisson_solve_static: the FP64 Poisson solve with no context, its
+    workspace in the library's static device array (nothing is allocated);
+    enqueued on torch's current stream.  rhs, phi: float64 device tensors of
+    nx*ny*nz values."""
+    yf = np.ascontiguousarray(np.asarray(y_faces, dtype=np.float64))
+    if yf.shape != (int(ny) + 1,):
+        raise ValueError("y_faces must hold ny+1 values")
+    g = IbmGrid(int(nx), int(ny), int(nz), 0, float(lx), float(lz),
+                yf.ctypes.data_as(POINTER(c_double)))
+    cells = int(nx) * int(ny) * int(nz)
+    _ok(_poisson_static(ctypes.byref(g), _dev(rhs, torch.float64, cells, "rhs"),
+                        _dev(phi, torch.float64, cells, "phi"), _stream()), "poisson_solve_static")
 
 
 def poisson_solve(ctx, rhs, phi):
