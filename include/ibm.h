@@ -287,6 +287,15 @@ int poisson_solve_static(const ibm_grid* g, const double* rhs, double* phi, void
 int ibm_noslip_error(ibm_ctx* ctx, const double* u, const double* v, const double* w,
                      double* eps);
 
+/* Post-projection divergence (paper Eq. mod_div, D u = q on the fluid
+ * cells): out (host double[2]) = max over C_F of |D u - q_F| with the C_F of
+ * the last ibm_tag (or ibm_step) and the uniform q_F of the last mass
+ * correction on this context (every cell and q = 0 with IBM_Q_NONE), and
+ * that q_F.  Not meaningful after the energy-conserving shape (q varies on
+ * C_F).  u, v, w: dev f64.  Synchronises. */
+int ibm_divergence(ibm_ctx* ctx, const double* u, const double* v, const double* w,
+                   double* out);
+
 /* Pressure on the boundary cells (paper Sec. 2, after Eq. q_F: the solve does
  * not define p on C_B; it is rebuilt from the surrounding field with the
  * strategy of the forcing, as post-processing that never enters the step).
@@ -416,10 +425,12 @@ int ibm_batch_tune(ibm_batch* b, const double* coef, double dt, int32_t steps, v
                    int32_t max_entries, int32_t* n_tried);
 
 /* Mixed form: synchronise and copy the refinement statistics since the
- * last reset to stats (host double[4]): Poisson solves, FP64-residual
- * corrections applied, the largest final max|rhs - L_c phi| * alpha_dt, and
- * the largest such residual left by the first correction.  reset = 1 clears
- * them. */
+ * last reset to stats (host double[IBM_REFINE_STATS]): Poisson solves,
+ * FP64-residual corrections applied, the largest final
+ * max|rhs - L_c phi| * alpha_dt, the largest such residual left by the first
+ * correction, the largest such residual of the initial (uncorrected) solve,
+ * and the sum over solves of that initial residual.  reset = 1 clears them. */
+#define IBM_REFINE_STATS 6
 int ibm_refine_stats(ibm_ctx* ctx, double* stats, int32_t reset);
 
 /* Synchronise the stream and return (and clear) the sticky device flags. */

@@ -104,9 +104,10 @@ struct ibm_ctx {
   void* H[3] = {};
   void* sa = nullptr;  // line-solve scratch (segments with forcing nodes)
   void* sc = nullptr;
-  double* rhs_tmp = nullptr;
   double* phi = nullptr;
   void* spec = nullptr;
+  // refined mixed form: the FP64 spectrum of the inverse passes
+  void* spec64 = nullptr;
   // mixed form: FP64-residual refinement of the Poisson solve
   double* rhs_keep = nullptr;
   u64* rmax = nullptr;
@@ -578,11 +579,11 @@ int ibm_create(const ibm_grid* gr, const ibm_opts* o, void* stream, ibm_ctx** ou
   }
   TRY(dalloc_bytes(c, &c->sa, c->nvface, c->es));
   TRY(dalloc_bytes(c, &c->sc, c->nvface, c->es));
-  TRY(dalloc(c, &c->rhs_tmp, c->ncell));
   TRY(dalloc(c, &c->phi, c->ncell));
   const int64_t nspec = (int64_t)ny * nz * spec_ld(g.nxh, c->pfp32);
   TRY(dalloc_bytes(c, &c->spec, nspec, c->pfp32 ? 2 * sizeof(float) : 2 * sizeof(double)));
   if (c->pfp32) {
+    TRY(dalloc_bytes(c, &c->spec64, (int64_t)ny * nz * spec_ld(g.nxh, false), 2 * sizeof(double)));
     TRY(dalloc(c, &c->rhs_keep, c->ncell));
     TRY(dalloc(c, &c->rmax, c->nref + 2));
     TRY(dalloc(c, &c->zm, ny));
@@ -590,7 +591,7 @@ int ibm_create(const ibm_grid* gr, const ibm_opts* o, void* stream, ibm_ctx** ou
     // per-block partials of the x passes (at least one x-row per block)
     TRY(dalloc(c, &c->psum, (int64_t)ny * nz));
   }
-  TRY(dalloc(c, &c->rstats, 4));
+  TRY(dalloc(c, &c->rstats, IBM_REFINE_STATS));
   TRY(dalloc(c, &c->partial, 5 * 512));  // block partials of the mass sums
   TRY(dalloc(c, &c->qf, 2));              // q_F, or (c0, c1) of the energy shape
   TRY(dalloc(c, &c->diag, 4));
@@ -659,7 +660,7 @@ int ibm_create(const ibm_grid* gr, const ibm_opts* o, void* stream, ibm_ctx** ou
   launch_fill_u32(nullptr, c->stream, c->flags, 1, 0u);
   launch_fill_u64(nullptr, c->stream, reinterpret_cast<u64*>(tb.count), 4, 0ull);
   launch_fill_f64(nullptr, c->stream, c->qf, 2, 0.0);
-  launch_fill_f64(nullptr, c->stream, c->rstats, 4, 0.0);
+  launch_fill_f64(nullptr, c->stream, c->rstats, IBM_REFINE_STATS, 0.0);
   if (hipStreamSynchronize(c->stream) != hipSuccess || hipGetLastError() != hipSuccess) {
     free_all(c);
     delete c;
@@ -893,6 +894,7 @@ static PoissonArgs pargs(ibm_ctx* c) {
   a.ylo = c->ylo;
   a.yhi = c->yhi;
   a.spec = c->spec;
+  a.spec64 = c->spec64;
   a.sum_dy = c->sum_dy;
   a.fp32 = c->pfp32;
   a.refine = c->pfp32;
@@ -933,6 +935,22 @@ int ibm_noslip_error(ibm_ctx* c, const double* u, const double* v, const double*
   eps[2] = h[1];
   eps[3] = h[2];
   eps[0] = (h[0] + h[1] + h[2]) / 3.0;
+  return IBM_OK;
+}
+
+int ibm_divergence(ibm_ctx* c, const double* u, const double* v, const double* w,
+                   double* out) {
+  if (!c || !u || !v || !w || !out) FAIL(IBM_EINVAL, "ibm_divergence: bad argument");
+  launch_divergence(&c->prof, c->stream, c->g, u, v, w,
+                    c->opts.use_q ? c->tb.cb_mask : nullptr, c->qf, c->partial, c->diag);
+  int rc = launch_status();
+  if (rc) return rc;
+  double h[2];
+  HIPCHK(hipMemcpyAsync(h, c->diag, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipMemcpyAsync(h + 1, c->qf, sizeof(double), hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(hipStreamSynchronize(c->stream));
+  out[0] = h[0];
+  out[1] = h[1];
   return IBM_OK;
 }
 
@@ -997,9 +1015,9 @@ int ibm_step(ibm_ctx* c, ibm_state* s, const ibm_body* b, int32_t nb, double dt)
 int ibm_refine_stats(ibm_ctx* c, double* stats, int32_t reset) {
   if (!c || !stats) FAIL(IBM_EINVAL, "null argument");
   HIPCHK(hipStreamSynchronize(c->stream));
-  HIPCHK(hipMemcpy(stats, c->rstats, 4 * sizeof(double), hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpy(stats, c->rstats, IBM_REFINE_STATS * sizeof(double), hipMemcpyDeviceToHost));
   if (reset) {
-    launch_fill_f64(nullptr, c->stream, c->rstats, 4, 0.0);
+    launch_fill_f64(nullptr, c->stream, c->rstats, IBM_REFINE_STATS, 0.0);
     HIPCHK(hipStreamSynchronize(c->stream));
   }
   return IBM_OK;

@@ -239,6 +239,10 @@ void launch_mass_rhs(Prof* pf, hipStream_t s, const GridView& g, const double* u
                      const double* w, const uint32_t* cb_mask, const double* qf,
                      double inv_adt, double* rhs);
 
+// max over C_F of |D u - qf[0]| into *out (partial: 256 doubles)
+void launch_divergence(Prof* pf, hipStream_t s, const GridView& g, const double* u,
+                       const double* v, const double* w, const uint32_t* cb_mask,
+                       const double* qf, double* partial, double* out);
 // compatibility of a Neumann right-hand side: FLAG_COMPAT when
 // |sum rhs dV| > 1e-12 sum |rhs| dV (fixed-order sums; partial: 512 doubles)
 void launch_compat(Prof* pf, hipStream_t s, const GridView& g, const double* rhs,
@@ -264,6 +268,8 @@ struct PoissonArgs {
   const double* ylo;   // ny: coefficient of phi[j-1]
   const double* yhi;   // ny: coefficient of phi[j+1]
   void* spec;          // ny*nz*spec_ld(nxh) complex: double2, or float2 when fp32
+  void* spec64;        // refined mixed form: the FP64 spectrum written by the wall-normal
+                       // solve and read by FP64 inverse passes (NULL: inverse passes on spec)
   double sum_dy;
   int fp32;            // FP32 spectrum and transforms
   int p_fp32;          // the pressure (read by the energy-conserving q) is FP32

@@ -327,6 +327,58 @@ void launch_compat(Prof* pf, hipStream_t s, const GridView& g, const double* rhs
   IBM_LAUNCH(pf, "compat", s, k_compat_final<<<1, CPB, 0, s>>>(partial, flags));
 }
 
+// Post-projection divergence (paper Eq. mod_div: D u = q): max over the
+// fluid cells C_F of |D u - q_F| with the uniform q_F of the last mass
+// correction; fixed chunks of rows per block, block maxima, then their
+// maximum.
+__global__ __launch_bounds__(MT) void k_div_partial(GridView g, const double* __restrict__ u,
+                                                    const double* __restrict__ v,
+                                                    const double* __restrict__ w,
+                                                    const uint32_t* __restrict__ cb_mask,
+                                                    const double* __restrict__ qf,
+                                                    double* __restrict__ partial) {
+  __shared__ double sm[MT];
+  const int64_t rows = (int64_t)g.ny * g.nz;
+  const int64_t chunk = (rows + CPB - 1) / CPB;
+  const int64_t r0 = (int64_t)blockIdx.x * chunk;
+  const int64_t r1 = (r0 + chunk < rows) ? r0 + chunk : rows;
+  const double q = *qf;
+  double m = 0.0;
+  for (int64_t r = r0; r < r1; ++r)
+    for (int i = threadIdx.x; i < g.nx; i += MT) {
+      const int64_t cell = r * g.nx + i;
+      if (cb_mask && test_bit(cb_mask, cell)) continue;
+      m = fmax(m, fabs(div_at(g, u, v, w, cell) - q));
+    }
+  sm[threadIdx.x] = m;
+  __syncthreads();
+  for (int off = MT / 2; off > 0; off >>= 1) {
+    if (threadIdx.x < off) sm[threadIdx.x] = fmax(sm[threadIdx.x], sm[threadIdx.x + off]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = sm[0];
+}
+
+__global__ __launch_bounds__(CPB) void k_div_final(const double* __restrict__ partial,
+                                                   double* __restrict__ out) {
+  __shared__ double sm[CPB];
+  sm[threadIdx.x] = partial[threadIdx.x];
+  __syncthreads();
+  for (int off = CPB / 2; off > 0; off >>= 1) {
+    if (threadIdx.x < off) sm[threadIdx.x] = fmax(sm[threadIdx.x], sm[threadIdx.x + off]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = sm[0];
+}
+
+void launch_divergence(Prof* pf, hipStream_t s, const GridView& g, const double* u,
+                       const double* v, const double* w, const uint32_t* cb_mask,
+                       const double* qf, double* partial, double* out) {
+  IBM_LAUNCH(pf, "divergence", s,
+             k_div_partial<<<CPB, MT, 0, s>>>(g, u, v, w, cb_mask, qf, partial));
+  IBM_LAUNCH(pf, "divergence", s, k_div_final<<<1, CPB, 0, s>>>(partial, out));
+}
+
 void launch_mass(Prof* pf, hipStream_t s, const GridView& g, const double* u, const double* v,
                  const double* w, const int64_t* cb, const int64_t* count, int64_t cap,
                  double vtot, int use_q, double* partial, double* qf, uint32_t* flags) {

@@ -192,6 +192,14 @@ struct PoisK {
   const double* msum;          // inverse x pass of a refinement: sum of phi dV to remove
   double inv_vtot;
   int ldx;                     // row stride of the spectrum (spec_ld)
+  // wall-normal solve output: a spectrum of another precision (the FP64
+  // spectrum of the refined mixed form, read by FP64 inverse passes) with its
+  // own row stride; NULL: in place in spec
+  void* spec_out;
+  int ldx_out;
+  // FP32 spectrum: the (0,0) mode's right-hand side loses its volume-weighted
+  // mean before the gauged solve (see the wall-normal solves)
+  int zero_in;
   int rows;                    // x-rows per block
   int tp;                      // x-modes per block in the z passes
   int yP, yL, yr, ytl;         // wall-normal solve: segments, base length, longer ones, lines per block
@@ -941,11 +949,30 @@ __device__ __forceinline__ double recip(double x) {
   return fma(r, e, r);
 }
 
+// One step of cyclic reduction on a row kept in excess form.  A row
+//   a x_minus + b x + g x_plus = d
+// is stored as (a, e, g) with e = a + b + g its row sum; the diagonal is
+// e - a - g.  The wall-normal systems have a, g >= 0 and e = lambda <= 0,
+// and every reduction keeps that sign pattern, so the new excess
+//   e' = e - k1 e_minus - k2 e_plus   (k1 = a / b_minus, k2 = g / b_plus)
+// and the diagonal e' - a' - g' are sums of terms of one sign.  Formed from
+// b directly they would cancel: for the low modes |b| exceeds a + g only
+// by |lambda|, and near a stretched wall a + g is large, so the separator
+// systems would lose up to a few hundred times the rounding of the data
+// (their residual, not that of the plain elimination, sets the
+// post-projection divergence of the largest grids).
+__device__ __forceinline__ void excess_row(double& a, double& e, double& g, double k1, double am,
+                                           double em, double k2, double gp, double ep) {
+  e = e - k1 * em - k2 * ep;
+  a = -am * k1;
+  g = -gp * k2;
+}
+
 // UNI: every segment holds exactly YL rows (ny = P YL), so the row loops
 // are straight-line code.
-template <typename C, bool UNI>
+template <typename C, bool UNI, typename CO>
 __global__ __launch_bounds__(1024) void k_tri_y(PoisK<C> K) {
-  using R = typename RealOf<C>::T;
+  using RO = typename RealOf<CO>::T;
   if (gated(K)) return;
   extern __shared__ __align__(16) unsigned char smraw[];
   double* sm = reinterpret_cast<double*>(smraw);  // 11 arrays [PP][TL + 1]
@@ -983,6 +1010,43 @@ __global__ __launch_bounds__(1024) void k_tri_y(PoisK<C> K) {
     xr[e] = (double)v.x;
     xi[e] = (double)v.y;
   }
+  if (K.zero_in && blockIdx.x == 0) {
+    // The (0,0) mode is the Neumann problem's singular one: its right-hand
+    // side must have zero volume-weighted sum (compatibility), which the FP32
+    // rounding of the forward transforms breaks; the gauge row phi_0 = 0
+    // would then take the whole excess, at the wall, where 1/dy amplifies
+    // it.  Removing the mean first leaves a uniform residual of the rounding's
+    // size instead (and changes nothing for a compatible right-hand side).
+    double pr = 0.0, pi = 0.0;
+    if (lb == 0 && active) {
+#pragma unroll
+      for (int e = 0; e < YL; ++e)
+        if (UNI || e < len) {
+          pr += g.dy[lo + e] * xr[e];
+          pi += g.dy[lo + e] * xi[e];
+        }
+    }
+    if (lb == 0 && active) {
+      A(0, s, 0) = pr;
+      A(1, s, 0) = pi;
+    }
+    __syncthreads();
+    if (lb == 0) {
+      double Mr = 0.0, Mi = 0.0;
+      for (int t = 0; t < P; ++t) {
+        Mr += A(0, t, 0);
+        Mi += A(1, t, 0);
+      }
+      Mr *= K.inv_sum_dy;
+      Mi *= K.inv_sum_dy;
+#pragma unroll
+      for (int e = 0; e < YL; ++e) {
+        xr[e] -= Mr;
+        xi[e] -= Mi;
+      }
+    }
+    __syncthreads();
+  }
   double zr = xr[YL - 1], zi = xi[YL - 1];
   if (!UNI) {
 #pragma unroll
@@ -994,69 +1058,71 @@ __global__ __launch_bounds__(1024) void k_tri_y(PoisK<C> K) {
   }
   // forward elimination of the interior rows: row e becomes
   //   x_e + ct_e x_{e+1} = dt_e - at_e z_left
-  double atp = 0.0, ctp = 0.0, dr = 0.0, di = 0.0;
+  // in excess form (see excess_row): with u = 1 + ct and tau = 1 + at + ct
+  // carried, every pivot and excess is a sum of terms of one sign
+  double atp = -1.0, up = 1.0, tp = 0.0, dr = 0.0, di = 0.0;
+  double tau[YL - 1];
 #pragma unroll
   for (int e = 0; e < YL - 1; ++e)
     if (UNI || e < m) {
       const int j = lo + e;
-      double a = K.ylo[j], c = K.yhi[j], b = lam - (a + c);
-      double er = xr[e], ei = xi[e];
-      if (e == 0 && z0) {
-        a = 0.0;
-        b = 1.0;
-        c = 0.0;
-        er = 0.0;
-        ei = 0.0;
-      }
-      const double inv = recip(b - a * ctp);
-      atp = (e == 0) ? a * inv : -a * atp * inv;
-      ctp = c * inv;
-      dr = (er - a * dr) * inv;
-      di = (ei - a * di) * inv;
+      const bool idr = (e == 0 && z0);  // the gauge row: identity, right side 0
+      const double a = idr ? 0.0 : K.ylo[j], c = idr ? 0.0 : K.yhi[j];
+      const double inv = idr ? 1.0 : recip(lam - c - a * up);
+      atp = -a * atp * inv;
+      up = idr ? 1.0 : (lam - a * up) * inv;
+      tp = idr ? 1.0 : (lam - a * tp) * inv;
+      dr = idr ? 0.0 : (xr[e] - a * dr) * inv;
+      di = idr ? 0.0 : (xi[e] - a * di) * inv;
       ah[e] = atp;
-      ch[e] = ctp;
+      ch[e] = c * inv;
+      tau[e] = tp;
       xr[e] = dr;
       xi[e] = di;
     }
-  // backward: x_e = d_e - ah_e z_left - ch_e z_right
-  double ahl = 0.0, chl = 0.0, dlr = 0.0, dli = 0.0;  // row m-1
+  // backward: x_e = d_e - ah_e z_left - ch_e z_right, with the excess
+  // sg_e = 1 + ah_e + ch_e
+  double ahl = 0.0, dlr = 0.0, dli = 0.0, sgl = 0.0, sg = 0.0;  // row m-1; sg: row e
 #pragma unroll
   for (int e = YL - 2; e >= 0; --e)
     if (UNI || e < m) {
       if (e == m - 1) {
         ahl = ah[e];
-        chl = ch[e];
         dlr = xr[e];
         dli = xi[e];
+        sgl = tau[e];
+        sg = sgl;
       } else {
         const double ct = ch[e];
         xr[e] -= ct * xr[e + 1];
         xi[e] -= ct * xi[e + 1];
         ah[e] -= ct * ah[e + 1];
         ch[e] = -ct * ch[e + 1];
+        sg = tau[e] - ct * sg;
       }
     }
   // the first interior row of each segment, for the separator row before it
+  // (its excess in slot 9, free until the separators are solved)
   if (active) {
-    A(0, s, lb) = ah[0];
     A(1, s, lb) = ch[0];
     A(2, s, lb) = xr[0];
     A(3, s, lb) = xi[0];
+    A(9, s, lb) = sg;
   }
   __syncthreads();
   if (active) {
     const int jz = lo + m;
-    const double az = K.ylo[jz], cz = K.yhi[jz], bz = lam - (az + cz);
-    double rb = bz - az * chl, rg = 0.0;
-    double rdr = zr - az * dlr, rdi = zi - az * dli;
+    const double az = K.ylo[jz], cz = K.yhi[jz];
+    double rg = 0.0, rdr = zr - az * dlr, rdi = zi - az * dli;
+    double re = lam - az * sgl - cz;
     if (s + 1 < P) {
-      rb -= cz * A(0, s + 1, lb);
+      re = lam - az * sgl - cz * A(9, s + 1, lb);
       rg = -cz * A(1, s + 1, lb);
       rdr -= cz * A(2, s + 1, lb);
       rdi -= cz * A(3, s + 1, lb);
     }
     A(4, s, lb) = -az * ahl;
-    A(5, s, lb) = rb;
+    A(5, s, lb) = re;
     A(6, s, lb) = rg;
     A(7, s, lb) = rdr;
     A(8, s, lb) = rdi;
@@ -1064,17 +1130,17 @@ __global__ __launch_bounds__(1024) void k_tri_y(PoisK<C> K) {
   __syncthreads();
   {
     // transposed: lane (mode lt, separator st), PP lanes per mode; rows past
-    // P act as identity rows.  Each step eliminates the neighbours at
-    // distance `step`; a neighbour outside 0..PP-1 is an identity row, which
-    // contributes nothing (its multiplier is 0), so the lane reads itself
-    // there and drops the term.
+    // P act as identity rows (excess 1).  Each step eliminates the
+    // neighbours at distance `step`; a neighbour outside 0..PP-1 is an
+    // identity row, which contributes nothing (its multiplier is 0), so the
+    // lane reads itself there and drops the term.
     const int lt = threadIdx.x / PP, st = threadIdx.x % PP;
     const int grp = (threadIdx.x & 63) - st;
     const bool own = lt < TL && st < P;
-    double ra = 0.0, rb = 1.0, rg = 0.0, rdr = 0.0, rdi = 0.0;
+    double ra = 0.0, re = 1.0, rg = 0.0, rdr = 0.0, rdi = 0.0;
     if (own) {
       ra = A(4, st, lt);
-      rb = A(5, st, lt);
+      re = A(5, st, lt);
       rg = A(6, st, lt);
       rdr = A(7, st, lt);
       rdi = A(8, st, lt);
@@ -1083,21 +1149,18 @@ __global__ __launch_bounds__(1024) void k_tri_y(PoisK<C> K) {
       const int im = st - step, ip = st + step;
       const bool hm = im >= 0, hp = ip < PP;
       const int sm_ = grp + (hm ? im : st), sp_ = grp + (hp ? ip : st);
-      const double rib = recip(rb);  // neighbours divide by this row's pivot
-      const double am = lane_read(ra, sm_), rm = lane_read(rib, sm_), gm = lane_read(rg, sm_);
+      const double rib = recip(re - ra - rg);  // neighbours divide by this row's pivot
+      const double am = lane_read(ra, sm_), rm = lane_read(rib, sm_), em = lane_read(re, sm_);
       const double dmr = lane_read(rdr, sm_), dmi = lane_read(rdi, sm_);
-      const double ap = lane_read(ra, sp_), rp = lane_read(rib, sp_), gp = lane_read(rg, sp_);
+      const double gp = lane_read(rg, sp_), rp = lane_read(rib, sp_), ep = lane_read(re, sp_);
       const double dpr = lane_read(rdr, sp_), dpi = lane_read(rdi, sp_);
       const double k1 = hm ? ra * rm : 0.0, k2 = hp ? rg * rp : 0.0;
-      const double na = -am * k1, ng = -gp * k2;
-      rb = rb - gm * k1 - ap * k2;
+      excess_row(ra, re, rg, k1, am, em, k2, gp, ep);
       rdr = rdr - dmr * k1 - dpr * k2;
       rdi = rdi - dmi * k1 - dpi * k2;
-      ra = na;
-      rg = ng;
     }
     if (own) {
-      const double rib = recip(rb);
+      const double rib = recip(re - ra - rg);
       A(9, st, lt) = rdr * rib;
       A(10, st, lt) = rdi * rib;
     }
@@ -1155,23 +1218,25 @@ __global__ __launch_bounds__(1024) void k_tri_y(PoisK<C> K) {
     // an FP32 spectrum hands the (0,0) mode (a real column) to the inverse x
     // pass in FP64, so that the zero-mean gauge survives the FP32 rounding
     const bool keep = (q == 0) && K.zm;
-    C* __restrict__ X = K.spec + q;
+    const int64_t nmo = (int64_t)g.nz * K.ldx_out;
+    CO* __restrict__ X = (K.spec_out ? static_cast<CO*>(K.spec_out) : reinterpret_cast<CO*>(K.spec)) +
+                         (int64_t)kq * K.ldx_out + pq;
 #pragma unroll
     for (int e = 0; e < YL; ++e)
       if (UNI || e < len) {
         const double vr = (e < m) ? xr[e] : zr;
         const double vi = (e < m) ? xi[e] : zi;
         if (keep) K.zm[lo + e] = vr;
-        X[(int64_t)(lo + e) * nm] = keep ? mkc<C>((R)0, (R)0) : mkc<C>((R)vr, (R)vi);
+        X[(int64_t)(lo + e) * nmo] = keep ? mkc<CO>((RO)0, (RO)0) : mkc<CO>((RO)vr, (RO)vi);
       }
   }
 }
 
 // The same solve with the separator system reduced block-wide in LDS, for
 // modes of more than 64 separators (P rounded up past one wavefront).
-template <typename C>
+template <typename C, typename CO>
 __global__ __launch_bounds__(1024) void k_tri_y_blk(PoisK<C> K) {
-  using R = typename RealOf<C>::T;
+  using RO = typename RealOf<CO>::T;
   if (gated(K)) return;
   extern __shared__ __align__(16) unsigned char smraw[];
   double* sm = reinterpret_cast<double*>(smraw);  // 7 arrays of P doubles per line
@@ -1213,110 +1278,144 @@ __global__ __launch_bounds__(1024) void k_tri_y_blk(PoisK<C> K) {
         }
       }
   }
+  if (K.zero_in && blockIdx.x == 0) {
+    // the (0,0) mode's right-hand side loses its volume-weighted mean (see
+    // the wavefront form of this solve)
+    double pr = 0.0, pi = 0.0;
+    if (lb == 0) {
+#pragma unroll
+      for (int e = 0; e < YL; ++e)
+        if (e < len) {
+          const double dyj = g.dy[lo + e];
+          pr += dyj * (e < m ? xr[e] : zr);
+          pi += dyj * (e < m ? xi[e] : zi);
+        }
+      at(0, s) = pr;
+      at(1, s) = pi;
+    }
+    __syncthreads();
+    if (lb == 0) {
+      double Mr = 0.0, Mi = 0.0;
+      for (int t = 0; t < P; ++t) {
+        Mr += sm[((size_t)0 * P + t) * TL];
+        Mi += sm[((size_t)1 * P + t) * TL];
+      }
+      Mr *= K.inv_sum_dy;
+      Mi *= K.inv_sum_dy;
+#pragma unroll
+      for (int e = 0; e < YL; ++e) {
+        xr[e] -= Mr;
+        xi[e] -= Mi;
+      }
+      zr -= Mr;
+      zi -= Mi;
+    }
+    __syncthreads();
+  }
   // forward elimination of the interior rows: row e becomes
   //   x_e + ct_e x_{e+1} = dt_e - at_e z_left
-  double atp = 0.0, ctp = 0.0, dr = 0.0, di = 0.0;
+  // in excess form (see excess_row and the wavefront form of this solve)
+  double atp = -1.0, up = 1.0, tp = 0.0, dr = 0.0, di = 0.0;
+  double tau[YL - 1];
 #pragma unroll
   for (int e = 0; e < YL - 1; ++e)
     if (e < m) {
       const int j = lo + e;
-      double a = K.ylo[j], c = K.yhi[j], b = lam - (a + c);
-      double er = xr[e], ei = xi[e];
-      if (zero && j == 0) {
-        a = 0.0;
-        b = 1.0;
-        c = 0.0;
-        er = 0.0;
-        ei = 0.0;
-      }
-      const double inv = 1.0 / (b - a * ctp);
-      atp = (e == 0) ? a * inv : -a * atp * inv;
-      ctp = c * inv;
-      dr = (er - a * dr) * inv;
-      di = (ei - a * di) * inv;
+      const bool idr = zero && j == 0;  // the gauge row: identity, right side 0
+      const double a = idr ? 0.0 : K.ylo[j], c = idr ? 0.0 : K.yhi[j];
+      const double inv = idr ? 1.0 : 1.0 / (lam - c - a * up);
+      atp = -a * atp * inv;
+      up = idr ? 1.0 : (lam - a * up) * inv;
+      tp = idr ? 1.0 : (lam - a * tp) * inv;
+      dr = idr ? 0.0 : (xr[e] - a * dr) * inv;
+      di = idr ? 0.0 : (xi[e] - a * di) * inv;
       ah[e] = atp;
-      ch[e] = ctp;
+      ch[e] = c * inv;
+      tau[e] = tp;
       xr[e] = dr;
       xi[e] = di;
     }
-  // backward: x_e = d_e - ah_e z_left - ch_e z_right
-  double ahl = 0.0, chl = 0.0, dlr = 0.0, dli = 0.0;  // row m-1
+  // backward: x_e = d_e - ah_e z_left - ch_e z_right, excess 1 + ah_e + ch_e
+  double ahl = 0.0, dlr = 0.0, dli = 0.0, sgl = 0.0, sg = 0.0;  // row m-1; sg: row e
 #pragma unroll
   for (int e = YL - 2; e >= 0; --e)
     if (e < m) {
       if (e == m - 1) {
         ahl = ah[e];
-        chl = ch[e];
         dlr = xr[e];
         dli = xi[e];
+        sgl = tau[e];
+        sg = sgl;
       } else {
         const double ct = ch[e];
         xr[e] -= ct * xr[e + 1];
         xi[e] -= ct * xi[e + 1];
         ah[e] -= ct * ah[e + 1];
         ch[e] = -ct * ch[e + 1];
+        sg = tau[e] - ct * sg;
       }
     }
   // the first interior row of each segment, for the separator row before it
-  at(0, s) = ah[0];
+  at(0, s) = sg;
   at(1, s) = ch[0];
   at(2, s) = xr[0];
   at(3, s) = xi[0];
   __syncthreads();
   const int jz = lo + m;
-  const double az = K.ylo[jz], cz = K.yhi[jz], bz = lam - (az + cz);
-  double ra = -az * ahl, rb = bz - az * chl, rg = 0.0;
+  const double az = K.ylo[jz], cz = K.yhi[jz];
+  double ra = -az * ahl, re = lam - az * sgl - cz, rg = 0.0;
   double rdr = zr - az * dlr, rdi = zi - az * dli;
   if (s + 1 < P) {
-    rb -= cz * at(0, s + 1);
+    re = lam - az * sgl - cz * at(0, s + 1);
     rg = -cz * at(1, s + 1);
     rdr -= cz * at(2, s + 1);
     rdi -= cz * at(3, s + 1);
   }
   __syncthreads();
   at(0, s) = ra;
-  at(1, s) = rb;
+  at(1, s) = re;
   at(2, s) = rg;
   at(3, s) = rdr;
   at(4, s) = rdi;
   __syncthreads();
-  // parallel cyclic reduction; rows outside 0..P-1 act as identity rows
+  // parallel cyclic reduction in excess form; rows outside 0..P-1 act as
+  // identity rows (multiplier 0)
   for (int st = 1; st < P; st <<= 1) {
     const int im = s - st, ip = s + st;
-    double am = 0.0, bm = 1.0, gm = 0.0, dmr = 0.0, dmi = 0.0;
-    double ap = 0.0, bp = 1.0, gp = 0.0, dpr = 0.0, dpi = 0.0;
+    double am = 0.0, em = 1.0, dmr = 0.0, dmi = 0.0, k1 = 0.0;
+    double gp = 0.0, ep = 1.0, dpr = 0.0, dpi = 0.0, k2 = 0.0;
     if (im >= 0) {
       am = at(0, im);
-      bm = at(1, im);
-      gm = at(2, im);
+      em = at(1, im);
       dmr = at(3, im);
       dmi = at(4, im);
+      k1 = ra / (em - am - at(2, im));
     }
     if (ip < P) {
-      ap = at(0, ip);
-      bp = at(1, ip);
       gp = at(2, ip);
+      ep = at(1, ip);
       dpr = at(3, ip);
       dpi = at(4, ip);
+      k2 = rg / (ep - at(0, ip) - gp);
     }
-    const double k1 = ra / bm, k2 = rg / bp;
-    const double na = -am * k1, ng = -gp * k2;
-    const double nb = rb - gm * k1 - ap * k2;
+    double na = ra, ne = re, ng = rg;
+    excess_row(na, ne, ng, k1, am, em, k2, gp, ep);
     const double ndr = rdr - dmr * k1 - dpr * k2;
     const double ndi = rdi - dmi * k1 - dpi * k2;
     __syncthreads();
     ra = na;
-    rb = nb;
+    re = ne;
     rg = ng;
     rdr = ndr;
     rdi = ndi;
     at(0, s) = ra;
-    at(1, s) = rb;
+    at(1, s) = re;
     at(2, s) = rg;
     at(3, s) = rdr;
     at(4, s) = rdi;
     __syncthreads();
   }
+  const double rb = re - ra - rg;
   at(5, s) = rdr / rb;
   at(6, s) = rdi / rb;
   __syncthreads();
@@ -1372,13 +1471,16 @@ __global__ __launch_bounds__(1024) void k_tri_y_blk(PoisK<C> K) {
     // an FP32 spectrum hands the (0,0) mode (a real column) to the inverse x
     // pass in FP64, so that the zero-mean gauge survives the FP32 rounding
     const bool keep = zero && K.zm;
+    const int64_t nmo = (int64_t)g.nz * K.ldx_out;
+    CO* __restrict__ XO = (K.spec_out ? static_cast<CO*>(K.spec_out) : reinterpret_cast<CO*>(K.spec)) +
+                          (q / K.ldx) * K.ldx_out + q % K.ldx;
 #pragma unroll
     for (int e = 0; e < YL; ++e)
       if (e < len) {
         const double vr = (e < m) ? xr[e] : zr;
         const double vi = (e < m) ? xi[e] : zi;
         if (keep) K.zm[lo + e] = vr;
-        X[(int64_t)(lo + e) * nm] = keep ? mkc<C>((R)0, (R)0) : mkc<C>((R)vr, (R)vi);
+        XO[(int64_t)(lo + e) * nmo] = keep ? mkc<CO>((RO)0, (RO)0) : mkc<CO>((RO)vr, (RO)vi);
       }
   }
 }
@@ -1444,7 +1546,8 @@ __global__ __launch_bounds__(256) void k_sum_partials(const double* __restrict__
 // Refinement bookkeeping after one mixed solve: rmax[k] (k = 1..nref) is the
 // residual that opened refinement k (0 if it never ran), rmax[nref+1] the
 // final check.  stats: [solves, corrections, largest final max|r| * adt,
-// largest max|r| * adt after the first correction].
+// largest max|r| * adt after the first correction, largest max|r| * adt of
+// the initial solve, sum over solves of that initial value].
 __global__ void k_refine_stats(const u64* rmax, int nref, double tol, double adt, double* stats,
                                uint32_t* flags) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
@@ -1463,6 +1566,9 @@ __global__ void k_refine_stats(const u64* rmax, int nref, double tol, double adt
   // the residual left by the first correction (0 when none was needed)
   const double r2 = (nref >= 2) ? __longlong_as_double((long long)rmax[2]) * adt : 0.0;
   if (!(r2 <= stats[3])) stats[3] = r2;
+  const double r1 = __longlong_as_double((long long)rmax[1]) * adt;
+  if (!(r1 <= stats[4])) stats[4] = r1;
+  stats[5] += r1;
 }
 
 template <typename C>
@@ -1475,9 +1581,9 @@ static PlanDev<C> to_dev(const FFTPlan* p, const C* tw) {
   return d;
 }
 
+// x-rows per block and x-modes per z-pass block for a spectrum type
 template <typename C>
-static void run_passes(Prof* pf, hipStream_t s, const GridView& g, PoisK<C> K) {
-  constexpr int CB = (int)sizeof(C);
+static void pass_shape(const GridView& g, PoisK<C>& K) {
   // per block two LDS buffers of at most fft_buf complex values: x passes
   // take an even number of real rows, two per complex sequence (nx and nz
   // <= fft_buf, checked when the context is created)
@@ -1487,6 +1593,19 @@ static void run_passes(Prof* pf, hipStream_t s, const GridView& g, PoisK<C> K) {
   int tp = fft_buf<C>() / g.nz;
   if (tp > 16) tp = 16;
   K.tp = tp;
+}
+
+// The five passes of a solve.  K (spectrum type C) runs the forward x and z
+// passes and the wall-normal solve; KI (type CI) the inverse z and x passes.
+// With CI != C the solve writes KI's spectrum (its own precision and row
+// stride): the refined mixed form transforms forward in FP32 and back in
+// FP64.
+template <typename C, typename CI>
+static void run_passes(Prof* pf, hipStream_t s, const GridView& g, PoisK<C> K, PoisK<CI> KI) {
+  constexpr int CB = (int)sizeof(C), CBI = (int)sizeof(CI);
+  pass_shape<C>(g, K);
+  pass_shape<CI>(g, KI);
+  const int rows = K.rows, tp = K.tp;
   line_plan(g.ny, false, YL, &K.yP, &K.yL, &K.yr);
   K.yPP = 1;
   while (K.yPP < K.yP) K.yPP <<= 1;
@@ -1499,10 +1618,18 @@ static void run_passes(Prof* pf, hipStream_t s, const GridView& g, PoisK<C> K) {
   if (K.ytl < 1) K.ytl = 1;
   const int64_t nrows = (int64_t)g.ny * g.nz;
   const int xblocks = (int)((nrows + rows - 1) / rows);
+  const int xblocks_i = (int)((nrows + KI.rows - 1) / KI.rows);
   const size_t xsh = 2 * (size_t)(rows / 2) * g.nx * CB;
+  const size_t xsh_i = 2 * (size_t)(KI.rows / 2) * g.nx * CBI;
   const size_t zsh = 2 * (size_t)tp * g.nz * CB;
-  dim3 zgrid((g.nxh + tp - 1) / tp, g.ny);
+  const size_t zsh_i = 2 * (size_t)KI.tp * g.nz * CBI;
+  const dim3 zgrid((g.nxh + tp - 1) / tp, g.ny), zgrid_i((g.nxh + KI.tp - 1) / KI.tp, g.ny);
   K.ldx = spec_ld(g.nxh, sizeof(C) == sizeof(float2));
+  KI.ldx = spec_ld(g.nxh, sizeof(CI) == sizeof(float2));
+  const bool split = (void*)KI.spec != (void*)K.spec;
+  K.spec_out = split ? (void*)KI.spec : nullptr;
+  K.ldx_out = split ? KI.ldx : K.ldx;
+  K.zero_in = split ? 1 : 0;
   const int64_t nm = (int64_t)g.nz * K.ldx;
   const int yblocks = (int)((nm + K.ytl - 1) / K.ytl);
   // wavefront form: z-major blocks of ytl modes of one z row
@@ -1512,7 +1639,9 @@ static void run_passes(Prof* pf, hipStream_t s, const GridView& g, PoisK<C> K) {
   const bool resid = K.mode >= SRC_RESIDUAL;
   // length-256 x transforms: 2 X16_SC rows per block
   const bool x256 = (g.nx == 256 && K.ldx <= X16_LDX_MAX);
+  const bool x256_i = (g.nx == 256 && KI.ldx <= X16_LDX_MAX);
   const int xb = x256 ? (int)((nrows + 2 * X16_SC - 1) / (2 * X16_SC)) : xblocks;
+  const int xb_i = x256_i ? (int)((nrows + 2 * X16_SC - 1) / (2 * X16_SC)) : xblocks_i;
   if (x256)
     IBM_LAUNCH(pf, resid ? "pois_resid_fftx" : "pois_fftx_fwd", s,
                (k_fftx256_fwd<C><<<xb, 32 * X16_SC, 0, s>>>(K)));
@@ -1522,6 +1651,8 @@ static void run_passes(Prof* pf, hipStream_t s, const GridView& g, PoisK<C> K) {
   if (K.mode == SRC_CHECK) return;
   if (resid) {
     K.gate = K.rmax;  // the rest of a refinement runs only if its residual is too large
+    KI.gate = K.rmax;
+    KI.gate_tol = K.gate_tol;
     IBM_LAUNCH(pf, "pois_mean", s,
                (k_sum_partials<<<1, 256, 0, s>>>(K.psum, xb, const_cast<double*>(K.msum),
                                                   K.gate, K.gate_tol)));
@@ -1538,23 +1669,64 @@ static void run_passes(Prof* pf, hipStream_t s, const GridView& g, PoisK<C> K) {
   else
     IBM_LAUNCH(pf, "pois_fftz_fwd", s, (k_fftz<C, false><<<zgrid, 256, zsh, s>>>(K)));
   if (ywave && K.yr == 0 && K.yL == YL)
-    IBM_LAUNCH(pf, "pois_tri_y", s, (k_tri_y<C, true><<<ywblocks, K.ytl * K.yPP, ysh, s>>>(K)));
+    IBM_LAUNCH(pf, "pois_tri_y", s,
+               (k_tri_y<C, true, CI><<<ywblocks, K.ytl * K.yPP, ysh, s>>>(K)));
   else if (ywave)
-    IBM_LAUNCH(pf, "pois_tri_y", s, (k_tri_y<C, false><<<ywblocks, K.ytl * K.yPP, ysh, s>>>(K)));
+    IBM_LAUNCH(pf, "pois_tri_y", s,
+               (k_tri_y<C, false, CI><<<ywblocks, K.ytl * K.yPP, ysh, s>>>(K)));
   else
-    IBM_LAUNCH(pf, "pois_tri_y", s, (k_tri_y_blk<C><<<yblocks, K.ytl * K.yP, ysh, s>>>(K)));
+    IBM_LAUNCH(pf, "pois_tri_y", s, (k_tri_y_blk<C, CI><<<yblocks, K.ytl * K.yP, ysh, s>>>(K)));
   if (z256)
-    IBM_LAUNCH(pf, "pois_fftz_inv", s, (k_fftz256<C, true><<<z16grid, 16 * Z16_TC, 0, s>>>(K)));
+    IBM_LAUNCH(pf, "pois_fftz_inv", s, (k_fftz256<CI, true><<<z16grid, 16 * Z16_TC, 0, s>>>(KI)));
   else if (g.nz == 512)
-    IBM_LAUNCH(pf, "pois_fftz_inv", s, (k_fftz4s<C, true, 2><<<z512grid, 256, 0, s>>>(K)));
+    IBM_LAUNCH(pf, "pois_fftz_inv", s, (k_fftz4s<CI, true, 2><<<z512grid, 256, 0, s>>>(KI)));
   else if (g.nz == 1024)
-    IBM_LAUNCH(pf, "pois_fftz_inv", s, (k_fftz4s<C, true, 4><<<z1kgrid, 256, 0, s>>>(K)));
+    IBM_LAUNCH(pf, "pois_fftz_inv", s, (k_fftz4s<CI, true, 4><<<z1kgrid, 256, 0, s>>>(KI)));
   else
-    IBM_LAUNCH(pf, "pois_fftz_inv", s, (k_fftz<C, true><<<zgrid, 256, zsh, s>>>(K)));
-  if (x256)
-    IBM_LAUNCH(pf, "pois_fftx_inv", s, (k_fftx256_inv<C><<<xb, 32 * X16_SC, 0, s>>>(K)));
+    IBM_LAUNCH(pf, "pois_fftz_inv", s, (k_fftz<CI, true><<<zgrid_i, 256, zsh_i, s>>>(KI)));
+  if (x256_i)
+    IBM_LAUNCH(pf, "pois_fftx_inv", s, (k_fftx256_inv<CI><<<xb_i, 32 * X16_SC, 0, s>>>(KI)));
   else
-    IBM_LAUNCH(pf, "pois_fftx_inv", s, (k_fftx_inv<C><<<xblocks, 256, xsh, s>>>(K)));
+    IBM_LAUNCH(pf, "pois_fftx_inv", s, (k_fftx_inv<CI><<<xblocks_i, 256, xsh_i, s>>>(KI)));
+}
+
+// the inverse passes' view of a solve: the fields the inverse z and x
+// passes read, over the spectrum `spec` of type CI
+template <typename CI, typename C>
+static PoisK<CI> inverse_view(const PoisK<C>& K, const PoissonArgs& a, void* spec) {
+  PoisK<CI> I{};
+  I.g = K.g;
+  const bool f32 = sizeof(CI) == sizeof(float2);
+  I.px = to_dev<CI>(a.px, reinterpret_cast<const CI*>(f32 ? (const void*)a.px->tw32
+                                                           : (const void*)a.px->tw));
+  I.pz = to_dev<CI>(a.pz, reinterpret_cast<const CI*>(f32 ? (const void*)a.pz->tw32
+                                                           : (const void*)a.pz->tw));
+  I.mode = K.mode;
+  I.spec = static_cast<CI*>(spec);
+  I.phi = K.phi;
+  I.accumulate = K.accumulate;
+  I.scale = K.scale;
+  I.msum = K.msum;
+  I.inv_vtot = K.inv_vtot;
+  I.zm = K.zm;
+  I.gate = K.gate;
+  I.gate_tol = K.gate_tol;
+  return I;
+}
+
+// one run of the five passes: FP64 throughout, or (refined mixed form) the
+// forward passes on the FP32 spectrum and the inverse ones on the FP64
+// spectrum a.spec64
+template <typename C>
+static void passes(Prof* pf, hipStream_t s, const GridView& g, const PoissonArgs& a,
+                   const PoisK<C>& K) {
+  if constexpr (sizeof(C) == sizeof(float2)) {
+    if (a.spec64) {
+      run_passes<C, double2>(pf, s, g, K, inverse_view<double2>(K, a, a.spec64));
+      return;
+    }
+  }
+  run_passes<C, C>(pf, s, g, K, K);
 }
 
 template <typename C>
@@ -1586,11 +1758,13 @@ static void solve(Prof* pf, hipStream_t s, const GridView& g, const PoissonArgs&
   K.phi = phi;
   const int nref = a.refine ? a.nref : 0;
   K.rhs_keep = a.refine ? a.rhs_keep : nullptr;
-  K.zm = a.fp32 ? a.zm : nullptr;
+  // with an FP64 spectrum after the wall-normal solve the (0,0) mode needs
+  // no FP64 side column
+  K.zm = (a.fp32 && !a.spec64) ? a.zm : nullptr;
   // the tolerance bounds max|r| * alpha dt
   K.gate_tol = a.tol * inv_adt;
   if (a.refine) launch_fill_u64(pf, s, a.rmax, nref + 2, 0ull);
-  run_passes<C>(pf, s, g, K);
+  passes<C>(pf, s, g, a, K);
   if (!a.refine) return;
   K.rhs = a.rhs_keep;
   K.rhs_keep = nullptr;
@@ -1603,7 +1777,7 @@ static void solve(Prof* pf, hipStream_t s, const GridView& g, const PoissonArgs&
     K.gate = (k > 1) ? a.rmax + (k - 1) : nullptr;
     K.psum = (k <= nref) ? a.psum : nullptr;
     K.msum = (k <= nref) ? a.msum + k : nullptr;
-    run_passes<C>(pf, s, g, K);
+    passes<C>(pf, s, g, a, K);
   }
   IBM_LAUNCH(pf, "pois_refine_stats", s,
              (k_refine_stats<<<1, 64, 0, s>>>(a.rmax, nref, K.gate_tol, 1.0 / inv_adt, a.stats,

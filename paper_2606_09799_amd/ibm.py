@@ -26,6 +26,7 @@ IBM_OK, IBM_EINVAL, IBM_ENOMEM, IBM_EHIP, IBM_ECAPACITY = 0, -1, -2, -3, -4
 IBM_ENONFINITE, IBM_ECFL, IBM_EGEOM, IBM_ECOMPAT = -5, -6, -7, -8
 FLAG_CAPACITY, FLAG_NONFINITE, FLAG_GEOM, FLAG_REFINE = 1, 2, 4, 8
 FLAG_CFL, FLAG_COMPAT = 16, 32
+IBM_REFINE_STATS = 6
 IBM_FP64, IBM_MIXED = 0, 1
 IBM_RK2CN, IBM_AB2CN = 0, 1
 IBM_Q_NONE, IBM_Q_UNIFORM, IBM_Q_ENERGY = 0, 1, 2
@@ -118,6 +119,8 @@ _check = _sig("ibm_check", c_int32, c_void_p, POINTER(c_uint32))
 _noslip = _sig("ibm_noslip_error", c_int32, c_void_p, c_void_p, c_void_p, c_void_p,
                POINTER(c_double))
 _pressure_cb = _sig("ibm_pressure_cb", c_int32, c_void_p, c_void_p, c_void_p, c_int64)
+_divergence = _sig("ibm_divergence", c_int32, c_void_p, c_void_p, c_void_p, c_void_p,
+                   POINTER(c_double))
 _strerror = _sig("ibm_strerror", c_char_p, c_int32)
 _profile = _sig("ibm_profile", c_int32, c_void_p, c_int32, c_char_p)
 _profile_read = _sig("ibm_profile_read", c_int32, c_void_p, c_char_p, c_int32,
@@ -130,7 +133,7 @@ EXPORTS = ("ibm_create", "ibm_destroy", "ibm_set_stream", "ibm_body_rigid", "ibm
            "ibm_batch_create", "ibm_batch_destroy", "ibm_batch_context", "ibm_batch_step",
            "ibm_batch_check", "ibm_batch_set_plan", "ibm_batch_get_plan", "ibm_batch_tune",
            "ibm_batch_tune_scratch_bytes", "poisson_solve_static",
-           "ibm_noslip_error", "ibm_pressure_cb")
+           "ibm_noslip_error", "ibm_pressure_cb", "ibm_divergence")
 COEF_STRIDE = 18
 BATCH_SERIAL, BATCH_STREAMS, BATCH_GRAPH, BATCH_PLAN = 0, 1, 2, 3
 _MODE_NAMES = {BATCH_STREAMS: "streams", BATCH_GRAPH: "graph"}
@@ -345,6 +348,15 @@ def ibm_mass_rhs(ctx, u, v, w, alpha_dt, rhs, qf=None, p=None):
                   _dev(qf, torch.float64, None, "qf")), "ibm_mass_rhs")
 
 
+def ibm_divergence(ctx, u, v, w):
+    """Post-projection divergence: (max over C_F of |D u - q_F|, q_F)."""
+    out = (c_double * 2)()
+    _ok(_divergence(ctx.handle, _dev(u, torch.float64, ctx.cells, "u"),
+                    _dev(v, torch.float64, ctx.vfaces, "v"),
+                    _dev(w, torch.float64, ctx.cells, "w"), out), "ibm_divergence")
+    return out[0], out[1]
+
+
 def poisson_solve_static(nx, ny, nz, lx, lz, y_faces, rhs, phi):
     """poisson_solve_static: the FP64 Poisson solve with no context, its
     workspace in the library's static device array (nothing is allocated);
@@ -382,14 +394,19 @@ def ibm_step(ctx, u, v, w, p, bodies, dt, h=None):
     _ok(_step(ctx.handle, ctypes.byref(st), arr, n, float(dt)), "ibm_step")
 
 
-def ibm_refine_stats(ctx, reset=False, after_first=False):
+def ibm_refine_stats(ctx, reset=False, after_first=False, initial=False):
     """Mixed form: (Poisson solves, FP64-residual corrections, largest final
     max|rhs - L_c phi| * alpha_dt) since the last reset (synchronises); with
-    after_first also the largest residual left by the first correction."""
-    out = (c_double * 4)()
+    after_first also the largest residual left by the first correction; with
+    initial also the largest and the mean residual of the uncorrected solve."""
+    out = (c_double * IBM_REFINE_STATS)()
     _ok(_refine_stats(ctx.handle, out, 1 if reset else 0), "ibm_refine_stats")
     r = (int(out[0]), int(out[1]), float(out[2]))
-    return r + (float(out[3]),) if after_first else r
+    if after_first:
+        r += (float(out[3]),)
+    if initial:
+        r += (float(out[4]), float(out[5]) / max(1, int(out[0])))
+    return r
 
 
 def ibm_check(ctx):
@@ -433,7 +450,8 @@ class Batch:
     u, v, w, p (device tensors, kept by pointer), motion ("rigid" or
     "deform"), ref, xyz, vel, tri (device tensors of the body)."""
 
-    def __init__(self, sims, precision="fp64", scheme="rk2", use_q=True):
+    def __init__(self, sims, precision="fp64", scheme="rk2", use_q=True, mixed_poisson="fp64",
+                 refine_tol=0.0):
         n = len(sims)
         self.n = n
         pdtype = torch.float32 if precision == "mixed" else torch.float64
@@ -451,8 +469,8 @@ class Batch:
             opts[s] = IbmOpts(IBM_MIXED if precision == "mixed" else IBM_FP64,
                               IBM_RK2CN if scheme == "rk2" else IBM_AB2CN, float(d["re"]),
                               float(d["dpdx"]), 0,
-                              IBM_Q_ENERGY if use_q == "energy" else (1 if use_q else 0), 0, 0.0,
-                              0, 0)
+                              IBM_Q_ENERGY if use_q == "energy" else (1 if use_q else 0), 0,
+                              float(refine_tol), 1 if mixed_poisson == "refined" else 0, 0)
             cells, vf = nx * ny * nz, nx * (ny + 1) * nz
             st = IbmState(_dev(d["u"], torch.float64, cells, "u"),
                           _dev(d["v"], torch.float64, vf, "v"),

@@ -24,8 +24,8 @@ import numpy as np
 __all__ = [
     "uniform_faces", "tanh_faces", "icosphere", "plate_mesh",
     "rigid_coef", "sphere_translation", "plate_heave_pitch",
-    "deform_vertex_data", "deform_coef", "splitmix64_uniform",
-    "initial_velocity", "Workload", "config", "CONFIG_NAMES", "batch_sim", "batch",
+    "deform_vertex_data", "deform_coef", "splitmix64_uniform", "splitmix64_uniform_torch",
+    "initial_velocity", "initial_velocity_torch", "Workload", "config", "CONFIG_NAMES", "batch_sim", "batch",
 ]
 
 # --------------------------------------------------------------------------
@@ -188,6 +188,54 @@ def splitmix64_uniform(seed: int, comp: int, n: int, start: int = 0) -> np.ndarr
     return (z >> np.uint64(11)).astype(np.float64) * (1.0 / 9007199254740992.0)
 
 
+def splitmix64_uniform_torch(seed: int, comp: int, n: int, device, start: int = 0):
+    """The same values as splitmix64_uniform, computed by torch on `device`
+    (int64 arithmetic wraps like uint64; logical right shifts are arithmetic
+    shifts masked to the low 64-k bits)."""
+    import torch
+
+    def srl(z, k):
+        return (z >> k) & ((1 << (64 - k)) - 1)
+
+    def c64(v):  # a uint64 constant as the int64 with the same bits
+        return v - (1 << 64) if v >= (1 << 63) else v
+
+    idx = torch.arange(start, start + n, dtype=torch.int64, device=device)
+    z = idx | ((int(seed) << 34) | (int(comp) << 32))
+    z = z + c64(0x9E3779B97F4A7C15)
+    z = (z ^ srl(z, 30)) * c64(0xBF58476D1CE4E5B9)
+    z = (z ^ srl(z, 27)) * c64(0x94D049BB133111EB)
+    z = z ^ srl(z, 31)
+    return srl(z, 11).to(torch.float64) * (1.0 / 9007199254740992.0)
+
+
+def initial_velocity_torch(nx, ny, nz, y_faces, uc=1.0, amp=0.01, seed=1, half=1.0,
+                           device="cpu"):
+    """initial_velocity computed by torch on `device`, plane by plane (the
+    same values bit for bit; flat tensors u, v, w)."""
+    import torch
+    yf = np.asarray(y_faces, np.float64)
+    yh = ((yf[:-1] + yf[1:]) * 0.5) / half
+    prof = torch.from_numpy(uc * (1.0 - yh * yh)).to(device)
+    plane = nx * nz
+    u = torch.empty(ny * plane, dtype=torch.float64, device=device)
+    v = torch.zeros((ny + 1) * plane, dtype=torch.float64, device=device)
+    w = torch.empty(ny * plane, dtype=torch.float64, device=device)
+    step = max(1, (1 << 26) // plane)  # planes per chunk
+    for j0 in range(0, ny, step):
+        j1 = min(ny, j0 + step)
+        a, b = j0 * plane, j1 * plane
+        xi = splitmix64_uniform_torch(seed, 0, b - a, device, start=a)
+        u[a:b] = prof[j0:j1].repeat_interleave(plane) + amp * (2.0 * xi - 1.0)
+        w[a:b] = amp * (2.0 * splitmix64_uniform_torch(seed, 2, b - a, device, start=a) - 1.0)
+        jv1 = min(j1, ny - 1)
+        if jv1 > j0:   # interior v planes j = 1..ny-1, counter index (j-1)*plane + ...
+            av, bv = j0 * plane, jv1 * plane
+            v[plane + av:plane + bv] = amp * (2.0 * splitmix64_uniform_torch(
+                seed, 1, bv - av, device, start=av) - 1.0)
+    return u, v, w
+
+
 def initial_velocity(nx, ny, nz, y_faces, uc=1.0, amp=0.01, seed=1, half=1.0):
     """Laminar profile u = uc (1 - (y/half)^2) at the u-node heights (walls at
     y = -half and +half) plus a seeded uniform perturbation amp*(2 xi - 1) on
@@ -245,6 +293,10 @@ class Workload:
     def fields(self):
         return initial_velocity(self.nx, self.ny, self.nz, self.y_faces,
                                 self.uc, self.amp, self.seed, self.half)
+
+    def fields_torch(self, device):
+        return initial_velocity_torch(self.nx, self.ny, self.nz, self.y_faces, self.uc,
+                                      self.amp, self.seed, self.half, device)
 
 
 def _sphere_body(level, radius, c0, U):
