@@ -968,10 +968,12 @@ __device__ __forceinline__ void excess_row(double& a, double& e, double& g, doub
   g = -gp * k2;
 }
 
-// UNI: every segment holds exactly YL rows (ny = P YL), so the row loops
-// are straight-line code.
-template <typename C, bool UNI, typename CO>
-__global__ __launch_bounds__(1024) void k_tri_y(PoisK<C> K) {
+// SL: rows per segment (at most; 6, or 12 where 6-row segments would need
+// more than 64 separators, so that a mode's separators still fit one
+// wavefront).  UNI: every segment holds exactly SL rows (ny = P SL), so the
+// row loops are straight-line code.
+template <typename C, bool UNI, typename CO, int SL>
+__global__ __launch_bounds__(SL == YL ? 1024 : 512) void k_tri_y(PoisK<C> K) {
   using RO = typename RealOf<CO>::T;
   if (gated(K)) return;
   extern __shared__ __align__(16) unsigned char smraw[];
@@ -995,16 +997,16 @@ __global__ __launch_bounds__(1024) void k_tri_y(PoisK<C> K) {
   // past the last mode the last mode's system: every lane loads and solves
   // unconditionally, only valid lanes store
   const int sx = active ? s : P - 1;
-  const int lo = UNI ? sx * YL : sx * K.yL + (sx < K.yr ? sx : K.yr);
-  const int len = UNI ? YL : K.yL + (sx < K.yr ? 1 : 0);
+  const int lo = UNI ? sx * SL : sx * K.yL + (sx < K.yr ? sx : K.yr);
+  const int len = UNI ? SL : K.yL + (sx < K.yr ? 1 : 0);
   const int m = len - 1;  // interior rows (at least 2); row lo+m is the separator
   const bool z0 = (q == 0) && lo == 0;  // the (0,0) mode's first row: identity, right side 0
   const int pl = pq < g.nxh ? pq : g.nxh - 1;
   const double lam = K.lamx[pl] + K.lamz[kq];
   const C* __restrict__ Xl = K.spec + (int64_t)kq * K.ldx + pl;
-  double xr[YL], xi[YL], ah[YL - 1], ch[YL - 1];
+  double xr[SL], xi[SL], ah[SL - 1], ch[SL - 1];
 #pragma unroll
-  for (int e = 0; e < YL; ++e) {
+  for (int e = 0; e < SL; ++e) {
     const int row = (UNI || lo + e < g.ny) ? lo + e : g.ny - 1;
     const C v = Xl[(int64_t)row * nm];
     xr[e] = (double)v.x;
@@ -1020,7 +1022,7 @@ __global__ __launch_bounds__(1024) void k_tri_y(PoisK<C> K) {
     double pr = 0.0, pi = 0.0;
     if (lb == 0 && active) {
 #pragma unroll
-      for (int e = 0; e < YL; ++e)
+      for (int e = 0; e < SL; ++e)
         if (UNI || e < len) {
           pr += g.dy[lo + e] * xr[e];
           pi += g.dy[lo + e] * xi[e];
@@ -1040,17 +1042,17 @@ __global__ __launch_bounds__(1024) void k_tri_y(PoisK<C> K) {
       Mr *= K.inv_sum_dy;
       Mi *= K.inv_sum_dy;
 #pragma unroll
-      for (int e = 0; e < YL; ++e) {
+      for (int e = 0; e < SL; ++e) {
         xr[e] -= Mr;
         xi[e] -= Mi;
       }
     }
     __syncthreads();
   }
-  double zr = xr[YL - 1], zi = xi[YL - 1];
+  double zr = xr[SL - 1], zi = xi[SL - 1];
   if (!UNI) {
 #pragma unroll
-    for (int e = 0; e < YL - 1; ++e)
+    for (int e = 0; e < SL - 1; ++e)
       if (e == m) {
         zr = xr[e];
         zi = xi[e];
@@ -1061,9 +1063,9 @@ __global__ __launch_bounds__(1024) void k_tri_y(PoisK<C> K) {
   // in excess form (see excess_row): with u = 1 + ct and tau = 1 + at + ct
   // carried, every pivot and excess is a sum of terms of one sign
   double atp = -1.0, up = 1.0, tp = 0.0, dr = 0.0, di = 0.0;
-  double tau[YL - 1];
+  double tau[SL - 1];
 #pragma unroll
-  for (int e = 0; e < YL - 1; ++e)
+  for (int e = 0; e < SL - 1; ++e)
     if (UNI || e < m) {
       const int j = lo + e;
       const bool idr = (e == 0 && z0);  // the gauge row: identity, right side 0
@@ -1084,7 +1086,7 @@ __global__ __launch_bounds__(1024) void k_tri_y(PoisK<C> K) {
   // sg_e = 1 + ah_e + ch_e
   double ahl = 0.0, dlr = 0.0, dli = 0.0, sgl = 0.0, sg = 0.0;  // row m-1; sg: row e
 #pragma unroll
-  for (int e = YL - 2; e >= 0; --e)
+  for (int e = SL - 2; e >= 0; --e)
     if (UNI || e < m) {
       if (e == m - 1) {
         ahl = ah[e];
@@ -1170,7 +1172,7 @@ __global__ __launch_bounds__(1024) void k_tri_y(PoisK<C> K) {
   const double zLr = (s > 0) ? A(9, s - 1, lb) : 0.0;
   const double zLi = (s > 0) ? A(10, s - 1, lb) : 0.0;
 #pragma unroll
-  for (int e = 0; e < YL - 1; ++e)
+  for (int e = 0; e < SL - 1; ++e)
     if (UNI || e < m) {
       xr[e] = xr[e] - ah[e] * zLr - ch[e] * zRr;
       xi[e] = xi[e] - ah[e] * zLi - ch[e] * zRi;
@@ -1183,7 +1185,7 @@ __global__ __launch_bounds__(1024) void k_tri_y(PoisK<C> K) {
     double pr = 0.0, pi = 0.0;
     if (lb == 0) {
 #pragma unroll
-      for (int e = 0; e < YL; ++e)
+      for (int e = 0; e < SL; ++e)
         if (UNI || e < len) {
           const double dyj = g.dy[lo + e];
           pr += dyj * (e < m ? xr[e] : zr);
@@ -1205,7 +1207,7 @@ __global__ __launch_bounds__(1024) void k_tri_y(PoisK<C> K) {
       Mr *= K.inv_sum_dy;
       Mi *= K.inv_sum_dy;
 #pragma unroll
-      for (int e = 0; e < YL - 1; ++e)
+      for (int e = 0; e < SL - 1; ++e)
         if (UNI || e < m) {
           xr[e] -= Mr;
           xi[e] -= Mi;
@@ -1222,7 +1224,7 @@ __global__ __launch_bounds__(1024) void k_tri_y(PoisK<C> K) {
     CO* __restrict__ X = (K.spec_out ? static_cast<CO*>(K.spec_out) : reinterpret_cast<CO*>(K.spec)) +
                          (int64_t)kq * K.ldx_out + pq;
 #pragma unroll
-    for (int e = 0; e < YL; ++e)
+    for (int e = 0; e < SL; ++e)
       if (UNI || e < len) {
         const double vr = (e < m) ? xr[e] : zr;
         const double vi = (e < m) ? xi[e] : zi;
@@ -1607,6 +1609,19 @@ static void run_passes(Prof* pf, hipStream_t s, const GridView& g, PoisK<C> K, P
   pass_shape<CI>(g, KI);
   const int rows = K.rows, tp = K.tp;
   line_plan(g.ny, false, YL, &K.yP, &K.yL, &K.yr);
+  // more than 64 separators of 6-row segments: 12-row segments when that
+  // brings a mode's separators into one wavefront
+  int sl = YL;
+  if (K.yP > 64) {
+    int P2, L2, r2;
+    line_plan(g.ny, false, 2 * YL, &P2, &L2, &r2);
+    if (P2 <= 64) {
+      sl = 2 * YL;
+      K.yP = P2;
+      K.yL = L2;
+      K.yr = r2;
+    }
+  }
   K.yPP = 1;
   while (K.yPP < K.yP) K.yPP <<= 1;
   // separators of one mode in one wavefront when they fit; else block-wide.
@@ -1668,12 +1683,18 @@ static void run_passes(Prof* pf, hipStream_t s, const GridView& g, PoisK<C> K, P
     IBM_LAUNCH(pf, "pois_fftz_fwd", s, (k_fftz4s<C, false, 4><<<z1kgrid, 256, 0, s>>>(K)));
   else
     IBM_LAUNCH(pf, "pois_fftz_fwd", s, (k_fftz<C, false><<<zgrid, 256, zsh, s>>>(K)));
-  if (ywave && K.yr == 0 && K.yL == YL)
+  if (ywave && sl == 2 * YL && K.yr == 0 && K.yL == sl)
     IBM_LAUNCH(pf, "pois_tri_y", s,
-               (k_tri_y<C, true, CI><<<ywblocks, K.ytl * K.yPP, ysh, s>>>(K)));
+               (k_tri_y<C, true, CI, 2 * YL><<<ywblocks, K.ytl * K.yPP, ysh, s>>>(K)));
+  else if (ywave && sl == 2 * YL)
+    IBM_LAUNCH(pf, "pois_tri_y", s,
+               (k_tri_y<C, false, CI, 2 * YL><<<ywblocks, K.ytl * K.yPP, ysh, s>>>(K)));
+  else if (ywave && K.yr == 0 && K.yL == YL)
+    IBM_LAUNCH(pf, "pois_tri_y", s,
+               (k_tri_y<C, true, CI, YL><<<ywblocks, K.ytl * K.yPP, ysh, s>>>(K)));
   else if (ywave)
     IBM_LAUNCH(pf, "pois_tri_y", s,
-               (k_tri_y<C, false, CI><<<ywblocks, K.ytl * K.yPP, ysh, s>>>(K)));
+               (k_tri_y<C, false, CI, YL><<<ywblocks, K.ytl * K.yPP, ysh, s>>>(K)));
   else
     IBM_LAUNCH(pf, "pois_tri_y", s, (k_tri_y_blk<C, CI><<<yblocks, K.ytl * K.yP, ysh, s>>>(K)));
   if (z256)

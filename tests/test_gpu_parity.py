@@ -218,16 +218,19 @@ def test_poisson_parity(name):
     assert abs(np.sum(got * dV)) < 1e-12 * np.sum(np.abs(got) * dV)
 
 
-@pytest.mark.parametrize("shape", [(256, 12, 16), (16, 12, 256), (16, 528, 16), (16, 8, 512),
-                                   (24, 6, 1024), (16, 192, 16), (24, 100, 16)])
+@pytest.mark.parametrize("shape", [(256, 12, 16), (16, 12, 256), (16, 800, 8), (16, 528, 16),
+                                   (16, 500, 16), (16, 8, 512), (24, 6, 1024), (16, 192, 16),
+                                   (24, 100, 16)])
 def test_poisson_parity_kernel_paths(shape):
     """Shapes that select the other kernel paths, compared with the oracle
     value by value: length-256 x transforms (four-step), length-256 z
     transforms (four-step), a wall-normal solve with more than 64
-    separators per mode (block-wide reduction), length-512 and -1024 z
-    transforms (16 x 16 x R; 24 x-points: a partial last tile of modes), the
-    wall-normal solve of 32 equal 6-row segments (ny = 192, straight-line
-    rows) and of 17 unequal ones (ny = 100); stretched y."""
+    separators per mode even in 12-row segments (ny = 800: block-wide
+    reduction), the wavefront solve in 44 equal 12-row segments (ny = 528)
+    and in 42 unequal ones of at most 12 rows (ny = 500), length-512 and
+    -1024 z transforms (16 x 16 x R; 24 x-points: a partial last tile of
+    modes), the wall-normal solve of 32 equal 6-row segments (ny = 192,
+    straight-line rows) and of 17 unequal ones (ny = 100); stretched y."""
     import workloads
     nx, ny, nz = shape
     wl = workloads.Workload("paths", nx, ny, nz, 2 * np.pi, np.pi, workloads.tanh_faces(ny),
@@ -393,12 +396,13 @@ def test_c2_full_size_tags_and_step_properties():
 
 
 @pytest.mark.parametrize("shape,stretch", [((32, 96, 16), 2.5), ((16, 390, 16), 2.5),
-                                           ((16, 768, 8), 2.0)])
+                                           ((16, 768, 8), 2.0), ((16, 800, 8), 2.0)])
 def test_poisson_residual_at_the_rounding_floor(shape, stretch):
     """The discrete residual max|rhs - L_c phi| of the direct solve on
     strongly stretched grids is that of the oracle's own solve (paper
     Eq. elliptic_mod; its size is the post-projection divergence over alpha
-    dt): wall-normal solves of 16, 65 and 128 separators per mode.  A
+    dt): wall-normal solves of 16 separators per mode (6-row segments), 33
+    and 64 (12-row segments) and 67 (12-row segments, block-wide).  A
     separator system formed and reduced from the diagonal b = lambda - a - c
     loses digits for the low modes where a + c is large (near the walls);
     such a solve left about 50 times the oracle's residual here."""
