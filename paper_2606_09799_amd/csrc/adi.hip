@@ -34,7 +34,7 @@ struct LineK {
   const uint32_t* mask;
   T* sa;              // scratch for segments holding identity rows
   T* sc;
-  const T* tab;       // mask-free elimination tables [LINE_NTAB][P][LMAX]
+  const T* tab;       // mask-free elimination tables [LINE_NTAB][P][LINE_TLD]
   int n, P, L, r;     // rows, segments, base length, segments with L+1 rows
   int cyc;
   T a, b, c;          // constant coefficients (x, z)
@@ -118,7 +118,7 @@ __global__ __launch_bounds__(MODE == 0 ? 256 : 1024) void k_line(LineK<T> K) {
   // (consecutive lanes on consecutive words)
   for (int q = tid; q < LINE_NTAB * tP * LMAX; q += blockDim.x) {
     const int qe = q / tP, ss = q % tP, qq = qe / LMAX, ee = qe % LMAX;
-    tabs[q] = K.tab[((size_t)qq * P + ss) * LMAX + ee];
+    tabs[q] = K.tab[((size_t)qq * P + ss) * LINE_TLD + ee];
   }
   __syncthreads();
   int lb, s;
@@ -462,7 +462,7 @@ void k_line_xw(LineK<T> K) {
   T* tab = lds;                      // [LINE_NTAB][LMAX]
   T* rows = lds + LINE_NTAB * LMAX + (size_t)wv * RW * RS;
   for (int q = threadIdx.x; q < LINE_NTAB * LMAX; q += blockDim.x)
-    tab[q] = K.tab[(size_t)(q / LMAX) * P * LMAX + q % LMAX];
+    tab[q] = K.tab[(size_t)(q / LMAX) * P * LINE_TLD + q % LMAX];
   __syncthreads();
   const int64_t nl = (int64_t)K.nj * K.nz;  // rows of the sweep
   const int64_t ng = (nl + RW - 1) / RW;    // groups
@@ -656,7 +656,8 @@ template <typename T, int MODE, int SL, int TL>
 __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(SL == 12 ? 5 : 1)))
 void k_line_col(LineK<T> K) {
   // TL lines per block: 16, or 32 in FP32 (a wavefront's loads then cover
-  // 128-byte row pieces in both)
+  // 128-byte row pieces in both), and 32 with the long segments (24 or 32
+  // rows) of the large planes
   constexpr int SP = TL + 1;   // padded stride of the separator arrays
   extern __shared__ __align__(16) unsigned char ldsraw[];
   T* lds = reinterpret_cast<T*>(ldsraw);
@@ -669,7 +670,7 @@ void k_line_col(LineK<T> K) {
   uint32_t* mws = reinterpret_cast<uint32_t*>(X + 4 * PP * SP);  // [P][SL] mask words
   for (int q = tid; q < LINE_NTAB * tP * SL; q += blockDim.x) {
     const int qe = q / tP, ss = q % tP, qq = qe / SL, ee = qe % SL;
-    tabs[q] = K.tab[((size_t)qq * P + ss) * LMAX + ee];  // global tables: LMAX per segment
+    tabs[q] = K.tab[((size_t)qq * P + ss) * LINE_TLD + ee];  // global: LINE_TLD per segment
   }
   const int lb = tid % TL, s = tid / TL;
   const bool active = s < P;
@@ -947,15 +948,20 @@ static void launch_line(Prof* pf, hipStream_t s, LineK<T> K, const char* name) {
     IBM_LAUNCH(pf, name, s, (k_line_xw<T><<<(unsigned)blocks, 256, xshm, s>>>(K)));
   } else if (K.mode == 0) {
     IBM_LINE(0);
-  } else if (K.r == 0 && (K.L == LMAX || (K.mode == 2 && K.L == 12)) && K.nx % 16 == 0 &&
-             K.P <= 64 && (!K.cyc || (K.P & (K.P - 1)) == 0) &&
+  } else if (K.r == 0 &&
+             (K.L == LMAX || (K.mode == 2 && (K.L == 12 || K.L == 24)) ||
+              (K.mode == 1 && K.L == 32)) &&
+             K.nx % (K.L > LMAX ? 32 : 16) == 0 && K.P <= 64 &&
+             (!K.cyc || (K.P & (K.P - 1)) == 0) &&
              (K.mode == 1 ? (int64_t)K.nx : K.plane) * 64 * 8 < ((int64_t)1 << 31)) {
     // column sweep: 16 lines per block (32 in FP32 where the block stays
-    // within 1024 threads), the separators solved per wavefront
+    // within 1024 threads, and with the long segments of the large planes),
+    // the separators solved per wavefront
     int pp = 1;
     while (pp < K.P) pp <<= 1;
     K.PP = pp;
-    const int tl = (sizeof(T) == sizeof(float) && pp <= 32 && K.nx % 32 == 0) ? 32 : 16;
+    const int tl = (K.L > LMAX || (sizeof(T) == sizeof(float) && pp <= 32 && K.nx % 32 == 0))
+                       ? 32 : 16;
     const int ct = tl * pp;
     const size_t cshm = sizeof(T) * (LINE_NTAB * (size_t)(K.tab1 ? 1 : K.P) * K.L +
                                      7 * (size_t)pp * (tl + 1)) +
@@ -971,6 +977,16 @@ static void launch_line(Prof* pf, hipStream_t s, LineK<T> K, const char* name) {
     }                                                                                         \
     IBM_LAUNCH(pf, name, s, (k_line_col<T, M, SL_, 16><<<cgrid, ct, cshm, s>>>(K)));          \
   } while (0)
+    if constexpr (sizeof(T) == sizeof(float)) {  // the long segments (FP32 plans only)
+      if (K.L == 32) {
+        IBM_LAUNCH(pf, name, s, (k_line_col<T, 1, 32, 32><<<cgrid, ct, cshm, s>>>(K)));
+        return;
+      }
+      if (K.L == 24) {
+        IBM_LAUNCH(pf, name, s, (k_line_col<T, 2, 24, 32><<<cgrid, ct, cshm, s>>>(K)));
+        return;
+      }
+    }
     if (K.mode == 1)
       IBM_COL(1, LMAX);
     else if (K.L == 12)
@@ -1007,7 +1023,8 @@ static void adi_periodic(Prof* pf, hipStream_t s, const GridView& g, int comp, i
   K.mode = mode;
   K.n = (mode == 0) ? g.nx : g.nz;
   K.cyc = 1;
-  line_plan(K.n, true, &K.P, &K.L, &K.r);
+  line_plan(K.n, true, mode == 0 ? LINE_LMAX : z_seg_len(K.n, g.nx, sizeof(T) == sizeof(float)),
+            &K.P, &K.L, &K.r);
   K.a = (T)t.a;
   K.b = (T)t.b;
   K.c = (T)t.c;
@@ -1042,7 +1059,7 @@ static void adi_wall(Prof* pf, hipStream_t s, const GridView& g, void* d, double
   K.u = u;
   K.n = t.n;
   K.cyc = 0;
-  line_plan(K.n, false, wall_seg_len(K.n), &K.P, &K.L, &K.r);
+  line_plan(K.n, false, wall_seg_len(K.n, g.nx, sizeof(T) == sizeof(float)), &K.P, &K.L, &K.r);
   K.A = static_cast<const T*>(f ? (const void*)t.a32 : (const void*)t.a);
   K.B = static_cast<const T*>(f ? (const void*)t.b32 : (const void*)t.b);
   K.C = static_cast<const T*>(f ? (const void*)t.c32 : (const void*)t.c);

@@ -276,7 +276,7 @@ static int build_tables(ibm_ctx* c, double beta) {
                     std::vector<double>& out) {
     int P, L, r;
     line_plan(n, cyc, lmax, &P, &L, &r);
-    std::vector<double> t(LINE_NTAB * (size_t)P * LINE_LMAX, 0.0);
+    std::vector<double> t(LINE_NTAB * (size_t)P * LINE_TLD, 0.0);
     for (int s = 0; s < P; ++s) {
       const int lo = s * L + std::min(s, r);
       const int m = L + (s < r ? 1 : 0) - 1;
@@ -287,9 +287,9 @@ static int build_tables(ibm_ctx* c, double beta) {
         const double inv = 1.0 / (B[i] - A[i] * ct);
         at = (e == 0) ? A[i] * inv : -A[i] * at * inv;
         ct = C[i] * inv;
-        t[(0 * P + s) * LINE_LMAX + e] = inv;
-        t[(1 * P + s) * LINE_LMAX + e] = ct;
-        t[(4 * P + s) * LINE_LMAX + e] = A[i];
+        t[(0 * P + s) * LINE_TLD + e] = inv;
+        t[(1 * P + s) * LINE_TLD + e] = ct;
+        t[(4 * P + s) * LINE_TLD + e] = A[i];
         va[e] = at;
         vc[e] = ct;
       }
@@ -302,27 +302,28 @@ static int build_tables(ibm_ctx* c, double beta) {
           ah = va[e] - vc[e] * ah;
           ch = -vc[e] * ch;
         }
-        t[(2 * P + s) * LINE_LMAX + e] = ah;
-        t[(3 * P + s) * LINE_LMAX + e] = ch;
+        t[(2 * P + s) * LINE_TLD + e] = ah;
+        t[(3 * P + s) * LINE_TLD + e] = ch;
       }
     }
     out.insert(out.end(), t.begin(), t.end());
   };
-  auto constseg = [&](int n, const CyclicTab& t, std::vector<double>& out) {
+  auto constseg = [&](int n, int lmax, const CyclicTab& t, std::vector<double>& out) {
     std::vector<double> A(n, t.a), B(n, t.b), C(n, t.c);
-    segtab(n, true, LINE_LMAX, A.data(), B.data(), C.data(), out);
+    segtab(n, true, lmax, A.data(), B.data(), C.data(), out);
   };
   std::vector<double> hx, hz, hy0, hy1, sx, sz, sy0, sy1;
   cyclic(nx, c->g.dx, &c->ctx_x, hx);
   cyclic(nz, c->g.dz, &c->ctx_z, hz);
   ysys(false, hy0, &c->yt[0]);
   ysys(true, hy1, &c->yt[1]);
-  constseg(nx, c->ctx_x, sx);
-  constseg(nz, c->ctx_z, sz);
+  constseg(nx, LINE_LMAX, c->ctx_x, sx);
+  constseg(nz, z_seg_len(nz, nx, c->fp32), c->ctx_z, sz);
   for (int q = 0; q < 2; ++q) {
     const int n = c->yt[q].n;
     const std::vector<double>& hy = q ? hy1 : hy0;
-    segtab(n, false, wall_seg_len(n), hy.data(), hy.data() + n, hy.data() + 2 * n, q ? sy1 : sy0);
+    segtab(n, false, wall_seg_len(n, nx, c->fp32), hy.data(), hy.data() + n, hy.data() + 2 * n,
+           q ? sy1 : sy0);
   }
   for (auto* v : {&hx, &hz, &hy0, &hy1, &sx, &sz, &sy0, &sy1}) h.insert(h.end(), v->begin(), v->end());
   if ((int64_t)h.size() > c->tabcap) {
@@ -600,11 +601,11 @@ int ibm_create(const ibm_grid* gr, const ibm_opts* o, void* stream, ibm_ctx** ou
     int P, L, r, segs = 0;
     line_plan(nx, true, &P, &L, &r);
     segs += P;
-    line_plan(nz, true, &P, &L, &r);
+    line_plan(nz, true, z_seg_len(nz, nx, c->fp32), &P, &L, &r);
     segs += P;
-    line_plan(ny, false, wall_seg_len(ny), &P, &L, &r);
+    line_plan(ny, false, wall_seg_len(ny, nx, c->fp32), &P, &L, &r);
     segs += 2 * P;
-    c->tabcap = 4 * (int64_t)(nx + nz) + 10 * (int64_t)ny + LINE_NTAB * (int64_t)segs * LINE_LMAX;
+    c->tabcap = 4 * (int64_t)(nx + nz) + 10 * (int64_t)ny + LINE_NTAB * (int64_t)segs * LINE_TLD;
     TRY(dalloc(c, &c->tabmem, c->tabcap));
     if (c->fp32) TRY(dalloc(c, &c->tabmem32, c->tabcap));
     for (int k = 0; k < ibm_ctx::NTSTAGE; ++k) {

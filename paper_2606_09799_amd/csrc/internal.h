@@ -55,7 +55,7 @@ struct CyclicTab {
   double a, b, c;        // constant sub/main/super diagonal
   double ratio;          // beta_corner / gamma
   double fden_inv;       // 1 / (1 + z_0 + ratio z_{n-1})
-  const double* seg;     // partitioned-solve tables [LINE_NTAB][P][LINE_LMAX]
+  const double* seg;     // partitioned-solve tables [LINE_NTAB][P][LINE_TLD]
   const float* seg32;    // the same tables in FP32 (mixed form)
 };
 
@@ -68,17 +68,19 @@ struct YTab {
   const double* c;   // super-diagonal
   const double* cp;  // Thomas c' of the mask-free system
   const double* inv; // 1/pivot of the mask-free system
-  const double* seg; // partitioned-solve tables [LINE_NTAB][P][LINE_LMAX]
+  const double* seg; // partitioned-solve tables [LINE_NTAB][P][LINE_TLD]
   // FP32 copies of a, b, c and seg (mixed form)
   const float *a32, *b32, *c32, *seg32;
   int n, j0;
 };
 
 // Segmentation of a line of n rows for the partitioned solves: P balanced
-// segments of at most LINE_LMAX rows (the first r segments hold L+1 rows,
-// the others L); cyclic lines use at least 3 segments.  Shared by the
-// kernels and the host code that builds their tables.
+// segments of at most lmax rows (the first r segments hold L+1 rows, the
+// others L); cyclic lines use at least 3 segments.  Shared by the kernels
+// and the host code that builds their tables.  The mask-free elimination
+// tables hold LINE_TLD entries per segment whatever its length.
 constexpr int LINE_LMAX = 16;
+constexpr int LINE_TLD = 32;
 constexpr int LINE_NTAB = 5;  // tables per segment row (see the partitioned solve)
 inline void line_plan(int n, bool cyc, int lmax, int* P, int* L, int* r) {
   int p = (n + lmax - 1) / lmax;
@@ -90,15 +92,27 @@ inline void line_plan(int n, bool cyc, int lmax, int* P, int* L, int* r) {
 inline void line_plan(int n, bool cyc, int* P, int* L, int* r) {
   line_plan(n, cyc, LINE_LMAX, P, L, r);
 }
-// Segment length of the wall-normal lines: 12 rows where that cuts a line of
-// n rows into a power of two of segments (4 to 64: the separator reduction
-// then has no idle lanes, and the per-thread arrays are shorter), else
-// LINE_LMAX.  The tables and the launch both take their plan from here.
-inline int wall_seg_len(int n) {
-  if (n % 12 == 0) {
-    const int p = n / 12;
-    if (p >= 4 && p <= 64 && (p & (p - 1)) == 0) return 12;
-  }
+inline bool pow2_in(int p, int lo, int hi) { return p >= lo && p <= hi && (p & (p - 1)) == 0; }
+// Segment length of the wall-normal lines (nx x-points per line row): 12
+// rows where that cuts a line of n rows into a power of two of segments (4
+// to 64: the separator reduction then has no idle lanes, and the
+// per-thread arrays are shorter); 24 rows where 12-row segments would number
+// 64 and 24-row ones a power of two (32 lines per block instead of 16, so
+// that each row access of a block covers twice the bytes of one plane: on
+// large planes every row of a line lies in another page; FP32 line data
+// only, the FP64 solve would not fit its registers); else LINE_LMAX.  The
+// tables and the launch both take their plan from here.
+inline int wall_seg_len(int n, int nx, bool fp32) {
+  if (fp32 && n % 24 == 0 && n / 12 == 64 && nx % 32 == 0) return 24;
+  if (n % 12 == 0 && pow2_in(n / 12, 4, 64)) return 12;
+  return LINE_LMAX;
+}
+// Segment length of the periodic z lines: 32 rows where 16-row segments
+// would number more than 32 and 32-row ones a power of two (32 lines per
+// block instead of 16: 128-byte row pieces; FP32 line data only, as above),
+// else LINE_LMAX.
+inline int z_seg_len(int n, int nx, bool fp32) {
+  if (fp32 && n % 32 == 0 && n / 16 > 32 && pow2_in(n / 32, 4, 32) && nx % 32 == 0) return 32;
   return LINE_LMAX;
 }
 

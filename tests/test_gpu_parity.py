@@ -95,17 +95,19 @@ def test_viscous_parity(name, stage):
         assert rel(n(ho[c], f[c].shape), Href[c]) < 1e-12, c
 
 
-def _long_line_workload(axis):
+def _long_line_workload(axis, nx=16):
     """Lines of 64 segments (blocks of 1024 threads in the column sweeps), with
     a sphere so that segments hold forcing nodes: y lines of 768 rows
-    (12-row segments) or z lines of 1024 rows (16-row segments)."""
+    (12-row segments) or z lines of 1024 rows (16-row segments); with nx = 32
+    the FP32 line data of the mixed form take 24-row (y) and 32-row (z)
+    segments instead, 32 lines per block."""
     import workloads
     if axis == "y":
-        return workloads.Workload("long_y", 16, 768, 16, 0.16, 0.16, workloads.uniform_faces(768),
-                                  100.0, 1e-3, 2, 1.0, 0.01, 13, -0.02,
-                                  [workloads._sphere_body(2, 0.04, (0.08, 0.0, 0.08),
-                                                          (0.2, 0.05, -0.1))])
-    return workloads.Workload("long_z", 16, 24, 1024, 16 * 2.0 / 24, 1024 * 2.0 / 24,
+        return workloads.Workload("long_y", nx, 768, 16, 0.01 * nx, 0.16,
+                                  workloads.uniform_faces(768), 100.0, 1e-3, 2, 1.0, 0.01, 13,
+                                  -0.02, [workloads._sphere_body(2, 0.04, (0.08, 0.0, 0.08),
+                                                                 (0.2, 0.05, -0.1))])
+    return workloads.Workload("long_z", nx, 24, 1024, nx * 2.0 / 24, 1024 * 2.0 / 24,
                               workloads.uniform_faces(24), 100.0, 1e-3, 2, 1.0, 0.01, 13, -0.02,
                               [workloads._sphere_body(2, 0.3, (0.66, 0.0, 40.0), (0.2, 0.05, -0.1))])
 
@@ -136,6 +138,42 @@ def test_viscous_parity_long_lines(axis, stage):
     for c in range(3):
         assert rel(n(d[c], f[c].shape) - f[c], ref[c] - f[c]) < 1e-12, c
         assert rel(n(ho[c], f[c].shape), Href[c]) < 1e-12, c
+
+
+@pytest.mark.parametrize("axis", ["y", "z"])
+@pytest.mark.parametrize("stage", [0, 1])
+def test_mixed_viscous_long_segments(axis, stage):
+    """The mixed form's FP32 column sweeps in 24-row (y, 768 rows) and
+    32-row (z, 1024 rows) segments, 32 lines per block, with forcing nodes
+    inside segments: du within the FP32 rounding of its stored right-hand
+    side of the FP64 oracle, du = 0 exactly on forcing nodes."""
+    case = Case(_long_line_workload(axis, nx=32), precision="mixed")
+    g = case.g
+    bodies, (X, U, T) = case.bodies_at(0.0)
+    case.ibm.ibm_tag(case.ctx, bodies)
+    tags = ostep.compute_tags(g, X, T)
+    assert min(len(i) for i in tags.idx) > 0
+    masks = ostep.masks_of(g, tags)
+    f = case.random_fields(5)
+    rng = np.random.default_rng(7)
+    p = rng.standard_normal(g.shape).astype(np.float32)
+    hprev = [rng.standard_normal(g.comp_shape(c)).astype(np.float32) for c in range(3)]
+    hprev[1][0] = hprev[1][-1] = 0.0
+    gamma, rho = ostep.SCHEMES["rk2"][stage]
+    dt = case.wl.dt
+    ref, Href = predictor.predictor(g, f, p.astype(np.float64),
+                                    [h.astype(np.float64) for h in hprev] if rho else None,
+                                    masks, gamma, rho, gamma + rho, dt, case.wl.re, case.fext)
+    d = [t(a) for a in f]
+    hp = [t(a) for a in hprev]
+    ho = [torch.zeros(x.numel(), dtype=torch.float32, device=DEV) for x in d]
+    case.ibm.ibm_viscous(case.ctx, t(p), hp if rho else None, ho, gamma, rho, dt, *d)
+    for c in range(3):
+        assert rel(n(d[c], f[c].shape) - f[c], ref[c] - f[c]) < 2e-6, c
+        m = masks[c].reshape(-1)
+        assert np.array_equal(n(d[c]).reshape(-1)[m], f[c].reshape(-1)[m])
+        assert rel(n(ho[c], f[c].shape).astype(np.float64), Href[c]) < 1e-7, c
+    case.ctx.close()
 
 
 @pytest.mark.parametrize("name,time", [("tiny", 0.011), ("tiny_plate", 0.137), ("c1", 0.0)])
