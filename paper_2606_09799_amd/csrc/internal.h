@@ -151,10 +151,10 @@ inline bool plan_fft(int n, FFTPlan* P) {
   return m == 1;
 }
 
-// blocks of a launch in the XCD slab order (geom.h, xcd_slab_tile): eight
-// bands of ceil(nbz/8) k-tiles, each walked over all ny planes
-inline int64_t xcd_slab_blocks(int nbx, int nbz, int ny) {
-  return 8 * (int64_t)nbx * ((nbz + 7) / 8) * ny;
+// blocks of the XCD band order (lanes.h: xcd_band_tile), bands of BW k-tiles
+inline int64_t xcd_band_blocks(int nbx, int nbz, int ny, int BW) {
+  const int64_t bands = (nbz + BW - 1) / BW;
+  return 8 * ((bands + 7) / 8) * (int64_t)nbx * BW * ny;
 }
 
 // profiling hook (ctx.cpp): an event pair around each kernel launch when

@@ -27,26 +27,27 @@ __device__ __forceinline__ int64_t xcd_tile(int64_t b, int64_t T) {
   return b;  // unreachable for b < T
 }
 
-// XCD slab order for stencil sweeps over tiles (it, kt, j) of a
-// [j][k][i] field: XCD x (the blocks b with b % 8 == x) owns the band of
-// k-tiles [x nbz/8, (x+1) nbz/8) and walks it plane by plane, j slowest, so
-// the planes j-1, j, j+1 that a stencil touches are all recent in its own
-// L2 (a band of whole planes per XCD would need three planes of every field
-// at once, more than one L2 holds).  The grid has xcd_slab_blocks() blocks;
-// the padding blocks of XCDs with a narrower band get false.
-__device__ __forceinline__ bool xcd_slab_tile(int64_t b, int nbx, int nbz, int ny, int& it,
-                                              int& kt, int& j) {
+// XCD band order for stencil passes over tiles (it, kt, j) of a [j][k][i]
+// field on large planes: the k-tiles are cut into bands of BW, dealt to the
+// XCDs round robin (XCD x takes bands x, x + 8, ...), and each XCD walks its
+// band plane by plane, j slowest, before the next one.  The planes j-1, j,
+// j+1 of a band are then a few hundred KB, recent in the XCD's own L2 when
+// a stencil reads them again (with whole-plane slabs per XCD, a plane of
+// phi at 1024 x 1024 cells is 8 MB, twice an L2, and the plane below was
+// fetched from HBM again).  The grid has xcd_band_blocks() blocks; padding
+// blocks get false.
+__device__ __forceinline__ bool xcd_band_tile(int64_t b, int nbx, int nbz, int ny, int BW,
+                                              int& it, int& kt, int& j) {
   const int x = (int)(b % NUM_XCD);
   const int64_t r = b / NUM_XCD;
-  const int kt0 = (int)((int64_t)x * nbz / NUM_XCD);
-  const int kt1 = (int)((int64_t)(x + 1) * nbz / NUM_XCD);
-  const int64_t per_plane = (int64_t)nbx * (kt1 - kt0);
-  if (per_plane == 0 || r >= per_plane * ny) return false;
-  j = (int)(r / per_plane);
-  const int rem = (int)(r % per_plane);
-  kt = kt0 + rem / nbx;
-  it = rem % nbx;
-  return true;
+  const int64_t per_band = (int64_t)nbx * BW * ny;
+  const int band = x + NUM_XCD * (int)(r / per_band);
+  const int64_t rem = r % per_band;
+  j = (int)(rem / ((int64_t)nbx * BW));
+  const int rem2 = (int)(rem % ((int64_t)nbx * BW));
+  kt = band * BW + rem2 / nbx;
+  it = rem2 % nbx;
+  return kt < nbz;
 }
 
 // The value v of lane `src` of this wavefront (ds_bpermute: no LDS storage,

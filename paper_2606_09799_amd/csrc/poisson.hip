@@ -514,6 +514,30 @@ __global__ __launch_bounds__(16 * Z16_TC) void k_fftz256(PoisK<C> K) {
 // pieces).  The LDS layouts keep every 16 consecutive lanes on distinct
 // 16-byte bank groups: step 2 reads stride-R rows, step 3 reads an XOR
 // swizzle of the (t1, mode) index by t1 of the reading thread.
+// XCD-aware order of those blocks: the G tiles of TC modes that share one
+// 128-byte line of a spectrum row go to one XCD, one after the other (blocks
+// are dealt to the 8 XCDs round robin by linear id), so that the line is
+// fetched from HBM once into that XCD's L2 instead of once per tile.  1-D
+// grid of zline_blocks blocks; false for the padding blocks.
+__device__ __forceinline__ bool zline_tile(int G, int gx, int ny, int& tile, int& j) {
+  const int64_t b = blockIdx.x;
+  const int u = (int)((b / NUM_XCD) % G);
+  const int64_t U = (b / (NUM_XCD * (int64_t)G)) * NUM_XCD + b % NUM_XCD;  // line group
+  const int LG = (gx + G - 1) / G;
+  if (U >= (int64_t)ny * LG) return false;
+  j = (int)(U / LG);
+  tile = (int)(U % LG) * G + u;
+  return tile < gx;
+}
+static int64_t zline_blocks(int G, int gx, int ny) {
+  const int64_t units = (int64_t)ny * ((gx + G - 1) / G);
+  return (units + NUM_XCD - 1) / NUM_XCD * NUM_XCD * G;
+}
+template <typename C, int TC>
+constexpr int zline_group() {
+  return (128 / (TC * (int)sizeof(C))) > 1 ? 128 / (TC * (int)sizeof(C)) : 1;
+}
+
 template <typename C, bool INV, int R>
 __global__ __launch_bounds__(256) void k_fftz4s(PoisK<C> K) {
   constexpr int M = 16 * R;    // threads per mode
@@ -524,11 +548,13 @@ __global__ __launch_bounds__(256) void k_fftz4s(PoisK<C> K) {
   __shared__ C T[4096];
   const GridView& g = K.g;
   const int nxh = g.nxh;
+  int tile, j;
+  if (!zline_tile(zline_group<C, TC>(), (nxh + TC - 1) / TC, g.ny, tile, j)) return;
   const int c = threadIdx.x % TC, tt = threadIdx.x / TC;
-  const int p = blockIdx.x * TC + c;
+  const int p = tile * TC + c;
   const bool valid = p < nxh;
   const int ldx = K.ldx;
-  C* col = K.spec + (int64_t)blockIdx.y * N * ldx + (valid ? p : 0);  // element k at col[k ldx]
+  C* col = K.spec + (int64_t)j * N * ldx + (valid ? p : 0);  // element k at col[k ldx]
   C x[16];
   // 1.
 #pragma unroll
@@ -918,6 +944,129 @@ __global__ __launch_bounds__(32 * X16_SC) void k_fftx256_inv(PoisK<C> K) {
       dst[e] += v;
     else
       dst[e] = v;
+  }
+}
+
+// Inverse x transforms of length 256 R (R = 2, 4: nx = 512, 1024) as
+// 16 x 16 x R, the scheme of the z transforms of those lengths, with one
+// complex sequence (two real rows: Z = A + iB over the Hermitian extensions
+// of their half spectra) per M = 16 R lanes of one wavefront, so that the
+// three DFT stages exchange data through the sequence's own LDS tile with
+// wavefront syncs only.  With n = t + M n2:
+//  1. lane t loads Z[t + M n2] (n2 = 0..15) straight from the two spectrum
+//     rows (64 consecutive bins per load), takes a 16-point DFT (output k2)
+//     and the twiddle W_N^(t k2), and writes tile[k2][t];
+//  2. lane (k2, t1) (t = t1 + R t2) reads the 16 values t2 of its k2, takes
+//     a 16-point DFT (output k3) and the twiddle W_M^(t1 k3), and writes
+//     tile[k2][k3 R + t1];
+//  3. lane (k2, t1) takes the length-R DFTs of k3 = t1 (16/R) + q and writes
+//     z[k2 + 16 k3 + 256 k4] to the tile in natural order;
+//  4. the lanes store the two phi rows (real and imaginary parts of z),
+//     coalesced.
+// Tile rows have a stride of M + 1 complex values, so that each step's LDS
+// accesses spread over all bank groups.  A sequence past the last row pair
+// transforms a copy of the last rows and stores nothing.
+template <typename C, int R>
+__global__ __launch_bounds__(256) void k_fftx4s_inv(PoisK<C> K) {
+  using RT = typename RealOf<C>::T;
+  constexpr int M = 16 * R;         // lanes per sequence
+  constexpr int N = 16 * M;         // transform length
+  constexpr int SPB = 256 / M;      // sequences per block
+  constexpr int LP = M + 1;         // tile row stride
+  constexpr int TS = 16 * LP;       // tile size (complex values)
+  static_assert(TS >= N, "natural-order output fits the tile");
+  if (gated(K)) return;
+  __shared__ C T[SPB * TS];
+  const GridView& g = K.g;
+  const int nxh = g.nxh;  // N/2 + 1
+  const int64_t nrows = (int64_t)g.ny * g.nz;
+  const int t = threadIdx.x % M, sq = threadIdx.x / M;
+  const int64_t ra = ((int64_t)blockIdx.x * SPB + sq) * 2;  // rows ra (real part), ra + 1
+  const bool live_a = ra < nrows, live_b = ra + 1 < nrows;
+  const C* sa = K.spec + (live_a ? ra : nrows - 1) * K.ldx;
+  const C* sb = K.spec + (live_b ? ra + 1 : nrows - 1) * K.ldx;
+  C* tile = T + sq * TS;
+  // bin k of a half spectrum over the Hermitian extension (bins 0, N/2 real)
+  auto bin = [&](const C* row, int k) -> C {
+    C c = row[k < nxh ? k : N - k];
+    if (k >= nxh) c.y = -c.y;
+    if (k == 0 || 2 * k == N) c.y = (RT)0;
+    return c;
+  };
+  C x[16];
+  // 1.
+#pragma unroll
+  for (int n2 = 0; n2 < 16; ++n2) {
+    const int k = t + M * n2;
+    const C A = bin(sa, k);
+    const C B = live_b ? bin(sb, k) : mkc<C>((RT)0, (RT)0);
+    x[n2] = mkc<C>(A.x - B.y, A.y + B.x);
+  }
+  dft16<C, true>(x);
+#pragma unroll
+  for (int k2 = 0; k2 < 16; ++k2) {
+    C w = K.px.tw[t * k2];
+    w.y = -w.y;
+    tile[k2 * LP + t] = (k2 && t) ? cmul(x[pos16(k2)], w) : x[pos16(k2)];
+  }
+  wave_sync();
+  // 2.
+  const int k2 = t / R, t1 = t % R;
+#pragma unroll
+  for (int t2 = 0; t2 < 16; ++t2) x[t2] = tile[k2 * LP + t1 + R * t2];
+  dft16<C, true>(x);
+  wave_sync();  // every step-2 read is done before the tile is rewritten
+#pragma unroll
+  for (int k3 = 0; k3 < 16; ++k3) {
+    C w = K.px.tw[16 * t1 * k3];  // W_M^(t1 k3)
+    w.y = -w.y;
+    tile[k2 * LP + k3 * R + t1] = (k3 && t1) ? cmul(x[pos16(k3)], w) : x[pos16(k3)];
+  }
+  wave_sync();
+  // 3.
+#pragma unroll
+  for (int q = 0; q < 16 / R; ++q)
+#pragma unroll
+    for (int r = 0; r < R; ++r) x[q * R + r] = tile[k2 * LP + (t1 * (16 / R) + q) * R + r];
+  wave_sync();
+#pragma unroll
+  for (int q = 0; q < 16 / R; ++q) {
+    C* u = x + q * R;
+    if constexpr (R == 2) {
+      const C a = u[0], b = u[1];
+      u[0] = cadd(a, b);
+      u[1] = csub(a, b);
+    } else {
+      dft4<C, true>(u[0], u[1], u[2], u[3]);
+    }
+    const int k3 = t1 * (16 / R) + q;
+#pragma unroll
+    for (int k4 = 0; k4 < R; ++k4) tile[k2 + 16 * k3 + 256 * k4] = u[k4];
+  }
+  wave_sync();
+  // 4.
+  const double msub = K.msum ? *K.msum * K.inv_vtot : 0.0;
+  const double za = (K.zm && live_a) ? K.zm[(int)(ra / g.nz)] * K.scale : 0.0;
+  const double zb = (K.zm && live_b) ? K.zm[(int)((ra + 1) / g.nz)] * K.scale : 0.0;
+  double* pa = K.phi + ra * N;
+#pragma unroll 4
+  for (int j = 0; j < 16; ++j) {
+    const int n = t + M * j;
+    const C z = tile[n];
+    const double va = (double)z.x * K.scale + za - msub;
+    const double vb = (double)z.y * K.scale + zb - msub;
+    if (live_a) {
+      if (K.accumulate)
+        pa[n] += va;
+      else
+        pa[n] = va;
+    }
+    if (live_b) {
+      if (K.accumulate)
+        pa[N + n] += vb;
+      else
+        pa[N + n] = vb;
+    }
   }
 }
 
@@ -1674,13 +1823,17 @@ static void run_passes(Prof* pf, hipStream_t s, const GridView& g, PoisK<C> K, P
   }
   const bool z256 = (g.nz == 256);
   const dim3 z16grid((g.nxh + Z16_TC - 1) / Z16_TC, g.ny);
-  const dim3 z512grid((g.nxh + 7) / 8, g.ny), z1kgrid((g.nxh + 3) / 4, g.ny);
+  // lengths 512 and 1024: 8 and 4 modes per block, XCD-aware 1-D grids
+  const unsigned z512b = (unsigned)zline_blocks(zline_group<C, 8>(), (g.nxh + 7) / 8, g.ny);
+  const unsigned z1kb = (unsigned)zline_blocks(zline_group<C, 4>(), (g.nxh + 3) / 4, g.ny);
+  const unsigned z512b_i = (unsigned)zline_blocks(zline_group<CI, 8>(), (g.nxh + 7) / 8, g.ny);
+  const unsigned z1kb_i = (unsigned)zline_blocks(zline_group<CI, 4>(), (g.nxh + 3) / 4, g.ny);
   if (z256)
     IBM_LAUNCH(pf, "pois_fftz_fwd", s, (k_fftz256<C, false><<<z16grid, 16 * Z16_TC, 0, s>>>(K)));
   else if (g.nz == 512)
-    IBM_LAUNCH(pf, "pois_fftz_fwd", s, (k_fftz4s<C, false, 2><<<z512grid, 256, 0, s>>>(K)));
+    IBM_LAUNCH(pf, "pois_fftz_fwd", s, (k_fftz4s<C, false, 2><<<z512b, 256, 0, s>>>(K)));
   else if (g.nz == 1024)
-    IBM_LAUNCH(pf, "pois_fftz_fwd", s, (k_fftz4s<C, false, 4><<<z1kgrid, 256, 0, s>>>(K)));
+    IBM_LAUNCH(pf, "pois_fftz_fwd", s, (k_fftz4s<C, false, 4><<<z1kb, 256, 0, s>>>(K)));
   else
     IBM_LAUNCH(pf, "pois_fftz_fwd", s, (k_fftz<C, false><<<zgrid, 256, zsh, s>>>(K)));
   if (ywave && sl == 2 * YL && K.yr == 0 && K.yL == sl)
@@ -1700,13 +1853,21 @@ static void run_passes(Prof* pf, hipStream_t s, const GridView& g, PoisK<C> K, P
   if (z256)
     IBM_LAUNCH(pf, "pois_fftz_inv", s, (k_fftz256<CI, true><<<z16grid, 16 * Z16_TC, 0, s>>>(KI)));
   else if (g.nz == 512)
-    IBM_LAUNCH(pf, "pois_fftz_inv", s, (k_fftz4s<CI, true, 2><<<z512grid, 256, 0, s>>>(KI)));
+    IBM_LAUNCH(pf, "pois_fftz_inv", s, (k_fftz4s<CI, true, 2><<<z512b_i, 256, 0, s>>>(KI)));
   else if (g.nz == 1024)
-    IBM_LAUNCH(pf, "pois_fftz_inv", s, (k_fftz4s<CI, true, 4><<<z1kgrid, 256, 0, s>>>(KI)));
+    IBM_LAUNCH(pf, "pois_fftz_inv", s, (k_fftz4s<CI, true, 4><<<z1kb_i, 256, 0, s>>>(KI)));
   else
     IBM_LAUNCH(pf, "pois_fftz_inv", s, (k_fftz<CI, true><<<zgrid_i, 256, zsh_i, s>>>(KI)));
+  // lengths 512 and 1024: one sequence (two rows) per 32 or 64 lanes, 2 x
+  // 4096/nx rows per block of 256 threads
+  const int rpb4 = (g.nx == 512 || g.nx == 1024) ? 2 * (4096 / g.nx) : 1;
+  const int xb4_i = (int)((nrows + rpb4 - 1) / rpb4);
   if (x256_i)
     IBM_LAUNCH(pf, "pois_fftx_inv", s, (k_fftx256_inv<CI><<<xb_i, 32 * X16_SC, 0, s>>>(KI)));
+  else if (g.nx == 1024)
+    IBM_LAUNCH(pf, "pois_fftx_inv", s, (k_fftx4s_inv<CI, 4><<<xb4_i, 256, 0, s>>>(KI)));
+  else if (g.nx == 512)
+    IBM_LAUNCH(pf, "pois_fftx_inv", s, (k_fftx4s_inv<CI, 2><<<xb4_i, 256, 0, s>>>(KI)));
   else
     IBM_LAUNCH(pf, "pois_fftx_inv", s, (k_fftx_inv<CI><<<xblocks_i, 256, xsh_i, s>>>(KI)));
 }

@@ -1,13 +1,16 @@
 // Projection and pressure update (paper Eqs. projection and update_pressure):
 //   u <- u_hat - alpha dt G phi   on every interior velocity node
 //   p <- p + phi - alpha dt/(2 Re) L_c phi,  L_c = D G (Neumann at the walls)
-// One thread per (i, j, k), x fastest; rows are ordered per XCD so that the
-// neighbouring rows of phi are reused from the same L2 (xcd_tile).  The
-// velocity update is FP64 in both forms; p is stored in T (float in the
-// mixed form) and updated in FP64 arithmetic.
+// One thread per (i, j, k), x fastest; blocks of 256 x-points of one row in
+// the XCD band order (xcd_band_tile: bands of 16 rows, walked plane by
+// plane), so that the rows of phi at k-1, k+1 and the planes j-1, j+1 are
+// reused from the same L2.  The velocity update is FP64 in both forms; p is
+// stored in T (float in the mixed form) and updated in FP64 arithmetic.
 #include "lanes.h"
 
 namespace ibm {
+
+constexpr int PROJ_BAND = 16;  // rows per band of the block order
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_project(GridView g, const double* __restrict__ phi,
@@ -15,10 +18,9 @@ __global__ __launch_bounds__(256) void k_project(GridView g, const double* __res
                                                  double* __restrict__ v, double* __restrict__ w,
                                                  T* __restrict__ p) {
   const int nbx = (g.nx + 255) / 256;
-  const int64_t t = xcd_tile(blockIdx.x, (int64_t)nbx * g.nz * g.ny);
-  const int i = (int)(t % nbx) * 256 + threadIdx.x;
-  const int k = (int)((t / nbx) % g.nz);
-  const int j = (int)(t / ((int64_t)nbx * g.nz));
+  int it, k, j;
+  if (!xcd_band_tile(blockIdx.x, nbx, g.nz, g.ny, PROJ_BAND, it, k, j)) return;
+  const int i = it * 256 + threadIdx.x;
   if (i >= g.nx) return;
   const int64_t plane = (int64_t)g.nz * g.nx;
   const int64_t c = (int64_t)j * plane + (int64_t)k * g.nx + i;
@@ -49,7 +51,7 @@ __global__ __launch_bounds__(256) void k_project(GridView g, const double* __res
 
 void launch_project(Prof* pf, hipStream_t s, const GridView& g, const double* phi, double adt,
                     double re, double* u, double* v, double* w, void* p, int fp32) {
-  dim3 grid((unsigned)((int64_t)((g.nx + 255) / 256) * g.nz * g.ny));
+  dim3 grid((unsigned)xcd_band_blocks((g.nx + 255) / 256, g.nz, g.ny, PROJ_BAND));
   const double pc = adt / (2.0 * re);
   if (fp32)
     IBM_LAUNCH(pf, "project", s,

@@ -68,11 +68,20 @@ def _one(path_dir: str, suffix: str) -> str:
 
 
 def pmc_per_kernel(path_dir: str):
+    """Counter values per kernel, and the values of the copy reference: the
+    last three dispatches of the runtime's copy kernel (bench.py runs the
+    reference copy three times after everything else; other copies of the
+    run, such as state clones, may be larger)."""
     out = collections.defaultdict(list)
+    copies = []
     with open(_one(path_dir, "counter_collection.csv")) as f:
         for r in csv.DictReader(f):
-            out[kernel_name(r["Kernel_Name"])].append(float(r["Counter_Value"]))
-    return out
+            k = kernel_name(r["Kernel_Name"])
+            out[k].append(float(r["Counter_Value"]))
+            if "copyBuffer" in k:
+                copies.append((int(r["Dispatch_Id"]), float(r["Counter_Value"])))
+    ref = sorted(v for _, v in sorted(copies)[-3:])
+    return out, (ref[len(ref) // 2] if ref else None)
 
 
 def summarise(tag, trace, fetch, write, copy_mib, trace_cmd, pmc_cmd, workload):
@@ -93,11 +102,8 @@ def summarise(tag, trace, fetch, write, copy_mib, trace_cmd, pmc_cmd, workload):
     with open(os.path.join(ROOT, "profiles", f"{tag}_kernel_trace.md"), "w") as f:
         f.write("\n".join(lines) + "\n")
 
-    fe, wr = pmc_per_kernel(fetch), pmc_per_kernel(write)
+    (fe, cf), (wr, cw) = pmc_per_kernel(fetch), pmc_per_kernel(write)
     ref_kib = copy_mib * 1024.0
-    # the copy reference: the largest dispatch of the runtime's copy kernel
-    cf = max(v for k, vs in fe.items() if "copyBuffer" in k for v in vs)
-    cw = max(v for k, vs in wr.items() if "copyBuffer" in k for v in vs)
     fs, ws = ref_kib / cf, ref_kib / cw
     lines = [f"# HBM traffic per dispatch, {workload}, rocprofv3 --pmc", "",
              "Two passes, one counter each (from the repository root on one MI355X):", "",

@@ -258,7 +258,7 @@ def test_poisson_parity(name):
 
 @pytest.mark.parametrize("shape", [(256, 12, 16), (16, 12, 256), (16, 800, 8), (16, 528, 16),
                                    (16, 500, 16), (16, 8, 512), (24, 6, 1024), (16, 192, 16),
-                                   (24, 100, 16)])
+                                   (24, 100, 16), (1024, 5, 9), (512, 7, 9)])
 def test_poisson_parity_kernel_paths(shape):
     """Shapes that select the other kernel paths, compared with the oracle
     value by value: length-256 x transforms (four-step), length-256 z
@@ -268,7 +268,9 @@ def test_poisson_parity_kernel_paths(shape):
     and in 42 unequal ones of at most 12 rows (ny = 500), length-512 and
     -1024 z transforms (16 x 16 x R; 24 x-points: a partial last tile of
     modes), the wall-normal solve of 32 equal 6-row segments (ny = 192,
-    straight-line rows) and of 17 unequal ones (ny = 100); stretched y."""
+    straight-line rows) and of 17 unequal ones (ny = 100), the inverse x
+    transforms of lengths 1024 and 512 (16 x 16 x R, one row pair per 64 or
+    32 lanes; an odd row count leaves a last pair of one row); stretched y."""
     import workloads
     nx, ny, nz = shape
     wl = workloads.Workload("paths", nx, ny, nz, 2 * np.pi, np.pi, workloads.tanh_faces(ny),
