@@ -28,17 +28,23 @@ from . import operators as op
 from .linsolve import cyclic, thomas
 
 
-def explicit_rhs(g, fields, p, hprev, masks, gamma, rho, alpha, dt, re, fext):
+def explicit_rhs(g, fields, p, hprev, masks, gamma, rho, alpha, dt, re, fext, kappa=None):
     """R of the delta form at every node; 0 on the forcing nodes and on the
     v wall planes.  Returns (R, H) with H = H(u^s) for reuse by a later
-    sub-stage."""
+    sub-stage.  The volume force of component c is fext[c] (a constant or an
+    array on the component's lattice) plus kappa[c] * u_c^s when kappa[c] is
+    given (a force linear in the component itself, evaluated explicitly like
+    the constant part: Sec. 4.2 and 4.3 add such forces to Eq. NS_prov)."""
     u, v, w = fields
     H = op.conv(g, u, v, w)
     G = op.gradient(g, p)
     Lu = (op.lap_cc(g, u), op.lap_v(g, v), op.lap_cc(g, w))
     R = []
     for c in range(3):
-        r = gamma * H[c] - alpha * (G[c] - fext[c]) + (alpha / re) * Lu[c]
+        f = fext[c]
+        if kappa is not None and kappa[c] is not None:
+            f = f + kappa[c] * fields[c]
+        r = gamma * H[c] - alpha * (G[c] - f) + (alpha / re) * Lu[c]
         if rho != 0.0:
             r = r + rho * hprev[c]
         r = dt * r
@@ -99,10 +105,10 @@ def factored_solve(g, R, masks, alpha, dt, re):
     return out
 
 
-def predictor(g, fields, p, hprev, masks, gamma, rho, alpha, dt, re, fext):
+def predictor(g, fields, p, hprev, masks, gamma, rho, alpha, dt, re, fext, kappa=None):
     """u_hat = u^s + du on every node (du = 0 on the forcing nodes and
     walls).  Returns ((u_hat, v_hat, w_hat), H(u^s))."""
-    R, H = explicit_rhs(g, fields, p, hprev, masks, gamma, rho, alpha, dt, re, fext)
+    R, H = explicit_rhs(g, fields, p, hprev, masks, gamma, rho, alpha, dt, re, fext, kappa)
     du = factored_solve(g, R, masks, alpha, dt, re)
     return tuple(fields[c] + du[c] for c in range(3)), H
 

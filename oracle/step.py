@@ -53,12 +53,13 @@ def masks_of(g, tags):
 
 
 def substage(g, fields, p, hprev, tags, verts, vel, tris, gamma, rho, dt, re, fext,
-             use_q=True, diag=None):
+             use_q=True, diag=None, kappa=None):
     """One sub-stage.  Returns (fields^{s+1}, p^{s+1}, H^s)."""
     alpha = gamma + rho
     masks = masks_of(g, tags)
     fib = forcing.apply_ib(g, fields, list(zip(tags.idx, tags.tri)), verts, vel, tris)
-    uhat, H = predictor.predictor(g, fib, p, hprev, masks, gamma, rho, alpha, dt, re, fext)
+    uhat, H = predictor.predictor(g, fib, p, hprev, masks, gamma, rho, alpha, dt, re, fext,
+                                  kappa)
     rhs, qF, _ = projection.mass_correction(g, uhat, tags.cb, alpha, dt, use_q, p)
     phi = poisson.solve(g, rhs)
     new, pn = projection.project(g, uhat, p, phi, alpha, dt, re)
@@ -68,7 +69,7 @@ def substage(g, fields, p, hprev, tags, verts, vel, tris, gamma, rho, dt, re, fe
 
 
 def step(g, fields, p, surface, dt, re, fext, scheme="rk2", hprev=None, use_q=True,
-         diag=None):
+         diag=None, kappa=None):
     """One time step from t^n.  surface = (verts, vel, tris) at t^n.
     Returns (fields^{n+1}, p^{n+1}, H for a following AB step, tags)."""
     verts, vel, tris = surface
@@ -79,7 +80,7 @@ def step(g, fields, p, surface, dt, re, fext, scheme="rk2", hprev=None, use_q=Tr
     H = hprev
     for gamma, rho in coefs:
         fields, p, Hs = substage(g, fields, p, H, tags, verts, vel, tris, gamma, rho,
-                                 dt, re, fext, use_q, diag)
+                                 dt, re, fext, use_q, diag, kappa)
         H = Hs
     return fields, p, H, tags
 
