@@ -177,8 +177,14 @@ def progress(msg):
 
 
 def describe(wl):
-    return (f"{wl.name}: {wl.nx}x{wl.ny}x{wl.nz} channel, tanh-stretched y, Re {wl.re:g}, "
-            f"dt {wl.dt:g}, RK2+CN, {len(wl.bodies)} bodies, "
+    if wl.vforce == "vortex":
+        kind = "immersed-plane channel y in [-1/4, 2], vortex forcing below the plane"
+    elif wl.vforce == "relax":
+        kind = "immersed-plane channel y in [-1/4, 2], Re_tau 200, relaxation forcing below"
+    else:
+        kind = "channel, tanh-stretched y"
+    return (f"{wl.name}: {wl.nx}x{wl.ny}x{wl.nz} {kind}, Re {wl.re:g}, "
+            f"dt {wl.dt:g}, {'AB2' if wl.scheme == 'ab2' else 'RK2'}+CN, {len(wl.bodies)} bodies, "
             f"{sum(b.tris.shape[0] for b in wl.bodies)} triangles")
 
 
@@ -186,19 +192,32 @@ def run_form(args, wl, form, dev, fields0):
     """Times args.steps full steps of workload wl in one precision form from
     the initial field fields0 (device tensors, copied).  Returns a dict of
     results and the final velocity (device tensors)."""
+    import numpy as np
     import torch
     from paper_2606_09799_amd import ibm
 
     ctx = ibm.Context(wl.nx, wl.ny, wl.nz, wl.lx, wl.lz, wl.y_faces, wl.re, wl.dpdx,
+                      scheme=wl.scheme,
                       precision="fp64" if form == "fp64" else "mixed",
                       mixed_poisson="refined" if form == "mixed_refined" else "fp64",
                       refine_tol=DIV_BOUND if form == "mixed_refined" else 0.0)
     u, v, w = (x.clone() for x in fields0)
     p = torch.zeros(ctx.cells, dtype=ctx.pdtype, device=dev)
     T = lambda a: torch.from_numpy(a).to(dev)
+    import workloads
+    vf = []
+    for c in range(3):  # the volume forces of the immersed-plane channels
+        f0, kap = workloads.volume_force(wl, c)
+        if f0 is not None:
+            vf.append((T(np.ascontiguousarray(f0)),
+                       T(np.ascontiguousarray(kap)) if kap is not None else None))
+            ibm.ibm_set_volume_force(ctx, c, *vf[-1])
+    # AB2 + CN: H^{n-1} in and H^n out through the state (zero before the
+    # first step)
+    hbuf = ([torch.zeros(ctx.comp_numel(c), dtype=ctx.pdtype, device=dev) for c in range(3)]
+            if wl.scheme == "ab2" else None)
     dbodies = []
     for b in wl.bodies:
-        import numpy as np
         ref = T(np.ascontiguousarray(b.ref))
         xyz = torch.empty(b.ref.shape[0], 3, dtype=torch.float64, device=dev)
         vel = torch.empty_like(xyz)
@@ -215,7 +234,7 @@ def run_form(args, wl, form, dev, fields0):
 
     def one_step(s):
         move(s * wl.dt)
-        ibm.ibm_step(ctx, u, v, w, p, bodies, wl.dt)
+        ibm.ibm_step(ctx, u, v, w, p, bodies, wl.dt, h=hbuf)
 
     # warm-up, profiling every kernel to find the dominant one (the first
     # step, which pays for code loading and cold caches, is not profiled)
@@ -420,7 +439,7 @@ def main():
                     help="headline workload (c5: 1024x768x1024 with 67 bodies)")
     ap.add_argument("--forms", default="mixed,fp64,mixed_refined",
                     help="forms of the headline workload; the first one is the headline value")
-    ap.add_argument("--also", default="c2",
+    ap.add_argument("--also", default="c2,plane,turb",
                     help="further workloads timed in every form (comma list, empty: none)")
     ap.add_argument("--batch-sims", type=int, default=64,
                     help="simulations of the batched workload (0 = skip it)")

@@ -191,6 +191,32 @@ int ibm_body_rigid(ibm_ctx* ctx, const double* x0, int32_t nv, const double* coe
                    double* xyz, double* vel);
 int ibm_body_deform(ibm_ctx* ctx, const double* data, int32_t nv, const double* coef,
                     double* xyz, double* vel);
+/* ibm_body_rigid with its 18 coefficients in device memory (coef: dev
+ * f64[18], e.g. written by ibm_rigid_advance), so that a free body's motion
+ * never visits the host. */
+int ibm_body_rigid_dev(ibm_ctx* ctx, const double* x0, int32_t nv, const double* coef,
+                       double* xyz, double* vel);
+
+/* Rigid-body dynamics of the loosely coupled FSI (paper Sec. 4.5, driven by
+ * the loads of Sec. 3.3): one AB2 step (explicit Euler on a body's first)
+ * of Newton's equations (fluid force plus an external force such as
+ * gravity with buoyancy, inertial frame), Euler's equations (principal
+ * frame; the torque is taken about the body's centre, as ibm_loads gives it
+ * with pole = c) and the unit orientation quaternion, renormalised.
+ * state: dev f64[nb * IBM_RIGID_STATE], per body c(3), q(4) = (w, x, y, z),
+ *   V(3), Omega(3) in the body frame, then the last derivatives (13) and a
+ *   started flag (0 before the first step), updated in place;
+ * props: dev f64[nb * IBM_RIGID_PROPS]: mass, principal moments (3),
+ *   external force (3), unused;
+ * loads: dev f64[6 nb], (F, M about c) per body as ibm_loads writes them;
+ * coef: dev f64[18 nb], out: the rigid-motion coefficients at the new time
+ *   (c, R row-major body -> world, cdot, omega world) for ibm_body_rigid_dev.
+ * The paper advances the fluid in a frame translating with the body; here
+ * the body moves through the fixed grid.  IBM_EINVAL for a bad argument. */
+#define IBM_RIGID_STATE 28
+#define IBM_RIGID_PROPS 8
+int ibm_rigid_advance(ibm_ctx* ctx, int32_t nb, double* state, const double* props,
+                      const double* loads, double dt, double* coef);
 
 /* Tagging (paper Alg. 1, Sec. 3.1) of the three staggered lattices and the
  * boundary cells C_B (Sec. 3.2: cells all of whose faces carry forcing
@@ -231,6 +257,17 @@ int ibm_force(ibm_ctx* ctx, double* u, double* v, double* w);
  * f32/f64.  u, v, w: dev f64, in
  * place (the mixed form computes R and H in FP64 arithmetic, stores them in
  * FP32, solves the three factors in FP32 and adds du to the FP64 u). */
+/* Volume force on component comp (0 = u, 1 = v, 2 = w) of the predictor,
+ * F = f0 + kappa u_comp (the forces that paper Sec. 4.2 and 4.3 add to
+ * Eq. NS_prov; a constant driving gradient is ibm_opts.dpdx), evaluated from
+ * u^s and weighted by alpha like the driving gradient, on every unknown node
+ * of the component that is not a forcing node.  f0, kappa: dev f64 arrays on
+ * the component's lattice (v: nx*(ny+1)*nz values, walls included and
+ * ignored), owned by the caller and read by every later ibm_viscous and
+ * ibm_step until replaced; NULL = 0 (both NULL clears the force).
+ * IBM_EINVAL for a bad component. */
+int ibm_set_volume_force(ibm_ctx* ctx, int32_t comp, const double* f0, const double* kappa);
+
 int ibm_viscous(ibm_ctx* ctx, const void* p, const void* const* h_prev,
                 void* const* h_out, double gamma, double rho, double dt,
                 double* u, double* v, double* w);
@@ -311,6 +348,25 @@ int ibm_divergence(ibm_ctx* ctx, const double* u, const double* v, const double*
  * count); a count above out_cap fills out_cap values and raises
  * IBM_FLAG_CAPACITY.  Enqueued on the context's stream. */
 int ibm_pressure_cb(ibm_ctx* ctx, const void* p, double* out, int64_t out_cap);
+
+/* Hydrodynamic loads (paper Sec. 3.3) on the bodies of the last ibm_tag
+ * (the same triangulation; the vertices as they were then).  Markers are the
+ * triangle centroids X (normal n from the triangle's winding, area A); for
+ * each, a probe point X + s h n (h twice the diagonal of the grid cell that
+ * holds X; side s = +1, and also -1 where sides[b] == 2: zero-thickness
+ * bodies) carries second-order moving-least-squares fits of p, u, v, w (the
+ * 4x4x4 nodes of each lattice around it that lie in front of the marker's
+ * tangent plane, fluid cells only for p, Gaussian weights), Taylor-expanded
+ * back to X; the traction t = -p n_s + (G + G^T) n_s / Re is summed over the
+ * sides.  u, v, w: dev f64 state arrays; p: dev, f64 (IBM_FP64) or f32
+ * (IBM_MIXED); sides: dev i32[nb] (2: two-sided, else one side); pole: dev
+ * f64[3 nb], the torque pole of each body; traction: dev f64[3 ntri] (per
+ * marker, bodies in tagging order); loads: dev f64[6 nb], (F, M) per body,
+ * F = sum t A, M = sum (X - pole) x t A, summed in a fixed order.  All
+ * buffers are the caller's.  IBM_EINVAL for a null argument or no tagged
+ * body.  Enqueued on the context's stream, no synchronisation. */
+int ibm_loads(ibm_ctx* ctx, const double* u, const double* v, const double* w, const void* p,
+              const int32_t* sides, const double* pole, double* traction, double* loads);
 
 /* Projection and pressure update (paper Eqs. projection, update_pressure):
  * u <- u - alpha_dt G phi on every interior velocity node;

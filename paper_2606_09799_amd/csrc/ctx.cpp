@@ -110,6 +110,9 @@ struct ibm_ctx {
   void* spec64 = nullptr;
   // mixed form: FP64-residual refinement of the Poisson solve
   double* rhs_keep = nullptr;
+  // volume force per component (caller's arrays): f0 + kappa u_c
+  const double* vf0[3] = {nullptr, nullptr, nullptr};
+  const double* vkap[3] = {nullptr, nullptr, nullptr};
   u64* rmax = nullptr;
   double* rstats = nullptr;
   double* zm = nullptr;
@@ -698,6 +701,22 @@ int ibm_body_rigid(ibm_ctx* c, const double* x0, int32_t nv, const double* coef,
   return launch_status();
 }
 
+int ibm_body_rigid_dev(ibm_ctx* c, const double* x0, int32_t nv, const double* coef,
+                       double* xyz, double* vel) {
+  if (!c || !coef || nv < 0 || (nv > 0 && (!x0 || !xyz || !vel)))
+    FAIL(IBM_EINVAL, "ibm_body_rigid_dev: bad argument");
+  launch_body_dev(&c->prof, c->stream, 0, x0, nv, coef, xyz, vel);
+  return launch_status();
+}
+
+int ibm_rigid_advance(ibm_ctx* c, int32_t nb, double* state, const double* props,
+                      const double* loads, double dt, double* coef) {
+  if (!c || nb < 0 || (nb > 0 && (!state || !props || !loads || !coef)) || !(dt > 0))
+    FAIL(IBM_EINVAL, "ibm_rigid_advance: bad argument");
+  launch_rigid_advance(&c->prof, c->stream, nb, state, props, loads, dt, coef);
+  return launch_status();
+}
+
 int ibm_body_deform(ibm_ctx* c, const double* data, int32_t nv, const double* coef, double* xyz,
                     double* vel) {
   if (!c || !coef || nv < 0 || (nv > 0 && (!data || !xyz || !vel))) FAIL(IBM_EINVAL, "ibm_body_deform: bad argument");
@@ -849,6 +868,10 @@ static int viscous(ibm_ctx* c, const void* p, const void* const* hprev, void* co
   a.planes = c->rhs_planes;
   launch_rhs(&c->prof, c->stream, c->g, a);
   double* f[3] = {u, v, w};
+  for (int q = 0; q < 3; ++q)
+    if (c->vf0[q] || c->vkap[q])
+      launch_vforce(&c->prof, c->stream, c->g, q, c->R[q], c->fp32, c->tb.mask[q], f[q],
+                    c->vf0[q], c->vkap[q], alpha * dt);
   for (int q = 0; q < 3; ++q) {
     launch_adi_x(&c->prof, c->stream, c->g, q, c->R[q], c->tb.mask[q], c->ctx_x, c->sa, c->sc,
                  c->fp32);
@@ -858,6 +881,13 @@ static int viscous(ibm_ctx* c, const void* p, const void* const* hprev, void* co
                  c->yt[q == 1 ? 1 : 0], c->sa, c->sc, c->fp32);
   }
   return launch_status();
+}
+
+int ibm_set_volume_force(ibm_ctx* c, int32_t comp, const double* f0, const double* kappa) {
+  if (!c || comp < 0 || comp > 2) FAIL(IBM_EINVAL, "ibm_set_volume_force: bad argument");
+  c->vf0[comp] = f0;
+  c->vkap[comp] = kappa;
+  return IBM_OK;
 }
 
 int ibm_viscous(ibm_ctx* c, const void* p, const void* const* h_prev, void* const* h_out,
@@ -953,6 +983,16 @@ int ibm_divergence(ibm_ctx* c, const double* u, const double* v, const double* w
   out[0] = h[0];
   out[1] = h[1];
   return IBM_OK;
+}
+
+int ibm_loads(ibm_ctx* c, const double* u, const double* v, const double* w, const void* p,
+              const int32_t* sides, const double* pole, double* traction, double* loads) {
+  if (!c || !u || !v || !w || !p || !sides || !pole || !traction || !loads)
+    FAIL(IBM_EINVAL, "ibm_loads: null argument");
+  if (c->bodies.empty()) FAIL(IBM_EINVAL, "ibm_loads: no bodies in the last tagging");
+  launch_loads(&c->prof, c->stream, c->g, c->d_bodies, (int)c->bodies.size(), c->ntri, u, v, w,
+               p, c->fp32, c->tb.cb_mask, sides, pole, c->opts.re, traction, loads);
+  return launch_status();
 }
 
 int ibm_pressure_cb(ibm_ctx* c, const void* p, double* out, int64_t out_cap) {

@@ -234,6 +234,11 @@ struct RhsArgs {
   int planes;  // wall-normal planes per block of the march (1..64; 0: the default)
 };
 void launch_rhs(Prof* pf, hipStream_t s, const GridView& g, const RhsArgs& a);
+// volume force of component comp: R += adt (f0 + kappa u) on its unknown
+// nodes that are not forcing nodes (f0, kappa: NULL = 0)
+void launch_vforce(Prof* pf, hipStream_t s, const GridView& g, int comp, void* R, int fp32,
+                   const uint32_t* mask, const double* u, const double* f0, const double* kappa,
+                   double adt);
 
 // adi.hip
 // d, sa, sc: FP64, or FP32 when fp32 is set.  sa, sc: scratch of the size of
@@ -313,6 +318,17 @@ void launch_poisson(Prof* pf, hipStream_t s, const GridView& g, const PoissonArg
 // p: FP64, or FP32 when fp32 is set
 void launch_project(Prof* pf, hipStream_t s, const GridView& g, const double* phi, double adt,
                     double re, double* u, double* v, double* w, void* p, int fp32);
+
+// hydrodynamic loads (loads.hip): per-marker tractions (3 ntri) and per-body
+// force and torque about pole (6 nb) of the bodies of the last tagging
+void launch_loads(Prof* pf, hipStream_t s, const GridView& g, const BodyDev* bodies, int nb,
+                  int ntri, const double* u, const double* v, const double* w, const void* p,
+                  int p32, const uint32_t* cb_mask, const int32_t* sides, const double* pole,
+                  double re, double* traction, double* loads);
+
+// rigid-body dynamics (rigid.hip): one AB2 step per body, coefficients out
+void launch_rigid_advance(Prof* pf, hipStream_t s, int nb, double* state, const double* props,
+                          const double* loads, double dt, double* coef);
 
 // utilities (util.hip)
 void launch_fill_u32(Prof* pf, hipStream_t s, uint32_t* p, int64_t n, uint32_t val);

@@ -452,4 +452,36 @@ void launch_rhs(Prof* pf, hipStream_t s, const GridView& g, const RhsArgs& a) {
     run_rhs<double>(pf, s, g, a);
 }
 
+// Volume force of one component (the forces that Sec. 4.2 and 4.3 add to
+// Eq. NS_prov), added to the right-hand side the RHS pass wrote:
+// R += alpha dt (f0 + kappa u) on the component's unknown nodes [lo, hi)
+// that are not forcing nodes, in FP64 arithmetic.
+template <typename T>
+__global__ __launch_bounds__(256) void k_vforce(int64_t lo, int64_t hi, T* __restrict__ R,
+                                                const uint32_t* __restrict__ mask,
+                                                const double* __restrict__ u,
+                                                const double* __restrict__ f0,
+                                                const double* __restrict__ kap, double adt) {
+  const int64_t i = lo + (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= hi || test_bit(mask, i)) return;
+  double f = f0 ? f0[i] : 0.0;
+  if (kap) f += kap[i] * u[i];
+  R[i] = (T)((double)R[i] + adt * f);
+}
+
+void launch_vforce(Prof* pf, hipStream_t s, const GridView& g, int comp, void* R, int fp32,
+                   const uint32_t* mask, const double* u, const double* f0, const double* kappa,
+                   double adt) {
+  const int64_t plane = (int64_t)g.nz * g.nx;
+  const int64_t lo = (comp == 1) ? plane : 0, hi = (int64_t)g.ny * plane;  // v: interior faces
+  const unsigned blocks = (unsigned)((hi - lo + 255) / 256);
+  if (fp32)
+    IBM_LAUNCH(pf, "vforce", s,
+               (k_vforce<float><<<blocks, 256, 0, s>>>(lo, hi, (float*)R, mask, u, f0, kappa, adt)));
+  else
+    IBM_LAUNCH(pf, "vforce", s,
+               (k_vforce<double><<<blocks, 256, 0, s>>>(lo, hi, (double*)R, mask, u, f0, kappa,
+                                                        adt)));
+}
+
 }  // namespace ibm

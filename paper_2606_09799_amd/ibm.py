@@ -27,6 +27,7 @@ IBM_ENONFINITE, IBM_ECFL, IBM_EGEOM, IBM_ECOMPAT = -5, -6, -7, -8
 FLAG_CAPACITY, FLAG_NONFINITE, FLAG_GEOM, FLAG_REFINE = 1, 2, 4, 8
 FLAG_CFL, FLAG_COMPAT = 16, 32
 IBM_REFINE_STATS = 6
+IBM_RIGID_STATE, IBM_RIGID_PROPS = 28, 8
 IBM_FP64, IBM_MIXED = 0, 1
 IBM_RK2CN, IBM_AB2CN = 0, 1
 IBM_Q_NONE, IBM_Q_UNIFORM, IBM_Q_ENERGY = 0, 1, 2
@@ -119,6 +120,13 @@ _check = _sig("ibm_check", c_int32, c_void_p, POINTER(c_uint32))
 _noslip = _sig("ibm_noslip_error", c_int32, c_void_p, c_void_p, c_void_p, c_void_p,
                POINTER(c_double))
 _pressure_cb = _sig("ibm_pressure_cb", c_int32, c_void_p, c_void_p, c_void_p, c_int64)
+_vforce = _sig("ibm_set_volume_force", c_int32, c_void_p, c_int32, c_void_p, c_void_p)
+_body_rigid_dev = _sig("ibm_body_rigid_dev", c_int32, c_void_p, c_void_p, c_int32, c_void_p,
+                       c_void_p, c_void_p)
+_rigid_advance = _sig("ibm_rigid_advance", c_int32, c_void_p, c_int32, c_void_p, c_void_p,
+                      c_void_p, c_double, c_void_p)
+_loads = _sig("ibm_loads", c_int32, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_void_p,
+              c_void_p, c_void_p, c_void_p)
 _divergence = _sig("ibm_divergence", c_int32, c_void_p, c_void_p, c_void_p, c_void_p,
                    POINTER(c_double))
 _strerror = _sig("ibm_strerror", c_char_p, c_int32)
@@ -133,7 +141,8 @@ EXPORTS = ("ibm_create", "ibm_destroy", "ibm_set_stream", "ibm_body_rigid", "ibm
            "ibm_batch_create", "ibm_batch_destroy", "ibm_batch_context", "ibm_batch_step",
            "ibm_batch_check", "ibm_batch_set_plan", "ibm_batch_get_plan", "ibm_batch_tune",
            "ibm_batch_tune_scratch_bytes", "poisson_solve_static",
-           "ibm_noslip_error", "ibm_pressure_cb", "ibm_divergence")
+           "ibm_noslip_error", "ibm_pressure_cb", "ibm_divergence", "ibm_loads",
+           "ibm_set_volume_force", "ibm_body_rigid_dev", "ibm_rigid_advance")
 COEF_STRIDE = 18
 BATCH_SERIAL, BATCH_STREAMS, BATCH_GRAPH, BATCH_PLAN = 0, 1, 2, 3
 _MODE_NAMES = {BATCH_STREAMS: "streams", BATCH_GRAPH: "graph"}
@@ -327,6 +336,50 @@ def ibm_noslip_error(ctx, u, v, w):
                 _dev(v, torch.float64, ctx.vfaces, "v"), _dev(w, torch.float64, ctx.cells, "w"),
                 eps), "ibm_noslip_error")
     return eps[0], [eps[1], eps[2], eps[3]]
+
+
+def ibm_body_rigid_dev(ctx, x0, coef, xyz, vel):
+    """ibm_body_rigid with the coefficients in a float64 device tensor (18)."""
+    nv = x0.shape[0]
+    _ok(_body_rigid_dev(ctx.handle, _dev(x0, torch.float64, 3 * nv, "x0"), nv,
+                        _dev(coef, torch.float64, 18, "coef"),
+                        _dev(xyz, torch.float64, 3 * nv, "xyz"),
+                        _dev(vel, torch.float64, 3 * nv, "vel")), "ibm_body_rigid_dev")
+
+
+def ibm_rigid_advance(ctx, state, props, loads, dt, coef):
+    """One AB2 step of nb free rigid bodies: state (nb, IBM_RIGID_STATE),
+    props (nb, IBM_RIGID_PROPS), loads (nb, 6), coef (nb, 18) float64 device
+    tensors."""
+    nb = loads.numel() // 6
+    _ok(_rigid_advance(ctx.handle, nb, _dev(state, torch.float64, nb * IBM_RIGID_STATE, "state"),
+                       _dev(props, torch.float64, nb * IBM_RIGID_PROPS, "props"),
+                       _dev(loads, torch.float64, 6 * nb, "loads"), float(dt),
+                       _dev(coef, torch.float64, 18 * nb, "coef")), "ibm_rigid_advance")
+
+
+def ibm_set_volume_force(ctx, comp, f0=None, kappa=None):
+    """Volume force f0 + kappa u_comp on component comp (float64 device
+    tensors on its lattice, or None); the context keeps references to them."""
+    numel = ctx.comp_numel(comp)
+    _ok(_vforce(ctx.handle, int(comp), _dev(f0, torch.float64, numel, "f0"),
+                _dev(kappa, torch.float64, numel, "kappa")), "ibm_set_volume_force")
+    if not hasattr(ctx, "_vforce"):
+        ctx._vforce = {}
+    ctx._vforce[comp] = (f0, kappa)
+
+
+def ibm_loads(ctx, u, v, w, p, sides, pole, traction, loads):
+    """Hydrodynamic loads (Sec. 3.3) of the bodies of the last tagging.
+    sides: i32 device tensor (nb,), 2 for a two-sided body; pole: f64 (nb, 3);
+    traction: f64 (ntri, 3) per marker; loads: f64 (nb, 6), force and torque."""
+    nb = sides.numel()
+    _ok(_loads(ctx.handle, _dev(u, torch.float64, ctx.cells, "u"),
+               _dev(v, torch.float64, ctx.vfaces, "v"), _dev(w, torch.float64, ctx.cells, "w"),
+               _dev(p, ctx.pdtype, ctx.cells, "p"), _dev(sides, torch.int32, nb, "sides"),
+               _dev(pole, torch.float64, 3 * nb, "pole"),
+               _dev(traction, torch.float64, traction.numel(), "traction"),
+               _dev(loads, torch.float64, 6 * nb, "loads")), "ibm_loads")
 
 
 def ibm_pressure_cb(ctx, p, out):

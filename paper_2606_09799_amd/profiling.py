@@ -101,6 +101,8 @@ def summarise(tag, trace, fetch, write, copy_mib, trace_cmd, pmc_cmd, workload):
     os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
     with open(os.path.join(ROOT, "profiles", f"{tag}_kernel_trace.md"), "w") as f:
         f.write("\n".join(lines) + "\n")
+    if not fetch or not write:  # a trace-only summary
+        return sha, None, None
 
     (fe, cf), (wr, cw) = pmc_per_kernel(fetch), pmc_per_kernel(write)
     ref_kib = copy_mib * 1024.0
@@ -140,8 +142,8 @@ def main():
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--tag", required=True)
     ap.add_argument("--trace", required=True)
-    ap.add_argument("--fetch", required=True)
-    ap.add_argument("--write", required=True)
+    ap.add_argument("--fetch", default="", help="FETCH_SIZE run (omit for a trace-only summary)")
+    ap.add_argument("--write", default="", help="WRITE_SIZE run (omit for a trace-only summary)")
     ap.add_argument("--copy-mib", type=int, default=1024)
     ap.add_argument("--trace-cmd", default="", help="bench.py arguments of the traced run")
     ap.add_argument("--pmc-cmd", default="", help="bench.py arguments of the counter runs")

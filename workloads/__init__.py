@@ -209,14 +209,20 @@ def splitmix64_uniform_torch(seed: int, comp: int, n: int, device, start: int = 
     return srl(z, 11).to(torch.float64) * (1.0 / 9007199254740992.0)
 
 
+def _profile(yn, uc, half, profile):
+    if profile is not None:
+        return np.asarray(profile(yn), np.float64)
+    yh = yn / half
+    return uc * (1.0 - yh * yh)
+
+
 def initial_velocity_torch(nx, ny, nz, y_faces, uc=1.0, amp=0.01, seed=1, half=1.0,
-                           device="cpu"):
+                           device="cpu", profile=None):
     """initial_velocity computed by torch on `device`, plane by plane (the
     same values bit for bit; flat tensors u, v, w)."""
     import torch
     yf = np.asarray(y_faces, np.float64)
-    yh = ((yf[:-1] + yf[1:]) * 0.5) / half
-    prof = torch.from_numpy(uc * (1.0 - yh * yh)).to(device)
+    prof = torch.from_numpy(_profile((yf[:-1] + yf[1:]) * 0.5, uc, half, profile)).to(device)
     plane = nx * nz
     u = torch.empty(ny * plane, dtype=torch.float64, device=device)
     v = torch.zeros((ny + 1) * plane, dtype=torch.float64, device=device)
@@ -236,16 +242,16 @@ def initial_velocity_torch(nx, ny, nz, y_faces, uc=1.0, amp=0.01, seed=1, half=1
     return u, v, w
 
 
-def initial_velocity(nx, ny, nz, y_faces, uc=1.0, amp=0.01, seed=1, half=1.0):
+def initial_velocity(nx, ny, nz, y_faces, uc=1.0, amp=0.01, seed=1, half=1.0, profile=None):
     """Laminar profile u = uc (1 - (y/half)^2) at the u-node heights (walls at
-    y = -half and +half) plus a seeded uniform perturbation amp*(2 xi - 1) on
-    every interior u, v, w unknown.  Layout [y][z][x]; v has ny+1 planes, the
-    wall planes are 0.  Returns (u, v, w) f64 arrays."""
+    y = -half and +half; or profile(y) when given) plus a seeded uniform
+    perturbation amp*(2 xi - 1) on every interior u, v, w unknown.  Layout
+    [y][z][x]; v has ny+1 planes, the wall planes are 0.  Returns (u, v, w)
+    f64 arrays."""
     yf = np.asarray(y_faces, np.float64)
     yn = (yf[:-1] + yf[1:]) * 0.5                     # u-node heights
     n = nx * ny * nz
-    yh = yn / half
-    u = (uc * (1.0 - yh * yh))[:, None, None] * np.ones((ny, nz, nx))
+    u = _profile(yn, uc, half, profile)[:, None, None] * np.ones((ny, nz, nx))
     u += amp * (2.0 * splitmix64_uniform(seed, 0, n).reshape(ny, nz, nx) - 1.0)
     v = np.zeros((ny + 1, nz, nx))
     nv = (ny - 1) * nz * nx
@@ -285,6 +291,12 @@ class Workload:
     bodies: list = field(default_factory=list)
     scheme: str = "rk2"
     half: float = 1.0          # channel half-height (walls at +-half)
+    # the initial laminar profile u(y) at the u-node heights (None: the
+    # parabola uc (1 - (y/half)^2) of a channel with walls at +-half)
+    profile: object = None
+    # volume force of the immersed-plane channels of Sec. 4.2 / 4.3
+    # ("vortex" / "relax"; None: only the constant driving gradient dpdx)
+    vforce: object = None
 
     @property
     def cells(self) -> int:
@@ -292,11 +304,11 @@ class Workload:
 
     def fields(self):
         return initial_velocity(self.nx, self.ny, self.nz, self.y_faces,
-                                self.uc, self.amp, self.seed, self.half)
+                                self.uc, self.amp, self.seed, self.half, self.profile)
 
     def fields_torch(self, device):
         return initial_velocity_torch(self.nx, self.ny, self.nz, self.y_faces, self.uc,
-                                      self.amp, self.seed, self.half, device)
+                                      self.amp, self.seed, self.half, device, self.profile)
 
 
 def _sphere_body(level, radius, c0, U):
@@ -349,6 +361,10 @@ def config(name: str) -> Workload:
         ny = 768
         return Workload("c5", 1024, ny, 1024, two_pi, pi, tanh_faces(ny, 2.0), 2800.0,
                         1e-3, 50, 1.5, 0.1, 5, -2.0 * 1.5 / 2800.0, c5_bodies())
+    if name == "plane":
+        return plane_channel(180)
+    if name == "turb":
+        return turbulent_plane_channel()
     if name == "tiny":
         # ragged, non-power-of-two sizes: 40 = 8*5 and 36 = 4*9 exercise the
         # mixed-radix transforms; the sphere spans several tiles.
@@ -363,6 +379,90 @@ def config(name: str) -> Workload:
                         2e-3, 3, 1.0, 0.02, 11, -2.0 / 200.0,
                         [Body("rigid", V, F, plate_heave_pitch)])
     raise KeyError(name)
+
+
+def _full_span_plane(lx, lz, y0, nq_x, nq_z):
+    P, T = plate_mesh(lx, lz, nq_x, nq_z)
+    centre = (0.5 * lx, y0, 0.5 * lz)
+    return Body("rigid", P, T, lambda t: sphere_translation(t, centre, (0.0, 0.0, 0.0)))
+
+
+def plane_channel(N: int = 180) -> Workload:
+    """Sec. 4.2: the channel x in [-1, 1) (here [0, 2)), z likewise, y in
+    [-1/4, 2] with no-slip walls, split by a full-span immersed plane near
+    y = 0; above it a driving force (plane Poiseuille flow of centre velocity
+    1 between the plane and y = 2, Re 100), below it the wall-normal vortex
+    forcing F_y = 50 sin(pi (y + 1/4)/(1/4)) cos(pi x).  Uniform spacing
+    Delta = 2/N; the plane sits at y0 = 0.37 Delta, off every node (the
+    paper scales the lower grid for the same purpose).  Starts from the
+    exact upper profile, zero below."""
+    d = 2.0 / N
+    ny = int(round(2.25 / d))
+    yf = uniform_faces(ny, -0.25, 2.0)
+    y0 = 0.37 * d
+    prof = lambda y: np.where(y > y0, (y - y0) * (2.0 - y) / ((1.0 - 0.5 * y0) ** 2), 0.0)
+    wl = Workload("plane", N, ny, N, 2.0, 2.0, yf, 100.0, 0.25 * d, 100, 1.0, 0.0, 6, 0.0,
+                  [_full_span_plane(2.0, 2.0, y0, N // 4, N // 4)], profile=prof, vforce="vortex")
+    return wl
+
+
+def _cluster_faces(n: int, y0: float, y1: float, beta: float = 1.6) -> np.ndarray:
+    """n+1 faces on [y0, y1] clustered at both ends (tanh)."""
+    j = np.arange(n + 1, dtype=np.float64)
+    s = np.tanh(beta * (2.0 * j / n - 1.0)) / math.tanh(beta)
+    yf = y0 + 0.5 * (y1 - y0) * (s + 1.0)
+    yf[0], yf[-1] = y0, y1
+    return yf
+
+
+def turbulent_plane_channel() -> Workload:
+    """Sec. 4.3: x in [0, 4 pi), z in [0, 2 pi) (256 x 256 points), y in
+    [-1/4, 2]: 127 cells clustered at the plane and at y = 2 above it, 31
+    uniform cells below; Re_tau = 200 (u_tau = delta = 1), AB2 + CN; a
+    driving force 1 (= u_tau^2/delta) above the plane and the relaxation
+    F_y = -5 (v - 1) below it.  The plane lies at 0.37 of the first upper
+    cell, off every node (the paper's formula for the upper grid is
+    garbled; tanh clustering stands in for it).  Starts from a turbulent-like
+    mean profile (centre velocity 18) with a 1.0 perturbation."""
+    upper = _cluster_faces(127, 0.0, 2.0)
+    lower = uniform_faces(31, -0.25, 0.0)
+    yf = np.concatenate([lower[:-1], upper])
+    y0 = 0.37 * (upper[1] - upper[0])
+    prof = lambda y: np.where(y > y0, 18.0 * (1.0 - (y - 1.0) ** 2), 0.0)
+    lx, lz = 4.0 * math.pi, 2.0 * math.pi
+    return Workload("turb", 256, 158, 256, lx, lz, yf, 200.0, 5e-4, 100, 1.0, 1.0, 7, 0.0,
+                    [_full_span_plane(lx, lz, y0, 64, 32)], scheme="ab2", profile=prof,
+                    vforce="relax")
+
+
+def volume_force(wl: Workload, comp: int):
+    """(f0, kappa) of component comp of the immersed-plane channels on its
+    lattice ([y][z][x] numpy arrays; kappa None where it vanishes), or
+    (None, None) for a workload without volume force."""
+    if wl.vforce is None:
+        return None, None
+    dx, dz = wl.lx / wl.nx, wl.lz / wl.nz
+    yf = np.asarray(wl.y_faces, np.float64)
+    ox, oz = {0: (0.0, 0.5), 1: (0.5, 0.5), 2: (0.5, 0.0)}[comp]
+    ys = yf if comp == 1 else 0.5 * (yf[:-1] + yf[1:])
+    x = (np.arange(wl.nx) + ox) * dx
+    z = (np.arange(wl.nz) + oz) * dz
+    Y, _, X = np.meshgrid(ys, z, x, indexing="ij")
+    lo = float(yf[0])
+    body_y = float(wl.bodies[0].coef(0.0)[1])     # the plane's height
+    f0 = np.zeros(Y.shape)
+    kappa = None
+    if comp == 0:
+        drive = 2.0 / (wl.re * (1.0 - 0.5 * body_y) ** 2) if wl.vforce == "vortex" else 1.0
+        f0[Y > body_y] = drive
+    elif comp == 1:
+        below = (Y > lo) & (Y < 0.0)
+        if wl.vforce == "vortex":
+            f0[below] = (50.0 * np.sin(np.pi * (Y - lo) / (-lo)) * np.cos(np.pi * X))[below]
+        else:
+            f0[below] = 5.0
+            kappa = np.where(below, -5.0, 0.0)
+    return f0, kappa
 
 
 def leaflet_mesh(radius: float, chord: float, span: float, n_arc: int, n_span: int):
