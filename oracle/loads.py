@@ -24,7 +24,10 @@ a cited companion paper):
   1, X, Y, Z, X^2, Y^2, Z^2, XY, YZ, XZ in the scaled coordinates
   (x - x^e)/D; the fit is the weighted least-squares solution;
 * with a quadratic basis the third derivatives vanish, so the h^2 term of
-  the velocity-gradient expansion is zero.
+  the velocity-gradient expansion is zero;
+* a probe point exactly on a lattice line (the paper is silent): the window
+  follows from floor(x^e/dx - o) as evaluated, and the tangent-plane test is
+  the three products summed left to right, both in plain binary64.
 """
 from __future__ import annotations
 
@@ -92,7 +95,8 @@ def mls_fit(g, q, field, xe, X, ns, D, cb_mask=None):
     (value, gradient (3,), Hessian (3, 3)) at xe."""
     rows, rhs, wts = [], [], []
     for pos, (j, k, i) in stencil(g, q, xe):
-        if np.dot(pos - X, ns) <= 0.0:
+        r = pos - X
+        if r[0] * ns[0] + r[1] * ns[1] + r[2] * ns[2] <= 0.0:
             continue                        # behind the marker's tangent plane
         if q == "p" and cb_mask is not None and cb_mask[j, k, i]:
             continue                        # C_B cell: p is not defined there

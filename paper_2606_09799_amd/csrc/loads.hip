@@ -14,7 +14,15 @@
 // at x_e, and the traction t = -p_X n_s + (G_X + G_X^T) n_s / Re, summed over
 // the sides.  A second kernel sums t A and (X - pole) x t A per body, in a
 // fixed order (one block per body).
+//
+// The marker geometry, the probe point and the stencil decisions (the floor
+// that places the 4 x 4 x 4 window, the y bracket, the tangent-plane test)
+// use IEEE binary64 +, -, *, / in the written order, without contraction
+// into FMA, so that a probe point lying exactly on a lattice line takes the
+// same window as a plain evaluation of the same expressions.
 #include "lanes.h"
+
+#pragma clang fp contract(off)
 
 namespace ibm {
 

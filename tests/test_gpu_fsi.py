@@ -8,6 +8,12 @@ Sec. 3.3) through the C-ABI against the oracle:
   its centre), its AB2 step and its new vertices (`ibm_body_rigid_dev`), for
   4 steps: the body state within 1e-10 and the fluid within 1e-10 of the
   same loop run by the oracle.
+
+The loop runs twice: with the sphere centred on grid lines, where 32
+probe points lie exactly on a lattice line of u, w or y (the 4x4x4 window
+is then decided by the last bit of x^e, which both sides form in plain
+binary64 without FMA: the ties must resolve alike), and off them, where the
+fixture checks that no probe point comes within 1e-9 cells of a line.
 """
 import numpy as np
 import pytest
@@ -48,13 +54,32 @@ def test_rigid_advance_against_oracle():
     ctx.close()
 
 
-def test_coupled_sphere_against_oracle():
+def _min_lattice_gap(g, X, tris):
+    """Smallest distance, in cells, of any marker's probe point from a
+    lattice line of u, v, w or p (x and z) or from a y node."""
+    Xm, nm, _ = oloads.markers(X, tris)
+    gap = np.inf
+    for m in range(len(Xm)):
+        j = oloads.cell_j(g, Xm[m][1])
+        h = 2.0 * np.sqrt(g.dx ** 2 + g.dz ** 2 + g.dy[j] ** 2)
+        xe = Xm[m] + h * nm[m]
+        for o in (0.0, 0.5):
+            for val in (xe[0] / g.dx - o, xe[2] / g.dz - o):
+                gap = min(gap, abs(val - np.round(val)))
+        gap = min(gap, np.min(np.abs(np.concatenate([g.yc, g.yf]) - xe[1])) / g.dy[j])
+    return gap
+
+
+@pytest.mark.parametrize("placement", ["on_grid_lines", "off_grid_lines"])
+def test_coupled_sphere_against_oracle(placement):
     wl = workloads.config("c1")
     b = wl.bodies[0]
     case = Case(wl)
     g = case.g
     X0 = b.ref                                   # vertices about the centre
     c0 = np.array([np.pi, 0.0, 0.5 * np.pi])
+    if placement == "off_grid_lines":
+        c0 += np.array([0.013, 0.021, 0.007])
     st = rigid.initial_state(c0, [1.0, 0.0, 0.0, 0.0], [0.5, 0.0, 0.0], [0.0, 0.0, 0.0])
     r = 0.25
     vol = 4.0 / 3.0 * np.pi * r ** 3
@@ -86,6 +111,11 @@ def test_coupled_sphere_against_oracle():
         body = ibm.Body(xyz, vel, trid)
         ibm.ibm_step(case.ctx, *d, pdv, [body], dt)
         X, U = kinematics.rigid(X0, coef)
+        gap = _min_lattice_gap(g, X, b.tris)
+        if placement == "off_grid_lines":
+            assert gap > 1e-9, k
+        elif k == 0:
+            assert gap == 0.0                    # the ties are exercised
         f, p, _, tags = ostep.step(g, f, p, (X, U, b.tris), dt, wl.re, case.fext)
         # loads about the centre, then the body's step
         ibm.ibm_loads(case.ctx, *d, pdv, sides, sd[:, 0:3].contiguous(), tr, ld)
