@@ -653,7 +653,7 @@ __device__ __forceinline__ void col_coef(const LineK<T>& K, int i, T& a, T& b, T
 }
 
 template <typename T, int MODE, int SL, int TL>
-__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(SL == 12 ? 5 : 1)))
+__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(SL == 12 ? 5 : (SL == 32 ? 8 : 1))))
 void k_line_col(LineK<T> K) {
   // TL lines per block: 16, or 32 in FP32 (a wavefront's loads then cover
   // 128-byte row pieces in both), and 32 with the long segments (24 or 32
@@ -668,9 +668,17 @@ void k_line_col(LineK<T> K) {
   T* Y = tabs + LINE_NTAB * SL * tP;         // a0, c0, d0 of each segment; then z
   T* X = Y + 3 * PP * SP;                    // separator rows ra, rb, rg, rd
   uint32_t* mws = reinterpret_cast<uint32_t*>(X + 4 * PP * SP);  // [P][SL] mask words
+  // y sweep: the rows' coefficients a, b, c (read by segments with identity
+  // rows), after the mask words
+  T* cf = reinterpret_cast<T*>(mws + P * SL);
   for (int q = tid; q < LINE_NTAB * tP * SL; q += blockDim.x) {
     const int qe = q / tP, ss = q % tP, qq = qe / SL, ee = qe % SL;
     tabs[q] = K.tab[((size_t)qq * P + ss) * LINE_TLD + ee];  // global: LINE_TLD per segment
+  }
+  if (MODE == 2) {
+    const int nl = P * SL;
+    for (int q = tid; q < 3 * nl; q += blockDim.x)
+      cf[q] = (q < nl) ? K.A[q] : (q < 2 * nl ? K.B[q - nl] : K.C[q - 2 * nl]);
   }
   const int lb = tid % TL, s = tid / TL;
   const bool active = s < P;
@@ -688,24 +696,51 @@ void k_line_col(LineK<T> K) {
   const int lo = s * SL;
   constexpr int m = SL - 1;
   T dd[SL];
-  double uu[MODE == 2 ? SL : 1];
+  // y sweep: the velocity is prefetched over the last barrier
+  constexpr bool UPRE = MODE == 2;
+  // segments with identity rows (rare): in the lean form (z sweeps, whose
+  // lines seldom meet a body, and long segments) the rows go through memory
+  // and the common path keeps its occupancy; the register form keeps them
+  // in dd, faster where many lines cross a body (a plate spanning the
+  // wall-normal lines)
+  constexpr bool LEAN = MODE == 1 || SL >= 24;
+  constexpr int RC = 4;  // rows per memory round trip on the lean rare path
+  double uu[UPRE ? SL : 1];
   T dz = 0, az = 0, bz = 1, cz = 0;
-  T a0 = 0, c0 = 0, ahl = 0, chl = 0, dhl = 0;
-  uint32_t mbits = 0;
-  // rows are addressed from the wavefront's first row (a uniform base) plus
-  // a 32-bit byte offset, one register per row instead of a 64-bit address
+  T a0 = 0, c0 = 0, d0 = 0, ahl = 0, chl = 0, dhl = 0;
+  // forcing rows: any among the segment's interior rows (then the rare
+  // path), and the separator row
+  bool rare = false, last_forced = false;
+  // rows are addressed through buffer descriptors based at the wavefront's
+  // first row: one per-lane byte offset (line and segment) and a uniform
+  // row offset in a scalar register, instead of one address per row held
+  // from the loads to the stores
   const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
-  const int64_t wrow = (int64_t)wv * (64 / TL) * SL;  // first row of the wavefront
-  const T* dbase = K.d + boff + wrow * es;
-  const double* ubase = (MODE == 2) ? K.u + boff + wrow * es : nullptr;
-  const uint32_t lrow = (uint32_t)(lo - wrow);           // this segment's first row, from wrow
-  auto boffs = [&](int e, uint32_t sz) -> uint32_t {
-    return ((uint32_t)lb + (lrow + (uint32_t)e) * (uint32_t)es) * sz;
+  constexpr int WROWS = (64 / TL) * SL;                   // rows of one wavefront
+  const int64_t wrow = (int64_t)wv * WROWS;               // its first row
+  const uint32_t lrow = (uint32_t)(lo - wrow);            // this segment's first row, from wrow
+  const __amdgpu_buffer_rsrc_t dres =
+      buf_rsrc(K.d + boff + wrow * es, (uint32_t)(WROWS * es * (int64_t)sizeof(T)));
+  const __amdgpu_buffer_rsrc_t ures =
+      buf_rsrc((MODE == 2) ? K.u + boff + wrow * es : nullptr, (uint32_t)(WROWS * es * 8));
+  const uint32_t vline = (uint32_t)lb + lrow * (uint32_t)es;  // element offset of row 0
+  const uint32_t rstride = (uint32_t)es;                      // elements per row
+  // the line-solve scratch (coefficients of segments with identity rows)
+  // has the layout of d
+  const __amdgpu_buffer_rsrc_t sares =
+      buf_rsrc(K.sa + boff + wrow * es, (uint32_t)(WROWS * es * (int64_t)sizeof(T)));
+  const __amdgpu_buffer_rsrc_t scres =
+      buf_rsrc(K.sc + boff + wrow * es, (uint32_t)(WROWS * es * (int64_t)sizeof(T)));
+  auto roff = [&](int e) -> uint32_t { return (uint32_t)e * rstride * (uint32_t)sizeof(T); };
+  const uint32_t vlb = vline * (uint32_t)sizeof(T);
+  auto u_at = [&](int e) -> double {
+    return UPRE ? uu[UPRE ? e : 0] : buf_ld<double>(ures, vline * 8u, (uint32_t)e * rstride * 8u);
   };
+  uint32_t mw = 0;  // lanes lb < SL: the mask word of row lo + lb
   if (active) {
 #pragma unroll
     for (int e = 0; e < SL; ++e)
-      dd[e] = *reinterpret_cast<const T*>(reinterpret_cast<const char*>(dbase) + boffs(e, sizeof(T)));
+      dd[e] = buf_ld<T>(dres, vlb, roff(e));
     // lane lb < SL fetches the mask word of row lo + lb (bits i0 .. i0+TL-1
     // of the row: within one word, nx and i0 being multiples of TL)
     static_assert(SL <= TL, "one mask word per lane");
@@ -714,18 +749,26 @@ void k_line_col(LineK<T> K) {
                                      : ((int64_t)(K.j0 + lo + lb) * K.nz + by) * K.nx;
       const int64_t bit = rb + i0;
       const uint32_t w = K.mask[bit >> 5] >> (uint32_t)(bit & 31);
-      mws[s * SL + lb] = (TL == 32) ? w : (w & ((1u << (TL & 31)) - 1u));
+      mw = (TL == 32) ? w : (w & ((1u << (TL & 31)) - 1u));
+      mws[s * SL + lb] = mw;
     }
+  }
+  {
+    // the OR of the interior rows' words over the segment's TL lanes (all
+    // lanes take part; inactive ones hold 0) and the separator row's word
+    uint32_t wi = (lb < m) ? mw : 0u;
+#pragma unroll
+    for (int o = 1; o < TL; o <<= 1) wi |= (uint32_t)__shfl_xor((int)wi, o, TL);
+    const uint32_t wl = (uint32_t)__shfl((int)mw, m, TL);
+    rare = (wi >> lb) & 1u;
+    last_forced = (wl >> lb) & 1u;
   }
   __syncthreads();  // tables and mask words
   if (active) {
-#pragma unroll
-    for (int e = 0; e < SL; ++e) mbits |= ((mws[s * SL + e] >> lb) & 1u) << e;
-#pragma unroll
-    for (int e = 0; e < SL; ++e)
-      if ((mbits >> e) & 1u) dd[e] = T(0);
-    dz = dd[m];
-    if ((mbits & ((1u << m) - 1u)) == 0u) {
+    // a forcing row's value is 0 (its update is zero); the interior rows of a
+    // segment that holds one take the rare path below, which applies it
+    dz = last_forced ? T(0) : dd[m];
+    if (!rare) {
       T dt = 0;
 #pragma unroll
       for (int e = 0; e < m; ++e) {
@@ -741,16 +784,24 @@ void k_line_col(LineK<T> K) {
       }
       a0 = CTAB(2, 0);
       c0 = CTAB(3, 0);
+      d0 = dd[0];
       ahl = CTAB(2, m - 1);
       chl = CTAB(3, m - 1);
-    } else {
-      // identity rows inside the segment: coefficients through the scratch
+    } else if constexpr (!LEAN) {
+      // identity rows inside the segment (rare), register form: the rows
+      // stay in dd, their coefficients go through the scratch
       T at = 0, ct = 0, dt = 0;
       for (int e = 0; e < m; ++e) {
-        const int64_t o = boff + lb + (lo + e) * es;
         T a, b, c;
-        col_coef<MODE>(K, lo + e, a, b, c);
-        if ((mbits >> e) & 1u) {
+        if (MODE == 2) {
+          a = cf[lo + e];
+          b = cf[P * SL + lo + e];
+          c = cf[2 * P * SL + lo + e];
+        } else {
+          col_coef<MODE>(K, lo + e, a, b, c);
+        }
+        const bool msk = (mws[s * SL + e] >> lb) & 1u;
+        if (msk) {
           a = 0;
           b = 1;
           c = 0;
@@ -758,15 +809,14 @@ void k_line_col(LineK<T> K) {
         const T inv = T(1) / (b - a * ct);
         at = (e == 0) ? a * inv : -a * at * inv;
         ct = c * inv;
-        dt = (dd[e] - a * dt) * inv;
+        dt = ((msk ? T(0) : dd[e]) - a * dt) * inv;
         dd[e] = dt;
-        K.sa[o] = at;
-        K.sc[o] = ct;
+        buf_st(at, sares, vlb, roff(e));
+        buf_st(ct, scres, vlb, roff(e));
       }
       T ah = 0, ch = 0, dh = 0;
       for (int e = m - 1; e >= 0; --e) {
-        const int64_t o = boff + lb + (lo + e) * es;
-        const T at_e = K.sa[o], ct_e = K.sc[o];
+        const T at_e = buf_ld<T>(sares, vlb, roff(e)), ct_e = buf_ld<T>(scres, vlb, roff(e));
         if (e == m - 1) {
           ah = at_e;
           ch = ct_e;
@@ -780,21 +830,93 @@ void k_line_col(LineK<T> K) {
           ch = -ct_e * ch;
         }
         dd[e] = dh;
-        K.sa[o] = ah;
-        K.sc[o] = ch;
+        buf_st(ah, sares, vlb, roff(e));
+        buf_st(ch, scres, vlb, roff(e));
       }
       a0 = ah;
       c0 = ch;
+      d0 = dd[0];
+    } else {
+      // identity rows inside the segment (rare): the eliminated rows and
+      // their coefficients go through memory (the rows in place in d, the
+      // coefficients in the scratch).  This path defines no row value in
+      // registers: a divergent branch runs both sides, so values of its own
+      // would need registers beside the common path's rows (twice the
+      // registers, half the occupancy).  It reads the loaded rows in dd, and
+      // fetches its operands RC rows at a time, so that it waits on memory
+      // once per RC rows with few registers in flight.
+      T at = 0, ct = 0, dt = 0;
+#pragma unroll
+      for (int e = 0; e < m; ++e) {
+        if (e > 0 && e % RC == 0) __builtin_amdgcn_sched_barrier(0);
+        T a, b, c;
+        if (MODE == 2) {
+          a = cf[lo + e];
+          b = cf[P * SL + lo + e];
+          c = cf[2 * P * SL + lo + e];
+        } else {
+          col_coef<MODE>(K, lo + e, a, b, c);
+        }
+        const bool msk = (mws[s * SL + e] >> lb) & 1u;
+        if (msk) {
+          a = 0;
+          b = 1;
+          c = 0;
+        }
+        const T inv = T(1) / (b - a * ct);
+        at = (e == 0) ? a * inv : -a * at * inv;
+        ct = c * inv;
+        dt = ((msk ? T(0) : dd[e]) - a * dt) * inv;
+        if (e < m - 1) {
+          buf_st(dt, dres, vlb, roff(e));
+          buf_st(at, sares, vlb, roff(e));
+          buf_st(ct, scres, vlb, roff(e));
+        }
+      }
+      // back substitution from row m - 1 (its values still in registers)
+      T ah = at, ch = ct, dh = dt;
+      ahl = ah;
+      chl = ch;
+      dhl = dh;
+      buf_st(dh, dres, vlb, roff(m - 1));
+      buf_st(ah, sares, vlb, roff(m - 1));
+      buf_st(ch, scres, vlb, roff(m - 1));
+#pragma unroll
+      for (int e1 = m - 2; e1 >= 0; e1 -= RC) {
+        __builtin_amdgcn_sched_barrier(0);
+        T ca[RC], cc[RC], cd[RC];
+#pragma unroll
+        for (int q = 0; q < RC; ++q)
+          if (e1 - q >= 0) {
+            ca[q] = buf_ld<T>(sares, vlb, roff(e1 - q));
+            cc[q] = buf_ld<T>(scres, vlb, roff(e1 - q));
+            cd[q] = buf_ld<T>(dres, vlb, roff(e1 - q));
+          }
+#pragma unroll
+        for (int q = 0; q < RC; ++q)
+          if (e1 - q >= 0) {
+            dh = cd[q] - cc[q] * dh;
+            ah = ca[q] - cc[q] * ah;
+            ch = -cc[q] * ch;
+            buf_st(dh, dres, vlb, roff(e1 - q));
+            buf_st(ah, sares, vlb, roff(e1 - q));
+            buf_st(ch, scres, vlb, roff(e1 - q));
+          }
+      }
+      __builtin_amdgcn_sched_barrier(0);
+      a0 = ah;
+      c0 = ch;
+      d0 = dh;  // dd[] stays as loaded (unused on this path)
     }
     col_coef<MODE>(K, lo + m, az, bz, cz);
-    if ((mbits >> m) & 1u) {
+    if (last_forced) {
       az = 0;
       bz = 1;
       cz = 0;
     }
     Y[(0 * PP + s) * SP + lb] = a0;
     Y[(1 * PP + s) * SP + lb] = c0;
-    Y[(2 * PP + s) * SP + lb] = dd[0];
+    Y[(2 * PP + s) * SP + lb] = d0;
   }
   __syncthreads();  // a0, c0, d0 of every segment
   if (active) {
@@ -857,36 +979,58 @@ void k_line_col(LineK<T> K) {
     }
     if (lt < TL && st < P) Y[st * SP + lt] = K.cyc ? rd / (ra + rb + rg) : rd / rb;
   }
-  if (MODE == 2 && active) {
+  if (UPRE && active) {
     // the velocity the solution is added to: loaded here, where the
     // registers of the separator solve are free, in flight over the barrier
 #pragma unroll
-    for (int e = 0; e < SL; ++e)
-      uu[e] = *reinterpret_cast<const double*>(reinterpret_cast<const char*>(ubase) + boffs(e, 8));
+    for (int e = 0; e < SL; ++e) uu[e] = buf_ld<double>(ures, vline * 8u, (uint32_t)e * rstride * 8u);
   }
   __syncthreads();  // separator values
   if (active) {
     const T zr = Y[s * SP + lb];
     const T zl = (s > 0) ? Y[(s - 1) * SP + lb] : (K.cyc ? Y[(P - 1) * SP + lb] : T(0));
-    if ((mbits & ((1u << m) - 1u)) == 0u) {
+    if (!rare || !LEAN) {
+      if (!rare) {
 #pragma unroll
-      for (int e = 0; e < m; ++e) dd[e] = dd[e] - CTAB(2, e) * zl - CTAB(3, e) * zr;
-    } else {
-#pragma unroll
-      for (int e = 0; e < m; ++e) {
-        const int64_t o = boff + lb + (lo + e) * es;
-        dd[e] = dd[e] - K.sa[o] * zl - K.sc[o] * zr;
+        for (int e = 0; e < m; ++e) dd[e] = dd[e] - CTAB(2, e) * zl - CTAB(3, e) * zr;
+      } else {
+        for (int e = 0; e < m; ++e)
+          dd[e] = dd[e] - buf_ld<T>(sares, vlb, roff(e)) * zl - buf_ld<T>(scres, vlb, roff(e)) * zr;
       }
-    }
-    dd[m] = zr;
+      dd[m] = zr;
 #pragma unroll
-    for (int e = 0; e < SL; ++e) {
-      if (MODE == 2)
-        *reinterpret_cast<double*>(reinterpret_cast<char*>(const_cast<double*>(ubase)) + boffs(e, 8)) =
-            uu[MODE == 2 ? e : 0] + (double)dd[e];
-      else
-        *reinterpret_cast<T*>(reinterpret_cast<char*>(const_cast<T*>(dbase)) + boffs(e, sizeof(T))) =
-            dd[e];
+      for (int e = 0; e < SL; ++e) {
+        if (MODE == 2)
+          buf_st(u_at(e) + (double)dd[e], ures, vline * 8u, (uint32_t)e * rstride * 8u);
+        else
+          buf_st(dd[e], dres, vlb, roff(e));
+      }
+    } else {
+      // the rare path again: rows and coefficients from memory, RC at a time
+#pragma unroll
+      for (int e0 = 0; e0 < SL; e0 += RC) {
+        __builtin_amdgcn_sched_barrier(0);
+        T ca[RC], cc[RC], cd[RC];
+#pragma unroll
+        for (int q = 0; q < RC; ++q)
+          if (e0 + q < m) {
+            ca[q] = buf_ld<T>(sares, vlb, roff(e0 + q));
+            cc[q] = buf_ld<T>(scres, vlb, roff(e0 + q));
+            cd[q] = buf_ld<T>(dres, vlb, roff(e0 + q));
+          }
+#pragma unroll
+        for (int q = 0; q < RC; ++q) {
+          const int e = e0 + q;
+          if (e < SL) {
+            const T x = (e < m) ? cd[q] - ca[q] * zl - cc[q] * zr : zr;
+            if (MODE == 2)
+              buf_st(u_at(e) + (double)x, ures, vline * 8u, (uint32_t)e * rstride * 8u);
+            else
+              buf_st(x, dres, vlb, roff(e));
+          }
+        }
+      }
+      __builtin_amdgcn_sched_barrier(0);
     }
 #undef CTAB
   }
@@ -956,7 +1100,8 @@ static void launch_line(Prof* pf, hipStream_t s, LineK<T> K, const char* name) {
              (K.mode == 1 ? (int64_t)K.nx : K.plane) * 64 * 8 < ((int64_t)1 << 31)) {
     // column sweep: 16 lines per block (32 in FP32 where the block stays
     // within 1024 threads, and with the long segments of the large planes),
-    // the separators solved per wavefront
+    // the separators solved per wavefront; a wavefront's rows (at most 64)
+    // span less than 2 GiB of any array, the range of its buffer descriptors
     int pp = 1;
     while (pp < K.P) pp <<= 1;
     K.PP = pp;
@@ -965,7 +1110,8 @@ static void launch_line(Prof* pf, hipStream_t s, LineK<T> K, const char* name) {
     const int ct = tl * pp;
     const size_t cshm = sizeof(T) * (LINE_NTAB * (size_t)(K.tab1 ? 1 : K.P) * K.L +
                                      7 * (size_t)pp * (tl + 1)) +
-                        sizeof(uint32_t) * (size_t)K.P * K.L;
+                        sizeof(uint32_t) * (size_t)K.P * K.L +
+                        (K.mode == 2 ? sizeof(T) * 3 * (size_t)K.P * K.L : 0);
     const dim3 cgrid = (K.mode == 1) ? dim3(K.nx / tl, K.nj) : dim3(K.nz, K.nx / tl);
 #define IBM_COL(M, SL_)                                                                        \
   do {                                                                                        \

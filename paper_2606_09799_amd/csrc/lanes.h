@@ -70,4 +70,80 @@ __device__ __forceinline__ void wave_sync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
+// Grouped launches (the batched form): one launch runs the blocks of several
+// simulations' launches of one kernel.  The grouped instantiation of a
+// kernel takes a GrpTab instead of its argument record: the records (ksize
+// bytes each), the block offsets of the members (n + 1 prefix sums) and each
+// member's grid; a block finds its member by binary search and runs as that
+// member's block.  grp_enter gives the argument record and the block's
+// position and grid, in both instantiations.
+struct GrpTab {
+  const unsigned char* k;
+  const uint32_t* boff;
+  const uint32_t* gdim;  // 3 per member
+  int n;
+  int ksize;
+};
+template <typename KT, bool G>
+struct GArgT {
+  using type = KT;
+};
+template <typename KT>
+struct GArgT<KT, true> {
+  using type = GrpTab;
+};
+template <typename KT, bool G>
+using GArg = typename GArgT<KT, G>::type;
+
+template <typename KT, bool G>
+__device__ __forceinline__ const KT& grp_enter(const GArg<KT, G>& A, uint3& bid, uint3& gdim) {
+  if constexpr (!G) {
+    bid = make_uint3(blockIdx.x, blockIdx.y, blockIdx.z);
+    gdim = make_uint3(gridDim.x, gridDim.y, gridDim.z);
+    return A;
+  } else {
+    const uint32_t b = blockIdx.x;
+    int lo = 0, hi = A.n;  // A.boff[lo] <= b < A.boff[hi]
+    while (hi - lo > 1) {
+      const int mid = (lo + hi) >> 1;
+      if (A.boff[mid] <= b) lo = mid; else hi = mid;
+    }
+    const uint32_t l = b - A.boff[lo];
+    const uint32_t gx = A.gdim[3 * lo], gy = A.gdim[3 * lo + 1], gz = A.gdim[3 * lo + 2];
+    gdim = make_uint3(gx, gy, gz);
+    bid = make_uint3(l % gx, (l / gx) % gy, l / (gx * gy));
+    return *reinterpret_cast<const KT*>(A.k + (size_t)lo * (size_t)A.ksize);
+  }
+}
+
+// Raw buffer access (gfx9 buffer descriptor, no stride, `bytes` records):
+// a uniform base in the descriptor, a per-lane byte offset in a vector
+// register and a uniform byte offset in a scalar register, so a loop over
+// rows at a uniform stride holds one vector offset for all rows.  Offsets at
+// or past `bytes` read 0 and drop stores.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buf_rsrc(const void* base, uint32_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes,
+                                           0x00020000);
+}
+template <typename T>
+__device__ __forceinline__ T buf_ld(__amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so);
+template <>
+__device__ __forceinline__ float buf_ld<float>(__amdgpu_buffer_rsrc_t r, uint32_t vo, uint32_t so) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)vo, (int)so, 0));
+}
+template <>
+__device__ __forceinline__ double buf_ld<double>(__amdgpu_buffer_rsrc_t r, uint32_t vo,
+                                                 uint32_t so) {
+  return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(r, (int)vo, (int)so, 0));
+}
+__device__ __forceinline__ void buf_st(float v, __amdgpu_buffer_rsrc_t r, uint32_t vo,
+                                       uint32_t so) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(int, v), r, (int)vo, (int)so, 0);
+}
+__device__ __forceinline__ void buf_st(double v, __amdgpu_buffer_rsrc_t r, uint32_t vo,
+                                       uint32_t so) {
+  typedef int i2 __attribute__((ext_vector_type(2)));
+  __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(i2, v), r, (int)vo, (int)so, 0);
+}
+
 }  // namespace ibm

@@ -376,19 +376,19 @@ def test_step_parity(name, steps):
     assert rel(centred(got), centred(p)) < 1e-10
 
 
-@pytest.mark.parametrize("nx", [512, 1024])
-def test_step_parity_long_x(nx):
+@pytest.mark.parametrize("nx,use_q", [(512, True), (1024, True), (1024, False)])
+def test_step_parity_long_x(nx, use_q):
     """Whole steps on x lines of 512 and 1024 cells (the x sweep on 32 and 64
     segments per line, the generic x transforms with the velocity source
-    formed branch-free), a sphere in the channel: velocity within 1e-10 of
-    the oracle after two steps."""
+    formed branch-free, with and without the C_B mask), a sphere in the
+    channel: velocity within 1e-10 of the oracle after two steps."""
     import workloads
     d = 2.0 / 24
     wl = workloads.Workload("long_x", nx, 24, 16, nx * d, 16 * d, workloads.uniform_faces(24),
                             100.0, 1e-3, 2, 1.0, 0.01, 13, -0.02,
                             [workloads._sphere_body(2, 0.3, (nx * d / 2, 0.0, 8 * d),
                                                     (0.2, 0.05, -0.1))])
-    case, g, d, pd, f, p, tags = _run_both(wl, 2)
+    case, g, d, pd, f, p, tags = _run_both(wl, 2, use_q=use_q)
     _tags_equal(case, tags)
     for c in range(3):
         assert rel(n(d[c], f[c].shape), f[c]) < 1e-10, c
