@@ -403,6 +403,8 @@ typedef struct ibm_batch ibm_batch;
 #define IBM_BATCH_STREAMS 1 /* concurrent streams, launched every step */
 #define IBM_BATCH_GRAPH 2   /* one captured HIP graph replayed every step */
 #define IBM_BATCH_PLAN 3    /* the mode of the batch's current plan */
+#define IBM_BATCH_GROUPED 4 /* each kernel of the step launched once for all
+                               simulations, captured into one graph */
 
 /* One simulation of a batch.  state: dev arrays as for ibm_step (the
  * batch keeps the pointers); ref: dev f64[nv*3] reference vertices (rigid)
@@ -421,7 +423,8 @@ typedef struct {
 
 /* grids, opts, sims: host arrays of nsim entries (copied).  stream: the
  * batch's hipStream_t (NULL = default).  Creates nsim contexts; all device
- * workspace is allocated here. */
+ * workspace is allocated here, including the launch tables of the grouped
+ * form (sized by recording every simulation's step once; synchronises). */
 int ibm_batch_create(const ibm_grid* grids, const ibm_opts* opts, const ibm_sim* sims,
                      int32_t nsim, void* stream, ibm_batch** out);
 void ibm_batch_destroy(ibm_batch* b);
@@ -431,9 +434,17 @@ ibm_ctx* ibm_batch_context(ibm_batch* b, int32_t sim);
  * coef (host f64[nsim*IBM_COEF_STRIDE]; simulation s at s*IBM_COEF_STRIDE,
  * rigid: the 18 values of ibm_body_rigid, deform: the first 6 values of
  * ibm_body_deform), then ibm_step.  mode: IBM_BATCH_SERIAL, _STREAMS,
- * _GRAPH or _PLAN (the current plan's mode; streams and graph modes use the
- * plan's stream groups and tile choice); the first graph call for a dt
- * captures the graph (a change of dt or of plan drops it).  Results are identical in every mode and to ibm_step run on
+ * _GRAPH, _GROUPED or _PLAN (the current plan's mode; streams and graph
+ * modes use the plan's stream groups and tile choice); the first graph call
+ * for a dt captures the graph (a change of dt or of plan drops it).
+ * _GROUPED: every simulation's step is recorded (no launch) and the k-th
+ * launch of all simulations becomes one launch per kernel variant and block
+ * size, whose blocks each run as one simulation's block with that
+ * simulation's argument record; the sequence is captured into one graph (a
+ * few hundred launches per batched step instead of a few dozen per
+ * simulation).  IBM_EINVAL if a simulation's step uses a kernel without a
+ * grouped form (the energy-conserving q_F, the refined Poisson solve, volume
+ * forces).  Results are identical in every mode and to ibm_step run on
  * each simulation alone.  The first call for a dt synchronises once (line
  * tables, waiting for any earlier step before a captured graph is dropped);
  * later calls only enqueue, except that the host waits when the coefficient
@@ -444,7 +455,7 @@ int ibm_batch_check(ibm_batch* b, uint32_t* flags);
 
 /* Execution plan of a batch (an arrangement of the same arithmetic: every
  * plan gives results identical to IBM_BATCH_SERIAL).
- *   mode:       IBM_BATCH_STREAMS or IBM_BATCH_GRAPH, used by IBM_BATCH_PLAN
+ *   mode:       IBM_BATCH_STREAMS, _GRAPH or _GROUPED, used by IBM_BATCH_PLAN
  *   streams:    stream groups, 1..nsim: the simulations, largest first, are
  *               dealt round-robin to the groups; a group runs its
  *               simulations one after the other, groups run concurrently
@@ -465,7 +476,8 @@ int ibm_batch_set_plan(ibm_batch* b, const ibm_batch_plan* plan);
 int ibm_batch_get_plan(ibm_batch* b, ibm_batch_plan* plan);
 /* Autotuner: times candidate plans on this batch's own simulations (a
  * coordinate search over streams in {1, 2, 4, ..., nsim}, then rhs_planes in
- * {16, 48, 8, 4}, then graph vs eager streams), `steps` timed steps each after
+ * {16, 48, 8, 4}, then graph vs eager streams; the grouped form is not among
+ * its candidates), `steps` timed steps each after
  * one untimed step, all with the body coefficients `coef` and step dt.  The
  * simulations' states (u, v, w, p and, for AB2, h) are saved first into
  * `scratch` (dev, 256-byte aligned, at least ibm_batch_tune_scratch_bytes

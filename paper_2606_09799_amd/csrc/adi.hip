@@ -99,8 +99,12 @@ __device__ void reduced_solve_cyclic(Acc A, int P) {
 // MODE: 0 x rows, 1 z lines, 2 y lines (compile time, so each instance
 // carries only its own addressing).  FIXED: every segment holds exactly LMAX
 // rows (n = P * LMAX), so the segment loops have no runtime bounds.
-template <typename T, int MODE, bool FIXED>
-__global__ __launch_bounds__(MODE == 0 ? 256 : 1024) void k_line(LineK<T> K) {
+template <typename T, int MODE, bool FIXED, bool G = false>
+__global__ __launch_bounds__(MODE == 0 ? 256 : 1024) void k_line(GArg<LineK<T>, G> grp_arg_) {
+  uint3 bid, gdim;
+  const LineK<T>& K = grp_enter<LineK<T>, G>(grp_arg_, bid, gdim);
+  (void)bid;
+  (void)gdim;
   extern __shared__ __align__(16) unsigned char ldsraw[];
   T* lds = reinterpret_cast<T*>(ldsraw);
   const int tid = threadIdx.x;
@@ -134,19 +138,19 @@ __global__ __launch_bounds__(MODE == 0 ? 256 : 1024) void k_line(LineK<T> K) {
   int64_t base = 0, es = 1;
   bool valid = active;
   if (MODE == 0) {
-    const int64_t line = (int64_t)blockIdx.x * K.tl + lb;
+    const int64_t line = (int64_t)bid.x * K.tl + lb;
     valid = valid && line < (int64_t)K.nj * K.nz;
     const int j = K.j0 + (int)(line / K.nz), k = (int)(line % K.nz);
     base = ((int64_t)j * K.nz + k) * K.nx;
     es = 1;
   } else {
-    const int i = blockIdx.x * K.tl + lb;
+    const int i = bid.x * K.tl + lb;
     valid = valid && i < K.nx;
     if (MODE == 1) {
-      base = (int64_t)(K.j0 + blockIdx.y) * K.plane + i;
+      base = (int64_t)(K.j0 + bid.y) * K.plane + i;
       es = K.nx;
     } else {
-      base = (int64_t)K.j0 * K.plane + (int64_t)blockIdx.y * K.nx + i;
+      base = (int64_t)K.j0 * K.plane + (int64_t)bid.y * K.nx + i;
       es = K.plane;
     }
   }
@@ -157,7 +161,7 @@ __global__ __launch_bounds__(MODE == 0 ? 256 : 1024) void k_line(LineK<T> K) {
   int xrows = 0;
   const T* xsrc = nullptr;
   if (MODE == 0) {
-    const int64_t l0 = (int64_t)blockIdx.x * K.tl;
+    const int64_t l0 = (int64_t)bid.x * K.tl;
     const int64_t nl = (int64_t)K.nj * K.nz;
     xrows = (int)((l0 + K.tl <= nl) ? K.tl : nl - l0);
     xsrc = K.d + ((int64_t)K.j0 * K.nz + l0) * K.n;
@@ -445,9 +449,13 @@ __device__ __forceinline__ void xw_fetch(const LineK<T>& K, typename Vec16<T>::t
 // and mask words into registers before it solves the current one, so that
 // the chip's loads stay in flight through the elimination and the stores
 // instead of arriving in one wave of requests per round of blocks.
-template <typename T>
+template <typename T, bool G = false>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3)))
-void k_line_xw(LineK<T> K) {
+void k_line_xw(GArg<LineK<T>, G> grp_arg_) {
+  uint3 bid, gdim;
+  const LineK<T>& K = grp_enter<LineK<T>, G>(grp_arg_, bid, gdim);
+  (void)bid;
+  (void)gdim;
   using V = typename Vec16<T>::type;
   constexpr int VN = 16 / sizeof(T);  // values per 16 bytes
   constexpr int SEGS = LMAX + VN;     // padded segment
@@ -466,8 +474,8 @@ void k_line_xw(LineK<T> K) {
   __syncthreads();
   const int64_t nl = (int64_t)K.nj * K.nz;  // rows of the sweep
   const int64_t ng = (nl + RW - 1) / RW;    // groups
-  const int64_t gstep = (int64_t)gridDim.x * (blockDim.x >> 6);
-  int64_t g = (int64_t)blockIdx.x * (blockDim.x >> 6) + wv;
+  const int64_t gstep = (int64_t)gdim.x * (blockDim.x >> 6);
+  int64_t g = (int64_t)bid.x * (blockDim.x >> 6) + wv;
   if (g >= ng) return;  // the whole wavefront is past the end
   const int lgn = 31 - __clz(n);  // n = P LMAX is a power of two
   const int rr = lane / P, s = lane % P;
@@ -652,9 +660,269 @@ __device__ __forceinline__ void col_coef(const LineK<T>& K, int i, T& a, T& b, T
   }
 }
 
-template <typename T, int MODE, int SL, int TL>
+// Register form of the column sweep for the wall-normal lines of 12- and
+// 16-row segments: every row of a segment is addressed and held in
+// registers through the whole launch, the rare segments with identity rows
+// included (their coefficients through the scratch).  Where lines cross a
+// body often (a plate spanning the wall-normal lines) it is faster than the
+// form below, whose rare path goes through memory.
+template <typename T, int MODE, int SL, int TL, bool G = false>
+__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(SL == 12 ? 5 : 1)))
+void k_line_col_reg(GArg<LineK<T>, G> grp_arg_) {
+  uint3 bid, gdim;
+  const LineK<T>& K = grp_enter<LineK<T>, G>(grp_arg_, bid, gdim);
+  (void)bid;
+  (void)gdim;
+  // TL lines per block: 16, or 32 in FP32 (a wavefront's loads then cover
+  // 128-byte row pieces in both), and 32 with the long segments (24 or 32
+  // rows) of the large planes
+  constexpr int SP = TL + 1;   // padded stride of the separator arrays
+  extern __shared__ __align__(16) unsigned char ldsraw[];
+  T* lds = reinterpret_cast<T*>(ldsraw);
+  const int tid = threadIdx.x;
+  const int P = K.P, PP = K.PP;
+  const int tP = K.tab1 ? 1 : P;
+  T* tabs = lds;                             // [LINE_NTAB][SL][tP]
+  T* Y = tabs + LINE_NTAB * SL * tP;         // a0, c0, d0 of each segment; then z
+  T* X = Y + 3 * PP * SP;                    // separator rows ra, rb, rg, rd
+  uint32_t* mws = reinterpret_cast<uint32_t*>(X + 4 * PP * SP);  // [P][SL] mask words
+  for (int q = tid; q < LINE_NTAB * tP * SL; q += blockDim.x) {
+    const int qe = q / tP, ss = q % tP, qq = qe / SL, ee = qe % SL;
+    tabs[q] = K.tab[((size_t)qq * P + ss) * LINE_TLD + ee];  // global: LINE_TLD per segment
+  }
+  const int lb = tid % TL, s = tid / TL;
+  const bool active = s < P;
+  // y sweep: blocks in z-major order (consecutive blocks on different z
+  // rows, hence different memory channels); z sweep: x-tile fastest
+  const int bx = (MODE == 2) ? (int)bid.y : (int)bid.x;
+  const int by = (MODE == 2) ? (int)bid.x : (int)bid.y;
+  const int i0 = bx * TL;
+  const int ts = K.tab1 ? 0 : s;
+#define CTAB(q, e) tabs[((q) * SL + (e)) * tP + ts]
+  // element (row r of line lb): blk[lb + r * es]
+  const int64_t es = (MODE == 1) ? K.nx : K.plane;
+  const int64_t boff = (MODE == 1) ? (int64_t)(K.j0 + by) * K.plane + i0
+                                   : (int64_t)K.j0 * K.plane + (int64_t)by * K.nx + i0;
+  const int lo = s * SL;
+  constexpr int m = SL - 1;
+  T dd[SL];
+  double uu[MODE == 2 ? SL : 1];
+  T dz = 0, az = 0, bz = 1, cz = 0;
+  T a0 = 0, c0 = 0, ahl = 0, chl = 0, dhl = 0;
+  uint32_t mbits = 0;
+  // rows are addressed from the wavefront's first row (a uniform base) plus
+  // a 32-bit byte offset, one register per row instead of a 64-bit address
+  const int wv = __builtin_amdgcn_readfirstlane(tid >> 6);
+  const int64_t wrow = (int64_t)wv * (64 / TL) * SL;  // first row of the wavefront
+  const T* dbase = K.d + boff + wrow * es;
+  const double* ubase = (MODE == 2) ? K.u + boff + wrow * es : nullptr;
+  const uint32_t lrow = (uint32_t)(lo - wrow);           // this segment's first row, from wrow
+  auto boffs = [&](int e, uint32_t sz) -> uint32_t {
+    return ((uint32_t)lb + (lrow + (uint32_t)e) * (uint32_t)es) * sz;
+  };
+  if (active) {
+#pragma unroll
+    for (int e = 0; e < SL; ++e)
+      dd[e] = *reinterpret_cast<const T*>(reinterpret_cast<const char*>(dbase) + boffs(e, sizeof(T)));
+    // lane lb < SL fetches the mask word of row lo + lb (bits i0 .. i0+TL-1
+    // of the row: within one word, nx and i0 being multiples of TL)
+    static_assert(SL <= TL, "one mask word per lane");
+    if (lb < SL) {
+      const int64_t rb = (MODE == 1) ? ((int64_t)(K.j0 + by) * K.nz + lo + lb) * K.nx
+                                     : ((int64_t)(K.j0 + lo + lb) * K.nz + by) * K.nx;
+      const int64_t bit = rb + i0;
+      const uint32_t w = K.mask[bit >> 5] >> (uint32_t)(bit & 31);
+      mws[s * SL + lb] = (TL == 32) ? w : (w & ((1u << (TL & 31)) - 1u));
+    }
+  }
+  __syncthreads();  // tables and mask words
+  if (active) {
+#pragma unroll
+    for (int e = 0; e < SL; ++e) mbits |= ((mws[s * SL + e] >> lb) & 1u) << e;
+#pragma unroll
+    for (int e = 0; e < SL; ++e)
+      if ((mbits >> e) & 1u) dd[e] = T(0);
+    dz = dd[m];
+    if ((mbits & ((1u << m) - 1u)) == 0u) {
+      T dt = 0;
+#pragma unroll
+      for (int e = 0; e < m; ++e) {
+        dt = (dd[e] - CTAB(4, e) * dt) * CTAB(0, e);
+        dd[e] = dt;
+      }
+      T dh = dd[m - 1];
+      dhl = dh;
+#pragma unroll
+      for (int e = m - 2; e >= 0; --e) {
+        dh = dd[e] - CTAB(1, e) * dh;
+        dd[e] = dh;
+      }
+      a0 = CTAB(2, 0);
+      c0 = CTAB(3, 0);
+      ahl = CTAB(2, m - 1);
+      chl = CTAB(3, m - 1);
+    } else {
+      // identity rows inside the segment: coefficients through the scratch
+      T at = 0, ct = 0, dt = 0;
+      for (int e = 0; e < m; ++e) {
+        const int64_t o = boff + lb + (lo + e) * es;
+        T a, b, c;
+        col_coef<MODE>(K, lo + e, a, b, c);
+        if ((mbits >> e) & 1u) {
+          a = 0;
+          b = 1;
+          c = 0;
+        }
+        const T inv = T(1) / (b - a * ct);
+        at = (e == 0) ? a * inv : -a * at * inv;
+        ct = c * inv;
+        dt = (dd[e] - a * dt) * inv;
+        dd[e] = dt;
+        K.sa[o] = at;
+        K.sc[o] = ct;
+      }
+      T ah = 0, ch = 0, dh = 0;
+      for (int e = m - 1; e >= 0; --e) {
+        const int64_t o = boff + lb + (lo + e) * es;
+        const T at_e = K.sa[o], ct_e = K.sc[o];
+        if (e == m - 1) {
+          ah = at_e;
+          ch = ct_e;
+          dh = dd[e];
+          ahl = ah;
+          chl = ch;
+          dhl = dh;
+        } else {
+          dh = dd[e] - ct_e * dh;
+          ah = at_e - ct_e * ah;
+          ch = -ct_e * ch;
+        }
+        dd[e] = dh;
+        K.sa[o] = ah;
+        K.sc[o] = ch;
+      }
+      a0 = ah;
+      c0 = ch;
+    }
+    col_coef<MODE>(K, lo + m, az, bz, cz);
+    if ((mbits >> m) & 1u) {
+      az = 0;
+      bz = 1;
+      cz = 0;
+    }
+    Y[(0 * PP + s) * SP + lb] = a0;
+    Y[(1 * PP + s) * SP + lb] = c0;
+    Y[(2 * PP + s) * SP + lb] = dd[0];
+  }
+  __syncthreads();  // a0, c0, d0 of every segment
+  if (active) {
+    int sn = s + 1;
+    T czz = cz;
+    if (sn == P) {
+      sn = 0;
+      if (!K.cyc) czz = 0;
+    }
+    X[(0 * PP + s) * SP + lb] = -az * ahl;
+    X[(1 * PP + s) * SP + lb] = bz - az * chl - czz * Y[(0 * PP + sn) * SP + lb];
+    X[(2 * PP + s) * SP + lb] = -czz * Y[(1 * PP + sn) * SP + lb];
+    X[(3 * PP + s) * SP + lb] = dz - az * dhl - czz * Y[(2 * PP + sn) * SP + lb];
+  }
+  __syncthreads();  // separator rows
+  // transposed: thread (line lt, separator st) in PP consecutive lanes
+  {
+    const int lt = tid / PP, st = tid % PP;
+    const int lane = tid & 63, grp = lane - st;
+    T ra = 0, rb = 1, rg = 0, rd = 0;
+    if (lt < TL && st < P) {
+      ra = X[(0 * PP + st) * SP + lt];
+      rb = X[(1 * PP + st) * SP + lt];
+      rg = X[(2 * PP + st) * SP + lt];
+      rd = X[(3 * PP + st) * SP + lt];
+    }
+    for (int step = 1; step < PP; step <<= 1) {
+      int im = st - step, ip = st + step;
+      bool hm = true, hp = true;
+      if (K.cyc) {
+        im &= PP - 1;
+        ip &= PP - 1;
+      } else {
+        hm = im >= 0;
+        hp = ip < PP;
+      }
+      const int sm_ = grp + (hm ? im : st), sp_ = grp + (hp ? ip : st);
+      T am = lane_read(ra, sm_), bm = lane_read(rb, sm_), gm = lane_read(rg, sm_),
+        dm = lane_read(rd, sm_);
+      T ap = lane_read(ra, sp_), bp = lane_read(rb, sp_), gp = lane_read(rg, sp_),
+        dp = lane_read(rd, sp_);
+      if (!hm) {
+        am = 0;
+        bm = 1;
+        gm = 0;
+        dm = 0;
+      }
+      if (!hp) {
+        ap = 0;
+        bp = 1;
+        gp = 0;
+        dp = 0;
+      }
+      const T k1 = ra / bm, k2 = rg / bp;
+      const T na = -am * k1, ng = -gp * k2;
+      rb = rb - gm * k1 - ap * k2;
+      rd = rd - dm * k1 - dp * k2;
+      ra = na;
+      rg = ng;
+    }
+    if (lt < TL && st < P) Y[st * SP + lt] = K.cyc ? rd / (ra + rb + rg) : rd / rb;
+  }
+  if (MODE == 2 && active) {
+    // the velocity the solution is added to: loaded here, where the
+    // registers of the separator solve are free, in flight over the barrier
+#pragma unroll
+    for (int e = 0; e < SL; ++e)
+      uu[e] = *reinterpret_cast<const double*>(reinterpret_cast<const char*>(ubase) + boffs(e, 8));
+  }
+  __syncthreads();  // separator values
+  if (active) {
+    const T zr = Y[s * SP + lb];
+    const T zl = (s > 0) ? Y[(s - 1) * SP + lb] : (K.cyc ? Y[(P - 1) * SP + lb] : T(0));
+    if ((mbits & ((1u << m) - 1u)) == 0u) {
+#pragma unroll
+      for (int e = 0; e < m; ++e) dd[e] = dd[e] - CTAB(2, e) * zl - CTAB(3, e) * zr;
+    } else {
+#pragma unroll
+      for (int e = 0; e < m; ++e) {
+        const int64_t o = boff + lb + (lo + e) * es;
+        dd[e] = dd[e] - K.sa[o] * zl - K.sc[o] * zr;
+      }
+    }
+    dd[m] = zr;
+#pragma unroll
+    for (int e = 0; e < SL; ++e) {
+      if (MODE == 2)
+        *reinterpret_cast<double*>(reinterpret_cast<char*>(const_cast<double*>(ubase)) + boffs(e, 8)) =
+            uu[MODE == 2 ? e : 0] + (double)dd[e];
+      else
+        *reinterpret_cast<T*>(reinterpret_cast<char*>(const_cast<T*>(dbase)) + boffs(e, sizeof(T))) =
+            dd[e];
+    }
+#undef CTAB
+  }
+}
+
+
+// Lean form of the column sweep (z sweeps, whose lines seldom meet a body,
+// and the 24- and 32-row segments of the large planes): rows through buffer
+// descriptors, and segments with identity rows through memory, so that the
+// common path keeps few registers (two blocks of 1024 threads per CU for
+// the 32-row FP32 z sweep).
+template <typename T, int MODE, int SL, int TL, bool G = false>
 __global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(SL == 12 ? 5 : (SL == 32 ? 8 : 1))))
-void k_line_col(LineK<T> K) {
+void k_line_col(GArg<LineK<T>, G> grp_arg_) {
+  uint3 bid, gdim;
+  const LineK<T>& K = grp_enter<LineK<T>, G>(grp_arg_, bid, gdim);
+  (void)bid;
+  (void)gdim;
   // TL lines per block: 16, or 32 in FP32 (a wavefront's loads then cover
   // 128-byte row pieces in both), and 32 with the long segments (24 or 32
   // rows) of the large planes
@@ -684,8 +952,8 @@ void k_line_col(LineK<T> K) {
   const bool active = s < P;
   // y sweep: blocks in z-major order (consecutive blocks on different z
   // rows, hence different memory channels); z sweep: x-tile fastest
-  const int bx = (MODE == 2) ? (int)blockIdx.y : (int)blockIdx.x;
-  const int by = (MODE == 2) ? (int)blockIdx.x : (int)blockIdx.y;
+  const int bx = (MODE == 2) ? (int)bid.y : (int)bid.x;
+  const int by = (MODE == 2) ? (int)bid.x : (int)bid.y;
   const int i0 = bx * TL;
   const int ts = K.tab1 ? 0 : s;
 #define CTAB(q, e) tabs[((q) * SL + (e)) * tP + ts]
@@ -698,13 +966,7 @@ void k_line_col(LineK<T> K) {
   T dd[SL];
   // y sweep: the velocity is prefetched over the last barrier
   constexpr bool UPRE = MODE == 2;
-  // segments with identity rows (rare): in the lean form (z sweeps, whose
-  // lines seldom meet a body, and long segments) the rows go through memory
-  // and the common path keeps its occupancy; the register form keeps them
-  // in dd, faster where many lines cross a body (a plate spanning the
-  // wall-normal lines)
-  constexpr bool LEAN = MODE == 1 || SL >= 24;
-  constexpr int RC = 4;  // rows per memory round trip on the lean rare path
+  constexpr int RC = 4;  // rows per memory round trip on the rare path
   double uu[UPRE ? SL : 1];
   T dz = 0, az = 0, bz = 1, cz = 0;
   T a0 = 0, c0 = 0, d0 = 0, ahl = 0, chl = 0, dhl = 0;
@@ -787,55 +1049,6 @@ void k_line_col(LineK<T> K) {
       d0 = dd[0];
       ahl = CTAB(2, m - 1);
       chl = CTAB(3, m - 1);
-    } else if constexpr (!LEAN) {
-      // identity rows inside the segment (rare), register form: the rows
-      // stay in dd, their coefficients go through the scratch
-      T at = 0, ct = 0, dt = 0;
-      for (int e = 0; e < m; ++e) {
-        T a, b, c;
-        if (MODE == 2) {
-          a = cf[lo + e];
-          b = cf[P * SL + lo + e];
-          c = cf[2 * P * SL + lo + e];
-        } else {
-          col_coef<MODE>(K, lo + e, a, b, c);
-        }
-        const bool msk = (mws[s * SL + e] >> lb) & 1u;
-        if (msk) {
-          a = 0;
-          b = 1;
-          c = 0;
-        }
-        const T inv = T(1) / (b - a * ct);
-        at = (e == 0) ? a * inv : -a * at * inv;
-        ct = c * inv;
-        dt = ((msk ? T(0) : dd[e]) - a * dt) * inv;
-        dd[e] = dt;
-        buf_st(at, sares, vlb, roff(e));
-        buf_st(ct, scres, vlb, roff(e));
-      }
-      T ah = 0, ch = 0, dh = 0;
-      for (int e = m - 1; e >= 0; --e) {
-        const T at_e = buf_ld<T>(sares, vlb, roff(e)), ct_e = buf_ld<T>(scres, vlb, roff(e));
-        if (e == m - 1) {
-          ah = at_e;
-          ch = ct_e;
-          dh = dd[e];
-          ahl = ah;
-          chl = ch;
-          dhl = dh;
-        } else {
-          dh = dd[e] - ct_e * dh;
-          ah = at_e - ct_e * ah;
-          ch = -ct_e * ch;
-        }
-        dd[e] = dh;
-        buf_st(ah, sares, vlb, roff(e));
-        buf_st(ch, scres, vlb, roff(e));
-      }
-      a0 = ah;
-      c0 = ch;
-      d0 = dd[0];
     } else {
       // identity rows inside the segment (rare): the eliminated rows and
       // their coefficients go through memory (the rows in place in d, the
@@ -989,14 +1202,9 @@ void k_line_col(LineK<T> K) {
   if (active) {
     const T zr = Y[s * SP + lb];
     const T zl = (s > 0) ? Y[(s - 1) * SP + lb] : (K.cyc ? Y[(P - 1) * SP + lb] : T(0));
-    if (!rare || !LEAN) {
-      if (!rare) {
+    if (!rare) {
 #pragma unroll
-        for (int e = 0; e < m; ++e) dd[e] = dd[e] - CTAB(2, e) * zl - CTAB(3, e) * zr;
-      } else {
-        for (int e = 0; e < m; ++e)
-          dd[e] = dd[e] - buf_ld<T>(sares, vlb, roff(e)) * zl - buf_ld<T>(scres, vlb, roff(e)) * zr;
-      }
+      for (int e = 0; e < m; ++e) dd[e] = dd[e] - CTAB(2, e) * zl - CTAB(3, e) * zr;
       dd[m] = zr;
 #pragma unroll
       for (int e = 0; e < SL; ++e) {
@@ -1067,9 +1275,9 @@ static void launch_line(Prof* pf, hipStream_t s, LineK<T> K, const char* name) {
 #define IBM_LINE(M)                                                                   \
   do {                                                                                \
     if (fixed)                                                                        \
-      IBM_LAUNCH(pf, name, s, (k_line<T, M, true><<<grid, threads, shm, s>>>(K)));   \
+      IBM_LAUNCH_G(pf, name, s, (&k_line<T, M, true, true>), dim3(grid), dim3(threads), shm, K, k_line<T, M, true><<<grid, threads, shm, s>>>(K));   \
     else                                                                              \
-      IBM_LAUNCH(pf, name, s, (k_line<T, M, false><<<grid, threads, shm, s>>>(K)));  \
+      IBM_LAUNCH_G(pf, name, s, (&k_line<T, M, false, true>), dim3(grid), dim3(threads), shm, K, k_line<T, M, false><<<grid, threads, shm, s>>>(K));  \
   } while (0)
   if (K.mode == 0 && fixed && (K.P & (K.P - 1)) == 0 && K.P >= 4 && K.P <= 64) {
     // one wavefront per group of 64/P rows, four wavefronts per block, as
@@ -1089,7 +1297,7 @@ static void launch_line(Prof* pf, hipStream_t s, LineK<T> K, const char* name) {
     }
     int64_t blocks = (waves + 3) / 4;
     if (blocks > resident) blocks = resident;
-    IBM_LAUNCH(pf, name, s, (k_line_xw<T><<<(unsigned)blocks, 256, xshm, s>>>(K)));
+    IBM_LAUNCH_G(pf, name, s, (&k_line_xw<T, true>), dim3((unsigned)blocks), dim3(256), xshm, K, k_line_xw<T><<<(unsigned)blocks, 256, xshm, s>>>(K));
   } else if (K.mode == 0) {
     IBM_LINE(0);
   } else if (K.r == 0 &&
@@ -1111,40 +1319,43 @@ static void launch_line(Prof* pf, hipStream_t s, LineK<T> K, const char* name) {
     const size_t cshm = sizeof(T) * (LINE_NTAB * (size_t)(K.tab1 ? 1 : K.P) * K.L +
                                      7 * (size_t)pp * (tl + 1)) +
                         sizeof(uint32_t) * (size_t)K.P * K.L +
-                        (K.mode == 2 ? sizeof(T) * 3 * (size_t)K.P * K.L : 0);
+                        ((K.mode == 2 && K.L > LMAX) ? sizeof(T) * 3 * (size_t)K.P * K.L : 0);
     const dim3 cgrid = (K.mode == 1) ? dim3(K.nx / tl, K.nj) : dim3(K.nz, K.nx / tl);
-#define IBM_COL(M, SL_)                                                                        \
+#define IBM_COL(M, SL_, KERN)                                                                  \
   do {                                                                                        \
     if constexpr (sizeof(T) == sizeof(float)) {                                               \
       if (tl == 32) {                                                                         \
-        IBM_LAUNCH(pf, name, s, (k_line_col<T, M, SL_, 32><<<cgrid, ct, cshm, s>>>(K)));      \
+        IBM_LAUNCH_G(pf, name, s, (&KERN<T, M, SL_, 32, true>), dim3(cgrid), dim3(ct), cshm, K, \
+                     KERN<T, M, SL_, 32><<<cgrid, ct, cshm, s>>>(K));                         \
         break;                                                                                \
       }                                                                                       \
     }                                                                                         \
-    IBM_LAUNCH(pf, name, s, (k_line_col<T, M, SL_, 16><<<cgrid, ct, cshm, s>>>(K)));          \
+    IBM_LAUNCH_G(pf, name, s, (&KERN<T, M, SL_, 16, true>), dim3(cgrid), dim3(ct), cshm, K,   \
+                 KERN<T, M, SL_, 16><<<cgrid, ct, cshm, s>>>(K));                             \
   } while (0)
     if constexpr (sizeof(T) == sizeof(float)) {  // the long segments (FP32 plans only)
       if (K.L == 32) {
-        IBM_LAUNCH(pf, name, s, (k_line_col<T, 1, 32, 32><<<cgrid, ct, cshm, s>>>(K)));
+        IBM_LAUNCH_G(pf, name, s, (&k_line_col<T, 1, 32, 32, true>), dim3(cgrid), dim3(ct), cshm, K, k_line_col<T, 1, 32, 32><<<cgrid, ct, cshm, s>>>(K));
         return;
       }
       if (K.L == 24) {
-        IBM_LAUNCH(pf, name, s, (k_line_col<T, 2, 24, 32><<<cgrid, ct, cshm, s>>>(K)));
+        IBM_LAUNCH_G(pf, name, s, (&k_line_col<T, 2, 24, 32, true>), dim3(cgrid), dim3(ct), cshm, K, k_line_col<T, 2, 24, 32><<<cgrid, ct, cshm, s>>>(K));
         return;
       }
     }
+    // wall-normal lines of 12 or 16 rows: the register form
     if (K.mode == 1)
-      IBM_COL(1, LMAX);
+      IBM_COL(1, LMAX, k_line_col);
     else if (K.L == 12)
-      IBM_COL(2, 12);
+      IBM_COL(2, 12, k_line_col_reg);
     else
-      IBM_COL(2, LMAX);
+      IBM_COL(2, LMAX, k_line_col_reg);
 #undef IBM_COL
   }
   else if (K.mode == 1)
-    IBM_LAUNCH(pf, name, s, (k_line<T, 1, false><<<grid, threads, shm, s>>>(K)));
+    IBM_LAUNCH_G(pf, name, s, (&k_line<T, 1, false, true>), dim3(grid), dim3(threads), shm, K, k_line<T, 1, false><<<grid, threads, shm, s>>>(K));
   else
-    IBM_LAUNCH(pf, name, s, (k_line<T, 2, false><<<grid, threads, shm, s>>>(K)));
+    IBM_LAUNCH_G(pf, name, s, (&k_line<T, 2, false, true>), dim3(grid), dim3(threads), shm, K, k_line<T, 2, false><<<grid, threads, shm, s>>>(K));
 #undef IBM_LINE
 }
 

@@ -10,6 +10,15 @@
 // device buffer that is refreshed (one stream-ordered copy) before each step,
 // so a replayed graph sees the new motion.
 //
+// Grouped form (IBM_BATCH_GROUPED): every simulation's step is recorded
+// once (the launches it would issue, with their argument records), and the
+// k-th launch of all simulations becomes one launch of the kernel's grouped
+// instantiation (one per kernel variant and block size among them), whose
+// blocks find their simulation in a table of argument records.  A step is
+// then a few hundred launches for the whole batch instead of a few dozen per
+// simulation, captured into one graph; the arithmetic of every block is that
+// of the simulation's own launch.
+//
 // Execution plans and the autotuner: the simulations, largest first, are
 // dealt round-robin to a chosen number of stream groups (each group runs its
 // simulations one after the other); together with the graph/eager choice and
@@ -62,6 +71,20 @@ struct ibm_batch {
   ibm_batch_plan plan{IBM_BATCH_GRAPH, 0, 16, 0, 0.0};
   std::vector<int> order;  // simulations by decreasing cell count
   std::vector<int> grp;    // stream group of each simulation
+  // grouped form: the launches of one step, their tables in `garena`
+  // (allocated at create, sized by a recording), and its captured graph
+  struct GLaunch {
+    const void* gfunc;
+    dim3 block;
+    size_t shm;
+    unsigned blocks;
+    GrpTab tab;
+  };
+  std::vector<GLaunch> glist;
+  unsigned char* garena = nullptr;
+  size_t garena_bytes = 0;
+  hipGraph_t ggraph = nullptr;
+  hipGraphExec_t gexec = nullptr;
 };
 
 #define BCHK(expr)                                                          \
@@ -76,6 +99,11 @@ static void drop_graph(ibm_batch* b) {
   if (b->graph) (void)hipGraphDestroy(b->graph);
   b->exec = nullptr;
   b->graph = nullptr;
+  if (b->gexec) (void)hipGraphExecDestroy(b->gexec);
+  if (b->ggraph) (void)hipGraphDestroy(b->ggraph);
+  b->gexec = nullptr;
+  b->ggraph = nullptr;
+  b->glist.clear();
 }
 
 static void free_batch(ibm_batch* b) {
@@ -98,6 +126,7 @@ static void free_batch(ibm_batch* b) {
     if (b->stage_ev[k]) (void)hipEventDestroy(b->stage_ev[k]);
   }
   if (b->coef_dev) (void)hipFree(b->coef_dev);
+  if (b->garena) (void)hipFree(b->garena);
   delete b;
 }
 
@@ -134,6 +163,121 @@ static int enqueue(ibm_batch* b, double dt, bool serial) {
   } else {
     for (int gi = 0; gi < b->n; ++gi)
       if (last[gi] >= 0) BCHK(hipStreamWaitEvent(b->own, b->done[last[gi]], 0));
+  }
+  return IBM_OK;
+}
+
+// Records every simulation's body transform and step (no launch is issued)
+// and groups the k-th launches of all simulations by kernel variant and
+// block size.  With `arena` NULL only the table bytes are counted (into
+// *bytes); otherwise the tables are written to the arena (at most
+// arena_bytes) and b->glist is filled.  The contexts must have been
+// prepared for dt.
+static int build_grouped(ibm_batch* b, double dt, unsigned char* arena, size_t arena_bytes,
+                         size_t* bytes) {
+  std::vector<Recorder> rec(b->n);
+  for (int s = 0; s < b->n; ++s) {
+    const ibm_sim& m = b->sim[s];
+    ibm_state st = m.state;
+    cur_recorder() = &rec[s];
+    launch_body_dev(nullptr, nullptr, m.motion == IBM_MOTION_DEFORM, m.ref, m.nv,
+                    b->coef_dev + (size_t)s * IBM_COEF_STRIDE, m.xyz, m.vel);
+    const int rc = ibm_step(b->ctx[s], &st, &b->body[s], 1, dt);
+    cur_recorder() = nullptr;
+    if (rc) return rc;
+    if (rec[s].bad || rec[s].recs.size() != rec[0].recs.size())
+      return ctx_fail(IBM_EINVAL, "grouped batch: the simulations' steps do not record alike");
+  }
+  auto align = [](size_t x) { return (x + 255) / 256 * 256; };
+  std::vector<unsigned char> host;
+  std::vector<ibm_batch::GLaunch> list;
+  const size_t nrec = rec[0].recs.size();
+  for (size_t k = 0; k < nrec; ++k) {
+    // members by (kernel, block), in order of first appearance
+    std::vector<std::vector<int>> groups;
+    for (int s = 0; s < b->n; ++s) {
+      const LaunchRec& r = rec[s].recs[k];
+      bool placed = false;
+      for (auto& gm : groups) {
+        const LaunchRec& q = rec[gm[0]].recs[k];
+        if (q.gfunc == r.gfunc && q.block.x == r.block.x && q.block.y == r.block.y &&
+            q.block.z == r.block.z && q.arg.size() == r.arg.size()) {
+          gm.push_back(s);
+          placed = true;
+          break;
+        }
+      }
+      if (!placed) groups.push_back({s});
+    }
+    for (const auto& gm : groups) {
+      const LaunchRec& r0 = rec[gm[0]].recs[k];
+      const size_t n = gm.size(), ks = r0.arg.size();
+      uint64_t blocks = 0;
+      for (size_t q = 0; q < n; ++q) {
+        const LaunchRec& r = rec[gm[q]].recs[k];
+        blocks += (uint64_t)r.grid.x * r.grid.y * r.grid.z;
+      }
+      if (blocks >= (1ull << 31) || n > 65535)
+        return ctx_fail(IBM_EINVAL, "grouped batch: too many blocks or members in one launch");
+      const size_t off_k = align(host.size());
+      const size_t off_b = align(off_k + n * ks);
+      const size_t off_g = align(off_b + (n + 1) * sizeof(uint32_t));
+      const size_t off_m = align(off_g + 3 * n * sizeof(uint32_t));
+      const size_t end = off_m + (size_t)blocks * sizeof(uint16_t);
+      host.resize(end);
+      uint32_t* bo = reinterpret_cast<uint32_t*>(host.data() + off_b);
+      uint32_t* gd = reinterpret_cast<uint32_t*>(host.data() + off_g);
+      uint16_t* bm = reinterpret_cast<uint16_t*>(host.data() + off_m);
+      uint64_t b0 = 0;
+      size_t shm = 0;
+      for (size_t q = 0; q < n; ++q) {
+        const LaunchRec& r = rec[gm[q]].recs[k];
+        std::memcpy(host.data() + off_k + q * ks, r.arg.data(), ks);
+        bo[q] = (uint32_t)b0;
+        gd[3 * q] = r.grid.x;
+        gd[3 * q + 1] = r.grid.y;
+        gd[3 * q + 2] = r.grid.z;
+        const uint64_t nbq = (uint64_t)r.grid.x * r.grid.y * r.grid.z;
+        for (uint64_t e = 0; e < nbq; ++e) bm[b0 + e] = (uint16_t)q;
+        b0 += nbq;
+        shm = r.shm > shm ? r.shm : shm;
+      }
+      bo[n] = (uint32_t)blocks;
+      ibm_batch::GLaunch gl;
+      gl.gfunc = r0.gfunc;
+      gl.block = r0.block;
+      gl.shm = shm;
+      gl.blocks = (unsigned)blocks;
+      // table pointers are offsets until the arena is known
+      gl.tab.k = reinterpret_cast<const unsigned char*>(off_k);
+      gl.tab.boff = reinterpret_cast<const uint32_t*>(off_b);
+      gl.tab.gdim = reinterpret_cast<const uint32_t*>(off_g);
+      gl.tab.bm = reinterpret_cast<const uint16_t*>(off_m);
+      gl.tab.n = (int)n;
+      gl.tab.ksize = (int)ks;
+      if (blocks > 0) list.push_back(gl);
+    }
+  }
+  *bytes = host.size();
+  if (!arena) return IBM_OK;
+  if (host.size() > arena_bytes)
+    return ctx_fail(IBM_EINVAL, "grouped batch: the launch tables outgrew their arena");
+  BCHK(hipMemcpy(arena, host.data(), host.size(), hipMemcpyHostToDevice));
+  for (auto& gl : list) {
+    gl.tab.k = arena + reinterpret_cast<uintptr_t>(gl.tab.k);
+    gl.tab.boff = reinterpret_cast<const uint32_t*>(arena + reinterpret_cast<uintptr_t>(gl.tab.boff));
+    gl.tab.gdim = reinterpret_cast<const uint32_t*>(arena + reinterpret_cast<uintptr_t>(gl.tab.gdim));
+    gl.tab.bm = reinterpret_cast<const uint16_t*>(arena + reinterpret_cast<uintptr_t>(gl.tab.bm));
+  }
+  b->glist = std::move(list);
+  return IBM_OK;
+}
+
+static int enqueue_grouped(ibm_batch* b) {
+  for (const auto& gl : b->glist) {
+    GrpTab tab = gl.tab;
+    void* args[] = {&tab};
+    BCHK(hipLaunchKernel(gl.gfunc, dim3(gl.blocks), gl.block, args, gl.shm, b->own));
   }
   return IBM_OK;
 }
@@ -223,6 +367,29 @@ int ibm_batch_create(const ibm_grid* grids, const ibm_opts* opts, const ibm_sim*
     BTRY(hipHostMalloc((void**)&b->coef_host[k], sizeof(double) * IBM_COEF_STRIDE * (size_t)nsim));
     BTRY(hipEventCreateWithFlags(&b->stage_ev[k], hipEventDisableTiming));
   }
+  {
+    // the grouped form's tables: their size does not depend on dt, and the
+    // plan changes only the RHS grid, largest with one plane per block, so
+    // one recording at a nominal dt with one plane per block sizes the arena
+    for (int s = 0; s < nsim; ++s) {
+      rc = ctx_prepare(b->ctx[s], &b->body[s], 1, 1.0);
+      if (rc) {
+        free_batch(b);
+        return rc;
+      }
+      ctx_set_rhs_planes(b->ctx[s], 1);
+    }
+    size_t bytes = 0;
+    rc = build_grouped(b, 1.0, nullptr, 0, &bytes);
+    for (int s = 0; s < nsim; ++s) ctx_set_rhs_planes(b->ctx[s], b->plan.rhs_planes);
+    if (rc == IBM_OK && bytes > 0) {
+      b->garena_bytes = bytes;
+      BTRY(hipMalloc((void**)&b->garena, bytes));
+    }
+    // a batch whose steps do not record alike keeps the stream plans only
+    rc = IBM_OK;
+    b->prep_dt = -1.0;
+  }
 #undef BTRY
   *out = b;
   return IBM_OK;
@@ -238,9 +405,11 @@ ibm_ctx* ibm_batch_context(ibm_batch* b, int32_t sim) {
 }
 
 int ibm_batch_step(ibm_batch* b, const double* coef, double dt, int32_t mode) {
-  if (!b || !coef || !(dt > 0) || mode < IBM_BATCH_SERIAL || mode > IBM_BATCH_PLAN)
+  if (!b || !coef || !(dt > 0) || mode < IBM_BATCH_SERIAL || mode > IBM_BATCH_GROUPED)
     return ctx_fail(IBM_EINVAL, "ibm_batch_step: bad argument");
   if (mode == IBM_BATCH_PLAN) mode = b->plan.mode;
+  if (mode == IBM_BATCH_GROUPED && !b->garena)
+    return ctx_fail(IBM_EINVAL, "ibm_batch_step: this batch has no grouped form");
   if (dt != b->prep_dt) {
     // tables and body descriptors for this dt, outside any capture; a graph
     // launched by an earlier step may still run on b->own: wait for it
@@ -266,7 +435,25 @@ int ibm_batch_step(ibm_batch* b, const double* coef, double dt, int32_t mode) {
   b->stage_used[k] = true;
   BCHK(hipEventRecord(b->ev_in, b->stream));
   BCHK(hipStreamWaitEvent(b->own, b->ev_in, 0));
-  if (mode != IBM_BATCH_GRAPH) {
+  if (mode == IBM_BATCH_GROUPED) {
+    if (!b->gexec) {
+      size_t bytes = 0;
+      int rc = build_grouped(b, dt, b->garena, b->garena_bytes, &bytes);
+      if (rc) return rc;
+      BCHK(hipStreamBeginCapture(b->own, hipStreamCaptureModeThreadLocal));
+      rc = enqueue_grouped(b);
+      hipGraph_t g = nullptr;
+      const hipError_t e = hipStreamEndCapture(b->own, &g);
+      if (rc) {
+        if (g) (void)hipGraphDestroy(g);
+        return rc;
+      }
+      BCHK(e);
+      b->ggraph = g;
+      BCHK(hipGraphInstantiate(&b->gexec, b->ggraph, nullptr, nullptr, 0));
+    }
+    BCHK(hipGraphLaunch(b->gexec, b->own));
+  } else if (mode != IBM_BATCH_GRAPH) {
     const int rc = enqueue(b, dt, mode == IBM_BATCH_SERIAL);
     if (rc) return rc;
   } else {
@@ -291,7 +478,8 @@ int ibm_batch_step(ibm_batch* b, const double* coef, double dt, int32_t mode) {
 }
 
 static bool plan_ok(const ibm_batch* b, const ibm_batch_plan& p) {
-  return (p.mode == IBM_BATCH_STREAMS || p.mode == IBM_BATCH_GRAPH) && p.streams >= 1 &&
+  return (p.mode == IBM_BATCH_STREAMS || p.mode == IBM_BATCH_GRAPH ||
+          (p.mode == IBM_BATCH_GROUPED && b->garena)) && p.streams >= 1 &&
          p.streams <= b->n && p.rhs_planes >= 1 && p.rhs_planes <= 64;
 }
 
@@ -434,6 +622,7 @@ int ibm_batch_tune(ibm_batch* b, const double* coef, double dt, int32_t steps, v
       if (rc) break;
       if (ms < bp.ms_per_step) bp = tried.back();
     }
+
   } while (false);
   // restore the states and apply the winner (or the starting plan on failure)
   const int rc2 = copy_all(false);

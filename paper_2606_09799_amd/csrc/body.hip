@@ -5,7 +5,7 @@
 // implementation of the same order.
 #pragma clang fp contract(off)
 
-#include "internal.h"
+#include "lanes.h"
 
 namespace ibm {
 
@@ -63,10 +63,25 @@ __global__ void k_body_deform(const double* __restrict__ data, int nv, Deform k,
 // the same transforms with the coefficients read from device memory (the
 // layout of the host coefficient vectors), so that a captured launch can be
 // replayed with new coefficients
-__global__ void k_body_rigid_dev(const double* __restrict__ x0, int nv,
-                                 const double* __restrict__ coef, double* __restrict__ xyz,
-                                 double* __restrict__ vel) {
-  int v = blockIdx.x * blockDim.x + threadIdx.x;
+struct BodyRigidDevK {
+  const double* x0;
+  int nv;
+  const double* coef;
+  double* xyz;
+  double* vel;
+};
+template <bool G = false>
+__global__ void k_body_rigid_dev(GArg<BodyRigidDevK, G> grp_arg_) {
+  uint3 bid, gdim;
+  const BodyRigidDevK& P_ = grp_enter<BodyRigidDevK, G>(grp_arg_, bid, gdim);
+  (void)bid;
+  (void)gdim;
+  const double* __restrict__ x0 = P_.x0;
+  int nv = P_.nv;
+  const double* __restrict__ coef = P_.coef;
+  double* __restrict__ xyz = P_.xyz;
+  double* __restrict__ vel = P_.vel;
+  int v = bid.x * blockDim.x + threadIdx.x;
   if (v >= nv) return;
   Rigid k;
   for (int d = 0; d < 3; ++d) k.c[d] = coef[d];
@@ -76,10 +91,25 @@ __global__ void k_body_rigid_dev(const double* __restrict__ x0, int nv,
   rigid_vertex(k, x0, v, xyz, vel);
 }
 
-__global__ void k_body_deform_dev(const double* __restrict__ data, int nv,
-                                  const double* __restrict__ coef, double* __restrict__ xyz,
-                                  double* __restrict__ vel) {
-  int v = blockIdx.x * blockDim.x + threadIdx.x;
+struct BodyDeformDevK {
+  const double* data;
+  int nv;
+  const double* coef;
+  double* xyz;
+  double* vel;
+};
+template <bool G = false>
+__global__ void k_body_deform_dev(GArg<BodyDeformDevK, G> grp_arg_) {
+  uint3 bid, gdim;
+  const BodyDeformDevK& P_ = grp_enter<BodyDeformDevK, G>(grp_arg_, bid, gdim);
+  (void)bid;
+  (void)gdim;
+  const double* __restrict__ data = P_.data;
+  int nv = P_.nv;
+  const double* __restrict__ coef = P_.coef;
+  double* __restrict__ xyz = P_.xyz;
+  double* __restrict__ vel = P_.vel;
+  int v = bid.x * blockDim.x + threadIdx.x;
   if (v >= nv) return;
   Deform k;
   for (int d = 0; d < 3; ++d) k.c[d] = coef[d];
@@ -116,12 +146,16 @@ void launch_body_deform(Prof* pf, hipStream_t s, const double* data, int nv, con
 void launch_body_dev(Prof* pf, hipStream_t s, int deform, const double* ref, int nv,
                      const double* coef_dev, double* xyz, double* vel) {
   if (nv <= 0) return;
-  if (deform)
-    IBM_LAUNCH(pf, "body_deform", s,
-               k_body_deform_dev<<<(nv + 255) / 256, 256, 0, s>>>(ref, nv, coef_dev, xyz, vel));
-  else
-    IBM_LAUNCH(pf, "body_rigid", s,
-               k_body_rigid_dev<<<(nv + 255) / 256, 256, 0, s>>>(ref, nv, coef_dev, xyz, vel));
+  const dim3 grid((unsigned)((nv + 255) / 256));
+  if (deform) {
+    const BodyDeformDevK K{ref, nv, coef_dev, xyz, vel};
+    IBM_LAUNCH_G(pf, "body_deform", s, (&k_body_deform_dev<true>), grid, dim3(256), 0, K,
+                 k_body_deform_dev<<<grid, 256, 0, s>>>(K));
+  } else {
+    const BodyRigidDevK K{ref, nv, coef_dev, xyz, vel};
+    IBM_LAUNCH_G(pf, "body_rigid", s, (&k_body_rigid_dev<true>), grid, dim3(256), 0, K,
+                 k_body_rigid_dev<<<grid, 256, 0, s>>>(K));
+  }
 }
 
 }  // namespace ibm

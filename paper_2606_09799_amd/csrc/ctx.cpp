@@ -27,8 +27,27 @@ static thread_local std::string g_last_error;
     }                                                                      \
   } while (0)
 
-// ------------------------------------------------------------ profiling
+// ------------------------------------------------------------ recording
 namespace ibm {
+Recorder*& cur_recorder() {
+  static thread_local Recorder* r = nullptr;
+  return r;
+}
+
+void record_launch(const char* name, const void* gfunc, dim3 grid, dim3 block, size_t shm,
+                   const void* arg, size_t bytes) {
+  Recorder* r = cur_recorder();
+  LaunchRec e;
+  e.name = name;
+  e.gfunc = gfunc;
+  e.arg.assign(static_cast<const unsigned char*>(arg), static_cast<const unsigned char*>(arg) + bytes);
+  e.grid = grid;
+  e.block = block;
+  e.shm = shm;
+  r->recs.push_back(std::move(e));
+}
+
+// ------------------------------------------------------------ profiling
 struct Prof {
   bool enabled = false;
   std::string filter;

@@ -68,15 +68,20 @@ __device__ double trilinear(const GridView& g, const Lattice& L, int c, const do
   return out;
 }
 
-__global__ __launch_bounds__(256) void k_force_compute(ForceK a) {
-  const int c = blockIdx.y;
+template <bool G = false>
+__global__ __launch_bounds__(256) void k_force_compute(GArg<ForceK, G> grp_arg_) {
+  uint3 bid, gdim;
+  const ForceK& a = grp_enter<ForceK, G>(grp_arg_, bid, gdim);
+  (void)bid;
+  (void)gdim;
+  const int c = bid.y;
   int64_t n = a.count[c];
   if (n > a.cap) n = a.cap;
   const GridView& g = a.g;
   const Lattice L = lattice(g, c);
   const int64_t plane = (int64_t)g.nz * g.nx;
-  for (int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; f < n;
-       f += (int64_t)gridDim.x * blockDim.x) {
+  for (int64_t f = (int64_t)bid.x * blockDim.x + threadIdx.x; f < n;
+       f += (int64_t)gdim.x * blockDim.x) {
     const int64_t node = a.idx[c][f];
     const int t = a.tri[c][f];
     double A[3], B[3], C[3];
@@ -123,12 +128,17 @@ __global__ __launch_bounds__(256) void k_force_compute(ForceK a) {
   }
 }
 
-__global__ __launch_bounds__(256) void k_force_scatter(ForceK a) {
-  const int c = blockIdx.y;
+template <bool G = false>
+__global__ __launch_bounds__(256) void k_force_scatter(GArg<ForceK, G> grp_arg_) {
+  uint3 bid, gdim;
+  const ForceK& a = grp_enter<ForceK, G>(grp_arg_, bid, gdim);
+  (void)bid;
+  (void)gdim;
+  const int c = bid.y;
   int64_t n = a.count[c];
   if (n > a.cap) n = a.cap;
-  for (int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; f < n;
-       f += (int64_t)gridDim.x * blockDim.x)
+  for (int64_t f = (int64_t)bid.x * blockDim.x + threadIdx.x; f < n;
+       f += (int64_t)gdim.x * blockDim.x)
     a.field[c][a.idx[c][f]] = a.vals[c * a.cap + f];
 }
 
@@ -432,8 +442,10 @@ void launch_force(Prof* pf, hipStream_t s, const GridView& g, const BodyDev* bod
   if (blocks > 512) blocks = 512;
   if (blocks < 1) blocks = 1;
   dim3 grid(blocks, 3);
-  IBM_LAUNCH(pf, "force_compute", s, k_force_compute<<<grid, 256, 0, s>>>(a));
-  IBM_LAUNCH(pf, "force_scatter", s, k_force_scatter<<<grid, 256, 0, s>>>(a));
+  IBM_LAUNCH_G(pf, "force_compute", s, (&k_force_compute<true>), grid, dim3(256), 0, a,
+               k_force_compute<<<grid, 256, 0, s>>>(a));
+  IBM_LAUNCH_G(pf, "force_scatter", s, (&k_force_scatter<true>), grid, dim3(256), 0, a,
+               k_force_scatter<<<grid, 256, 0, s>>>(a));
 }
 
 }  // namespace ibm

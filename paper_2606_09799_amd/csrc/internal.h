@@ -4,7 +4,9 @@
 
 #include <hip/hip_runtime.h>
 
+#include <cstddef>
 #include <cstdint>
+#include <vector>
 
 namespace ibm {
 
@@ -162,11 +164,62 @@ inline int64_t xcd_band_blocks(int nbx, int nbz, int ny, int BW) {
 struct Prof;
 void prof_begin(Prof* p, const char* name, hipStream_t s);
 void prof_end(Prof* p, hipStream_t s);
-#define IBM_LAUNCH(pf, name, s, ...)  \
-  do {                                \
-    ::ibm::prof_begin(pf, name, s);   \
-    __VA_ARGS__;                      \
-    ::ibm::prof_end(pf, s);           \
+
+// Launch recording (the grouped batched form).  While a recorder is set on
+// this host thread, a launch that has a grouped form is appended to it
+// instead of being issued: the grouped instantiation of its kernel, its
+// argument record, grid, block and dynamic LDS size.  A launch without a
+// grouped form marks the recording unusable (the batch then keeps its
+// stream plans).
+struct LaunchRec {
+  const char* name;
+  const void* gfunc;
+  std::vector<unsigned char> arg;
+  dim3 grid, block;
+  size_t shm;
+};
+struct Recorder {
+  std::vector<LaunchRec> recs;
+  bool bad = false;
+};
+// The argument of a kernel's grouped instantiation: the members' argument
+// records (ksize bytes each), their block offsets (n + 1 prefix sums), their
+// grids (3 per member) and the member of every block of the launch, all in
+// device memory.
+struct GrpTab {
+  const unsigned char* k;
+  const uint32_t* boff;
+  const uint32_t* gdim;
+  const uint16_t* bm;
+  int n;
+  int ksize;
+};
+Recorder*& cur_recorder();
+void record_launch(const char* name, const void* gfunc, dim3 grid, dim3 block, size_t shm,
+                   const void* arg, size_t bytes);
+
+#define IBM_LAUNCH(pf, name, s, ...)          \
+  do {                                        \
+    if (::ibm::cur_recorder()) {              \
+      ::ibm::cur_recorder()->bad = true;      \
+    } else {                                  \
+      ::ibm::prof_begin(pf, name, s);         \
+      __VA_ARGS__;                            \
+      ::ibm::prof_end(pf, s);                 \
+    }                                         \
+  } while (0)
+// A launch with a grouped form: GF is the address of the kernel's grouped
+// instantiation (in parentheses), K its single argument; the launch
+// expression follows.
+#define IBM_LAUNCH_G(pf, name, s, GF, GRID, BLOCK, SHM, K, ...)                       \
+  do {                                                                               \
+    if (::ibm::cur_recorder()) {                                                     \
+      ::ibm::record_launch(name, (const void*)GF, GRID, BLOCK, SHM, &(K), sizeof(K)); \
+    } else {                                                                         \
+      ::ibm::prof_begin(pf, name, s);                                                \
+      __VA_ARGS__;                                                                   \
+      ::ibm::prof_end(pf, s);                                                        \
+    }                                                                                \
   } while (0)
 
 // sticky flags (same bits as IBM_FLAG_*)

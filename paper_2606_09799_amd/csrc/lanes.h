@@ -73,17 +73,12 @@ __device__ __forceinline__ void wave_sync() {
 // Grouped launches (the batched form): one launch runs the blocks of several
 // simulations' launches of one kernel.  The grouped instantiation of a
 // kernel takes a GrpTab instead of its argument record: the records (ksize
-// bytes each), the block offsets of the members (n + 1 prefix sums) and each
-// member's grid; a block finds its member by binary search and runs as that
-// member's block.  grp_enter gives the argument record and the block's
-// position and grid, in both instantiations.
-struct GrpTab {
-  const unsigned char* k;
-  const uint32_t* boff;
-  const uint32_t* gdim;  // 3 per member
-  int n;
-  int ksize;
-};
+// bytes each), the block offsets of the members (n + 1 prefix sums), each
+// member's grid and a member index per block; a block reads its member (one
+// load: a search over the offsets cost small blocks several dependent
+// loads) and runs as that member's block (GrpTab: internal.h).  grp_enter
+// gives the argument record and the block's position and grid, in both
+// instantiations.
 template <typename KT, bool G>
 struct GArgT {
   using type = KT;
@@ -103,11 +98,7 @@ __device__ __forceinline__ const KT& grp_enter(const GArg<KT, G>& A, uint3& bid,
     return A;
   } else {
     const uint32_t b = blockIdx.x;
-    int lo = 0, hi = A.n;  // A.boff[lo] <= b < A.boff[hi]
-    while (hi - lo > 1) {
-      const int mid = (lo + hi) >> 1;
-      if (A.boff[mid] <= b) lo = mid; else hi = mid;
-    }
+    const int lo = __builtin_amdgcn_readfirstlane((int)A.bm[b]);
     const uint32_t l = b - A.boff[lo];
     const uint32_t gx = A.gdim[3 * lo], gy = A.gdim[3 * lo + 1], gz = A.gdim[3 * lo + 2];
     gdim = make_uint3(gx, gy, gz);

@@ -27,17 +27,35 @@ __device__ __forceinline__ double div_at(const GridView& g, const double* u, con
          (w[(int64_t)j * plane + (int64_t)kp * g.nx + i] - w[cell]) * g.idz;
 }
 
-__global__ __launch_bounds__(MT) void k_mass_partial(GridView g, const double* __restrict__ u,
-                                                     const double* __restrict__ v,
-                                                     const double* __restrict__ w,
-                                                     const int64_t* __restrict__ cb,
-                                                     const int64_t* __restrict__ count, int64_t cap,
-                                                     double* __restrict__ partial) {
+struct MassPartK {
+  GridView g;
+  const double* u;
+  const double* v;
+  const double* w;
+  const int64_t* cb;
+  const int64_t* count;
+  int64_t cap;
+  double* partial;
+};
+template <bool G = false>
+__global__ __launch_bounds__(MT) void k_mass_partial(GArg<MassPartK, G> grp_arg_) {
+  uint3 bid, gdim;
+  const MassPartK& P_ = grp_enter<MassPartK, G>(grp_arg_, bid, gdim);
+  (void)bid;
+  (void)gdim;
+  GridView g = P_.g;
+  const double* __restrict__ u = P_.u;
+  const double* __restrict__ v = P_.v;
+  const double* __restrict__ w = P_.w;
+  const int64_t* __restrict__ cb = P_.cb;
+  const int64_t* __restrict__ count = P_.count;
+  int64_t cap = P_.cap;
+  double* __restrict__ partial = P_.partial;
   __shared__ double sa[MT], sv[MT];
   int64_t n = count[3];
   if (n > cap) n = cap;
   const int64_t chunk = (n + MB - 1) / MB;
-  const int64_t lo = blockIdx.x * chunk;
+  const int64_t lo = bid.x * chunk;
   const int64_t hi = (lo + chunk < n) ? lo + chunk : n;
   double A = 0.0, V = 0.0;
   const double dxdz = g.dx * g.dz;
@@ -59,15 +77,31 @@ __global__ __launch_bounds__(MT) void k_mass_partial(GridView g, const double* _
     __syncthreads();
   }
   if (threadIdx.x == 0) {
-    partial[2 * blockIdx.x] = sa[0];
-    partial[2 * blockIdx.x + 1] = sv[0];
+    partial[2 * bid.x] = sa[0];
+    partial[2 * bid.x + 1] = sv[0];
   }
 }
 
-__global__ __launch_bounds__(MB) void k_mass_final(const double* __restrict__ partial,
-                                                   const int64_t* __restrict__ count, double vtot,
-                                                   int use_q, double* __restrict__ qf,
-                                                   uint32_t* flags) {
+struct MassFinK {
+  const double* partial;
+  const int64_t* count;
+  double vtot;
+  int use_q;
+  double* qf;
+  uint32_t* flags;
+};
+template <bool G = false>
+__global__ __launch_bounds__(MB) void k_mass_final(GArg<MassFinK, G> grp_arg_) {
+  uint3 bid, gdim;
+  const MassFinK& P_ = grp_enter<MassFinK, G>(grp_arg_, bid, gdim);
+  (void)bid;
+  (void)gdim;
+  const double* __restrict__ partial = P_.partial;
+  const int64_t* __restrict__ count = P_.count;
+  double vtot = P_.vtot;
+  int use_q = P_.use_q;
+  double* __restrict__ qf = P_.qf;
+  uint32_t* flags = P_.flags;
   __shared__ double sa[MB], sv[MB];
   sa[threadIdx.x] = partial[2 * threadIdx.x];
   sv[threadIdx.x] = partial[2 * threadIdx.x + 1];
@@ -382,10 +416,12 @@ void launch_divergence(Prof* pf, hipStream_t s, const GridView& g, const double*
 void launch_mass(Prof* pf, hipStream_t s, const GridView& g, const double* u, const double* v,
                  const double* w, const int64_t* cb, const int64_t* count, int64_t cap,
                  double vtot, int use_q, double* partial, double* qf, uint32_t* flags) {
-  IBM_LAUNCH(pf, "mass_partial", s,
-             k_mass_partial<<<MB, MT, 0, s>>>(g, u, v, w, cb, count, cap, partial));
-  IBM_LAUNCH(pf, "mass_final", s,
-             k_mass_final<<<1, MB, 0, s>>>(partial, count, vtot, use_q, qf, flags));
+  const MassPartK P{g, u, v, w, cb, count, cap, partial};
+  IBM_LAUNCH_G(pf, "mass_partial", s, (&k_mass_partial<true>), dim3(MB), dim3(MT), 0, P,
+               k_mass_partial<<<MB, MT, 0, s>>>(P));
+  const MassFinK F{partial, count, vtot, use_q, qf, flags};
+  IBM_LAUNCH_G(pf, "mass_final", s, (&k_mass_final<true>), dim3(1), dim3(MB), 0, F,
+               k_mass_final<<<1, MB, 0, s>>>(F));
 }
 
 void launch_mass_rhs(Prof* pf, hipStream_t s, const GridView& g, const double* u, const double* v,

@@ -275,10 +275,11 @@ __device__ __forceinline__ double fftx_source(const PoisK<C>& K, int64_t rr, int
 }
 
 // block maximum of |r| (one atomic on its bit pattern: non-negative doubles
-// order like their bits) and block sum of phi dV into psum[blockIdx.x], in a
-// fixed order; red: 2 * (waves per block) doubles of LDS
+// order like their bits) and block sum of phi dV into psum[bx] (bx: the
+// block's index in its launch), in a fixed order; red: 2 * (waves per block)
+// doubles of LDS
 __device__ __forceinline__ void resid_reduce(double rmax, double vsum, double* red, u64* rmax_out,
-                                             double* psum, double dxdz) {
+                                             double* psum, double dxdz, uint32_t bx) {
   for (int off = 32; off > 0; off >>= 1) {
     rmax = fmax(rmax, __shfl_xor(rmax, off));
     vsum += __shfl_xor(vsum, off);
@@ -297,7 +298,7 @@ __device__ __forceinline__ void resid_reduce(double rmax, double vsum, double* r
     }
     atomicMax(reinterpret_cast<unsigned long long*>(rmax_out),
               (unsigned long long)__double_as_longlong(m));
-    if (psum) psum[blockIdx.x] = sm * dxdz;
+    if (psum) psum[bx] = sm * dxdz;
   }
 }
 
@@ -337,8 +338,12 @@ __device__ __forceinline__ void fftx_stage_vel_rows(const PoisK<C>& K, typename 
   }
 }
 
-template <typename C>
-__global__ __launch_bounds__(256) void k_fftx_fwd(PoisK<C> K) {
+template <typename C, bool G = false>
+__global__ __launch_bounds__(256) void k_fftx_fwd(GArg<PoisK<C>, G> grp_arg_) {
+  uint3 bid, gdim;
+  const PoisK<C>& K = grp_enter<PoisK<C>, G>(grp_arg_, bid, gdim);
+  (void)bid;
+  (void)gdim;
   using R = typename RealOf<C>::T;
   if (gated(K)) return;
   extern __shared__ __align__(16) unsigned char smraw[];
@@ -347,7 +352,7 @@ __global__ __launch_bounds__(256) void k_fftx_fwd(PoisK<C> K) {
   const GridView& g = K.g;
   const int nx = g.nx, nxh = g.nxh;
   const int64_t nrows = (int64_t)g.ny * g.nz;
-  const int64_t row0 = (int64_t)blockIdx.x * K.rows;
+  const int64_t row0 = (int64_t)bid.x * K.rows;
   const int nr = (int)((row0 + K.rows <= nrows) ? K.rows : nrows - row0);
   // two real rows per complex sequence: row r is the real (r even) or the
   // imaginary (r odd) part of sequence r/2
@@ -375,7 +380,7 @@ __global__ __launch_bounds__(256) void k_fftx_fwd(PoisK<C> K) {
       if (K.mode != SRC_CHECK) sr[2 * ((r >> 1) * nx + i) + (r & 1)] = (R)val;
     }
     if (resid) {
-      resid_reduce(rmax, vsum, red, K.rmax, K.psum, g.dx * g.dz);
+      resid_reduce(rmax, vsum, red, K.rmax, K.psum, g.dx * g.dz, bid.x);
       if (K.mode == SRC_CHECK) return;  // block-uniform
     }
     for (int e = nr * nx + threadIdx.x; e < K.rows * nx; e += blockDim.x) {
@@ -396,16 +401,20 @@ __global__ __launch_bounds__(256) void k_fftx_fwd(PoisK<C> K) {
   }
 }
 
-template <typename C, bool INV>
-__global__ __launch_bounds__(256) void k_fftz(PoisK<C> K) {
+template <typename C, bool INV, bool G = false>
+__global__ __launch_bounds__(256) void k_fftz(GArg<PoisK<C>, G> grp_arg_) {
+  uint3 bid, gdim;
+  const PoisK<C>& K = grp_enter<PoisK<C>, G>(grp_arg_, bid, gdim);
+  (void)bid;
+  (void)gdim;
   using R = typename RealOf<C>::T;
   if (gated(K)) return;
   extern __shared__ __align__(16) unsigned char smraw[];
   C* sm = reinterpret_cast<C*>(smraw);
   const GridView& g = K.g;
   const int nz = g.nz, nxh = g.nxh, tp = K.tp;
-  const int j = blockIdx.y;
-  const int p0 = blockIdx.x * tp;
+  const int j = bid.y;
+  const int p0 = bid.x * tp;
   const int nc = (p0 + tp <= nxh) ? tp : nxh - p0;
   C* spec = K.spec + (int64_t)j * nz * K.ldx + p0;
   for (int e = threadIdx.x; e < nz * tp; e += blockDim.x) {
@@ -469,17 +478,21 @@ __device__ __forceinline__ constexpr int pos16(int k) { return 4 * (k & 3) + (k 
 constexpr int Z16_TC = 8;                  // x-modes per block
 constexpr int Z16_LP = 16 * Z16_TC + 8;    // padded LDS stride of one k2 group
 
-template <typename C, bool INV>
-__global__ __launch_bounds__(16 * Z16_TC) void k_fftz256(PoisK<C> K) {
+template <typename C, bool INV, bool G = false>
+__global__ __launch_bounds__(16 * Z16_TC) void k_fftz256(GArg<PoisK<C>, G> grp_arg_) {
+  uint3 bid, gdim;
+  const PoisK<C>& K = grp_enter<PoisK<C>, G>(grp_arg_, bid, gdim);
+  (void)bid;
+  (void)gdim;
   if (gated(K)) return;
   __shared__ C T[16 * Z16_LP];
   const GridView& g = K.g;
   const int nxh = g.nxh;
   const int c = threadIdx.x % Z16_TC, t = threadIdx.x / Z16_TC;
-  const int p = blockIdx.x * Z16_TC + c;
+  const int p = bid.x * Z16_TC + c;
   const bool valid = p < nxh;
   const int ldx = K.ldx;
-  C* col = K.spec + (int64_t)blockIdx.y * 256 * ldx + (valid ? p : 0);  // element k at col[k * ldx]
+  C* col = K.spec + (int64_t)bid.y * 256 * ldx + (valid ? p : 0);  // element k at col[k * ldx]
   C x[16];
 #pragma unroll
   for (int n2 = 0; n2 < 16; ++n2) x[n2] = col[(int64_t)(t + 16 * n2) * ldx];
@@ -518,9 +531,10 @@ __global__ __launch_bounds__(16 * Z16_TC) void k_fftz256(PoisK<C> K) {
 // 128-byte line of a spectrum row go to one XCD, one after the other (blocks
 // are dealt to the 8 XCDs round robin by linear id), so that the line is
 // fetched from HBM once into that XCD's L2 instead of once per tile.  1-D
-// grid of zline_blocks blocks; false for the padding blocks.
-__device__ __forceinline__ bool zline_tile(int G, int gx, int ny, int& tile, int& j) {
-  const int64_t b = blockIdx.x;
+// grid of zline_blocks blocks (bx: the block's index); false for the padding
+// blocks.
+__device__ __forceinline__ bool zline_tile(uint32_t bx, int G, int gx, int ny, int& tile, int& j) {
+  const int64_t b = bx;
   const int u = (int)((b / NUM_XCD) % G);
   const int64_t U = (b / (NUM_XCD * (int64_t)G)) * NUM_XCD + b % NUM_XCD;  // line group
   const int LG = (gx + G - 1) / G;
@@ -538,8 +552,12 @@ constexpr int zline_group() {
   return (128 / (TC * (int)sizeof(C))) > 1 ? 128 / (TC * (int)sizeof(C)) : 1;
 }
 
-template <typename C, bool INV, int R>
-__global__ __launch_bounds__(256) void k_fftz4s(PoisK<C> K) {
+template <typename C, bool INV, int R, bool G = false>
+__global__ __launch_bounds__(256) void k_fftz4s(GArg<PoisK<C>, G> grp_arg_) {
+  uint3 bid, gdim;
+  const PoisK<C>& K = grp_enter<PoisK<C>, G>(grp_arg_, bid, gdim);
+  (void)bid;
+  (void)gdim;
   constexpr int M = 16 * R;    // threads per mode
   constexpr int N = 16 * M;    // transform length
   constexpr int TC = 256 / M;  // modes per block
@@ -549,7 +567,7 @@ __global__ __launch_bounds__(256) void k_fftz4s(PoisK<C> K) {
   const GridView& g = K.g;
   const int nxh = g.nxh;
   int tile, j;
-  if (!zline_tile(zline_group<C, TC>(), (nxh + TC - 1) / TC, g.ny, tile, j)) return;
+  if (!zline_tile(bid.x, zline_group<C, TC>(), (nxh + TC - 1) / TC, g.ny, tile, j)) return;
   const int c = threadIdx.x % TC, tt = threadIdx.x / TC;
   const int p = tile * TC + c;
   const bool valid = p < nxh;
@@ -756,8 +774,12 @@ __device__ __forceinline__ void fftx256_stage_vel_any(const PoisK<C>& K,
   }
 }
 
-template <typename C>
-__global__ __launch_bounds__(32 * X16_SC) void k_fftx256_fwd(PoisK<C> K) {
+template <typename C, bool G = false>
+__global__ __launch_bounds__(32 * X16_SC) void k_fftx256_fwd(GArg<PoisK<C>, G> grp_arg_) {
+  uint3 bid, gdim;
+  const PoisK<C>& K = grp_enter<PoisK<C>, G>(grp_arg_, bid, gdim);
+  (void)bid;
+  (void)gdim;
   using R = typename RealOf<C>::T;
   if (gated(K)) return;
   __shared__ C T[X16_SC * X16_SS];
@@ -765,7 +787,7 @@ __global__ __launch_bounds__(32 * X16_SC) void k_fftx256_fwd(PoisK<C> K) {
   const GridView& g = K.g;
   const int nxh = g.nxh;
   const int64_t nrows = (int64_t)g.ny * g.nz;
-  const int64_t row0 = (int64_t)blockIdx.x * (2 * X16_SC);
+  const int64_t row0 = (int64_t)bid.x * (2 * X16_SC);
   const int nr = (int)((row0 + 2 * X16_SC <= nrows) ? 2 * X16_SC : nrows - row0);
   const double q = (K.mode == SRC_VELOCITY) ? K.qf[0] : 0.0;
   const double q1 = (K.mode == SRC_VELOCITY && K.pq) ? K.qf[1] : 0.0;
@@ -801,7 +823,7 @@ __global__ __launch_bounds__(32 * X16_SC) void k_fftx256_fwd(PoisK<C> K) {
     tr[2 * ((r >> 1) * X16_SS + i) + (r & 1)] = (R)val;
   }
   if (K.mode >= SRC_RESIDUAL) {
-    resid_reduce(rmax, vsum, red, K.rmax, K.psum, g.dx * g.dz);
+    resid_reduce(rmax, vsum, red, K.rmax, K.psum, g.dx * g.dz, bid.x);
     if (K.mode == SRC_CHECK) return;  // block-uniform
   }
   __syncthreads();
@@ -858,15 +880,19 @@ __global__ __launch_bounds__(32 * X16_SC) void k_fftx256_fwd(PoisK<C> K) {
   }
 }
 
-template <typename C>
-__global__ __launch_bounds__(32 * X16_SC) void k_fftx256_inv(PoisK<C> K) {
+template <typename C, bool G = false>
+__global__ __launch_bounds__(32 * X16_SC) void k_fftx256_inv(GArg<PoisK<C>, G> grp_arg_) {
+  uint3 bid, gdim;
+  const PoisK<C>& K = grp_enter<PoisK<C>, G>(grp_arg_, bid, gdim);
+  (void)bid;
+  (void)gdim;
   using R = typename RealOf<C>::T;
   if (gated(K)) return;
   __shared__ C T[X16_SC * X16_SS];
   const GridView& g = K.g;
   const int nxh = g.nxh;
   const int64_t nrows = (int64_t)g.ny * g.nz;
-  const int64_t row0 = (int64_t)blockIdx.x * (2 * X16_SC);
+  const int64_t row0 = (int64_t)bid.x * (2 * X16_SC);
   const int nr = (int)((row0 + 2 * X16_SC <= nrows) ? 2 * X16_SC : nrows - row0);
   // 1. the block's half spectra, coalesced: row r at T[(r/2) X16_SS + (r%2) nxh].
   //    The rows are contiguous in memory (padding included): every load is
@@ -966,8 +992,12 @@ __global__ __launch_bounds__(32 * X16_SC) void k_fftx256_inv(PoisK<C> K) {
 // Tile rows have a stride of M + 1 complex values, so that each step's LDS
 // accesses spread over all bank groups.  A sequence past the last row pair
 // transforms a copy of the last rows and stores nothing.
-template <typename C, int R>
-__global__ __launch_bounds__(256) void k_fftx4s_inv(PoisK<C> K) {
+template <typename C, int R, bool G = false>
+__global__ __launch_bounds__(256) void k_fftx4s_inv(GArg<PoisK<C>, G> grp_arg_) {
+  uint3 bid, gdim;
+  const PoisK<C>& K = grp_enter<PoisK<C>, G>(grp_arg_, bid, gdim);
+  (void)bid;
+  (void)gdim;
   using RT = typename RealOf<C>::T;
   constexpr int M = 16 * R;         // lanes per sequence
   constexpr int N = 16 * M;         // transform length
@@ -981,7 +1011,7 @@ __global__ __launch_bounds__(256) void k_fftx4s_inv(PoisK<C> K) {
   const int nxh = g.nxh;  // N/2 + 1
   const int64_t nrows = (int64_t)g.ny * g.nz;
   const int t = threadIdx.x % M, sq = threadIdx.x / M;
-  const int64_t ra = ((int64_t)blockIdx.x * SPB + sq) * 2;  // rows ra (real part), ra + 1
+  const int64_t ra = ((int64_t)bid.x * SPB + sq) * 2;  // rows ra (real part), ra + 1
   const bool live_a = ra < nrows, live_b = ra + 1 < nrows;
   const C* sa = K.spec + (live_a ? ra : nrows - 1) * K.ldx;
   const C* sb = K.spec + (live_b ? ra + 1 : nrows - 1) * K.ldx;
@@ -1121,8 +1151,12 @@ __device__ __forceinline__ void excess_row(double& a, double& e, double& g, doub
 // more than 64 separators, so that a mode's separators still fit one
 // wavefront).  UNI: every segment holds exactly SL rows (ny = P SL), so the
 // row loops are straight-line code.
-template <typename C, bool UNI, typename CO, int SL>
-__global__ __launch_bounds__(SL == YL ? 1024 : 512) void k_tri_y(PoisK<C> K) {
+template <typename C, bool UNI, typename CO, int SL, bool G = false>
+__global__ __launch_bounds__(SL == YL ? 1024 : 512) void k_tri_y(GArg<PoisK<C>, G> grp_arg_) {
+  uint3 bid, gdim;
+  const PoisK<C>& K = grp_enter<PoisK<C>, G>(grp_arg_, bid, gdim);
+  (void)bid;
+  (void)gdim;
   using RO = typename RealOf<CO>::T;
   if (gated(K)) return;
   extern __shared__ __align__(16) unsigned char smraw[];
@@ -1135,8 +1169,8 @@ __global__ __launch_bounds__(SL == YL ? 1024 : 512) void k_tri_y(PoisK<C> K) {
   // modes p of tile b / nz), so that consecutive blocks read different z
   // rows, hence different memory channels; padding columns are skipped
   const int64_t nm = (int64_t)g.nz * K.ldx;  // stride of one y row of modes
-  const int kq = (int)(blockIdx.x % (unsigned)g.nz);
-  const int pq = (int)(blockIdx.x / (unsigned)g.nz) * TL + lb;
+  const int kq = (int)(bid.x % (unsigned)g.nz);
+  const int pq = (int)(bid.x / (unsigned)g.nz) * TL + lb;
   const int64_t q = (int64_t)kq * K.ldx + pq;
   const bool valid = active && pq < g.nxh;
   // LDS array f, separator seg, mode lane ln (padded stride: conflict-free in
@@ -1161,7 +1195,7 @@ __global__ __launch_bounds__(SL == YL ? 1024 : 512) void k_tri_y(PoisK<C> K) {
     xr[e] = (double)v.x;
     xi[e] = (double)v.y;
   }
-  if (K.zero_in && blockIdx.x == 0) {
+  if (K.zero_in && bid.x == 0) {
     // The (0,0) mode is the Neumann problem's singular one: its right-hand
     // side must have zero volume-weighted sum (compatibility), which the FP32
     // rounding of the forward transforms breaks; the gauge row phi_0 = 0
@@ -1328,7 +1362,7 @@ __global__ __launch_bounds__(SL == YL ? 1024 : 512) void k_tri_y(PoisK<C> K) {
     }
   zr = zRr;
   zi = zRi;
-  if (blockIdx.x == 0) {
+  if (bid.x == 0) {
     // zero volume-weighted mean of the (0,0) mode (lane 0 of block 0):
     // per-segment partial sums, then their sum in segment order
     double pr = 0.0, pi = 0.0;
@@ -1385,8 +1419,12 @@ __global__ __launch_bounds__(SL == YL ? 1024 : 512) void k_tri_y(PoisK<C> K) {
 
 // The same solve with the separator system reduced block-wide in LDS, for
 // modes of more than 64 separators (P rounded up past one wavefront).
-template <typename C, typename CO>
-__global__ __launch_bounds__(1024) void k_tri_y_blk(PoisK<C> K) {
+template <typename C, typename CO, bool G = false>
+__global__ __launch_bounds__(1024) void k_tri_y_blk(GArg<PoisK<C>, G> grp_arg_) {
+  uint3 bid, gdim;
+  const PoisK<C>& K = grp_enter<PoisK<C>, G>(grp_arg_, bid, gdim);
+  (void)bid;
+  (void)gdim;
   using RO = typename RealOf<CO>::T;
   if (gated(K)) return;
   extern __shared__ __align__(16) unsigned char smraw[];
@@ -1396,7 +1434,7 @@ __global__ __launch_bounds__(1024) void k_tri_y_blk(PoisK<C> K) {
   const int lb = threadIdx.x % TL, s = threadIdx.x / TL;
   // modes q = k ldx + p over the padded rows; padding columns are skipped
   const int64_t nm = (int64_t)g.nz * K.ldx;
-  const int64_t q = (int64_t)blockIdx.x * TL + lb;
+  const int64_t q = (int64_t)bid.x * TL + lb;
   const bool valid = q < nm && (int)(q % K.ldx) < g.nxh;
   auto at = [&](int f, int seg) -> double& { return sm[((size_t)f * P + seg) * TL + lb]; };
   const int lo = s * K.yL + (s < K.yr ? s : K.yr);
@@ -1429,7 +1467,7 @@ __global__ __launch_bounds__(1024) void k_tri_y_blk(PoisK<C> K) {
         }
       }
   }
-  if (K.zero_in && blockIdx.x == 0) {
+  if (K.zero_in && bid.x == 0) {
     // the (0,0) mode's right-hand side loses its volume-weighted mean (see
     // the wavefront form of this solve)
     double pr = 0.0, pi = 0.0;
@@ -1581,7 +1619,7 @@ __global__ __launch_bounds__(1024) void k_tri_y_blk(PoisK<C> K) {
     }
   zr = zRr;
   zi = zRi;
-  if (blockIdx.x == 0) {
+  if (bid.x == 0) {
     // zero volume-weighted mean of the (0,0) mode (lane 0 of block 0):
     // per-segment partial sums, then their sum in segment order
     double pr = 0.0, pi = 0.0;
@@ -1636,8 +1674,12 @@ __global__ __launch_bounds__(1024) void k_tri_y_blk(PoisK<C> K) {
   }
 }
 
-template <typename C>
-__global__ __launch_bounds__(256) void k_fftx_inv(PoisK<C> K) {
+template <typename C, bool G = false>
+__global__ __launch_bounds__(256) void k_fftx_inv(GArg<PoisK<C>, G> grp_arg_) {
+  uint3 bid, gdim;
+  const PoisK<C>& K = grp_enter<PoisK<C>, G>(grp_arg_, bid, gdim);
+  (void)bid;
+  (void)gdim;
   using R = typename RealOf<C>::T;
   if (gated(K)) return;
   extern __shared__ __align__(16) unsigned char smraw[];
@@ -1645,7 +1687,7 @@ __global__ __launch_bounds__(256) void k_fftx_inv(PoisK<C> K) {
   const GridView& g = K.g;
   const int nx = g.nx, nxh = g.nxh;
   const int64_t nrows = (int64_t)g.ny * g.nz;
-  const int64_t row0 = (int64_t)blockIdx.x * K.rows;
+  const int64_t row0 = (int64_t)bid.x * K.rows;
   const int nr = (int)((row0 + K.rows <= nrows) ? K.rows : nrows - row0);
   // two half spectra per complex sequence: Z = A + iB over the Hermitian
   // extension (the bins 0 and nx/2 of a real sequence are real), so that the
@@ -1807,11 +1849,9 @@ static void run_passes(Prof* pf, hipStream_t s, const GridView& g, PoisK<C> K, P
   const int xb = x256 ? (int)((nrows + 2 * X16_SC - 1) / (2 * X16_SC)) : xblocks;
   const int xb_i = x256_i ? (int)((nrows + 2 * X16_SC - 1) / (2 * X16_SC)) : xblocks_i;
   if (x256)
-    IBM_LAUNCH(pf, resid ? "pois_resid_fftx" : "pois_fftx_fwd", s,
-               (k_fftx256_fwd<C><<<xb, 32 * X16_SC, 0, s>>>(K)));
+    IBM_LAUNCH_G(pf, resid ? "pois_resid_fftx" : "pois_fftx_fwd", s, (&k_fftx256_fwd<C, true>), dim3(xb), dim3(32 * X16_SC), 0, K, k_fftx256_fwd<C><<<xb, 32 * X16_SC, 0, s>>>(K));
   else
-    IBM_LAUNCH(pf, resid ? "pois_resid_fftx" : "pois_fftx_fwd", s,
-               (k_fftx_fwd<C><<<xblocks, 256, xsh, s>>>(K)));
+    IBM_LAUNCH_G(pf, resid ? "pois_resid_fftx" : "pois_fftx_fwd", s, (&k_fftx_fwd<C, true>), dim3(xblocks), dim3(256), xsh, K, k_fftx_fwd<C><<<xblocks, 256, xsh, s>>>(K));
   if (K.mode == SRC_CHECK) return;
   if (resid) {
     K.gate = K.rmax;  // the rest of a refinement runs only if its residual is too large
@@ -1829,47 +1869,43 @@ static void run_passes(Prof* pf, hipStream_t s, const GridView& g, PoisK<C> K, P
   const unsigned z512b_i = (unsigned)zline_blocks(zline_group<CI, 8>(), (g.nxh + 7) / 8, g.ny);
   const unsigned z1kb_i = (unsigned)zline_blocks(zline_group<CI, 4>(), (g.nxh + 3) / 4, g.ny);
   if (z256)
-    IBM_LAUNCH(pf, "pois_fftz_fwd", s, (k_fftz256<C, false><<<z16grid, 16 * Z16_TC, 0, s>>>(K)));
+    IBM_LAUNCH_G(pf, "pois_fftz_fwd", s, (&k_fftz256<C, false, true>), dim3(z16grid), dim3(16 * Z16_TC), 0, K, k_fftz256<C, false><<<z16grid, 16 * Z16_TC, 0, s>>>(K));
   else if (g.nz == 512)
-    IBM_LAUNCH(pf, "pois_fftz_fwd", s, (k_fftz4s<C, false, 2><<<z512b, 256, 0, s>>>(K)));
+    IBM_LAUNCH_G(pf, "pois_fftz_fwd", s, (&k_fftz4s<C, false, 2, true>), dim3(z512b), dim3(256), 0, K, k_fftz4s<C, false, 2><<<z512b, 256, 0, s>>>(K));
   else if (g.nz == 1024)
-    IBM_LAUNCH(pf, "pois_fftz_fwd", s, (k_fftz4s<C, false, 4><<<z1kb, 256, 0, s>>>(K)));
+    IBM_LAUNCH_G(pf, "pois_fftz_fwd", s, (&k_fftz4s<C, false, 4, true>), dim3(z1kb), dim3(256), 0, K, k_fftz4s<C, false, 4><<<z1kb, 256, 0, s>>>(K));
   else
-    IBM_LAUNCH(pf, "pois_fftz_fwd", s, (k_fftz<C, false><<<zgrid, 256, zsh, s>>>(K)));
+    IBM_LAUNCH_G(pf, "pois_fftz_fwd", s, (&k_fftz<C, false, true>), dim3(zgrid), dim3(256), zsh, K, k_fftz<C, false><<<zgrid, 256, zsh, s>>>(K));
   if (ywave && sl == 2 * YL && K.yr == 0 && K.yL == sl)
-    IBM_LAUNCH(pf, "pois_tri_y", s,
-               (k_tri_y<C, true, CI, 2 * YL><<<ywblocks, K.ytl * K.yPP, ysh, s>>>(K)));
+    IBM_LAUNCH_G(pf, "pois_tri_y", s, (&k_tri_y<C, true, CI, 2 * YL, true>), dim3(ywblocks), dim3(K.ytl * K.yPP), ysh, K, k_tri_y<C, true, CI, 2 * YL><<<ywblocks, K.ytl * K.yPP, ysh, s>>>(K));
   else if (ywave && sl == 2 * YL)
-    IBM_LAUNCH(pf, "pois_tri_y", s,
-               (k_tri_y<C, false, CI, 2 * YL><<<ywblocks, K.ytl * K.yPP, ysh, s>>>(K)));
+    IBM_LAUNCH_G(pf, "pois_tri_y", s, (&k_tri_y<C, false, CI, 2 * YL, true>), dim3(ywblocks), dim3(K.ytl * K.yPP), ysh, K, k_tri_y<C, false, CI, 2 * YL><<<ywblocks, K.ytl * K.yPP, ysh, s>>>(K));
   else if (ywave && K.yr == 0 && K.yL == YL)
-    IBM_LAUNCH(pf, "pois_tri_y", s,
-               (k_tri_y<C, true, CI, YL><<<ywblocks, K.ytl * K.yPP, ysh, s>>>(K)));
+    IBM_LAUNCH_G(pf, "pois_tri_y", s, (&k_tri_y<C, true, CI, YL, true>), dim3(ywblocks), dim3(K.ytl * K.yPP), ysh, K, k_tri_y<C, true, CI, YL><<<ywblocks, K.ytl * K.yPP, ysh, s>>>(K));
   else if (ywave)
-    IBM_LAUNCH(pf, "pois_tri_y", s,
-               (k_tri_y<C, false, CI, YL><<<ywblocks, K.ytl * K.yPP, ysh, s>>>(K)));
+    IBM_LAUNCH_G(pf, "pois_tri_y", s, (&k_tri_y<C, false, CI, YL, true>), dim3(ywblocks), dim3(K.ytl * K.yPP), ysh, K, k_tri_y<C, false, CI, YL><<<ywblocks, K.ytl * K.yPP, ysh, s>>>(K));
   else
-    IBM_LAUNCH(pf, "pois_tri_y", s, (k_tri_y_blk<C, CI><<<yblocks, K.ytl * K.yP, ysh, s>>>(K)));
+    IBM_LAUNCH_G(pf, "pois_tri_y", s, (&k_tri_y_blk<C, CI, true>), dim3(yblocks), dim3(K.ytl * K.yP), ysh, K, k_tri_y_blk<C, CI><<<yblocks, K.ytl * K.yP, ysh, s>>>(K));
   if (z256)
-    IBM_LAUNCH(pf, "pois_fftz_inv", s, (k_fftz256<CI, true><<<z16grid, 16 * Z16_TC, 0, s>>>(KI)));
+    IBM_LAUNCH_G(pf, "pois_fftz_inv", s, (&k_fftz256<CI, true, true>), dim3(z16grid), dim3(16 * Z16_TC), 0, KI, k_fftz256<CI, true><<<z16grid, 16 * Z16_TC, 0, s>>>(KI));
   else if (g.nz == 512)
-    IBM_LAUNCH(pf, "pois_fftz_inv", s, (k_fftz4s<CI, true, 2><<<z512b_i, 256, 0, s>>>(KI)));
+    IBM_LAUNCH_G(pf, "pois_fftz_inv", s, (&k_fftz4s<CI, true, 2, true>), dim3(z512b_i), dim3(256), 0, KI, k_fftz4s<CI, true, 2><<<z512b_i, 256, 0, s>>>(KI));
   else if (g.nz == 1024)
-    IBM_LAUNCH(pf, "pois_fftz_inv", s, (k_fftz4s<CI, true, 4><<<z1kb_i, 256, 0, s>>>(KI)));
+    IBM_LAUNCH_G(pf, "pois_fftz_inv", s, (&k_fftz4s<CI, true, 4, true>), dim3(z1kb_i), dim3(256), 0, KI, k_fftz4s<CI, true, 4><<<z1kb_i, 256, 0, s>>>(KI));
   else
-    IBM_LAUNCH(pf, "pois_fftz_inv", s, (k_fftz<CI, true><<<zgrid_i, 256, zsh_i, s>>>(KI)));
+    IBM_LAUNCH_G(pf, "pois_fftz_inv", s, (&k_fftz<CI, true, true>), dim3(zgrid_i), dim3(256), zsh_i, KI, k_fftz<CI, true><<<zgrid_i, 256, zsh_i, s>>>(KI));
   // lengths 512 and 1024: one sequence (two rows) per 32 or 64 lanes, 2 x
   // 4096/nx rows per block of 256 threads
   const int rpb4 = (g.nx == 512 || g.nx == 1024) ? 2 * (4096 / g.nx) : 1;
   const int xb4_i = (int)((nrows + rpb4 - 1) / rpb4);
   if (x256_i)
-    IBM_LAUNCH(pf, "pois_fftx_inv", s, (k_fftx256_inv<CI><<<xb_i, 32 * X16_SC, 0, s>>>(KI)));
+    IBM_LAUNCH_G(pf, "pois_fftx_inv", s, (&k_fftx256_inv<CI, true>), dim3(xb_i), dim3(32 * X16_SC), 0, KI, k_fftx256_inv<CI><<<xb_i, 32 * X16_SC, 0, s>>>(KI));
   else if (g.nx == 1024)
-    IBM_LAUNCH(pf, "pois_fftx_inv", s, (k_fftx4s_inv<CI, 4><<<xb4_i, 256, 0, s>>>(KI)));
+    IBM_LAUNCH_G(pf, "pois_fftx_inv", s, (&k_fftx4s_inv<CI, 4, true>), dim3(xb4_i), dim3(256), 0, KI, k_fftx4s_inv<CI, 4><<<xb4_i, 256, 0, s>>>(KI));
   else if (g.nx == 512)
-    IBM_LAUNCH(pf, "pois_fftx_inv", s, (k_fftx4s_inv<CI, 2><<<xb4_i, 256, 0, s>>>(KI)));
+    IBM_LAUNCH_G(pf, "pois_fftx_inv", s, (&k_fftx4s_inv<CI, 2, true>), dim3(xb4_i), dim3(256), 0, KI, k_fftx4s_inv<CI, 2><<<xb4_i, 256, 0, s>>>(KI));
   else
-    IBM_LAUNCH(pf, "pois_fftx_inv", s, (k_fftx_inv<CI><<<xblocks_i, 256, xsh_i, s>>>(KI)));
+    IBM_LAUNCH_G(pf, "pois_fftx_inv", s, (&k_fftx_inv<CI, true>), dim3(xblocks_i), dim3(256), xsh_i, KI, k_fftx_inv<CI><<<xblocks_i, 256, xsh_i, s>>>(KI));
 }
 
 // the inverse passes' view of a solve: the fields the inverse z and x

@@ -166,8 +166,12 @@ enum : int {
   RHS_HOUT = 4,  // H is written (all three components)
 };
 
-template <typename T, int F>
-__global__ __launch_bounds__(RTX * RTZ) __attribute__((amdgpu_waves_per_eu(4))) void k_rhs(RhsK<T> K) {
+template <typename T, int F, bool G = false>
+__global__ __launch_bounds__(RTX * RTZ) __attribute__((amdgpu_waves_per_eu(4))) void k_rhs(GArg<RhsK<T>, G> grp_arg_) {
+  uint3 bid, gdim;
+  const RhsK<T>& K = grp_enter<RhsK<T>, G>(grp_arg_, bid, gdim);
+  (void)bid;
+  (void)gdim;
   constexpr bool FULL = F & RHS_FULL, HPREV = F & RHS_HPREV, HOUT = F & RHS_HOUT;
   extern __shared__ double lds[];
   const GridView& g = K.g;
@@ -175,7 +179,7 @@ __global__ __launch_bounds__(RTX * RTZ) __attribute__((amdgpu_waves_per_eu(4))) 
   const int nbx = (g.nx + RTX - 1) / RTX, nbz = (g.nz + RTZ - 1) / RTZ;
   const int jc = K.jc;
   const int nchunk = (g.ny + jc - 1) / jc;
-  const int64_t t = xcd_tile(blockIdx.x, (int64_t)nbx * nbz * nchunk);
+  const int64_t t = xcd_tile(bid.x, (int64_t)nbx * nbz * nchunk);
   const int i0 = (int)(t % nbx) * RTX;
   const int k0 = (int)((t / nbx) % nbz) * RTZ;
   const int j0 = (int)(t / ((int64_t)nbx * nbz)) * jc;
@@ -437,7 +441,8 @@ static void run_rhs(Prof* pf, hipStream_t s, const GridView& g, const RhsArgs& a
   switch (f) {
 #define RHS_CASE(F_)                                                              \
   case F_:                                                                        \
-    IBM_LAUNCH(pf, "rhs", s, k_rhs<T, F_><<<(unsigned)blocks, RTX * RTZ, shm, s>>>(K)); \
+    IBM_LAUNCH_G(pf, "rhs", s, (&k_rhs<T, F_, true>), dim3((unsigned)blocks), dim3(RTX * RTZ), shm, \
+                 K, k_rhs<T, F_><<<(unsigned)blocks, RTX * RTZ, shm, s>>>(K));           \
     break;
     RHS_CASE(0) RHS_CASE(1) RHS_CASE(2) RHS_CASE(3)
     RHS_CASE(4) RHS_CASE(5) RHS_CASE(6) RHS_CASE(7)

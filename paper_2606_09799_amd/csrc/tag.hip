@@ -32,9 +32,17 @@ struct TagK {
   uint32_t* flags;
 };
 
-__global__ __launch_bounds__(64) void k_tag_pairs(TagK a) {
-  const int t = blockIdx.x;
-  const int c = blockIdx.y;
+// One wavefront per (triangle, lattice), four triangles per block (no block
+// barrier: each wavefront works alone).
+constexpr int TAG_TPB = 4;
+template <bool G = false>
+__global__ __launch_bounds__(64 * TAG_TPB) void k_tag_pairs(GArg<TagK, G> grp_arg_) {
+  uint3 bid, gdim;
+  const TagK& a = grp_enter<TagK, G>(grp_arg_, bid, gdim);
+  (void)gdim;
+  const int lane = (int)(threadIdx.x & 63);
+  const int t = (int)bid.x * TAG_TPB + (int)(threadIdx.x >> 6);
+  const int c = bid.y;
   if (t >= a.ntri) return;
   const GridView& g = a.g;
   double A[3], B[3], C[3];
@@ -49,7 +57,7 @@ __global__ __launch_bounds__(64) void k_tag_pairs(TagK a) {
   // the one-layer fresh-cell assumption (Sec. 3.1): over dt no vertex may
   // move more than half the local spacing along an axis (the y spacing of the
   // cell the vertex lies in)
-  if (a.dt > 0.0 && a.pass == 0 && c == 0 && threadIdx.x == 0) {
+  if (a.dt > 0.0 && a.pass == 0 && c == 0 && lane == 0) {
     bool over = false;
     for (int q = 0; q < 3; ++q) {
       const double* U = vel + 3 * vid[q];
@@ -65,14 +73,14 @@ __global__ __launch_bounds__(64) void k_tag_pairs(TagK a) {
   const Box bx = candidate_box(g, L, lo, hi);
   const int ni = bx.i1 - bx.i0 + 1, ne = bx.e1 - bx.e0 + 1, nk = bx.k1 - bx.k0 + 1;
   if (ni + 1 >= g.nx || nk + 1 >= g.nz) {  // a node would have two images
-    if (threadIdx.x == 0) atomicOr(a.flags, FLAG_GEOM);
+    if (lane == 0) atomicOr(a.flags, FLAG_GEOM);
     return;
   }
   const int64_t total = (int64_t)ni * ne * nk;
   uint32_t* mask = a.mask[c];
   u64* best_d = a.best_d[c];
   int32_t* best_t = a.best_t[c];
-  for (int64_t q = threadIdx.x; q < total; q += blockDim.x) {
+  for (int64_t q = lane; q < total; q += 64) {
     const int ii = bx.i0 + (int)(q % ni);
     const int64_t r = q / ni;
     const int ee = bx.e0 + (int)(r % ne);
@@ -146,26 +154,36 @@ struct CompactSet {
   uint32_t* flags;
 };
 
-__global__ __launch_bounds__(CT) void k_count(CompactSet S) {
+template <bool G = false>
+__global__ __launch_bounds__(CT) void k_count(GArg<CompactSet, G> grp_arg_) {
+  uint3 bid, gdim;
+  const CompactSet& S = grp_enter<CompactSet, G>(grp_arg_, bid, gdim);
+  (void)bid;
+  (void)gdim;
   __shared__ int64_t sh[CT];
-  const int l = blockIdx.y;
-  if ((int64_t)blockIdx.x >= S.nb[l]) return;  // block-uniform
+  const int l = bid.y;
+  if ((int64_t)bid.x >= S.nb[l]) return;  // block-uniform
   const uint32_t* mask = S.mask[l];
   const int64_t nwords = S.nwords[l];
-  const int64_t base = (int64_t)blockIdx.x * CWB + (int64_t)threadIdx.x * CWT;
+  const int64_t base = (int64_t)bid.x * CWB + (int64_t)threadIdx.x * CWT;
   int64_t c = 0;
   for (int q = 0; q < CWT; ++q)
     if (base + q < nwords) c += __popc(mask[base + q]);
   int64_t tot;
   block_excl_scan(c, sh, &tot);
-  if (threadIdx.x == 0) S.bsum[l][blockIdx.x] = tot;
+  if (threadIdx.x == 0) S.bsum[l][bid.x] = tot;
 }
 
 // exclusive scan of a list's nb block sums in place (one block per list);
 // total -> its count
-__global__ __launch_bounds__(1024) void k_scan(CompactSet S) {
+template <bool G = false>
+__global__ __launch_bounds__(1024) void k_scan(GArg<CompactSet, G> grp_arg_) {
+  uint3 bid, gdim;
+  const CompactSet& S = grp_enter<CompactSet, G>(grp_arg_, bid, gdim);
+  (void)bid;
+  (void)gdim;
   __shared__ int64_t sh[1024];
-  const int l = blockIdx.x;
+  const int l = bid.x;
   int64_t* bsum = S.bsum[l];
   const int64_t nb = S.nb[l];
   const int t = threadIdx.x;
@@ -190,10 +208,15 @@ __global__ __launch_bounds__(1024) void k_scan(CompactSet S) {
   if (t == 1023) *S.count[l] = sh[1023];
 }
 
-__global__ __launch_bounds__(CT) void k_emit(CompactSet S) {
+template <bool G = false>
+__global__ __launch_bounds__(CT) void k_emit(GArg<CompactSet, G> grp_arg_) {
+  uint3 bid, gdim;
+  const CompactSet& S = grp_enter<CompactSet, G>(grp_arg_, bid, gdim);
+  (void)bid;
+  (void)gdim;
   __shared__ int64_t sh[CT];
-  const int l = blockIdx.y;
-  if ((int64_t)blockIdx.x >= S.nb[l]) return;  // block-uniform
+  const int l = bid.y;
+  if ((int64_t)bid.x >= S.nb[l]) return;  // block-uniform
   const uint32_t* mask = S.mask[l];
   const int64_t nwords = S.nwords[l];
   int64_t* idx = S.idx[l];
@@ -201,7 +224,7 @@ __global__ __launch_bounds__(CT) void k_emit(CompactSet S) {
   u64* best_d = S.best_d[l];
   int32_t* best_t = S.best_t[l];
   const int64_t cap = S.cap;
-  const int64_t base = (int64_t)blockIdx.x * CWB + (int64_t)threadIdx.x * CWT;
+  const int64_t base = (int64_t)bid.x * CWB + (int64_t)threadIdx.x * CWT;
   uint32_t w[CWT];
   int64_t c = 0;
   for (int q = 0; q < CWT; ++q) {
@@ -209,7 +232,7 @@ __global__ __launch_bounds__(CT) void k_emit(CompactSet S) {
     c += __popc(w[q]);
   }
   int64_t tot;
-  int64_t pos = S.bsum[l][blockIdx.x] + block_excl_scan(c, sh, &tot);
+  int64_t pos = S.bsum[l][bid.x] + block_excl_scan(c, sh, &tot);
   bool over = false;
   for (int q = 0; q < CWT; ++q) {
     uint32_t m = w[q];
@@ -234,27 +257,68 @@ __global__ __launch_bounds__(CT) void k_emit(CompactSet S) {
 }
 
 // zero up to four bitmaps in one launch (array blockIdx.y)
-__global__ __launch_bounds__(256) void k_zero_masks(uint32_t* m0, int64_t n0, uint32_t* m1,
-                                                    int64_t n1, uint32_t* m2, int64_t n2,
-                                                    uint32_t* m3, int64_t n3) {
-  uint32_t* m = blockIdx.y == 0 ? m0 : (blockIdx.y == 1 ? m1 : (blockIdx.y == 2 ? m2 : m3));
-  const int64_t n = blockIdx.y == 0 ? n0 : (blockIdx.y == 1 ? n1 : (blockIdx.y == 2 ? n2 : n3));
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n;
-       i += (int64_t)gridDim.x * blockDim.x)
+struct ZeroMasksK {
+  uint32_t* m0;
+  int64_t n0;
+  uint32_t* m1;
+  int64_t n1;
+  uint32_t* m2;
+  int64_t n2;
+  uint32_t* m3;
+  int64_t n3;
+};
+template <bool G = false>
+__global__ __launch_bounds__(256) void k_zero_masks(GArg<ZeroMasksK, G> grp_arg_) {
+  uint3 bid, gdim;
+  const ZeroMasksK& P_ = grp_enter<ZeroMasksK, G>(grp_arg_, bid, gdim);
+  (void)bid;
+  (void)gdim;
+  uint32_t* m0 = P_.m0;
+  int64_t n0 = P_.n0;
+  uint32_t* m1 = P_.m1;
+  int64_t n1 = P_.n1;
+  uint32_t* m2 = P_.m2;
+  int64_t n2 = P_.n2;
+  uint32_t* m3 = P_.m3;
+  int64_t n3 = P_.n3;
+  uint32_t* m = bid.y == 0 ? m0 : (bid.y == 1 ? m1 : (bid.y == 2 ? m2 : m3));
+  const int64_t n = bid.y == 0 ? n0 : (bid.y == 1 ? n1 : (bid.y == 2 ? n2 : n3));
+  for (int64_t i = (int64_t)bid.x * blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gdim.x * blockDim.x)
     m[i] = 0u;
 }
 
 // C_B: cells all six of whose faces carry forcing nodes (checked from the
 // u list: the west face u(i,j,k) of cell (i,j,k)).
-__global__ void k_cells(GridView g, const int64_t* __restrict__ idx_u,
-                        const int64_t* __restrict__ count, int64_t cap,
-                        const uint32_t* __restrict__ mu, const uint32_t* __restrict__ mv,
-                        const uint32_t* __restrict__ mw, uint32_t* __restrict__ cb_mask) {
+struct CellsK {
+  GridView g;
+  const int64_t* idx_u;
+  const int64_t* count;
+  int64_t cap;
+  const uint32_t* mu;
+  const uint32_t* mv;
+  const uint32_t* mw;
+  uint32_t* cb_mask;
+};
+template <bool G = false>
+__global__ void k_cells(GArg<CellsK, G> grp_arg_) {
+  uint3 bid, gdim;
+  const CellsK& P_ = grp_enter<CellsK, G>(grp_arg_, bid, gdim);
+  (void)bid;
+  (void)gdim;
+  GridView g = P_.g;
+  const int64_t* __restrict__ idx_u = P_.idx_u;
+  const int64_t* __restrict__ count = P_.count;
+  int64_t cap = P_.cap;
+  const uint32_t* __restrict__ mu = P_.mu;
+  const uint32_t* __restrict__ mv = P_.mv;
+  const uint32_t* __restrict__ mw = P_.mw;
+  uint32_t* __restrict__ cb_mask = P_.cb_mask;
   int64_t n = count[0];
   if (n > cap) n = cap;
   const int64_t plane = (int64_t)g.nz * g.nx;
-  for (int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; f < n;
-       f += (int64_t)gridDim.x * blockDim.x) {
+  for (int64_t f = (int64_t)bid.x * blockDim.x + threadIdx.x; f < n;
+       f += (int64_t)gdim.x * blockDim.x) {
     const int64_t node = idx_u[f];
     const int i = (int)(node % g.nx);
     const int k = (int)((node / g.nx) % g.nz);
@@ -277,9 +341,12 @@ static void compact(Prof* pf, hipStream_t s, CompactSet S, int nl) {
     if (S.nb[l] > nbmax) nbmax = S.nb[l];
   }
   const dim3 grid((unsigned)nbmax, (unsigned)nl);
-  IBM_LAUNCH(pf, "tag_count", s, k_count<<<grid, CT, 0, s>>>(S));
-  IBM_LAUNCH(pf, "tag_scan", s, k_scan<<<nl, 1024, 0, s>>>(S));
-  IBM_LAUNCH(pf, "tag_emit", s, k_emit<<<grid, CT, 0, s>>>(S));
+  IBM_LAUNCH_G(pf, "tag_count", s, (&k_count<true>), grid, dim3(CT), 0, S,
+               k_count<<<grid, CT, 0, s>>>(S));
+  IBM_LAUNCH_G(pf, "tag_scan", s, (&k_scan<true>), dim3(nl), dim3(1024), 0, S,
+               k_scan<<<nl, 1024, 0, s>>>(S));
+  IBM_LAUNCH_G(pf, "tag_emit", s, (&k_emit<true>), grid, dim3(CT), 0, S,
+               k_emit<<<grid, CT, 0, s>>>(S));
 }
 
 void launch_tag(Prof* pf, hipStream_t s, const GridView& g, const BodyDev* bodies, int nbody,
@@ -289,10 +356,11 @@ void launch_tag(Prof* pf, hipStream_t s, const GridView& g, const BodyDev* bodie
     for (int c = 0; c < 3; ++c) nmax = tb.nwords[c] > nmax ? tb.nwords[c] : nmax;
     int64_t blocks = (nmax + 255) / 256;
     if (blocks > 4096) blocks = 4096;
-    IBM_LAUNCH(pf, "fill_u32", s,
-               (k_zero_masks<<<dim3((unsigned)blocks, 4), 256, 0, s>>>(
-                   tb.mask[0], tb.nwords[0], tb.mask[1], tb.nwords[1], tb.mask[2], tb.nwords[2],
-                   tb.cb_mask, tb.nwords_cb)));
+    const ZeroMasksK Z{tb.mask[0], tb.nwords[0], tb.mask[1], tb.nwords[1],
+                       tb.mask[2], tb.nwords[2], tb.cb_mask, tb.nwords_cb};
+    const dim3 zg((unsigned)blocks, 4);
+    IBM_LAUNCH_G(pf, "fill_u32", s, (&k_zero_masks<true>), zg, dim3(256), 0, Z,
+                 k_zero_masks<<<zg, 256, 0, s>>>(Z));
   }
   if (ntri > 0) {
     TagK a;
@@ -307,11 +375,13 @@ void launch_tag(Prof* pf, hipStream_t s, const GridView& g, const BodyDev* bodie
     }
     a.flags = flags;
     a.dt = dt;
-    dim3 grid(ntri, 3);
+    dim3 grid((ntri + TAG_TPB - 1) / TAG_TPB, 3);
     a.pass = 0;
-    IBM_LAUNCH(pf, "tag_pairs", s, k_tag_pairs<<<grid, 64, 0, s>>>(a));
+    IBM_LAUNCH_G(pf, "tag_pairs", s, (&k_tag_pairs<true>), grid, dim3(64 * TAG_TPB), 0, a,
+                 k_tag_pairs<<<grid, 64 * TAG_TPB, 0, s>>>(a));
     a.pass = 1;
-    IBM_LAUNCH(pf, "tag_pairs", s, k_tag_pairs<<<grid, 64, 0, s>>>(a));
+    IBM_LAUNCH_G(pf, "tag_pairs", s, (&k_tag_pairs<true>), grid, dim3(64 * TAG_TPB), 0, a,
+                 k_tag_pairs<<<grid, 64 * TAG_TPB, 0, s>>>(a));
   }
   // the three forcing lists in one pass; each list has its own block sums
   // (tb.bsum_stride values apart)
@@ -329,9 +399,9 @@ void launch_tag(Prof* pf, hipStream_t s, const GridView& g, const BodyDev* bodie
     S.count[c] = tb.count + c;
   }
   compact(pf, s, S, 3);
-  IBM_LAUNCH(pf, "tag_cells", s,
-             k_cells<<<1024, 256, 0, s>>>(g, tb.idx[0], tb.count, tb.cap, tb.mask[0], tb.mask[1],
-                                          tb.mask[2], tb.cb_mask));
+  const CellsK CK{g, tb.idx[0], tb.count, tb.cap, tb.mask[0], tb.mask[1], tb.mask[2], tb.cb_mask};
+  IBM_LAUNCH_G(pf, "tag_cells", s, (&k_cells<true>), dim3(1024), dim3(256), 0, CK,
+               k_cells<<<1024, 256, 0, s>>>(CK));
   CompactSet B{};
   B.cap = tb.cap;
   B.flags = flags;

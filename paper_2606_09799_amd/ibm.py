@@ -144,8 +144,8 @@ EXPORTS = ("ibm_create", "ibm_destroy", "ibm_set_stream", "ibm_body_rigid", "ibm
            "ibm_noslip_error", "ibm_pressure_cb", "ibm_divergence", "ibm_loads",
            "ibm_set_volume_force", "ibm_body_rigid_dev", "ibm_rigid_advance")
 COEF_STRIDE = 18
-BATCH_SERIAL, BATCH_STREAMS, BATCH_GRAPH, BATCH_PLAN = 0, 1, 2, 3
-_MODE_NAMES = {BATCH_STREAMS: "streams", BATCH_GRAPH: "graph"}
+BATCH_SERIAL, BATCH_STREAMS, BATCH_GRAPH, BATCH_PLAN, BATCH_GROUPED = 0, 1, 2, 3, 4
+_MODE_NAMES = {BATCH_STREAMS: "streams", BATCH_GRAPH: "graph", BATCH_GROUPED: "grouped"}
 MOTION_RIGID, MOTION_DEFORM = 0, 1
 
 
@@ -588,7 +588,7 @@ class Batch:
         return self._plan_dict(best), [self._plan_dict(table[k]) for k in range(ntried.value)]
 
     def set_plan(self, mode="graph", streams=None, rhs_planes=16):
-        m = {"graph": BATCH_GRAPH, "streams": BATCH_STREAMS}[mode]
+        m = {"graph": BATCH_GRAPH, "streams": BATCH_STREAMS, "grouped": BATCH_GROUPED}[mode]
         p = IbmBatchPlan(m, int(streams or self.n), int(rhs_planes), 0, 0.0)
         _ok(_batch_set_plan(self.handle, ctypes.byref(p)), "ibm_batch_set_plan")
 

@@ -1,11 +1,13 @@
 """The batched form (many simulations advanced together) through the C-ABI.
 
 Bars: every mode (serial, concurrent streams, one captured HIP graph
-replayed each step) gives results bit-identical to ibm_step run on each
-simulation alone (the same kernels in the same order per simulation); every
-replay of the graph is checked against the eager streams run, with other
-device work and host synchronisations between the replays; one simulation
-of the batch agrees with the FP64 oracle within 1e-10 relative."""
+replayed each step, grouped launches) gives results bit-identical to
+ibm_step run on each simulation alone (the same kernels in the same order
+per simulation; a grouped launch runs each simulation's blocks with its own
+argument record); every replay of the graphs is checked against the eager
+streams run, with other device work and host synchronisations between the
+replays; one simulation of the batch agrees with the FP64 oracle within
+1e-10 relative."""
 import numpy as np
 import pytest
 import torch
@@ -81,7 +83,7 @@ def test_batch_modes_match_each_simulation_alone():
     assert len({wl.bodies[0].kind for wl in wls}) == 2  # rigid and deforming bodies
     steps = 3
     alone = [_run_alone(wl, steps) for wl in wls]
-    for mode in (ibm.BATCH_SERIAL, ibm.BATCH_STREAMS, ibm.BATCH_GRAPH):
+    for mode in (ibm.BATCH_SERIAL, ibm.BATCH_STREAMS, ibm.BATCH_GRAPH, ibm.BATCH_GROUPED):
         got = _run_batch(wls, steps, mode)
         for s in range(len(wls)):
             for q in range(4):
@@ -95,19 +97,22 @@ def test_graph_replays_match_eager_streams():
     wls = _small_sims(4)
     eager = [_device_sim(wl) for wl in wls]
     graph = [_device_sim(wl) for wl in wls]
-    be, bg = ibm.Batch(eager), ibm.Batch(graph)
+    grouped = [_device_sim(wl) for wl in wls]
+    be, bg, bq = ibm.Batch(eager), ibm.Batch(graph), ibm.Batch(grouped)
     dt = wls[0].dt
     for k in range(5):
         coef = [wl.bodies[0].coef(k * dt) for wl in wls]
         be.step(coef, dt, ibm.BATCH_STREAMS)
         bg.step(coef, dt, ibm.BATCH_GRAPH)
+        bq.step(coef, dt, ibm.BATCH_GROUPED)
         torch.cuda.synchronize()
         junk = torch.arange(1 << 16, device=DEV, dtype=torch.float64).sum().item()
         assert junk > 0
         for s in range(len(wls)):
             for key in ("u", "v", "w", "p"):
                 assert torch.equal(eager[s][key], graph[s][key]), (k, s, key)
-    assert be.check() == 0 and bg.check() == 0
+                assert torch.equal(eager[s][key], grouped[s][key]), (k, s, key)
+    assert be.check() == 0 and bg.check() == 0 and bq.check() == 0
 
 
 def test_batch_simulation_against_oracle():
@@ -153,7 +158,8 @@ def test_autotuner_keeps_states_and_results():
             assert np.array_equal(x, y)
     batch.close()
     for plan in ({"mode": "streams", "streams": 1, "rhs_planes": 1},
-                 {"mode": "graph", "streams": 2, "rhs_planes": 5}):
+                 {"mode": "graph", "streams": 2, "rhs_planes": 5},
+                 {"mode": "grouped", "streams": 1, "rhs_planes": 3}):
         sims = [_device_sim(wl) for wl in wls]
         batch = ibm.Batch(sims)
         batch.set_plan(**plan)
@@ -207,3 +213,34 @@ def test_autotuner_takes_caller_scratch_and_allocates_nothing():
         for x, y in zip(a, b):
             assert np.array_equal(x, y)
     ref.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_grouped_launches_on_uneven_grids(precision):
+    """Twelve simulations of the batched workload's uneven sizes (several
+    kernel variants per launch, rigid and deforming bodies), in FP64 and in
+    the mixed form: the grouped launches give the eager streams' results bit
+    for bit over three steps."""
+    from paper_2606_09799_amd import ibm
+    wls = _small_sims(12, max_cells=400_000)
+    pdt = torch.float64 if precision == "fp64" else torch.float32
+
+    def sims():
+        out = [_device_sim(wl) for wl in wls]
+        for d in out:
+            d["p"] = d["p"].to(pdt)
+        return out
+    a, b = sims(), sims()
+    ba = ibm.Batch(a, precision=precision)
+    bb = ibm.Batch(b, precision=precision)
+    dt = wls[0].dt
+    for k in range(3):
+        coef = [wl.bodies[0].coef(k * dt) for wl in wls]
+        ba.step(coef, dt, ibm.BATCH_STREAMS)
+        bb.step(coef, dt, ibm.BATCH_GROUPED)
+    assert ba.check() == 0 and bb.check() == 0
+    for s in range(len(wls)):
+        for key in ("u", "v", "w", "p"):
+            assert torch.equal(a[s][key], b[s][key]), (s, key)
+    ba.close()
+    bb.close()
