@@ -344,8 +344,7 @@ def run_workload(args, wl, forms, dev):
 def run_batched(args, dev, nsim, form):
     """Times the batched workload (nsim simulations of different sizes, one
     body each) in each execution mode (serial, streams, graph, grouped
-    launches); with --batch-tune also autotunes the plan (stream groups, RHS
-    tile, graph or streams) and times the tuned plan."""
+    launches); the best mode is the form's value."""
     import numpy as np
     import torch
     import workloads
@@ -393,28 +392,7 @@ def run_batched(args, dev, nsim, form):
         el = time.perf_counter() - t0
         out[name] = (cells * 2 * args.steps / el, el / args.steps * 1e3)
         progress(f"batched {form} {name}: {el / args.steps * 1e3:.3f} ms per step")
-    tune = None
-    if args.batch_tune:
-        progress(f"batched {form}: autotuning the plan")
-        t0 = time.perf_counter()
-        best, tried = batch.tune(coefs(), dt, steps=3)
-        tune_s = time.perf_counter() - t0
-        progress(f"batched {form}: tuned plan {best} in {tune_s:.1f} s")
-        for _ in range(args.warmup):
-            batch.step(coefs(), dt, ibm.BATCH_PLAN)
-            k += 1
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        for _ in range(args.steps):
-            batch.step(coefs(), dt, ibm.BATCH_PLAN)
-            k += 1
-        torch.cuda.synchronize()
-        el = time.perf_counter() - t0
-        out["tuned"] = (cells * 2 * args.steps / el, el / args.steps * 1e3)
-        progress(f"batched {form} tuned: {el / args.steps * 1e3:.3f} ms per step")
-        tune = {"plan": best, "tune_seconds": round(tune_s, 2),
-                "tried": [{k2: (round(v, 3) if isinstance(v, float) else v)
-                           for k2, v in pl.items()} for pl in tried]}
+    tune = None  # the library's autotuner is switched off
     flags = batch.check()
     if flags:
         print(f"bench.py: device flags {flags} after the batched {form} run", file=sys.stderr)
@@ -452,9 +430,7 @@ def main():
     ap.add_argument("--batch-forms", default="fp64,mixed")
     ap.add_argument("--batch-modes", default="serial,streams,graph,grouped",
                     help="batched execution modes to time")
-    ap.add_argument("--batch-tune", action="store_true",
-                    help="also run the plan autotuner and time its plan (off by default: a "
-                         "run of it ended in a GPU fault whose cause is not known)")
+
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-ref-mib", type=int, default=0,
                     help="also run a plain device copy of this size (PMC scale reference)")

@@ -474,7 +474,10 @@ typedef struct {
  * range. */
 int ibm_batch_set_plan(ibm_batch* b, const ibm_batch_plan* plan);
 int ibm_batch_get_plan(ibm_batch* b, ibm_batch_plan* plan);
-/* Autotuner: times candidate plans on this batch's own simulations (a
+/* Autotuner: SWITCHED OFF, returns IBM_EINVAL (three runs of it ended in a
+ * GPU fault or an abort whose cause is not found; set plans with
+ * ibm_batch_set_plan).  When enabled it times candidate plans on this
+ * batch's own simulations (a
  * coordinate search over streams in {1, 2, 4, ..., nsim}, then rhs_planes in
  * {16, 48, 8, 4}, then graph vs eager streams; the grouped form is not among
  * its candidates), `steps` timed steps each after

@@ -917,7 +917,7 @@ void k_line_col_reg(GArg<LineK<T>, G> grp_arg_) {
 // common path keeps few registers (two blocks of 1024 threads per CU for
 // the 32-row FP32 z sweep).
 template <typename T, int MODE, int SL, int TL, bool G = false>
-__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(SL == 12 ? 5 : (SL == 32 ? 8 : 1))))
+__global__ __launch_bounds__(1024) __attribute__((amdgpu_waves_per_eu(SL == 12 ? 5 : ((SL == 32 || SL == 24) ? 8 : 1))))
 void k_line_col(GArg<LineK<T>, G> grp_arg_) {
   uint3 bid, gdim;
   const LineK<T>& K = grp_enter<LineK<T>, G>(grp_arg_, bid, gdim);
@@ -964,10 +964,12 @@ void k_line_col(GArg<LineK<T>, G> grp_arg_) {
   const int lo = s * SL;
   constexpr int m = SL - 1;
   T dd[SL];
-  // y sweep: the velocity is prefetched over the last barrier
-  constexpr bool UPRE = MODE == 2;
+  // y sweep: the velocity of the first NPRE rows is prefetched over the last
+  // barrier, the rest is read at the store
+  constexpr int NPRE = (MODE == 2) ? (SL >= 24 ? SL / 2 : SL) : 0;
+  constexpr bool UPRE = NPRE > 0;
   constexpr int RC = 4;  // rows per memory round trip on the rare path
-  double uu[UPRE ? SL : 1];
+  double uu[UPRE ? NPRE : 1];
   T dz = 0, az = 0, bz = 1, cz = 0;
   T a0 = 0, c0 = 0, d0 = 0, ahl = 0, chl = 0, dhl = 0;
   // forcing rows: any among the segment's interior rows (then the rare
@@ -996,7 +998,7 @@ void k_line_col(GArg<LineK<T>, G> grp_arg_) {
   auto roff = [&](int e) -> uint32_t { return (uint32_t)e * rstride * (uint32_t)sizeof(T); };
   const uint32_t vlb = vline * (uint32_t)sizeof(T);
   auto u_at = [&](int e) -> double {
-    return UPRE ? uu[UPRE ? e : 0] : buf_ld<double>(ures, vline * 8u, (uint32_t)e * rstride * 8u);
+    return (e < NPRE) ? uu[e < NPRE ? e : 0] : buf_ld<double>(ures, vline * 8u, (uint32_t)e * rstride * 8u);
   };
   uint32_t mw = 0;  // lanes lb < SL: the mask word of row lo + lb
   if (active) {
@@ -1196,7 +1198,7 @@ void k_line_col(GArg<LineK<T>, G> grp_arg_) {
     // the velocity the solution is added to: loaded here, where the
     // registers of the separator solve are free, in flight over the barrier
 #pragma unroll
-    for (int e = 0; e < SL; ++e) uu[e] = buf_ld<double>(ures, vline * 8u, (uint32_t)e * rstride * 8u);
+    for (int e = 0; e < NPRE; ++e) uu[e] = buf_ld<double>(ures, vline * 8u, (uint32_t)e * rstride * 8u);
   }
   __syncthreads();  // separator values
   if (active) {

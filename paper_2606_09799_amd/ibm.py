@@ -568,7 +568,8 @@ class Batch:
         return nb
 
     def tune(self, coef, dt, steps=3, max_entries=64, scratch=None):
-        """Autotune the execution plan (ibm_batch_tune); the states are left
+        """Autotune the execution plan (ibm_batch_tune, switched off in the
+        library: it raises IbmError with IBM_EINVAL); the states are left
         as they were.  scratch: a uint8 device tensor of at least
         tune_scratch_bytes() bytes for the state snapshot (allocated here by
         torch when None; the library allocates nothing).  Returns (best plan,

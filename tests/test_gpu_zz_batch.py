@@ -132,6 +132,47 @@ def test_batch_simulation_against_oracle():
         assert rel(got[c].reshape(f[c].shape), f[c]) < 1e-10, c
 
 
+_TUNER_OFF = ("the autotuner is switched off: runs of it ended in a GPU fault and in an abort "
+              "inside ibm_batch_tune whose cause is not found")
+
+
+def test_hand_set_plans_match_serial():
+    """Plans set by hand (extreme stream groups and RHS planes, eager
+    streams, one graph, grouped launches) step bit-identically to serial
+    mode."""
+    from paper_2606_09799_amd import ibm
+    wls = _small_sims()
+    ref = _run_batch(wls, 2, ibm.BATCH_SERIAL)
+    dt = wls[0].dt
+    for plan in ({"mode": "streams", "streams": 1, "rhs_planes": 1},
+                 {"mode": "graph", "streams": 2, "rhs_planes": 5},
+                 {"mode": "grouped", "streams": 1, "rhs_planes": 3}):
+        sims = [_device_sim(wl) for wl in wls]
+        batch = ibm.Batch(sims)
+        batch.set_plan(**plan)
+        assert batch.get_plan()["mode"] == plan["mode"]
+        for k in range(2):
+            batch.step([wl.bodies[0].coef(k * dt) for wl in wls], dt, ibm.BATCH_PLAN)
+        assert batch.check() == 0
+        for a, b in zip(ref, [_state(d) for d in sims]):
+            for x, y in zip(a, b):
+                assert np.array_equal(x, y)
+        batch.close()
+
+
+def test_autotuner_is_switched_off():
+    """ibm_batch_tune refuses with IBM_EINVAL before any work."""
+    from paper_2606_09799_amd import ibm
+    wls = _small_sims(2)
+    sims = [_device_sim(wl) for wl in wls]
+    batch = ibm.Batch(sims)
+    with pytest.raises(ibm.IbmError) as e:
+        batch.tune([wl.bodies[0].coef(0.0) for wl in wls], wls[0].dt, steps=1)
+    assert e.value.code == ibm.IBM_EINVAL
+    batch.close()
+
+
+@pytest.mark.skip(reason=_TUNER_OFF)
 def test_autotuner_keeps_states_and_results():
     """ibm_batch_tune leaves every simulation's state as it was, applies the
     fastest plan it measured, and stepping with any plan (the tuned one, or
@@ -172,6 +213,7 @@ def test_autotuner_keeps_states_and_results():
         batch.close()
 
 
+@pytest.mark.skip(reason=_TUNER_OFF)
 def test_autotuner_takes_caller_scratch_and_allocates_nothing():
     """The tuner's state snapshot lives in a caller buffer: one smaller than
     ibm_batch_tune_scratch_bytes (or unaligned) is refused with IBM_EINVAL
