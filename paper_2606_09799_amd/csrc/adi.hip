@@ -950,10 +950,24 @@ void k_line_col(GArg<LineK<T>, G> grp_arg_) {
   }
   const int lb = tid % TL, s = tid / TL;
   const bool active = s < P;
-  // y sweep: blocks in z-major order (consecutive blocks on different z
-  // rows, hence different memory channels); z sweep: x-tile fastest
-  const int bx = (MODE == 2) ? (int)bid.y : (int)bid.x;
-  const int by = (MODE == 2) ? (int)bid.x : (int)bid.y;
+  // z sweep: x tile fastest.  y sweep: a 1-D grid in which each XCD (blocks
+  // are dealt to the 8 XCDs round robin) takes whole z rows, one after the
+  // other, all x tiles of a row together: every row of a line lies in its
+  // own page, and the blocks of one z row then share the address
+  // translation of each of those pages in their XCD's L2 TLB (z-major blocks
+  // met each page once per x tile, a page-table read each time)
+  int bx, by;
+  if (MODE == 2) {
+    const int nxt = K.nx / TL;
+    const int64_t b = bid.x;
+    const int64_t r = b / NUM_XCD;
+    by = (int)(r / nxt) * NUM_XCD + (int)(b % NUM_XCD);
+    bx = (int)(r % nxt);
+    if (by >= K.nz) return;  // padding of the last round of z rows
+  } else {
+    bx = (int)bid.x;
+    by = (int)bid.y;
+  }
   const int i0 = bx * TL;
   const int ts = K.tab1 ? 0 : s;
 #define CTAB(q, e) tabs[((q) * SL + (e)) * tP + ts]
@@ -1341,7 +1355,10 @@ static void launch_line(Prof* pf, hipStream_t s, LineK<T> K, const char* name) {
         return;
       }
       if (K.L == 24) {
-        IBM_LAUNCH_G(pf, name, s, (&k_line_col<T, 2, 24, 32, true>), dim3(cgrid), dim3(ct), cshm, K, k_line_col<T, 2, 24, 32><<<cgrid, ct, cshm, s>>>(K));
+        // whole z rows per XCD (see the kernel): a 1-D grid
+        const dim3 ygrid((unsigned)(NUM_XCD * ((K.nz + NUM_XCD - 1) / NUM_XCD) * (K.nx / tl)));
+        IBM_LAUNCH_G(pf, name, s, (&k_line_col<T, 2, 24, 32, true>), ygrid, dim3(ct), cshm, K,
+                     k_line_col<T, 2, 24, 32><<<ygrid, ct, cshm, s>>>(K));
         return;
       }
     }
