@@ -950,23 +950,23 @@ void k_line_col(GArg<LineK<T>, G> grp_arg_) {
   }
   const int lb = tid % TL, s = tid / TL;
   const bool active = s < P;
-  // z sweep: x tile fastest.  y sweep: a 1-D grid in which each XCD (blocks
+  // y sweep: a 1-D grid in which each XCD (blocks
   // are dealt to the 8 XCDs round robin) takes whole z rows, one after the
   // other, all x tiles of a row together: every row of a line lies in its
   // own page, and the blocks of one z row then share the address
   // translation of each of those pages in their XCD's L2 TLB (z-major blocks
   // met each page once per x tile, a page-table read each time)
+  // The z sweep likewise: each XCD takes whole y planes, all x tiles of a
+  // plane together (the rows of a z line are a plane's z rows).
   int bx, by;
-  if (MODE == 2) {
+  {
     const int nxt = K.nx / TL;
+    const int nout = (MODE == 2) ? K.nz : K.nj;  // z rows (y sweep) or planes (z sweep)
     const int64_t b = bid.x;
     const int64_t r = b / NUM_XCD;
     by = (int)(r / nxt) * NUM_XCD + (int)(b % NUM_XCD);
     bx = (int)(r % nxt);
-    if (by >= K.nz) return;  // padding of the last round of z rows
-  } else {
-    bx = (int)bid.x;
-    by = (int)bid.y;
+    if (by >= nout) return;  // padding of the last round
   }
   const int i0 = bx * TL;
   const int ts = K.tab1 ? 0 : s;
@@ -1337,38 +1337,41 @@ static void launch_line(Prof* pf, hipStream_t s, LineK<T> K, const char* name) {
                         sizeof(uint32_t) * (size_t)K.P * K.L +
                         ((K.mode == 2 && K.L > LMAX) ? sizeof(T) * 3 * (size_t)K.P * K.L : 0);
     const dim3 cgrid = (K.mode == 1) ? dim3(K.nx / tl, K.nj) : dim3(K.nz, K.nx / tl);
-#define IBM_COL(M, SL_, KERN)                                                                  \
+    // the lean kernel (z sweeps, long y segments): whole rows or planes per
+    // XCD in a 1-D grid (see the kernel)
+    const int nout = (K.mode == 2) ? K.nz : K.nj;
+    const dim3 lgrid((unsigned)(NUM_XCD * ((nout + NUM_XCD - 1) / NUM_XCD) * (K.nx / tl)));
+#define IBM_COL(M, SL_, KERN, GRID)                                                            \
   do {                                                                                        \
     if constexpr (sizeof(T) == sizeof(float)) {                                               \
       if (tl == 32) {                                                                         \
-        IBM_LAUNCH_G(pf, name, s, (&KERN<T, M, SL_, 32, true>), dim3(cgrid), dim3(ct), cshm, K, \
-                     KERN<T, M, SL_, 32><<<cgrid, ct, cshm, s>>>(K));                         \
+        IBM_LAUNCH_G(pf, name, s, (&KERN<T, M, SL_, 32, true>), dim3(GRID), dim3(ct), cshm, K, \
+                     KERN<T, M, SL_, 32><<<GRID, ct, cshm, s>>>(K));                          \
         break;                                                                                \
       }                                                                                       \
     }                                                                                         \
-    IBM_LAUNCH_G(pf, name, s, (&KERN<T, M, SL_, 16, true>), dim3(cgrid), dim3(ct), cshm, K,   \
-                 KERN<T, M, SL_, 16><<<cgrid, ct, cshm, s>>>(K));                             \
+    IBM_LAUNCH_G(pf, name, s, (&KERN<T, M, SL_, 16, true>), dim3(GRID), dim3(ct), cshm, K,    \
+                 KERN<T, M, SL_, 16><<<GRID, ct, cshm, s>>>(K));                              \
   } while (0)
     if constexpr (sizeof(T) == sizeof(float)) {  // the long segments (FP32 plans only)
       if (K.L == 32) {
-        IBM_LAUNCH_G(pf, name, s, (&k_line_col<T, 1, 32, 32, true>), dim3(cgrid), dim3(ct), cshm, K, k_line_col<T, 1, 32, 32><<<cgrid, ct, cshm, s>>>(K));
+        IBM_LAUNCH_G(pf, name, s, (&k_line_col<T, 1, 32, 32, true>), lgrid, dim3(ct), cshm, K,
+                     k_line_col<T, 1, 32, 32><<<lgrid, ct, cshm, s>>>(K));
         return;
       }
       if (K.L == 24) {
-        // whole z rows per XCD (see the kernel): a 1-D grid
-        const dim3 ygrid((unsigned)(NUM_XCD * ((K.nz + NUM_XCD - 1) / NUM_XCD) * (K.nx / tl)));
-        IBM_LAUNCH_G(pf, name, s, (&k_line_col<T, 2, 24, 32, true>), ygrid, dim3(ct), cshm, K,
-                     k_line_col<T, 2, 24, 32><<<ygrid, ct, cshm, s>>>(K));
+        IBM_LAUNCH_G(pf, name, s, (&k_line_col<T, 2, 24, 32, true>), lgrid, dim3(ct), cshm, K,
+                     k_line_col<T, 2, 24, 32><<<lgrid, ct, cshm, s>>>(K));
         return;
       }
     }
     // wall-normal lines of 12 or 16 rows: the register form
     if (K.mode == 1)
-      IBM_COL(1, LMAX, k_line_col);
+      IBM_COL(1, LMAX, k_line_col, lgrid);
     else if (K.L == 12)
-      IBM_COL(2, 12, k_line_col_reg);
+      IBM_COL(2, 12, k_line_col_reg, cgrid);
     else
-      IBM_COL(2, LMAX, k_line_col_reg);
+      IBM_COL(2, LMAX, k_line_col_reg, cgrid);
 #undef IBM_COL
   }
   else if (K.mode == 1)
