@@ -95,16 +95,17 @@ def counter_names(kernel, form):
     T = "double" if form == "fp64" else "float"
     C = "float2" if form == "mixed_refined" else "double2"
     return {"rhs": [f"k_rhs<{T},"],
-            "adi_x": [f"k_line_xw<{T}>", f"k_line<{T}, 0,"],
+            "adi_x": [f"k_line_xw<{T},", f"k_line<{T}, 0,"],
             "adi_z": [f"k_line_col<{T}, 1,", f"k_line<{T}, 1,"],
-            "adi_y": [f"k_line_col<{T}, 2,", f"k_line<{T}, 2,"],
+            "adi_y": [f"k_line_col<{T}, 2,", f"k_line_col_reg<{T}, 2,", f"k_line<{T}, 2,"],
             "pois_fftx_fwd": [f"k_fftx256_fwd<{C}", f"k_fftx_fwd<{C}"],
-            "pois_fftz_fwd": [f"k_fftz256<{C}, false>", f"k_fftz<{C}, false>",
+            "pois_fftz_fwd": [f"k_fftz256<{C}, false,", f"k_fftz<{C}, false,",
                               f"k_fftz4s<{C}, false,"],
-            "pois_fftz_inv": ["k_fftz256<double2, true>", "k_fftz<double2, true>",
+            "pois_fftz_inv": ["k_fftz256<double2, true,", "k_fftz<double2, true,",
                               "k_fftz4s<double2, true,"],
             "pois_tri_y": [f"k_tri_y<{C},", f"k_tri_y_blk<{C},"],
-            "pois_fftx_inv": ["k_fftx256_inv<double2", "k_fftx_inv<double2"],
+            "pois_fftx_inv": ["k_fftx256_inv<double2", "k_fftx_inv<double2",
+                              "k_fftx4s_inv<double2,"],
             "project": [f"k_project<{T},"]}.get(kernel, [])
 
 

@@ -48,6 +48,8 @@ struct LineK {
   int64_t plane;
   int tl;             // lines per block
   int PP;             // column sweeps: P rounded up to a power of two
+  int xrow;           // y sweep, register kernel: whole z rows per XCD (1-D
+                      // grid) rather than z-major blocks (2-D grid)
 };
 
 template <typename T>
@@ -692,10 +694,23 @@ void k_line_col_reg(GArg<LineK<T>, G> grp_arg_) {
   }
   const int lb = tid % TL, s = tid / TL;
   const bool active = s < P;
-  // y sweep: blocks in z-major order (consecutive blocks on different z
-  // rows, hence different memory channels); z sweep: x-tile fastest
-  const int bx = (MODE == 2) ? (int)bid.y : (int)bid.x;
-  const int by = (MODE == 2) ? (int)bid.x : (int)bid.y;
+  // large planes: whole z rows (y sweep) or y planes (z sweep) per XCD, all
+  // x tiles of a row together, in a 1-D grid (as in the lean kernel below);
+  // small planes: z-major 2-D grid (consecutive blocks on different z rows,
+  // hence different memory channels), x-tile fastest for the z sweep
+  int bx, by;
+  if (K.xrow) {
+    const int nxt = K.nx / TL;
+    const int nout = (MODE == 2) ? K.nz : K.nj;
+    const int64_t b = bid.x;
+    const int64_t r = b / NUM_XCD;
+    by = (int)(r / nxt) * NUM_XCD + (int)(b % NUM_XCD);
+    bx = (int)(r % nxt);
+    if (by >= nout) return;  // padding of the last round
+  } else {
+    bx = (MODE == 2) ? (int)bid.y : (int)bid.x;
+    by = (MODE == 2) ? (int)bid.x : (int)bid.y;
+  }
   const int i0 = bx * TL;
   const int ts = K.tab1 ? 0 : s;
 #define CTAB(q, e) tabs[((q) * SL + (e)) * tP + ts]
@@ -1336,11 +1351,13 @@ static void launch_line(Prof* pf, hipStream_t s, LineK<T> K, const char* name) {
                                      7 * (size_t)pp * (tl + 1)) +
                         sizeof(uint32_t) * (size_t)K.P * K.L +
                         ((K.mode == 2 && K.L > LMAX) ? sizeof(T) * 3 * (size_t)K.P * K.L : 0);
-    const dim3 cgrid = (K.mode == 1) ? dim3(K.nx / tl, K.nj) : dim3(K.nz, K.nx / tl);
-    // the lean kernel (z sweeps, long y segments): whole rows or planes per
-    // XCD in a 1-D grid (see the kernel)
+    // whole rows or planes per XCD in a 1-D grid (see the kernels); the
+    // register kernel keeps its z-major 2-D grid on planes below 512 x 512,
+    // where the 1-D order measured slower
     const int nout = (K.mode == 2) ? K.nz : K.nj;
     const dim3 lgrid((unsigned)(NUM_XCD * ((nout + NUM_XCD - 1) / NUM_XCD) * (K.nx / tl)));
+    K.xrow = (int64_t)K.nx * K.nz >= 512 * 512;
+    const dim3 rgrid = K.xrow ? lgrid : dim3(K.nz, K.nx / tl);
 #define IBM_COL(M, SL_, KERN, GRID)                                                            \
   do {                                                                                        \
     if constexpr (sizeof(T) == sizeof(float)) {                                               \
@@ -1369,9 +1386,9 @@ static void launch_line(Prof* pf, hipStream_t s, LineK<T> K, const char* name) {
     if (K.mode == 1)
       IBM_COL(1, LMAX, k_line_col, lgrid);
     else if (K.L == 12)
-      IBM_COL(2, 12, k_line_col_reg, cgrid);
+      IBM_COL(2, 12, k_line_col_reg, rgrid);
     else
-      IBM_COL(2, LMAX, k_line_col_reg, cgrid);
+      IBM_COL(2, LMAX, k_line_col_reg, rgrid);
 #undef IBM_COL
   }
   else if (K.mode == 1)
