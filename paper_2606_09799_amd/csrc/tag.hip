@@ -3,7 +3,9 @@
 //
 // Pipeline, all on the device and free of host synchronisation:
 //   1. k_tag_pairs, pass 0: one 64-lane wavefront per (triangle, lattice)
-//      visits the nodes of the triangle's inflated bounding box, computes the
+//      visits the nodes of the triangle's inflated bounding box that lie
+//      within the largest neighbour spacing of its bounding box and of its
+//      plane (the others cannot classify), computes the
 //      closest point X, N = x - X and the six-neighbour sign test; every
 //      classifying pair lowers best_d[node] (the bit pattern of |N|^2, an
 //      order-preserving key for non-negative doubles) with an integer
@@ -76,16 +78,24 @@ __global__ __launch_bounds__(64 * TAG_TPB) void k_tag_pairs(GArg<TagK, G> grp_ar
     if (lane == 0) atomicOr(a.flags, FLAG_GEOM);
     return;
   }
-  const int64_t total = (int64_t)ni * ne * nk;
+  // (ni, ne, nk below the periodic lengths and ny + 2: the box index fits 32 bits)
+  const int total = ni * ne * nk;
   uint32_t* mask = a.mask[c];
   u64* best_d = a.best_d[c];
   int32_t* best_t = a.best_t[c];
-  for (int64_t q = lane; q < total; q += 64) {
-    const int ii = bx.i0 + (int)(q % ni);
-    const int64_t r = q / ni;
-    const int ee = bx.e0 + (int)(r % ne);
-    const int kk = bx.k0 + (int)(r / ne);
-    const double p[3] = {((double)ii + L.ox) * g.dx, L.ext[ee], ((double)kk + L.oz) * g.dz};
+  auto node_pos = [&](int q, int& ii, int& ee, int& kk, double p[3]) {
+    ii = bx.i0 + q % ni;
+    const int r = q / ni;
+    ee = bx.e0 + r % ne;
+    kk = bx.k0 + r / ne;
+    p[0] = ((double)ii + L.ox) * g.dx;
+    p[1] = L.ext[ee];
+    p[2] = ((double)kk + L.oz) * g.dz;
+  };
+  auto visit = [&](int q) {
+    int ii, ee, kk;
+    double p[3];
+    node_pos(q, ii, ee, kk, p);
     const ClosestPt X = closest_point(p, A, B, C);
     const double N0 = p[0] - X.x[0], N1 = p[1] - X.x[1], N2 = p[2] - X.x[2];
     const double n2 = dot3(N0, N1, N2, N0, N1, N2);
@@ -104,7 +114,7 @@ __global__ __launch_bounds__(64 * TAG_TPB) void k_tag_pairs(GArg<TagK, G> grp_ar
           dot3(N0, N1, zm - X.x[2], N0, N1, N2) < 0.0 ||
           dot3(N0, N1, zp - X.x[2], N0, N1, N2) < 0.0;
     }
-    if (!f) continue;
+    if (!f) return;
     const int j = (c == 1) ? ee : ee - 1;
     const int64_t node = ((int64_t)j * g.nz + wrapi(kk, g.nz)) * g.nx + wrapi(ii, g.nx);
     const u64 bits = (u64)__double_as_longlong(n2);
@@ -114,6 +124,61 @@ __global__ __launch_bounds__(64 * TAG_TPB) void k_tag_pairs(GArg<TagK, G> grp_ar
     } else if (best_d[node] == bits) {
       atomicMin(&best_t[node], t);
     }
+  };
+  // Conservative prune.  A node classifies only if some neighbour x_n gives
+  // (x_n - X).N < 0, i.e. |N|^2 < (x - x_n).N <= h |N| with h the spacing to
+  // that neighbour (at most dmax), or if N = 0: |N| < dmax either way (up to
+  // the rounding of the computed test, relative 1e-15, far inside the margin
+  // below).  |N| = |x - X| is at least the distance of x to the triangle's
+  // bounding box and to its plane, so a node for which either exceeds dmax
+  // (with the margin) cannot classify and is skipped; the classification
+  // itself is unchanged.  A degenerate triangle has a NaN plane distance,
+  // which prunes nothing.  The surviving nodes are queued per wavefront in
+  // LDS (ballot and lane prefix count) and visited 64 at a time, so that the
+  // lanes of a visit are all busy.
+  const double e1x = B[0] - A[0], e1y = B[1] - A[1], e1z = B[2] - A[2];
+  const double e2x = C[0] - A[0], e2y = C[1] - A[1], e2z = C[2] - A[2];
+  const double cx = e1y * e2z - e1z * e2y, cy = e1z * e2x - e1x * e2z, cz = e1x * e2y - e1y * e2x;
+  const double cn = sqrt(dot3(cx, cy, cz, cx, cy, cz));
+  const double un0 = cx / cn, un1 = cy / cn, un2 = cz / cn;
+  const double lim = g.dmax * g.dmax * (1.0 + 1e-6);
+  __shared__ int qbuf[TAG_TPB][128];
+  int* qb = qbuf[threadIdx.x >> 6];
+  int cnt = 0;  // queued nodes (uniform over the wavefront, below 64 between visits)
+  for (int base = 0; base < total; base += 64) {
+    const int q = base + lane;
+    bool cand = false;
+    if (q < total) {
+      int ii, ee, kk;
+      double p[3];
+      node_pos(q, ii, ee, kk, p);
+      const double b0 = fmax(fmax(lo[0] - p[0], p[0] - hi[0]), 0.0);
+      const double b1 = fmax(fmax(lo[1] - p[1], p[1] - hi[1]), 0.0);
+      const double b2 = fmax(fmax(lo[2] - p[2], p[2] - hi[2]), 0.0);
+      const double pd = dot3(p[0] - A[0], p[1] - A[1], p[2] - A[2], un0, un1, un2);
+      cand = !(dot3(b0, b1, b2, b0, b1, b2) > lim) && !(pd * pd > lim);
+    }
+    const u64 bal = (u64)__ballot(cand);
+    if (cand) {
+      const int below = (int)__builtin_amdgcn_mbcnt_hi(
+          (uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
+      qb[cnt + below] = q;
+    }
+    cnt += __popcll(bal);
+    if (cnt >= 64) {
+      wave_sync();
+      const int qq = qb[lane];
+      const int rem = cnt - 64;
+      const int mv = (lane < rem) ? qb[64 + lane] : 0;
+      wave_sync();
+      if (lane < rem) qb[lane] = mv;
+      cnt = rem;
+      visit(qq);
+    }
+  }
+  if (cnt > 0) {
+    wave_sync();
+    if (lane < cnt) visit(qb[lane]);
   }
 }
 
