@@ -357,7 +357,9 @@ def run_batched(args, dev, nsim, form):
     import workloads
     from paper_2606_09799_amd import ibm
 
-    wls = workloads.batch(nsim)
+    # the bodies' wall clearance covers every step the modes below run
+    nmodes = len([m for m in args.batch_modes.split(",") if m])
+    wls = workloads.batch(nsim, steps=nmodes * (args.warmup + args.steps))
     pdt = torch.float64 if form == "fp64" else torch.float32
     T = lambda a: torch.from_numpy(np.ascontiguousarray(a)).to(dev)
     sims = []

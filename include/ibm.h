@@ -184,8 +184,9 @@ int ibm_set_stream(ibm_ctx* ctx, void* stream);
  * rigid:  X = c + R X0, U = cdot + omega x (X - c);
  *         coef (host) = [c(3), R(9 row-major), cdot(3), omega(3)];
  *         x0: dev f64[nv*3] reference positions.
- * deform: X = c + (r0 + f s) d, U = (f sdot) d;
- *         coef (host) = [c(3), r0, s, sdot]; data: dev f64[nv*4] = [d(3), f].
+ * deform: X = c + (r0 + f s) d, U = cdot + (f sdot) d (a shape carried by
+ *         a centre moving at cdot); coef (host) = [c(3), r0, s, sdot,
+ *         cdot(3)]; data: dev f64[nv*4] = [d(3), f].
  * Output xyz, vel: dev f64[nv*3]. */
 int ibm_body_rigid(ibm_ctx* ctx, const double* x0, int32_t nv, const double* coef,
                    double* xyz, double* vel);
@@ -432,7 +433,7 @@ void ibm_batch_destroy(ibm_batch* b);
 ibm_ctx* ibm_batch_context(ibm_batch* b, int32_t sim);
 /* One time step of every simulation: body transform at t^n from
  * coef (host f64[nsim*IBM_COEF_STRIDE]; simulation s at s*IBM_COEF_STRIDE,
- * rigid: the 18 values of ibm_body_rigid, deform: the first 6 values of
+ * rigid: the 18 values of ibm_body_rigid, deform: the first 9 values of
  * ibm_body_deform), then ibm_step.  mode: IBM_BATCH_SERIAL, _STREAMS,
  * _GRAPH, _GROUPED or _PLAN (the current plan's mode; streams and graph
  * modes use the plan's stream groups and tile choice); the first graph call

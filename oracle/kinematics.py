@@ -8,8 +8,10 @@ hence bit-identical tags).
 
 rigid:   X = c + R X0,  U = cdot + omega x (X - c)
          coef = [c(3), R(9 row-major), cdot(3), omega(3)]
-deform:  X = c + (r0 + f s) d,  U = (f sdot) d
-         per-vertex data [d(3), f], coef = [c(3), r0, s, sdot]
+deform:  X = c + (r0 + f s) d,  U = cdot + (f sdot) d
+         per-vertex data [d(3), f], coef = [c(3), r0, s, sdot, cdot(3)]
+         (a shape r(theta, t) carried by a centre moving at cdot: the wall
+         velocity is the time derivative of X)
 """
 from __future__ import annotations
 
@@ -33,7 +35,7 @@ def rigid(X0, coef):
 
 def deform(data, coef):
     data = np.asarray(data, np.float64)
-    c, r0, s, sd = coef[0:3], coef[3], coef[4], coef[5]
+    c, r0, s, sd, cd = coef[0:3], coef[3], coef[4], coef[5], coef[6:9]
     f = data[:, 3]
     rad = r0 + f * s
     rd = f * sd
@@ -41,7 +43,7 @@ def deform(data, coef):
     U = np.empty((len(data), 3))
     for d in range(3):
         X[:, d] = c[d] + rad * data[:, d]
-        U[:, d] = rd * data[:, d]
+        U[:, d] = cd[d] + rd * data[:, d]
     return X, U
 
 

@@ -13,7 +13,7 @@ struct Rigid {
   double c[3], R[9], cd[3], om[3];
 };
 struct Deform {
-  double c[3], r0, s, sd;
+  double c[3], r0, s, sd, cd[3];
 };
 
 // X = c + R X0, U = cdot + omega x (X - c)
@@ -32,7 +32,8 @@ __device__ __forceinline__ void rigid_vertex(const Rigid& k, const double* __res
   vel[3 * v + 2] = k.cd[2] + (k.om[0] * r1 - k.om[1] * r0);
 }
 
-// X = c + (r0 + f s) d, U = (f sdot) d
+// X = c + (r0 + f s) d, U = cdot + (f sdot) d (the shape carried by a
+// centre moving at cdot)
 __device__ __forceinline__ void deform_vertex(const Deform& k, const double* __restrict__ data,
                                               int v, double* __restrict__ xyz,
                                               double* __restrict__ vel) {
@@ -42,7 +43,7 @@ __device__ __forceinline__ void deform_vertex(const Deform& k, const double* __r
   for (int d = 0; d < 3; ++d) {
     double dir = data[4 * v + d];
     xyz[3 * v + d] = k.c[d] + rad * dir;
-    vel[3 * v + d] = rd * dir;
+    vel[3 * v + d] = k.cd[d] + rd * dir;
   }
 }
 
@@ -116,6 +117,7 @@ __global__ void k_body_deform_dev(GArg<BodyDeformDevK, G> grp_arg_) {
   k.r0 = coef[3];
   k.s = coef[4];
   k.sd = coef[5];
+  for (int d = 0; d < 3; ++d) k.cd[d] = coef[6 + d];
   deform_vertex(k, data, v, xyz, vel);
 }
 
@@ -138,6 +140,7 @@ void launch_body_deform(Prof* pf, hipStream_t s, const double* data, int nv, con
   k.r0 = coef[3];
   k.s = coef[4];
   k.sd = coef[5];
+  for (int d = 0; d < 3; ++d) k.cd[d] = coef[6 + d];
   if (nv <= 0) return;
   IBM_LAUNCH(pf, "body_deform", s,
              k_body_deform<<<(nv + 255) / 256, 256, 0, s>>>(data, nv, k, xyz, vel));

@@ -34,6 +34,33 @@ struct TagK {
   uint32_t* flags;
 };
 
+// Counts over an ascending array by the 64 lanes of a wavefront together
+// (every lane reads the entries lane, lane + 64, ...; the counts are sums of
+// ballots): one memory round trip per 64 entries instead of one per
+// bisection step, and two bounds from the same reads.  lt: entries below v0
+// (the lower bound of v0, numpy searchsorted side 'left'); le: entries at
+// most v1 (the upper bound of v1, side 'right').
+__device__ __forceinline__ void wave_bounds(const double* ext, int n, double v0, double v1,
+                                            int lane, int& lt, int& le) {
+  lt = 0;
+  le = 0;
+  for (int m = 0; m < n; m += 64) {
+    const double x = (m + lane < n) ? ext[m + lane] : 0.0;
+    const bool in = m + lane < n;
+    lt += __popcll((u64)__ballot(in && x < v0));
+    le += __popcll((u64)__ballot(in && x <= v1));
+  }
+}
+
+// find_body by the lanes of a wavefront: the last body whose first triangle
+// id is at most t (the ids ascend)
+__device__ __forceinline__ int wave_find_body(const BodyDev* b, int nbody, int t, int lane) {
+  int cnt = 0;
+  for (int m = 0; m < nbody; m += 64)
+    cnt += __popcll((u64)__ballot(m + lane < nbody && b[m + lane].toff <= t));
+  return cnt > 0 ? cnt - 1 : 0;
+}
+
 // One wavefront per (triangle, lattice), four triangles per block (no block
 // barrier: each wavefront works alone).
 constexpr int TAG_TPB = 4;
@@ -50,7 +77,19 @@ __global__ __launch_bounds__(64 * TAG_TPB) void k_tag_pairs(GArg<TagK, G> grp_ar
   double A[3], B[3], C[3];
   const double* vel;
   int vid[3];
-  load_triangle(a.bodies, a.nbody, t, A, B, C, &vel, vid);
+  {
+    const BodyDev& bd = a.bodies[wave_find_body(a.bodies, a.nbody, t, lane)];
+    const int lt = t - bd.toff;
+    vid[0] = bd.tri[3 * lt];
+    vid[1] = bd.tri[3 * lt + 1];
+    vid[2] = bd.tri[3 * lt + 2];
+    for (int d = 0; d < 3; ++d) {
+      A[d] = bd.xyz[3 * vid[0] + d];
+      B[d] = bd.xyz[3 * vid[1] + d];
+      C[d] = bd.xyz[3 * vid[2] + d];
+    }
+    vel = bd.vel;
+  }
   double lo[3], hi[3];
   for (int d = 0; d < 3; ++d) {
     lo[d] = fmin(A[d], fmin(B[d], C[d]));
@@ -59,35 +98,66 @@ __global__ __launch_bounds__(64 * TAG_TPB) void k_tag_pairs(GArg<TagK, G> grp_ar
   // the one-layer fresh-cell assumption (Sec. 3.1): over dt no vertex may
   // move more than half the local spacing along an axis (the y spacing of the
   // cell the vertex lies in)
-  if (a.dt > 0.0 && a.pass == 0 && c == 0 && lane == 0) {
+  if (a.dt > 0.0 && a.pass == 0 && c == 0) {
     bool over = false;
     for (int q = 0; q < 3; ++q) {
       const double* U = vel + 3 * vid[q];
       const double y = (q == 0) ? A[1] : (q == 1 ? B[1] : C[1]);
-      int j = upper_bound(g.yf, g.ny + 1, y) - 1;
+      int below, upto;
+      wave_bounds(g.yf, g.ny + 1, y, y, lane, below, upto);
+      int j = upto - 1;  // the face at or below y
       j = j < 0 ? 0 : (j > g.ny - 1 ? g.ny - 1 : j);
       over = over || fabs(U[0]) * a.dt > 0.5 * g.dx || fabs(U[2]) * a.dt > 0.5 * g.dz ||
              fabs(U[1]) * a.dt > 0.5 * g.dy[j];
     }
-    if (over) atomicOr(a.flags, FLAG_CFL);
+    if (over && lane == 0) atomicOr(a.flags, FLAG_CFL);
   }
   const Lattice L = lattice(g, c);
-  const Box bx = candidate_box(g, L, lo, hi);
-  const int ni = bx.i1 - bx.i0 + 1, ne = bx.e1 - bx.e0 + 1, nk = bx.k1 - bx.k0 + 1;
+  // the candidate box of candidate_box, its y range counted by the lanes
+  // together (the same bounds as its bisections)
+  Box bx;
+  {
+    const double dm = g.dmax;
+    bx.i0 = (int)floor((lo[0] - dm) / g.dx - L.ox) - 1;
+    bx.i1 = (int)floor((hi[0] + dm) / g.dx - L.ox) + 1;
+    bx.k0 = (int)floor((lo[2] - dm) / g.dz - L.oz) - 1;
+    bx.k1 = (int)floor((hi[2] + dm) / g.dz - L.oz) + 1;
+    int lb, ub;
+    wave_bounds(L.ext, L.next, lo[1] - dm, hi[1] + dm, lane, lb, ub);
+    const int e0 = lb - 1, e1 = ub;
+    bx.e0 = e0 < L.e_first ? L.e_first : (e0 > L.e_last ? L.e_last : e0);
+    bx.e1 = e1 < L.e_first ? L.e_first : (e1 > L.e_last ? L.e_last : e1);
+  }
+  const int ni = bx.i1 - bx.i0 + 1, nk = bx.k1 - bx.k0 + 1;
   if (ni + 1 >= g.nx || nk + 1 >= g.nz) {  // a node would have two images
     if (lane == 0) atomicOr(a.flags, FLAG_GEOM);
     return;
   }
-  // (ni, ne, nk below the periodic lengths and ny + 2: the box index fits 32 bits)
-  const int total = ni * ne * nk;
+  // The nodes scanned: those of the box within the largest neighbour spacing
+  // (plus a relative margin of 1e-6, beyond the prune's below) of the
+  // triangle's bounding box along each axis; the box's margin nodes and the
+  // rest cannot classify (see the prune below).
+  const double dms = g.dmax * (1.0 + 1e-6);
+  const int si0 = max(bx.i0, (int)floor((lo[0] - dms) / g.dx - L.ox));
+  const int si1 = min(bx.i1, (int)ceil((hi[0] + dms) / g.dx - L.ox));
+  const int sk0 = max(bx.k0, (int)floor((lo[2] - dms) / g.dz - L.oz));
+  const int sk1 = min(bx.k1, (int)ceil((hi[2] + dms) / g.dz - L.oz));
+  int slb, sub;
+  wave_bounds(L.ext, L.next, lo[1] - dms, hi[1] + dms, lane, slb, sub);
+  const int se0 = max(bx.e0, slb);
+  const int se1 = min(bx.e1, sub - 1);
+  const int sni = si1 - si0 + 1, sne = se1 - se0 + 1, snk = sk1 - sk0 + 1;
+  // (the scanned box lies within the candidate box, whose extents are below
+  // the periodic lengths and ny + 2: the node index fits 32 bits)
+  const int total = (sni > 0 && sne > 0 && snk > 0) ? sni * sne * snk : 0;
   uint32_t* mask = a.mask[c];
   u64* best_d = a.best_d[c];
   int32_t* best_t = a.best_t[c];
   auto node_pos = [&](int q, int& ii, int& ee, int& kk, double p[3]) {
-    ii = bx.i0 + q % ni;
-    const int r = q / ni;
-    ee = bx.e0 + r % ne;
-    kk = bx.k0 + r / ne;
+    ii = si0 + q % sni;
+    const int r = q / sni;
+    ee = se0 + r % sne;
+    kk = sk0 + r / sne;
     p[0] = ((double)ii + L.ox) * g.dx;
     p[1] = L.ext[ee];
     p[2] = ((double)kk + L.oz) * g.dz;

@@ -266,8 +266,8 @@ def ibm_body_rigid(ctx, x0, coef, xyz, vel):
 def ibm_body_deform(ctx, data, coef, xyz, vel):
     nv = data.shape[0]
     cf = np.ascontiguousarray(np.asarray(coef, np.float64))
-    if cf.shape != (6,):
-        raise ValueError("deform coefficients: 6 values")
+    if cf.shape != (9,):
+        raise ValueError("deform coefficients: 9 values")
     _ok(_body_deform(ctx.handle, _dev(data, torch.float64, 4 * nv, "data"), nv,
                      cf.ctypes.data_as(POINTER(c_double)),
                      _dev(xyz, torch.float64, 3 * nv, "xyz"),

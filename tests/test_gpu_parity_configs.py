@@ -29,9 +29,10 @@ def _tags_equal(case, tags):
 
 
 def test_deforming_body_transform_bit_exact():
-    """The deforming law X = c + (r0 + f s) d, U = (f sdot) d of the
-    512x384x512 body (20480 triangles) at several times, host-coefficient
-    kernel against the oracle's transform, bit for bit."""
+    """The deforming law X = c + (r0 + f s) d, U = cdot + (f sdot) d of the
+    512x384x512 body (20480 triangles) at several times, at rest and with its
+    centre translating, host-coefficient kernel against the oracle's
+    transform, bit for bit."""
     from paper_2606_09799_amd import ibm
     wl = workloads.config("c3")
     b = wl.bodies[0]
@@ -40,11 +41,14 @@ def test_deforming_body_transform_bit_exact():
     nv = b.ref.shape[0]
     xyz = torch.empty(nv, 3, dtype=torch.float64, device=DEV)
     vel = torch.empty_like(xyz)
-    for time in (0.0, 0.0137, 0.125, 0.31, 0.6):
-        ibm.ibm_body_deform(ctx, ref, b.coef(time), xyz, vel)
-        X, U = kinematics.body_at(b, time)
-        assert np.array_equal(n(xyz), X), time
-        assert np.array_equal(n(vel), U), time
+    moving = lambda tt: workloads.deform_coef(tt, (3.0, 0.1, 1.5), 0.4, U=(0.3, -0.2, 0.7))
+    for law in (b.coef, moving):
+        for time in (0.0, 0.0137, 0.125, 0.31, 0.6):
+            coef = law(time)
+            ibm.ibm_body_deform(ctx, ref, coef, xyz, vel)
+            X, U = kinematics.deform(b.ref, coef)
+            assert np.array_equal(n(xyz), X), time
+            assert np.array_equal(n(vel), U), time
     ctx.close()
 
 

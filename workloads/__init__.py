@@ -161,12 +161,13 @@ def deform_vertex_data(unit_verts: np.ndarray, r0: float, amp: float = 0.1):
     return out
 
 
-def deform_coef(t: float, centre, r0: float, freq: float = 2.0) -> np.ndarray:
-    """Scalars of the deforming body at time t: [c(3), r0, s, sdot] with
-    s = sin(2 pi freq t)."""
+def deform_coef(t: float, centre, r0: float, freq: float = 2.0, U=(0.0, 0.0, 0.0)) -> np.ndarray:
+    """Scalars of the deforming body at time t: [c(3), r0, s, sdot, cdot(3)]
+    with s = sin(2 pi freq t) and the centre c = centre + U t moving at
+    cdot = U."""
     w = 2.0 * math.pi * freq
-    return np.array([centre[0], centre[1], centre[2], r0,
-                     math.sin(w * t), w * math.cos(w * t)], dtype=np.float64)
+    return np.array([centre[0] + U[0] * t, centre[1] + U[1] * t, centre[2] + U[2] * t, r0,
+                     math.sin(w * t), w * math.cos(w * t), U[0], U[1], U[2]], dtype=np.float64)
 
 # --------------------------------------------------------------------------
 # initial fields
@@ -561,11 +562,13 @@ def batch_sim(s: int, steps: int = 20) -> Workload:
     centre velocity 1 plus a 0.01 perturbation.  One body, its type drawn
     uniformly: a sphere (level 2..4, diameter 0.3..0.5), a plate (chord and
     span 0.3..0.6, 320..5120 triangles, pitched by a fixed angle within +-15
-    deg) - both translating at a speed drawn from U[0, 1] in a random
-    direction - or a deforming closed body (the law of the large deforming
-    case, r0 0.15..0.25, level 2..4) at rest.  The centre is uniform in the
-    box with a wall clearance of at least r + h + 2 d0 + 20 dt |U|
-    (h = 2 sqrt(3) d0 the probe length)."""
+    deg) or a deforming closed body (the law of the large deforming case,
+    r0 0.15..0.25, level 2..4), each translating at a speed drawn from
+    U[0, 1] in a random direction.  The centre is uniform in the box with a
+    wall clearance of at least r + h + 2 d0 + steps dt |U| (h = 2 sqrt(3) d0
+    the probe length), so that the body stays clear of the walls over
+    `steps` steps; where the channel is too narrow for that, the speed is
+    lowered until it fits."""
     rng = np.random.default_rng(4000 + s)
     d0 = 1.0 / 32.0
     nx = int(rng.choice(np.arange(32, 129, 16)))
@@ -594,8 +597,10 @@ def batch_sim(s: int, steps: int = 20) -> Workload:
         level = int(rng.integers(2, 5))
         r0 = float(rng.uniform(0.15, 0.25))
         r = r0 * 1.07
-        U = np.zeros(3)
-    clear = r + h + 2.0 * d0 + 20.0 * dt * float(np.linalg.norm(U))
+    room = 0.95 * half - (r + h + 2.0 * d0)
+    if steps * dt * float(np.linalg.norm(U)) > room:
+        U = U * (max(room, 0.0) / (steps * dt * float(np.linalg.norm(U))))
+    clear = r + h + 2.0 * d0 + steps * dt * float(np.linalg.norm(U))
     c = np.array([rng.uniform(0.0, lx), rng.uniform(-half + clear, half - clear),
                   rng.uniform(0.0, lz)])
     if kind == 0:
@@ -606,8 +611,9 @@ def batch_sim(s: int, steps: int = 20) -> Workload:
     else:
         V, F = icosphere(level)
         cc = tuple(c)
+        Ut = tuple(float(x) for x in U)
         body = Body("deform", deform_vertex_data(V, r0), F,
-                    lambda t, cc=cc, r0=r0: deform_coef(t, cc, r0))
+                    lambda t, cc=cc, r0=r0, Ut=Ut: deform_coef(t, cc, r0, U=Ut))
     dpdx = -2.0 * 1.0 / (re * half * half)
     return Workload(f"c4.{s}", nx, ny, nz, lx, lz, yf, re, dt, steps, 1.0, 0.01, 4000 + s,
                     dpdx, [body], half=half)
