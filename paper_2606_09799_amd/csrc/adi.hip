@@ -167,9 +167,12 @@ __global__ __launch_bounds__(MODE == 0 ? 256 : 1024) void k_line(GArg<LineK<T>, 
     const int64_t nl = (int64_t)K.nj * K.nz;
     xrows = (int)((l0 + K.tl <= nl) ? K.tl : nl - l0);
     xsrc = K.d + ((int64_t)K.j0 * K.nz + l0) * K.n;
-    for (int r = 0; r < xrows; ++r)
-      for (int c = tid; c < K.n; c += blockDim.x)
-        rowbuf[r * RS + c + (c >> 4)] = xsrc[(int64_t)r * K.n + c];
+    // the block's rows are consecutive in memory: one flat, coalesced pass
+    // over all of them (short rows would leave most threads idle row by row)
+    for (int e = tid; e < xrows * K.n; e += blockDim.x) {
+      const int r = e / K.n, c = e - r * K.n;
+      rowbuf[r * RS + c + (c >> 4)] = xsrc[e];
+    }
     __syncthreads();
   }
   auto xpos = [&](int e) { return lb * RS + (lo + e) + ((lo + e) >> 4); };
@@ -403,9 +406,10 @@ __global__ __launch_bounds__(MODE == 0 ? 256 : 1024) void k_line(GArg<LineK<T>, 
     }
     __syncthreads();
     T* xdst = K.d + (xsrc - K.d);
-    for (int r = 0; r < xrows; ++r)
-      for (int c = tid; c < K.n; c += blockDim.x)
-        xdst[(int64_t)r * K.n + c] = rowbuf[r * RS + c + (c >> 4)];
+    for (int e = tid; e < xrows * K.n; e += blockDim.x) {
+      const int r = e / K.n, c = e - r * K.n;
+      xdst[e] = rowbuf[r * RS + c + (c >> 4)];
+    }
   }
 }
 
