@@ -5,6 +5,7 @@ import numpy as np
 import pytest
 
 import workloads
+from oracle import kinematics
 
 
 @pytest.mark.parametrize("name", ["tiny", "tiny_plate", "c1"])
@@ -24,3 +25,25 @@ def test_torch_generator_chunks_and_offsets():
     part = workloads.splitmix64_uniform_torch(7, 2, 1234, "cpu", start=3000)
     assert np.array_equal(full[3000:4234], part.numpy())
     assert part.dtype == torch.float64
+
+
+@pytest.mark.parametrize("steps", [20, 92])
+def test_batched_bodies_stay_clear_of_the_walls(steps):
+    """Every batched simulation's body keeps the wall clearance of its
+    generator (radius, probe length and two cells) over the given number of
+    steps at its drawn speed; the deforming bodies translate too."""
+    import math
+    d0 = 1.0 / 32.0
+    h = 2.0 * math.sqrt(3.0) * d0
+    moving_deform = 0
+    for s in range(64):
+        wl = workloads.batch_sim(s, steps)
+        b = wl.bodies[0]
+        X0, _ = kinematics.body_at(b, 0.0)
+        X1, U1 = kinematics.body_at(b, steps * wl.dt)
+        half = 0.5 * wl.ny * d0
+        for X in (X0, X1):
+            assert np.max(np.abs(X[:, 1])) + h + 2.0 * d0 <= half + 1e-12, (s, steps)
+        if b.kind == "deform" and np.linalg.norm(b.coef(0.0)[6:9]) > 0:
+            moving_deform += 1
+    assert moving_deform > 0
